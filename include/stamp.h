@@ -1,0 +1,193 @@
+/*
+ * stamp.h -- C ABI of the MI355X (gfx950) STAMP SVGD hot path.
+ *
+ * STAMP (Lee et al., arXiv 2310.01775) samples task-and-motion plans with Stein
+ * variational gradient descent.  Each particle is a relaxed discrete action
+ * sequence plus continuous push parameters; its log-posterior gradient comes from
+ * a differentiable rigid-body pushing rollout.  This library runs one SVGD
+ * iteration (and loops of them) on the GPU:
+ *
+ *   rollout forward  (Sec. III-B; Sec. IV-A; Appendix E-B)  stamp_rollout_fwd
+ *   rollout adjoint  (Sec. III-B, back-propagation through the trajectory)
+ *                                                            stamp_rollout_adj
+ *   median bandwidth + SVGD direction (Eq. 1; Appendix D-B) stamp_svgd_step
+ *   update (Algorithm 1's step, or Adam)                     stamp_adam_step
+ *   the loop of Algorithm 1 (SVGD phase)                     stamp_solve
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Particle arrays are structure-of-arrays, particle index fastest:
+ *   theta[l * N + i] is coordinate l of particle i, d = 6 * H coordinates.
+ *   For push k: l = 6k+0..6k+3 are the side logits a_k (North, East, South,
+ *   West), l = 6k+4 the contact offset o_k (m), l = 6k+5 the push depth D_k (m).
+ * - All array arguments are DEVICE pointers to float32 (or int32/uint32 where
+ *   typed so), owned by the caller, contiguous, 4-byte aligned.  Scene, cost and
+ *   solver structs are HOST pointers, read during the call only.
+ * - Every compute call is asynchronous on `stream` (a hipStream_t passed as
+ *   void*; NULL = the null stream) and returns once its kernels are enqueued.
+ *   No compute call allocates memory; scratch comes in through `workspace`,
+ *   sized by the matching *_bytes call.
+ * - Return value: STAMP_OK or a negative STAMP_E* code.  Argument errors are
+ *   detected on the host before anything is enqueued.  STAMP_EHIP means a HIP
+ *   runtime call failed; stamp_last_error() returns its text.
+ * - Asynchronous numerical faults (a non-finite cost, state or gradient) set
+ *   bits in the caller's device word `status` (may be NULL to skip), which the
+ *   caller reads after synchronising.  The library never clears it.
+ * - One stamp_ctx per thread that issues calls; a context is not thread-safe.
+ */
+#ifndef STAMP_H
+#define STAMP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define STAMP_OK 0
+#define STAMP_EINVAL (-1)       /* null pointer, size or parameter out of range */
+#define STAMP_ENOSPACE (-2)     /* workspace or tape smaller than required */
+#define STAMP_EHIP (-3)         /* HIP runtime error; see stamp_last_error */
+#define STAMP_EUNSUPPORTED (-4) /* valid request this build does not implement */
+
+#define STAMP_MODES 4       /* push sides N, E, S, W (Sec. V-A) */
+#define STAMP_MAX_BLOCKS 4  /* blocks per scene */
+#define STAMP_MAX_PUSHES 8  /* H, pushes per plan */
+
+/* bits of the device status word */
+#define STAMP_STATUS_NONFINITE_COST 1u
+#define STAMP_STATUS_NONFINITE_GRAD 2u
+#define STAMP_STATUS_NONFINITE_PHI 4u
+
+typedef struct stamp_ctx stamp_ctx;
+
+/* Planar pushing scene (Sec. IV-A "Block-Pushing", Appendix E-A).  Block 0 is
+ * the pushed block; blocks 1..B-1 are free obstacles it can collide with.
+ * T is the total number of integration steps, split into H push phases of
+ * floor/ceil(T/H) steps; dt the step (s).  The model constants parameterise the
+ * spring-based penalty contacts and regularised Coulomb friction of Sec. III-B:
+ *   k_push, k_block  penalty stiffness (N/m) of pusher and block-block contact
+ *   sp_beta          sharpness (1/m) of the softplus penalty log(1+e^{beta z})/beta
+ *   standoff         distance (m) outside the face where each push starts
+ *   g                gravity (m/s^2); eps_v_scale: eps_v = eps_v_scale*dt*mu*g
+ *   eps_r            regulariser (m) of the block-centre distance */
+typedef struct stamp_scene {
+    int32_t H, M, B, T; /* pushes (1..8), modes (must be 4), blocks (1..4), steps (>= H) */
+    float dt;
+    float half[STAMP_MAX_BLOCKS];  /* half side length (m) */
+    float mass[STAMP_MAX_BLOCKS];  /* kg */
+    float mu[STAMP_MAX_BLOCKS];    /* ground friction coefficient */
+    float pose0[STAMP_MAX_BLOCKS][3]; /* initial x, y (m), phi (rad) */
+    float goal[3];                 /* goal x, y, phi of block 0 */
+    float goal_tol;                /* dead-zone half-width of the target loss (m) */
+    float k_push, k_block, sp_beta, standoff, g, eps_v_scale, eps_r;
+} stamp_scene;
+
+/* Cost weights (Appendix E-B): C = target*L_target + rot*L_rot + traj*L_traj
+ * + bound*L_bound; o_max/d_max bound the offset and depth; traj_eps smooths the
+ * Manhattan distance of L_traj.  log rho = -C. */
+typedef struct stamp_cost_w {
+    float target, rot, traj, bound, o_max, d_max, traj_eps;
+} stamp_cost_w;
+
+/* Solver settings (Algorithm 1, SVGD phase, a fixed number of iterations). */
+typedef struct stamp_solver_cfg {
+    int32_t iters;     /* SVGD iterations (>= 0) */
+    int32_t t0;        /* Adam steps already taken (resume); step t = t0+1.. */
+    float lr;          /* Adam lr, or epsilon of the plain step theta += lr*phi */
+    float beta1, beta2, adam_eps;
+    int32_t use_adam;  /* 1: Adam on -phi; 0: plain step */
+    float bandwidth;   /* > 0: fixed h; <= 0: median heuristic every iteration */
+    int32_t ckpt_every;/* tape mode inside the solve: 0 full tape, K>0 checkpoints */
+    int32_t reserved;
+} stamp_solver_cfg;
+
+/* ---- context ----------------------------------------------------------- */
+
+/* Create a context bound to HIP device `device` (made current).  Returns
+ * STAMP_EINVAL for a null ctx or a bad device, STAMP_EHIP on runtime errors. */
+int32_t stamp_create(stamp_ctx** ctx, int32_t device);
+void stamp_destroy(stamp_ctx* ctx);
+/* Text of the last error recorded in ctx ("" if none); valid until the next call. */
+const char* stamp_last_error(const stamp_ctx* ctx);
+/* Library version string. */
+const char* stamp_version(void);
+
+/* ---- sizing (host only, no GPU work) ------------------------------------- */
+
+/* Floats of the rollout tape for N particles.  ckpt_every = 0 keeps the full
+ * trajectory; K > 0 keeps a checkpoint every K steps inside each push phase.
+ * Layout: [n_entries][6B][4N] then the phase-end block [H][6B][4N]; lane
+ * 4i+s holds particle i's sub-rollout of side s.  Returns 0 on bad arguments. */
+size_t stamp_tape_floats(const stamp_scene* scene, int32_t N, int32_t ckpt_every);
+/* Workspace bytes of stamp_rollout_adj (segment replay buffer when K > 0). */
+size_t stamp_adj_workspace_bytes(const stamp_scene* scene, int32_t N, int32_t ckpt_every);
+/* Workspace bytes of stamp_svgd_step for N particles of dimension d. */
+size_t stamp_svgd_workspace_bytes(int32_t N, int32_t d);
+/* Workspace bytes of stamp_solve over n_problems problems (host arrays). */
+size_t stamp_solve_workspace_bytes(int32_t n_problems, const stamp_scene* scenes,
+                                   const int32_t* N, const stamp_solver_cfg* cfg);
+
+/* ---- hot path ------------------------------------------------------------ */
+
+/* Roll N particles through the relaxed pushing simulation (Sec. III-B, IV-A):
+ * each push phase runs once per side from the shared phase-start state and the
+ * next phase starts from the softmax(a_k)-weighted mixture of the outcomes.
+ *   theta [d][N] in; cost [N] out (C of Appendix E-B);
+ *   tape  [stamp_tape_floats] out, or NULL when no adjoint follows.
+ * Errors: STAMP_EINVAL for null ctx/scene/w/theta/cost, N < 1, H not in 1..8,
+ * M != 4, B not in 1..4, T < H, dt <= 0, ckpt_every < 0. */
+int32_t stamp_rollout_fwd(stamp_ctx* ctx, const stamp_scene* scene, const stamp_cost_w* w,
+                          int32_t N, const float* theta, float* cost, float* tape,
+                          int32_t ckpt_every, uint32_t* status, void* stream);
+
+/* Reverse sweep of the rollout (back-propagation through the trajectory,
+ * Sec. III-B): grad[l*N+i] = cost_bar[i] * dC_i/dtheta_{l,i}.
+ *   tape from stamp_rollout_fwd with the same theta and ckpt_every;
+ *   cost_bar [N] or NULL (= all ones); pass cost_bar = -1 to get grad log rho.
+ *   workspace >= stamp_adj_workspace_bytes (may be NULL when that is 0).
+ * Errors as stamp_rollout_fwd; STAMP_ENOSPACE if ws_bytes is too small. */
+int32_t stamp_rollout_adj(stamp_ctx* ctx, const stamp_scene* scene, const stamp_cost_w* w,
+                          int32_t N, const float* theta, const float* tape, int32_t ckpt_every,
+                          const float* cost_bar, float* grad, void* workspace, size_t ws_bytes,
+                          uint32_t* status, void* stream);
+
+/* SVGD direction of Eq. (1) with the RBF kernel K_ij = exp(-|theta_i-theta_j|^2/h):
+ *   phi_i = (1/N) sum_j K_ij [ grad_logp_j + (2/h)(theta_i - theta_j) ].
+ * bandwidth > 0 fixes h; otherwise h = max(m2 / ln N, 1e-12) with m2 the exact
+ * lower median (the ceil(P/2)-th smallest) of the P = N(N-1)/2 squared distances
+ * over i < j (median heuristic, Appendix D-B).  N = 1 gives phi = grad_logp.
+ *   theta, grad_logp, phi: [d][N]; h_out: one device float (may be NULL).
+ * Errors: STAMP_EINVAL for null pointers, N < 1, d < 1; STAMP_ENOSPACE. */
+int32_t stamp_svgd_step(stamp_ctx* ctx, int32_t N, int32_t d, const float* theta,
+                        const float* grad_logp, float bandwidth, float* phi, float* h_out,
+                        void* workspace, size_t ws_bytes, void* stream);
+
+/* Update of Algorithm 1 on n = d*N floats, in place:
+ *   use_adam = 1: Adam minimising -phi at step t (>= 1), bias-corrected;
+ *   use_adam = 0: theta += lr * phi (m, v untouched, may be NULL). */
+int32_t stamp_adam_step(stamp_ctx* ctx, int64_t n, float* theta, const float* phi, float* m,
+                        float* v, int32_t t, float lr, float beta1, float beta2, float eps,
+                        int32_t use_adam, void* stream);
+
+/* Algorithm 1 (SVGD phase) for cfg->iters iterations over n_problems
+ * independent problems: rollout -> adjoint -> bandwidth -> phi -> update.
+ * Problem p has N[p] particles and scene scenes[p]; its particles, Adam moments
+ * and outputs are packed one after another:
+ *   theta, adam_m, adam_v: sum_p 6*H_p*N_p floats, problem p's block [d_p][N_p];
+ *   cost_out: sum_p N_p (final true cost); modes_out: sum_p H_p*N_p int32,
+ *   problem p's block [H_p][N_p] = argmax side per push (Gamma, Eq. 5), or NULL;
+ *   solve_time_us: n_problems floats (device time of each problem's solve) or NULL.
+ * adam_m/adam_v may be NULL only when use_adam = 0. */
+int32_t stamp_solve(stamp_ctx* ctx, int32_t n_problems, const stamp_scene* scenes,
+                    const stamp_cost_w* w, const int32_t* N, const stamp_solver_cfg* cfg,
+                    float* theta, float* adam_m, float* adam_v, float* cost_out,
+                    int32_t* modes_out, float* solve_time_us, void* workspace,
+                    size_t ws_bytes, uint32_t* status, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* STAMP_H */

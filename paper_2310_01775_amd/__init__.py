@@ -1,0 +1,251 @@
+"""Python binding of libstamp.so, the gfx950 STAMP SVGD hot path.
+
+Argument marshalling only: every step of the path runs in the library's HIP
+kernels.  torch supplies device memory and the current HIP stream.  Names follow
+include/stamp.h; particle tensors on the device are structure-of-arrays
+``[d][N]`` float32 (coordinate-major), see ``soa``/``aos``.
+
+The extension is required: importing this package without a built
+``libstamp.so`` raises ImportError (run ``python -m paper_2310_01775_amd.build``).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libstamp.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2310_01775_amd.build`")
+_lib = C.CDLL(LIB_PATH)
+
+OK, EINVAL, ENOSPACE, EHIP, EUNSUPPORTED = 0, -1, -2, -3, -4
+STATUS_NONFINITE_COST, STATUS_NONFINITE_GRAD, STATUS_NONFINITE_PHI = 1, 2, 4
+MAX_BLOCKS, MAX_PUSHES, MODES = 4, 8, 4
+
+
+class Scene(C.Structure):
+    _fields_ = [("H", C.c_int32), ("M", C.c_int32), ("B", C.c_int32), ("T", C.c_int32),
+                ("dt", C.c_float),
+                ("half", C.c_float * 4), ("mass", C.c_float * 4), ("mu", C.c_float * 4),
+                ("pose0", (C.c_float * 3) * 4), ("goal", C.c_float * 3), ("goal_tol", C.c_float),
+                ("k_push", C.c_float), ("k_block", C.c_float), ("sp_beta", C.c_float),
+                ("standoff", C.c_float), ("g", C.c_float), ("eps_v_scale", C.c_float),
+                ("eps_r", C.c_float)]
+
+
+class CostW(C.Structure):
+    _fields_ = [("target", C.c_float), ("rot", C.c_float), ("traj", C.c_float), ("bound", C.c_float),
+                ("o_max", C.c_float), ("d_max", C.c_float), ("traj_eps", C.c_float)]
+
+
+class SolverCfg(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("t0", C.c_int32), ("lr", C.c_float), ("beta1", C.c_float),
+                ("beta2", C.c_float), ("adam_eps", C.c_float), ("use_adam", C.c_int32),
+                ("bandwidth", C.c_float), ("ckpt_every", C.c_int32), ("reserved", C.c_int32)]
+
+
+_vp, _i32, _i64, _f32, _sz = C.c_void_p, C.c_int32, C.c_int64, C.c_float, C.c_size_t
+_P = C.POINTER
+_sig = {
+    "stamp_create": (_i32, [_P(_vp), _i32]),
+    "stamp_destroy": (None, [_vp]),
+    "stamp_last_error": (C.c_char_p, [_vp]),
+    "stamp_version": (C.c_char_p, []),
+    "stamp_tape_floats": (_sz, [_P(Scene), _i32, _i32]),
+    "stamp_adj_workspace_bytes": (_sz, [_P(Scene), _i32, _i32]),
+    "stamp_svgd_workspace_bytes": (_sz, [_i32, _i32]),
+    "stamp_solve_workspace_bytes": (_sz, [_i32, _P(Scene), _P(_i32), _P(SolverCfg)]),
+    "stamp_rollout_fwd": (_i32, [_vp, _P(Scene), _P(CostW), _i32, _vp, _vp, _vp, _i32, _vp, _vp]),
+    "stamp_rollout_adj": (_i32, [_vp, _P(Scene), _P(CostW), _i32, _vp, _vp, _i32, _vp, _vp, _vp, _sz,
+                                 _vp, _vp]),
+    "stamp_svgd_step": (_i32, [_vp, _i32, _i32, _vp, _vp, _f32, _vp, _vp, _vp, _sz, _vp]),
+    "stamp_adam_step": (_i32, [_vp, _i64, _vp, _vp, _vp, _vp, _i32, _f32, _f32, _f32, _f32, _i32, _vp]),
+    "stamp_solve": (_i32, [_vp, _i32, _P(Scene), _P(CostW), _P(_i32), _P(SolverCfg), _vp, _vp, _vp, _vp,
+                           _vp, _vp, _vp, _sz, _vp, _vp]),
+}
+for _name, (_res, _args) in _sig.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+EXPORTS = tuple(_sig)
+
+
+class StampError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"stamp error {code}: {msg}")
+        self.code = code
+
+
+def version() -> str:
+    return _lib.stamp_version().decode()
+
+
+# ---------------------------------------------------------------------------
+# marshalling helpers
+# ---------------------------------------------------------------------------
+def make_scene(d: dict) -> Scene:
+    """stamp_scene from a scene dict (keys as in workloads.make_scene)."""
+    s = Scene()
+    s.H, s.M, s.B, s.T = int(d["H"]), int(d.get("M", 4)), int(d["B"]), int(d["T"])
+    s.dt = d["dt"]
+    for b in range(s.B):
+        s.half[b], s.mass[b], s.mu[b] = d["half"][b], d["mass"][b], d["mu"][b]
+        for q in range(3):
+            s.pose0[b][q] = d["pose0"][b][q]
+    for q in range(3):
+        s.goal[q] = d["goal"][q]
+    for k in ("goal_tol", "k_push", "k_block", "sp_beta", "standoff", "g", "eps_v_scale", "eps_r"):
+        setattr(s, k, d[k])
+    return s
+
+
+def make_cost(w: dict) -> CostW:
+    c = CostW()
+    for k, _ in CostW._fields_:
+        setattr(c, k, w[k])
+    return c
+
+
+def make_cfg(iters, t0=0, lr=1e-3, beta1=0.9, beta2=0.999, adam_eps=1e-8, use_adam=True,
+             bandwidth=0.0, ckpt_every=0) -> SolverCfg:
+    return SolverCfg(int(iters), int(t0), lr, beta1, beta2, adam_eps, int(bool(use_adam)), bandwidth,
+                     int(ckpt_every), 0)
+
+
+def soa(theta_nd, device="cuda") -> torch.Tensor:
+    """[N][d] host particles -> contiguous float32 [d][N] device tensor."""
+    t = torch.as_tensor(np.asarray(theta_nd), dtype=torch.float32)
+    return t.t().contiguous().to(device)
+
+
+def aos(theta_dn: torch.Tensor) -> np.ndarray:
+    """[d][N] device tensor -> [N][d] float64 numpy (host)."""
+    return theta_dn.detach().to("cpu", torch.float64).t().contiguous().numpy()
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError("device tensors must be contiguous CUDA/HIP tensors")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+# ---------------------------------------------------------------------------
+class Context:
+    """One library context on a device (not thread-safe)."""
+
+    def __init__(self, device: int = 0):
+        h = C.c_void_p()
+        rc = _lib.stamp_create(C.byref(h), int(device))
+        if rc != OK:
+            raise StampError(rc, "stamp_create failed")
+        self._h = h
+        self.device = torch.device("cuda", device)
+
+    def close(self):
+        if self._h:
+            _lib.stamp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        if rc != OK:
+            raise StampError(rc, _lib.stamp_last_error(self._h).decode())
+
+    # -- sizing --------------------------------------------------------------
+    @staticmethod
+    def tape_floats(scene: Scene, N: int, ckpt_every: int = 0) -> int:
+        return int(_lib.stamp_tape_floats(C.byref(scene), N, ckpt_every))
+
+    @staticmethod
+    def adj_workspace_bytes(scene: Scene, N: int, ckpt_every: int = 0) -> int:
+        return int(_lib.stamp_adj_workspace_bytes(C.byref(scene), N, ckpt_every))
+
+    @staticmethod
+    def svgd_workspace_bytes(N: int, d: int) -> int:
+        return int(_lib.stamp_svgd_workspace_bytes(N, d))
+
+    @staticmethod
+    def solve_workspace_bytes(scenes, Ns, cfg: SolverCfg) -> int:
+        arr = (Scene * len(scenes))(*scenes)
+        ns = (C.c_int32 * len(Ns))(*Ns)
+        return int(_lib.stamp_solve_workspace_bytes(len(scenes), arr, ns, C.byref(cfg)))
+
+    def _bytes(self, n):
+        return torch.empty(max(int(n), 1), dtype=torch.uint8, device=self.device)
+
+    def status_word(self):
+        return torch.zeros(1, dtype=torch.int32, device=self.device)
+
+    # -- hot path -------------------------------------------------------------
+    def rollout_fwd(self, scene: Scene, w: CostW, theta: torch.Tensor, tape=None, ckpt_every: int = 0,
+                    status=None, stream=None, cost=None):
+        N = theta.shape[1]
+        if cost is None:
+            cost = torch.empty(N, dtype=torch.float32, device=self.device)
+        self._check(_lib.stamp_rollout_fwd(self._h, C.byref(scene), C.byref(w), N, _ptr(theta), _ptr(cost),
+                                           _ptr(tape), ckpt_every, _ptr(status), _stream(stream)))
+        return cost
+
+    def rollout_adj(self, scene: Scene, w: CostW, theta: torch.Tensor, tape: torch.Tensor,
+                    ckpt_every: int = 0, cost_bar=None, grad=None, workspace=None, status=None, stream=None):
+        N = theta.shape[1]
+        if grad is None:
+            grad = torch.empty_like(theta)
+        need = self.adj_workspace_bytes(scene, N, ckpt_every)
+        if workspace is None and need:
+            workspace = self._bytes(need)
+        ws_bytes = workspace.numel() if workspace is not None else 0
+        self._check(_lib.stamp_rollout_adj(self._h, C.byref(scene), C.byref(w), N, _ptr(theta), _ptr(tape),
+                                           ckpt_every, _ptr(cost_bar), _ptr(grad), _ptr(workspace), ws_bytes,
+                                           _ptr(status), _stream(stream)))
+        return grad
+
+    def svgd_step(self, theta: torch.Tensor, grad_logp: torch.Tensor, bandwidth: float = 0.0, phi=None,
+                  h_out=None, workspace=None, stream=None):
+        d, N = theta.shape
+        if phi is None:
+            phi = torch.empty_like(theta)
+        if workspace is None:
+            workspace = self._bytes(self.svgd_workspace_bytes(N, d))
+        self._check(_lib.stamp_svgd_step(self._h, N, d, _ptr(theta), _ptr(grad_logp), float(bandwidth),
+                                         _ptr(phi), _ptr(h_out), _ptr(workspace), workspace.numel(),
+                                         _stream(stream)))
+        return phi
+
+    def adam_step(self, theta, phi, m, v, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, use_adam=True,
+                  stream=None):
+        self._check(_lib.stamp_adam_step(self._h, theta.numel(), _ptr(theta), _ptr(phi), _ptr(m), _ptr(v),
+                                         int(t), lr, beta1, beta2, eps, int(bool(use_adam)), _stream(stream)))
+
+    def solve(self, scenes, ws_, Ns, cfg: SolverCfg, theta, adam_m=None, adam_v=None, cost_out=None,
+              modes_out=None, solve_time_us=None, workspace=None, status=None, stream=None):
+        n = len(scenes)
+        arr = (Scene * n)(*scenes)
+        warr = (CostW * n)(*ws_)
+        ns = (C.c_int32 * n)(*Ns)
+        if cost_out is None:
+            cost_out = torch.empty(sum(Ns), dtype=torch.float32, device=self.device)
+        if workspace is None:
+            workspace = self._bytes(self.solve_workspace_bytes(scenes, Ns, cfg))
+        self._check(_lib.stamp_solve(self._h, n, arr, warr, ns, C.byref(cfg), _ptr(theta), _ptr(adam_m),
+                                     _ptr(adam_v), _ptr(cost_out), _ptr(modes_out), _ptr(solve_time_us),
+                                     _ptr(workspace), workspace.numel(), _ptr(status), _stream(stream)))
+        return cost_out

@@ -1,0 +1,49 @@
+// Host-side launchers of the STAMP kernels (internal to libstamp.so).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "common.h"
+
+namespace stamp {
+
+hipError_t launch_rollout_fwd(const SimConst& c, int N, const float* theta, float* cost, float* tape,
+                              const TapeGeom& g, uint32_t* status, hipStream_t st);
+hipError_t launch_rollout_adj(const SimConst& c, int N, const float* theta, const float* tape,
+                              const TapeGeom& g, const float* cost_bar, float cb_scalar, float* grad,
+                              float* seg, uint32_t* status, hipStream_t st);
+
+// SVGD step.  Workspace carve-up is computed by svgd_workspace_layout.
+struct SvgdLayout {
+    size_t dist_off, dist_floats;   // tile-packed squared distances (i < j)
+    size_t hist_off;                // 3 histograms of the radix select
+    size_t sel_off;                 // select state
+    size_t h_off;                   // bandwidth scalar
+    size_t part_off, part_floats;   // phi partial sums [splits][d+1][N]
+    int splits;                     // column splits of the phi contraction
+    int tiles;                      // 64-row tiles
+    size_t total;
+};
+SvgdLayout svgd_workspace_layout(int N, int d);
+// h: when bandwidth > 0 it is used as is; otherwise the median heuristic runs and
+// writes h into the workspace (and h_out if non-null).
+hipError_t launch_svgd(int N, int d, const float* theta, const float* grad_logp, float bandwidth,
+                       float* phi, float* h_out, void* ws, const SvgdLayout& L, uint32_t* status,
+                       hipStream_t st);
+
+// Adam (use_adam=1) or plain step, n elements.  t_dev: if non-null, the step
+// count is read as t0 + *t_dev + 1 on the device (graph replay); else t0 is t.
+hipError_t launch_update(int64_t n, float* theta, const float* phi, float* m, float* v, int t0,
+                         const int* t_dev, float lr, float b1, float b2, float eps, int use_adam,
+                         hipStream_t st);
+
+// Final read-out: Gamma(a_k) = first argmax side per push, modes [H][N].
+hipError_t launch_modes(int N, int H, const float* theta, int32_t* modes, hipStream_t st);
+
+// tiny device helpers
+hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st);
+hipError_t launch_incr(int* p, hipStream_t st);
+
+}  // namespace stamp

@@ -1,0 +1,523 @@
+// Relaxed block-pushing rollout and its adjoint on gfx950.
+//
+// Model (Sec. III-B: semi-implicit Euler with spring-based penalty contacts;
+// Sec. IV-A and Appendix E: pushing from the N/E/S/W faces of block 0).
+// Push phase k runs once per side s from the shared phase-start state S_k; the
+// next phase starts from S_{k+1} = sum_s softmax(a_k)_s X_s(t_{k+1}).  One lane
+// per (particle, side): lane 4i+s integrates X_s of particle i in registers;
+// the quad of a particle meets only at phase boundaries (DPP).
+//
+// The adjoint is the exact reverse of the forward arithmetic (Sec. III-B:
+// gradients back-propagated through the whole trajectory), either from a full
+// tape of pre-step states or by replaying checkpointed segments of <= K steps
+// into a scratch buffer and reversing each.
+#include "common.h"
+#include "internal.h"
+
+namespace stamp {
+
+template <int B>
+struct State {
+    float x[B], y[B], ph[B], vx[B], vy[B], om[B];
+};
+
+// Fixed data of one lane during one push phase.
+struct Push {
+    float nx, ny, tx, ty;  // face normal n_s and tangent t_s (block frame)
+    float Ax, Ay, cA, sA;  // anchor: block-0 position and rotation of S_k
+    float o, D;            // contact offset and push depth of phase k
+};
+
+template <int B>
+__device__ __forceinline__ void load_state(State<B>& X, const float* __restrict__ e, int64_t lanes,
+                                           int64_t lane) {
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+        X.x[b] = e[(6 * b + 0) * lanes + lane];
+        X.y[b] = e[(6 * b + 1) * lanes + lane];
+        X.ph[b] = e[(6 * b + 2) * lanes + lane];
+        X.vx[b] = e[(6 * b + 3) * lanes + lane];
+        X.vy[b] = e[(6 * b + 4) * lanes + lane];
+        X.om[b] = e[(6 * b + 5) * lanes + lane];
+    }
+}
+
+template <int B>
+__device__ __forceinline__ void store_state(const State<B>& X, float* __restrict__ e, int64_t lanes,
+                                            int64_t lane) {
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+        e[(6 * b + 0) * lanes + lane] = X.x[b];
+        e[(6 * b + 1) * lanes + lane] = X.y[b];
+        e[(6 * b + 2) * lanes + lane] = X.ph[b];
+        e[(6 * b + 3) * lanes + lane] = X.vx[b];
+        e[(6 * b + 4) * lanes + lane] = X.vy[b];
+        e[(6 * b + 5) * lanes + lane] = X.om[b];
+    }
+}
+
+// One semi-implicit Euler step of the sub-rollout (pusher of this lane's side).
+template <int B>
+__device__ __forceinline__ void step_forward(const SimConst& c, State<B>& X, const Push& p, float sig) {
+    float Fx[B], Fy[B], Tq[B];
+    // regularised Coulomb friction, every block
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+        float inv = 1.0f / sqrtf(X.vx[b] * X.vx[b] + X.vy[b] * X.vy[b] + c.ev2[b]);
+        Fx[b] = -c.cf[b] * X.vx[b] * inv;
+        Fy[b] = -c.cf[b] * X.vy[b] * inv;
+        float invw = 1.0f / sqrtf(X.om[b] * X.om[b] + c.ew2[b]);
+        Tq[b] = -c.cr[b] * X.om[b] * invw;
+    }
+    // block-block penalty on the inscribed disks, central force
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+#pragma unroll
+        for (int q = b + 1; q < B; ++q) {
+            float dx = X.x[b] - X.x[q], dy = X.y[b] - X.y[q];
+            float r = sqrtf(dx * dx + dy * dy + c.er2);
+            float f = c.kb * softplus(c.hsum[b][q] - r, c.beta, c.inv_beta);
+            float ux = dx / r, uy = dy / r;
+            Fx[b] += f * ux;
+            Fy[b] += f * uy;
+            Fx[q] -= f * ux;
+            Fy[q] -= f * uy;
+        }
+    }
+    // the virtual pusher of this side, on block 0
+    {
+        float depth = c.h0d - p.D * sig;
+        float qx = depth * p.nx + p.o * p.tx, qy = depth * p.ny + p.o * p.ty;
+        float psx = p.Ax + p.cA * qx - p.sA * qy;
+        float psy = p.Ay + p.sA * qx + p.cA * qy;
+        float relx = psx - X.x[0], rely = psy - X.y[0];
+        float s0, c0;
+        sincosf(X.ph[0], &s0, &c0);
+        float lx = c0 * relx + s0 * rely, ly = -s0 * relx + c0 * rely;
+        float pen = c.h0 - (p.nx * lx + p.ny * ly);
+        float f = c.kp * softplus(pen, c.beta, c.inv_beta);
+        float ex = c0 * p.nx - s0 * p.ny, ey = s0 * p.nx + c0 * p.ny;
+        float Fpx = -f * ex, Fpy = -f * ey;
+        Fx[0] += Fpx;
+        Fy[0] += Fpy;
+        Tq[0] += relx * Fpy - rely * Fpx;
+    }
+    // semi-implicit Euler: velocities, then positions with the new velocities
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+        X.vx[b] = X.vx[b] + c.dt * (Fx[b] * c.inv_m[b]);
+        X.vy[b] = X.vy[b] + c.dt * (Fy[b] * c.inv_m[b]);
+        X.om[b] = X.om[b] + c.dt * (Tq[b] * c.inv_I[b]);
+        X.x[b] = X.x[b] + c.dt * X.vx[b];
+        X.y[b] = X.y[b] + c.dt * X.vy[b];
+        X.ph[b] = X.ph[b] + c.dt * X.om[b];
+    }
+}
+
+// Reverse of step_forward at pre-step state X.  On entry L is the adjoint of the
+// post-step state; on exit the adjoint of the pre-step state.  Adjoints of the
+// phase data (o, D, anchor) are accumulated.
+template <int B>
+__device__ __forceinline__ void step_reverse(const SimConst& c, const State<B>& X, State<B>& L,
+                                             const Push& p, float sig, float& o_b, float& D_b,
+                                             float& Ax_b, float& Ay_b, float& cA_b, float& sA_b) {
+    float Fxb[B], Fyb[B], Tqb[B];
+    // integrator: x' = x + dt v', v' = v + dt F/m
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+        float vxb = L.vx[b] + c.dt * L.x[b];
+        float vyb = L.vy[b] + c.dt * L.y[b];
+        float omb = L.om[b] + c.dt * L.ph[b];
+        L.vx[b] = vxb;
+        L.vy[b] = vyb;
+        L.om[b] = omb;
+        Fxb[b] = c.dt * c.inv_m[b] * vxb;
+        Fyb[b] = c.dt * c.inv_m[b] * vyb;
+        Tqb[b] = c.dt * c.inv_I[b] * omb;
+    }
+    // pusher
+    {
+        float depth = c.h0d - p.D * sig;
+        float qx = depth * p.nx + p.o * p.tx, qy = depth * p.ny + p.o * p.ty;
+        float psx = p.Ax + p.cA * qx - p.sA * qy;
+        float psy = p.Ay + p.sA * qx + p.cA * qy;
+        float relx = psx - X.x[0], rely = psy - X.y[0];
+        float s0, c0;
+        sincosf(X.ph[0], &s0, &c0);
+        float lx = c0 * relx + s0 * rely, ly = -s0 * relx + c0 * rely;
+        float pen = c.h0 - (p.nx * lx + p.ny * ly);
+        float f = c.kp * softplus(pen, c.beta, c.inv_beta);
+        float ex = c0 * p.nx - s0 * p.ny, ey = s0 * p.nx + c0 * p.ny;
+        float Fpx = -f * ex, Fpy = -f * ey;
+
+        float Fpxb = Fxb[0], Fpyb = Fyb[0], Tpb = Tqb[0];
+        // T = relx Fpy - rely Fpx
+        float relxb = Tpb * Fpy, relyb = -Tpb * Fpx;
+        Fpyb += Tpb * relx;
+        Fpxb += -Tpb * rely;
+        // Fp = -f e
+        float fb = -(Fpxb * ex + Fpyb * ey);
+        float exb = -Fpxb * f, eyb = -Fpyb * f;
+        // e = R(phi0) n
+        float c0b = exb * p.nx + eyb * p.ny;
+        float s0b = -exb * p.ny + eyb * p.nx;
+        // f = kp sp(pen), pen = h0 - n.l
+        float penb = fb * c.kp * softplus_grad(pen, c.beta);
+        float lxb = -penb * p.nx, lyb = -penb * p.ny;
+        // l = R(phi0)^T rel
+        c0b += lxb * relx + lyb * rely;
+        s0b += lxb * rely - lyb * relx;
+        relxb += lxb * c0 - lyb * s0;
+        relyb += lxb * s0 + lyb * c0;
+        L.ph[0] += -c0b * s0 + s0b * c0;
+        // rel = ps - x0
+        L.x[0] -= relxb;
+        L.y[0] -= relyb;
+        // ps = A + R(A) q
+        Ax_b += relxb;
+        Ay_b += relyb;
+        cA_b += relxb * qx + relyb * qy;
+        sA_b += -relxb * qy + relyb * qx;
+        float qxb = relxb * p.cA + relyb * p.sA;
+        float qyb = -relxb * p.sA + relyb * p.cA;
+        // q = depth n + o t, depth = h0 + standoff - D s(tau)
+        float depthb = qxb * p.nx + qyb * p.ny;
+        o_b += qxb * p.tx + qyb * p.ty;
+        D_b += -depthb * sig;
+    }
+    // block-block contacts
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+#pragma unroll
+        for (int q = b + 1; q < B; ++q) {
+            float dx = X.x[b] - X.x[q], dy = X.y[b] - X.y[q];
+            float r = sqrtf(dx * dx + dy * dy + c.er2);
+            float pen = c.hsum[b][q] - r;
+            float f = c.kb * softplus(pen, c.beta, c.inv_beta);
+            float ux = dx / r, uy = dy / r;
+            float gx = Fxb[b] - Fxb[q], gy = Fyb[b] - Fyb[q];
+            float fb = gx * ux + gy * uy;
+            float uxb = f * gx, uyb = f * gy;
+            float invr = 1.0f / r;
+            float dxb = uxb * invr, dyb = uyb * invr;
+            float rb = -(uxb * dx + uyb * dy) * invr * invr;
+            rb += -fb * c.kb * softplus_grad(pen, c.beta);
+            dxb += rb * dx * invr;
+            dyb += rb * dy * invr;
+            L.x[b] += dxb;
+            L.x[q] -= dxb;
+            L.y[b] += dyb;
+            L.y[q] -= dyb;
+        }
+    }
+    // friction
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+        float inv = 1.0f / sqrtf(X.vx[b] * X.vx[b] + X.vy[b] * X.vy[b] + c.ev2[b]);
+        float inv3 = inv * inv * inv;
+        float dotF = Fxb[b] * X.vx[b] + Fyb[b] * X.vy[b];
+        L.vx[b] += -c.cf[b] * inv * Fxb[b] + c.cf[b] * inv3 * X.vx[b] * dotF;
+        L.vy[b] += -c.cf[b] * inv * Fyb[b] + c.cf[b] * inv3 * X.vy[b] * dotF;
+        float invw = 1.0f / sqrtf(X.om[b] * X.om[b] + c.ew2[b]);
+        L.om[b] += -c.cr[b] * Tqb[b] * c.ew2[b] * invw * invw * invw;
+    }
+}
+
+__device__ __forceinline__ void side_frame(int s, Push& p) {
+    p.nx = (s == 1) ? 1.0f : ((s == 3) ? -1.0f : 0.0f);
+    p.ny = (s == 0) ? 1.0f : ((s == 2) ? -1.0f : 0.0f);
+    p.tx = -p.ny;
+    p.ty = p.nx;
+}
+
+// softmax(a_k)_s of this lane's side (max-subtracted, Eq. 5's relaxation)
+__device__ __forceinline__ float side_weight(const float* __restrict__ theta, int N, int i, int k, int s) {
+    float a0 = theta[(int64_t)(6 * k + 0) * N + i];
+    float a1 = theta[(int64_t)(6 * k + 1) * N + i];
+    float a2 = theta[(int64_t)(6 * k + 2) * N + i];
+    float a3 = theta[(int64_t)(6 * k + 3) * N + i];
+    float m = fmaxf(fmaxf(a0, a1), fmaxf(a2, a3));
+    float e0 = expf(a0 - m), e1 = expf(a1 - m), e2 = expf(a2 - m), e3 = expf(a3 - m);
+    float es = (s == 0) ? e0 : (s == 1) ? e1 : (s == 2) ? e2 : e3;
+    return es / (((e0 + e1) + e2) + e3);
+}
+
+__device__ __forceinline__ float smooth_abs(float u, float ea2) { return sqrtf(u * u + ea2); }
+
+// ---------------------------------------------------------------------------
+template <int B>
+__global__ __launch_bounds__(256) void k_rollout_fwd(SimConst c, int N, const float* __restrict__ theta,
+                                                     float* __restrict__ cost, float* __restrict__ tape,
+                                                     TapeGeom g, uint32_t* status) {
+    const int64_t lane = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = (int)(lane >> 2);
+    const int s = (int)(lane & 3);
+    if (i >= N) return;  // whole quads leave together
+    const int H = c.H, T = c.T;
+
+    State<B> S;
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+        S.x[b] = c.pose0[b][0];
+        S.y[b] = c.pose0[b][1];
+        S.ph[b] = c.pose0[b][2];
+        S.vx[b] = S.vy[b] = S.om[b] = 0.0f;
+    }
+    float Px[kMaxPushes + 1], Py[kMaxPushes + 1];
+    float Lbound = 0.0f;
+    Push p;
+    side_frame(s, p);
+    int64_t entry = 0;
+    for (int k = 0; k < H; ++k) {
+        const int tk = phase_start(k, T, H), tk1 = phase_start(k + 1, T, H);
+        const float Lk = (float)(tk1 - tk);
+        Px[k] = S.x[0];
+        Py[k] = S.y[0];
+        p.Ax = S.x[0];
+        p.Ay = S.y[0];
+        sincosf(S.ph[0], &p.sA, &p.cA);
+        const float z = side_weight(theta, N, i, k, s);
+        p.o = theta[(int64_t)(6 * k + 4) * N + i];
+        p.D = theta[(int64_t)(6 * k + 5) * N + i];
+        Lbound += relu(fabsf(p.o) - c.omax) * relu(fabsf(p.o) - c.omax) + relu(-p.D) * relu(-p.D) +
+                  relu(p.D - c.dmax) * relu(p.D - c.dmax);
+        State<B> X = S;
+        for (int t = tk; t < tk1; ++t) {
+            if (tape) {
+                if (g.ckpt == 0) {
+                    store_state(X, tape + (int64_t)t * 6 * B * g.lanes, g.lanes, lane);
+                } else if ((t - tk) % g.ckpt == 0) {
+                    store_state(X, tape + entry * 6 * B * g.lanes, g.lanes, lane);
+                    ++entry;
+                }
+            }
+            const float sig = push_profile((float)(t - tk + 1) / Lk);
+            step_forward<B>(c, X, p, sig);
+        }
+        if (tape) store_state(X, tape + g.ends_off + (int64_t)k * 6 * B * g.lanes, g.lanes, lane);
+        // phase mixture
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            S.x[b] = quad_sum(z * X.x[b]);
+            S.y[b] = quad_sum(z * X.y[b]);
+            S.ph[b] = quad_sum(z * X.ph[b]);
+            S.vx[b] = quad_sum(z * X.vx[b]);
+            S.vy[b] = quad_sum(z * X.vy[b]);
+            S.om[b] = quad_sum(z * X.om[b]);
+        }
+    }
+    Px[H] = S.x[0];
+    Py[H] = S.y[0];
+    // cost (Appendix E-B)
+    const float dxg = fabsf(Px[H] - c.goal[0]) - c.tol, dyg = fabsf(Py[H] - c.goal[1]) - c.tol;
+    const float Ltarget = relu(dxg) * relu(dxg) + relu(dyg) * relu(dyg);
+    const float Lrot = 1.0f - cosf(S.ph[0] - c.goal[2]);
+    float Ltraj = 0.0f;
+    for (int k = 1; k <= H; ++k) {
+        Ltraj += smooth_abs(Px[k - 1] - Px[k], c.ea2) + smooth_abs(Py[k - 1] - Py[k], c.ea2);
+        Ltraj += smooth_abs(Px[k] - Px[H], c.ea2) + smooth_abs(Py[k] - Py[H], c.ea2);
+        Ltraj -= smooth_abs(Px[k - 1] - Px[H], c.ea2) + smooth_abs(Py[k - 1] - Py[H], c.ea2);
+    }
+    const float C = c.wt * Ltarget + c.wr * Lrot + c.wtr * Ltraj + c.wb * Lbound;
+    if (s == 0) {
+        cost[i] = C;
+        if (status && !isfinite(C)) atomicOr(status, STAMP_STATUS_NONFINITE_COST);
+    }
+}
+
+// ---------------------------------------------------------------------------
+template <int B>
+__global__ __launch_bounds__(256) void k_rollout_adj(SimConst c, int N, const float* __restrict__ theta,
+                                                     const float* __restrict__ tape, TapeGeom g,
+                                                     const float* __restrict__ cost_bar, float cb_scalar,
+                                                     float* __restrict__ grad, float* __restrict__ seg,
+                                                     uint32_t* status) {
+    const int64_t lane = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = (int)(lane >> 2);
+    const int s = (int)(lane & 3);
+    if (i >= N) return;
+    const int H = c.H, T = c.T;
+    const int64_t stride = 6 * B * g.lanes;  // floats per tape entry
+
+    // entry index of each phase start
+    int ent[kMaxPushes];
+    {
+        int e = 0;
+        for (int k = 0; k < H; ++k) {
+            const int tk = phase_start(k, T, H), tk1 = phase_start(k + 1, T, H);
+            ent[k] = (g.ckpt == 0) ? tk : e;
+            if (g.ckpt) e += (tk1 - tk + g.ckpt - 1) / g.ckpt;
+        }
+    }
+    // phase-start positions P_k and the final block-0 pose
+    float Px[kMaxPushes + 1], Py[kMaxPushes + 1];
+    for (int k = 0; k < H; ++k) {
+        Px[k] = tape[ent[k] * stride + 0 * g.lanes + lane];
+        Py[k] = tape[ent[k] * stride + 1 * g.lanes + lane];
+    }
+    float phT;
+    {
+        const float z = side_weight(theta, N, i, H - 1, s);
+        const float* e = tape + g.ends_off + (int64_t)(H - 1) * stride;
+        Px[H] = quad_sum(z * e[0 * g.lanes + lane]);
+        Py[H] = quad_sum(z * e[1 * g.lanes + lane]);
+        phT = quad_sum(z * e[2 * g.lanes + lane]);
+    }
+    const float cb = cost_bar ? cost_bar[i] : cb_scalar;
+
+    // dC/dP_k and dC/dphi_T, scaled by cost_bar
+    float Pxb[kMaxPushes + 1], Pyb[kMaxPushes + 1];
+    for (int k = 0; k <= H; ++k) Pxb[k] = Pyb[k] = 0.0f;
+    {
+        const float ux = Px[H] - c.goal[0], uy = Py[H] - c.goal[1];
+        Pxb[H] += cb * c.wt * 2.0f * relu(fabsf(ux) - c.tol) * copysignf(1.0f, ux);
+        Pyb[H] += cb * c.wt * 2.0f * relu(fabsf(uy) - c.tol) * copysignf(1.0f, uy);
+    }
+    const float phTb = cb * c.wr * sinf(phT - c.goal[2]);
+    const float wtr = cb * c.wtr;
+    for (int k = 1; k <= H; ++k) {
+        float u, d;
+        u = Px[k - 1] - Px[k];  d = wtr * u / smooth_abs(u, c.ea2);  Pxb[k - 1] += d; Pxb[k] -= d;
+        u = Py[k - 1] - Py[k];  d = wtr * u / smooth_abs(u, c.ea2);  Pyb[k - 1] += d; Pyb[k] -= d;
+        u = Px[k] - Px[H];      d = wtr * u / smooth_abs(u, c.ea2);  Pxb[k] += d;     Pxb[H] -= d;
+        u = Py[k] - Py[H];      d = wtr * u / smooth_abs(u, c.ea2);  Pyb[k] += d;     Pyb[H] -= d;
+        u = Px[k - 1] - Px[H];  d = wtr * u / smooth_abs(u, c.ea2);  Pxb[k - 1] -= d; Pxb[H] += d;
+        u = Py[k - 1] - Py[H];  d = wtr * u / smooth_abs(u, c.ea2);  Pyb[k - 1] -= d; Pyb[H] += d;
+    }
+
+    // adjoint of S_H
+    State<B> Ls;
+#pragma unroll
+    for (int b = 0; b < B; ++b) Ls.x[b] = Ls.y[b] = Ls.ph[b] = Ls.vx[b] = Ls.vy[b] = Ls.om[b] = 0.0f;
+    Ls.x[0] = Pxb[H];
+    Ls.y[0] = Pyb[H];
+    Ls.ph[0] = phTb;
+
+    Push p;
+    side_frame(s, p);
+    bool bad = false;
+    for (int k = H - 1; k >= 0; --k) {
+        const int tk = phase_start(k, T, H), tk1 = phase_start(k + 1, T, H);
+        const float Lk = (float)(tk1 - tk);
+        const float z = side_weight(theta, N, i, k, s);
+        p.o = theta[(int64_t)(6 * k + 4) * N + i];
+        p.D = theta[(int64_t)(6 * k + 5) * N + i];
+        // phase end: S_{k+1} = sum_s z_s X_s
+        State<B> Xe, L;
+        load_state(Xe, tape + g.ends_off + (int64_t)k * stride, g.lanes, lane);
+        float zb = 0.0f;
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            zb += Ls.x[b] * Xe.x[b] + Ls.y[b] * Xe.y[b] + Ls.ph[b] * Xe.ph[b] + Ls.vx[b] * Xe.vx[b] +
+                  Ls.vy[b] * Xe.vy[b] + Ls.om[b] * Xe.om[b];
+            L.x[b] = z * Ls.x[b];
+            L.y[b] = z * Ls.y[b];
+            L.ph[b] = z * Ls.ph[b];
+            L.vx[b] = z * Ls.vx[b];
+            L.vy[b] = z * Ls.vy[b];
+            L.om[b] = z * Ls.om[b];
+        }
+        const float ab = z * (zb - quad_sum(z * zb));  // softmax VJP
+        // anchor of the phase
+        const float* ea = tape + ent[k] * stride;
+        p.Ax = ea[0 * g.lanes + lane];
+        p.Ay = ea[1 * g.lanes + lane];
+        const float Aph = ea[2 * g.lanes + lane];
+        sincosf(Aph, &p.sA, &p.cA);
+        float ob = 0.0f, Db = 0.0f, Axb = 0.0f, Ayb = 0.0f, cAb = 0.0f, sAb = 0.0f;
+        if (g.ckpt == 0) {
+            for (int t = tk1 - 1; t >= tk; --t) {
+                State<B> X;
+                load_state(X, tape + (int64_t)t * stride, g.lanes, lane);
+                const float sig = push_profile((float)(t - tk + 1) / Lk);
+                step_reverse<B>(c, X, L, p, sig, ob, Db, Axb, Ayb, cAb, sAb);
+            }
+        } else {
+            const int nseg = (tk1 - tk + g.ckpt - 1) / g.ckpt;
+            for (int j = nseg - 1; j >= 0; --j) {
+                const int ts = tk + j * g.ckpt;
+                const int te = min(ts + g.ckpt, tk1);
+                State<B> X;
+                load_state(X, tape + (int64_t)(ent[k] + j) * stride, g.lanes, lane);
+                for (int t = ts; t < te; ++t) {  // replay the segment
+                    store_state(X, seg + (int64_t)(t - ts) * stride, g.lanes, lane);
+                    step_forward<B>(c, X, p, push_profile((float)(t - tk + 1) / Lk));
+                }
+                for (int t = te - 1; t >= ts; --t) {
+                    load_state(X, seg + (int64_t)(t - ts) * stride, g.lanes, lane);
+                    const float sig = push_profile((float)(t - tk + 1) / Lk);
+                    step_reverse<B>(c, X, L, p, sig, ob, Db, Axb, Ayb, cAb, sAb);
+                }
+            }
+        }
+        const float Aphb = -cAb * p.sA + sAb * p.cA;
+        // adjoint of S_k: the four sub-rollouts share it
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            Ls.x[b] = quad_sum(L.x[b]);
+            Ls.y[b] = quad_sum(L.y[b]);
+            Ls.ph[b] = quad_sum(L.ph[b]);
+            Ls.vx[b] = quad_sum(L.vx[b]);
+            Ls.vy[b] = quad_sum(L.vy[b]);
+            Ls.om[b] = quad_sum(L.om[b]);
+        }
+        Ls.x[0] += quad_sum(Axb) + Pxb[k];
+        Ls.y[0] += quad_sum(Ayb) + Pyb[k];
+        Ls.ph[0] += quad_sum(Aphb);
+        // bound loss on o_k, D_k
+        const float wb2 = 2.0f * cb * c.wb;
+        const float obt = quad_sum(ob) + wb2 * relu(fabsf(p.o) - c.omax) * copysignf(1.0f, p.o);
+        const float Dbt = quad_sum(Db) + wb2 * (relu(p.D - c.dmax) - relu(-p.D));
+        grad[(int64_t)(6 * k + s) * N + i] = ab;
+        if (s == 0) grad[(int64_t)(6 * k + 4) * N + i] = obt;
+        if (s == 1) grad[(int64_t)(6 * k + 5) * N + i] = Dbt;
+        bad = bad || !isfinite(ab) || !isfinite(obt) || !isfinite(Dbt);
+    }
+    if (status && bad) atomicOr(status, STAMP_STATUS_NONFINITE_GRAD);
+}
+
+// ---------------------------------------------------------------------------
+template <int B>
+static hipError_t launch_fwd_b(const SimConst& c, int N, const float* theta, float* cost, float* tape,
+                               const TapeGeom& g, uint32_t* status, hipStream_t st) {
+    const int64_t lanes = 4 * (int64_t)N;
+    const unsigned grid = (unsigned)((lanes + 255) / 256);
+    hipLaunchKernelGGL(k_rollout_fwd<B>, dim3(grid), dim3(256), 0, st, c, N, theta, cost, tape, g, status);
+    return hipGetLastError();
+}
+
+template <int B>
+static hipError_t launch_adj_b(const SimConst& c, int N, const float* theta, const float* tape,
+                               const TapeGeom& g, const float* cost_bar, float cb_scalar, float* grad,
+                               float* seg, uint32_t* status, hipStream_t st) {
+    const int64_t lanes = 4 * (int64_t)N;
+    const unsigned grid = (unsigned)((lanes + 255) / 256);
+    hipLaunchKernelGGL(k_rollout_adj<B>, dim3(grid), dim3(256), 0, st, c, N, theta, tape, g, cost_bar,
+                       cb_scalar, grad, seg, status);
+    return hipGetLastError();
+}
+
+hipError_t launch_rollout_fwd(const SimConst& c, int N, const float* theta, float* cost, float* tape,
+                              const TapeGeom& g, uint32_t* status, hipStream_t st) {
+    switch (c.B) {
+        case 1: return launch_fwd_b<1>(c, N, theta, cost, tape, g, status, st);
+        case 2: return launch_fwd_b<2>(c, N, theta, cost, tape, g, status, st);
+        case 3: return launch_fwd_b<3>(c, N, theta, cost, tape, g, status, st);
+        case 4: return launch_fwd_b<4>(c, N, theta, cost, tape, g, status, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_rollout_adj(const SimConst& c, int N, const float* theta, const float* tape,
+                              const TapeGeom& g, const float* cost_bar, float cb_scalar, float* grad,
+                              float* seg, uint32_t* status, hipStream_t st) {
+    switch (c.B) {
+        case 1: return launch_adj_b<1>(c, N, theta, tape, g, cost_bar, cb_scalar, grad, seg, status, st);
+        case 2: return launch_adj_b<2>(c, N, theta, tape, g, cost_bar, cb_scalar, grad, seg, status, st);
+        case 3: return launch_adj_b<3>(c, N, theta, tape, g, cost_bar, cb_scalar, grad, seg, status, st);
+        case 4: return launch_adj_b<4>(c, N, theta, tape, g, cost_bar, cb_scalar, grad, seg, status, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace stamp

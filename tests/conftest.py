@@ -17,3 +17,15 @@ def pytest_configure(config):
 def _torch_threads():
     import torch
     torch.set_num_threads(min(8, os.cpu_count() or 1))
+
+
+@pytest.fixture(scope="session")
+def ctx():
+    """A library context on cuda:0; GPU tests fail loudly without a GPU."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU test selected but no HIP device is visible")
+    import paper_2310_01775_amd as S
+    c = S.Context(0)
+    yield c
+    c.close()

@@ -1,0 +1,147 @@
+"""GPU rollout forward and adjoint against the FP64 oracle, through the C ABI.
+
+FP32 tolerance: each step's force evaluation rounds at ~6e-8 relative and the
+trajectory carries the error forward through T steps; the measured relative
+error of the cost stays well under the 1e-4 that the FP32 paths are held to.
+Gradients are compared relative to each particle's largest gradient entry."""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import sim
+
+pytestmark = pytest.mark.gpu
+
+CASES = [
+    # (label, scene builder, N)
+    ("cfg1", lambda: W.config_problem(1)[0], 32),
+    ("b3h3t60-ragged", lambda: W.make_scene(2, 1, 3, 3, 60, 0.005), 37),
+    ("b4h2t40", lambda: W.make_scene(4, 2, 4, 2, 40, 0.005), 70),
+    ("b2h5t23-uneven", lambda: W.make_scene(4, 3, 2, 5, 23, 0.005), 5),
+    ("b1h1t1", lambda: W.make_scene(4, 4, 1, 1, 1, 0.01), 3),
+]
+
+
+def _setup(label, builder, N, seed=0):
+    import paper_2310_01775_amd as S
+    scene = builder()
+    w = W.cost_weights(rot=2.0)
+    th = W.make_particles(7, seed, N, scene["H"])
+    return S, scene, w, th
+
+
+@pytest.mark.parametrize("label,builder,N", CASES, ids=[c[0] for c in CASES])
+def test_forward_cost_and_tape_match_oracle(ctx, label, builder, N):
+    S, scene, w, th = _setup(label, builder, N)
+    print("case", label, flush=True)
+    sc, cw = S.make_scene(scene), S.make_cost(w)
+    theta = S.soa(th)
+    tape = torch.empty(ctx.tape_floats(sc, N, 0), dtype=torch.float32, device="cuda")
+    cost = ctx.rollout_fwd(sc, cw, theta, tape=tape)
+    torch.cuda.synchronize()
+    ref_cost, ref_tape, ref_ends, _ = sim.record(scene, w, th)
+    c = cost.cpu().double().numpy()
+    rel = np.abs(c - ref_cost) / np.maximum(np.abs(ref_cost), 1e-3)
+    print("max cost rel err", rel.max(), flush=True)
+    assert rel.max() < 1e-4
+    T, B, H = scene["T"], scene["B"], scene["H"]
+    tp = tape.cpu().double().numpy()
+    got = tp[: T * 6 * B * 4 * N].reshape(T, 6 * B, N, 4)
+    ends = tp[T * 6 * B * 4 * N:].reshape(H, 6 * B, N, 4)
+    # per state component: its largest magnitude over the run, floored at
+    # 1 cm, 1 cm/s, 0.01 rad (obstacles that never move hold ~1e-20 values)
+    scale = np.maximum(np.maximum(np.abs(ref_tape).max(axis=(0, 2, 3), keepdims=True),
+                                  np.abs(ref_ends).max(axis=(0, 2, 3), keepdims=True)), 1e-2)
+    e_tape = float((np.abs(got - ref_tape) / scale).max())
+    e_ends = float((np.abs(ends - ref_ends) / scale[0]).max())
+    print("tape err", e_tape, "ends err", e_ends, flush=True)
+    assert e_tape < 1e-4 and e_ends < 1e-4
+
+
+@pytest.mark.parametrize("label,builder,N", CASES, ids=[c[0] for c in CASES])
+def test_adjoint_matches_oracle_gradient(ctx, label, builder, N):
+    S, scene, w, th = _setup(label, builder, N, seed=1)
+    print("case", label, flush=True)
+    sc, cw = S.make_scene(scene), S.make_cost(w)
+    theta = S.soa(th)
+    tape = torch.empty(ctx.tape_floats(sc, N, 0), dtype=torch.float32, device="cuda")
+    ctx.rollout_fwd(sc, cw, theta, tape=tape)
+    rng = np.random.default_rng(3)
+    cb = rng.uniform(-2, 2, N)
+    cbar = torch.tensor(cb, dtype=torch.float32, device="cuda")
+    grad = ctx.rollout_adj(sc, cw, theta, tape, cost_bar=cbar)
+    torch.cuda.synchronize()
+    _, ref = sim.cost_and_grad(scene, w, th, cost_bar=cb.astype(np.float32).astype(np.float64))
+    g = S.aos(grad)
+    scale = np.abs(ref).max(axis=1, keepdims=True) + 1e-6
+    err = (np.abs(g - ref) / scale).max()
+    print("max grad err / particle scale", err, flush=True)
+    assert err < 1e-3
+
+
+@pytest.mark.parametrize("K", [1, 7, 32])
+def test_checkpointed_adjoint_equals_full_tape(ctx, K):
+    import paper_2310_01775_amd as S
+    scene = W.make_scene(3, 0, 2, 4, 150, 0.002)
+    w = W.cost_weights(rot=1.0)
+    N = 45
+    th = W.make_particles(3, 0, N, 4)
+    sc, cw = S.make_scene(scene), S.make_cost(w)
+    theta = S.soa(th)
+    full = torch.empty(ctx.tape_floats(sc, N, 0), dtype=torch.float32, device="cuda")
+    c0 = ctx.rollout_fwd(sc, cw, theta, tape=full)
+    g0 = ctx.rollout_adj(sc, cw, theta, full)
+    ck = torch.empty(ctx.tape_floats(sc, N, K), dtype=torch.float32, device="cuda")
+    c1 = ctx.rollout_fwd(sc, cw, theta, tape=ck, ckpt_every=K)
+    g1 = ctx.rollout_adj(sc, cw, theta, ck, ckpt_every=K)
+    torch.cuda.synchronize()
+    assert torch.equal(c0, c1)
+    assert torch.equal(g0, g1)  # replay repeats the forward arithmetic exactly
+    assert ck.numel() < full.numel() or K == 1
+
+
+def test_one_hot_plan_and_status_word(ctx):
+    import paper_2310_01775_amd as S
+    scene = W.make_scene(2, 0, 3, 3, 90, 0.005)
+    w = W.cost_weights()
+    th = np.zeros((4, 18))
+    for i in range(4):
+        for k in range(3):
+            th[i, 6 * k:6 * k + 4] = -20
+            th[i, 6 * k + (i + k) % 4] = 20
+            th[i, 6 * k + 4] = 0.01 * (i - 1.5)
+            th[i, 6 * k + 5] = 0.1
+    sc, cw = S.make_scene(scene), S.make_cost(w)
+    st = ctx.status_word()
+    cost = ctx.rollout_fwd(sc, cw, S.soa(th), status=st)
+    torch.cuda.synchronize()
+    assert np.allclose(cost.cpu().double().numpy(), sim.cost_np(scene, w, th), rtol=1e-4)
+    assert int(st.item()) == 0
+    bad = th.copy()
+    bad[0, 5] = np.nan
+    cost = ctx.rollout_fwd(sc, cw, S.soa(bad), status=st)
+    torch.cuda.synchronize()
+    assert int(st.item()) & S.STATUS_NONFINITE_COST
+
+
+def test_argument_errors(ctx):
+    import paper_2310_01775_amd as S
+    scene = W.make_scene(2, 0, 1, 2, 50, 0.01)
+    sc, cw = S.make_scene(scene), S.make_cost(W.cost_weights())
+    theta = S.soa(W.make_particles(2, 0, 4, 2))
+    bad = S.make_scene(scene)
+    bad.H = 9
+    with pytest.raises(S.StampError) as e:
+        ctx.rollout_fwd(bad, cw, theta)
+    assert e.value.code == S.EINVAL and "H=9" in str(e.value)
+    bad = S.make_scene(scene)
+    bad.dt = 0.0
+    with pytest.raises(S.StampError):
+        ctx.rollout_fwd(bad, cw, theta)
+    tape = torch.empty(ctx.tape_floats(sc, 4, 8), dtype=torch.float32, device="cuda")
+    ctx.rollout_fwd(sc, cw, theta, tape=tape, ckpt_every=8)
+    small = torch.empty(16, dtype=torch.uint8, device="cuda")
+    with pytest.raises(S.StampError) as e:
+        ctx.rollout_adj(sc, cw, theta, tape, ckpt_every=8, workspace=small)
+    assert e.value.code == S.ENOSPACE

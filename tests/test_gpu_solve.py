@@ -1,0 +1,68 @@
+"""GPU solve (Algorithm 1, SVGD phase) against the FP64 oracle.
+
+Parity bar on particle states: |theta_gpu - theta_ref| <= 1e-4 * max_i |theta_ref[:, l]|
+per coordinate l, after 100 iterations at the default lr 1e-3 (the regime in
+which the FP64 oracle is itself well-conditioned; see the conditioning test)."""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import svgd
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _gpu_solve(ctx, scene, w, th, iters, lr, ckpt=0):
+    import paper_2310_01775_amd as S
+    N, d = th.shape
+    theta = S.soa(th)
+    m = torch.zeros_like(theta)
+    v = torch.zeros_like(theta)
+    cfg = S.make_cfg(iters, lr=lr, ckpt_every=ckpt)
+    modes = torch.empty(scene["H"] * N, dtype=torch.int32, device="cuda")
+    st = ctx.status_word()
+    cost = ctx.solve([S.make_scene(scene)], [S.make_cost(w)], [N], cfg, theta, m, v, modes_out=modes, status=st)
+    torch.cuda.synchronize()
+    assert int(st.item()) == 0
+    return S.aos(theta), cost.cpu().double().numpy(), modes.cpu().numpy().reshape(scene["H"], N).T
+
+
+def _rel_err(got, ref):
+    scale = np.abs(ref).max(axis=0, keepdims=True)
+    return (np.abs(got - ref) / scale).max()
+
+
+def test_cfg1_solve_100_iterations(ctx):
+    scene, w, th = W.config_problem(1)
+    got, cost, modes = _gpu_solve(ctx, scene, w, th, 100, 1e-3)
+    ref = svgd.solve(scene, w, th, 100, lr=1e-3)
+    err = _rel_err(got, ref["theta"])
+    print("cfg1 100-iteration state error", err, flush=True)
+    assert err < 1e-4
+    assert np.allclose(cost, ref["cost"], rtol=1e-3, atol=1e-3)
+    assert np.array_equal(modes, ref["modes"])
+
+
+def test_cfg1_checkpointed_solve_equals_full_tape(ctx):
+    scene, w, th = W.config_problem(1)
+    a = _gpu_solve(ctx, scene, w, th, 10, 1e-3, ckpt=0)
+    b = _gpu_solve(ctx, scene, w, th, 10, 1e-3, ckpt=8)
+    assert np.array_equal(a[0], b[0])
+
+
+@pytest.mark.parametrize("name", ["cfg2_solve_lr1e-3_it100", "cfg2_solve_lr1e-2_it20"])
+def test_cfg2_solve_matches_stored_oracle(ctx, name):
+    path = os.path.join(GOLDEN, name + ".npz")
+    gold = np.load(path)
+    scene, w, th = W.config_problem(int(gold["cfg"]))
+    got, cost, modes = _gpu_solve(ctx, scene, w, th, int(gold["iters"]), float(gold["lr"]))
+    err = _rel_err(got, gold["theta"])
+    print(name, "state error", err, flush=True)
+    assert err < 1e-4
+    agree = (modes == gold["modes"]).mean()
+    print("mode agreement", agree, flush=True)
+    assert agree == 1.0

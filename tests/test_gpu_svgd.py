@@ -1,0 +1,93 @@
+"""GPU SVGD step (median bandwidth + Eq. (1) direction) and update against the
+FP64 oracle, through the C ABI."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import svgd
+
+pytestmark = pytest.mark.gpu
+
+
+def _pair_sqdist(th):
+    diff = th[:, None, :] - th[None, :, :]
+    D = (diff * diff).sum(-1)
+    return D[np.triu_indices(th.shape[0], 1)]
+
+
+@pytest.mark.parametrize("N,d", [(2, 6), (3, 2), (37, 12), (64, 18), (65, 18), (130, 30), (1024, 18), (777, 48)])
+def test_median_bandwidth_is_the_exact_order_statistic(ctx, N, d):
+    import paper_2310_01775_amd as S
+    print("case", N, d, flush=True)
+    rng = np.random.default_rng(N * 100 + d)
+    th = rng.standard_normal((N, d)).astype(np.float32).astype(np.float64)
+    g = rng.standard_normal((N, d))
+    h_out = torch.zeros(1, dtype=torch.float32, device="cuda")
+    ctx.svgd_step(S.soa(th), S.soa(g), 0.0, h_out=h_out)
+    torch.cuda.synchronize()
+    h = float(h_out.item())
+    m2 = h * math.log(N)
+    ref = svgd.median_sqdist(th)
+    assert abs(m2 - ref) <= 3e-6 * ref
+    # rank check in FP64: the selected value sits at rank ceil(P/2)
+    D = _pair_sqdist(th)
+    k = (D.size + 1) // 2
+    lo, hi = m2 * (1 - 3e-6), m2 * (1 + 3e-6)
+    assert (D < lo).sum() < k <= (D <= hi).sum()
+
+
+@pytest.mark.parametrize("N,d,bw", [(1, 6, 0.0), (2, 6, 0.0), (37, 12, 0.0), (65, 18, 2.5), (300, 18, 0.0),
+                                    (1024, 18, 0.0), (513, 30, 0.0), (200, 48, 0.0)])
+def test_phi_matches_oracle(ctx, N, d, bw):
+    import paper_2310_01775_amd as S
+    print("case", N, d, bw, flush=True)
+    rng = np.random.default_rng(N + d)
+    th = rng.standard_normal((N, d)).astype(np.float32).astype(np.float64)
+    th[:, ::6] *= 0.1  # mixed coordinate scales, like offsets next to logits
+    g = (rng.standard_normal((N, d)) * 50).astype(np.float32).astype(np.float64)
+    h_out = torch.zeros(1, dtype=torch.float32, device="cuda")
+    phi = ctx.svgd_step(S.soa(th), S.soa(g), bw, h_out=h_out)
+    torch.cuda.synchronize()
+    h = svgd.bandwidth(th, bw)
+    ref = g if N == 1 else svgd.svgd_phi(th, g, h)
+    got = S.aos(phi)
+    scale = np.abs(ref).max(axis=0, keepdims=True) + 1e-9
+    err = (np.abs(got - ref) / scale).max()
+    print("phi err", err, flush=True)
+    assert err < 2e-5
+    if N == 1:
+        assert np.array_equal(got, g)
+
+
+def test_adam_and_plain_step_match_oracle(ctx):
+    import paper_2310_01775_amd as S
+    rng = np.random.default_rng(9)
+    x = rng.standard_normal((50, 18)).astype(np.float32).astype(np.float64)
+    m = np.zeros_like(x)
+    v = np.zeros_like(x)
+    tx, tm, tv = S.soa(x), S.soa(m), S.soa(v)
+    for t in range(1, 25):
+        phi = (rng.standard_normal(x.shape) * 10.0 ** rng.integers(-3, 3)).astype(np.float32).astype(np.float64)
+        x, m, v = svgd.adam_step(x, phi, m, v, t, 1e-2)
+        ctx.adam_step(tx, S.soa(phi), tm, tv, t, lr=1e-2)
+    torch.cuda.synchronize()
+    assert np.allclose(S.aos(tx), x, rtol=1e-5, atol=1e-6)
+    phi = rng.standard_normal(x.shape)
+    ctx.adam_step(tx, S.soa(phi), None, None, 1, lr=0.5, use_adam=False)
+    torch.cuda.synchronize()
+    assert np.allclose(S.aos(tx), x + 0.5 * phi.astype(np.float32), rtol=1e-5, atol=1e-6)
+
+
+def test_svgd_argument_errors(ctx):
+    import paper_2310_01775_amd as S
+    th = torch.zeros(70, 4, device="cuda")
+    with pytest.raises(S.StampError) as e:
+        ctx.svgd_step(th, th, 0.0)
+    assert e.value.code == S.EUNSUPPORTED
+    th = torch.zeros(6, 4, device="cuda")
+    small = torch.empty(8, dtype=torch.uint8, device="cuda")
+    with pytest.raises(S.StampError) as e:
+        ctx.svgd_step(th, th, 0.0, workspace=small)
+    assert e.value.code == S.ENOSPACE
