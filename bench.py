@@ -1,0 +1,189 @@
+"""Benchmark of the STAMP SVGD hot path on one MI355X.
+
+One step = one SVGD iteration of Algorithm 1 over the whole particle set:
+rollout forward (full tape) -> rollout adjoint (grad log rho) -> median
+bandwidth -> SVGD direction (Eq. 1) -> Adam update, all in the library's HIP
+kernels.  Workload: N=1024 particles, 3 blocks, 3 pushes (d=18), T=200 steps
+of dt=0.005, seeded synthetic scene and particles.
+
+Metric: particle-iterations/s = N * steps / wall seconds of the timed region
+(inputs resident in HBM, synchronised on both sides).  The dominant kernel's
+duration comes from HIP events recorded on the stream it is launched on.
+cpu_baseline times the FP64 oracle on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "SVGD particle-iters/s incl. sim fwd+adjoint; surrogate vs plain at equal cost"
+UNIT = "particle-iters/s"
+FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X published FP32 vector peak
+HBM_PEAK_GBS = 8000.0
+
+
+def rollout_flops_per_lane_step(B, adjoint=False):
+    """Algorithmic FP32 operations of one sub-rollout step (one lane), counted
+    from the forward step (friction 16/block, contact 26/pair, pusher 52,
+    integrator 15/block, time scaling 8) and its reverse (which also recomputes
+    the forward intermediates it needs)."""
+    pairs = B * (B - 1) // 2
+    if not adjoint:
+        return 16 * B + 26 * pairs + 52 + 15 * B + 8
+    return 12 * B + 36 * B + 54 * pairs + 119 + 8
+
+
+def rollout_bytes(N, d, B, T, H):
+    """Algorithmic HBM bytes of one forward (or adjoint) launch with the full
+    tape: theta (4d per particle), the tape of (T+H) states of 6B floats for
+    each of the 4 side lanes, and the per-particle output (cost, or 4d grad)."""
+    tape = (T + H) * 6 * B * 4 * 4
+    return N * (4 * d + tape), N * (4 * d + tape + 4 * d)
+
+
+def cpu_baseline(seconds_target=15.0):
+    """Time the FP64 oracle (as it stands) on a bounded sample of the same
+    workload: full N=1024 scene, a few iterations of rollout+autodiff gradient,
+    median bandwidth, phi and Adam."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from oracle import sim, svgd
+
+    threads = os.cpu_count() or 1
+    torch.set_num_threads(threads)
+    scene, w, th = W.config_problem(2)
+    N = th.shape[0]
+    m = np.zeros_like(th)
+    v = np.zeros_like(th)
+    t0 = time.perf_counter()
+    it = 0
+    while True:
+        _, dC = sim.cost_and_grad(scene, w, th)
+        h = svgd.bandwidth(th)
+        phi = svgd.svgd_phi(th, -dC, h)
+        th, m, v = svgd.adam_step(th, phi, m, v, it + 1, 1e-3)
+        it += 1
+        el = time.perf_counter() - t0
+        if el > seconds_target or it >= 20:
+            break
+    return {"value": N * it / el, "unit": UNIT, "cores": torch.get_num_threads(), "kind": "oracle",
+            "sample": f"{it} SVGD iterations of the N={N}, B=3, H=3, T=200 workload in FP64 "
+                      f"(torch CPU autodiff rollout + numpy SVGD), {el:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="only run a plain device copy of this many MiB (HBM counter calibration)")
+    args = ap.parse_args()
+    if args.calibrate_copy_mib:
+        import torch
+        n = args.calibrate_copy_mib * (1 << 20) // 4
+        x = torch.ones(n, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 3}))
+        return
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the particle set would shard by particle with one all-gather of "
+              "[theta | grad] per iteration; see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2310_01775_amd as S
+    import workloads as W
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    cfg = W.CONFIGS[2]
+    scene, w, th = W.config_problem(2)
+    N, d, B, T, H = th.shape[0], th.shape[1], scene["B"], scene["T"], scene["H"]
+    ctx = S.Context(0)
+    sc, cw = S.make_scene(scene), S.make_cost(w)
+    theta = S.soa(th)
+    m = torch.zeros_like(theta)
+    v = torch.zeros_like(theta)
+    tape = torch.empty(ctx.tape_floats(sc, N, 0), dtype=torch.float32, device=dev)
+    cost = torch.empty(N, dtype=torch.float32, device=dev)
+    grad = torch.empty_like(theta)
+    phi = torch.empty_like(theta)
+    minus_one = torch.full((N,), -1.0, dtype=torch.float32, device=dev)
+    sws = torch.empty(ctx.svgd_workspace_bytes(N, d), dtype=torch.uint8, device=dev)
+    status = ctx.status_word()
+    lr = W.DEFAULT_ADAM["lr"]
+
+    def iteration(t, evs=None):
+        if evs:
+            evs[0].record()
+        ctx.rollout_fwd(sc, cw, theta, tape=tape, cost=cost, status=status)
+        if evs:
+            evs[1].record()
+        ctx.rollout_adj(sc, cw, theta, tape, cost_bar=minus_one, grad=grad, status=status)
+        if evs:
+            evs[2].record()
+        ctx.svgd_step(theta, grad, 0.0, phi=phi, workspace=sws)
+        ctx.adam_step(theta, phi, m, v, t, lr=lr)
+        if evs:
+            evs[3].record()
+
+    for t in range(1, args.warmup + 1):
+        iteration(t)
+    torch.cuda.synchronize()
+    events = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        iteration(args.warmup + k + 1, events[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    assert int(status.item()) == 0, "non-finite values during the benchmark"
+
+    fwd_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in events]))
+    adj_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in events]))
+    svgd_ms = float(np.mean([e[2].elapsed_time(e[3]) for e in events]))
+    value = N * args.steps / wall
+    fl_f = rollout_flops_per_lane_step(B) * 4 * N * T
+    fl_a = rollout_flops_per_lane_step(B, True) * 4 * N * T
+    by_f, by_a = rollout_bytes(N, d, B, T, H)
+    dom = "rollout_adj" if adj_ms >= fwd_ms else "rollout_fwd"
+    dom_ms = max(adj_ms, fwd_ms)
+    dom_fl = fl_a if dom == "rollout_adj" else fl_f
+    achieved = dom_fl / (dom_ms * 1e-3) / 1e12
+    out = {
+        "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": wall * 1e3 / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"plain STAMP SVGD, FP32: N={N} particles, B={B} blocks, H={H} pushes "
+                               f"(d={d}), T={T} steps of dt={scene['dt']:.3f}, full-tape adjoint, "
+                               f"median bandwidth, Adam",
+                   "N": N, "d": d, "B": B, "H": H, "T": T, "tape": "full"},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "traffic": None,
+                     "kernel": dom, "kernel_ms": dom_ms,
+                     "hbm_GBps": (by_a if dom == "rollout_adj" else by_f) / (dom_ms * 1e-3) / 1e9},
+        "kernels_ms": {"rollout_fwd": fwd_ms, "rollout_adj": adj_ms, "svgd+update": svgd_ms},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

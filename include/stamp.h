@@ -118,8 +118,9 @@ const char* stamp_version(void);
 
 /* Floats of the rollout tape for N particles.  ckpt_every = 0 keeps the full
  * trajectory; K > 0 keeps a checkpoint every K steps inside each push phase.
- * Layout: [n_entries][6B][4N] then the phase-end block [H][6B][4N]; lane
- * 4i+s holds particle i's sub-rollout of side s.  Returns 0 on bad arguments. */
+ * Layout: [n_entries][4N][6B] then the phase-end block [H][4N][6B]: lane
+ * 4i+s holds particle i's sub-rollout of side s, its state of block b at
+ * 6b + (x, y, phi, vx, vy, omega).  Returns 0 on bad arguments. */
 size_t stamp_tape_floats(const stamp_scene* scene, int32_t N, int32_t ckpt_every);
 /* Workspace bytes of stamp_rollout_adj (segment replay buffer when K > 0). */
 size_t stamp_adj_workspace_bytes(const stamp_scene* scene, int32_t N, int32_t ckpt_every);

@@ -34,14 +34,19 @@ struct SimConst {
     float h0;                  // half size of the pushed block
     float h0d;                 // h0 + standoff
     float kp, kb, beta, inv_beta, er2;
+    float beta_log2e;          // beta * log2(e): exp(-beta|z|) = 2^(-beta_log2e |z|)
+    float ln2_over_beta;       // log1p(u)/beta = log2(1+u) * ln2/beta
     // cost (Appendix E-B)
     float goal[3], tol;
     float wt, wr, wtr, wb, omax, dmax, ea2;
 };
 
-// Layout of the rollout tape (floats):
-//   entries [n_entries][6B][4N] : pre-step states (every step, or checkpoints)
-//   ends    [H][6B][4N]         : sub-rollout states after each phase's last step
+// Layout of the rollout tape (floats), lane-contiguous so that each lane moves
+// its 6B-float state with 3B dwordx2 accesses and a wave touches one contiguous
+// 64*24B*B span per entry:
+//   entries [n_entries][4N][6B] : pre-step states (every step, or checkpoints)
+//   ends    [H][4N][6B]         : sub-rollout states after each phase's last step
+//   state order per block b: x, y, phi, vx, vy, omega
 struct TapeGeom {
     int64_t lanes;      // 4N
     int64_t n_entries;  // T, or sum_k ceil(L_k / K)
@@ -67,16 +72,28 @@ __device__ __forceinline__ float quad_sum(float v) {
     return v + quad_xor2(v);
 }
 
+// ---- hardware transcendentals (v_rsq/v_rcp/v_exp/v_log, ~1 ulp) -------------
+__device__ __forceinline__ float hw_rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ float hw_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float hw_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
+__device__ __forceinline__ float hw_log2(float x) { return __builtin_amdgcn_logf(x); }
+
 // ---- smooth penalty ---------------------------------------------------------
-// sp(z) = log(1 + exp(beta z)) / beta = max(z,0) + log1p(exp(-beta|z|)) / beta
-__device__ __forceinline__ float softplus(float z, float beta, float inv_beta) {
-    return fmaxf(z, 0.0f) + log1pf(expf(-beta * fabsf(z))) * inv_beta;
+// sp(z) = log(1 + exp(beta z)) / beta = max(z,0) + log1p(exp(-beta|z|)) / beta.
+// log1p(u) is taken as log2(1+u) ln2: for u below FP32 resolution this drops a
+// term of size u/beta (< 1e-10 m at beta = 1000), far under the step's rounding.
+__device__ __forceinline__ float softplus_u(float z, float beta_log2e) {
+    return hw_exp2(-beta_log2e * fabsf(z));
 }
-// d sp / dz = 1 / (1 + exp(-beta z)), evaluated without overflow
-__device__ __forceinline__ float softplus_grad(float z, float beta) {
-    float e = expf(-beta * fabsf(z));
-    float r = 1.0f / (1.0f + e);
-    return z >= 0.0f ? r : e * r;
+__device__ __forceinline__ float softplus(float z, float beta_log2e, float ln2_over_beta) {
+    const float u = softplus_u(z, beta_log2e);
+    return fmaxf(z, 0.0f) + hw_log2(1.0f + u) * ln2_over_beta;
+}
+// d sp / dz = 1 / (1 + exp(-beta z)), from u = exp(-beta|z|) without overflow
+__device__ __forceinline__ float softplus_grad(float z, float beta_log2e) {
+    const float u = softplus_u(z, beta_log2e);
+    const float r = hw_rcp(1.0f + u);
+    return z >= 0.0f ? r : u * r;
 }
 
 __device__ __forceinline__ float relu(float x) { return fmaxf(x, 0.0f); }

@@ -16,6 +16,10 @@
 
 namespace stamp {
 
+// One wave per workgroup: a small particle set spreads over as many CUs as it
+// has waves instead of stacking four waves on one CU.
+constexpr int kRolloutBlock = 64;
+
 template <int B>
 struct State {
     float x[B], y[B], ph[B], vx[B], vy[B], om[B];
@@ -28,31 +32,30 @@ struct Push {
     float o, D;            // contact offset and push depth of phase k
 };
 
+// Entry e of the tape holds, for every lane, its 6B-float state contiguously.
 template <int B>
-__device__ __forceinline__ void load_state(State<B>& X, const float* __restrict__ e, int64_t lanes,
-                                           int64_t lane) {
+__device__ __forceinline__ void load_state(State<B>& X, const float* __restrict__ entry, int64_t lane) {
+    const float2* p = reinterpret_cast<const float2*>(entry + lane * (6 * B));
 #pragma unroll
     for (int b = 0; b < B; ++b) {
-        X.x[b] = e[(6 * b + 0) * lanes + lane];
-        X.y[b] = e[(6 * b + 1) * lanes + lane];
-        X.ph[b] = e[(6 * b + 2) * lanes + lane];
-        X.vx[b] = e[(6 * b + 3) * lanes + lane];
-        X.vy[b] = e[(6 * b + 4) * lanes + lane];
-        X.om[b] = e[(6 * b + 5) * lanes + lane];
+        const float2 a = p[3 * b + 0], c = p[3 * b + 1], e = p[3 * b + 2];
+        X.x[b] = a.x;
+        X.y[b] = a.y;
+        X.ph[b] = c.x;
+        X.vx[b] = c.y;
+        X.vy[b] = e.x;
+        X.om[b] = e.y;
     }
 }
 
 template <int B>
-__device__ __forceinline__ void store_state(const State<B>& X, float* __restrict__ e, int64_t lanes,
-                                            int64_t lane) {
+__device__ __forceinline__ void store_state(const State<B>& X, float* __restrict__ entry, int64_t lane) {
+    float2* p = reinterpret_cast<float2*>(entry + lane * (6 * B));
 #pragma unroll
     for (int b = 0; b < B; ++b) {
-        e[(6 * b + 0) * lanes + lane] = X.x[b];
-        e[(6 * b + 1) * lanes + lane] = X.y[b];
-        e[(6 * b + 2) * lanes + lane] = X.ph[b];
-        e[(6 * b + 3) * lanes + lane] = X.vx[b];
-        e[(6 * b + 4) * lanes + lane] = X.vy[b];
-        e[(6 * b + 5) * lanes + lane] = X.om[b];
+        p[3 * b + 0] = make_float2(X.x[b], X.y[b]);
+        p[3 * b + 1] = make_float2(X.ph[b], X.vx[b]);
+        p[3 * b + 2] = make_float2(X.vy[b], X.om[b]);
     }
 }
 
@@ -63,10 +66,10 @@ __device__ __forceinline__ void step_forward(const SimConst& c, State<B>& X, con
     // regularised Coulomb friction, every block
 #pragma unroll
     for (int b = 0; b < B; ++b) {
-        float inv = 1.0f / sqrtf(X.vx[b] * X.vx[b] + X.vy[b] * X.vy[b] + c.ev2[b]);
+        const float inv = hw_rsq(X.vx[b] * X.vx[b] + X.vy[b] * X.vy[b] + c.ev2[b]);
         Fx[b] = -c.cf[b] * X.vx[b] * inv;
         Fy[b] = -c.cf[b] * X.vy[b] * inv;
-        float invw = 1.0f / sqrtf(X.om[b] * X.om[b] + c.ew2[b]);
+        const float invw = hw_rsq(X.om[b] * X.om[b] + c.ew2[b]);
         Tq[b] = -c.cr[b] * X.om[b] * invw;
     }
     // block-block penalty on the inscribed disks, central force
@@ -74,30 +77,32 @@ __device__ __forceinline__ void step_forward(const SimConst& c, State<B>& X, con
     for (int b = 0; b < B; ++b) {
 #pragma unroll
         for (int q = b + 1; q < B; ++q) {
-            float dx = X.x[b] - X.x[q], dy = X.y[b] - X.y[q];
-            float r = sqrtf(dx * dx + dy * dy + c.er2);
-            float f = c.kb * softplus(c.hsum[b][q] - r, c.beta, c.inv_beta);
-            float ux = dx / r, uy = dy / r;
-            Fx[b] += f * ux;
-            Fy[b] += f * uy;
-            Fx[q] -= f * ux;
-            Fy[q] -= f * uy;
+            const float dx = X.x[b] - X.x[q], dy = X.y[b] - X.y[q];
+            const float d2 = dx * dx + dy * dy + c.er2;
+            const float rinv = hw_rsq(d2);
+            const float r = d2 * rinv;
+            const float f = c.kb * softplus(c.hsum[b][q] - r, c.beta_log2e, c.ln2_over_beta);
+            const float fr = f * rinv;
+            Fx[b] += fr * dx;
+            Fy[b] += fr * dy;
+            Fx[q] -= fr * dx;
+            Fy[q] -= fr * dy;
         }
     }
     // the virtual pusher of this side, on block 0
     {
-        float depth = c.h0d - p.D * sig;
-        float qx = depth * p.nx + p.o * p.tx, qy = depth * p.ny + p.o * p.ty;
-        float psx = p.Ax + p.cA * qx - p.sA * qy;
-        float psy = p.Ay + p.sA * qx + p.cA * qy;
-        float relx = psx - X.x[0], rely = psy - X.y[0];
+        const float depth = c.h0d - p.D * sig;
+        const float qx = depth * p.nx + p.o * p.tx, qy = depth * p.ny + p.o * p.ty;
+        const float psx = p.Ax + p.cA * qx - p.sA * qy;
+        const float psy = p.Ay + p.sA * qx + p.cA * qy;
+        const float relx = psx - X.x[0], rely = psy - X.y[0];
         float s0, c0;
         sincosf(X.ph[0], &s0, &c0);
-        float lx = c0 * relx + s0 * rely, ly = -s0 * relx + c0 * rely;
-        float pen = c.h0 - (p.nx * lx + p.ny * ly);
-        float f = c.kp * softplus(pen, c.beta, c.inv_beta);
-        float ex = c0 * p.nx - s0 * p.ny, ey = s0 * p.nx + c0 * p.ny;
-        float Fpx = -f * ex, Fpy = -f * ey;
+        const float lx = c0 * relx + s0 * rely, ly = -s0 * relx + c0 * rely;
+        const float pen = c.h0 - (p.nx * lx + p.ny * ly);
+        const float f = c.kp * softplus(pen, c.beta_log2e, c.ln2_over_beta);
+        const float ex = c0 * p.nx - s0 * p.ny, ey = s0 * p.nx + c0 * p.ny;
+        const float Fpx = -f * ex, Fpy = -f * ey;
         Fx[0] += Fpx;
         Fy[0] += Fpy;
         Tq[0] += relx * Fpy - rely * Fpx;
@@ -125,9 +130,9 @@ __device__ __forceinline__ void step_reverse(const SimConst& c, const State<B>& 
     // integrator: x' = x + dt v', v' = v + dt F/m
 #pragma unroll
     for (int b = 0; b < B; ++b) {
-        float vxb = L.vx[b] + c.dt * L.x[b];
-        float vyb = L.vy[b] + c.dt * L.y[b];
-        float omb = L.om[b] + c.dt * L.ph[b];
+        const float vxb = L.vx[b] + c.dt * L.x[b];
+        const float vyb = L.vy[b] + c.dt * L.y[b];
+        const float omb = L.om[b] + c.dt * L.ph[b];
         L.vx[b] = vxb;
         L.vy[b] = vyb;
         L.om[b] = omb;
@@ -137,33 +142,34 @@ __device__ __forceinline__ void step_reverse(const SimConst& c, const State<B>& 
     }
     // pusher
     {
-        float depth = c.h0d - p.D * sig;
-        float qx = depth * p.nx + p.o * p.tx, qy = depth * p.ny + p.o * p.ty;
-        float psx = p.Ax + p.cA * qx - p.sA * qy;
-        float psy = p.Ay + p.sA * qx + p.cA * qy;
-        float relx = psx - X.x[0], rely = psy - X.y[0];
+        const float depth = c.h0d - p.D * sig;
+        const float qx = depth * p.nx + p.o * p.tx, qy = depth * p.ny + p.o * p.ty;
+        const float psx = p.Ax + p.cA * qx - p.sA * qy;
+        const float psy = p.Ay + p.sA * qx + p.cA * qy;
+        const float relx = psx - X.x[0], rely = psy - X.y[0];
         float s0, c0;
         sincosf(X.ph[0], &s0, &c0);
-        float lx = c0 * relx + s0 * rely, ly = -s0 * relx + c0 * rely;
-        float pen = c.h0 - (p.nx * lx + p.ny * ly);
-        float f = c.kp * softplus(pen, c.beta, c.inv_beta);
-        float ex = c0 * p.nx - s0 * p.ny, ey = s0 * p.nx + c0 * p.ny;
-        float Fpx = -f * ex, Fpy = -f * ey;
+        const float lx = c0 * relx + s0 * rely, ly = -s0 * relx + c0 * rely;
+        const float pen = c.h0 - (p.nx * lx + p.ny * ly);
+        const float f = c.kp * softplus(pen, c.beta_log2e, c.ln2_over_beta);
+        const float ex = c0 * p.nx - s0 * p.ny, ey = s0 * p.nx + c0 * p.ny;
+        const float Fpx = -f * ex, Fpy = -f * ey;
 
-        float Fpxb = Fxb[0], Fpyb = Fyb[0], Tpb = Tqb[0];
+        float Fpxb = Fxb[0], Fpyb = Fyb[0];
+        const float Tpb = Tqb[0];
         // T = relx Fpy - rely Fpx
         float relxb = Tpb * Fpy, relyb = -Tpb * Fpx;
         Fpyb += Tpb * relx;
         Fpxb += -Tpb * rely;
         // Fp = -f e
-        float fb = -(Fpxb * ex + Fpyb * ey);
-        float exb = -Fpxb * f, eyb = -Fpyb * f;
+        const float fb = -(Fpxb * ex + Fpyb * ey);
+        const float exb = -Fpxb * f, eyb = -Fpyb * f;
         // e = R(phi0) n
         float c0b = exb * p.nx + eyb * p.ny;
         float s0b = -exb * p.ny + eyb * p.nx;
         // f = kp sp(pen), pen = h0 - n.l
-        float penb = fb * c.kp * softplus_grad(pen, c.beta);
-        float lxb = -penb * p.nx, lyb = -penb * p.ny;
+        const float penb = fb * c.kp * softplus_grad(pen, c.beta_log2e);
+        const float lxb = -penb * p.nx, lyb = -penb * p.ny;
         // l = R(phi0)^T rel
         c0b += lxb * relx + lyb * rely;
         s0b += lxb * rely - lyb * relx;
@@ -178,32 +184,32 @@ __device__ __forceinline__ void step_reverse(const SimConst& c, const State<B>& 
         Ay_b += relyb;
         cA_b += relxb * qx + relyb * qy;
         sA_b += -relxb * qy + relyb * qx;
-        float qxb = relxb * p.cA + relyb * p.sA;
-        float qyb = -relxb * p.sA + relyb * p.cA;
+        const float qxb = relxb * p.cA + relyb * p.sA;
+        const float qyb = -relxb * p.sA + relyb * p.cA;
         // q = depth n + o t, depth = h0 + standoff - D s(tau)
-        float depthb = qxb * p.nx + qyb * p.ny;
+        const float depthb = qxb * p.nx + qyb * p.ny;
         o_b += qxb * p.tx + qyb * p.ty;
         D_b += -depthb * sig;
     }
-    // block-block contacts
+    // block-block contacts: F_b += f u, F_c -= f u with u = Delta / r
 #pragma unroll
     for (int b = 0; b < B; ++b) {
 #pragma unroll
         for (int q = b + 1; q < B; ++q) {
-            float dx = X.x[b] - X.x[q], dy = X.y[b] - X.y[q];
-            float r = sqrtf(dx * dx + dy * dy + c.er2);
-            float pen = c.hsum[b][q] - r;
-            float f = c.kb * softplus(pen, c.beta, c.inv_beta);
-            float ux = dx / r, uy = dy / r;
-            float gx = Fxb[b] - Fxb[q], gy = Fyb[b] - Fyb[q];
-            float fb = gx * ux + gy * uy;
-            float uxb = f * gx, uyb = f * gy;
-            float invr = 1.0f / r;
-            float dxb = uxb * invr, dyb = uyb * invr;
-            float rb = -(uxb * dx + uyb * dy) * invr * invr;
-            rb += -fb * c.kb * softplus_grad(pen, c.beta);
-            dxb += rb * dx * invr;
-            dyb += rb * dy * invr;
+            const float dx = X.x[b] - X.x[q], dy = X.y[b] - X.y[q];
+            const float d2 = dx * dx + dy * dy + c.er2;
+            const float rinv = hw_rsq(d2);
+            const float r = d2 * rinv;
+            const float pen = c.hsum[b][q] - r;
+            const float f = c.kb * softplus(pen, c.beta_log2e, c.ln2_over_beta);
+            const float gx = Fxb[b] - Fxb[q], gy = Fyb[b] - Fyb[q];
+            const float gu = (gx * dx + gy * dy) * rinv;   // adjoint of f
+            // d(f u)/dDelta = f/r (I - u u^T) + f'(pen)(-u) u^T, f' = kb sp'(pen)
+            const float fp = c.kb * softplus_grad(pen, c.beta_log2e);
+            const float fr = f * rinv;
+            const float k2 = (fr + fp) * gu * rinv;  // coefficient of Delta
+            const float dxb = fr * gx - k2 * dx;
+            const float dyb = fr * gy - k2 * dy;
             L.x[b] += dxb;
             L.x[q] -= dxb;
             L.y[b] += dyb;
@@ -213,12 +219,12 @@ __device__ __forceinline__ void step_reverse(const SimConst& c, const State<B>& 
     // friction
 #pragma unroll
     for (int b = 0; b < B; ++b) {
-        float inv = 1.0f / sqrtf(X.vx[b] * X.vx[b] + X.vy[b] * X.vy[b] + c.ev2[b]);
-        float inv3 = inv * inv * inv;
-        float dotF = Fxb[b] * X.vx[b] + Fyb[b] * X.vy[b];
+        const float inv = hw_rsq(X.vx[b] * X.vx[b] + X.vy[b] * X.vy[b] + c.ev2[b]);
+        const float inv3 = inv * inv * inv;
+        const float dotF = Fxb[b] * X.vx[b] + Fyb[b] * X.vy[b];
         L.vx[b] += -c.cf[b] * inv * Fxb[b] + c.cf[b] * inv3 * X.vx[b] * dotF;
         L.vy[b] += -c.cf[b] * inv * Fyb[b] + c.cf[b] * inv3 * X.vy[b] * dotF;
-        float invw = 1.0f / sqrtf(X.om[b] * X.om[b] + c.ew2[b]);
+        const float invw = hw_rsq(X.om[b] * X.om[b] + c.ew2[b]);
         L.om[b] += -c.cr[b] * Tqb[b] * c.ew2[b] * invw * invw * invw;
     }
 }
@@ -246,7 +252,7 @@ __device__ __forceinline__ float smooth_abs(float u, float ea2) { return sqrtf(u
 
 // ---------------------------------------------------------------------------
 template <int B>
-__global__ __launch_bounds__(256) void k_rollout_fwd(SimConst c, int N, const float* __restrict__ theta,
+__global__ __launch_bounds__(kRolloutBlock) void k_rollout_fwd(SimConst c, int N, const float* __restrict__ theta,
                                                      float* __restrict__ cost, float* __restrict__ tape,
                                                      TapeGeom g, uint32_t* status) {
     const int64_t lane = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -270,7 +276,7 @@ __global__ __launch_bounds__(256) void k_rollout_fwd(SimConst c, int N, const fl
     int64_t entry = 0;
     for (int k = 0; k < H; ++k) {
         const int tk = phase_start(k, T, H), tk1 = phase_start(k + 1, T, H);
-        const float Lk = (float)(tk1 - tk);
+        const float invL = 1.0f / (float)(tk1 - tk);
         Px[k] = S.x[0];
         Py[k] = S.y[0];
         p.Ax = S.x[0];
@@ -285,16 +291,15 @@ __global__ __launch_bounds__(256) void k_rollout_fwd(SimConst c, int N, const fl
         for (int t = tk; t < tk1; ++t) {
             if (tape) {
                 if (g.ckpt == 0) {
-                    store_state(X, tape + (int64_t)t * 6 * B * g.lanes, g.lanes, lane);
+                    store_state(X, tape + (int64_t)t * 6 * B * g.lanes, lane);
                 } else if ((t - tk) % g.ckpt == 0) {
-                    store_state(X, tape + entry * 6 * B * g.lanes, g.lanes, lane);
+                    store_state(X, tape + entry * 6 * B * g.lanes, lane);
                     ++entry;
                 }
             }
-            const float sig = push_profile((float)(t - tk + 1) / Lk);
-            step_forward<B>(c, X, p, sig);
+            step_forward<B>(c, X, p, push_profile((float)(t - tk + 1) * invL));
         }
-        if (tape) store_state(X, tape + g.ends_off + (int64_t)k * 6 * B * g.lanes, g.lanes, lane);
+        if (tape) store_state(X, tape + g.ends_off + (int64_t)k * 6 * B * g.lanes, lane);
         // phase mixture
 #pragma unroll
         for (int b = 0; b < B; ++b) {
@@ -327,7 +332,7 @@ __global__ __launch_bounds__(256) void k_rollout_fwd(SimConst c, int N, const fl
 
 // ---------------------------------------------------------------------------
 template <int B>
-__global__ __launch_bounds__(256) void k_rollout_adj(SimConst c, int N, const float* __restrict__ theta,
+__global__ __launch_bounds__(kRolloutBlock) void k_rollout_adj(SimConst c, int N, const float* __restrict__ theta,
                                                      const float* __restrict__ tape, TapeGeom g,
                                                      const float* __restrict__ cost_bar, float cb_scalar,
                                                      float* __restrict__ grad, float* __restrict__ seg,
@@ -352,16 +357,16 @@ __global__ __launch_bounds__(256) void k_rollout_adj(SimConst c, int N, const fl
     // phase-start positions P_k and the final block-0 pose
     float Px[kMaxPushes + 1], Py[kMaxPushes + 1];
     for (int k = 0; k < H; ++k) {
-        Px[k] = tape[ent[k] * stride + 0 * g.lanes + lane];
-        Py[k] = tape[ent[k] * stride + 1 * g.lanes + lane];
+        Px[k] = tape[ent[k] * stride + lane * 6 * B + 0];
+        Py[k] = tape[ent[k] * stride + lane * 6 * B + 1];
     }
     float phT;
     {
         const float z = side_weight(theta, N, i, H - 1, s);
-        const float* e = tape + g.ends_off + (int64_t)(H - 1) * stride;
-        Px[H] = quad_sum(z * e[0 * g.lanes + lane]);
-        Py[H] = quad_sum(z * e[1 * g.lanes + lane]);
-        phT = quad_sum(z * e[2 * g.lanes + lane]);
+        const float* e = tape + g.ends_off + (int64_t)(H - 1) * stride + lane * 6 * B;
+        Px[H] = quad_sum(z * e[0]);
+        Py[H] = quad_sum(z * e[1]);
+        phT = quad_sum(z * e[2]);
     }
     const float cb = cost_bar ? cost_bar[i] : cb_scalar;
 
@@ -398,13 +403,13 @@ __global__ __launch_bounds__(256) void k_rollout_adj(SimConst c, int N, const fl
     bool bad = false;
     for (int k = H - 1; k >= 0; --k) {
         const int tk = phase_start(k, T, H), tk1 = phase_start(k + 1, T, H);
-        const float Lk = (float)(tk1 - tk);
+        const float invL = 1.0f / (float)(tk1 - tk);
         const float z = side_weight(theta, N, i, k, s);
         p.o = theta[(int64_t)(6 * k + 4) * N + i];
         p.D = theta[(int64_t)(6 * k + 5) * N + i];
         // phase end: S_{k+1} = sum_s z_s X_s
         State<B> Xe, L;
-        load_state(Xe, tape + g.ends_off + (int64_t)k * stride, g.lanes, lane);
+        load_state(Xe, tape + g.ends_off + (int64_t)k * stride, lane);
         float zb = 0.0f;
 #pragma unroll
         for (int b = 0; b < B; ++b) {
@@ -419,18 +424,22 @@ __global__ __launch_bounds__(256) void k_rollout_adj(SimConst c, int N, const fl
         }
         const float ab = z * (zb - quad_sum(z * zb));  // softmax VJP
         // anchor of the phase
-        const float* ea = tape + ent[k] * stride;
-        p.Ax = ea[0 * g.lanes + lane];
-        p.Ay = ea[1 * g.lanes + lane];
-        const float Aph = ea[2 * g.lanes + lane];
+        const float* ea = tape + ent[k] * stride + lane * 6 * B;
+        p.Ax = ea[0];
+        p.Ay = ea[1];
+        const float Aph = ea[2];
         sincosf(Aph, &p.sA, &p.cA);
         float ob = 0.0f, Db = 0.0f, Axb = 0.0f, Ayb = 0.0f, cAb = 0.0f, sAb = 0.0f;
         if (g.ckpt == 0) {
+            // reverse sweep over the full tape; the next (earlier) state is
+            // fetched while the current step is reversed
+            State<B> Xn;
+            load_state(Xn, tape + (int64_t)(tk1 - 1) * stride, lane);
             for (int t = tk1 - 1; t >= tk; --t) {
-                State<B> X;
-                load_state(X, tape + (int64_t)t * stride, g.lanes, lane);
-                const float sig = push_profile((float)(t - tk + 1) / Lk);
-                step_reverse<B>(c, X, L, p, sig, ob, Db, Axb, Ayb, cAb, sAb);
+                const State<B> X = Xn;
+                if (t > tk) load_state(Xn, tape + (int64_t)(t - 1) * stride, lane);
+                step_reverse<B>(c, X, L, p, push_profile((float)(t - tk + 1) * invL), ob, Db, Axb, Ayb, cAb,
+                                sAb);
             }
         } else {
             const int nseg = (tk1 - tk + g.ckpt - 1) / g.ckpt;
@@ -438,15 +447,15 @@ __global__ __launch_bounds__(256) void k_rollout_adj(SimConst c, int N, const fl
                 const int ts = tk + j * g.ckpt;
                 const int te = min(ts + g.ckpt, tk1);
                 State<B> X;
-                load_state(X, tape + (int64_t)(ent[k] + j) * stride, g.lanes, lane);
+                load_state(X, tape + (int64_t)(ent[k] + j) * stride, lane);
                 for (int t = ts; t < te; ++t) {  // replay the segment
-                    store_state(X, seg + (int64_t)(t - ts) * stride, g.lanes, lane);
-                    step_forward<B>(c, X, p, push_profile((float)(t - tk + 1) / Lk));
+                    store_state(X, seg + (int64_t)(t - ts) * stride, lane);
+                    step_forward<B>(c, X, p, push_profile((float)(t - tk + 1) * invL));
                 }
                 for (int t = te - 1; t >= ts; --t) {
-                    load_state(X, seg + (int64_t)(t - ts) * stride, g.lanes, lane);
-                    const float sig = push_profile((float)(t - tk + 1) / Lk);
-                    step_reverse<B>(c, X, L, p, sig, ob, Db, Axb, Ayb, cAb, sAb);
+                    load_state(X, seg + (int64_t)(t - ts) * stride, lane);
+                    step_reverse<B>(c, X, L, p, push_profile((float)(t - tk + 1) * invL), ob, Db, Axb, Ayb,
+                                    cAb, sAb);
                 }
             }
         }
@@ -481,8 +490,9 @@ template <int B>
 static hipError_t launch_fwd_b(const SimConst& c, int N, const float* theta, float* cost, float* tape,
                                const TapeGeom& g, uint32_t* status, hipStream_t st) {
     const int64_t lanes = 4 * (int64_t)N;
-    const unsigned grid = (unsigned)((lanes + 255) / 256);
-    hipLaunchKernelGGL(k_rollout_fwd<B>, dim3(grid), dim3(256), 0, st, c, N, theta, cost, tape, g, status);
+    const unsigned grid = (unsigned)((lanes + kRolloutBlock - 1) / kRolloutBlock);
+    hipLaunchKernelGGL(k_rollout_fwd<B>, dim3(grid), dim3(kRolloutBlock), 0, st, c, N, theta, cost, tape, g,
+                       status);
     return hipGetLastError();
 }
 
@@ -491,8 +501,8 @@ static hipError_t launch_adj_b(const SimConst& c, int N, const float* theta, con
                                const TapeGeom& g, const float* cost_bar, float cb_scalar, float* grad,
                                float* seg, uint32_t* status, hipStream_t st) {
     const int64_t lanes = 4 * (int64_t)N;
-    const unsigned grid = (unsigned)((lanes + 255) / 256);
-    hipLaunchKernelGGL(k_rollout_adj<B>, dim3(grid), dim3(256), 0, st, c, N, theta, tape, g, cost_bar,
+    const unsigned grid = (unsigned)((lanes + kRolloutBlock - 1) / kRolloutBlock);
+    hipLaunchKernelGGL(k_rollout_adj<B>, dim3(grid), dim3(kRolloutBlock), 0, st, c, N, theta, tape, g, cost_bar,
                        cb_scalar, grad, seg, status);
     return hipGetLastError();
 }

@@ -92,6 +92,8 @@ int derive(stamp_ctx* ctx, const stamp_scene* s, const stamp_cost_w* w, SimConst
     c->beta = s->sp_beta;
     c->inv_beta = (float)(1.0 / (double)s->sp_beta);
     c->er2 = (float)((double)s->eps_r * (double)s->eps_r);
+    c->beta_log2e = (float)((double)s->sp_beta / log(2.0));
+    c->ln2_over_beta = (float)(log(2.0) / (double)s->sp_beta);
     for (int q = 0; q < 3; ++q) c->goal[q] = s->goal[q];
     c->tol = s->goal_tol;
     c->wt = w->target;

@@ -21,7 +21,7 @@ from oracle import svgd  # noqa: E402
 CASES = {
     # name: (cfg_id, iters, lr)
     "cfg2_solve_lr1e-3_it100": (2, 100, 1e-3),
-    "cfg2_solve_lr1e-2_it20": (2, 20, 1e-2),
+    "cfg2_solve_lr1e-2_it10": (2, 10, 1e-2),
 }
 
 

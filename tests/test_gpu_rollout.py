@@ -47,8 +47,9 @@ def test_forward_cost_and_tape_match_oracle(ctx, label, builder, N):
     assert rel.max() < 1e-4
     T, B, H = scene["T"], scene["B"], scene["H"]
     tp = tape.cpu().double().numpy()
-    got = tp[: T * 6 * B * 4 * N].reshape(T, 6 * B, N, 4)
-    ends = tp[T * 6 * B * 4 * N:].reshape(H, 6 * B, N, 4)
+    # tape layout [entry][lane = 4i+s][6B] -> the oracle's [entry][6B][i][s]
+    got = tp[: T * 6 * B * 4 * N].reshape(T, N, 4, 6 * B).transpose(0, 3, 1, 2)
+    ends = tp[T * 6 * B * 4 * N:].reshape(H, N, 4, 6 * B).transpose(0, 3, 1, 2)
     # per state component: its largest magnitude over the run, floored at
     # 1 cm, 1 cm/s, 0.01 rad (obstacles that never move hold ~1e-20 values)
     scale = np.maximum(np.maximum(np.abs(ref_tape).max(axis=(0, 2, 3), keepdims=True),

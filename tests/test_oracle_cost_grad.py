@@ -155,3 +155,22 @@ def test_cost_bar_scales_gradient():
     _, g1 = sim.cost_and_grad(scene, w, th)
     _, g2 = sim.cost_and_grad(scene, w, th, cost_bar=cb)
     assert np.allclose(g2, g1 * cb[:, None], rtol=1e-13, atol=1e-12)
+
+
+def test_long_horizon_gradient_matches_fd():
+    # the 1-block, 5-push, T=1000 workload: the GPU checkpointed adjoint is held
+    # to this gradient, pinned here to central differences in FP64 (all
+    # perturbed particles in one batched rollout)
+    scene, w, th = W.config_problem(3)
+    rng = np.random.default_rng(0)
+    pick = np.sort(rng.choice(th.shape[0], 16, replace=False))[:2]
+    x = th[pick]
+    _, g = sim.cost_and_grad(scene, w, x)
+    n, d = x.shape
+    eps = 1e-6
+    steps = np.tile(np.eye(d) * eps, (n, 1))
+    base = np.repeat(x, d, axis=0)
+    c = sim.cost_np(scene, w, np.concatenate([base + steps, base - steps]))
+    fd = ((c[: n * d] - c[n * d:]) / (2 * eps)).reshape(n, d)
+    rel = np.abs(fd - g) / np.maximum(np.abs(g), 1e-3 * np.abs(g).max(axis=1, keepdims=True))
+    assert np.median(rel) < 1e-6 and rel.max() < 1e-4
