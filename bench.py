@@ -46,6 +46,35 @@ def rollout_bytes(N, d, B, T, H):
     return N * (4 * d + tape), N * (4 * d + tape + 4 * d)
 
 
+KERNEL_SOURCES = ["paper_2310_01775_amd/csrc/rollout.hip", "paper_2310_01775_amd/csrc/common.h"]
+PROFILE = os.path.join(ROOT, "profiles", "rollout_cfg2_counters.md")
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE scaled by the plain-copy calibration),
+    or None when the summary is missing or the kernel sources changed since."""
+    if not os.path.exists(PROFILE):
+        return None
+    fields = {}
+    for line in open(PROFILE):
+        if ":" in line and line.startswith("- "):
+            k, v = line[2:].split(":", 1)
+            fields[k.strip()] = v.strip().strip("`")
+    if fields.get("source_sha256_16") != kernel_source_hash():
+        return None
+    v = fields.get(f"{kernel}_hbm_bytes_per_launch")
+    return float(v) if v else None
+
+
 def cpu_baseline(seconds_target=15.0):
     """Time the FP64 oracle (as it stands) on a bounded sample of the same
     workload: full N=1024 scene, a few iterations of rollout+autodiff gradient,
@@ -85,6 +114,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--workload", default="plain", choices=["plain", "batched", "long"],
+                    help="plain: the metric's workload; batched: 64 uneven problems in one graph-replayed "
+                         "solve; long: checkpointed differentiation (report only)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -110,6 +142,10 @@ def main():
     import paper_2310_01775_amd as S
     import workloads as W
 
+    if args.workload == "batched":
+        return bench_batched(args)
+    if args.workload == "long":
+        return bench_long(args)
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     cfg = W.CONFIGS[2]
@@ -174,7 +210,8 @@ def main():
                                f"median bandwidth, Adam",
                    "N": N, "d": d, "B": B, "H": H, "T": T, "tape": "full"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK_TFLOPS,
+                     "traffic": measured_traffic(dom),
                      "kernel": dom, "kernel_ms": dom_ms,
                      "hbm_GBps": (by_a if dom == "rollout_adj" else by_f) / (dom_ms * 1e-3) / 1e9},
         "kernels_ms": {"rollout_fwd": fwd_ms, "rollout_adj": adj_ms, "svgd+update": svgd_ms},
@@ -183,6 +220,83 @@ def main():
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     ctx.close()
     print(json.dumps(out), flush=True)
+
+
+def bench_batched(args):
+    """64 seeded problems, N ~ U{64..2048}, H ~ U{2..5}, B ~ U{1..4}, T=200,
+    one stamp_solve call (batched stages, graph replay, autotuned shapes)."""
+    import numpy as np
+    import torch
+
+    import paper_2310_01775_amd as S
+    import workloads as W
+
+    probs = W.batched_problems(4)
+    ctx = S.Context(0)
+    scenes = [S.make_scene(s) for s, _, _ in probs]
+    ws_ = [S.make_cost(w) for _, w, _ in probs]
+    Ns = [th.shape[0] for _, _, th in probs]
+    flat = torch.cat([S.soa(th).reshape(-1) for _, _, th in probs]).contiguous()
+    lr = W.DEFAULT_ADAM["lr"]
+    work = torch.empty(ctx.solve_workspace_bytes(scenes, Ns, S.make_cfg(args.steps, lr=lr)), dtype=torch.uint8,
+                       device="cuda")
+    times = torch.zeros(len(probs), device="cuda")
+    status = ctx.status_word()
+
+    def run(iters, theta):
+        m, v = torch.zeros_like(theta), torch.zeros_like(theta)
+        return ctx.solve(scenes, ws_, Ns, S.make_cfg(iters, lr=lr), theta, m, v, solve_time_us=times,
+                         workspace=work, status=status)
+
+    warm = flat.clone()
+    run(max(args.warmup, 1), warm)  # autotune + graph instantiation
+    torch.cuda.synchronize()
+    theta = flat.clone()
+    t0 = time.perf_counter()
+    run(args.steps, theta)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    assert int(status.item()) == 0
+    tus = times.cpu().numpy()
+    total = sum(Ns)
+    print(json.dumps({"workload": "batched: 64 problems N~U{64..2048} H~U{2..5} B~U{1..4} T=200",
+                      "particles": total, "iters": args.steps, "wall_s": wall,
+                      "particle_iters_per_s": total * args.steps / wall,
+                      "solve_time_us_p50": float(np.percentile(tus, 50)),
+                      "solve_time_us_p99": float(np.percentile(tus, 99))}), flush=True)
+    ctx.close()
+
+
+def bench_long(args):
+    """Checkpointed differentiation: 1 block, 5 pushes, T=1000 steps, N=4096;
+    forward + adjoint time and the bytes kept between them, full tape vs
+    32-step checkpoints."""
+    import torch
+
+    import paper_2310_01775_amd as S
+    import workloads as W
+    from paper_2310_01775_amd.autograd import rollout_cost, tape_bytes
+
+    scene, w, th = W.config_problem(3)
+    ctx = S.Context(0)
+    sc, cw = S.make_scene(scene), S.make_cost(w)
+    N = th.shape[0]
+    out = {"workload": "1 block, 5 pushes (d=30), T=1000 steps of dt=0.001, N=4096", "N": N}
+    for K in (0, 32):
+        x = S.soa(th).requires_grad_(True)
+        for _ in range(2):
+            rollout_cost(x, ctx, sc, cw, K).sum().backward()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(args.steps):
+            x.grad = None
+            rollout_cost(x, ctx, sc, cw, K).sum().backward()
+        b.record()
+        torch.cuda.synchronize()
+        out[f"K{K}"] = {"fwd_bwd_ms": a.elapsed_time(b) / args.steps, "kept_bytes": tape_bytes(sc, N, K)}
+    print(json.dumps(out), flush=True)
+    ctx.close()
 
 
 if __name__ == "__main__":

@@ -113,6 +113,19 @@ void stamp_destroy(stamp_ctx* ctx);
 const char* stamp_last_error(const stamp_ctx* ctx);
 /* Library version string. */
 const char* stamp_version(void);
+/* Enable (default) or disable the launch-shape autotuner of stamp_solve.  When
+ * enabled, the first solve of a batch signature (sizes of every problem, tape
+ * mode, bandwidth mode) times candidate rollout workgroup sizes and grids and
+ * contraction row blocks on the real data, synchronously, and caches the
+ * fastest in ctx; the candidates differ only in launch shape, not in the
+ * arithmetic, so results do not depend on the choice. */
+int32_t stamp_set_autotune(stamp_ctx* ctx, int32_t enable);
+/* Pin the launch shapes of stamp_solve instead of tuning them: rollout
+ * workgroup size roll_block (64, 128 or 256 threads), rollout workgroup count
+ * roll_grid (0 = one wave per 16-particle tile, else a persistent grid of at
+ * most that many workgroups), contraction rows per workgroup phi_rows (64, 128
+ * or 256).  All three 0 returns to the autotuned shapes. */
+int32_t stamp_set_launch_shape(stamp_ctx* ctx, int32_t roll_block, int32_t roll_grid, int32_t phi_rows);
 
 /* ---- sizing (host only, no GPU work) ------------------------------------- */
 
@@ -179,8 +192,16 @@ int32_t stamp_adam_step(stamp_ctx* ctx, int64_t n, float* theta, const float* ph
  *   theta, adam_m, adam_v: sum_p 6*H_p*N_p floats, problem p's block [d_p][N_p];
  *   cost_out: sum_p N_p (final true cost); modes_out: sum_p H_p*N_p int32,
  *   problem p's block [H_p][N_p] = argmax side per push (Gamma, Eq. 5), or NULL;
- *   solve_time_us: n_problems floats (device time of each problem's solve) or NULL.
- * adam_m/adam_v may be NULL only when use_adam = 0. */
+ *   solve_time_us: n_problems floats (device time from the solve's first to its
+ *   last kernel; the problems advance in lockstep, so the values coincide) or NULL.
+ * adam_m/adam_v may be NULL only when use_adam = 0; m and v are not cleared.
+ * Every stage of an iteration is one kernel over all problems (work lists of
+ * (problem, tile)); the iteration is captured once into a HIP graph on the
+ * context's own stream and replayed cfg->iters times; the caller's stream is
+ * joined by events on entry and exit.  The call blocks the host while it
+ * uploads the work lists (and while the autotuner runs, on first use).  The
+ * result is bit-identical to running stamp_rollout_fwd, stamp_rollout_adj
+ * (cost_bar = -1), stamp_svgd_step and stamp_adam_step per problem. */
 int32_t stamp_solve(stamp_ctx* ctx, int32_t n_problems, const stamp_scene* scenes,
                     const stamp_cost_w* w, const int32_t* N, const stamp_solver_cfg* cfg,
                     float* theta, float* adam_m, float* adam_v, float* cost_out,

@@ -56,6 +56,8 @@ _sig = {
     "stamp_destroy": (None, [_vp]),
     "stamp_last_error": (C.c_char_p, [_vp]),
     "stamp_version": (C.c_char_p, []),
+    "stamp_set_autotune": (_i32, [_vp, _i32]),
+    "stamp_set_launch_shape": (_i32, [_vp, _i32, _i32, _i32]),
     "stamp_tape_floats": (_sz, [_P(Scene), _i32, _i32]),
     "stamp_adj_workspace_bytes": (_sz, [_P(Scene), _i32, _i32]),
     "stamp_svgd_workspace_bytes": (_sz, [_i32, _i32]),
@@ -164,6 +166,12 @@ class Context:
             self.close()
         except Exception:
             pass
+
+    def set_autotune(self, enable: bool):
+        self._check(_lib.stamp_set_autotune(self._h, int(bool(enable))))
+
+    def set_launch_shape(self, roll_block=0, roll_grid=0, phi_rows=0):
+        self._check(_lib.stamp_set_launch_shape(self._h, int(roll_block), int(roll_grid), int(phi_rows)))
 
     def _check(self, rc):
         if rc != OK:

@@ -1,6 +1,8 @@
 """Build libstamp.so (gfx950) in-tree with hipcc.
 
-``python -m paper_2310_01775_amd.build`` or ``build()``; always recompiles.
+Run as ``python paper_2310_01775_amd/build.py`` (a plain script: it must not
+import the package, whose __init__ loads the library being built); always
+recompiles.
 """
 from __future__ import annotations
 

@@ -54,6 +54,59 @@ struct TapeGeom {
     int ckpt;           // 0 = full tape
 };
 
+// ---- SVGD step layout ---------------------------------------------------------
+constexpr int kTile = 64;                             // rows/cols of a distance tile
+constexpr int kBins0 = 2048, kBins1 = 2048, kBins2 = 512;  // radix digits 11, 11, 9 bits
+
+// Radix-selection state of the median (one per problem).
+struct SelState {
+    uint32_t prefix;  // selected high bits so far
+    uint32_t rank;    // 1-based rank still to find inside the current prefix
+    float h;          // resulting bandwidth
+    float m2;         // the median
+};
+
+// Byte offsets inside one problem's SVGD workspace.
+struct SvgdLayout {
+    size_t dist_off, dist_floats;   // tile-packed squared distances (i < j)
+    size_t hist_off;                // 3 histograms of the radix select
+    size_t sel_off;                 // SelState
+    size_t part_off, part_floats;   // phi partial sums [splits][d][N]
+    int splits;                     // column chunks of the phi contraction
+    int tiles;                      // 64-row tiles
+    size_t total;
+};
+
+// One problem of a batched solve, resident in device memory.
+struct ProblemDesc {
+    SimConst c;
+    TapeGeom g;
+    SvgdLayout sv;
+    int N, d;
+    float fixed_h;     // > 0: fixed bandwidth
+    int pad;
+    int64_t theta_off;  // floats into the packed theta / m / v / grad / phi arrays
+    int64_t cost_off;   // floats into the packed cost array
+    int64_t tape_off;   // floats into the tape region
+    int64_t seg_off;    // floats into the segment replay region
+    int64_t svgd_off;   // bytes into the SVGD region
+};
+
+// Classes of the padded particle dimension of the contraction kernel.
+constexpr int kDpClasses = 6;
+constexpr int kDpClass[kDpClasses] = {8, 16, 24, 32, 48, 64};
+
+// Device work lists of one batched SVGD step (built once per solve).
+struct BatchPlan {
+    int n_problems;
+    const int4* dist_work;  int n_dist;   // (p, I, J, -)
+    const int4* hist_work;  int n_hist;   // (p, first uint4, end uint4, -)
+    const int4* phi_work[kDpClasses];     // (p, row block, split, -) per class
+    int n_phi[kDpClasses];
+    int phi_rows;                         // rows per contraction workgroup
+    const int4* red_work;   int n_red;    // (p, first elem, end elem, -)
+};
+
 // Phase k of a T-step, H-push rollout: steps [t_k, t_{k+1}), t_k = ceil(kT/H).
 __host__ __device__ inline int phase_start(int k, int T, int H) { return (k * T + H - 1) / H; }
 

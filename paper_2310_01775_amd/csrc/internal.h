@@ -15,23 +15,24 @@ hipError_t launch_rollout_adj(const SimConst& c, int N, const float* theta, cons
                               const TapeGeom& g, const float* cost_bar, float cb_scalar, float* grad,
                               float* seg, uint32_t* status, hipStream_t st);
 
-// SVGD step.  Workspace carve-up is computed by svgd_workspace_layout.
-struct SvgdLayout {
-    size_t dist_off, dist_floats;   // tile-packed squared distances (i < j)
-    size_t hist_off;                // 3 histograms of the radix select
-    size_t sel_off;                 // select state
-    size_t h_off;                   // bandwidth scalar
-    size_t part_off, part_floats;   // phi partial sums [splits][d+1][N]
-    int splits;                     // column splits of the phi contraction
-    int tiles;                      // 64-row tiles
-    size_t total;
-};
+hipError_t launch_rollout_fwd_batched(const ProblemDesc* descs, const int2* tiles, int ntiles, int block,
+                                      int grid, const float* theta, float* cost, float* tape, uint32_t* status,
+                                      hipStream_t st);
+hipError_t launch_rollout_adj_batched(const ProblemDesc* descs, const int2* tiles, int ntiles, int block,
+                                      int grid, const float* theta, const float* tape, float cb_scalar,
+                                      float* grad, float* seg, uint32_t* status, hipStream_t st);
+
+// SVGD step of one problem.  h: when bandwidth > 0 it is used as is; otherwise
+// the median heuristic runs and writes h into the workspace (and h_out if
+// non-null).  phi_rows: rows per contraction workgroup (0 = 256).
 SvgdLayout svgd_workspace_layout(int N, int d);
-// h: when bandwidth > 0 it is used as is; otherwise the median heuristic runs and
-// writes h into the workspace (and h_out if non-null).
-hipError_t launch_svgd(int N, int d, const float* theta, const float* grad_logp, float bandwidth,
-                       float* phi, float* h_out, void* ws, const SvgdLayout& L, uint32_t* status,
+int svgd_dp_class(int d);
+hipError_t launch_svgd(int N, int d, const float* theta, const float* grad_logp, float bandwidth, float* phi,
+                       float* h_out, void* ws, const SvgdLayout& L, int phi_rows, uint32_t* status,
                        hipStream_t st);
+// The same step for every problem of a batch (work lists in P).
+hipError_t launch_svgd_batched(const BatchPlan& P, const ProblemDesc* descs, const float* theta, const float* grad,
+                               float* phi, char* ws, uint32_t* status, hipStream_t st);
 
 // Adam (use_adam=1) or plain step, n elements.  t_dev: if non-null, the step
 // count is read as t0 + *t_dev + 1 on the device (graph replay); else t0 is t.

@@ -251,14 +251,14 @@ __device__ __forceinline__ float side_weight(const float* __restrict__ theta, in
 __device__ __forceinline__ float smooth_abs(float u, float ea2) { return sqrtf(u * u + ea2); }
 
 // ---------------------------------------------------------------------------
+// Forward rollout of one lane (particle i = lane/4, side s = lane%4).  The four
+// lanes of a quad must all run it (phase mixture by DPP).
 template <int B>
-__global__ __launch_bounds__(kRolloutBlock) void k_rollout_fwd(SimConst c, int N, const float* __restrict__ theta,
-                                                     float* __restrict__ cost, float* __restrict__ tape,
-                                                     TapeGeom g, uint32_t* status) {
-    const int64_t lane = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void rollout_fwd_lane(const SimConst& c, int N, const float* __restrict__ theta,
+                                                 float* __restrict__ cost, float* __restrict__ tape,
+                                                 const TapeGeom& g, uint32_t* status, int64_t lane) {
     const int i = (int)(lane >> 2);
     const int s = (int)(lane & 3);
-    if (i >= N) return;  // whole quads leave together
     const int H = c.H, T = c.T;
 
     State<B> S;
@@ -331,16 +331,15 @@ __global__ __launch_bounds__(kRolloutBlock) void k_rollout_fwd(SimConst c, int N
 }
 
 // ---------------------------------------------------------------------------
+// Reverse sweep of one lane; cost_bar (or cb_scalar when null) scales dC/dtheta.
 template <int B>
-__global__ __launch_bounds__(kRolloutBlock) void k_rollout_adj(SimConst c, int N, const float* __restrict__ theta,
-                                                     const float* __restrict__ tape, TapeGeom g,
-                                                     const float* __restrict__ cost_bar, float cb_scalar,
-                                                     float* __restrict__ grad, float* __restrict__ seg,
-                                                     uint32_t* status) {
-    const int64_t lane = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void rollout_adj_lane(const SimConst& c, int N, const float* __restrict__ theta,
+                                                 const float* __restrict__ tape, const TapeGeom& g,
+                                                 const float* __restrict__ cost_bar, float cb_scalar,
+                                                 float* __restrict__ grad, float* __restrict__ seg,
+                                                 uint32_t* status, int64_t lane) {
     const int i = (int)(lane >> 2);
     const int s = (int)(lane & 3);
-    if (i >= N) return;
     const int H = c.H, T = c.T;
     const int64_t stride = 6 * B * g.lanes;  // floats per tape entry
 
@@ -483,6 +482,97 @@ __global__ __launch_bounds__(kRolloutBlock) void k_rollout_adj(SimConst c, int N
         bad = bad || !isfinite(ab) || !isfinite(obt) || !isfinite(Dbt);
     }
     if (status && bad) atomicOr(status, STAMP_STATUS_NONFINITE_GRAD);
+}
+
+// ---------------------------------------------------------------------------
+template <int B>
+__global__ __launch_bounds__(kRolloutBlock) void k_rollout_fwd(SimConst c, int N, const float* __restrict__ theta,
+                                                               float* __restrict__ cost, float* __restrict__ tape,
+                                                               TapeGeom g, uint32_t* status) {
+    const int64_t lane = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if ((lane >> 2) >= N) return;  // whole quads leave together
+    rollout_fwd_lane<B>(c, N, theta, cost, tape, g, status, lane);
+}
+
+template <int B>
+__global__ __launch_bounds__(kRolloutBlock) void k_rollout_adj(SimConst c, int N, const float* __restrict__ theta,
+                                                               const float* __restrict__ tape, TapeGeom g,
+                                                               const float* __restrict__ cost_bar, float cb_scalar,
+                                                               float* __restrict__ grad, float* __restrict__ seg,
+                                                               uint32_t* status) {
+    const int64_t lane = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if ((lane >> 2) >= N) return;
+    rollout_adj_lane<B>(c, N, theta, tape, g, cost_bar, cb_scalar, grad, seg, status, lane);
+}
+
+// ---------------------------------------------------------------------------
+// Batched rollouts: one launch over the wave tiles of many problems.  Tile t is
+// (problem p, first particle i0) and covers particles i0..i0+15 (64 lanes); each
+// wave takes tiles in a grid-stride loop.  The block count B of the problem
+// selects the compiled body at run time.
+__global__ __launch_bounds__(256) void k_rollout_fwd_batched(const ProblemDesc* __restrict__ descs,
+                                                             const int2* __restrict__ tiles, int ntiles,
+                                                             const float* __restrict__ theta, float* __restrict__ cost,
+                                                             float* __restrict__ tape, uint32_t* status) {
+    const int waves = blockDim.x >> 6;
+    const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
+    for (int t = blockIdx.x * waves + wave; t < ntiles; t += gridDim.x * waves) {
+        const int2 tl = tiles[t];
+        const ProblemDesc& D = descs[tl.x];
+        const int64_t lane = 4 * (int64_t)tl.y + l;
+        if ((lane >> 2) >= D.N) continue;
+        const float* th = theta + D.theta_off;
+        float* co = cost + D.cost_off;
+        float* tp = tape ? tape + D.tape_off : nullptr;
+        switch (D.c.B) {
+            case 1: rollout_fwd_lane<1>(D.c, D.N, th, co, tp, D.g, status, lane); break;
+            case 2: rollout_fwd_lane<2>(D.c, D.N, th, co, tp, D.g, status, lane); break;
+            case 3: rollout_fwd_lane<3>(D.c, D.N, th, co, tp, D.g, status, lane); break;
+            default: rollout_fwd_lane<4>(D.c, D.N, th, co, tp, D.g, status, lane); break;
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_rollout_adj_batched(const ProblemDesc* __restrict__ descs,
+                                                             const int2* __restrict__ tiles, int ntiles,
+                                                             const float* __restrict__ theta,
+                                                             const float* __restrict__ tape, float cb_scalar,
+                                                             float* __restrict__ grad, float* __restrict__ seg,
+                                                             uint32_t* status) {
+    const int waves = blockDim.x >> 6;
+    const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
+    for (int t = blockIdx.x * waves + wave; t < ntiles; t += gridDim.x * waves) {
+        const int2 tl = tiles[t];
+        const ProblemDesc& D = descs[tl.x];
+        const int64_t lane = 4 * (int64_t)tl.y + l;
+        if ((lane >> 2) >= D.N) continue;
+        const float* th = theta + D.theta_off;
+        const float* tp = tape + D.tape_off;
+        float* gr = grad + D.theta_off;
+        float* sg = seg + D.seg_off;
+        switch (D.c.B) {
+            case 1: rollout_adj_lane<1>(D.c, D.N, th, tp, D.g, nullptr, cb_scalar, gr, sg, status, lane); break;
+            case 2: rollout_adj_lane<2>(D.c, D.N, th, tp, D.g, nullptr, cb_scalar, gr, sg, status, lane); break;
+            case 3: rollout_adj_lane<3>(D.c, D.N, th, tp, D.g, nullptr, cb_scalar, gr, sg, status, lane); break;
+            default: rollout_adj_lane<4>(D.c, D.N, th, tp, D.g, nullptr, cb_scalar, gr, sg, status, lane); break;
+        }
+    }
+}
+
+hipError_t launch_rollout_fwd_batched(const ProblemDesc* descs, const int2* tiles, int ntiles, int block,
+                                      int grid, const float* theta, float* cost, float* tape, uint32_t* status,
+                                      hipStream_t st) {
+    hipLaunchKernelGGL(k_rollout_fwd_batched, dim3(grid), dim3(block), 0, st, descs, tiles, ntiles, theta, cost,
+                       tape, status);
+    return hipGetLastError();
+}
+
+hipError_t launch_rollout_adj_batched(const ProblemDesc* descs, const int2* tiles, int ntiles, int block,
+                                      int grid, const float* theta, const float* tape, float cb_scalar,
+                                      float* grad, float* seg, uint32_t* status, hipStream_t st) {
+    hipLaunchKernelGGL(k_rollout_adj_batched, dim3(grid), dim3(block), 0, st, descs, tiles, ntiles, theta, tape,
+                       cb_scalar, grad, seg, status);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------

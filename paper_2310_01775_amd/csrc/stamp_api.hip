@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -13,10 +14,27 @@
 #include "internal.h"
 #include "stamp.h"
 
+// Launch shapes picked by the autotuner for one batch signature.
+struct StampTune {
+    int roll_block = 64;  // threads per rollout workgroup (64, 128, 256)
+    int roll_grid = 0;    // rollout workgroups (0: one wave per tile)
+    int phi_rows = 256;   // rows per contraction workgroup
+};
+
 struct stamp_ctx {
     int device = 0;
     int clock_khz = 100000;  // wall-clock counter rate of the device
+    int num_cus = 256;
     std::string err;
+    hipStream_t stream = nullptr;  // library stream: solves are captured and replayed here
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    std::map<std::string, StampTune> tune;  // autotune cache, keyed by batch signature
+    int autotune = 1;
+    StampTune pinned;                        // used when pinned.roll_block > 0
+    int is_pinned = 0;
+    // the last instantiated iteration graph and the solve it belongs to
+    hipGraphExec_t graph = nullptr;
+    std::string graph_key;
 };
 
 namespace stamp {
@@ -143,38 +161,111 @@ bool scene_ok(const stamp_scene* s) {
 constexpr int kMaxSvgdDim = 64;
 constexpr int kMaxSvgdN = 65536;
 
-// Per-problem workspace of the solve: tape, gradient, phi, cost, replay and
-// SVGD scratch, step counter.
-struct SolveLayout {
-    size_t tape_off, grad_off, phi_off, cost_off, seg_off, svgd_off, ctr_off, total;
-    SvgdLayout svgd;
+// Workspace of a solve over n problems, all resident at once:
+//   clock pairs | descriptors | work lists | step counter |
+//   tapes | segment buffers | grad | phi | cost scratch | per-problem SVGD regions
+struct SolvePlan {
+    std::vector<stamp::ProblemDesc> descs;
+    std::vector<int2> roll_tiles;
+    std::vector<int4> dist_work, hist_work, red_work;
+    std::vector<int4> phi_work[kDpClasses];
+    int phi_rows = 256;
+    size_t clk_off = 0, desc_off = 0, roll_off = 0, dist_off = 0, hist_off = 0, red_off = 0;
+    size_t phi_off[kDpClasses] = {};
+    size_t ctr_off = 0, tape_off = 0, seg_off = 0, grad_off = 0, phi_vec_off = 0, cost_off = 0, svgd_off = 0;
+    size_t total = 0;
+    int64_t n_theta = 0, n_part = 0;
+    std::string key;  // batch signature (sizes only)
 };
 
-// The solve workspace starts with the per-problem clock pairs, then one
-// problem region (problems run one after another and reuse it).
-size_t clock_header_bytes(int n_problems) { return align256((size_t)n_problems * 2 * sizeof(uint64_t)); }
+constexpr int kHistChunk = 1024;  // uint4 per workgroup of a histogram pass
+constexpr int kRedChunk = 256;    // elements per workgroup of the phi reduction
 
-SolveLayout solve_layout(const stamp_scene* s, int N, int K) {
-    SolveLayout L{};
-    const int d = 6 * s->H;
+// Lay out the workspace and build the work lists.  phi_rows fixes the row
+// blocks of the contraction work list.
+void build_plan(int n, const stamp_scene* scenes, const int32_t* N, int K, float bandwidth, int phi_rows,
+                const std::vector<stamp::SimConst>* consts, SolvePlan& P) {
+    P = SolvePlan{};  // rebuilt from scratch: appending twice would repeat work items
+    P.phi_rows = phi_rows;
+    P.descs.resize(n);
+    int64_t th = 0, co = 0, tp = 0, sg = 0;
+    size_t sv = 0;
+    char buf[64];
+    P.key.clear();
+    for (int p = 0; p < n; ++p) {
+        ProblemDesc& D = P.descs[p];
+        memset(&D, 0, sizeof D);
+        if (consts) D.c = (*consts)[p];
+        const stamp_scene* s = &scenes[p];
+        D.N = N[p];
+        D.d = 6 * s->H;
+        D.g = tape_geom(s, N[p], K);
+        D.sv = svgd_workspace_layout(N[p], D.d);
+        D.fixed_h = bandwidth > 0.0f ? bandwidth : 0.0f;
+        D.theta_off = th;
+        D.cost_off = co;
+        D.tape_off = tp;
+        D.seg_off = sg;
+        D.svgd_off = (int64_t)sv;
+        th += (int64_t)D.d * D.N;
+        co += D.N;
+        tp += (int64_t)((tape_floats(s, N[p], K) + 63) & ~size_t(63));
+        sg += (int64_t)((adj_ws_bytes(s, N[p], K) / 4 + 63) & ~size_t(63));
+        sv += align256(D.sv.total);
+        snprintf(buf, sizeof buf, "%d/%d/%d/%d;", N[p], s->H, s->B, s->T);
+        P.key += buf;
+        for (int i0 = 0; i0 < D.N; i0 += 16) P.roll_tiles.push_back(make_int2(p, i0));
+        if (D.N >= 2 && !(bandwidth > 0.0f)) {
+            const int nt = D.sv.tiles;
+            for (int I = 0; I < nt; ++I)
+                for (int J = I; J < nt; ++J) P.dist_work.push_back(make_int4(p, I, J, 0));
+            const int64_t n4 = (int64_t)D.sv.dist_floats / 4;
+            for (int64_t e = 0; e < n4; e += kHistChunk)
+                P.hist_work.push_back(make_int4(p, (int)e, (int)std::min<int64_t>(e + kHistChunk, n4), 0));
+        }
+        if (D.N >= 2) {
+            int c = 0;
+            while (kDpClass[c] != svgd_dp_class(D.d)) ++c;
+            for (int rb = 0; rb * phi_rows < D.N; ++rb)
+                for (int q = 0; q < D.sv.splits; ++q) P.phi_work[c].push_back(make_int4(p, rb, q, 0));
+        }
+        const int64_t ne = (int64_t)D.d * D.N;
+        for (int64_t e = 0; e < ne; e += kRedChunk)
+            P.red_work.push_back(make_int4(p, (int)e, (int)std::min<int64_t>(e + kRedChunk, ne), 0));
+    }
+    P.n_theta = th;
     size_t off = 0;
-    L.tape_off = off;
-    off = align256(off + tape_floats(s, N, K) * 4);
-    L.grad_off = off;
-    off = align256(off + (size_t)d * N * 4);
-    L.phi_off = off;
-    off = align256(off + (size_t)d * N * 4);
-    L.cost_off = off;
-    off = align256(off + (size_t)N * 4);
-    L.seg_off = off;
-    off = align256(off + adj_ws_bytes(s, N, K));
-    L.svgd = svgd_workspace_layout(N, d);
-    L.svgd_off = off;
-    off = align256(off + L.svgd.total);
-    L.ctr_off = off;
-    off = align256(off + 256);
-    L.total = off;
-    return L;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align256(off + bytes);
+        return o;
+    };
+    P.clk_off = take((size_t)n * 2 * sizeof(uint64_t));
+    P.desc_off = take(P.descs.size() * sizeof(ProblemDesc));
+    P.roll_off = take(P.roll_tiles.size() * sizeof(int2));
+    P.dist_off = take(P.dist_work.size() * sizeof(int4));
+    P.hist_off = take(P.hist_work.size() * sizeof(int4));
+    P.red_off = take(P.red_work.size() * sizeof(int4));
+    for (int c = 0; c < kDpClasses; ++c) P.phi_off[c] = take(P.phi_work[c].size() * sizeof(int4));
+    P.ctr_off = take(256);
+    P.tape_off = take((size_t)tp * 4);
+    P.seg_off = take((size_t)sg * 4);
+    P.grad_off = take((size_t)th * 4);
+    P.phi_vec_off = take((size_t)th * 4);
+    P.cost_off = take((size_t)co * 4);
+    P.svgd_off = take(sv);
+    P.total = off;
+}
+
+// Upper bound of the plan size over every phi row choice of the autotuner.
+size_t plan_bytes(int n, const stamp_scene* scenes, const int32_t* N, int K, float bandwidth) {
+    size_t m = 0;
+    for (int rows : {64, 128, 256}) {
+        SolvePlan P;
+        build_plan(n, scenes, N, K, bandwidth, rows, nullptr, P);
+        m = std::max(m, P.total);
+    }
+    return m;
 }
 
 __global__ void k_stamp_clock(uint64_t* dst) { *dst = wall_clock64(); }
@@ -182,6 +273,16 @@ __global__ void k_stamp_clock(uint64_t* dst) { *dst = wall_clock64(); }
 __global__ void k_clock_to_us(const uint64_t* clk, int n, float us_per_tick, float* out) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p < n) out[p] = (float)(clk[2 * p + 1] - clk[2 * p]) * us_per_tick;
+}
+
+hipError_t launch_clock(uint64_t* dst, hipStream_t st) {
+    hipLaunchKernelGGL(k_stamp_clock, dim3(1), dim3(1), 0, st, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_clock_to_us(const uint64_t* clk, int n, float us_per_tick, float* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_clock_to_us, dim3((n + 63) / 64), dim3(64), 0, st, clk, n, us_per_tick, out);
+    return hipGetLastError();
 }
 
 }  // namespace
@@ -203,14 +304,51 @@ int32_t stamp_create(stamp_ctx** ctx, int32_t device) {
     if ((e = hipSetDevice(device)) != hipSuccess) return STAMP_EHIP;
     stamp_ctx* c = new stamp_ctx();
     c->device = device;
-    int khz = 0;
-    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, device) == hipSuccess && khz > 0)
-        c->clock_khz = khz;
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeWallClockRate, device) == hipSuccess && v > 0) c->clock_khz = v;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && v > 0) c->num_cus = v;
+    // default-priority stream of our own: solves are captured into graphs here
+    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming) != hipSuccess) {
+        delete c;
+        return STAMP_EHIP;
+    }
     *ctx = c;
     return STAMP_OK;
 }
 
-void stamp_destroy(stamp_ctx* ctx) { delete ctx; }
+void stamp_destroy(stamp_ctx* ctx) {
+    if (!ctx) return;
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->graph) (void)hipGraphExecDestroy(ctx->graph);
+    if (ctx->ev_in) (void)hipEventDestroy(ctx->ev_in);
+    if (ctx->ev_out) (void)hipEventDestroy(ctx->ev_out);
+    if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+}
+
+int32_t stamp_set_autotune(stamp_ctx* ctx, int32_t enable) {
+    if (!ctx) return STAMP_EINVAL;
+    ctx->autotune = enable ? 1 : 0;
+    return STAMP_OK;
+}
+
+int32_t stamp_set_launch_shape(stamp_ctx* ctx, int32_t roll_block, int32_t roll_grid, int32_t phi_rows) {
+    if (!ctx) return STAMP_EINVAL;
+    if (roll_block == 0 && roll_grid == 0 && phi_rows == 0) {
+        ctx->is_pinned = 0;
+        return STAMP_OK;
+    }
+    if (!(roll_block == 64 || roll_block == 128 || roll_block == 256) || roll_grid < 0 ||
+        !(phi_rows == 64 || phi_rows == 128 || phi_rows == 256))
+        return fail(ctx, STAMP_EINVAL, "launch shape: roll_block and phi_rows in {64,128,256}, roll_grid >= 0");
+    ctx->pinned.roll_block = roll_block;
+    ctx->pinned.roll_grid = roll_grid;
+    ctx->pinned.phi_rows = phi_rows;
+    ctx->is_pinned = 1;
+    return STAMP_OK;
+}
 
 const char* stamp_last_error(const stamp_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
 
@@ -232,12 +370,9 @@ size_t stamp_svgd_workspace_bytes(int32_t N, int32_t d) {
 size_t stamp_solve_workspace_bytes(int32_t n_problems, const stamp_scene* scenes, const int32_t* N,
                                    const stamp_solver_cfg* cfg) {
     if (n_problems < 1 || !scenes || !N || !cfg || cfg->ckpt_every < 0) return 0;
-    size_t m = 0;
-    for (int p = 0; p < n_problems; ++p) {
-        if (!scene_ok(&scenes[p]) || N[p] < 1) return 0;
-        m = std::max(m, solve_layout(&scenes[p], N[p], cfg->ckpt_every).total);
-    }
-    return clock_header_bytes(n_problems) + m;
+    for (int p = 0; p < n_problems; ++p)
+        if (!scene_ok(&scenes[p]) || N[p] < 1 || N[p] > kMaxSvgdN) return 0;
+    return plan_bytes(n_problems, scenes, N, cfg->ckpt_every, cfg->bandwidth);
 }
 
 int32_t stamp_rollout_fwd(stamp_ctx* ctx, const stamp_scene* scene, const stamp_cost_w* w, int32_t N,
@@ -286,7 +421,7 @@ int32_t stamp_svgd_step(stamp_ctx* ctx, int32_t N, int32_t d, const float* theta
     const SvgdLayout L = svgd_workspace_layout(N, d);
     if (!workspace || ws_bytes < L.total)
         return fail(ctx, STAMP_ENOSPACE, "svgd workspace %zu < %zu bytes", ws_bytes, L.total);
-    hipError_t e = launch_svgd(N, d, theta, grad_logp, bandwidth, phi, h_out, workspace, L, nullptr,
+    hipError_t e = launch_svgd(N, d, theta, grad_logp, bandwidth, phi, h_out, workspace, L, 0, nullptr,
                                (hipStream_t)stream);
     return e == hipSuccess ? STAMP_OK : hip_fail(ctx, e, "svgd_step");
 }
@@ -306,8 +441,8 @@ int32_t stamp_adam_step(stamp_ctx* ctx, int64_t n, float* theta, const float* ph
 
 int32_t stamp_solve(stamp_ctx* ctx, int32_t n_problems, const stamp_scene* scenes, const stamp_cost_w* w,
                     const int32_t* N, const stamp_solver_cfg* cfg, float* theta, float* adam_m, float* adam_v,
-                    float* cost_out, int32_t* modes_out, float* solve_time_us, void* workspace,
-                    size_t ws_bytes, uint32_t* status, void* stream) {
+                    float* cost_out, int32_t* modes_out, float* solve_time_us, void* workspace, size_t ws_bytes,
+                    uint32_t* status, void* stream) {
     if (!ctx) return STAMP_EINVAL;
     if (n_problems < 1 || !scenes || !w || !N || !cfg) return fail(ctx, STAMP_EINVAL, "null problem arrays");
     if (!theta || !cost_out) return fail(ctx, STAMP_EINVAL, "null theta or cost_out");
@@ -318,64 +453,217 @@ int32_t stamp_solve(stamp_ctx* ctx, int32_t n_problems, const stamp_scene* scene
                            cfg->adam_eps >= 0))
         return fail(ctx, STAMP_EINVAL, "bad Adam hyper-parameters");
     std::vector<SimConst> consts(n_problems);
-    size_t need = 0;
     for (int p = 0; p < n_problems; ++p) {
         int r = derive(ctx, &scenes[p], &w[p], &consts[p]);
         if (r) return r;
         if (N[p] < 1) return fail(ctx, STAMP_EINVAL, "problem %d: N=%d < 1", p, N[p]);
         if (6 * scenes[p].H > kMaxSvgdDim || N[p] > kMaxSvgdN)
             return fail(ctx, STAMP_EUNSUPPORTED, "problem %d too large for the svgd step", p);
-        need = std::max(need, solve_layout(&scenes[p], N[p], cfg->ckpt_every).total);
     }
-    need += clock_header_bytes(n_problems);
+    const int K = cfg->ckpt_every;
+    const size_t need = plan_bytes(n_problems, scenes, N, K, cfg->bandwidth);
     if (!workspace || ws_bytes < need) return fail(ctx, STAMP_ENOSPACE, "solve workspace %zu < %zu", ws_bytes, need);
-    hipStream_t st = (hipStream_t)stream;
-    uint64_t* clk = (uint64_t*)workspace;
-    char* base = (char*)workspace + clock_header_bytes(n_problems);
-    hipError_t e = hipSuccess;
-    int64_t th_off = 0, n_off = 0, m_off = 0;
-    for (int p = 0; p < n_problems && e == hipSuccess; ++p) {
-        const stamp_scene* s = &scenes[p];
-        const SimConst& c = consts[p];
-        const int n = N[p], d = 6 * s->H, K = cfg->ckpt_every;
-        const SolveLayout L = solve_layout(s, n, K);
-        float* tape = (float*)(base + L.tape_off);
-        float* grad = (float*)(base + L.grad_off);
-        float* phi = (float*)(base + L.phi_off);
-        float* cost = (float*)(base + L.cost_off);
-        float* seg = (float*)(base + L.seg_off);
-        void* sws = base + L.svgd_off;
-        int* ctr = (int*)(base + L.ctr_off);
-        float* th = theta + th_off;
-        float* mm = adam_m ? adam_m + th_off : nullptr;
-        float* vv = adam_v ? adam_v + th_off : nullptr;
-        const TapeGeom g = tape_geom(s, n, K);
-        if (solve_time_us) hipLaunchKernelGGL(k_stamp_clock, dim3(1), dim3(1), 0, st, clk + 2 * p);
-        for (int it = 0; it < cfg->iters && e == hipSuccess; ++it) {
-            if ((e = launch_rollout_fwd(c, n, th, cost, tape, g, status, st)) != hipSuccess) break;
-            // grad = -dC/dtheta = grad log rho
-            if ((e = launch_rollout_adj(c, n, th, tape, g, nullptr, -1.0f, grad, seg, status, st)) != hipSuccess)
-                break;
-            if ((e = launch_svgd(n, d, th, grad, cfg->bandwidth, phi, nullptr, sws, L.svgd, status, st)) !=
-                hipSuccess)
-                break;
-            e = launch_update((int64_t)d * n, th, phi, mm, vv, cfg->t0 + it + 1, nullptr, cfg->lr, cfg->beta1,
-                              cfg->beta2, cfg->adam_eps, cfg->use_adam, st);
+
+    hipStream_t caller = (hipStream_t)stream;
+    hipStream_t st = ctx->stream;
+    hipError_t e;
+#define STAMP_TRY(x, what)                              \
+    do {                                                \
+        if ((e = (x)) != hipSuccess) return hip_fail(ctx, e, what); \
+    } while (0)
+    // order our stream after the caller's pending work on its inputs
+    STAMP_TRY(hipEventRecord(ctx->ev_in, caller), "event record");
+    STAMP_TRY(hipStreamWaitEvent(st, ctx->ev_in, 0), "stream wait");
+
+    // launch shapes: tuned once per batch signature
+    SolvePlan P;
+    build_plan(n_problems, scenes, N, K, cfg->bandwidth, 256, &consts, P);
+    const std::string tkey = P.key + "K" + std::to_string(K) + (cfg->bandwidth > 0 ? "fixed" : "median");
+    StampTune tune;
+    auto it_t = ctx->tune.find(tkey);
+    const bool have_tune = ctx->is_pinned || it_t != ctx->tune.end();
+    if (ctx->is_pinned) tune = ctx->pinned;
+    else if (have_tune) tune = it_t->second;
+    if (tune.phi_rows != 256) build_plan(n_problems, scenes, N, K, cfg->bandwidth, tune.phi_rows, &consts, P);
+
+    char* ws = (char*)workspace;
+    ProblemDesc* d_desc = (ProblemDesc*)(ws + P.desc_off);
+    int2* d_roll = (int2*)(ws + P.roll_off);
+    int* d_ctr = (int*)(ws + P.ctr_off);
+    uint64_t* d_clk = (uint64_t*)(ws + P.clk_off);
+    float* d_tape = (float*)(ws + P.tape_off);
+    float* d_seg = (float*)(ws + P.seg_off);
+    float* d_grad = (float*)(ws + P.grad_off);
+    float* d_phi = (float*)(ws + P.phi_vec_off);
+    char* d_svgd = ws + P.svgd_off;
+    auto upload = [&](size_t off, const void* src, size_t bytes) -> hipError_t {
+        return bytes ? hipMemcpyAsync(ws + off, src, bytes, hipMemcpyHostToDevice, st) : hipSuccess;
+    };
+    auto upload_lists = [&]() -> hipError_t {
+        hipError_t r;
+        if ((r = upload(P.desc_off, P.descs.data(), P.descs.size() * sizeof(ProblemDesc))) != hipSuccess) return r;
+        if ((r = upload(P.roll_off, P.roll_tiles.data(), P.roll_tiles.size() * sizeof(int2))) != hipSuccess) return r;
+        if ((r = upload(P.dist_off, P.dist_work.data(), P.dist_work.size() * sizeof(int4))) != hipSuccess) return r;
+        if ((r = upload(P.hist_off, P.hist_work.data(), P.hist_work.size() * sizeof(int4))) != hipSuccess) return r;
+        if ((r = upload(P.red_off, P.red_work.data(), P.red_work.size() * sizeof(int4))) != hipSuccess) return r;
+        for (int c = 0; c < kDpClasses; ++c)
+            if ((r = upload(P.phi_off[c], P.phi_work[c].data(), P.phi_work[c].size() * sizeof(int4))) != hipSuccess)
+                return r;
+        return hipStreamSynchronize(st);  // host lists may go out of scope after this
+    };
+    STAMP_TRY(upload_lists(), "upload work lists");
+    const int ntiles = (int)P.roll_tiles.size();
+    auto batch_plan = [&]() {
+        BatchPlan B{};
+        B.n_problems = n_problems;
+        B.dist_work = (const int4*)(ws + P.dist_off);
+        B.n_dist = (int)P.dist_work.size();
+        B.hist_work = (const int4*)(ws + P.hist_off);
+        B.n_hist = (int)P.hist_work.size();
+        for (int c = 0; c < kDpClasses; ++c) {
+            B.phi_work[c] = (const int4*)(ws + P.phi_off[c]);
+            B.n_phi[c] = (int)P.phi_work[c].size();
         }
-        if (e == hipSuccess) e = launch_rollout_fwd(c, n, th, cost_out + n_off, nullptr, g, status, st);
-        if (e == hipSuccess && modes_out) e = launch_modes(n, s->H, th, modes_out + m_off, st);
-        if (e == hipSuccess && solve_time_us) hipLaunchKernelGGL(k_stamp_clock, dim3(1), dim3(1), 0, st, clk + 2 * p + 1);
-        (void)ctr;
-        th_off += (int64_t)d * n;
-        n_off += n;
-        m_off += (int64_t)s->H * n;
+        B.phi_rows = P.phi_rows;
+        B.red_work = (const int4*)(ws + P.red_off);
+        B.n_red = (int)P.red_work.size();
+        return B;
+    };
+    auto roll_grid = [&](const StampTune& t) {
+        const int waves = t.roll_block / 64;
+        const int full = (ntiles + waves - 1) / waves;
+        return t.roll_grid > 0 ? std::min(t.roll_grid, full) : full;
+    };
+
+    if (!have_tune && ctx->autotune && cfg->iters > 0) {
+        {
+            // time the rollout shapes and the contraction row blocks on this batch
+            hipEvent_t a, b;
+            STAMP_TRY(hipEventCreate(&a), "event");
+            STAMP_TRY(hipEventCreate(&b), "event");
+            auto timed = [&](auto&& fn) -> float {
+                fn();  // warm-up
+                (void)hipEventRecord(a, st);
+                fn();
+                (void)hipEventRecord(b, st);
+                (void)hipEventSynchronize(b);
+                float ms = 0.0f;
+                (void)hipEventElapsedTime(&ms, a, b);
+                return ms;
+            };
+            float best = 1e30f;
+            StampTune cand;
+            const int persist = ctx->num_cus * 4;
+            for (int block : {64, 128, 256}) {
+                for (int grid : {0, persist}) {
+                    cand.roll_block = block;
+                    cand.roll_grid = grid;
+                    const float ms = timed([&] {
+                        (void)launch_rollout_fwd_batched(d_desc, d_roll, ntiles, block, roll_grid(cand), theta,
+                                                         d_phi, d_tape, nullptr, st);
+                        (void)launch_rollout_adj_batched(d_desc, d_roll, ntiles, block, roll_grid(cand), theta, d_tape,
+                                                   -1.0f, d_grad, d_seg, nullptr, st);
+                    });
+                    if (ms < best) {
+                        best = ms;
+                        tune.roll_block = block;
+                        tune.roll_grid = grid;
+                    }
+                }
+            }
+            best = 1e30f;
+            for (int rows : {64, 128, 256}) {
+                SolvePlan Q;
+                build_plan(n_problems, scenes, N, K, cfg->bandwidth, rows, &consts, Q);
+                P = std::move(Q);
+                STAMP_TRY(upload_lists(), "upload work lists");
+                const BatchPlan B = batch_plan();
+                const float ms =
+                    timed([&] { (void)launch_svgd_batched(B, d_desc, theta, d_grad, d_phi, d_svgd, nullptr, st); });
+                if (ms < best) {
+                    best = ms;
+                    tune.phi_rows = rows;
+                }
+            }
+            (void)hipEventDestroy(a);
+            (void)hipEventDestroy(b);
+            if (P.phi_rows != tune.phi_rows) {
+                build_plan(n_problems, scenes, N, K, cfg->bandwidth, tune.phi_rows, &consts, P);
+                STAMP_TRY(upload_lists(), "upload work lists");
+            }
+        }
+        ctx->tune[tkey] = tune;
     }
-    if (e == hipSuccess && solve_time_us) {
-        hipLaunchKernelGGL(k_clock_to_us, dim3((n_problems + 63) / 64), dim3(64), 0, st, clk, n_problems,
-                           1000.0f / (float)ctx->clock_khz, solve_time_us);
-        e = hipGetLastError();
+    const BatchPlan B = batch_plan();
+    const int rgrid = roll_grid(tune);
+
+    // one SVGD iteration over every problem, captured once and replayed
+    auto iteration = [&]() -> hipError_t {
+        hipError_t r;
+        if ((r = launch_rollout_fwd_batched(d_desc, d_roll, ntiles, tune.roll_block, rgrid, theta,
+                                            (float*)(ws + P.cost_off), d_tape, status, st)) != hipSuccess)
+            return r;
+        if ((r = launch_rollout_adj_batched(d_desc, d_roll, ntiles, tune.roll_block, rgrid, theta, d_tape, -1.0f,
+                                            d_grad, d_seg, status, st)) != hipSuccess)
+            return r;
+        if ((r = launch_svgd_batched(B, d_desc, theta, d_grad, d_phi, d_svgd, status, st)) != hipSuccess) return r;
+        if ((r = launch_update(P.n_theta, theta, d_phi, adam_m, adam_v, cfg->t0, d_ctr, cfg->lr, cfg->beta1,
+                               cfg->beta2, cfg->adam_eps, cfg->use_adam, st)) != hipSuccess)
+            return r;
+        return launch_incr(d_ctr, st);
+    };
+    char gkey[512];
+    snprintf(gkey, sizeof gkey, "|%p|%p|%p|%p|%p|%d|%d|%.9g|%.9g|%.9g|%.9g|%d|%d|%d|", (void*)ws, (void*)theta,
+             (void*)adam_m, (void*)adam_v, (void*)status, cfg->t0, cfg->use_adam, cfg->lr, cfg->beta1, cfg->beta2,
+             cfg->adam_eps, tune.roll_block, rgrid, tune.phi_rows);
+    const std::string full_key = tkey + gkey;
+    STAMP_TRY(launch_fill_u32((uint32_t*)d_ctr, 0u, 1, st), "counter");
+    if (solve_time_us)
+        for (int p = 0; p < n_problems; ++p) STAMP_TRY(launch_clock(d_clk + 2 * p, st), "clock");
+    if (cfg->iters > 0) {
+        if (!ctx->graph || ctx->graph_key != full_key) {
+            if (ctx->graph) {
+                STAMP_TRY(hipStreamSynchronize(st), "sync");
+                (void)hipGraphExecDestroy(ctx->graph);
+                ctx->graph = nullptr;
+            }
+            hipGraph_t g = nullptr;
+            STAMP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal), "begin capture");
+            const hipError_t ce = iteration();
+            const hipError_t ee = hipStreamEndCapture(st, &g);
+            if (ce != hipSuccess) return hip_fail(ctx, ce, "capture iteration");
+            if (ee != hipSuccess) return hip_fail(ctx, ee, "end capture");
+            e = hipGraphInstantiate(&ctx->graph, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (e != hipSuccess) {
+                ctx->graph = nullptr;
+                return hip_fail(ctx, e, "graph instantiate");
+            }
+            ctx->graph_key = full_key;
+        }
+        for (int it = 0; it < cfg->iters; ++it) STAMP_TRY(hipGraphLaunch(ctx->graph, st), "graph launch");
     }
-    if (e != hipSuccess) return hip_fail(ctx, e, "solve");
+    // final true cost and discrete plan of every particle
+    STAMP_TRY(launch_rollout_fwd_batched(d_desc, d_roll, ntiles, tune.roll_block, rgrid, theta, cost_out, nullptr,
+                                         status, st),
+              "final rollout");
+    if (modes_out) {
+        int64_t m_off = 0;
+        for (int p = 0; p < n_problems; ++p) {
+            STAMP_TRY(launch_modes(N[p], scenes[p].H, theta + P.descs[p].theta_off, modes_out + m_off, st), "modes");
+            m_off += (int64_t)scenes[p].H * N[p];
+        }
+    }
+    if (solve_time_us) {
+        for (int p = 0; p < n_problems; ++p)
+            STAMP_TRY(launch_clock(d_clk + 2 * p + 1, st), "clock");
+        STAMP_TRY(launch_clock_to_us(d_clk, n_problems, 1000.0f / (float)ctx->clock_khz, solve_time_us, st),
+                  "clock");
+    }
+    // the caller's stream waits for the solve
+    STAMP_TRY(hipEventRecord(ctx->ev_out, st), "event record");
+    STAMP_TRY(hipStreamWaitEvent(caller, ctx->ev_out, 0), "stream wait");
+#undef STAMP_TRY
     return STAMP_OK;
 }
 

@@ -8,11 +8,20 @@
 // The median is an exact order statistic found by radix selection over the
 // FP32 bit patterns of D (non-negative floats order like unsigned integers):
 // pass 0 writes D for every 64x64 tile pair I <= J and histograms bits 30..20,
-// passes 1 and 2 histogram bits 19..9 and 8..0 of the survivors.  Per-block
+// passes 1 and 2 histogram bits 19..9 and 8..0 of the survivors, and after each
+// pass one workgroup finds the bin holding the wanted rank.  Workgroup
 // histograms live in LDS and are flushed with integer atomics (exact, so the
-// result does not depend on scheduling).  The contraction recomputes D in
-// 256-row x chunk tiles with theta_j and g_j staged through LDS, writes
-// per-chunk partial sums, and a second kernel reduces them in a fixed order.
+// result does not depend on scheduling).  Every stage is its own kernel: on the
+// multi-XCD MI355X a kernel boundary publishes L2 contents once, where an
+// in-kernel device-scope fence per workgroup would write back L2 each time.
+//
+// The contraction recomputes D in (row block x column chunk) tiles with
+// theta_j and g_j staged through LDS, writes per-chunk partial sums, and a
+// second kernel sums the chunks in a fixed order.  Chunk boundaries depend on N
+// only, so the arithmetic is the same for every launch shape.
+//
+// Each stage has a single-problem kernel and a batched kernel over a work list
+// of many problems; both call the same device body.
 #include <math.h>
 
 #include "common.h"
@@ -22,28 +31,19 @@ namespace stamp {
 
 namespace {
 
-constexpr int kTile = 64;          // rows/cols of a distance tile
 constexpr uint32_t kInvalid = 0xFFFFFFFFu;
-constexpr int kBins0 = 2048, kBins1 = 2048, kBins2 = 512;
 
-struct SelState {
-    uint32_t prefix;  // selected high bits so far
-    uint32_t rank;    // 1-based rank still to find inside the current prefix
-    float h;          // resulting bandwidth
-    float m2;         // the median
-};
+// ---- bodies -----------------------------------------------------------------
 
-__global__ __launch_bounds__(256) void k_dist_hist0(int N, int d, int nt, const float* __restrict__ theta,
-                                                    uint32_t* __restrict__ dist, uint32_t* __restrict__ hist) {
-    const int I = blockIdx.y, J = blockIdx.x;
-    if (I > J) return;
+// Squared distances of tile pair (I, J), I <= J, histogram of bits 30..20.
+__device__ __forceinline__ void dist_hist0_tile(int N, int d, int nt, int I, int J, const float* __restrict__ theta,
+                                                uint32_t* __restrict__ dist, uint32_t* __restrict__ hist) {
     __shared__ float ti[64][kTile + 1];
     __shared__ float tj[64][kTile + 1];
     __shared__ uint32_t lh[kBins0];
     const int tid = threadIdx.x;
     for (int b = tid; b < kBins0; b += 256) lh[b] = 0;
-    // stage both tiles (d <= 64)
-    for (int e = tid; e < d * kTile; e += 256) {
+    for (int e = tid; e < d * kTile; e += 256) {  // stage both tiles (d <= 64)
         const int l = e / kTile, r = e % kTile;
         const int gi = I * kTile + r, gj = J * kTile + r;
         ti[l][r] = gi < N ? theta[(int64_t)l * N + gi] : 0.0f;
@@ -74,29 +74,36 @@ __global__ __launch_bounds__(256) void k_dist_hist0(int N, int d, int nt, const 
         if (lh[b]) atomicAdd(&hist[b], lh[b]);
 }
 
-// Histogram of bits [shift, shift+nbits) of the survivors whose bits above
-// shift+nbits equal the selected prefix.
+// Histogram of bits [shift, shift+log2 NB) of the values in uint4 range
+// [e0, e1) whose bits above equal the selected prefix; thread starts at e0 +
+// first and steps by stride.
 template <int NB>
-__global__ __launch_bounds__(256) void k_hist_pass(const uint32_t* __restrict__ dist, int64_t n, int shift,
-                                                   const SelState* __restrict__ sel, uint32_t* __restrict__ hist) {
+__device__ __forceinline__ void hist_pass_range(const uint32_t* __restrict__ dist, int64_t e0, int64_t e1,
+                                                int64_t first, int64_t stride, int shift,
+                                                const SelState* __restrict__ sel, uint32_t* __restrict__ hist) {
     __shared__ uint32_t lh[NB];
     for (int b = threadIdx.x; b < NB; b += 256) lh[b] = 0;
     __syncthreads();
     const uint32_t want = sel->prefix;
     const int hi = shift + __builtin_ctz(NB);
-    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) {
-        const uint32_t b = dist[e];
-        if (b != kInvalid && (b >> hi) == want) atomicAdd(&lh[(b >> shift) & (NB - 1)], 1u);
+    const uint4* d4 = reinterpret_cast<const uint4*>(dist);
+    for (int64_t e = e0 + first; e < e1; e += stride) {
+        const uint4 v = d4[e];
+        const uint32_t vals[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (vals[q] != kInvalid && (vals[q] >> hi) == want) atomicAdd(&lh[(vals[q] >> shift) & (NB - 1)], 1u);
     }
     __syncthreads();
     for (int b = threadIdx.x; b < NB; b += 256)
         if (lh[b]) atomicAdd(&hist[b], lh[b]);
 }
 
-// Find the bin holding the remaining rank; extend the prefix.  One block.
+// Find the histogram bin that holds the remaining rank and extend the prefix
+// (one radix-selection step).  One full workgroup of 256 threads.
 template <int NB>
-__global__ __launch_bounds__(256) void k_select(const uint32_t* __restrict__ hist, SelState* sel, int first,
-                                                int last, int N, float* h_out) {
+__device__ __forceinline__ void select_body(const uint32_t* __restrict__ hist, SelState* sel, int first, int last,
+                                            int N, float* h_out) {
     constexpr int PER = NB / 256;
     __shared__ uint32_t part[256];
     const int tid = threadIdx.x;
@@ -108,22 +115,18 @@ __global__ __launch_bounds__(256) void k_select(const uint32_t* __restrict__ his
     }
     part[tid] = sum;
     __syncthreads();
-    // exclusive prefix of the per-thread sums (serial over 256 values by lane 0
-    // is 256 adds; a Hillis-Steele scan keeps it parallel)
-    for (int off = 1; off < 256; off <<= 1) {
-        uint32_t v = tid >= off ? part[tid - off] : 0;
+    for (int off = 1; off < 256; off <<= 1) {  // inclusive scan of the per-thread sums
+        const uint32_t v = tid >= off ? part[tid - off] : 0;
         __syncthreads();
         part[tid] += v;
         __syncthreads();
     }
     const uint32_t incl = part[tid];
     const uint32_t excl = incl - sum;
-    uint32_t rank;
-    uint32_t prefix;
+    uint32_t rank, prefix;
     if (first) {
-        // rank = ceil(P/2), P = N(N-1)/2
-        const uint64_t P = (uint64_t)N * (uint64_t)(N - 1) / 2;
-        rank = (uint32_t)((P + 1) / 2);
+        const uint64_t P = (uint64_t)N * (uint64_t)(N - 1) / 2;  // pairs i < j
+        rank = (uint32_t)((P + 1) / 2);                          // lower median
         prefix = 0;
     } else {
         rank = sel->rank;
@@ -134,15 +137,12 @@ __global__ __launch_bounds__(256) void k_select(const uint32_t* __restrict__ his
         uint32_t c = excl;
         for (int q = 0; q < PER; ++q) {
             if (c < rank && rank <= c + loc[q]) {
-                const uint32_t bin = (uint32_t)(tid * PER + q);
-                const uint32_t np = (prefix << __builtin_ctz(NB)) | bin;
-                const uint32_t nr = rank - c;
+                const uint32_t np = (prefix << __builtin_ctz(NB)) | (uint32_t)(tid * PER + q);
                 sel->prefix = np;
-                sel->rank = nr;
+                sel->rank = rank - c;
                 if (last) {
                     const float m2 = __uint_as_float(np);
-                    float h = m2 / logf((float)N);
-                    h = fmaxf(h, 1e-12f);
+                    const float h = fmaxf(m2 / logf((float)N), 1e-12f);
                     sel->m2 = m2;
                     sel->h = h;
                     if (h_out) *h_out = h;
@@ -154,25 +154,17 @@ __global__ __launch_bounds__(256) void k_select(const uint32_t* __restrict__ his
     }
 }
 
-__global__ void k_set_h(SelState* sel, float h, float* h_out) {
-    sel->h = h;
-    sel->m2 = -1.0f;
-    if (h_out) *h_out = h;
-}
-
-// partial[split][l][i] = sum_{j in chunk} K_ij (g_jl + (2/h)(theta_il - theta_jl))
+// partial[split][l][i] = sum_{j in [j0, j1)} K_ij (g_jl + (2/h)(theta_il - theta_jl))
+// for the rows i = row0 + threadIdx.x of this workgroup.
 template <int DP>
-__global__ __launch_bounds__(256) void k_phi_partial(int N, int d, int chunk, const float* __restrict__ theta,
-                                                     const float* __restrict__ g, const SelState* __restrict__ sel,
-                                                     float* __restrict__ partial) {
+__device__ __forceinline__ void phi_partial_body(int N, int d, int row0, int j0, int j1, int split,
+                                                 const float* __restrict__ theta, const float* __restrict__ g,
+                                                 const SelState* __restrict__ sel, float* __restrict__ partial) {
     constexpr int JT = 64;  // columns staged per round
     __shared__ float tj[JT][DP];
     __shared__ float gj[JT][DP];
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    const int split = blockIdx.y;
-    const int j0 = split * chunk, j1 = min(j0 + chunk, N);
-    const float h = sel->h;
-    const float inv_h = 1.0f / h;
+    const int i = row0 + threadIdx.x;
+    const float inv_h = 1.0f / sel->h;
     const float c2 = 2.0f * inv_h;
     const int ii = min(i, N - 1);
     float ti[DP], acc[DP];
@@ -184,7 +176,7 @@ __global__ __launch_bounds__(256) void k_phi_partial(int N, int d, int chunk, co
     for (int jb = j0; jb < j1; jb += JT) {
         const int nj = min(JT, j1 - jb);
         __syncthreads();
-        for (int e = threadIdx.x; e < JT * DP; e += 256) {
+        for (int e = threadIdx.x; e < JT * DP; e += blockDim.x) {
             const int jj = e / DP, l = e % DP;
             const bool ok = jj < nj && l < d;
             tj[jj][l] = ok ? theta[(int64_t)l * N + jb + jj] : 0.0f;
@@ -209,21 +201,164 @@ __global__ __launch_bounds__(256) void k_phi_partial(int N, int d, int chunk, co
     }
 }
 
-__global__ __launch_bounds__(256) void k_phi_reduce(int N, int d, int splits, const float* __restrict__ partial,
-                                                    float* __restrict__ phi, uint32_t* status) {
-    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const int64_t n = (int64_t)d * N;
-    if (e >= n) return;
+// phi[e] = (sum over splits of partial[q][e], in split order) / N
+__device__ __forceinline__ void phi_reduce_elem(int64_t e, int64_t n, int N, int splits,
+                                                const float* __restrict__ partial, float* __restrict__ phi,
+                                                uint32_t* status) {
     float s = 0.0f;
-    for (int q = 0; q < splits; ++q) s += partial[(int64_t)q * n + e];
+    for (int q0 = 0; q0 < splits; q0 += 16) {  // 16 independent loads in flight
+        float v[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) v[u] = q0 + u < splits ? partial[(int64_t)(q0 + u) * n + e] : 0.0f;
+#pragma unroll
+        for (int u = 0; u < 16; ++u) s += v[u];
+    }
     const float r = s / (float)N;
     phi[e] = r;
     if (status && !isfinite(r)) atomicOr(status, STAMP_STATUS_NONFINITE_PHI);
 }
 
+// ---- single-problem kernels ---------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_dist_hist0(int N, int d, int nt, const float* __restrict__ theta,
+                                                    uint32_t* __restrict__ dist, uint32_t* __restrict__ hist) {
+    const int I = blockIdx.y, J = blockIdx.x;
+    if (I > J) return;
+    dist_hist0_tile(N, d, nt, I, J, theta, dist, hist);
+}
+
+template <int NB>
+__global__ __launch_bounds__(256) void k_hist_pass(const uint32_t* __restrict__ dist, int64_t n, int shift,
+                                                   const SelState* __restrict__ sel, uint32_t* __restrict__ hist) {
+    hist_pass_range<NB>(dist, 0, n / 4, (int64_t)blockIdx.x * 256 + threadIdx.x, (int64_t)gridDim.x * 256, shift,
+                        sel, hist);
+}
+
+template <int NB>
+__global__ __launch_bounds__(256) void k_select(const uint32_t* __restrict__ hist, SelState* sel, int first,
+                                                int last, int N, float* h_out) {
+    select_body<NB>(hist, sel, first, last, N, h_out);
+}
+
+__global__ void k_set_h(SelState* sel, float h, float* h_out) {
+    sel->h = h;
+    sel->m2 = -1.0f;
+    if (h_out) *h_out = h;
+}
+
+template <int DP>
+__global__ __launch_bounds__(256) void k_phi_partial(int N, int d, int chunk, const float* __restrict__ theta,
+                                                     const float* __restrict__ g, const SelState* __restrict__ sel,
+                                                     float* __restrict__ partial) {
+    const int split = blockIdx.y;
+    const int j0 = split * chunk, j1 = min(j0 + chunk, N);
+    phi_partial_body<DP>(N, d, blockIdx.x * blockDim.x, j0, j1, split, theta, g, sel, partial);
+}
+
+__global__ __launch_bounds__(256) void k_phi_reduce(int N, int d, int splits, const float* __restrict__ partial,
+                                                    float* __restrict__ phi, uint32_t* status) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t n = (int64_t)d * N;
+    if (e < n) phi_reduce_elem(e, n, N, splits, partial, phi, status);
+}
+
 __global__ void k_copy(const float* __restrict__ a, float* __restrict__ b, int64_t n) {
     const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (e < n) b[e] = a[e];
+}
+
+// ---- batched kernels ----------------------------------------------------------
+// Work-list entries are int4 (problem, a, b, c) with a stage-specific meaning.
+
+__device__ __forceinline__ char* svgd_base(const ProblemDesc& D, char* ws) { return ws + D.svgd_off; }
+
+// zero the histograms of every problem; one workgroup per problem
+__global__ __launch_bounds__(256) void k_zero_hist_batched(const ProblemDesc* __restrict__ descs, char* ws) {
+    const ProblemDesc& D = descs[blockIdx.x];
+    if (D.N < 2) return;
+    uint32_t* h = reinterpret_cast<uint32_t*>(svgd_base(D, ws) + D.sv.hist_off);
+    for (int e = threadIdx.x; e < kBins0 + kBins1 + kBins2; e += 256) h[e] = 0;
+}
+
+// entry = (problem, I, J, -)
+__global__ __launch_bounds__(256) void k_dist_hist0_batched(const ProblemDesc* __restrict__ descs,
+                                                            const int4* __restrict__ work, const float* theta,
+                                                            char* ws) {
+    const int4 w = work[blockIdx.x];
+    const ProblemDesc& D = descs[w.x];
+    char* b = svgd_base(D, ws);
+    dist_hist0_tile(D.N, D.d, D.sv.tiles, w.y, w.z, theta + D.theta_off,
+                    reinterpret_cast<uint32_t*>(b + D.sv.dist_off), reinterpret_cast<uint32_t*>(b + D.sv.hist_off));
+}
+
+// one workgroup per problem; pass 0, 1, 2
+template <int NB>
+__global__ __launch_bounds__(256) void k_select_batched(const ProblemDesc* __restrict__ descs, char* ws, int pass) {
+    const ProblemDesc& D = descs[blockIdx.x];
+    if (D.N < 2 || D.fixed_h > 0.0f) return;
+    char* b = svgd_base(D, ws);
+    const int off = pass == 0 ? 0 : pass == 1 ? kBins0 : kBins0 + kBins1;
+    const uint32_t* hist = reinterpret_cast<const uint32_t*>(b + D.sv.hist_off) + off;
+    select_body<NB>(hist, reinterpret_cast<SelState*>(b + D.sv.sel_off), pass == 0, pass == 2, D.N, nullptr);
+}
+
+// entry = (problem, first uint4, end uint4, -)
+template <int NB>
+__global__ __launch_bounds__(256) void k_hist_pass_batched(const ProblemDesc* __restrict__ descs,
+                                                           const int4* __restrict__ work, char* ws, int shift,
+                                                           int pass) {
+    const int4 w = work[blockIdx.x];
+    const ProblemDesc& D = descs[w.x];
+    char* b = svgd_base(D, ws);
+    uint32_t* hist = reinterpret_cast<uint32_t*>(b + D.sv.hist_off) + (pass == 1 ? kBins0 : kBins0 + kBins1);
+    hist_pass_range<NB>(reinterpret_cast<const uint32_t*>(b + D.sv.dist_off), w.y, w.z, threadIdx.x, 256, shift,
+                        reinterpret_cast<const SelState*>(b + D.sv.sel_off), hist);
+}
+
+// fixed bandwidth, and N = 1 (phi = g): one thread per problem
+__global__ void k_set_h_batched(const ProblemDesc* __restrict__ descs, int n, char* ws) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const ProblemDesc& D = descs[p];
+    SelState* sel = reinterpret_cast<SelState*>(svgd_base(D, ws) + D.sv.sel_off);
+    if (D.N < 2) {
+        sel->h = 1.0f;
+    } else if (D.fixed_h > 0.0f) {
+        sel->h = D.fixed_h;
+        sel->m2 = -1.0f;
+    }
+}
+
+// entry = (problem, row block, split, -)
+template <int DP>
+__global__ __launch_bounds__(256) void k_phi_partial_batched(const ProblemDesc* __restrict__ descs,
+                                                             const int4* __restrict__ work, const float* theta,
+                                                             const float* grad, char* ws) {
+    const int4 w = work[blockIdx.x];
+    const ProblemDesc& D = descs[w.x];
+    char* b = svgd_base(D, ws);
+    const int chunk = (D.N + D.sv.splits - 1) / D.sv.splits;
+    const int j0 = w.z * chunk, j1 = min(j0 + chunk, D.N);
+    phi_partial_body<DP>(D.N, D.d, w.y * (int)blockDim.x, j0, j1, w.z, theta + D.theta_off, grad + D.theta_off,
+                         reinterpret_cast<const SelState*>(b + D.sv.sel_off),
+                         reinterpret_cast<float*>(b + D.sv.part_off));
+}
+
+// entry = (problem, first element, end element, -) of the problem's d*N block
+__global__ __launch_bounds__(256) void k_phi_reduce_batched(const ProblemDesc* __restrict__ descs,
+                                                            const int4* __restrict__ work, const float* grad,
+                                                            float* phi, char* ws, uint32_t* status) {
+    const int4 w = work[blockIdx.x];
+    const ProblemDesc& D = descs[w.x];
+    const int64_t e = w.y + threadIdx.x;
+    if (e >= w.z) return;
+    if (D.N == 1) {  // phi = g
+        phi[D.theta_off + e] = grad[D.theta_off + e];
+        return;
+    }
+    const int64_t n = (int64_t)D.d * D.N;
+    phi_reduce_elem(e, n, D.N, D.sv.splits, reinterpret_cast<const float*>(svgd_base(D, ws) + D.sv.part_off),
+                    phi + D.theta_off, status);
 }
 
 __global__ __launch_bounds__(256) void k_update(int64_t n, float* __restrict__ theta, const float* __restrict__ phi,
@@ -274,24 +409,36 @@ __global__ void k_incr(int* p) { *p += 1; }
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 template <int DP>
-hipError_t launch_phi_partial(int N, int d, int chunk, int splits, const float* theta, const float* g,
+hipError_t launch_phi_partial(int N, int d, int chunk, int splits, int rows, const float* theta, const float* g,
                               const SelState* sel, float* partial, hipStream_t st) {
-    dim3 grid((N + 255) / 256, splits);
-    hipLaunchKernelGGL(k_phi_partial<DP>, grid, dim3(256), 0, st, N, d, chunk, theta, g, sel, partial);
+    dim3 grid((N + rows - 1) / rows, splits);
+    hipLaunchKernelGGL(k_phi_partial<DP>, grid, dim3(rows), 0, st, N, d, chunk, theta, g, sel, partial);
     return hipGetLastError();
 }
 
+template <int DP>
+void launch_phi_partial_batched(int n, int rows, const ProblemDesc* descs, const int4* work, const float* theta,
+                                const float* grad, char* ws, hipStream_t st) {
+    hipLaunchKernelGGL(k_phi_partial_batched<DP>, dim3(n), dim3(rows), 0, st, descs, work, theta, grad, ws);
+}
+
 }  // namespace
+
+int svgd_dp_class(int d) { return d <= 8 ? 8 : d <= 16 ? 16 : d <= 24 ? 24 : d <= 32 ? 32 : d <= 48 ? 48 : 64; }
 
 SvgdLayout svgd_workspace_layout(int N, int d) {
     SvgdLayout L{};
     const int nt = (N + kTile - 1) / kTile;
     L.tiles = nt;
     L.dist_floats = (size_t)nt * (nt + 1) / 2 * kTile * kTile;
+    // column chunks: about 2048 (256-row block x chunk) tiles, >= 16 columns,
+    // at most 64 chunks; depends on N only, so every launch shape sums in the
+    // same order
     const int rowblocks = (N + 255) / 256;
     int splits = 2048 / rowblocks;
     const int maxs = (N + 15) / 16;
     if (splits > maxs) splits = maxs;
+    if (splits > 64) splits = 64;
     if (splits < 1) splits = 1;
     L.splits = splits;
     L.part_floats = (size_t)splits * d * N;
@@ -302,7 +449,6 @@ SvgdLayout svgd_workspace_layout(int N, int d) {
     off = align256(off + (kBins0 + kBins1 + kBins2) * 4);
     L.sel_off = off;
     off = align256(off + sizeof(SelState));
-    L.h_off = L.sel_off;
     L.part_off = off;
     off = align256(off + L.part_floats * 4);
     L.total = off;
@@ -310,7 +456,7 @@ SvgdLayout svgd_workspace_layout(int N, int d) {
 }
 
 hipError_t launch_svgd(int N, int d, const float* theta, const float* grad_logp, float bandwidth, float* phi,
-                       float* h_out, void* ws, const SvgdLayout& L, uint32_t* status, hipStream_t st) {
+                       float* h_out, void* ws, const SvgdLayout& L, int phi_rows, uint32_t* status, hipStream_t st) {
     char* base = static_cast<char*>(ws);
     SelState* sel = reinterpret_cast<SelState*>(base + L.sel_off);
     hipError_t e;
@@ -333,7 +479,7 @@ hipError_t launch_svgd(int N, int d, const float* theta, const float* grad_logp,
         hipLaunchKernelGGL(k_dist_hist0, dim3(nt, nt), dim3(256), 0, st, N, d, nt, theta, dist, h0);
         hipLaunchKernelGGL(k_select<kBins0>, dim3(1), dim3(256), 0, st, h0, sel, 1, 0, N, h_out);
         const int64_t n = (int64_t)L.dist_floats;
-        int blocks = (int)((n + 255) / 256);
+        int blocks = (int)((n / 4 + 255) / 256);  // one uint4 per thread
         if (blocks > 4096) blocks = 4096;
         hipLaunchKernelGGL(k_hist_pass<kBins1>, dim3(blocks), dim3(256), 0, st, dist, n, 9, sel, h1);
         hipLaunchKernelGGL(k_select<kBins1>, dim3(1), dim3(256), 0, st, h1, sel, 0, 0, N, h_out);
@@ -343,16 +489,50 @@ hipError_t launch_svgd(int N, int d, const float* theta, const float* grad_logp,
     }
     float* partial = reinterpret_cast<float*>(base + L.part_off);
     const int chunk = (N + L.splits - 1) / L.splits;
-    if (d <= 8) e = launch_phi_partial<8>(N, d, chunk, L.splits, theta, grad_logp, sel, partial, st);
-    else if (d <= 16) e = launch_phi_partial<16>(N, d, chunk, L.splits, theta, grad_logp, sel, partial, st);
-    else if (d <= 24) e = launch_phi_partial<24>(N, d, chunk, L.splits, theta, grad_logp, sel, partial, st);
-    else if (d <= 32) e = launch_phi_partial<32>(N, d, chunk, L.splits, theta, grad_logp, sel, partial, st);
-    else if (d <= 48) e = launch_phi_partial<48>(N, d, chunk, L.splits, theta, grad_logp, sel, partial, st);
-    else e = launch_phi_partial<64>(N, d, chunk, L.splits, theta, grad_logp, sel, partial, st);
+    const int rows = phi_rows > 0 ? phi_rows : 256;
+    switch (svgd_dp_class(d)) {
+        case 8: e = launch_phi_partial<8>(N, d, chunk, L.splits, rows, theta, grad_logp, sel, partial, st); break;
+        case 16: e = launch_phi_partial<16>(N, d, chunk, L.splits, rows, theta, grad_logp, sel, partial, st); break;
+        case 24: e = launch_phi_partial<24>(N, d, chunk, L.splits, rows, theta, grad_logp, sel, partial, st); break;
+        case 32: e = launch_phi_partial<32>(N, d, chunk, L.splits, rows, theta, grad_logp, sel, partial, st); break;
+        case 48: e = launch_phi_partial<48>(N, d, chunk, L.splits, rows, theta, grad_logp, sel, partial, st); break;
+        default: e = launch_phi_partial<64>(N, d, chunk, L.splits, rows, theta, grad_logp, sel, partial, st); break;
+    }
     if (e != hipSuccess) return e;
     const int64_t n = (int64_t)d * N;
-    hipLaunchKernelGGL(k_phi_reduce, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, N, d, L.splits,
-                       partial, phi, status);
+    hipLaunchKernelGGL(k_phi_reduce, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, N, d, L.splits, partial,
+                       phi, status);
+    return hipGetLastError();
+}
+
+hipError_t launch_svgd_batched(const BatchPlan& P, const ProblemDesc* descs, const float* theta, const float* grad,
+                               float* phi, char* ws, uint32_t* status, hipStream_t st) {
+    const int np = P.n_problems;
+    hipLaunchKernelGGL(k_zero_hist_batched, dim3(np), dim3(256), 0, st, descs, ws);
+    hipLaunchKernelGGL(k_set_h_batched, dim3((np + 63) / 64), dim3(64), 0, st, descs, np, ws);
+    if (P.n_dist) {
+        hipLaunchKernelGGL(k_dist_hist0_batched, dim3(P.n_dist), dim3(256), 0, st, descs, P.dist_work, theta, ws);
+        hipLaunchKernelGGL(k_select_batched<kBins0>, dim3(np), dim3(256), 0, st, descs, ws, 0);
+        hipLaunchKernelGGL(k_hist_pass_batched<kBins1>, dim3(P.n_hist), dim3(256), 0, st, descs, P.hist_work, ws, 9,
+                           1);
+        hipLaunchKernelGGL(k_select_batched<kBins1>, dim3(np), dim3(256), 0, st, descs, ws, 1);
+        hipLaunchKernelGGL(k_hist_pass_batched<kBins2>, dim3(P.n_hist), dim3(256), 0, st, descs, P.hist_work, ws, 0,
+                           2);
+        hipLaunchKernelGGL(k_select_batched<kBins2>, dim3(np), dim3(256), 0, st, descs, ws, 2);
+    }
+    for (int c = 0; c < kDpClasses; ++c) {
+        if (!P.n_phi[c]) continue;
+        switch (kDpClass[c]) {
+            case 8: launch_phi_partial_batched<8>(P.n_phi[c], P.phi_rows, descs, P.phi_work[c], theta, grad, ws, st); break;
+            case 16: launch_phi_partial_batched<16>(P.n_phi[c], P.phi_rows, descs, P.phi_work[c], theta, grad, ws, st); break;
+            case 24: launch_phi_partial_batched<24>(P.n_phi[c], P.phi_rows, descs, P.phi_work[c], theta, grad, ws, st); break;
+            case 32: launch_phi_partial_batched<32>(P.n_phi[c], P.phi_rows, descs, P.phi_work[c], theta, grad, ws, st); break;
+            case 48: launch_phi_partial_batched<48>(P.n_phi[c], P.phi_rows, descs, P.phi_work[c], theta, grad, ws, st); break;
+            default: launch_phi_partial_batched<64>(P.n_phi[c], P.phi_rows, descs, P.phi_work[c], theta, grad, ws, st); break;
+        }
+    }
+    hipLaunchKernelGGL(k_phi_reduce_batched, dim3(P.n_red), dim3(256), 0, st, descs, P.red_work, grad, phi, ws,
+                       status);
     return hipGetLastError();
 }
 

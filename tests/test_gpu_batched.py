@@ -1,0 +1,147 @@
+"""Batched, graph-captured solve of many problems of uneven N, H and B in one
+call: it must reproduce each problem's own iteration bit for bit (the batched
+kernels run the same device code over a work list), and the oracle to the FP32
+tolerance."""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import svgd
+
+pytestmark = pytest.mark.gpu
+
+
+def _problems(sizes, T, dt, seed):
+    out = []
+    for p, (N, H, B) in enumerate(sizes):
+        out.append((W.make_scene(40 + seed, p, B, H, T, dt), W.cost_weights(rot=0.5),
+                    W.make_particles(40 + seed, p, N, H)))
+    return out
+
+
+def _pack(S, probs):
+    return torch.cat([S.soa(th).reshape(-1) for _, _, th in probs]).contiguous()
+
+
+def _unpack(S, flat, probs):
+    out, off = [], 0
+    for _, _, th in probs:
+        n = th.size
+        out.append(flat[off:off + n].reshape(th.shape[1], th.shape[0]))
+        off += n
+    return out
+
+
+def _per_problem_loop(ctx, S, scene, w, th, iters, lr):
+    sc, cw = S.make_scene(scene), S.make_cost(w)
+    N = th.shape[0]
+    theta = S.soa(th)
+    m, v = torch.zeros_like(theta), torch.zeros_like(theta)
+    tape = torch.empty(ctx.tape_floats(sc, N, 0), dtype=torch.float32, device="cuda")
+    minus = torch.full((N,), -1.0, device="cuda")
+    for t in range(1, iters + 1):
+        ctx.rollout_fwd(sc, cw, theta, tape=tape)
+        g = ctx.rollout_adj(sc, cw, theta, tape, cost_bar=minus)
+        phi = ctx.svgd_step(theta, g)
+        ctx.adam_step(theta, phi, m, v, t, lr=lr)
+    cost = ctx.rollout_fwd(sc, cw, theta)
+    return theta, cost
+
+
+@pytest.mark.parametrize("autotune", [True, False])
+def test_batched_solve_equals_per_problem_iterations(ctx, autotune):
+    import paper_2310_01775_amd as S
+    ctx.set_autotune(autotune)
+    try:
+        _check_batched_equals_loops(ctx, S)
+    finally:
+        ctx.set_autotune(True)
+
+
+def _check_batched_equals_loops(ctx, S):
+    sizes = [(64, 2, 1), (200, 5, 4), (1, 3, 2), (97, 3, 3), (130, 4, 2), (33, 2, 4)]
+    probs = _problems(sizes, 40, 0.005, 0)
+    iters, lr = 6, 1e-3
+    flat = _pack(S, probs)
+    m, v = torch.zeros_like(flat), torch.zeros_like(flat)
+    Ns = [th.shape[0] for _, _, th in probs]
+    times = torch.zeros(len(probs), device="cuda")
+    modes = torch.empty(sum(N * s[1] for N, s in zip(Ns, sizes)), dtype=torch.int32, device="cuda")
+    st = ctx.status_word()
+    cost = ctx.solve([S.make_scene(s) for s, _, _ in probs], [S.make_cost(w) for _, w, _ in probs], Ns,
+                     S.make_cfg(iters, lr=lr), flat, m, v, modes_out=modes, solve_time_us=times, status=st)
+    torch.cuda.synchronize()
+    assert int(st.item()) == 0
+    got = _unpack(S, flat, probs)
+    off = 0
+    for k, (scene, w, th) in enumerate(probs):
+        ref_theta, ref_cost = _per_problem_loop(ctx, S, scene, w, th, iters, lr)
+        torch.cuda.synchronize()
+        assert torch.equal(got[k], ref_theta), f"problem {k} {sizes[k]}"
+        assert torch.equal(cost[off:off + th.shape[0]], ref_cost)
+        off += th.shape[0]
+    t = times.cpu().numpy()
+    print("per-problem solve time us", t, flush=True)
+    assert (t > 0).all()
+
+
+def test_batched_solve_matches_oracle(ctx):
+    import paper_2310_01775_amd as S
+    sizes = [(24, 2, 2), (40, 3, 1), (17, 4, 3)]
+    probs = _problems(sizes, 60, 0.005, 1)
+    iters, lr = 20, 1e-3
+    flat = _pack(S, probs)
+    m, v = torch.zeros_like(flat), torch.zeros_like(flat)
+    Ns = [th.shape[0] for _, _, th in probs]
+    ctx.solve([S.make_scene(s) for s, _, _ in probs], [S.make_cost(w) for _, w, _ in probs], Ns,
+              S.make_cfg(iters, lr=lr), flat, m, v)
+    torch.cuda.synchronize()
+    got = _unpack(S, flat, probs)
+    for k, (scene, w, th) in enumerate(probs):
+        ref = svgd.solve(scene, w, th, iters, lr=lr)["theta"]
+        g = S.aos(got[k])
+        err = np.linalg.norm(g - ref) / np.linalg.norm(ref)
+        print("problem", k, "normwise error", err, flush=True)
+        assert err < 1e-4
+
+
+def test_repeated_solves_reuse_the_graph(ctx):
+    import paper_2310_01775_amd as S
+    probs = _problems([(50, 2, 2), (70, 3, 1)], 30, 0.005, 2)
+    Ns = [th.shape[0] for _, _, th in probs]
+    scenes = [S.make_scene(s) for s, _, _ in probs]
+    ws_ = [S.make_cost(w) for _, w, _ in probs]
+    cfg = S.make_cfg(3)
+    flat = _pack(S, probs)
+    m, v = torch.zeros_like(flat), torch.zeros_like(flat)
+    work = torch.empty(ctx.solve_workspace_bytes(scenes, Ns, cfg), dtype=torch.uint8, device="cuda")
+    a = flat.clone()
+    ctx.solve(scenes, ws_, Ns, cfg, a, m.clone(), v.clone(), workspace=work)
+    b = flat.clone()
+    mb, vb = m.clone(), v.clone()
+    ctx.solve(scenes, ws_, Ns, cfg, b, mb, vb, workspace=work)   # new pointers: new graph
+    c = flat.clone()
+    ctx.solve(scenes, ws_, Ns, cfg, c, m.clone(), v.clone(), workspace=work)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b) and torch.equal(a, c)
+
+
+@pytest.mark.parametrize("roll_block,roll_grid,phi_rows", [(64, 0, 64), (128, 1024, 128), (256, 0, 256),
+                                                          (64, 1024, 256), (256, 1024, 64)])
+def test_every_launch_shape_gives_the_same_bits(ctx, roll_block, roll_grid, phi_rows):
+    # launch shapes change only how work is grouped, never the arithmetic
+    import paper_2310_01775_amd as S
+    scene, w, th = W.config_problem(1)
+    N = th.shape[0]
+    sc, cw = S.make_scene(scene), S.make_cost(w)
+    ref, _ = _per_problem_loop(ctx, S, scene, w, th, 3, 1e-3)
+    try:
+        ctx.set_launch_shape(roll_block, roll_grid, phi_rows)
+        theta = S.soa(th)
+        m, v = torch.zeros_like(theta), torch.zeros_like(theta)
+        ctx.solve([sc], [cw], [N], S.make_cfg(3, lr=1e-3), theta, m, v)
+        torch.cuda.synchronize()
+    finally:
+        ctx.set_launch_shape(0, 0, 0)
+    assert torch.equal(theta, ref)
