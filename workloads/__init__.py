@@ -183,3 +183,50 @@ def batched_problems(cfg_id: int = 4):
         out.append((make_scene(cfg_id, p, B, H, c.T, c.dt), cost_weights(),
                     make_particles(cfg_id, p, N, H)))
     return out
+
+
+# --------------------------------------------------------------------------
+# Surrogate inputs: scene encoding, random scenes and plans, initial weights.
+# --------------------------------------------------------------------------
+SCENE_ENC = 24  # 4 block slots x (x, y, cos phi, sin phi, present) + goal (x, y, cos, sin)
+
+
+def scene_encoding(scene: dict) -> np.ndarray:
+    """Fixed 24-float description of a scene: for block slots 0..3 (x, y,
+    cos phi, sin phi, present) -- absent slots are zero -- then the goal's
+    (x, y, cos phi, sin phi).  Rounded to FP32."""
+    enc = np.zeros(SCENE_ENC)
+    for b in range(MAX_BLOCKS):
+        if b < scene["B"]:
+            x, y, ph = scene["pose0"][b]
+            enc[5 * b:5 * b + 5] = [x, y, math.cos(ph), math.sin(ph), 1.0]
+    gx, gy, gph = scene["goal"]
+    enc[20:24] = [gx, gy, math.cos(gph), math.sin(gph)]
+    return f32(enc)
+
+
+def surrogate_dataset_scenes(n_scenes: int, B: int = 3, H: int = 5, T: int = 200, dt: float = 0.005,
+                             cfg_id: int = 5):
+    """Training scenes of the surrogate: the config's scene sampler over problem
+    ids 1000.. (disjoint from the evaluation scene, problem 0)."""
+    return [make_scene(cfg_id, 1000 + p, B, H, T, dt) for p in range(n_scenes)]
+
+
+def surrogate_dataset_particles(n_scenes: int, per_scene: int, H: int = 5, cfg_id: int = 5):
+    """Plans of the training set: the particle sampler, per training scene."""
+    return [make_particles(cfg_id, 1000 + p, per_scene, H) for p in range(n_scenes)]
+
+
+def mlp_init(n_in: int, width: int = 256, seed: int = 0) -> dict:
+    """He-uniform initial weights of the surrogate network, float64 holding FP32
+    values; mu / inv_sigma start as the identity standardisation."""
+    rng = rng_for(5, 0, STREAM_SURROGATE + 10 + seed)
+
+    def u(shape, fan_in):
+        lim = math.sqrt(6.0 / fan_in)
+        return f32(rng.uniform(-lim, lim, size=shape))
+
+    return dict(mu=np.zeros(n_in), inv_sigma=np.ones(n_in),
+                W1=u((width, n_in), n_in), b1=np.zeros(width),
+                W2=u((width, width), width), b2=np.zeros(width),
+                w3=u((width,), width) * 0.1, b3=np.zeros(1))
