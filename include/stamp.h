@@ -55,6 +55,13 @@ extern "C" {
 #define STAMP_MAX_BLOCKS 4  /* blocks per scene */
 #define STAMP_MAX_PUSHES 8  /* H, pushes per plan */
 
+/* learned cost surrogate (stamp_mlp_*) */
+#define STAMP_MLP_WIDTH 256          /* hidden width of both hidden layers */
+#define STAMP_MLP_IN_PAD 64          /* input width the weights are stored at */
+#define STAMP_MLP_PARAMS 82817       /* floats of the parameter vector */
+#define STAMP_MLP_BF16_WEIGHTS 163840 /* bf16 elements of the working copies */
+#define STAMP_SCENE_ENC 24           /* floats of the scene encoding */
+
 /* bits of the device status word */
 #define STAMP_STATUS_NONFINITE_COST 1u
 #define STAMP_STATUS_NONFINITE_GRAD 2u
@@ -207,6 +214,59 @@ int32_t stamp_solve(stamp_ctx* ctx, int32_t n_problems, const stamp_scene* scene
                     float* theta, float* adam_m, float* adam_v, float* cost_out,
                     int32_t* modes_out, float* solve_time_us, void* workspace,
                     size_t ws_bytes, uint32_t* status, void* stream);
+
+
+/* ---- learned cost surrogate ------------------------------------------------
+ * A network that predicts a plan's rollout cost from the plan and a scene
+ * encoding, so that early SVGD iterations can take its gradient in place of
+ * the adjoint's.  It extends the method (the paper differentiates the
+ * simulator throughout, Sec. III-B); the true rollout stays the judge.
+ *
+ *   x = [theta (d), scene encoding (n_in - d)],  n_in <= 64
+ *   u = (x - mu) * inv_sigma
+ *   h1 = gelu(W1 u + b1), h2 = gelu(W2 h1 + b2)       (width 256, exact erf GELU)
+ *   y = w3 . h2 + b3,    C_hat = exp(y) - 1             (y predicts log(1 + C))
+ *
+ * Parameter vector `params` (STAMP_MLP_PARAMS floats, FP32 master copy):
+ *   [0,64) mu, [64,128) inv_sigma, [128, 16512) W1 as [256][64] (row = output,
+ *   columns n_in..63 zero), [16512,16768) b1, [16768, 82304) W2 as [256][256],
+ *   [82304,82560) b2, [82560,82816) w3, [82816] b3.
+ * `wbf16` (STAMP_MLP_BF16_WEIGHTS bf16 = 2 bytes each, device) holds the BF16
+ * copies the matrix cores read: W1, W1^T, W2, W2^T.  stamp_mlp_prepare fills it
+ * from params; stamp_mlp_train_step refreshes it after each update.
+ * Arithmetic: BF16 inputs to the matrix products, FP32 accumulation, FP32
+ * biases, GELU, output layer and Adam. */
+
+/* Fill wbf16 from params.  Errors: STAMP_EINVAL for null pointers. */
+int32_t stamp_mlp_prepare(stamp_ctx* ctx, const float* params, void* wbf16, void* stream);
+
+/* Evaluate the network on M samples.
+ *   x_layout 0: x is [M][n_in] (sample-major), enc ignored;
+ *   x_layout 1: x is [d][M] (the particle layout), enc [n_in - d] device floats
+ *               shared by all samples.
+ *   y [M] (log-cost), cost [M] (C_hat) and grad [d][M] = grad_scale * dC_hat/dx
+ *   over the first d inputs are each optional (NULL skips).
+ * Errors: STAMP_EINVAL for null params/wbf16/x, M < 1, n_in not in 1..64,
+ * d not in 1..n_in, x_layout not 0 or 1, or enc NULL with x_layout 1 and d < n_in. */
+int32_t stamp_mlp_forward(stamp_ctx* ctx, int32_t M, int32_t n_in, int32_t d, const float* params,
+                          const void* wbf16, const float* x, int32_t x_layout, const float* enc,
+                          float* y, float* cost, float* grad, float grad_scale, void* stream);
+
+/* Workspace bytes of stamp_mlp_train_step for a minibatch of M samples. */
+size_t stamp_mlp_train_workspace_bytes(int32_t M);
+
+/* One Adam step (step count t >= 1, bias-corrected) of the mean squared error
+ * (1/M) sum_i (y_i - target_i)^2 over the minibatch x [M][n_in], target [M],
+ * updating W1, b1, W2, b2, w3, b3 of params in place (mu and inv_sigma fixed)
+ * with the Adam moments adam_m, adam_v (STAMP_MLP_PARAMS floats each, caller
+ * zeroes them before step 1), then refreshing wbf16.  loss (one device float,
+ * may be NULL) receives the loss of the weights before the step.
+ * Errors: STAMP_EINVAL for null pointers, M < 64 or not a multiple of 64, n_in
+ * not in 1..64, t < 1; STAMP_ENOSPACE if ws_bytes is too small. */
+int32_t stamp_mlp_train_step(stamp_ctx* ctx, int32_t M, int32_t n_in, const float* x, const float* target,
+                             float* params, void* wbf16, float* adam_m, float* adam_v, int32_t t, float lr,
+                             float beta1, float beta2, float eps, float* loss, void* workspace,
+                             size_t ws_bytes, void* stream);
 
 #ifdef __cplusplus
 }

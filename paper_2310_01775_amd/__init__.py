@@ -69,6 +69,11 @@ _sig = {
     "stamp_adam_step": (_i32, [_vp, _i64, _vp, _vp, _vp, _vp, _i32, _f32, _f32, _f32, _f32, _i32, _vp]),
     "stamp_solve": (_i32, [_vp, _i32, _P(Scene), _P(CostW), _P(_i32), _P(SolverCfg), _vp, _vp, _vp, _vp,
                            _vp, _vp, _vp, _sz, _vp, _vp]),
+    "stamp_mlp_prepare": (_i32, [_vp, _vp, _vp, _vp]),
+    "stamp_mlp_forward": (_i32, [_vp, _i32, _i32, _i32, _vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp, _f32, _vp]),
+    "stamp_mlp_train_workspace_bytes": (_sz, [_i32]),
+    "stamp_mlp_train_step": (_i32, [_vp, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _f32, _f32, _f32,
+                                    _f32, _vp, _vp, _sz, _vp]),
 }
 for _name, (_res, _args) in _sig.items():
     _f = getattr(_lib, _name)
@@ -142,6 +147,46 @@ def _ptr(t):
 def _stream(stream=None):
     s = torch.cuda.current_stream() if stream is None else stream
     return C.c_void_p(s.cuda_stream)
+
+
+# ---------------------------------------------------------------------------
+# Surrogate network parameter vector (layout of include/stamp.h).
+MLP_WIDTH, MLP_IN_PAD, MLP_PARAMS, MLP_BF16_WEIGHTS = 256, 64, 82817, 163840
+_MLP_FIELDS = (("mu", (MLP_IN_PAD,)), ("inv_sigma", (MLP_IN_PAD,)), ("W1", (MLP_WIDTH, MLP_IN_PAD)),
+               ("b1", (MLP_WIDTH,)), ("W2", (MLP_WIDTH, MLP_WIDTH)), ("b2", (MLP_WIDTH,)),
+               ("w3", (MLP_WIDTH,)), ("b3", (1,)))
+
+
+def pack_mlp(params: dict) -> np.ndarray:
+    """Dict of arrays (W1 as [256][n_in], mu/inv_sigma [n_in]) -> the flat
+    float32 parameter vector, inputs padded to 64 with zeros."""
+    out = np.zeros(MLP_PARAMS, dtype=np.float32)
+    off = 0
+    for name, shape in _MLP_FIELDS:
+        size = int(np.prod(shape))
+        v = np.asarray(params[name], dtype=np.float32)
+        blk = np.zeros(shape, dtype=np.float32)
+        blk[tuple(slice(0, n) for n in v.shape)] = v
+        out[off:off + size] = blk.ravel()
+        off += size
+    assert off == MLP_PARAMS
+    return out
+
+
+def unpack_mlp(flat, n_in: int) -> dict:
+    """The flat parameter vector -> dict of float64 arrays cut to n_in inputs."""
+    flat = np.asarray(flat, dtype=np.float64)
+    out, off = {}, 0
+    for name, shape in _MLP_FIELDS:
+        size = int(np.prod(shape))
+        v = flat[off:off + size].reshape(shape)
+        if name in ("mu", "inv_sigma"):
+            v = v[:n_in]
+        elif name == "W1":
+            v = v[:, :n_in]
+        out[name] = v.copy()
+        off += size
+    return out
 
 
 # ---------------------------------------------------------------------------
@@ -257,3 +302,59 @@ class Context:
                                      _ptr(adam_v), _ptr(cost_out), _ptr(modes_out), _ptr(solve_time_us),
                                      _ptr(workspace), workspace.numel(), _ptr(status), _stream(stream)))
         return cost_out
+
+    # -- learned cost surrogate -------------------------------------------------
+    def mlp_weights(self):
+        """An uninitialised buffer for the BF16 working copies."""
+        return torch.empty(MLP_BF16_WEIGHTS, dtype=torch.bfloat16, device=self.device)
+
+    @staticmethod
+    def _mlp_buffers(params, wbf16, *moments):
+        if params.dtype != torch.float32 or params.numel() < MLP_PARAMS:
+            raise ValueError("params must hold %d float32" % MLP_PARAMS)
+        if wbf16.dtype != torch.bfloat16 or wbf16.numel() < MLP_BF16_WEIGHTS:
+            raise ValueError("wbf16 must hold %d bfloat16" % MLP_BF16_WEIGHTS)
+        for t in moments:
+            if t.dtype != torch.float32 or t.numel() < MLP_PARAMS:
+                raise ValueError("Adam moments must hold %d float32" % MLP_PARAMS)
+
+    def mlp_prepare(self, params: torch.Tensor, wbf16: torch.Tensor, stream=None):
+        self._mlp_buffers(params, wbf16)
+        self._check(_lib.stamp_mlp_prepare(self._h, _ptr(params), _ptr(wbf16), _stream(stream)))
+
+    def mlp_forward(self, params, wbf16, x, n_in: int, d: int, x_layout: int = 0, enc=None, want_y=True,
+                    want_cost=False, want_grad=False, grad_scale: float = 1.0, grad=None, stream=None):
+        """x [M][n_in] (x_layout 0) or [d][M] (x_layout 1).  Returns (y, cost, grad)
+        with None for what was not asked; grad is [d][M] (written into `grad`
+        when given, which implies want_grad)."""
+        self._mlp_buffers(params, wbf16)
+        M = x.shape[0] if x_layout == 0 else x.shape[1]
+        if x.shape != ((M, n_in) if x_layout == 0 else (d, M)):
+            raise ValueError("x has shape %s, expected %s" % (tuple(x.shape), (M, n_in) if x_layout == 0 else (d, M)))
+        y = torch.empty(M, dtype=torch.float32, device=self.device) if want_y else None
+        c = torch.empty(M, dtype=torch.float32, device=self.device) if want_cost else None
+        g = grad
+        if g is None and want_grad:
+            g = torch.empty((d, M), dtype=torch.float32, device=self.device)
+        if g is not None and tuple(g.shape) != (d, M):
+            raise ValueError("grad must be [d][M]")
+        self._check(_lib.stamp_mlp_forward(self._h, M, n_in, d, _ptr(params), _ptr(wbf16), _ptr(x), int(x_layout),
+                                           _ptr(enc), _ptr(y), _ptr(c), _ptr(g), float(grad_scale),
+                                           _stream(stream)))
+        return y, c, g
+
+    @staticmethod
+    def mlp_train_workspace_bytes(M: int) -> int:
+        return int(_lib.stamp_mlp_train_workspace_bytes(M))
+
+    def mlp_train_step(self, params, wbf16, adam_m, adam_v, x, target, t, lr=1e-3, beta1=0.9, beta2=0.999,
+                       eps=1e-8, loss=None, workspace=None, stream=None):
+        self._mlp_buffers(params, wbf16, adam_m, adam_v)
+        M, n_in = x.shape
+        if tuple(target.shape) != (M,):
+            raise ValueError("target must be [M]")
+        if workspace is None:
+            workspace = self._bytes(self.mlp_train_workspace_bytes(M))
+        self._check(_lib.stamp_mlp_train_step(self._h, M, n_in, _ptr(x), _ptr(target), _ptr(params), _ptr(wbf16),
+                                              _ptr(adam_m), _ptr(adam_v), int(t), lr, beta1, beta2, eps,
+                                              _ptr(loss), _ptr(workspace), workspace.numel(), _stream(stream)))

@@ -156,4 +156,28 @@ __device__ __forceinline__ float push_profile(float tau) {
     return tau * tau * tau * (10.0f + tau * (-15.0f + 6.0f * tau));
 }
 
+
+// ---------------------------------------------------------------------------
+// Surrogate network (n_in -> 256 -> 256 -> 1).  FP32 parameter vector, floats:
+constexpr int kMlpIn = STAMP_MLP_IN_PAD;     // padded input width
+constexpr int kMlpWidth = STAMP_MLP_WIDTH;   // hidden width
+constexpr int kMlpOffMu = 0;                                   // [kMlpIn]
+constexpr int kMlpOffIsig = kMlpOffMu + kMlpIn;                // [kMlpIn]
+constexpr int kMlpOffW1 = kMlpOffIsig + kMlpIn;                // [256][kMlpIn]
+constexpr int kMlpOffB1 = kMlpOffW1 + kMlpWidth * kMlpIn;      // [256]
+constexpr int kMlpOffW2 = kMlpOffB1 + kMlpWidth;               // [256][256]
+constexpr int kMlpOffB2 = kMlpOffW2 + kMlpWidth * kMlpWidth;   // [256]
+constexpr int kMlpOffW3 = kMlpOffB2 + kMlpWidth;               // [256]
+constexpr int kMlpOffB3 = kMlpOffW3 + kMlpWidth;               // [1]
+constexpr int kMlpParams = kMlpOffB3 + 1;
+static_assert(kMlpParams == STAMP_MLP_PARAMS, "parameter layout");
+// BF16 working copies, elements: W1, W1^T, W2, W2^T
+constexpr int kMlpBfW1 = 0;
+constexpr int kMlpBfW1T = kMlpBfW1 + kMlpWidth * kMlpIn;
+constexpr int kMlpBfW2 = kMlpBfW1T + kMlpWidth * kMlpIn;
+constexpr int kMlpBfW2T = kMlpBfW2 + kMlpWidth * kMlpWidth;
+constexpr int kMlpBfTotal = kMlpBfW2T + kMlpWidth * kMlpWidth;
+static_assert(kMlpBfTotal == STAMP_MLP_BF16_WEIGHTS, "bf16 layout");
+constexpr int kMlpPartStride = 772;  // per-tile partial sums of a training step
+
 }  // namespace stamp

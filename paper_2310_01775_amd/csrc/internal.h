@@ -47,4 +47,21 @@ hipError_t launch_modes(int N, int H, const float* theta, int32_t* modes, hipStr
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st);
 hipError_t launch_incr(int* p, hipStream_t st);
 
+// Surrogate network.  Wb holds the BF16 copies (kMlpBfTotal elements).
+struct MlpTrainLayout {
+    size_t ut, h1t, d2t, d1t, dw1, dw2, part, total;  // byte offsets into the workspace
+};
+MlpTrainLayout mlp_train_layout(int M);
+hipError_t launch_mlp_prepare(const float* P, __bf16* Wb, hipStream_t st);
+// x_mode 0: X is [M][n_in]; x_mode 1: X is [d][M] (structure of arrays) and
+// inputs d..n_in-1 are enc[0..n_in-d).  Any of y_out / cost_out / grad_out may
+// be null; grad_out is [d][M] = grad_scale * dC_hat/dx.
+hipError_t launch_mlp_infer(const float* P, const __bf16* Wb, const float* X, int x_mode, int M, int n_in, int d,
+                            const float* enc, float* y_out, float* cost_out, float* grad_out, float grad_scale,
+                            hipStream_t st);
+// One Adam step of the mean squared error over M samples (M % 64 == 0).
+hipError_t launch_mlp_train_step(float* P, __bf16* Wb, float* mom, float* vel, int t, float lr, float b1, float b2,
+                                 float eps, const float* X, const float* target, int M, int n_in, float* loss_out,
+                                 char* ws, const MlpTrainLayout& L, hipStream_t st);
+
 }  // namespace stamp

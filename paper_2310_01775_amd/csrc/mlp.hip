@@ -1,0 +1,467 @@
+// Learned surrogate of the rollout cost on gfx950: a 3-layer network
+// (n_in -> 256 -> 256 -> 1, GELU) on BF16 MFMA with FP32 accumulation.
+//
+//   u = (x - mu) * inv_sigma,  h1 = gelu(W1 u + b1),  h2 = gelu(W2 h1 + b2),
+//   y = w3 . h2 + b3  (y predicts log(1 + C))
+//
+// Layers 1 and 2 and every backward contraction run on
+// v_mfma_f32_16x16x32_bf16: lane l holds A[l%16][8(l/16)..+7] and
+// B[8(l/16)..+7][l%16] (8 bf16 each) and receives D[4(l/16)+j][l%16], j < 4.
+// Weights are read as BF16 working copies in both orientations (W and W^T),
+// so every B operand is one contiguous 16-byte load.  Layer 3 (one output)
+// and the GELUs are FP32 VALU work.
+//
+// Inference (k_mlp_infer): a workgroup takes 64 samples, each wave 16 rows;
+// the wave keeps its 16 x 256 pre-activations of layer 2 in registers, and
+// runs forward, the output dot, and the input gradient
+//   dy/dx = ((w3 * gelu'(z2)) W2 * gelu'(z1)) W1 * inv_sigma
+// with z1 recomputed by MFMA instead of stored.
+// Training (k_mlp_train_fb, k_mlp_wgrad, k_mlp_adam): the same forward with
+// the loss gradient, activations written feature-major for the weight
+// gradients dW = delta^T act (MFMA with the samples as K), per-tile bias
+// partial sums reduced in a fixed order, then Adam on FP32 master weights and
+// a refresh of the BF16 copies.
+#include <math.h>
+
+#include "common.h"
+#include "internal.h"
+
+namespace stamp {
+
+namespace {
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f4;
+
+constexpr int kIn = kMlpIn;    // padded input width
+constexpr int kW = kMlpWidth;  // hidden width
+constexpr int kRows = 64;      // samples per workgroup
+constexpr int kLdU = kIn + 8;  // LDS row strides (bf16), padded against bank conflicts
+constexpr int kLdH = kW + 8;
+
+__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu_grad(float z) {
+    return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * 0.39894228040143268f * expf(-0.5f * z * z);
+}
+
+// acc += A (16 rows x K, LDS, row stride lda) * B where B[k][n] = Bt[n][k]
+// (global, rows of ldb bf16); the 16 B columns start at Bt row n0.
+__device__ __forceinline__ f4 mma_rows(const __bf16* A, int lda, const __bf16* __restrict__ Bt, int ldb, int n0,
+                                       int K, f4 acc) {
+    const int l = threadIdx.x & 63;
+    const int r = l & 15, kq = l >> 4;
+    const __bf16* a = A + r * lda + 8 * kq;
+    const __bf16* b = Bt + (int64_t)(n0 + r) * ldb + 8 * kq;
+    for (int k0 = 0; k0 < K; k0 += 32) {
+        const bf16x8 av = *reinterpret_cast<const bf16x8*>(a + k0);
+        const bf16x8 bv = *reinterpret_cast<const bf16x8*>(b + k0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc, 0, 0, 0);
+    }
+    return acc;
+}
+
+// Sum over the 16 lanes that share l/16 (they hold the 16 columns of a block).
+__device__ __forceinline__ float sum16(float v) {
+    v += __shfl_xor(v, 1);
+    v += __shfl_xor(v, 2);
+    v += __shfl_xor(v, 4);
+    v += __shfl_xor(v, 8);
+    return v;
+}
+// Sum over the 4 lane groups l/16 (the 4 row quarters of a block).
+__device__ __forceinline__ float sum_groups(float v) {
+    v += __shfl_xor(v, 16);
+    v += __shfl_xor(v, 32);
+    return v;
+}
+
+struct MlpPtrs {
+    const float* mu;
+    const float* isig;
+    const float* b1;
+    const float* b2;
+    const float* w3;
+    float b3;
+    const __bf16* W1;   // [256][64]   (out, in)
+    const __bf16* W1T;  // [64][256]   (in, out)
+    const __bf16* W2;   // [256][256]  (out, in)
+    const __bf16* W2T;  // [256][256]  (in, out)
+};
+
+__device__ __forceinline__ MlpPtrs mlp_ptrs(const float* P, const __bf16* Wb) {
+    MlpPtrs m;
+    m.mu = P + kMlpOffMu;
+    m.isig = P + kMlpOffIsig;
+    m.b1 = P + kMlpOffB1;
+    m.b2 = P + kMlpOffB2;
+    m.w3 = P + kMlpOffW3;
+    m.b3 = P[kMlpOffB3];
+    m.W1 = Wb + kMlpBfW1;
+    m.W1T = Wb + kMlpBfW1T;
+    m.W2 = Wb + kMlpBfW2;
+    m.W2T = Wb + kMlpBfW2T;
+    return m;
+}
+
+// Stage this wave's 16 standardised input rows into U (bf16).  Input sample i:
+// x_mode 0: X[i * n_in + f] (d unused); x_mode 1: f < d from X[f * M + i]
+// (structure of arrays), f >= d from enc[f - d].
+__device__ __forceinline__ void stage_inputs(__bf16* U, const MlpPtrs& m, const float* __restrict__ X, int x_mode,
+                                             int M, int n_in, int d, const float* __restrict__ enc, int row0) {
+    const int l = threadIdx.x & 63;
+    const int r = l & 15;
+    const int i = row0 + r;
+    for (int f = l >> 4; f < kIn; f += 4) {
+        float x = 0.0f;
+        if (i < M && f < n_in) {
+            if (x_mode == 0) x = X[(int64_t)i * n_in + f];
+            else x = f < d ? X[(int64_t)f * M + i] : enc[f - d];
+        }
+        const float u = f < n_in ? (x - m.mu[f]) * m.isig[f] : 0.0f;
+        U[r * kLdU + f] = (__bf16)u;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Inference: y (and cost = expm1 y) and grad_out[f][i] = scale * e^y * dy/dx_f
+// for f < d (structure of arrays, the SVGD gradient layout; grad_out holds
+// exactly d rows of M, in either input layout).
+__global__ __launch_bounds__(256) void k_mlp_infer(const float* __restrict__ P, const __bf16* __restrict__ Wb,
+                                                   const float* __restrict__ X, int x_mode, int M, int n_in, int d,
+                                                   const float* __restrict__ enc, float* __restrict__ y_out,
+                                                   float* __restrict__ cost_out, float* __restrict__ grad_out,
+                                                   float grad_scale) {
+    __shared__ __bf16 sU[4][16 * kLdU];
+    __shared__ __bf16 sH[4][16 * kLdH];
+    __shared__ __bf16 sD[4][16 * kLdH];
+    const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int kq = l >> 4, col = l & 15;
+    const int row0 = blockIdx.x * kRows + wave * 16;
+    __bf16* U = sU[wave];
+    __bf16* Hb = sH[wave];
+    __bf16* Db = sD[wave];
+    const MlpPtrs m = mlp_ptrs(P, Wb);
+
+    stage_inputs(U, m, X, x_mode, M, n_in, d, enc, row0);
+    __syncthreads();
+    // layer 1
+    for (int cb = 0; cb < kW / 16; ++cb) {
+        f4 acc = {0.f, 0.f, 0.f, 0.f};
+        acc = mma_rows(U, kLdU, m.W1, kIn, cb * 16, kIn, acc);
+        const int c = cb * 16 + col;
+        for (int j = 0; j < 4; ++j) Hb[(4 * kq + j) * kLdH + c] = (__bf16)gelu(acc[j] + m.b1[c]);
+    }
+    __syncthreads();
+    // layer 2, pre-activations kept in registers
+    f4 z2[kW / 16];
+    float yp[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int cb = 0; cb < kW / 16; ++cb) {
+        f4 acc = {0.f, 0.f, 0.f, 0.f};
+        acc = mma_rows(Hb, kLdH, m.W2, kW, cb * 16, kW, acc);
+        const int c = cb * 16 + col;
+        for (int j = 0; j < 4; ++j) {
+            acc[j] += m.b2[c];
+            yp[j] += m.w3[c] * gelu(acc[j]);
+        }
+        z2[cb] = acc;
+    }
+    float y[4];
+    for (int j = 0; j < 4; ++j) y[j] = sum16(yp[j]) + m.b3;
+    const bool want_grad = grad_out != nullptr;
+    if (want_grad) {
+        // delta2 = w3 * gelu'(z2)
+#pragma unroll
+        for (int cb = 0; cb < kW / 16; ++cb) {
+            const int c = cb * 16 + col;
+            for (int j = 0; j < 4; ++j) Db[(4 * kq + j) * kLdH + c] = (__bf16)(m.w3[c] * gelu_grad(z2[cb][j]));
+        }
+    }
+    __syncthreads();
+    if (want_grad) {
+        // delta1 = (delta2 W2) * gelu'(z1), z1 recomputed
+        for (int kb = 0; kb < kW / 16; ++kb) {
+            f4 t = {0.f, 0.f, 0.f, 0.f};
+            t = mma_rows(Db, kLdH, m.W2T, kW, kb * 16, kW, t);
+            f4 z1 = {0.f, 0.f, 0.f, 0.f};
+            z1 = mma_rows(U, kLdU, m.W1, kIn, kb * 16, kIn, z1);
+            const int k = kb * 16 + col;
+            for (int j = 0; j < 4; ++j) Hb[(4 * kq + j) * kLdH + k] = (__bf16)(t[j] * gelu_grad(z1[j] + m.b1[k]));
+        }
+    }
+    __syncthreads();
+    if (want_grad) {
+        // dy/dx = delta1 W1, then the chain through the standardisation
+        for (int fb = 0; fb < kIn / 16; ++fb) {
+            f4 g = {0.f, 0.f, 0.f, 0.f};
+            g = mma_rows(Hb, kLdH, m.W1T, kW, fb * 16, kW, g);
+            const int f = fb * 16 + col;
+            if (f < d) {
+                for (int j = 0; j < 4; ++j) {
+                    const int i = row0 + 4 * kq + j;
+                    if (i < M) grad_out[(int64_t)f * M + i] = grad_scale * expf(y[j]) * g[j] * m.isig[f];
+                }
+            }
+        }
+    }
+    if (col == 0) {
+        for (int j = 0; j < 4; ++j) {
+            const int i = row0 + 4 * kq + j;
+            if (i < M) {
+                if (y_out) y_out[i] = y[j];
+                if (cost_out) cost_out[i] = expm1f(y[j]);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Training forward + backward of a minibatch (M a multiple of 64, inputs AoS).
+// Writes feature-major BF16 activations for the weight gradients and per-tile
+// partial sums: part[tile][0..255] = sum delta1, [256..511] = sum delta2,
+// [512..767] = sum delta3 * h2, [768] = sum delta3, [769] = sum (y - t)^2 / M.
+__global__ __launch_bounds__(256) void k_mlp_train_fb(const float* __restrict__ P, const __bf16* __restrict__ Wb,
+                                                      const float* __restrict__ X, const float* __restrict__ target,
+                                                      int M, int n_in, __bf16* __restrict__ UT,
+                                                      __bf16* __restrict__ H1T, __bf16* __restrict__ D2T,
+                                                      __bf16* __restrict__ D1T, float* __restrict__ part) {
+    __shared__ __bf16 sU[4][16 * kLdU];
+    __shared__ __bf16 sH[4][16 * kLdH];
+    __shared__ __bf16 sD[4][16 * kLdH];
+    __shared__ float sRed[4][kMlpPartStride];
+    const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int kq = l >> 4, col = l & 15;
+    const int row0 = blockIdx.x * kRows + wave * 16;
+    __bf16* U = sU[wave];
+    __bf16* Hb = sH[wave];
+    __bf16* Db = sD[wave];
+    float* red = sRed[wave];
+    const MlpPtrs m = mlp_ptrs(P, Wb);
+    const float inv_m = 1.0f / (float)M;
+
+    stage_inputs(U, m, X, 0, M, n_in, 0, nullptr, row0);
+    __syncthreads();
+    // U^T for dW1
+    for (int f = kq; f < kIn; f += 4) UT[(int64_t)f * M + row0 + col] = U[col * kLdU + f];
+    for (int cb = 0; cb < kW / 16; ++cb) {
+        f4 acc = {0.f, 0.f, 0.f, 0.f};
+        acc = mma_rows(U, kLdU, m.W1, kIn, cb * 16, kIn, acc);
+        const int c = cb * 16 + col;
+        for (int j = 0; j < 4; ++j) {
+            const __bf16 h = (__bf16)gelu(acc[j] + m.b1[c]);
+            Hb[(4 * kq + j) * kLdH + c] = h;
+            H1T[(int64_t)c * M + row0 + 4 * kq + j] = h;
+        }
+    }
+    __syncthreads();
+    f4 z2[kW / 16];
+    float yp[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int cb = 0; cb < kW / 16; ++cb) {
+        f4 acc = {0.f, 0.f, 0.f, 0.f};
+        acc = mma_rows(Hb, kLdH, m.W2, kW, cb * 16, kW, acc);
+        const int c = cb * 16 + col;
+        for (int j = 0; j < 4; ++j) {
+            acc[j] += m.b2[c];
+            yp[j] += m.w3[c] * gelu(acc[j]);
+        }
+        z2[cb] = acc;
+    }
+    // delta3 = dL/dy = 2 (y - t) / M
+    float d3[4];
+    float lsum = 0.0f;
+    for (int j = 0; j < 4; ++j) {
+        const float y = sum16(yp[j]) + m.b3;
+        const float e = y - target[row0 + 4 * kq + j];
+        d3[j] = 2.0f * e * inv_m;
+        lsum += e * e * inv_m;
+    }
+    // delta2 = delta3 w3 gelu'(z2); partial sums of delta2 and delta3 h2
+#pragma unroll
+    for (int cb = 0; cb < kW / 16; ++cb) {
+        const int c = cb * 16 + col;
+        float s2 = 0.0f, s3 = 0.0f;
+        for (int j = 0; j < 4; ++j) {
+            const float dz = d3[j] * m.w3[c] * gelu_grad(z2[cb][j]);
+            const __bf16 db = (__bf16)dz;
+            Db[(4 * kq + j) * kLdH + c] = db;
+            D2T[(int64_t)c * M + row0 + 4 * kq + j] = db;
+            s2 += dz;
+            s3 += d3[j] * gelu(z2[cb][j]);
+        }
+        s2 = sum_groups(s2);
+        s3 = sum_groups(s3);
+        if (kq == 0) {
+            red[256 + c] = s2;
+            red[512 + c] = s3;
+        }
+    }
+    {
+        float s = d3[0] + d3[1] + d3[2] + d3[3];
+        s = sum_groups(s);
+        float ls = sum_groups(lsum);
+        if (l == 0) {
+            red[768] = s;
+            red[769] = ls;
+        }
+    }
+    __syncthreads();
+    // delta1 = (delta2 W2) gelu'(z1)
+    for (int kb = 0; kb < kW / 16; ++kb) {
+        f4 t = {0.f, 0.f, 0.f, 0.f};
+        t = mma_rows(Db, kLdH, m.W2T, kW, kb * 16, kW, t);
+        f4 z1 = {0.f, 0.f, 0.f, 0.f};
+        z1 = mma_rows(U, kLdU, m.W1, kIn, kb * 16, kIn, z1);
+        const int k = kb * 16 + col;
+        float s1 = 0.0f;
+        for (int j = 0; j < 4; ++j) {
+            const float dz = t[j] * gelu_grad(z1[j] + m.b1[k]);
+            D1T[(int64_t)k * M + row0 + 4 * kq + j] = (__bf16)dz;
+            s1 += dz;
+        }
+        s1 = sum_groups(s1);
+        if (kq == 0) red[k] = s1;
+    }
+    __syncthreads();
+    // per-tile partial sums: the four waves in a fixed order
+    for (int e = threadIdx.x; e < kMlpPartStride; e += 256) {
+        float s = 0.0f;
+        if (e < 770) s = ((sRed[0][e] + sRed[1][e]) + sRed[2][e]) + sRed[3][e];
+        part[(int64_t)blockIdx.x * kMlpPartStride + e] = s;
+    }
+}
+
+// out[c][k] (row stride ldo) = sum_s AT[c][s] BT[k][s], one wave per 16 x 16
+// block; K = M samples (multiple of 32).
+__global__ __launch_bounds__(64) void k_mlp_wgrad(const __bf16* __restrict__ AT, const __bf16* __restrict__ BT, int M,
+                                                  int ncol, float* __restrict__ out) {
+    const int nb = ncol / 16;
+    const int cb = blockIdx.x / nb, kb = blockIdx.x % nb;
+    const int l = threadIdx.x;
+    const int r = l & 15, kq = l >> 4;
+    const __bf16* a = AT + (int64_t)(cb * 16 + r) * M + 8 * kq;
+    const __bf16* b = BT + (int64_t)(kb * 16 + r) * M + 8 * kq;
+    f4 acc = {0.f, 0.f, 0.f, 0.f};
+    for (int s0 = 0; s0 < M; s0 += 32) {
+        const bf16x8 av = *reinterpret_cast<const bf16x8*>(a + s0);
+        const bf16x8 bv = *reinterpret_cast<const bf16x8*>(b + s0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc, 0, 0, 0);
+    }
+    for (int j = 0; j < 4; ++j) out[(int64_t)(cb * 16 + 4 * kq + j) * ncol + kb * 16 + r] = acc[j];
+}
+
+// Adam on the trained tensors (FP32 master weights), gradients from the
+// weight-gradient buffers and the per-tile partial sums (summed in tile order).
+__global__ __launch_bounds__(256) void k_mlp_adam(float* __restrict__ P, float* __restrict__ mom,
+                                                  float* __restrict__ vel, const float* __restrict__ dW1,
+                                                  const float* __restrict__ dW2, const float* __restrict__ part,
+                                                  int tiles, int n_in, int t, float lr, float b1, float b2,
+                                                  float eps) {
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    if (e >= kMlpParams) return;
+    float g;
+    if (e >= kMlpOffW1 && e < kMlpOffB1) {
+        const int k = (e - kMlpOffW1) / kIn, f = (e - kMlpOffW1) % kIn;
+        g = f < n_in ? dW1[k * kIn + f] : 0.0f;
+    } else if (e >= kMlpOffW2 && e < kMlpOffB2) {
+        g = dW2[e - kMlpOffW2];
+    } else {
+        int idx;
+        if (e >= kMlpOffB1 && e < kMlpOffW2) idx = e - kMlpOffB1;              // sum delta1
+        else if (e >= kMlpOffB2 && e < kMlpOffW3) idx = 256 + (e - kMlpOffB2);  // sum delta2
+        else if (e >= kMlpOffW3 && e < kMlpOffB3) idx = 512 + (e - kMlpOffW3);  // sum delta3 h2
+        else if (e == kMlpOffB3) idx = 768;                                     // sum delta3
+        else return;  // mu, inv_sigma and padding are not trained
+        g = 0.0f;
+        for (int q = 0; q < tiles; ++q) g += part[(int64_t)q * kMlpPartStride + idx];
+    }
+    const float mm = b1 * mom[e] + (1.0f - b1) * g;
+    const float vv = b2 * vel[e] + (1.0f - b2) * g * g;
+    mom[e] = mm;
+    vel[e] = vv;
+    const float mhat = mm / (1.0f - powf(b1, (float)t));
+    const float vhat = vv / (1.0f - powf(b2, (float)t));
+    P[e] = P[e] - lr * mhat / (sqrtf(vhat) + eps);
+}
+
+// BF16 working copies of W1, W1^T, W2, W2^T from the FP32 parameters.
+__global__ __launch_bounds__(256) void k_mlp_prepare(const float* __restrict__ P, __bf16* __restrict__ Wb) {
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    if (e < kW * kIn) {
+        const int k = e / kIn, f = e % kIn;
+        const __bf16 w = (__bf16)P[kMlpOffW1 + e];
+        Wb[kMlpBfW1 + e] = w;
+        Wb[kMlpBfW1T + f * kW + k] = w;
+    }
+    if (e < kW * kW) {
+        const int c = e / kW, k = e % kW;
+        const __bf16 w = (__bf16)P[kMlpOffW2 + e];
+        Wb[kMlpBfW2 + e] = w;
+        Wb[kMlpBfW2T + k * kW + c] = w;
+    }
+}
+
+__global__ void k_mlp_loss(const float* __restrict__ part, int tiles, float* loss) {
+    float s = 0.0f;
+    for (int q = 0; q < tiles; ++q) s += part[(int64_t)q * kMlpPartStride + 769];
+    *loss = s;
+}
+
+}  // namespace
+
+hipError_t launch_mlp_prepare(const float* P, __bf16* Wb, hipStream_t st) {
+    hipLaunchKernelGGL(k_mlp_prepare, dim3((kW * kW + 255) / 256), dim3(256), 0, st, P, Wb);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_infer(const float* P, const __bf16* Wb, const float* X, int x_mode, int M, int n_in, int d,
+                            const float* enc, float* y_out, float* cost_out, float* grad_out, float grad_scale,
+                            hipStream_t st) {
+    hipLaunchKernelGGL(k_mlp_infer, dim3((M + kRows - 1) / kRows), dim3(256), 0, st, P, Wb, X, x_mode, M, n_in, d,
+                       enc, y_out, cost_out, grad_out, grad_scale);
+    return hipGetLastError();
+}
+
+MlpTrainLayout mlp_train_layout(int M) {
+    MlpTrainLayout L{};
+    const size_t act = (size_t)M * 2;  // bytes per feature row of a bf16 activation
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = (off + bytes + 255) & ~size_t(255);
+        return o;
+    };
+    L.ut = take(act * kIn);
+    L.h1t = take(act * kW);
+    L.d2t = take(act * kW);
+    L.d1t = take(act * kW);
+    L.dw1 = take((size_t)kW * kIn * 4);
+    L.dw2 = take((size_t)kW * kW * 4);
+    L.part = take((size_t)(M / kRows) * kMlpPartStride * 4);
+    L.total = off;
+    return L;
+}
+
+hipError_t launch_mlp_train_step(float* P, __bf16* Wb, float* mom, float* vel, int t, float lr, float b1, float b2,
+                                 float eps, const float* X, const float* target, int M, int n_in, float* loss_out,
+                                 char* ws, const MlpTrainLayout& L, hipStream_t st) {
+    __bf16* UT = reinterpret_cast<__bf16*>(ws + L.ut);
+    __bf16* H1T = reinterpret_cast<__bf16*>(ws + L.h1t);
+    __bf16* D2T = reinterpret_cast<__bf16*>(ws + L.d2t);
+    __bf16* D1T = reinterpret_cast<__bf16*>(ws + L.d1t);
+    float* dW1 = reinterpret_cast<float*>(ws + L.dw1);
+    float* dW2 = reinterpret_cast<float*>(ws + L.dw2);
+    float* part = reinterpret_cast<float*>(ws + L.part);
+    const int tiles = M / kRows;
+    hipLaunchKernelGGL(k_mlp_train_fb, dim3(tiles), dim3(256), 0, st, P, Wb, X, target, M, n_in, UT, H1T, D2T, D1T,
+                       part);
+    hipLaunchKernelGGL(k_mlp_wgrad, dim3((kW / 16) * (kW / 16)), dim3(64), 0, st, D2T, H1T, M, kW, dW2);
+    hipLaunchKernelGGL(k_mlp_wgrad, dim3((kW / 16) * (kIn / 16)), dim3(64), 0, st, D1T, UT, M, kIn, dW1);
+    if (loss_out) hipLaunchKernelGGL(k_mlp_loss, dim3(1), dim3(1), 0, st, part, tiles, loss_out);
+    hipLaunchKernelGGL(k_mlp_adam, dim3((kMlpParams + 255) / 256), dim3(256), 0, st, P, mom, vel, dW1, dW2, part,
+                       tiles, n_in, t, lr, b1, b2, eps);
+    hipLaunchKernelGGL(k_mlp_prepare, dim3((kW * kW + 255) / 256), dim3(256), 0, st, P, Wb);
+    return hipGetLastError();
+}
+
+}  // namespace stamp

@@ -667,4 +667,53 @@ int32_t stamp_solve(stamp_ctx* ctx, int32_t n_problems, const stamp_scene* scene
     return STAMP_OK;
 }
 
+// ---- learned cost surrogate --------------------------------------------------
+
+int32_t stamp_mlp_prepare(stamp_ctx* ctx, const float* params, void* wbf16, void* stream) {
+    if (!ctx) return STAMP_EINVAL;
+    if (!params || !wbf16) return fail(ctx, STAMP_EINVAL, "null params or wbf16");
+    hipError_t e = launch_mlp_prepare(params, (__bf16*)wbf16, (hipStream_t)stream);
+    return e == hipSuccess ? STAMP_OK : hip_fail(ctx, e, "mlp_prepare");
+}
+
+int32_t stamp_mlp_forward(stamp_ctx* ctx, int32_t M, int32_t n_in, int32_t d, const float* params, const void* wbf16,
+                          const float* x, int32_t x_layout, const float* enc, float* y, float* cost, float* grad,
+                          float grad_scale, void* stream) {
+    if (!ctx) return STAMP_EINVAL;
+    if (!params || !wbf16 || !x) return fail(ctx, STAMP_EINVAL, "null params, wbf16 or x");
+    if (M < 1) return fail(ctx, STAMP_EINVAL, "M=%d < 1", M);
+    if (n_in < 1 || n_in > kMlpIn) return fail(ctx, STAMP_EINVAL, "n_in=%d not in [1,%d]", n_in, kMlpIn);
+    if (d < 1 || d > n_in) return fail(ctx, STAMP_EINVAL, "d=%d not in [1,n_in]", d);
+    if (x_layout != 0 && x_layout != 1) return fail(ctx, STAMP_EINVAL, "x_layout=%d not 0 or 1", x_layout);
+    if (x_layout == 1 && d < n_in && !enc) return fail(ctx, STAMP_EINVAL, "null scene encoding");
+    if (!isfinite(grad_scale)) return fail(ctx, STAMP_EINVAL, "non-finite grad_scale");
+    hipError_t e = launch_mlp_infer(params, (const __bf16*)wbf16, x, x_layout, M, n_in, d, enc, y, cost, grad,
+                                    grad_scale, (hipStream_t)stream);
+    return e == hipSuccess ? STAMP_OK : hip_fail(ctx, e, "mlp_forward");
+}
+
+size_t stamp_mlp_train_workspace_bytes(int32_t M) {
+    if (M < 64 || M % 64) return 0;
+    return mlp_train_layout(M).total;
+}
+
+int32_t stamp_mlp_train_step(stamp_ctx* ctx, int32_t M, int32_t n_in, const float* x, const float* target,
+                             float* params, void* wbf16, float* adam_m, float* adam_v, int32_t t, float lr,
+                             float beta1, float beta2, float eps, float* loss, void* workspace, size_t ws_bytes,
+                             void* stream) {
+    if (!ctx) return STAMP_EINVAL;
+    if (!x || !target || !params || !wbf16 || !adam_m || !adam_v) return fail(ctx, STAMP_EINVAL, "null pointer");
+    if (M < 64 || M % 64) return fail(ctx, STAMP_EINVAL, "M=%d must be a positive multiple of 64", M);
+    if (n_in < 1 || n_in > kMlpIn) return fail(ctx, STAMP_EINVAL, "n_in=%d not in [1,%d]", n_in, kMlpIn);
+    if (t < 1) return fail(ctx, STAMP_EINVAL, "Adam step t=%d < 1", t);
+    if (!isfinite(lr) || !(beta1 >= 0 && beta1 < 1 && beta2 >= 0 && beta2 < 1 && eps >= 0))
+        return fail(ctx, STAMP_EINVAL, "bad Adam hyper-parameters");
+    const MlpTrainLayout L = mlp_train_layout(M);
+    if (!workspace || ws_bytes < L.total)
+        return fail(ctx, STAMP_ENOSPACE, "mlp train workspace %zu < %zu bytes", ws_bytes, L.total);
+    hipError_t e = launch_mlp_train_step(params, (__bf16*)wbf16, adam_m, adam_v, t, lr, beta1, beta2, eps, x, target,
+                                         M, n_in, loss, (char*)workspace, L, (hipStream_t)stream);
+    return e == hipSuccess ? STAMP_OK : hip_fail(ctx, e, "mlp_train_step");
+}
+
 }  // extern "C"

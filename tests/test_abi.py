@@ -86,3 +86,28 @@ def test_null_context_is_rejected():
     assert lib.stamp_rollout_fwd(None, None, None, 1, None, None, None, 0, None, None) == S.EINVAL
     assert lib.stamp_svgd_step(None, 1, 1, None, None, 0.0, None, None, None, 0, None) == S.EINVAL
     assert lib.stamp_create(None, 0) == S.EINVAL
+
+
+def test_mlp_parameter_layout_and_sizing():
+    """pack/unpack of the surrogate parameter vector follow the documented
+    offsets; the training workspace is defined for multiples of 64 only."""
+    import numpy as np
+    import paper_2310_01775_amd as S
+    src = open(HEADER).read()
+    for name, val in (("STAMP_MLP_PARAMS", S.MLP_PARAMS), ("STAMP_MLP_BF16_WEIGHTS", S.MLP_BF16_WEIGHTS),
+                      ("STAMP_MLP_WIDTH", S.MLP_WIDTH), ("STAMP_MLP_IN_PAD", S.MLP_IN_PAD),
+                      ("STAMP_SCENE_ENC", W.SCENE_ENC)):
+        assert re.search(r"#define %s %d\b" % (name, val), src), name
+    p = W.mlp_init(54)
+    p["b3"] = np.array([0.25])
+    flat = S.pack_mlp(p)
+    assert flat.shape == (S.MLP_PARAMS,)
+    W1 = flat[128:128 + 256 * 64].reshape(256, 64)
+    assert np.array_equal(W1[:, :54], p["W1"]) and not W1[:, 54:].any()
+    assert np.array_equal(flat[16768:16768 + 65536].reshape(256, 256), p["W2"])
+    assert np.array_equal(flat[82560:82816], p["w3"]) and flat[82816] == 0.25
+    q = S.unpack_mlp(flat, 54)
+    for k in p:
+        assert np.array_equal(q[k], p[k]), k
+    assert S.Context.mlp_train_workspace_bytes(100) == 0
+    assert S.Context.mlp_train_workspace_bytes(64) > 0

@@ -229,4 +229,4 @@ def mlp_init(n_in: int, width: int = 256, seed: int = 0) -> dict:
     return dict(mu=np.zeros(n_in), inv_sigma=np.ones(n_in),
                 W1=u((width, n_in), n_in), b1=np.zeros(width),
                 W2=u((width, width), width), b2=np.zeros(width),
-                w3=u((width,), width) * 0.1, b3=np.zeros(1))
+                w3=f32(u((width,), width) * 0.1), b3=np.zeros(1))
