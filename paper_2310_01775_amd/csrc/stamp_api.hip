@@ -234,6 +234,17 @@ void build_plan(int n, const stamp_scene* scenes, const int32_t* N, int K, float
             P.red_work.push_back(make_int4(p, (int)e, (int)std::min<int64_t>(e + kRedChunk, ne), 0));
     }
     P.n_theta = th;
+    // The contraction lists get the room of their longest form (64-row
+    // blocks), so that no region of the workspace moves when the row block
+    // changes: pointers into it stay valid across every launch shape.
+    size_t phi_cap[kDpClasses] = {};
+    for (int p = 0; p < n; ++p) {
+        const ProblemDesc& D = P.descs[p];
+        if (D.N < 2) continue;
+        int c = 0;
+        while (kDpClass[c] != svgd_dp_class(D.d)) ++c;
+        phi_cap[c] += (size_t)((D.N + 63) / 64) * D.sv.splits;
+    }
     size_t off = 0;
     auto take = [&](size_t bytes) {
         const size_t o = off;
@@ -246,7 +257,7 @@ void build_plan(int n, const stamp_scene* scenes, const int32_t* N, int K, float
     P.dist_off = take(P.dist_work.size() * sizeof(int4));
     P.hist_off = take(P.hist_work.size() * sizeof(int4));
     P.red_off = take(P.red_work.size() * sizeof(int4));
-    for (int c = 0; c < kDpClasses; ++c) P.phi_off[c] = take(P.phi_work[c].size() * sizeof(int4));
+    for (int c = 0; c < kDpClasses; ++c) P.phi_off[c] = take(phi_cap[c] * sizeof(int4));
     P.ctr_off = take(256);
     P.tape_off = take((size_t)tp * 4);
     P.seg_off = take((size_t)sg * 4);
@@ -257,15 +268,22 @@ void build_plan(int n, const stamp_scene* scenes, const int32_t* N, int K, float
     P.total = off;
 }
 
-// Upper bound of the plan size over every phi row choice of the autotuner.
+// Workspace of a solve (the same for every phi row choice of the autotuner).
 size_t plan_bytes(int n, const stamp_scene* scenes, const int32_t* N, int K, float bandwidth) {
-    size_t m = 0;
-    for (int rows : {64, 128, 256}) {
-        SolvePlan P;
-        build_plan(n, scenes, N, K, bandwidth, rows, nullptr, P);
-        m = std::max(m, P.total);
-    }
-    return m;
+    SolvePlan P;
+    build_plan(n, scenes, N, K, bandwidth, 256, nullptr, P);
+    return P.total;
+}
+
+// True when two plans place every workspace region at the same offset.
+bool same_layout(const SolvePlan& a, const SolvePlan& b) {
+    bool ok = a.total == b.total && a.clk_off == b.clk_off && a.desc_off == b.desc_off && a.roll_off == b.roll_off &&
+              a.dist_off == b.dist_off && a.hist_off == b.hist_off && a.red_off == b.red_off &&
+              a.ctr_off == b.ctr_off && a.tape_off == b.tape_off && a.seg_off == b.seg_off &&
+              a.grad_off == b.grad_off && a.phi_vec_off == b.phi_vec_off && a.cost_off == b.cost_off &&
+              a.svgd_off == b.svgd_off;
+    for (int c = 0; c < kDpClasses; ++c) ok = ok && a.phi_off[c] == b.phi_off[c];
+    return ok;
 }
 
 __global__ void k_stamp_clock(uint64_t* dst) { *dst = wall_clock64(); }
@@ -478,13 +496,21 @@ int32_t stamp_solve(stamp_ctx* ctx, int32_t n_problems, const stamp_scene* scene
     // launch shapes: tuned once per batch signature
     SolvePlan P;
     build_plan(n_problems, scenes, N, K, cfg->bandwidth, 256, &consts, P);
+    // Every rebuild below (another row block) must keep the regions where the
+    // pointers derived next point: the layout reserves the longest lists.
+    const SolvePlan layout0 = P;
+    auto rebuild = [&](int rows) -> bool {
+        build_plan(n_problems, scenes, N, K, cfg->bandwidth, rows, &consts, P);
+        return same_layout(P, layout0);
+    };
     const std::string tkey = P.key + "K" + std::to_string(K) + (cfg->bandwidth > 0 ? "fixed" : "median");
     StampTune tune;
     auto it_t = ctx->tune.find(tkey);
     const bool have_tune = ctx->is_pinned || it_t != ctx->tune.end();
     if (ctx->is_pinned) tune = ctx->pinned;
     else if (have_tune) tune = it_t->second;
-    if (tune.phi_rows != 256) build_plan(n_problems, scenes, N, K, cfg->bandwidth, tune.phi_rows, &consts, P);
+    if (tune.phi_rows != 256 && !rebuild(tune.phi_rows))
+        return fail(ctx, STAMP_EINVAL, "internal: workspace layout depends on the row block");
 
     char* ws = (char*)workspace;
     ProblemDesc* d_desc = (ProblemDesc*)(ws + P.desc_off);
@@ -573,9 +599,7 @@ int32_t stamp_solve(stamp_ctx* ctx, int32_t n_problems, const stamp_scene* scene
             }
             best = 1e30f;
             for (int rows : {64, 128, 256}) {
-                SolvePlan Q;
-                build_plan(n_problems, scenes, N, K, cfg->bandwidth, rows, &consts, Q);
-                P = std::move(Q);
+                if (!rebuild(rows)) return fail(ctx, STAMP_EINVAL, "internal: workspace layout depends on the row block");
                 STAMP_TRY(upload_lists(), "upload work lists");
                 const BatchPlan B = batch_plan();
                 const float ms =
@@ -588,7 +612,8 @@ int32_t stamp_solve(stamp_ctx* ctx, int32_t n_problems, const stamp_scene* scene
             (void)hipEventDestroy(a);
             (void)hipEventDestroy(b);
             if (P.phi_rows != tune.phi_rows) {
-                build_plan(n_problems, scenes, N, K, cfg->bandwidth, tune.phi_rows, &consts, P);
+                if (!rebuild(tune.phi_rows))
+                    return fail(ctx, STAMP_EINVAL, "internal: workspace layout depends on the row block");
                 STAMP_TRY(upload_lists(), "upload work lists");
             }
         }

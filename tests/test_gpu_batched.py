@@ -145,3 +145,35 @@ def test_every_launch_shape_gives_the_same_bits(ctx, roll_block, roll_grid, phi_
     finally:
         ctx.set_launch_shape(0, 0, 0)
     assert torch.equal(theta, ref)
+
+
+def test_first_autotuned_solve_of_a_large_batch_is_exact():
+    """The first solve of a batch signature tunes the contraction row block,
+    which changes the length of its work lists; every other workspace region
+    must stay where the solve's pointers point (regression: a tuned row block
+    below 256 once moved the tape and counter regions under the stale
+    pointers, so the first rollout overwrote the work lists).  The tuned run,
+    on a fresh context, must equal a run with pinned shapes bit for bit, and
+    so must the following calls that resume the Adam step count."""
+    import paper_2310_01775_amd as S
+    sizes = [(1024, 3, 2)] * 24 + [(2048, 5, 3)] * 8
+    probs = _problems(sizes, 20, 0.005, 3)
+    Ns = [th.shape[0] for _, _, th in probs]
+    scenes = [S.make_scene(s) for s, _, _ in probs]
+    ws_ = [S.make_cost(w) for _, w, _ in probs]
+    flat = _pack(S, probs)
+    results = []
+    for pinned in (False, True):
+        c = S.Context(0)
+        try:
+            if pinned:
+                c.set_launch_shape(64, 0, 256)
+            th, m, v = flat.clone(), torch.zeros_like(flat), torch.zeros_like(flat)
+            print("large batch, pinned" if pinned else "large batch, autotuned", flush=True)
+            for k in range(3):
+                c.solve(scenes, ws_, Ns, S.make_cfg(2, t0=2 * k, lr=1e-3), th, m, v)
+            torch.cuda.synchronize()
+            results.append(th)
+        finally:
+            c.close()
+    assert torch.equal(results[0], results[1])
