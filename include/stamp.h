@@ -66,6 +66,7 @@ extern "C" {
 #define STAMP_STATUS_NONFINITE_COST 1u
 #define STAMP_STATUS_NONFINITE_GRAD 2u
 #define STAMP_STATUS_NONFINITE_PHI 4u
+#define STAMP_STATUS_BAD_INDEX 8u     /* a training index outside the dataset */
 
 typedef struct stamp_ctx stamp_ctx;
 
@@ -217,15 +218,19 @@ int32_t stamp_solve(stamp_ctx* ctx, int32_t n_problems, const stamp_scene* scene
 
 
 /* ---- learned cost surrogate ------------------------------------------------
- * A network that predicts a plan's rollout cost from the plan and a scene
- * encoding, so that early SVGD iterations can take its gradient in place of
- * the adjoint's.  It extends the method (the paper differentiates the
- * simulator throughout, Sec. III-B); the true rollout stays the judge.
+ * A network that predicts the rollout part of a plan's cost from the plan and
+ * a scene encoding, so that early SVGD iterations can take its gradient in
+ * place of the adjoint's.  It extends the method (the paper differentiates the
+ * simulator throughout, Sec. III-B); the true rollout stays the judge and the
+ * fallback.
  *
  *   x = [theta (d), scene encoding (n_in - d)],  n_in <= 64
  *   u = (x - mu) * inv_sigma
  *   h1 = gelu(W1 u + b1), h2 = gelu(W2 h1 + b2)       (width 256, exact erf GELU)
- *   y = w3 . h2 + b3,    C_hat = exp(y) - 1             (y predicts log(1 + C))
+ *   y = w3 . h2 + b3                                    (y predicts log(1 + C_roll))
+ *   C_hat = exp(y) - 1 + bound * L_bound(theta)
+ * C_roll is the cost of Appendix E-B without its bound term; L_bound (a closed
+ * form in theta, no rollout) is added exactly, with its gradient.
  *
  * Parameter vector `params` (STAMP_MLP_PARAMS floats, FP32 master copy):
  *   [0,64) mu, [64,128) inv_sigma, [128, 16512) W1 as [256][64] (row = output,
@@ -235,38 +240,105 @@ int32_t stamp_solve(stamp_ctx* ctx, int32_t n_problems, const stamp_scene* scene
  * copies the matrix cores read: W1, W1^T, W2, W2^T.  stamp_mlp_prepare fills it
  * from params; stamp_mlp_train_step refreshes it after each update.
  * Arithmetic: BF16 inputs to the matrix products, FP32 accumulation, FP32
- * biases, GELU, output layer and Adam. */
+ * biases, GELU, output layer, bound term and Adam. */
 
 /* Fill wbf16 from params.  Errors: STAMP_EINVAL for null pointers. */
 int32_t stamp_mlp_prepare(stamp_ctx* ctx, const float* params, void* wbf16, void* stream);
+
+/* Set mu and inv_sigma of params from training inputs x [M][n_in]: the mean
+ * and population standard deviation of each input (inv_sigma = 1/max(sd,
+ * 1e-3)); inputs n_in..63 get mu 0, inv_sigma 1.  With cost [M] (device, may
+ * be NULL) the output bias b3 starts at the mean target, mean log(1 + cost).
+ * Other entries untouched.
+ * Errors: STAMP_EINVAL for null x or params, M < 1, n_in not in 1..64. */
+int32_t stamp_mlp_standardize(stamp_ctx* ctx, int32_t M, int32_t n_in, const float* x, const float* cost,
+                              float* params, void* stream);
+
+/* Label training plans with the simulator: roll the N particles theta [d][N]
+ * forward (as stamp_rollout_fwd, without the bound term of w) into cost [N],
+ * and write their network inputs x [N][n_in] = [theta_i, enc] with enc the
+ * n_in - d floats of the scene encoding (device).
+ * Errors: as stamp_rollout_fwd; STAMP_EINVAL if n_in < d or n_in > 64, or enc
+ * is NULL while n_in > d. */
+int32_t stamp_mlp_label(stamp_ctx* ctx, const stamp_scene* scene, const stamp_cost_w* w, int32_t N,
+                        const float* theta, int32_t n_in, const float* enc, float* x, float* cost,
+                        uint32_t* status, void* stream);
 
 /* Evaluate the network on M samples.
  *   x_layout 0: x is [M][n_in] (sample-major), enc ignored;
  *   x_layout 1: x is [d][M] (the particle layout), enc [n_in - d] device floats
  *               shared by all samples.
- *   y [M] (log-cost), cost [M] (C_hat) and grad [d][M] = grad_scale * dC_hat/dx
- *   over the first d inputs are each optional (NULL skips).
+ *   w: NULL, or cost weights whose bound term (weight, o_max, d_max) is added
+ *      to cost and grad; then d must be a multiple of 6 (plan inputs).
+ *   y [M] (the network output), cost [M] (C_hat) and grad [d][M] =
+ *   grad_scale * dC_hat/dx over the first d inputs are each optional (NULL skips).
  * Errors: STAMP_EINVAL for null params/wbf16/x, M < 1, n_in not in 1..64,
- * d not in 1..n_in, x_layout not 0 or 1, or enc NULL with x_layout 1 and d < n_in. */
+ * d not in 1..n_in, x_layout not 0 or 1, enc NULL with x_layout 1 and d < n_in,
+ * or w given with d not a multiple of 6. */
 int32_t stamp_mlp_forward(stamp_ctx* ctx, int32_t M, int32_t n_in, int32_t d, const float* params,
                           const void* wbf16, const float* x, int32_t x_layout, const float* enc,
-                          float* y, float* cost, float* grad, float grad_scale, void* stream);
+                          const stamp_cost_w* w, float* y, float* cost, float* grad, float grad_scale,
+                          void* stream);
 
 /* Workspace bytes of stamp_mlp_train_step for a minibatch of M samples. */
 size_t stamp_mlp_train_workspace_bytes(int32_t M);
 
 /* One Adam step (step count t >= 1, bias-corrected) of the mean squared error
- * (1/M) sum_i (y_i - target_i)^2 over the minibatch x [M][n_in], target [M],
- * updating W1, b1, W2, b2, w3, b3 of params in place (mu and inv_sigma fixed)
- * with the Adam moments adam_m, adam_v (STAMP_MLP_PARAMS floats each, caller
- * zeroes them before step 1), then refreshing wbf16.  loss (one device float,
- * may be NULL) receives the loss of the weights before the step.
+ * (1/M) sum_i (y_i - log(1 + cost[r_i]))^2 over a minibatch of M dataset rows
+ * r_i = idx[i] (idx: M device int32, or NULL for rows 0..M-1) of the dataset
+ * x [n_rows][n_in], cost [n_rows] (stamp_mlp_label writes both).  Updates W1,
+ * b1, W2, b2, w3, b3 of params in place (mu, inv_sigma fixed) with the Adam
+ * moments adam_m, adam_v (STAMP_MLP_PARAMS floats each, zero before step 1),
+ * then refreshes wbf16.  loss (one device float, may be NULL) receives the
+ * loss of the weights before the step.  An index outside [0, n_rows) reads
+ * row 0 and sets STAMP_STATUS_BAD_INDEX in status (may be NULL).
  * Errors: STAMP_EINVAL for null pointers, M < 64 or not a multiple of 64, n_in
- * not in 1..64, t < 1; STAMP_ENOSPACE if ws_bytes is too small. */
-int32_t stamp_mlp_train_step(stamp_ctx* ctx, int32_t M, int32_t n_in, const float* x, const float* target,
-                             float* params, void* wbf16, float* adam_m, float* adam_v, int32_t t, float lr,
-                             float beta1, float beta2, float eps, float* loss, void* workspace,
-                             size_t ws_bytes, void* stream);
+ * not in 1..64, n_rows < 1 (or < M without idx), t < 1; STAMP_ENOSPACE if
+ * ws_bytes is too small. */
+int32_t stamp_mlp_train_step(stamp_ctx* ctx, int32_t M, int32_t n_in, const float* x, const float* cost,
+                             const int32_t* idx, int32_t n_rows, float* params, void* wbf16, float* adam_m,
+                             float* adam_v, int32_t t, float lr, float beta1, float beta2, float eps, float* loss,
+                             uint32_t* status, void* workspace, size_t ws_bytes, void* stream);
+
+/* Surrogate phase of stamp_solve_surrogate. */
+typedef struct stamp_surrogate {
+    int32_t iters;        /* leading iterations that take the network's gradient (0..cfg->iters) */
+    int32_t n_in;         /* network inputs; problem p's encoding has n_in - d_p floats */
+    int32_t check_every;  /* > 0: judge the network against the rollout every so many
+                             surrogate iterations; the phase always ends with one check */
+    float max_log_err;    /* > 0: leave the surrogate phase early when a check finds the
+                             mean |log(1+C_hat) - log(1+C)| of any problem above it */
+    const float* params;  /* device, STAMP_MLP_PARAMS floats */
+    const void* wbf16;    /* device, STAMP_MLP_BF16_WEIGHTS bf16 (stamp_mlp_prepare) */
+    const float* enc;     /* device, the problems' scene encodings one after another */
+} stamp_surrogate;
+
+/* What the surrogate phase did (host struct, filled before the call returns). */
+typedef struct stamp_surrogate_report {
+    int32_t iters_run;    /* surrogate iterations actually taken */
+    int32_t fell_back;    /* 1 if a check ended the phase early */
+    int32_t checks;       /* checks made */
+    float log_err;        /* mean |log(1+C_hat) - log(1+C)| at the last check, max over problems */
+} stamp_surrogate_report;
+
+/* stamp_solve with a surrogate phase: the first sur->iters iterations use the
+ * network's cost gradient (exact bound term included) in place of the
+ * rollout adjoint, every other stage unchanged; the remaining iterations are
+ * the true iterations of stamp_solve, continuing the same Adam step count.
+ * The surrogate iteration is captured once into its own HIP graph and
+ * replayed in chunks of check_every.  Each check rolls the particles forward
+ * through the simulator, compares its cost with the network's and may end the
+ * phase (fallback to the simulator).  The call blocks the host at each check.
+ * Workspace: stamp_solve_workspace_bytes (the same plan).  report may be NULL.
+ * Errors: as stamp_solve; STAMP_EINVAL for a null sur, sur->iters outside
+ * [0, cfg->iters], n_in outside [max d_p, 64], null params/wbf16, or a null
+ * enc while some problem has n_in > d_p. */
+int32_t stamp_solve_surrogate(stamp_ctx* ctx, int32_t n_problems, const stamp_scene* scenes,
+                              const stamp_cost_w* w, const int32_t* N, const stamp_solver_cfg* cfg,
+                              const stamp_surrogate* sur, float* theta, float* adam_m, float* adam_v,
+                              float* cost_out, int32_t* modes_out, float* solve_time_us,
+                              stamp_surrogate_report* report, void* workspace, size_t ws_bytes,
+                              uint32_t* status, void* stream);
 
 #ifdef __cplusplus
 }

@@ -15,6 +15,11 @@ Network (float64 here):
     C_hat = exp(y) - 1,   grad_theta C_hat = exp(y) * grad_theta y
 Training: mean squared error of y against log(1 + C) over a minibatch, Adam on
 the weights (mu and inv_sigma are fixed standardisation constants).
+
+In the solver the network learns the rollout part of the cost only (the cost
+of Appendix E-B with its bound weight set to zero); the bound term, a closed
+form in the plan, is added exactly:
+    C_hat(theta) = exp(y(theta, enc)) - 1 + b_b L_bound(theta)
 """
 from __future__ import annotations
 
@@ -22,6 +27,8 @@ import math
 
 import numpy as np
 import torch
+
+from . import sim
 
 DT = torch.float64
 WIDTH = 256
@@ -84,3 +91,36 @@ def adam_update(params: dict, grads: dict, m: dict, v: dict, t: int, lr=1e-3, be
         out_p[k] = np.asarray(params[k], dtype=np.float64) - lr * mhat / (np.sqrt(vhat) + eps)
         out_m[k], out_v[k] = mm, vv
     return out_p, out_m, out_v
+
+
+def _net(P, X):
+    u = (X - P["mu"]) * P["inv_sigma"]
+    h1 = gelu(u @ P["W1"].T + P["b1"])
+    h2 = gelu(h1 @ P["W2"].T + P["b2"])
+    return h2 @ P["w3"] + P["b3"]
+
+
+def surrogate_cost_and_grad(params: dict, theta, enc, w: dict):
+    """C_hat and dC_hat/dtheta of plans theta [N][d] (d = 6H) in the scene
+    encoded by enc [n_in - d]: the network's rollout-cost prediction plus the
+    exact bound term."""
+    P = unpack(params)
+    th = torch.as_tensor(np.asarray(theta, dtype=np.float64)).clone().requires_grad_(True)
+    N, d = th.shape
+    e = torch.as_tensor(np.asarray(enc, dtype=np.float64)).reshape(1, -1).expand(N, -1)
+    y = _net(P, torch.cat([th, e], dim=1))
+    C = torch.expm1(y) + float(w["bound"]) * sim.bound_term(th, w, d // 6)
+    (g,) = torch.autograd.grad(C.sum(), th)
+    return C.detach().numpy(), g.numpy()
+
+
+def training_loss_and_grads(params: dict, x, cost):
+    """loss_and_grads against the targets log(1 + cost) of labelled rollouts."""
+    return loss_and_grads(params, x, np.log1p(np.asarray(cost, dtype=np.float64)))
+
+
+def standardization(x):
+    """mu and inv_sigma = 1/max(sigma, 1e-3) of inputs x [M][n_in] (population
+    standard deviation)."""
+    x = np.asarray(x, dtype=np.float64)
+    return x.mean(0), 1.0 / np.maximum(x.std(0), 1e-3)

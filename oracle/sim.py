@@ -246,13 +246,20 @@ def total_cost(scene, w, theta, P, phiT):
     L_traj = torch.zeros_like(PHx)
     for k in range(1, H + 1):
         L_traj = L_traj + mh(P[k - 1], P[k]) + mh(P[k], P[H]) - mh(P[k - 1], P[H])
-    L_bound = torch.zeros_like(PHx)
+    return (float(w["target"]) * L_target + float(w["rot"]) * L_rot
+            + float(w["traj"]) * L_traj + float(w["bound"]) * bound_term(theta, w, H))
+
+
+def bound_term(theta, w, H):
+    """L_bound = sum_k relu(|o_k|-o_max)^2 + relu(-D_k)^2 + relu(D_k-D_max)^2
+    (Appendix E-B): keeps each push's offset on its face and its depth in
+    range.  theta [N][d] tensor; a closed form in the plan, no rollout."""
+    L_bound = torch.zeros(theta.shape[0], dtype=theta.dtype)
     for k in range(H):
         o, Dk = theta[:, 6 * k + 4], theta[:, 6 * k + 5]
         L_bound = (L_bound + _relu(torch.abs(o) - float(w["o_max"])) ** 2
                    + _relu(-Dk) ** 2 + _relu(Dk - float(w["d_max"])) ** 2)
-    return (float(w["target"]) * L_target + float(w["rot"]) * L_rot
-            + float(w["traj"]) * L_traj + float(w["bound"]) * L_bound)
+    return L_bound
 
 
 def cost_np(scene, w, theta, **kw):

@@ -24,7 +24,7 @@ if not os.path.exists(LIB_PATH):
 _lib = C.CDLL(LIB_PATH)
 
 OK, EINVAL, ENOSPACE, EHIP, EUNSUPPORTED = 0, -1, -2, -3, -4
-STATUS_NONFINITE_COST, STATUS_NONFINITE_GRAD, STATUS_NONFINITE_PHI = 1, 2, 4
+STATUS_NONFINITE_COST, STATUS_NONFINITE_GRAD, STATUS_NONFINITE_PHI, STATUS_BAD_INDEX = 1, 2, 4, 8
 MAX_BLOCKS, MAX_PUSHES, MODES = 4, 8, 4
 
 
@@ -49,6 +49,16 @@ class SolverCfg(C.Structure):
                 ("bandwidth", C.c_float), ("ckpt_every", C.c_int32), ("reserved", C.c_int32)]
 
 
+class Surrogate(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("n_in", C.c_int32), ("check_every", C.c_int32),
+                ("max_log_err", C.c_float), ("params", C.c_void_p), ("wbf16", C.c_void_p), ("enc", C.c_void_p)]
+
+
+class SurrogateReport(C.Structure):
+    _fields_ = [("iters_run", C.c_int32), ("fell_back", C.c_int32), ("checks", C.c_int32),
+                ("log_err", C.c_float)]
+
+
 _vp, _i32, _i64, _f32, _sz = C.c_void_p, C.c_int32, C.c_int64, C.c_float, C.c_size_t
 _P = C.POINTER
 _sig = {
@@ -70,10 +80,15 @@ _sig = {
     "stamp_solve": (_i32, [_vp, _i32, _P(Scene), _P(CostW), _P(_i32), _P(SolverCfg), _vp, _vp, _vp, _vp,
                            _vp, _vp, _vp, _sz, _vp, _vp]),
     "stamp_mlp_prepare": (_i32, [_vp, _vp, _vp, _vp]),
-    "stamp_mlp_forward": (_i32, [_vp, _i32, _i32, _i32, _vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp, _f32, _vp]),
+    "stamp_mlp_standardize": (_i32, [_vp, _i32, _i32, _vp, _vp, _vp, _vp]),
+    "stamp_mlp_label": (_i32, [_vp, _P(Scene), _P(CostW), _i32, _vp, _i32, _vp, _vp, _vp, _vp, _vp]),
+    "stamp_mlp_forward": (_i32, [_vp, _i32, _i32, _i32, _vp, _vp, _vp, _i32, _vp, _P(CostW), _vp, _vp, _vp, _f32,
+                                 _vp]),
     "stamp_mlp_train_workspace_bytes": (_sz, [_i32]),
-    "stamp_mlp_train_step": (_i32, [_vp, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _f32, _f32, _f32,
-                                    _f32, _vp, _vp, _sz, _vp]),
+    "stamp_mlp_train_step": (_i32, [_vp, _i32, _i32, _vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp, _i32, _f32, _f32,
+                                    _f32, _f32, _vp, _vp, _vp, _sz, _vp]),
+    "stamp_solve_surrogate": (_i32, [_vp, _i32, _P(Scene), _P(CostW), _P(_i32), _P(SolverCfg), _P(Surrogate), _vp,
+                                     _vp, _vp, _vp, _vp, _vp, _P(SurrogateReport), _vp, _sz, _vp, _vp]),
 }
 for _name, (_res, _args) in _sig.items():
     _f = getattr(_lib, _name)
@@ -322,39 +337,108 @@ class Context:
         self._mlp_buffers(params, wbf16)
         self._check(_lib.stamp_mlp_prepare(self._h, _ptr(params), _ptr(wbf16), _stream(stream)))
 
+    def mlp_standardize(self, params, x, cost=None, stream=None):
+        """Set params' mu / inv_sigma from the rows of x [M][n_in] (and b3 from
+        the mean target log(1 + cost) when cost [M] is given)."""
+        if params.dtype != torch.float32 or params.numel() < MLP_PARAMS:
+            raise ValueError("params must hold %d float32" % MLP_PARAMS)
+        M, n_in = x.shape
+        if cost is not None and tuple(cost.shape) != (M,):
+            raise ValueError("cost must be [M]")
+        self._check(_lib.stamp_mlp_standardize(self._h, M, n_in, _ptr(x), _ptr(cost), _ptr(params),
+                                               _stream(stream)))
+
+    def mlp_label(self, scene: Scene, w: CostW, theta, n_in: int, enc=None, x=None, cost=None, status=None,
+                  stream=None):
+        """Rollout part of the cost of theta [d][N] and the network inputs
+        [N][n_in] = [theta_i, enc]; returns (x, cost)."""
+        d, N = theta.shape
+        if x is None:
+            x = torch.empty((N, n_in), dtype=torch.float32, device=self.device)
+        if cost is None:
+            cost = torch.empty(N, dtype=torch.float32, device=self.device)
+        if tuple(x.shape) != (N, n_in) or tuple(cost.shape) != (N,):
+            raise ValueError("x must be [N][n_in] and cost [N]")
+        if n_in > d and (enc is None or enc.numel() < n_in - d):
+            raise ValueError("enc needs n_in - d floats")
+        self._check(_lib.stamp_mlp_label(self._h, C.byref(scene), C.byref(w), N, _ptr(theta), n_in, _ptr(enc),
+                                         _ptr(x), _ptr(cost), _ptr(status), _stream(stream)))
+        return x, cost
+
     def mlp_forward(self, params, wbf16, x, n_in: int, d: int, x_layout: int = 0, enc=None, want_y=True,
-                    want_cost=False, want_grad=False, grad_scale: float = 1.0, grad=None, stream=None):
+                    want_cost=False, want_grad=False, grad_scale: float = 1.0, grad=None, w: CostW = None,
+                    cost=None, stream=None):
         """x [M][n_in] (x_layout 0) or [d][M] (x_layout 1).  Returns (y, cost, grad)
         with None for what was not asked; grad is [d][M] (written into `grad`
-        when given, which implies want_grad)."""
+        when given, which implies want_grad).  w adds the exact bound term."""
         self._mlp_buffers(params, wbf16)
+        if x_layout == 1 and n_in > d and (enc is None or enc.numel() < n_in - d):
+            raise ValueError("enc needs n_in - d = %d floats" % (n_in - d))
         M = x.shape[0] if x_layout == 0 else x.shape[1]
         if x.shape != ((M, n_in) if x_layout == 0 else (d, M)):
             raise ValueError("x has shape %s, expected %s" % (tuple(x.shape), (M, n_in) if x_layout == 0 else (d, M)))
         y = torch.empty(M, dtype=torch.float32, device=self.device) if want_y else None
-        c = torch.empty(M, dtype=torch.float32, device=self.device) if want_cost else None
+        c = cost
+        if c is None and want_cost:
+            c = torch.empty(M, dtype=torch.float32, device=self.device)
         g = grad
         if g is None and want_grad:
             g = torch.empty((d, M), dtype=torch.float32, device=self.device)
         if g is not None and tuple(g.shape) != (d, M):
             raise ValueError("grad must be [d][M]")
         self._check(_lib.stamp_mlp_forward(self._h, M, n_in, d, _ptr(params), _ptr(wbf16), _ptr(x), int(x_layout),
-                                           _ptr(enc), _ptr(y), _ptr(c), _ptr(g), float(grad_scale),
-                                           _stream(stream)))
+                                           _ptr(enc), C.byref(w) if w is not None else None, _ptr(y), _ptr(c),
+                                           _ptr(g), float(grad_scale), _stream(stream)))
         return y, c, g
 
     @staticmethod
     def mlp_train_workspace_bytes(M: int) -> int:
         return int(_lib.stamp_mlp_train_workspace_bytes(M))
 
-    def mlp_train_step(self, params, wbf16, adam_m, adam_v, x, target, t, lr=1e-3, beta1=0.9, beta2=0.999,
-                       eps=1e-8, loss=None, workspace=None, stream=None):
+    def mlp_train_step(self, params, wbf16, adam_m, adam_v, x, cost, t, idx=None, M=None, lr=1e-3, beta1=0.9,
+                       beta2=0.999, eps=1e-8, loss=None, status=None, workspace=None, stream=None):
+        """One Adam step on the minibatch rows idx (int32 [M]) of the dataset
+        x [n_rows][n_in], cost [n_rows] (targets log(1 + cost)); without idx
+        the first M rows (M defaults to n_rows)."""
         self._mlp_buffers(params, wbf16, adam_m, adam_v)
-        M, n_in = x.shape
-        if tuple(target.shape) != (M,):
-            raise ValueError("target must be [M]")
+        n_rows, n_in = x.shape
+        if tuple(cost.shape) != (n_rows,):
+            raise ValueError("cost must be [n_rows]")
+        if idx is not None:
+            if idx.dtype != torch.int32:
+                raise ValueError("idx must be int32")
+            M = idx.numel()
+        elif M is None:
+            M = n_rows
         if workspace is None:
             workspace = self._bytes(self.mlp_train_workspace_bytes(M))
-        self._check(_lib.stamp_mlp_train_step(self._h, M, n_in, _ptr(x), _ptr(target), _ptr(params), _ptr(wbf16),
-                                              _ptr(adam_m), _ptr(adam_v), int(t), lr, beta1, beta2, eps,
-                                              _ptr(loss), _ptr(workspace), workspace.numel(), _stream(stream)))
+        self._check(_lib.stamp_mlp_train_step(self._h, M, n_in, _ptr(x), _ptr(cost), _ptr(idx), n_rows, _ptr(params),
+                                              _ptr(wbf16), _ptr(adam_m), _ptr(adam_v), int(t), lr, beta1, beta2, eps,
+                                              _ptr(loss), _ptr(status), _ptr(workspace), workspace.numel(),
+                                              _stream(stream)))
+
+    def solve_surrogate(self, scenes, ws_, Ns, cfg: SolverCfg, sur_iters: int, params, wbf16, n_in: int, enc,
+                        theta, adam_m=None, adam_v=None, check_every: int = 0, max_log_err: float = 0.0,
+                        cost_out=None, modes_out=None, solve_time_us=None, workspace=None, status=None,
+                        stream=None):
+        """stamp_solve_surrogate: returns (cost_out, report)."""
+        self._mlp_buffers(params, wbf16)
+        n = len(scenes)
+        arr = (Scene * n)(*scenes)
+        warr = (CostW * n)(*ws_)
+        ns = (C.c_int32 * n)(*Ns)
+        if cost_out is None:
+            cost_out = torch.empty(sum(Ns), dtype=torch.float32, device=self.device)
+        if workspace is None:
+            workspace = self._bytes(self.solve_workspace_bytes(scenes, Ns, cfg))
+        need_enc = sum(max(0, n_in - 6 * sc.H) for sc in scenes)
+        if need_enc and (enc is None or enc.numel() < need_enc):
+            raise ValueError("enc needs %d floats" % need_enc)
+        sur = Surrogate(int(sur_iters), int(n_in), int(check_every), float(max_log_err), params.data_ptr(),
+                        wbf16.data_ptr(), enc.data_ptr() if enc is not None else None)
+        rep = SurrogateReport()
+        self._check(_lib.stamp_solve_surrogate(self._h, n, arr, warr, ns, C.byref(cfg), C.byref(sur), _ptr(theta),
+                                               _ptr(adam_m), _ptr(adam_v), _ptr(cost_out), _ptr(modes_out),
+                                               _ptr(solve_time_us), C.byref(rep), _ptr(workspace), workspace.numel(),
+                                               _ptr(status), _stream(stream)))
+        return cost_out, rep

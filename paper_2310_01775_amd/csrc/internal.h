@@ -56,12 +56,23 @@ hipError_t launch_mlp_prepare(const float* P, __bf16* Wb, hipStream_t st);
 // x_mode 0: X is [M][n_in]; x_mode 1: X is [d][M] (structure of arrays) and
 // inputs d..n_in-1 are enc[0..n_in-d).  Any of y_out / cost_out / grad_out may
 // be null; grad_out is [d][M] = grad_scale * dC_hat/dx.
+// bound_H > 0 adds the exact bound term (weight wb) of the first 6*bound_H
+// inputs to cost_out and grad_out.
 hipError_t launch_mlp_infer(const float* P, const __bf16* Wb, const float* X, int x_mode, int M, int n_in, int d,
-                            const float* enc, float* y_out, float* cost_out, float* grad_out, float grad_scale,
-                            hipStream_t st);
-// One Adam step of the mean squared error over M samples (M % 64 == 0).
+                            const float* enc, int bound_H, float wb, float omax, float dmax, float* y_out,
+                            float* cost_out, float* grad_out, float grad_scale, hipStream_t st);
+// One Adam step of the mean squared error of y against log(1 + cost) over M
+// samples (M % 64 == 0), sample i = dataset row idx[i] (or i).
 hipError_t launch_mlp_train_step(float* P, __bf16* Wb, float* mom, float* vel, int t, float lr, float b1, float b2,
-                                 float eps, const float* X, const float* target, int M, int n_in, float* loss_out,
-                                 char* ws, const MlpTrainLayout& L, hipStream_t st);
+                                 float eps, const float* X, const float* cost, const int* idx, int n_rows, int M,
+                                 int n_in, float* loss_out, uint32_t* status, char* ws, const MlpTrainLayout& L,
+                                 hipStream_t st);
+// out[p] = mean over problem p's particles of |log(1 + c_sur) - log(1 + c_true)|
+// (costs at the problems' cost offsets).
+hipError_t launch_log_err(const ProblemDesc* descs, int n_problems, const float* c_true, const float* c_sur,
+                          float* out, hipStream_t st);
+hipError_t launch_mlp_standardize(const float* X, const float* cost, int M, int n_in, float* P, hipStream_t st);
+hipError_t launch_mlp_pack_rows(const float* theta, int N, int d, const float* enc, int n_in, float* Xo,
+                                hipStream_t st);
 
 }  // namespace stamp

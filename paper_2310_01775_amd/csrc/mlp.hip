@@ -104,22 +104,63 @@ __device__ __forceinline__ MlpPtrs mlp_ptrs(const float* P, const __bf16* Wb) {
 }
 
 // Stage this wave's 16 standardised input rows into U (bf16).  Input sample i:
-// x_mode 0: X[i * n_in + f] (d unused); x_mode 1: f < d from X[f * M + i]
-// (structure of arrays), f >= d from enc[f - d].
+// x_mode 0: X[src * n_in + f] with src = idx ? idx[i] : i (d unused);
+// x_mode 1: f < d from X[f * M + i] (structure of arrays), f >= d from enc[f - d].
 __device__ __forceinline__ void stage_inputs(__bf16* U, const MlpPtrs& m, const float* __restrict__ X, int x_mode,
-                                             int M, int n_in, int d, const float* __restrict__ enc, int row0) {
+                                             int M, int n_in, int d, const float* __restrict__ enc, int row0,
+                                             const int* __restrict__ src_row = nullptr) {
     const int l = threadIdx.x & 63;
     const int r = l & 15;
     const int i = row0 + r;
+    const int64_t src = (src_row && i < M) ? src_row[r] : i;
     for (int f = l >> 4; f < kIn; f += 4) {
         float x = 0.0f;
         if (i < M && f < n_in) {
-            if (x_mode == 0) x = X[(int64_t)i * n_in + f];
+            if (x_mode == 0) x = X[src * n_in + f];
             else x = f < d ? X[(int64_t)f * M + i] : enc[f - d];
         }
         const float u = f < n_in ? (x - m.mu[f]) * m.isig[f] : 0.0f;
         U[r * kLdU + f] = (__bf16)u;
     }
+}
+
+// Exact bound term of the plan cost, added to the network's prediction of
+// the rollout part: wb * sum_k relu(|o_k| - o_max)^2 + relu(-D_k)^2 +
+// relu(D_k - d_max)^2 over the H pushes (o_k = x_{6k+4}, D_k = x_{6k+5}).
+struct BoundTerm {
+    int H;  // 0: no bound term
+    float wb, omax, dmax;
+};
+
+__device__ __forceinline__ float x_raw(const float* __restrict__ X, int x_mode, int M, int n_in, int i, int f) {
+    return x_mode == 0 ? X[(int64_t)i * n_in + f] : X[(int64_t)f * M + i];
+}
+
+__device__ __forceinline__ float bound_cost(const BoundTerm& bt, const float* __restrict__ X, int x_mode, int M,
+                                            int n_in, int i) {
+    float L = 0.0f;
+    for (int k = 0; k < bt.H; ++k) {
+        const float o = x_raw(X, x_mode, M, n_in, i, 6 * k + 4);
+        const float D = x_raw(X, x_mode, M, n_in, i, 6 * k + 5);
+        const float a = fmaxf(fabsf(o) - bt.omax, 0.0f);
+        const float b1 = fmaxf(-D, 0.0f);
+        const float b2 = fmaxf(D - bt.dmax, 0.0f);
+        L += a * a + b1 * b1 + b2 * b2;
+    }
+    return bt.wb * L;
+}
+
+// d(bound term)/dx_f for the raw input value x of coordinate f.
+__device__ __forceinline__ float bound_grad(const BoundTerm& bt, int f, float x) {
+    if (f >= 6 * bt.H) return 0.0f;
+    const int r = f % 6;
+    if (r == 4) {
+        const float a = fmaxf(fabsf(x) - bt.omax, 0.0f);
+        const float sg = x > 0.0f ? 1.0f : (x < 0.0f ? -1.0f : 0.0f);
+        return bt.wb * 2.0f * a * sg;
+    }
+    if (r == 5) return bt.wb * (2.0f * fmaxf(x - bt.dmax, 0.0f) - 2.0f * fmaxf(-x, 0.0f));
+    return 0.0f;
 }
 
 // ---------------------------------------------------------------------------
@@ -128,9 +169,9 @@ __device__ __forceinline__ void stage_inputs(__bf16* U, const MlpPtrs& m, const 
 // exactly d rows of M, in either input layout).
 __global__ __launch_bounds__(256) void k_mlp_infer(const float* __restrict__ P, const __bf16* __restrict__ Wb,
                                                    const float* __restrict__ X, int x_mode, int M, int n_in, int d,
-                                                   const float* __restrict__ enc, float* __restrict__ y_out,
-                                                   float* __restrict__ cost_out, float* __restrict__ grad_out,
-                                                   float grad_scale) {
+                                                   const float* __restrict__ enc, BoundTerm bt,
+                                                   float* __restrict__ y_out, float* __restrict__ cost_out,
+                                                   float* __restrict__ grad_out, float grad_scale) {
     __shared__ __bf16 sU[4][16 * kLdU];
     __shared__ __bf16 sH[4][16 * kLdH];
     __shared__ __bf16 sD[4][16 * kLdH];
@@ -199,7 +240,11 @@ __global__ __launch_bounds__(256) void k_mlp_infer(const float* __restrict__ P, 
             if (f < d) {
                 for (int j = 0; j < 4; ++j) {
                     const int i = row0 + 4 * kq + j;
-                    if (i < M) grad_out[(int64_t)f * M + i] = grad_scale * expf(y[j]) * g[j] * m.isig[f];
+                    if (i < M) {
+                        float gi = expf(y[j]) * g[j] * m.isig[f];
+                        if (bt.H) gi += bound_grad(bt, f, x_raw(X, x_mode, M, n_in, i, f));
+                        grad_out[(int64_t)f * M + i] = grad_scale * gi;
+                    }
                 }
             }
         }
@@ -209,26 +254,31 @@ __global__ __launch_bounds__(256) void k_mlp_infer(const float* __restrict__ P, 
             const int i = row0 + 4 * kq + j;
             if (i < M) {
                 if (y_out) y_out[i] = y[j];
-                if (cost_out) cost_out[i] = expm1f(y[j]);
+                if (cost_out) cost_out[i] = expm1f(y[j]) + (bt.H ? bound_cost(bt, X, x_mode, M, n_in, i) : 0.0f);
             }
         }
     }
 }
 
 // ---------------------------------------------------------------------------
-// Training forward + backward of a minibatch (M a multiple of 64, inputs AoS).
+// Training forward + backward of a minibatch (M a multiple of 64, inputs AoS):
+// sample i is dataset row src = idx ? idx[i] : i of X [n_rows][n_in], its
+// target log(1 + cost[src]).  An index outside [0, n_rows) reads row 0 and
+// sets STAMP_STATUS_BAD_INDEX.
 // Writes feature-major BF16 activations for the weight gradients and per-tile
 // partial sums: part[tile][0..255] = sum delta1, [256..511] = sum delta2,
 // [512..767] = sum delta3 * h2, [768] = sum delta3, [769] = sum (y - t)^2 / M.
 __global__ __launch_bounds__(256) void k_mlp_train_fb(const float* __restrict__ P, const __bf16* __restrict__ Wb,
-                                                      const float* __restrict__ X, const float* __restrict__ target,
-                                                      int M, int n_in, __bf16* __restrict__ UT,
+                                                      const float* __restrict__ X, const float* __restrict__ cost,
+                                                      const int* __restrict__ idx, int n_rows, int M, int n_in,
+                                                      uint32_t* __restrict__ status, __bf16* __restrict__ UT,
                                                       __bf16* __restrict__ H1T, __bf16* __restrict__ D2T,
                                                       __bf16* __restrict__ D1T, float* __restrict__ part) {
     __shared__ __bf16 sU[4][16 * kLdU];
     __shared__ __bf16 sH[4][16 * kLdH];
     __shared__ __bf16 sD[4][16 * kLdH];
     __shared__ float sRed[4][kMlpPartStride];
+    __shared__ int sSrc[4][16];
     const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
     const int kq = l >> 4, col = l & 15;
     const int row0 = blockIdx.x * kRows + wave * 16;
@@ -239,7 +289,16 @@ __global__ __launch_bounds__(256) void k_mlp_train_fb(const float* __restrict__ 
     const MlpPtrs m = mlp_ptrs(P, Wb);
     const float inv_m = 1.0f / (float)M;
 
-    stage_inputs(U, m, X, 0, M, n_in, 0, nullptr, row0);
+    if (l < 16) {
+        int src = idx ? idx[row0 + l] : row0 + l;
+        if (src < 0 || src >= n_rows) {
+            if (status) atomicOr(status, (uint32_t)STAMP_STATUS_BAD_INDEX);
+            src = 0;
+        }
+        sSrc[wave][l] = src;
+    }
+    __syncthreads();
+    stage_inputs(U, m, X, 0, M, n_in, 0, nullptr, row0, sSrc[wave]);
     __syncthreads();
     // U^T for dW1
     for (int f = kq; f < kIn; f += 4) UT[(int64_t)f * M + row0 + col] = U[col * kLdU + f];
@@ -272,7 +331,7 @@ __global__ __launch_bounds__(256) void k_mlp_train_fb(const float* __restrict__ 
     float lsum = 0.0f;
     for (int j = 0; j < 4; ++j) {
         const float y = sum16(yp[j]) + m.b3;
-        const float e = y - target[row0 + 4 * kq + j];
+        const float e = y - log1pf(cost[sSrc[wave][4 * kq + j]]);
         d3[j] = 2.0f * e * inv_m;
         lsum += e * e * inv_m;
     }
@@ -401,6 +460,86 @@ __global__ __launch_bounds__(256) void k_mlp_prepare(const float* __restrict__ P
     }
 }
 
+// mu and inv_sigma from the data: mean and population standard deviation of
+// each input over the M rows of X [M][n_in] (FP64 sums, two passes, one
+// workgroup: 16 row lanes x 64 features, summed in a fixed order).
+// inv_sigma = 1 / max(sigma, 1e-3); padded inputs get mu 0, inv_sigma 1.
+// With cost, b3 = mean log(1 + cost) (the mean training target).
+__global__ __launch_bounds__(1024) void k_mlp_standardize(const float* __restrict__ X, const float* __restrict__ cost,
+                                                          int M, int n_in, float* __restrict__ P) {
+    __shared__ double red[16][kIn];
+    __shared__ double mean[kIn];
+    __shared__ double tsum[1024];
+    const int f = threadIdx.x & 63, r = threadIdx.x >> 6;
+    double s = 0.0;
+    if (f < n_in)
+        for (int64_t i = r; i < M; i += 16) s += (double)X[i * n_in + f];
+    red[r][f] = s;
+    __syncthreads();
+    if (r == 0) {
+        double t = 0.0;
+        for (int q = 0; q < 16; ++q) t += red[q][f];
+        mean[f] = t / (double)M;
+    }
+    __syncthreads();
+    const double mu = mean[f];
+    s = 0.0;
+    if (f < n_in)
+        for (int64_t i = r; i < M; i += 16) {
+            const double e = (double)X[i * n_in + f] - mu;
+            s += e * e;
+        }
+    __syncthreads();
+    red[r][f] = s;
+    __syncthreads();
+    if (r == 0) {
+        double t = 0.0;
+        for (int q = 0; q < 16; ++q) t += red[q][f];
+        const double sd = sqrt(t / (double)M);
+        P[kMlpOffMu + f] = f < n_in ? (float)mu : 0.0f;
+        P[kMlpOffIsig + f] = f < n_in ? (float)(1.0 / fmax(sd, 1e-3)) : 1.0f;
+    }
+    if (cost) {
+        double t = 0.0;
+        for (int64_t i = threadIdx.x; i < M; i += 1024) t += log1p((double)cost[i]);
+        tsum[threadIdx.x] = t;
+        __syncthreads();
+        for (int w = 512; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w) tsum[threadIdx.x] += tsum[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) P[kMlpOffB3] = (float)(tsum[0] / (double)M);
+    }
+}
+
+// Training rows from particles: Xo[i][f] = theta[f][i] for f < d, enc[f - d] after.
+__global__ void k_mlp_pack_rows(const float* __restrict__ theta, int N, int d, const float* __restrict__ enc,
+                                int n_in, float* __restrict__ Xo) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)N * n_in) return;
+    const int i = (int)(e / n_in), f = (int)(e % n_in);
+    Xo[e] = f < d ? theta[(int64_t)f * N + i] : enc[f - d];
+}
+
+// Surrogate check: out[p] = mean_i |log(1 + c_sur_i) - log(1 + c_true_i)| over
+// problem p's particles (one workgroup per problem, fixed-order tree sum).
+__global__ __launch_bounds__(256) void k_log_err(const ProblemDesc* __restrict__ descs, const float* __restrict__ c_true,
+                                                 const float* __restrict__ c_sur, float* __restrict__ out) {
+    __shared__ float red[256];
+    const int p = blockIdx.x;
+    const int N = descs[p].N;
+    const int64_t off = descs[p].cost_off;
+    float s = 0.0f;
+    for (int i = threadIdx.x; i < N; i += 256) s += fabsf(log1pf(c_sur[off + i]) - log1pf(c_true[off + i]));
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[p] = red[0] / (float)N;
+}
+
 __global__ void k_mlp_loss(const float* __restrict__ part, int tiles, float* loss) {
     float s = 0.0f;
     for (int q = 0; q < tiles; ++q) s += part[(int64_t)q * kMlpPartStride + 769];
@@ -415,10 +554,30 @@ hipError_t launch_mlp_prepare(const float* P, __bf16* Wb, hipStream_t st) {
 }
 
 hipError_t launch_mlp_infer(const float* P, const __bf16* Wb, const float* X, int x_mode, int M, int n_in, int d,
-                            const float* enc, float* y_out, float* cost_out, float* grad_out, float grad_scale,
-                            hipStream_t st) {
+                            const float* enc, int bound_H, float wb, float omax, float dmax, float* y_out,
+                            float* cost_out, float* grad_out, float grad_scale, hipStream_t st) {
+    const BoundTerm bt{bound_H, wb, omax, dmax};
     hipLaunchKernelGGL(k_mlp_infer, dim3((M + kRows - 1) / kRows), dim3(256), 0, st, P, Wb, X, x_mode, M, n_in, d,
-                       enc, y_out, cost_out, grad_out, grad_scale);
+                       enc, bt, y_out, cost_out, grad_out, grad_scale);
+    return hipGetLastError();
+}
+
+hipError_t launch_log_err(const ProblemDesc* descs, int n_problems, const float* c_true, const float* c_sur,
+                          float* out, hipStream_t st) {
+    hipLaunchKernelGGL(k_log_err, dim3(n_problems), dim3(256), 0, st, descs, c_true, c_sur, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_standardize(const float* X, const float* cost, int M, int n_in, float* P, hipStream_t st) {
+    hipLaunchKernelGGL(k_mlp_standardize, dim3(1), dim3(1024), 0, st, X, cost, M, n_in, P);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_pack_rows(const float* theta, int N, int d, const float* enc, int n_in, float* Xo,
+                                hipStream_t st) {
+    const int64_t n = (int64_t)N * n_in;
+    hipLaunchKernelGGL(k_mlp_pack_rows, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, theta, N, d, enc, n_in,
+                       Xo);
     return hipGetLastError();
 }
 
@@ -443,8 +602,9 @@ MlpTrainLayout mlp_train_layout(int M) {
 }
 
 hipError_t launch_mlp_train_step(float* P, __bf16* Wb, float* mom, float* vel, int t, float lr, float b1, float b2,
-                                 float eps, const float* X, const float* target, int M, int n_in, float* loss_out,
-                                 char* ws, const MlpTrainLayout& L, hipStream_t st) {
+                                 float eps, const float* X, const float* cost, const int* idx, int n_rows, int M,
+                                 int n_in, float* loss_out, uint32_t* status, char* ws, const MlpTrainLayout& L,
+                                 hipStream_t st) {
     __bf16* UT = reinterpret_cast<__bf16*>(ws + L.ut);
     __bf16* H1T = reinterpret_cast<__bf16*>(ws + L.h1t);
     __bf16* D2T = reinterpret_cast<__bf16*>(ws + L.d2t);
@@ -453,8 +613,8 @@ hipError_t launch_mlp_train_step(float* P, __bf16* Wb, float* mom, float* vel, i
     float* dW2 = reinterpret_cast<float*>(ws + L.dw2);
     float* part = reinterpret_cast<float*>(ws + L.part);
     const int tiles = M / kRows;
-    hipLaunchKernelGGL(k_mlp_train_fb, dim3(tiles), dim3(256), 0, st, P, Wb, X, target, M, n_in, UT, H1T, D2T, D1T,
-                       part);
+    hipLaunchKernelGGL(k_mlp_train_fb, dim3(tiles), dim3(256), 0, st, P, Wb, X, cost, idx, n_rows, M, n_in, status,
+                       UT, H1T, D2T, D1T, part);
     hipLaunchKernelGGL(k_mlp_wgrad, dim3((kW / 16) * (kW / 16)), dim3(64), 0, st, D2T, H1T, M, kW, dW2);
     hipLaunchKernelGGL(k_mlp_wgrad, dim3((kW / 16) * (kIn / 16)), dim3(64), 0, st, D1T, UT, M, kIn, dW1);
     if (loss_out) hipLaunchKernelGGL(k_mlp_loss, dim3(1), dim3(1), 0, st, part, tiles, loss_out);

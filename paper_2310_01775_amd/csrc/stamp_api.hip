@@ -35,6 +35,9 @@ struct stamp_ctx {
     // the last instantiated iteration graph and the solve it belongs to
     hipGraphExec_t graph = nullptr;
     std::string graph_key;
+    // the same for the surrogate-phase iteration
+    hipGraphExec_t graph_sur = nullptr;
+    std::string graph_sur_key;
 };
 
 namespace stamp {
@@ -172,7 +175,8 @@ struct SolvePlan {
     int phi_rows = 256;
     size_t clk_off = 0, desc_off = 0, roll_off = 0, dist_off = 0, hist_off = 0, red_off = 0;
     size_t phi_off[kDpClasses] = {};
-    size_t ctr_off = 0, tape_off = 0, seg_off = 0, grad_off = 0, phi_vec_off = 0, cost_off = 0, svgd_off = 0;
+    size_t ctr_off = 0, err_off = 0, tape_off = 0, seg_off = 0, grad_off = 0, phi_vec_off = 0, cost_off = 0,
+           svgd_off = 0;
     size_t total = 0;
     int64_t n_theta = 0, n_part = 0;
     std::string key;  // batch signature (sizes only)
@@ -259,6 +263,7 @@ void build_plan(int n, const stamp_scene* scenes, const int32_t* N, int K, float
     P.red_off = take(P.red_work.size() * sizeof(int4));
     for (int c = 0; c < kDpClasses; ++c) P.phi_off[c] = take(phi_cap[c] * sizeof(int4));
     P.ctr_off = take(256);
+    P.err_off = take((size_t)n * sizeof(float));
     P.tape_off = take((size_t)tp * 4);
     P.seg_off = take((size_t)sg * 4);
     P.grad_off = take((size_t)th * 4);
@@ -279,7 +284,7 @@ size_t plan_bytes(int n, const stamp_scene* scenes, const int32_t* N, int K, flo
 bool same_layout(const SolvePlan& a, const SolvePlan& b) {
     bool ok = a.total == b.total && a.clk_off == b.clk_off && a.desc_off == b.desc_off && a.roll_off == b.roll_off &&
               a.dist_off == b.dist_off && a.hist_off == b.hist_off && a.red_off == b.red_off &&
-              a.ctr_off == b.ctr_off && a.tape_off == b.tape_off && a.seg_off == b.seg_off &&
+              a.ctr_off == b.ctr_off && a.err_off == b.err_off && a.tape_off == b.tape_off && a.seg_off == b.seg_off &&
               a.grad_off == b.grad_off && a.phi_vec_off == b.phi_vec_off && a.cost_off == b.cost_off &&
               a.svgd_off == b.svgd_off;
     for (int c = 0; c < kDpClasses; ++c) ok = ok && a.phi_off[c] == b.phi_off[c];
@@ -340,6 +345,7 @@ void stamp_destroy(stamp_ctx* ctx) {
     if (!ctx) return;
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
     if (ctx->graph) (void)hipGraphExecDestroy(ctx->graph);
+    if (ctx->graph_sur) (void)hipGraphExecDestroy(ctx->graph_sur);
     if (ctx->ev_in) (void)hipEventDestroy(ctx->ev_in);
     if (ctx->ev_out) (void)hipEventDestroy(ctx->ev_out);
     if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
@@ -457,10 +463,15 @@ int32_t stamp_adam_step(stamp_ctx* ctx, int64_t n, float* theta, const float* ph
     return e == hipSuccess ? STAMP_OK : hip_fail(ctx, e, "adam_step");
 }
 
-int32_t stamp_solve(stamp_ctx* ctx, int32_t n_problems, const stamp_scene* scenes, const stamp_cost_w* w,
-                    const int32_t* N, const stamp_solver_cfg* cfg, float* theta, float* adam_m, float* adam_v,
-                    float* cost_out, int32_t* modes_out, float* solve_time_us, void* workspace, size_t ws_bytes,
-                    uint32_t* status, void* stream) {
+}  // extern "C"
+
+// Algorithm 1's loop over a batch of problems; sur (may be null) adds the
+// surrogate phase in front of the true iterations.
+static int32_t solve_impl(stamp_ctx* ctx, int32_t n_problems, const stamp_scene* scenes, const stamp_cost_w* w,
+                          const int32_t* N, const stamp_solver_cfg* cfg, const stamp_surrogate* sur, float* theta,
+                          float* adam_m, float* adam_v, float* cost_out, int32_t* modes_out, float* solve_time_us,
+                          stamp_surrogate_report* rep, void* workspace, size_t ws_bytes, uint32_t* status,
+                          void* stream) {
     if (!ctx) return STAMP_EINVAL;
     if (n_problems < 1 || !scenes || !w || !N || !cfg) return fail(ctx, STAMP_EINVAL, "null problem arrays");
     if (!theta || !cost_out) return fail(ctx, STAMP_EINVAL, "null theta or cost_out");
@@ -637,36 +648,111 @@ int32_t stamp_solve(stamp_ctx* ctx, int32_t n_problems, const stamp_scene* scene
             return r;
         return launch_incr(d_ctr, st);
     };
+    // the surrogate-phase iteration: the network's cost gradient (exact bound
+    // term included) replaces rollout + adjoint, every other stage unchanged
+    const int s_iters = sur ? sur->iters : 0;
+    std::vector<int64_t> enc_off(n_problems, 0);
+    if (sur)
+        for (int p = 1; p < n_problems; ++p) enc_off[p] = enc_off[p - 1] + (sur->n_in - 6 * scenes[p - 1].H);
+    auto sur_infer = [&](int p, float* cost, float* grad, float scale) -> hipError_t {
+        const ProblemDesc& D = P.descs[p];
+        const float* enc = sur->n_in > D.d ? sur->enc + enc_off[p] : nullptr;
+        return launch_mlp_infer(sur->params, (const __bf16*)sur->wbf16, theta + D.theta_off, 1, D.N, sur->n_in, D.d,
+                                enc, scenes[p].H, w[p].bound, w[p].o_max, w[p].d_max, nullptr,
+                                cost ? cost + D.cost_off : nullptr, grad ? grad + D.theta_off : nullptr, scale, st);
+    };
+    auto sur_iteration = [&]() -> hipError_t {
+        hipError_t r;
+        for (int p = 0; p < n_problems; ++p)
+            if ((r = sur_infer(p, nullptr, d_grad, -1.0f)) != hipSuccess) return r;
+        if ((r = launch_svgd_batched(B, d_desc, theta, d_grad, d_phi, d_svgd, status, st)) != hipSuccess) return r;
+        if ((r = launch_update(P.n_theta, theta, d_phi, adam_m, adam_v, cfg->t0, d_ctr, cfg->lr, cfg->beta1,
+                               cfg->beta2, cfg->adam_eps, cfg->use_adam, st)) != hipSuccess)
+            return r;
+        return launch_incr(d_ctr, st);
+    };
     char gkey[512];
     snprintf(gkey, sizeof gkey, "|%p|%p|%p|%p|%p|%d|%d|%.9g|%.9g|%.9g|%.9g|%d|%d|%d|", (void*)ws, (void*)theta,
              (void*)adam_m, (void*)adam_v, (void*)status, cfg->t0, cfg->use_adam, cfg->lr, cfg->beta1, cfg->beta2,
              cfg->adam_eps, tune.roll_block, rgrid, tune.phi_rows);
     const std::string full_key = tkey + gkey;
+    // capture `body` into `graph` unless the cached one was made for `key`
+    auto ensure_graph = [&](hipGraphExec_t& graph, std::string& have_key, const std::string& key,
+                            auto&& body) -> int32_t {
+        if (graph && have_key == key) return STAMP_OK;
+        if (graph) {
+            STAMP_TRY(hipStreamSynchronize(st), "sync");
+            (void)hipGraphExecDestroy(graph);
+            graph = nullptr;
+        }
+        hipGraph_t g = nullptr;
+        STAMP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal), "begin capture");
+        const hipError_t ce = body();
+        const hipError_t ee = hipStreamEndCapture(st, &g);
+        if (ce != hipSuccess) return hip_fail(ctx, ce, "capture iteration");
+        if (ee != hipSuccess) return hip_fail(ctx, ee, "end capture");
+        e = hipGraphInstantiate(&graph, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) {
+            graph = nullptr;
+            return hip_fail(ctx, e, "graph instantiate");
+        }
+        have_key = key;
+        return STAMP_OK;
+    };
     STAMP_TRY(launch_fill_u32((uint32_t*)d_ctr, 0u, 1, st), "counter");
     if (solve_time_us)
         for (int p = 0; p < n_problems; ++p) STAMP_TRY(launch_clock(d_clk + 2 * p, st), "clock");
-    if (cfg->iters > 0) {
-        if (!ctx->graph || ctx->graph_key != full_key) {
-            if (ctx->graph) {
-                STAMP_TRY(hipStreamSynchronize(st), "sync");
-                (void)hipGraphExecDestroy(ctx->graph);
-                ctx->graph = nullptr;
-            }
-            hipGraph_t g = nullptr;
-            STAMP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal), "begin capture");
-            const hipError_t ce = iteration();
-            const hipError_t ee = hipStreamEndCapture(st, &g);
-            if (ce != hipSuccess) return hip_fail(ctx, ce, "capture iteration");
-            if (ee != hipSuccess) return hip_fail(ctx, ee, "end capture");
-            e = hipGraphInstantiate(&ctx->graph, g, nullptr, nullptr, 0);
-            (void)hipGraphDestroy(g);
-            if (e != hipSuccess) {
-                ctx->graph = nullptr;
-                return hip_fail(ctx, e, "graph instantiate");
-            }
-            ctx->graph_key = full_key;
+    // surrogate phase, judged against the rollout at each check
+    int run = 0, checks = 0, fell_back = 0;
+    float last_err = 0.0f;
+    if (s_iters > 0) {
+        // the network's pointers and each problem's bound weights are kernel
+        // arguments of the captured graph, so they are part of its key
+        char skey[160];
+        snprintf(skey, sizeof skey, "sur|%p|%p|%p|%d|", (const void*)sur->params, sur->wbf16, (const void*)sur->enc,
+                 sur->n_in);
+        std::string sk = full_key + skey;
+        for (int p = 0; p < n_problems; ++p) {
+            snprintf(skey, sizeof skey, "%.9g/%.9g/%.9g;", w[p].bound, w[p].o_max, w[p].d_max);
+            sk += skey;
         }
-        for (int it = 0; it < cfg->iters; ++it) STAMP_TRY(hipGraphLaunch(ctx->graph, st), "graph launch");
+        int32_t r = ensure_graph(ctx->graph_sur, ctx->graph_sur_key, sk, sur_iteration);
+        if (r) return r;
+        float* d_err = (float*)(ws + P.err_off);
+        float* c_true = (float*)(ws + P.cost_off);
+        std::vector<float> h_err(n_problems);
+        while (run < s_iters) {
+            const int chunk = sur->check_every > 0 ? std::min(sur->check_every, s_iters - run) : s_iters - run;
+            for (int it = 0; it < chunk; ++it) STAMP_TRY(hipGraphLaunch(ctx->graph_sur, st), "graph launch");
+            run += chunk;
+            STAMP_TRY(launch_rollout_fwd_batched(d_desc, d_roll, ntiles, tune.roll_block, rgrid, theta, c_true,
+                                                 nullptr, status, st),
+                      "check rollout");
+            for (int p = 0; p < n_problems; ++p) STAMP_TRY(sur_infer(p, d_phi, nullptr, 1.0f), "check network");
+            STAMP_TRY(launch_log_err(d_desc, n_problems, c_true, d_phi, d_err, st), "check error");
+            STAMP_TRY(hipMemcpyAsync(h_err.data(), d_err, n_problems * sizeof(float), hipMemcpyDeviceToHost, st),
+                      "check copy");
+            STAMP_TRY(hipStreamSynchronize(st), "check sync");
+            ++checks;
+            last_err = 0.0f;
+            for (float v : h_err) last_err = (v > last_err || !(v == v)) ? v : last_err;
+            if (sur->max_log_err > 0.0f && !(last_err <= sur->max_log_err) && run < s_iters) {
+                fell_back = 1;
+                break;
+            }
+        }
+    }
+    if (rep) {
+        rep->iters_run = run;
+        rep->fell_back = fell_back;
+        rep->checks = checks;
+        rep->log_err = last_err;
+    }
+    if (cfg->iters - run > 0) {
+        int32_t r = ensure_graph(ctx->graph, ctx->graph_key, full_key, iteration);
+        if (r) return r;
+        for (int it = run; it < cfg->iters; ++it) STAMP_TRY(hipGraphLaunch(ctx->graph, st), "graph launch");
     }
     // final true cost and discrete plan of every particle
     STAMP_TRY(launch_rollout_fwd_batched(d_desc, d_roll, ntiles, tune.roll_block, rgrid, theta, cost_out, nullptr,
@@ -692,6 +778,38 @@ int32_t stamp_solve(stamp_ctx* ctx, int32_t n_problems, const stamp_scene* scene
     return STAMP_OK;
 }
 
+extern "C" {
+
+int32_t stamp_solve(stamp_ctx* ctx, int32_t n_problems, const stamp_scene* scenes, const stamp_cost_w* w,
+                    const int32_t* N, const stamp_solver_cfg* cfg, float* theta, float* adam_m, float* adam_v,
+                    float* cost_out, int32_t* modes_out, float* solve_time_us, void* workspace, size_t ws_bytes,
+                    uint32_t* status, void* stream) {
+    return solve_impl(ctx, n_problems, scenes, w, N, cfg, nullptr, theta, adam_m, adam_v, cost_out, modes_out,
+                      solve_time_us, nullptr, workspace, ws_bytes, status, stream);
+}
+
+int32_t stamp_solve_surrogate(stamp_ctx* ctx, int32_t n_problems, const stamp_scene* scenes, const stamp_cost_w* w,
+                              const int32_t* N, const stamp_solver_cfg* cfg, const stamp_surrogate* sur, float* theta,
+                              float* adam_m, float* adam_v, float* cost_out, int32_t* modes_out, float* solve_time_us,
+                              stamp_surrogate_report* report, void* workspace, size_t ws_bytes, uint32_t* status,
+                              void* stream) {
+    if (!ctx) return STAMP_EINVAL;
+    if (!sur || !cfg || !scenes || n_problems < 1) return fail(ctx, STAMP_EINVAL, "null surrogate, cfg or scenes");
+    if (sur->iters < 0 || sur->iters > cfg->iters)
+        return fail(ctx, STAMP_EINVAL, "surrogate iters=%d not in [0, iters=%d]", sur->iters, cfg->iters);
+    if (sur->n_in < 1 || sur->n_in > kMlpIn) return fail(ctx, STAMP_EINVAL, "n_in=%d not in [1,%d]", sur->n_in, kMlpIn);
+    if (!sur->params || !sur->wbf16) return fail(ctx, STAMP_EINVAL, "null network parameters");
+    if (sur->check_every < 0 || !isfinite(sur->max_log_err)) return fail(ctx, STAMP_EINVAL, "bad check settings");
+    for (int p = 0; p < n_problems; ++p) {
+        const int d = 6 * scenes[p].H;
+        if (scenes[p].H < 1 || d > sur->n_in)
+            return fail(ctx, STAMP_EINVAL, "problem %d: d=%d exceeds the network's n_in=%d", p, d, sur->n_in);
+        if (d < sur->n_in && !sur->enc) return fail(ctx, STAMP_EINVAL, "null scene encodings");
+    }
+    return solve_impl(ctx, n_problems, scenes, w, N, cfg, sur, theta, adam_m, adam_v, cost_out, modes_out,
+                      solve_time_us, report, workspace, ws_bytes, status, stream);
+}
+
 // ---- learned cost surrogate --------------------------------------------------
 
 int32_t stamp_mlp_prepare(stamp_ctx* ctx, const float* params, void* wbf16, void* stream) {
@@ -701,9 +819,40 @@ int32_t stamp_mlp_prepare(stamp_ctx* ctx, const float* params, void* wbf16, void
     return e == hipSuccess ? STAMP_OK : hip_fail(ctx, e, "mlp_prepare");
 }
 
+int32_t stamp_mlp_standardize(stamp_ctx* ctx, int32_t M, int32_t n_in, const float* x, const float* cost,
+                              float* params, void* stream) {
+    if (!ctx) return STAMP_EINVAL;
+    if (!x || !params) return fail(ctx, STAMP_EINVAL, "null x or params");
+    if (M < 1) return fail(ctx, STAMP_EINVAL, "M=%d < 1", M);
+    if (n_in < 1 || n_in > kMlpIn) return fail(ctx, STAMP_EINVAL, "n_in=%d not in [1,%d]", n_in, kMlpIn);
+    hipError_t e = launch_mlp_standardize(x, cost, M, n_in, params, (hipStream_t)stream);
+    return e == hipSuccess ? STAMP_OK : hip_fail(ctx, e, "mlp_standardize");
+}
+
+int32_t stamp_mlp_label(stamp_ctx* ctx, const stamp_scene* scene, const stamp_cost_w* w, int32_t N,
+                        const float* theta, int32_t n_in, const float* enc, float* x, float* cost, uint32_t* status,
+                        void* stream) {
+    if (!ctx) return STAMP_EINVAL;
+    if (!theta || !x || !cost) return fail(ctx, STAMP_EINVAL, "null theta, x or cost");
+    if (N < 1) return fail(ctx, STAMP_EINVAL, "N=%d < 1", N);
+    if (!w || !scene) return fail(ctx, STAMP_EINVAL, "null scene or cost weights");
+    stamp_cost_w w_roll = *w;
+    w_roll.bound = 0.0f;  // the network learns the rollout part only
+    SimConst c;
+    int r = derive(ctx, scene, &w_roll, &c);
+    if (r) return r;
+    const int d = 6 * scene->H;
+    if (n_in < d || n_in > kMlpIn) return fail(ctx, STAMP_EINVAL, "n_in=%d not in [d=%d, %d]", n_in, d, kMlpIn);
+    if (n_in > d && !enc) return fail(ctx, STAMP_EINVAL, "null scene encoding");
+    const TapeGeom g = tape_geom(scene, N, 0);
+    hipError_t e = launch_rollout_fwd(c, N, theta, cost, nullptr, g, status, (hipStream_t)stream);
+    if (e == hipSuccess) e = launch_mlp_pack_rows(theta, N, d, enc, n_in, x, (hipStream_t)stream);
+    return e == hipSuccess ? STAMP_OK : hip_fail(ctx, e, "mlp_label");
+}
+
 int32_t stamp_mlp_forward(stamp_ctx* ctx, int32_t M, int32_t n_in, int32_t d, const float* params, const void* wbf16,
-                          const float* x, int32_t x_layout, const float* enc, float* y, float* cost, float* grad,
-                          float grad_scale, void* stream) {
+                          const float* x, int32_t x_layout, const float* enc, const stamp_cost_w* w, float* y,
+                          float* cost, float* grad, float grad_scale, void* stream) {
     if (!ctx) return STAMP_EINVAL;
     if (!params || !wbf16 || !x) return fail(ctx, STAMP_EINVAL, "null params, wbf16 or x");
     if (M < 1) return fail(ctx, STAMP_EINVAL, "M=%d < 1", M);
@@ -711,8 +860,12 @@ int32_t stamp_mlp_forward(stamp_ctx* ctx, int32_t M, int32_t n_in, int32_t d, co
     if (d < 1 || d > n_in) return fail(ctx, STAMP_EINVAL, "d=%d not in [1,n_in]", d);
     if (x_layout != 0 && x_layout != 1) return fail(ctx, STAMP_EINVAL, "x_layout=%d not 0 or 1", x_layout);
     if (x_layout == 1 && d < n_in && !enc) return fail(ctx, STAMP_EINVAL, "null scene encoding");
+    if (w && d % 6) return fail(ctx, STAMP_EINVAL, "bound term needs plan inputs (d=%d not a multiple of 6)", d);
+    if (w && (!isfinite(w->bound) || !isfinite(w->o_max) || !isfinite(w->d_max)))
+        return fail(ctx, STAMP_EINVAL, "non-finite bound weights");
     if (!isfinite(grad_scale)) return fail(ctx, STAMP_EINVAL, "non-finite grad_scale");
-    hipError_t e = launch_mlp_infer(params, (const __bf16*)wbf16, x, x_layout, M, n_in, d, enc, y, cost, grad,
+    hipError_t e = launch_mlp_infer(params, (const __bf16*)wbf16, x, x_layout, M, n_in, d, enc, w ? d / 6 : 0,
+                                    w ? w->bound : 0.0f, w ? w->o_max : 0.0f, w ? w->d_max : 0.0f, y, cost, grad,
                                     grad_scale, (hipStream_t)stream);
     return e == hipSuccess ? STAMP_OK : hip_fail(ctx, e, "mlp_forward");
 }
@@ -722,22 +875,25 @@ size_t stamp_mlp_train_workspace_bytes(int32_t M) {
     return mlp_train_layout(M).total;
 }
 
-int32_t stamp_mlp_train_step(stamp_ctx* ctx, int32_t M, int32_t n_in, const float* x, const float* target,
-                             float* params, void* wbf16, float* adam_m, float* adam_v, int32_t t, float lr,
-                             float beta1, float beta2, float eps, float* loss, void* workspace, size_t ws_bytes,
-                             void* stream) {
+int32_t stamp_mlp_train_step(stamp_ctx* ctx, int32_t M, int32_t n_in, const float* x, const float* cost,
+                             const int32_t* idx, int32_t n_rows, float* params, void* wbf16, float* adam_m,
+                             float* adam_v, int32_t t, float lr, float beta1, float beta2, float eps, float* loss,
+                             uint32_t* status, void* workspace, size_t ws_bytes, void* stream) {
     if (!ctx) return STAMP_EINVAL;
-    if (!x || !target || !params || !wbf16 || !adam_m || !adam_v) return fail(ctx, STAMP_EINVAL, "null pointer");
+    if (!x || !cost || !params || !wbf16 || !adam_m || !adam_v) return fail(ctx, STAMP_EINVAL, "null pointer");
     if (M < 64 || M % 64) return fail(ctx, STAMP_EINVAL, "M=%d must be a positive multiple of 64", M);
     if (n_in < 1 || n_in > kMlpIn) return fail(ctx, STAMP_EINVAL, "n_in=%d not in [1,%d]", n_in, kMlpIn);
+    if (n_rows < 1 || (!idx && n_rows < M))
+        return fail(ctx, STAMP_EINVAL, "n_rows=%d too small for a minibatch of %d", n_rows, M);
     if (t < 1) return fail(ctx, STAMP_EINVAL, "Adam step t=%d < 1", t);
     if (!isfinite(lr) || !(beta1 >= 0 && beta1 < 1 && beta2 >= 0 && beta2 < 1 && eps >= 0))
         return fail(ctx, STAMP_EINVAL, "bad Adam hyper-parameters");
     const MlpTrainLayout L = mlp_train_layout(M);
     if (!workspace || ws_bytes < L.total)
         return fail(ctx, STAMP_ENOSPACE, "mlp train workspace %zu < %zu bytes", ws_bytes, L.total);
-    hipError_t e = launch_mlp_train_step(params, (__bf16*)wbf16, adam_m, adam_v, t, lr, beta1, beta2, eps, x, target,
-                                         M, n_in, loss, (char*)workspace, L, (hipStream_t)stream);
+    hipError_t e = launch_mlp_train_step(params, (__bf16*)wbf16, adam_m, adam_v, t, lr, beta1, beta2, eps, x, cost,
+                                         idx, n_rows, M, n_in, loss, status, (char*)workspace, L,
+                                         (hipStream_t)stream);
     return e == hipSuccess ? STAMP_OK : hip_fail(ctx, e, "mlp_train_step");
 }
 

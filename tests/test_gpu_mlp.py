@@ -128,16 +128,16 @@ def test_training_gradient_matches_oracle(ctx):
     x, _ = _inputs(M)
     p = _params(2, x=x)
     rng = np.random.default_rng(7)
-    t_np = W.f32(rng.normal(1.0, 1.0, M))
+    c_np = W.f32(np.expm1(rng.normal(1.0, 1.0, M)))  # targets log(1 + c) ~ N(1, 1)
     P = _dev(S.pack_mlp(p))
     Wb = ctx.mlp_weights()
     ctx.mlp_prepare(P, Wb)
     m = torch.zeros(S.MLP_PARAMS, device="cuda")
     v = torch.zeros(S.MLP_PARAMS, device="cuda")
     loss = torch.zeros(1, device="cuda")
-    ctx.mlp_train_step(P, Wb, m, v, _dev(x), _dev(t_np), 1, lr=1e-3, loss=loss)
+    ctx.mlp_train_step(P, Wb, m, v, _dev(x), _dev(c_np), 1, lr=1e-3, loss=loss)
     torch.cuda.synchronize()
-    L_ref, g_ref = mlp.loss_and_grads(p, x, t_np)
+    L_ref, g_ref = mlp.training_loss_and_grads(p, x, c_np)
     g_gpu = S.unpack_mlp(m.cpu().double().numpy() / 0.1, N_IN)
     print("loss", float(loss.item()), L_ref, flush=True)
     assert abs(float(loss.item()) - L_ref) < 1e-2 * L_ref
@@ -166,14 +166,16 @@ def test_training_fits_and_oracle_agrees(ctx):
     x, _ = _inputs(M)
     p = _params(3, x=x)
     u = (x - p["mu"]) * p["inv_sigma"]
-    t_np = W.f32(np.sin(u[:, 0]) + 0.5 * u[:, 4] * u[:, 5] - 0.3 * u[:, D_PLAN + 1])
+    t_np = np.sin(u[:, 0]) + 0.5 * u[:, 4] * u[:, 5] - 0.3 * u[:, D_PLAN + 1]
+    c_np = W.f32(np.expm1(t_np))
+    t_np = np.log1p(c_np)
     P = _dev(S.pack_mlp(p))
     Wb = ctx.mlp_weights()
     ctx.mlp_prepare(P, Wb)
     m = torch.zeros(S.MLP_PARAMS, device="cuda")
     v = torch.zeros(S.MLP_PARAMS, device="cuda")
     loss = torch.zeros(1, device="cuda")
-    X, T = _dev(x), _dev(t_np)
+    X, T = _dev(x), _dev(c_np)
     ws = torch.empty(ctx.mlp_train_workspace_bytes(M), dtype=torch.uint8, device="cuda")
     losses = []
     for t in range(1, 301):
@@ -209,3 +211,5 @@ def test_argument_errors(ctx):
     with pytest.raises(S.StampError):  # workspace too small
         ctx.mlp_train_step(P, Wb, m, m.clone(), x[:64], torch.zeros(64, device="cuda"), 1,
                            workspace=torch.empty(16, dtype=torch.uint8, device="cuda"))
+    with pytest.raises(S.StampError):  # a minibatch larger than the dataset without indices
+        ctx.mlp_train_step(P, Wb, m, m.clone(), x[:64], torch.zeros(64, device="cuda"), 1, M=128)

@@ -103,3 +103,51 @@ def test_adam_matches_torch():
         opt.step()
     for tt, k in zip(tp, names):
         assert np.allclose(tt.detach().numpy(), p[k], rtol=1e-12, atol=1e-13)
+
+
+def test_surrogate_cost_adds_the_exact_bound_term():
+    """With a network that outputs a constant log(1 + c0), C_hat is c0 plus
+    the bound term, whose value and gradient are checked by hand: o = 0.07
+    and D = -0.01 on push 0, D = 0.35 on push 1 (o_max 0.05, d_max 0.3)."""
+    H, n_enc = 2, 3
+    d = 6 * H
+    p = W.mlp_init(d + n_enc, 8, 0)
+    for k in ("W1", "W2", "w3"):
+        p[k] = np.zeros_like(p[k])
+    c0 = 2.5
+    p["b3"] = np.array([math.log1p(c0)])
+    w = W.cost_weights()
+    th = np.zeros((2, d))
+    th[0, 4], th[0, 5] = 0.07, -0.01
+    th[0, 11] = 0.35
+    th[1, 4], th[1, 5], th[1, 10], th[1, 11] = 0.01, 0.1, -0.03, 0.2  # inside every bound
+    C, g = mlp.surrogate_cost_and_grad(p, th, np.ones(n_enc), w)
+    b = w["bound"]
+    L0 = (0.07 - w["o_max"]) ** 2 + 0.01 ** 2 + (0.35 - w["d_max"]) ** 2
+    assert abs(C[0] - (c0 + b * L0)) < 1e-12 * (1 + b * L0)
+    assert abs(C[1] - c0) < 1e-12
+    want = np.zeros(d)
+    want[4] = b * 2 * (0.07 - w["o_max"])
+    want[5] = b * (-2) * 0.01
+    want[11] = b * 2 * (0.35 - w["d_max"])
+    assert np.allclose(g[0], want, rtol=1e-12, atol=1e-12)
+    assert np.allclose(g[1], 0.0, atol=1e-15)
+
+
+def test_surrogate_cost_without_bound_is_the_network_cost():
+    p = _params(n_in=15, width=8)
+    th = np.random.default_rng(5).normal(size=(4, 12)) * 0.02
+    enc = np.random.default_rng(6).normal(size=3)
+    w = dict(W.cost_weights(), bound=0.0)
+    C, g = mlp.surrogate_cost_and_grad(p, th, enc, w)
+    x = np.concatenate([th, np.repeat(enc[None], 4, 0)], 1)
+    C2, g2 = mlp.cost_and_grad(p, x, 12)
+    assert np.allclose(C, C2, rtol=1e-13) and np.allclose(g, g2, rtol=1e-12, atol=1e-14)
+
+
+def test_standardization_is_mean_and_population_std():
+    x = np.random.default_rng(8).normal(size=(500, 4)) * [1.0, 3.0, 1e-5, 0.0] + [0.0, 2.0, 1.0, 7.0]
+    mu, isg = mlp.standardization(x)
+    assert np.allclose(mu, [x[:, 0].mean(), x[:, 1].mean(), 1.0 + x[:, 2].mean() - 1.0, 7.0], atol=1e-12)
+    assert abs(1 / isg[1] - np.sqrt(((x[:, 1] - x[:, 1].mean()) ** 2).mean())) < 1e-12
+    assert isg[2] == 1e3 and isg[3] == 1e3  # floor of the standard deviation

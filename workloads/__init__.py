@@ -230,3 +230,27 @@ def mlp_init(n_in: int, width: int = 256, seed: int = 0) -> dict:
                 W1=u((width, n_in), n_in), b1=np.zeros(width),
                 W2=u((width, width), width), b2=np.zeros(width),
                 w3=f32(u((width,), width) * 0.1), b3=np.zeros(1))
+
+
+def surrogate_training_plans(p: int, per: int, H: int = 5, cfg_id: int = 5) -> np.ndarray:
+    """Random plans of training scene p [per][6H]: the first half from the
+    particle sampler, the second half wider (logits ~ N(0, 1.3^2), offsets
+    U[-0.05, 0.05] m, depths U[0, 0.3] m: the whole in-bounds box), so the
+    network also sees plans the solver moves to.  Rounded to FP32."""
+    rng = rng_for(cfg_id, 1000 + p, STREAM_SURROGATE)
+    th = make_particles(cfg_id, 1000 + p, per, H)
+    half = per // 2
+    for k in range(H):
+        th[half:, 6 * k:6 * k + 4] = rng.normal(0.0, 1.3, (per - half, 4))
+        th[half:, 6 * k + 4] = rng.uniform(-0.05, 0.05, per - half)
+        th[half:, 6 * k + 5] = rng.uniform(0.0, 0.3, per - half)
+    return f32(th)
+
+
+# Training recipe of the surrogate for the N=16384 workload: 2^20 labelled
+# rollouts = random plans on 128 scenes x 2048, then 2 on-policy rounds of the
+# surrogate solver on 64 scenes x 2048 particles labelled at iterations 80,
+# 160 and 240 (3 x 131072 rows per round); Adam steps on minibatches of 8192
+# after the random phase and after each round.
+SURROGATE_RECIPE = dict(random_scenes=128, per=2048, rounds=2, round_scenes=64, round_iters=240,
+                        snapshot_every=80, steps=4000, round_steps=2000, batch=8192, lr=1e-3, seed=0)
