@@ -186,6 +186,21 @@ int32_t stamp_svgd_step(stamp_ctx* ctx, int32_t N, int32_t d, const float* theta
                         const float* grad_logp, float bandwidth, float* phi, float* h_out,
                         void* workspace, size_t ws_bytes, void* stream);
 
+/* The SVGD direction of stamp_svgd_step in reduced precision on the BF16
+ * matrix cores, for iterations whose gradients are approximate anyway (the
+ * surrogate phase).  Differences from stamp_svgd_step:
+ *   - the median heuristic uses a fixed sample of 8192 particle pairs (all
+ *     pairs when N(N-1)/2 <= 8192, then it is exact), distances in FP32;
+ *   - the particles are centred on their mean and rounded to BF16; distances
+ *     come from the Gram form |x~_i|^2 + |x~_j|^2 - 2 x~_i.x~_j (MFMA, FP32
+ *     accumulation), clamped at 0;
+ *   - K_ij is rounded to BF16 and K [g | x~ | 1] is accumulated on MFMA in FP32
+ *     with g rounded to BF16.
+ * Same arguments, layouts and workspace (stamp_svgd_workspace_bytes). */
+int32_t stamp_svgd_step_bf16(stamp_ctx* ctx, int32_t N, int32_t d, const float* theta,
+                             const float* grad_logp, float bandwidth, float* phi, float* h_out,
+                             void* workspace, size_t ws_bytes, void* stream);
+
 /* Update of Algorithm 1 on n = d*N floats, in place:
  *   use_adam = 1: Adam minimising -phi at step t (>= 1), bias-corrected;
  *   use_adam = 0: theta += lr * phi (m, v untouched, may be NULL). */
@@ -308,6 +323,9 @@ typedef struct stamp_surrogate {
                              surrogate iterations; the phase always ends with one check */
     float max_log_err;    /* > 0: leave the surrogate phase early when a check finds the
                              mean |log(1+C_hat) - log(1+C)| of any problem above it */
+    int32_t phi_bf16;     /* 1: the surrogate iterations take the SVGD direction of
+                             stamp_svgd_step_bf16; 0: that of stamp_svgd_step */
+    int32_t reserved;
     const float* params;  /* device, STAMP_MLP_PARAMS floats */
     const void* wbf16;    /* device, STAMP_MLP_BF16_WEIGHTS bf16 (stamp_mlp_prepare) */
     const float* enc;     /* device, the problems' scene encodings one after another */

@@ -51,7 +51,8 @@ class SolverCfg(C.Structure):
 
 class Surrogate(C.Structure):
     _fields_ = [("iters", C.c_int32), ("n_in", C.c_int32), ("check_every", C.c_int32),
-                ("max_log_err", C.c_float), ("params", C.c_void_p), ("wbf16", C.c_void_p), ("enc", C.c_void_p)]
+                ("max_log_err", C.c_float), ("phi_bf16", C.c_int32), ("reserved", C.c_int32),
+                ("params", C.c_void_p), ("wbf16", C.c_void_p), ("enc", C.c_void_p)]
 
 
 class SurrogateReport(C.Structure):
@@ -76,6 +77,7 @@ _sig = {
     "stamp_rollout_adj": (_i32, [_vp, _P(Scene), _P(CostW), _i32, _vp, _vp, _i32, _vp, _vp, _vp, _sz,
                                  _vp, _vp]),
     "stamp_svgd_step": (_i32, [_vp, _i32, _i32, _vp, _vp, _f32, _vp, _vp, _vp, _sz, _vp]),
+    "stamp_svgd_step_bf16": (_i32, [_vp, _i32, _i32, _vp, _vp, _f32, _vp, _vp, _vp, _sz, _vp]),
     "stamp_adam_step": (_i32, [_vp, _i64, _vp, _vp, _vp, _vp, _i32, _f32, _f32, _f32, _f32, _i32, _vp]),
     "stamp_solve": (_i32, [_vp, _i32, _P(Scene), _P(CostW), _P(_i32), _P(SolverCfg), _vp, _vp, _vp, _vp,
                            _vp, _vp, _vp, _sz, _vp, _vp]),
@@ -298,6 +300,18 @@ class Context:
                                          _stream(stream)))
         return phi
 
+    def svgd_step_bf16(self, theta: torch.Tensor, grad_logp: torch.Tensor, bandwidth: float = 0.0, phi=None,
+                       h_out=None, workspace=None, stream=None):
+        d, N = theta.shape
+        if phi is None:
+            phi = torch.empty_like(theta)
+        if workspace is None:
+            workspace = self._bytes(self.svgd_workspace_bytes(N, d))
+        self._check(_lib.stamp_svgd_step_bf16(self._h, N, d, _ptr(theta), _ptr(grad_logp), float(bandwidth),
+                                              _ptr(phi), _ptr(h_out), _ptr(workspace), workspace.numel(),
+                                              _stream(stream)))
+        return phi
+
     def adam_step(self, theta, phi, m, v, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, use_adam=True,
                   stream=None):
         self._check(_lib.stamp_adam_step(self._h, theta.numel(), _ptr(theta), _ptr(phi), _ptr(m), _ptr(v),
@@ -419,7 +433,7 @@ class Context:
 
     def solve_surrogate(self, scenes, ws_, Ns, cfg: SolverCfg, sur_iters: int, params, wbf16, n_in: int, enc,
                         theta, adam_m=None, adam_v=None, check_every: int = 0, max_log_err: float = 0.0,
-                        cost_out=None, modes_out=None, solve_time_us=None, workspace=None, status=None,
+                        phi_bf16: bool = False, cost_out=None, modes_out=None, solve_time_us=None, workspace=None, status=None,
                         stream=None):
         """stamp_solve_surrogate: returns (cost_out, report)."""
         self._mlp_buffers(params, wbf16)
@@ -434,8 +448,8 @@ class Context:
         need_enc = sum(max(0, n_in - 6 * sc.H) for sc in scenes)
         if need_enc and (enc is None or enc.numel() < need_enc):
             raise ValueError("enc needs %d floats" % need_enc)
-        sur = Surrogate(int(sur_iters), int(n_in), int(check_every), float(max_log_err), params.data_ptr(),
-                        wbf16.data_ptr(), enc.data_ptr() if enc is not None else None)
+        sur = Surrogate(int(sur_iters), int(n_in), int(check_every), float(max_log_err), int(bool(phi_bf16)), 0,
+                        params.data_ptr(), wbf16.data_ptr(), enc.data_ptr() if enc is not None else None)
         rep = SurrogateReport()
         self._check(_lib.stamp_solve_surrogate(self._h, n, arr, warr, ns, C.byref(cfg), C.byref(sur), _ptr(theta),
                                                _ptr(adam_m), _ptr(adam_v), _ptr(cost_out), _ptr(modes_out),

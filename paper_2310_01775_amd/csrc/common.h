@@ -74,8 +74,21 @@ struct SvgdLayout {
     size_t part_off, part_floats;   // phi partial sums [splits][d][N]
     int splits;                     // column chunks of the phi contraction
     int tiles;                      // 64-row tiles
+    // BF16 matrix-core form (sampled median, centred Gram distances)
+    int npad;                       // N rounded up to the 256-row block
+    int kd, vc;                     // padded dimension (32 or 64) and V columns (2 kd)
+    int splits16, chunk16;          // column splits of its contraction and their width
+    size_t smp_off;                 // kMedSample floats: the sampled distances
+    size_t ctr_off;                 // 64 floats: particle mean
+    size_t nrm_off;                 // npad floats: |x~_i|^2
+    size_t xb_off;                  // npad x kd bf16: centred particles, row-major
+    size_t vt_off;                  // vc x npad bf16: V = [g | x~ | 1 | 0], chunked
+    size_t p16_off;                 // splits16 x vc x npad floats: partial sums
     size_t total;
 };
+
+constexpr int kMedSample = 8192;  // distances drawn for the sampled median
+constexpr int kRows16 = 256;      // rows per workgroup of the BF16 contraction
 
 // One problem of a batched solve, resident in device memory.
 struct ProblemDesc {
@@ -103,6 +116,14 @@ struct BatchPlan {
     const int4* hist_work;  int n_hist;   // (p, first uint4, end uint4, -)
     const int4* phi_work[kDpClasses];     // (p, row block, split, -) per class
     int n_phi[kDpClasses];
+    // BF16 matrix-core form: (problem, coordinate), (problem, 256-row chunk),
+    // and (problem, row block, split) per padded dimension 32 / 64
+    const int4* ctr_work;
+    int n_ctr;
+    const int4* row16_work;
+    int n_row16;
+    const int4* phi16_work[2];
+    int n_phi16[2];
     int phi_rows;                         // rows per contraction workgroup
     const int4* red_work;   int n_red;    // (p, first elem, end elem, -)
 };

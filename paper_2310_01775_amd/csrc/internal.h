@@ -34,6 +34,12 @@ hipError_t launch_svgd(int N, int d, const float* theta, const float* grad_logp,
 hipError_t launch_svgd_batched(const BatchPlan& P, const ProblemDesc* descs, const float* theta, const float* grad,
                                float* phi, char* ws, uint32_t* status, hipStream_t st);
 
+// The same step on the BF16 matrix cores with a sampled median (phi16.hip).
+hipError_t launch_svgd16(int N, int d, const float* theta, const float* grad, float bandwidth, float* phi,
+                         float* h_out, void* ws, const SvgdLayout& L, uint32_t* status, hipStream_t st);
+hipError_t launch_svgd16_batched(const BatchPlan& P, const ProblemDesc* descs, const float* theta, const float* grad,
+                                 float* phi, char* ws, uint32_t* status, hipStream_t st);
+
 // Adam (use_adam=1) or plain step, n elements.  t_dev: if non-null, the step
 // count is read as t0 + *t_dev + 1 on the device (graph replay); else t0 is t.
 hipError_t launch_update(int64_t n, float* theta, const float* phi, float* m, float* v, int t0,

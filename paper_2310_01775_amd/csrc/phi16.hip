@@ -1,0 +1,480 @@
+// SVGD step on the BF16 matrix cores (the direction of Eq. (1) in reduced
+// precision, for iterations whose gradients are approximate anyway).
+//
+//   bandwidth: h = max(m2 / ln N, 1e-12) with m2 the lower median of the
+//     squared distances of a fixed sample of kMedSample particle pairs (all
+//     N(N-1)/2 pairs when there are at most that many: then m2 is exact);
+//   x~_i = bf16(theta_i - mean theta)   (centring shrinks the Gram cancellation)
+//   D_ij = |x~_i|^2 + |x~_j|^2 - 2 x~_i . x~_j   (Gram on MFMA, FP32 accumulate)
+//   K_ij = exp(-max(D_ij, 0) / h)
+//   [A_G | A_X | A_1]_i = sum_j bf16(K_ij) [g_j | x~_j | 1]   (MFMA, FP32 accumulate)
+//   phi_i = (A_G + (2/h)(x~_i A_1 - A_X)) / N
+// which is Eq. (1) with theta_i - theta_j = x~_i - x~_j.
+//
+// Contraction tiling: a workgroup owns 256 rows (4 waves x 4 row tiles of 16)
+// and one column split; per 32 columns a wave issues, per row tile, two Gram
+// MFMAs (16x16x32) giving S^T for 2 x 16 columns, turns them into K in
+// registers and feeds K as the A operand of the K.V MFMAs.  The S^T output
+// layout (lane holds columns j = 4(l/16)+t of row l%16) is exactly an A
+// operand whose k index is permuted; V is stored chunk by chunk in that same
+// permuted order, so no data moves between the two products and every lane
+// reads its 8 V values with one 16-byte load.
+#include <math.h>
+
+#include "common.h"
+#include "internal.h"
+
+namespace stamp {
+
+namespace {
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f4;
+
+__device__ __forceinline__ uint32_t mix32(uint32_t x) {  // MurmurHash3 finaliser
+    x ^= x >> 16;
+    x *= 0x85ebca6bu;
+    x ^= x >> 13;
+    x *= 0xc2b2ae35u;
+    x ^= x >> 16;
+    return x;
+}
+
+struct View16 {  // one problem's BF16-form workspace
+    float* smp;
+    float* ctr;
+    float* nrm;
+    __bf16* xb;
+    __bf16* vt;  // V by 32-particle chunk: [npad / 32][vc][32], particles in MFMA k order
+    float* p16;
+    SelState* sel;
+};
+
+__device__ __forceinline__ View16 view16(const SvgdLayout& L, char* base) {
+    View16 v;
+    v.smp = reinterpret_cast<float*>(base + L.smp_off);
+    v.ctr = reinterpret_cast<float*>(base + L.ctr_off);
+    v.nrm = reinterpret_cast<float*>(base + L.nrm_off);
+    v.xb = reinterpret_cast<__bf16*>(base + L.xb_off);
+    v.vt = reinterpret_cast<__bf16*>(base + L.vt_off);
+    v.p16 = reinterpret_cast<float*>(base + L.p16_off);
+    v.sel = reinterpret_cast<SelState*>(base + L.sel_off);
+    return v;
+}
+
+// ---- bandwidth from a sample of pairs ----------------------------------------
+// Sample slot t: pair t of the row-major enumeration of i < j when all pairs
+// fit (N <= 128), else a hashed ordered pair i != j.  Slots beyond the sample
+// hold +inf.  Distances in FP32 by direct differences.
+__device__ __forceinline__ float sample_dist(int N, int d, int t, const float* __restrict__ theta) {
+    const uint64_t P = (uint64_t)N * (uint64_t)(N - 1) / 2;
+    const bool all = P <= (uint64_t)kMedSample;
+    if (N < 2 || (all && (uint64_t)t >= P)) return __int_as_float(0x7f800000);
+    int i, j;
+    if (all) {
+        int r = t;
+        i = 0;
+        while (r >= N - 1 - i) {
+            r -= N - 1 - i;
+            ++i;
+        }
+        j = i + 1 + r;
+    } else {
+        i = (int)(mix32(2u * (uint32_t)t + 1u) % (uint32_t)N);
+        j = (int)(mix32((2u * (uint32_t)t + 2u) ^ 0x9e3779b9u) % (uint32_t)(N - 1));
+        if (j >= i) ++j;
+    }
+    const float* ti = theta + i;
+    const float* tj = theta + j;
+    float acc = 0.0f;
+    int l = 0;
+    for (; l + 8 <= d; l += 8) {  // 16 loads in flight
+        float a[8], b[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            a[u] = ti[(int64_t)(l + u) * N];
+            b[u] = tj[(int64_t)(l + u) * N];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const float df = a[u] - b[u];
+            acc = fmaf(df, df, acc);
+        }
+    }
+    for (; l < d; ++l) {
+        const float df = ti[(int64_t)l * N] - tj[(int64_t)l * N];
+        acc = fmaf(df, df, acc);
+    }
+    return acc;
+}
+
+// Lower median of the sample (one workgroup of 1024 threads, 8 values each):
+// bisection on the FP32 bit pattern (non-negative floats order like unsigned
+// integers) for the smallest x with #{v <= x} >= rank; that x is a sample
+// value, so the result is the exact order statistic of the sample.
+__device__ void med_sort_body(int N, float fixed_h, const float* __restrict__ smp, SelState* sel, float* h_out) {
+    __shared__ uint32_t part[16];
+    const int tid = threadIdx.x;
+    if (N < 2 || fixed_h > 0.0f) {
+        if (tid == 0) {
+            const float h = N < 2 ? 1.0f : fixed_h;
+            sel->h = h;
+            sel->m2 = -1.0f;
+            if (h_out) *h_out = h;
+        }
+        return;
+    }
+    const uint64_t P = (uint64_t)N * (uint64_t)(N - 1) / 2;
+    const uint32_t S = P <= (uint64_t)kMedSample ? (uint32_t)P : (uint32_t)kMedSample;
+    const uint32_t rank = (S + 1) / 2;
+    uint32_t v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v[q] = __float_as_uint(smp[tid + 1024 * q]);
+    uint32_t lo = 0, hi = 0x7f800000u;  // [0, +inf]: +inf pads the sample
+    while (lo < hi) {
+        const uint32_t mid = lo + (hi - lo) / 2;
+        uint32_t c = 0;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) c += v[q] <= mid ? 1u : 0u;
+        for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
+        if ((tid & 63) == 0) part[tid >> 6] = c;
+        __syncthreads();
+        uint32_t tot = 0;
+        for (int w = 0; w < 16; ++w) tot += part[w];
+        __syncthreads();
+        if (tot >= rank) hi = mid;
+        else lo = mid + 1;
+    }
+    if (tid == 0) {
+        const float m2 = __uint_as_float(lo);
+        const float h = fmaxf(m2 / logf((float)N), 1e-12f);
+        sel->m2 = m2;
+        sel->h = h;
+        if (h_out) *h_out = h;
+    }
+}
+
+// ---- particle mean of coordinate l (one workgroup of 256) --------------------
+__device__ void center_body(int N, int l, const float* __restrict__ theta, float* __restrict__ ctr) {
+    __shared__ float red[256];
+    float s = 0.0f;
+    for (int i = threadIdx.x; i < N; i += 256) s += theta[(int64_t)l * N + i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) ctr[l] = red[0] / (float)N;
+}
+
+// Position of particle i inside its 32-particle chunk of V: lane group kq of
+// the K.V MFMA holds k slots 8 kq .. 8 kq + 7 = particles 4 kq .. 4 kq + 3
+// and 16 + 4 kq .. 16 + 4 kq + 3 of the chunk.
+__device__ __forceinline__ int64_t vpos(int i, int c, int vc) {
+    const int q = i >> 5, r = i & 31;
+    const int kq = (r & 15) >> 2, s = (r & 3) + (r >= 16 ? 4 : 0);
+    return ((int64_t)q * vc + c) * 32 + 8 * kq + s;
+}
+
+// ---- operands: x~ rows, their norms, V (one thread per padded row) -------------
+__device__ void pack16_row(int N, int d, int npad, int kd, int vc, int i, const float* __restrict__ theta,
+                           const float* __restrict__ g, const View16& w) {
+    float nrm = 0.0f;
+    for (int l = 0; l < kd; ++l) {
+        float x = 0.0f;
+        if (i < N && l < d) x = theta[(int64_t)l * N + i] - w.ctr[l];
+        const __bf16 xb = (__bf16)x;
+        const float xr = (float)xb;
+        nrm = fmaf(xr, xr, nrm);
+        w.xb[(int64_t)i * kd + l] = xb;
+        if (l < d) {
+            w.vt[vpos(i, d + l, vc)] = xb;
+            w.vt[vpos(i, l, vc)] = (__bf16)(i < N ? g[(int64_t)l * N + i] : 0.0f);
+        }
+    }
+    for (int c = 2 * d; c < vc; ++c) w.vt[vpos(i, c, vc)] = (__bf16)(c == 2 * d && i < N ? 1.0f : 0.0f);
+    w.nrm[i] = nrm;
+}
+
+// ---- contraction: partial sums of K [g | x~ | 1] over columns [j0, j1) --------
+// Operands of one 32-column chunk, as this lane holds them.
+template <int KS, int OT>
+struct Chunk16 {
+    bf16x8 xj[2][KS];  // A of the Gram: rows j = jc + 16 sub + (l % 16)
+    f4 nj[2];          // |x~_j|^2 for j = jc + 16 sub + 4 (l / 16) + t
+    bf16x8 vb[OT];     // B of K.V: V[j][16 o + l % 16], j in the permuted order
+};
+
+template <int KD, int VC>
+__device__ __forceinline__ void load_chunk(Chunk16<KD / 32, VC / 16>& c, const View16& w, int npad, int jc, int col,
+                                           int kq) {
+#pragma unroll
+    for (int sub = 0; sub < 2; ++sub) {
+        const int j = jc + 16 * sub + col;
+#pragma unroll
+        for (int ks = 0; ks < KD / 32; ++ks)
+            c.xj[sub][ks] = *reinterpret_cast<const bf16x8*>(w.xb + (int64_t)j * KD + 32 * ks + 8 * kq);
+        c.nj[sub] = *reinterpret_cast<const f4*>(w.nrm + jc + 16 * sub + 4 * kq);
+    }
+    const __bf16* vch = w.vt + ((int64_t)(jc >> 5) * VC + col) * 32 + 8 * kq;
+#pragma unroll
+    for (int o = 0; o < VC / 16; ++o) c.vb[o] = *reinterpret_cast<const bf16x8*>(vch + 16 * o * 32);
+}
+
+// One 32-column chunk for the wave's 4 row tiles: the 8 Gram MFMAs first,
+// then K for every row tile (VALU), then the K.V MFMAs, so the VALU work of a
+// row tile overlaps the MFMAs still in flight for the next ones.
+template <int KD, int VC>
+__device__ __forceinline__ void chunk16_compute(const Chunk16<KD / 32, VC / 16>& cur, const bf16x8 (&xi)[4][KD / 32],
+                                                const float (&ni)[4], float c, float m2c, f4 (&acc)[4][VC / 16]) {
+    constexpr int KS = KD / 32;
+    constexpr int OT = VC / 16;
+    f4 s[4][2];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        s[r][0] = f4{0.f, 0.f, 0.f, 0.f};
+        s[r][1] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            s[r][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cur.xj[0][ks], xi[r][ks], s[r][0], 0, 0, 0);
+            s[r][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cur.xj[1][ks], xi[r][ks], s[r][1], 0, 0, 0);
+        }
+    }
+    float cn[8];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        cn[t] = c * cur.nj[0][t];
+        cn[4 + t] = c * cur.nj[1][t];
+    }
+    bf16x8 ka[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        float kv[8];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            kv[t] = hw_exp2(fminf(fmaf(m2c, s[r][0][t], ni[r] + cn[t]), 0.0f));
+            kv[4 + t] = hw_exp2(fminf(fmaf(m2c, s[r][1][t], ni[r] + cn[4 + t]), 0.0f));
+        }
+        ka[r] = bf16x8{(__bf16)kv[0], (__bf16)kv[1], (__bf16)kv[2], (__bf16)kv[3],
+                       (__bf16)kv[4], (__bf16)kv[5], (__bf16)kv[6], (__bf16)kv[7]};
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int o = 0; o < OT; ++o) acc[r][o] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ka[r], cur.vb[o], acc[r][o], 0, 0, 0);
+}
+
+template <int KD, int VC>
+__device__ void phi16_body(int npad, int row0, int j0, int j1, int split, const View16& w) {
+    constexpr int KS = KD / 32;   // Gram k-steps
+    constexpr int OT = VC / 16;   // output column tiles
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int col = lane & 15, kq = lane >> 4;
+    const int rbase = row0 + wave * 64;
+    const float c = -1.44269504088896341f / w.sel->h;  // -log2(e) / h
+    const float m2c = -2.0f * c;
+    bf16x8 xi[4][KS];
+    float ni[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int i = rbase + 16 * r + col;
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) xi[r][ks] = *reinterpret_cast<const bf16x8*>(w.xb + (int64_t)i * KD + 32 * ks + 8 * kq);
+        ni[r] = c * w.nrm[i];
+    }
+    f4 acc[4][OT];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int o = 0; o < OT; ++o) acc[r][o] = f4{0.f, 0.f, 0.f, 0.f};
+
+    // the next chunk's operands load while this one computes
+    Chunk16<KS, OT> cur, nxt;
+    load_chunk<KD, VC>(cur, w, npad, j0, col, kq);
+    for (int jc = j0; jc < j1; jc += 32) {
+        if (jc + 32 < j1) load_chunk<KD, VC>(nxt, w, npad, jc + 32, col, kq);
+        chunk16_compute<KD, VC>(cur, xi, ni, c, m2c, acc);
+        cur = nxt;
+    }
+    float* out = w.p16 + (int64_t)split * VC * npad;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int o = 0; o < OT; ++o)
+            *reinterpret_cast<f4*>(out + (int64_t)(16 * o + col) * npad + rbase + 16 * r + 4 * kq) = acc[r][o];
+}
+
+// ---- phi from the split sums (fixed split order) ---------------------------
+// One thread per element (l, i); rows l, d+l and 2d of every split are summed
+// with 16 loads in flight.
+__device__ __forceinline__ float split_sum(const float* __restrict__ p, int64_t sstride, int splits) {
+    float s = 0.0f;
+    for (int q0 = 0; q0 < splits; q0 += 16) {
+        float v[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) v[u] = q0 + u < splits ? p[(q0 + u) * sstride] : 0.0f;
+#pragma unroll
+        for (int u = 0; u < 16; ++u) s += v[u];
+    }
+    return s;
+}
+
+__device__ void reduce16_elem(int N, int d, int npad, int kd, int vc, int splits, int l, int i, float* __restrict__ phi,
+                              const View16& w, uint32_t* status) {
+    const int64_t sstride = (int64_t)vc * npad;
+    const float sg = split_sum(w.p16 + (int64_t)l * npad + i, sstride, splits);
+    const float sx = split_sum(w.p16 + (int64_t)(d + l) * npad + i, sstride, splits);
+    const float s1 = split_sum(w.p16 + (int64_t)(2 * d) * npad + i, sstride, splits);
+    const float xi = (float)w.xb[(int64_t)i * kd + l];
+    const float r = (sg + (2.0f / w.sel->h) * (xi * s1 - sx)) / (float)N;
+    phi[(int64_t)l * N + i] = r;
+    if (status && !isfinite(r)) atomicOr(status, STAMP_STATUS_NONFINITE_PHI);
+}
+
+// ---- single-problem kernels -----------------------------------------------------
+struct One16 {
+    int N, d;
+    SvgdLayout L;
+    float fixed_h;
+};
+
+__global__ __launch_bounds__(256) void k_med_dist(One16 a, const float* theta, char* ws) {
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (a.N < 2 || a.fixed_h > 0.0f) return;
+    view16(a.L, ws).smp[t] = sample_dist(a.N, a.d, t, theta);
+}
+
+__global__ __launch_bounds__(1024) void k_med_sort(One16 a, char* ws, float* h_out) {
+    const View16 w = view16(a.L, ws);
+    med_sort_body(a.N, a.fixed_h, w.smp, w.sel, h_out);
+}
+
+__global__ __launch_bounds__(256) void k_center(One16 a, const float* theta, char* ws) {
+    center_body(a.N, blockIdx.x, theta, view16(a.L, ws).ctr);
+}
+
+__global__ __launch_bounds__(256) void k_pack16(One16 a, const float* theta, const float* g, char* ws) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    pack16_row(a.N, a.d, a.L.npad, a.L.kd, a.L.vc, i, theta, g, view16(a.L, ws));
+}
+
+template <int KD, int VC>
+__global__ __launch_bounds__(256) void k_phi16(One16 a, char* ws) {
+    const int split = blockIdx.y;
+    const int j0 = split * a.L.chunk16, j1 = min(j0 + a.L.chunk16, a.L.npad);
+    phi16_body<KD, VC>(a.L.npad, blockIdx.x * kRows16, j0, j1, split, view16(a.L, ws));
+}
+
+__global__ __launch_bounds__(256) void k_reduce16(One16 a, const float* g, float* phi, char* ws, uint32_t* status) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= (int64_t)a.d * a.N) return;
+    const int l = (int)(e / a.N), i = (int)(e % a.N);
+    if (a.N == 1) {
+        phi[e] = g[e];
+        return;
+    }
+    reduce16_elem(a.N, a.d, a.L.npad, a.L.kd, a.L.vc, a.L.splits16, l, i, phi, view16(a.L, ws), status);
+}
+
+// ---- batched kernels (work-list entries as in svgd.hip) ---------------------------
+__device__ __forceinline__ char* base_of(const ProblemDesc& D, char* ws) { return ws + D.svgd_off; }
+
+// grid (kMedSample / 256, problems)
+__global__ __launch_bounds__(256) void k_med_dist_batched(const ProblemDesc* __restrict__ descs, const float* theta,
+                                                          char* ws) {
+    const ProblemDesc& D = descs[blockIdx.y];
+    if (D.N < 2 || D.fixed_h > 0.0f) return;
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    view16(D.sv, base_of(D, ws)).smp[t] = sample_dist(D.N, D.d, t, theta + D.theta_off);
+}
+
+__global__ __launch_bounds__(1024) void k_med_sort_batched(const ProblemDesc* __restrict__ descs, char* ws) {
+    const ProblemDesc& D = descs[blockIdx.x];
+    const View16 w = view16(D.sv, base_of(D, ws));
+    med_sort_body(D.N, D.fixed_h, w.smp, w.sel, nullptr);
+}
+
+// entry = (problem, coordinate, -, -)
+__global__ __launch_bounds__(256) void k_center_batched(const ProblemDesc* __restrict__ descs,
+                                                        const int4* __restrict__ work, const float* theta, char* ws) {
+    const int4 e = work[blockIdx.x];
+    const ProblemDesc& D = descs[e.x];
+    center_body(D.N, e.y, theta + D.theta_off, view16(D.sv, base_of(D, ws)).ctr);
+}
+
+// entry = (problem, first row of a 256-row chunk, -, -)
+__global__ __launch_bounds__(256) void k_pack16_batched(const ProblemDesc* __restrict__ descs,
+                                                        const int4* __restrict__ work, const float* theta,
+                                                        const float* grad, char* ws) {
+    const int4 e = work[blockIdx.x];
+    const ProblemDesc& D = descs[e.x];
+    if (D.N < 2) return;
+    pack16_row(D.N, D.d, D.sv.npad, D.sv.kd, D.sv.vc, e.y + threadIdx.x, theta + D.theta_off, grad + D.theta_off,
+               view16(D.sv, base_of(D, ws)));
+}
+
+// entry = (problem, row block, split, -)
+template <int KD, int VC>
+__global__ __launch_bounds__(256) void k_phi16_batched(const ProblemDesc* __restrict__ descs,
+                                                       const int4* __restrict__ work, char* ws) {
+    const int4 e = work[blockIdx.x];
+    const ProblemDesc& D = descs[e.x];
+    const int j0 = e.z * D.sv.chunk16, j1 = min(j0 + D.sv.chunk16, D.sv.npad);
+    phi16_body<KD, VC>(D.sv.npad, e.y * kRows16, j0, j1, e.z, view16(D.sv, base_of(D, ws)));
+}
+
+// entry = (problem, first element, end element, -) of the problem's d*N block
+__global__ __launch_bounds__(256) void k_reduce16_batched(const ProblemDesc* __restrict__ descs,
+                                                          const int4* __restrict__ work, const float* grad, float* phi,
+                                                          char* ws, uint32_t* status) {
+    const int4 w = work[blockIdx.x];
+    const ProblemDesc& D = descs[w.x];
+    const int64_t e = w.y + threadIdx.x;
+    if (e >= w.z) return;
+    if (D.N == 1) {
+        phi[D.theta_off + e] = grad[D.theta_off + e];
+        return;
+    }
+    reduce16_elem(D.N, D.d, D.sv.npad, D.sv.kd, D.sv.vc, D.sv.splits16, (int)(e / D.N), (int)(e % D.N),
+                  phi + D.theta_off, view16(D.sv, base_of(D, ws)), status);
+}
+
+}  // namespace
+
+hipError_t launch_svgd16(int N, int d, const float* theta, const float* grad, float bandwidth, float* phi,
+                         float* h_out, void* ws, const SvgdLayout& L, uint32_t* status, hipStream_t st) {
+    One16 a{N, d, L, bandwidth > 0.0f ? bandwidth : 0.0f};
+    char* b = static_cast<char*>(ws);
+    hipLaunchKernelGGL(k_med_dist, dim3(kMedSample / 256), dim3(256), 0, st, a, theta, b);
+    hipLaunchKernelGGL(k_med_sort, dim3(1), dim3(1024), 0, st, a, b, h_out);
+    if (N >= 2) {
+        hipLaunchKernelGGL(k_center, dim3(d), dim3(256), 0, st, a, theta, b);
+        hipLaunchKernelGGL(k_pack16, dim3(L.npad / 256), dim3(256), 0, st, a, theta, grad, b);
+        const dim3 grid(L.npad / kRows16, L.splits16);
+        if (L.kd == 32) hipLaunchKernelGGL((k_phi16<32, 64>), grid, dim3(256), 0, st, a, b);
+        else hipLaunchKernelGGL((k_phi16<64, 128>), grid, dim3(256), 0, st, a, b);
+    }
+    const int64_t n = (int64_t)d * N;
+    hipLaunchKernelGGL(k_reduce16, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a, grad, phi, b, status);
+    return hipGetLastError();
+}
+
+hipError_t launch_svgd16_batched(const BatchPlan& P, const ProblemDesc* descs, const float* theta, const float* grad,
+                                 float* phi, char* ws, uint32_t* status, hipStream_t st) {
+    hipLaunchKernelGGL(k_med_dist_batched, dim3(kMedSample / 256, P.n_problems), dim3(256), 0, st, descs, theta, ws);
+    hipLaunchKernelGGL(k_med_sort_batched, dim3(P.n_problems), dim3(1024), 0, st, descs, ws);
+    if (P.n_ctr) hipLaunchKernelGGL(k_center_batched, dim3(P.n_ctr), dim3(256), 0, st, descs, P.ctr_work, theta, ws);
+    if (P.n_row16)
+        hipLaunchKernelGGL(k_pack16_batched, dim3(P.n_row16), dim3(256), 0, st, descs, P.row16_work, theta, grad, ws);
+    if (P.n_phi16[0])
+        hipLaunchKernelGGL((k_phi16_batched<32, 64>), dim3(P.n_phi16[0]), dim3(256), 0, st, descs, P.phi16_work[0], ws);
+    if (P.n_phi16[1])
+        hipLaunchKernelGGL((k_phi16_batched<64, 128>), dim3(P.n_phi16[1]), dim3(256), 0, st, descs, P.phi16_work[1],
+                           ws);
+    hipLaunchKernelGGL(k_reduce16_batched, dim3(P.n_red), dim3(256), 0, st, descs, P.red_work, grad, phi, ws, status);
+    return hipGetLastError();
+}
+
+}  // namespace stamp

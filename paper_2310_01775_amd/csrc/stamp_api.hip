@@ -172,8 +172,10 @@ struct SolvePlan {
     std::vector<int2> roll_tiles;
     std::vector<int4> dist_work, hist_work, red_work;
     std::vector<int4> phi_work[kDpClasses];
+    std::vector<int4> ctr_work, row16_work, phi16_work[2];  // BF16 form
     int phi_rows = 256;
     size_t clk_off = 0, desc_off = 0, roll_off = 0, dist_off = 0, hist_off = 0, red_off = 0;
+    size_t ctr16_off = 0, row16_off = 0, phi16_off[2] = {};
     size_t phi_off[kDpClasses] = {};
     size_t ctr_off = 0, err_off = 0, tape_off = 0, seg_off = 0, grad_off = 0, phi_vec_off = 0, cost_off = 0,
            svgd_off = 0;
@@ -233,6 +235,14 @@ void build_plan(int n, const stamp_scene* scenes, const int32_t* N, int K, float
             for (int rb = 0; rb * phi_rows < D.N; ++rb)
                 for (int q = 0; q < D.sv.splits; ++q) P.phi_work[c].push_back(make_int4(p, rb, q, 0));
         }
+        // BF16 form: its lists do not depend on the row block of the FP32 form
+        for (int r0 = 0; r0 < D.N; r0 += kRows16) P.row16_work.push_back(make_int4(p, r0, 0, 0));
+        if (D.N >= 2) {
+            for (int l = 0; l < D.d; ++l) P.ctr_work.push_back(make_int4(p, l, 0, 0));
+            const int c16 = D.sv.kd == 32 ? 0 : 1;
+            for (int rb = 0; rb < D.sv.npad / kRows16; ++rb)
+                for (int q = 0; q < D.sv.splits16; ++q) P.phi16_work[c16].push_back(make_int4(p, rb, q, 0));
+        }
         const int64_t ne = (int64_t)D.d * D.N;
         for (int64_t e = 0; e < ne; e += kRedChunk)
             P.red_work.push_back(make_int4(p, (int)e, (int)std::min<int64_t>(e + kRedChunk, ne), 0));
@@ -262,6 +272,9 @@ void build_plan(int n, const stamp_scene* scenes, const int32_t* N, int K, float
     P.hist_off = take(P.hist_work.size() * sizeof(int4));
     P.red_off = take(P.red_work.size() * sizeof(int4));
     for (int c = 0; c < kDpClasses; ++c) P.phi_off[c] = take(phi_cap[c] * sizeof(int4));
+    P.ctr16_off = take(P.ctr_work.size() * sizeof(int4));
+    P.row16_off = take(P.row16_work.size() * sizeof(int4));
+    for (int c = 0; c < 2; ++c) P.phi16_off[c] = take(P.phi16_work[c].size() * sizeof(int4));
     P.ctr_off = take(256);
     P.err_off = take((size_t)n * sizeof(float));
     P.tape_off = take((size_t)tp * 4);
@@ -288,6 +301,8 @@ bool same_layout(const SolvePlan& a, const SolvePlan& b) {
               a.grad_off == b.grad_off && a.phi_vec_off == b.phi_vec_off && a.cost_off == b.cost_off &&
               a.svgd_off == b.svgd_off;
     for (int c = 0; c < kDpClasses; ++c) ok = ok && a.phi_off[c] == b.phi_off[c];
+    ok = ok && a.ctr16_off == b.ctr16_off && a.row16_off == b.row16_off && a.phi16_off[0] == b.phi16_off[0] &&
+         a.phi16_off[1] == b.phi16_off[1];
     return ok;
 }
 
@@ -450,6 +465,23 @@ int32_t stamp_svgd_step(stamp_ctx* ctx, int32_t N, int32_t d, const float* theta
     return e == hipSuccess ? STAMP_OK : hip_fail(ctx, e, "svgd_step");
 }
 
+int32_t stamp_svgd_step_bf16(stamp_ctx* ctx, int32_t N, int32_t d, const float* theta, const float* grad_logp,
+                             float bandwidth, float* phi, float* h_out, void* workspace, size_t ws_bytes,
+                             void* stream) {
+    if (!ctx) return STAMP_EINVAL;
+    if (!theta || !grad_logp || !phi) return fail(ctx, STAMP_EINVAL, "null theta, grad_logp or phi");
+    if (N < 1 || d < 1) return fail(ctx, STAMP_EINVAL, "N=%d, d=%d must be >= 1", N, d);
+    if (d > kMaxSvgdDim || N > kMaxSvgdN)
+        return fail(ctx, STAMP_EUNSUPPORTED, "svgd step supports d <= %d, N <= %d", kMaxSvgdDim, kMaxSvgdN);
+    if (!isfinite(bandwidth)) return fail(ctx, STAMP_EINVAL, "non-finite bandwidth");
+    const SvgdLayout L = svgd_workspace_layout(N, d);
+    if (!workspace || ws_bytes < L.total)
+        return fail(ctx, STAMP_ENOSPACE, "svgd workspace %zu < %zu bytes", ws_bytes, L.total);
+    hipError_t e = launch_svgd16(N, d, theta, grad_logp, bandwidth, phi, h_out, workspace, L, nullptr,
+                                 (hipStream_t)stream);
+    return e == hipSuccess ? STAMP_OK : hip_fail(ctx, e, "svgd_step_bf16");
+}
+
 int32_t stamp_adam_step(stamp_ctx* ctx, int64_t n, float* theta, const float* phi, float* m, float* v, int32_t t,
                         float lr, float beta1, float beta2, float eps, int32_t use_adam, void* stream) {
     if (!ctx) return STAMP_EINVAL;
@@ -546,6 +578,12 @@ static int32_t solve_impl(stamp_ctx* ctx, int32_t n_problems, const stamp_scene*
         for (int c = 0; c < kDpClasses; ++c)
             if ((r = upload(P.phi_off[c], P.phi_work[c].data(), P.phi_work[c].size() * sizeof(int4))) != hipSuccess)
                 return r;
+        if ((r = upload(P.ctr16_off, P.ctr_work.data(), P.ctr_work.size() * sizeof(int4))) != hipSuccess) return r;
+        if ((r = upload(P.row16_off, P.row16_work.data(), P.row16_work.size() * sizeof(int4))) != hipSuccess) return r;
+        for (int c = 0; c < 2; ++c)
+            if ((r = upload(P.phi16_off[c], P.phi16_work[c].data(), P.phi16_work[c].size() * sizeof(int4))) !=
+                hipSuccess)
+                return r;
         return hipStreamSynchronize(st);  // host lists may go out of scope after this
     };
     STAMP_TRY(upload_lists(), "upload work lists");
@@ -564,6 +602,14 @@ static int32_t solve_impl(stamp_ctx* ctx, int32_t n_problems, const stamp_scene*
         B.phi_rows = P.phi_rows;
         B.red_work = (const int4*)(ws + P.red_off);
         B.n_red = (int)P.red_work.size();
+        B.ctr_work = (const int4*)(ws + P.ctr16_off);
+        B.n_ctr = (int)P.ctr_work.size();
+        B.row16_work = (const int4*)(ws + P.row16_off);
+        B.n_row16 = (int)P.row16_work.size();
+        for (int c = 0; c < 2; ++c) {
+            B.phi16_work[c] = (const int4*)(ws + P.phi16_off[c]);
+            B.n_phi16[c] = (int)P.phi16_work[c].size();
+        }
         return B;
     };
     auto roll_grid = [&](const StampTune& t) {
@@ -665,7 +711,9 @@ static int32_t solve_impl(stamp_ctx* ctx, int32_t n_problems, const stamp_scene*
         hipError_t r;
         for (int p = 0; p < n_problems; ++p)
             if ((r = sur_infer(p, nullptr, d_grad, -1.0f)) != hipSuccess) return r;
-        if ((r = launch_svgd_batched(B, d_desc, theta, d_grad, d_phi, d_svgd, status, st)) != hipSuccess) return r;
+        r = sur->phi_bf16 ? launch_svgd16_batched(B, d_desc, theta, d_grad, d_phi, d_svgd, status, st)
+                          : launch_svgd_batched(B, d_desc, theta, d_grad, d_phi, d_svgd, status, st);
+        if (r != hipSuccess) return r;
         if ((r = launch_update(P.n_theta, theta, d_phi, adam_m, adam_v, cfg->t0, d_ctr, cfg->lr, cfg->beta1,
                                cfg->beta2, cfg->adam_eps, cfg->use_adam, st)) != hipSuccess)
             return r;
@@ -710,8 +758,8 @@ static int32_t solve_impl(stamp_ctx* ctx, int32_t n_problems, const stamp_scene*
         // the network's pointers and each problem's bound weights are kernel
         // arguments of the captured graph, so they are part of its key
         char skey[160];
-        snprintf(skey, sizeof skey, "sur|%p|%p|%p|%d|", (const void*)sur->params, sur->wbf16, (const void*)sur->enc,
-                 sur->n_in);
+        snprintf(skey, sizeof skey, "sur|%p|%p|%p|%d|%d|", (const void*)sur->params, sur->wbf16,
+                 (const void*)sur->enc, sur->n_in, sur->phi_bf16);
         std::string sk = full_key + skey;
         for (int p = 0; p < n_problems; ++p) {
             snprintf(skey, sizeof skey, "%.9g/%.9g/%.9g;", w[p].bound, w[p].o_max, w[p].d_max);

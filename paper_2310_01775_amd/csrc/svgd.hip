@@ -451,6 +451,32 @@ SvgdLayout svgd_workspace_layout(int N, int d) {
     off = align256(off + sizeof(SelState));
     L.part_off = off;
     off = align256(off + L.part_floats * 4);
+    // BF16 matrix-core form
+    L.npad = (N + kRows16 - 1) / kRows16 * kRows16;
+    L.kd = d <= 32 ? 32 : 64;
+    L.vc = 2 * L.kd;
+    {
+        const int rowblocks = L.npad / kRows16;
+        int s16 = (1024 + rowblocks - 1) / rowblocks;
+        if (s16 > L.npad / 128) s16 = L.npad / 128;
+        if (s16 > 32) s16 = 32;
+        if (s16 < 1) s16 = 1;
+        const int chunk = ((L.npad + s16 - 1) / s16 + 31) / 32 * 32;
+        L.splits16 = (L.npad + chunk - 1) / chunk;
+        L.chunk16 = chunk;
+    }
+    L.smp_off = off;
+    off = align256(off + (size_t)kMedSample * 4);
+    L.ctr_off = off;
+    off = align256(off + 64 * 4);
+    L.nrm_off = off;
+    off = align256(off + (size_t)L.npad * 4);
+    L.xb_off = off;
+    off = align256(off + (size_t)L.npad * L.kd * 2);
+    L.vt_off = off;
+    off = align256(off + (size_t)L.vc * L.npad * 2);
+    L.p16_off = off;
+    off = align256(off + (size_t)L.splits16 * L.vc * L.npad * 4);
     L.total = off;
     return L;
 }

@@ -16,7 +16,7 @@ HEADER = os.path.join(ROOT, "include", "stamp.h")
 
 def _declared():
     src = open(HEADER).read()
-    return sorted(set(re.findall(r"\b(stamp_[a-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(stamp_[a-z0-9_]+)\s*\(", src)))
 
 
 def test_header_declares_the_hot_path_calls():

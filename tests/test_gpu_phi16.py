@@ -1,0 +1,106 @@
+"""The BF16 matrix-core SVGD direction (stamp_svgd_step_bf16): its bandwidth
+is the exact median heuristic whenever all pairs fit the sample, a close one
+otherwise; its direction matches the FP64 oracle's Eq. (1) at the same
+bandwidth to the BF16 bar; the surrogate solve with it equals its per-call
+loop bit for bit.
+
+BF16 bar: x~, g and K are rounded to 8 significant bits (unit roundoff
+2^-9 = 1.95e-3) and every product accumulates in FP32; summed over many
+particles the rounding errors average, so the direction is held to 2e-2
+normwise (and the FP32 path's bar does not apply)."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import svgd
+
+pytestmark = pytest.mark.gpu
+
+
+def _case(N, d, seed):
+    rng = np.random.default_rng(seed)
+    th = rng.standard_normal((N, d))
+    th[:, 4::6] *= 0.03   # offsets and depths on their metre scale
+    th[:, 5::6] = np.abs(th[:, 5::6]) * 0.1
+    g = rng.standard_normal((N, d)) * 20.0
+    return W.f32(th), W.f32(g)
+
+
+@pytest.mark.parametrize("N,d", [(2, 6), (37, 12), (128, 30)])
+def test_all_pairs_give_the_exact_median(ctx, N, d):
+    import paper_2310_01775_amd as S
+    th, g = _case(N, d, N)
+    h16 = torch.zeros(1, device="cuda")
+    h32 = torch.zeros(1, device="cuda")
+    ctx.svgd_step_bf16(S.soa(th), S.soa(g), h_out=h16)
+    ctx.svgd_step(S.soa(th), S.soa(g), h_out=h32)
+    torch.cuda.synchronize()
+    assert h16.item() == h32.item()  # same FP32 distances, same order statistic
+    assert abs(h16.item() - svgd.bandwidth(th)) < 3e-6 * svgd.bandwidth(th)
+
+
+@pytest.mark.parametrize("N,d", [(129, 18), (1000, 30), (4096, 30)])
+def test_sampled_median_is_close(ctx, N, d):
+    import paper_2310_01775_amd as S
+    th, g = _case(N, d, N + 1)
+    h16 = torch.zeros(1, device="cuda")
+    ctx.svgd_step_bf16(S.soa(th), S.soa(g), h_out=h16)
+    torch.cuda.synchronize()
+    ref = svgd.bandwidth(th)
+    print("sampled/exact bandwidth", h16.item() / ref, flush=True)
+    assert abs(h16.item() / ref - 1.0) < 0.03
+
+
+@pytest.mark.parametrize("N,d,bw", [(1, 6, 0.0), (2, 6, 0.0), (37, 12, 0.0), (300, 18, 0.0), (513, 30, 0.0),
+                                    (1024, 30, 2.0), (700, 36, 0.0), (2100, 48, 0.0)])
+def test_direction_matches_oracle_at_the_same_bandwidth(ctx, N, d, bw):
+    import paper_2310_01775_amd as S
+    print("case", N, d, bw, flush=True)
+    th, g = _case(N, d, 7 * N + d)
+    h_out = torch.zeros(1, device="cuda")
+    phi = ctx.svgd_step_bf16(S.soa(th), S.soa(g), bw, h_out=h_out)
+    torch.cuda.synchronize()
+    got = S.aos(phi)
+    if N == 1:
+        assert np.array_equal(got, g)
+        return
+    h = float(h_out.item())
+    if bw > 0:
+        assert h == np.float32(bw)
+    ref = svgd.svgd_phi(th, g, h)
+    err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    print("normwise error", err, flush=True)
+    assert err < 2e-2
+    assert np.isfinite(got).all()
+
+
+def test_surrogate_solve_with_the_bf16_direction_equals_its_loop(ctx):
+    import paper_2310_01775_amd as S
+    from tests.test_gpu_surrogate import _batch, _enc, _network, _dev
+    probs = _batch(S, [(300, 3, 2), (64, 5, 1)], 4)
+    n_in = 30 + W.SCENE_ENC
+    P, Wb = _network(ctx, S, n_in, 8)
+    flat = torch.cat([S.soa(th).reshape(-1) for _, _, th, _ in probs]).contiguous()
+    enc = _dev(np.concatenate([_enc(e, n_in, 6 * s["H"]) for s, _, _, e in probs]))
+    m, v = torch.zeros_like(flat), torch.zeros_like(flat)
+    ctx.solve_surrogate([S.make_scene(s) for s, _, _, _ in probs], [S.make_cost(w) for _, w, _, _ in probs],
+                        [th.shape[0] for _, _, th, _ in probs], S.make_cfg(4, lr=1e-3), 4, P, Wb, n_in, enc, flat,
+                        m, v, phi_bf16=True)
+    torch.cuda.synchronize()
+    off = 0
+    for scene, w, th, e in probs:
+        N, d = th.shape
+        theta = S.soa(th)
+        mm, vv = torch.zeros_like(theta), torch.zeros_like(theta)
+        g = torch.empty_like(theta)
+        for t in range(1, 5):
+            ctx.mlp_forward(P, Wb, theta, n_in, d, x_layout=1, enc=_dev(_enc(e, n_in, d)), want_y=False, grad=g,
+                            grad_scale=-1.0, w=S.make_cost(w))
+            phi = ctx.svgd_step_bf16(theta, g)
+            ctx.adam_step(theta, phi, mm, vv, t, lr=1e-3)
+        torch.cuda.synchronize()
+        assert torch.equal(flat[off:off + th.size].view(d, N), theta)
+        off += th.size
