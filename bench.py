@@ -114,9 +114,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--workload", default="plain", choices=["plain", "batched", "long"],
+    ap.add_argument("--workload", default="plain", choices=["plain", "batched", "long", "surrogate"],
                     help="plain: the metric's workload; batched: 64 uneven problems in one graph-replayed "
-                         "solve; long: checkpointed differentiation (report only)")
+                         "solve; long: checkpointed differentiation (report only); surrogate: the learned "
+                         "surrogate form against the plain method at N=16384 (report only)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -146,6 +147,8 @@ def main():
         return bench_batched(args)
     if args.workload == "long":
         return bench_long(args)
+    if args.workload == "surrogate":
+        return bench_surrogate(args)
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     cfg = W.CONFIGS[2]
@@ -295,6 +298,93 @@ def bench_long(args):
         b.record()
         torch.cuda.synchronize()
         out[f"K{K}"] = {"fwd_bwd_ms": a.elapsed_time(b) / args.steps, "kept_bytes": tape_bytes(sc, N, K)}
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+def bench_surrogate(args):
+    """The surrogate form against the plain method on the N=16384, B=3, H=5,
+    T=200 scene: 300 SVGD iterations each, the surrogate form taking the
+    network's gradient for the first 240 (simulator checks every 80).  The
+    network is first trained by the library (2^20 labelled rollouts, two
+    on-policy rounds); its training time is reported apart."""
+    import numpy as np
+    import torch
+
+    import paper_2310_01775_amd as S
+    import workloads as W
+    from paper_2310_01775_amd import surrogate as SG
+
+    ctx = S.Context(0)
+    R = dict(W.SURROGATE_RECIPE)
+    H = 5
+    n_in = 6 * H + W.SCENE_ENC
+    cw = S.make_cost(W.cost_weights())
+    scenes = W.surrogate_dataset_scenes(max(R["random_scenes"], R["rounds"] * R["round_scenes"]))
+    structs = [S.make_scene(sc) for sc in scenes]
+    encs = [torch.as_tensor(W.scene_encoding(sc), dtype=torch.float32, device="cuda") for sc in scenes]
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(R["seed"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    net, ds, log, reps = SG.train_recipe(ctx, R, lambda p: (structs[p], cw, encs[p]),
+                                         lambda p, n: S.soa(W.surrogate_training_plans(p, n, H)),
+                                         lambda p, n: S.soa(W.make_particles(5, 1000 + p, n, H)),
+                                         W.mlp_init(n_in, seed=R["seed"]), n_in, gen)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    scene, _, th0 = W.config_problem(5)
+    N = th0.shape[0]
+    sc = S.make_scene(scene)
+    enc = torch.as_tensor(W.scene_encoding(scene), dtype=torch.float32, device="cuda")
+    iters, s_iters = 300, 240
+    lr = W.DEFAULT_ADAM["lr"]
+    work = ctx._bytes(ctx.solve_workspace_bytes([sc], [N], S.make_cfg(iters, lr=lr)))
+    status = ctx.status_word()
+
+    def plain():
+        th = S.soa(th0)
+        m, v = torch.zeros_like(th), torch.zeros_like(th)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        c = ctx.solve([sc], [cw], [N], S.make_cfg(iters, lr=lr), th, m, v, workspace=work, status=status)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t, c, None
+
+    def surrogate(phi_bf16):
+        th = S.soa(th0)
+        m, v = torch.zeros_like(th), torch.zeros_like(th)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        c, rep = ctx.solve_surrogate([sc], [cw], [N], S.make_cfg(iters, lr=lr), s_iters, net.params, net.wbf16,
+                                     n_in, enc, th, m, v, check_every=80, phi_bf16=phi_bf16, workspace=work,
+                                     status=status)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t, c, rep
+
+    def stats(c):
+        c = c.double()
+        return {"mean": float(c.mean()), "median": float(c.median()), "p10": float(c.quantile(0.1)),
+                "min": float(c.min())}
+
+    out = {"workload": f"surrogate form vs plain: N={N}, B=3, H=5 (d=30), T=200 steps of dt=0.005, "
+                       f"{iters} Adam SVGD iterations, surrogate for the first {s_iters}",
+           "training": {"rows": ds.n, "seconds": train_s, "steps": log.steps,
+                        "final_minibatch_loss": log.losses[-1][1]}}
+    for name, fn in (("plain", plain), ("surrogate_bf16_phi", lambda: surrogate(True)),
+                     ("surrogate_fp32_phi", lambda: surrogate(False))):
+        fn()  # autotune, graph capture
+        wall, c, rep = fn()
+        out[name] = {"wall_s": wall, "particle_iters_per_s": N * iters / wall, "final_true_cost": stats(c)}
+        if rep is not None:
+            out[name]["surrogate_iters"] = rep.iters_run
+            out[name]["fell_back"] = rep.fell_back
+            out[name]["handoff_log_error"] = rep.log_err
+    assert int(status.item()) == 0
+    for name in ("surrogate_bf16_phi", "surrogate_fp32_phi"):
+        out[name]["speedup_vs_plain"] = out["plain"]["wall_s"] / out[name]["wall_s"]
+        out[name]["median_cost_vs_plain"] = (out[name]["final_true_cost"]["median"] /
+                                             out["plain"]["final_true_cost"]["median"])
     print(json.dumps(out), flush=True)
     ctx.close()
 
