@@ -55,21 +55,34 @@ struct TapeGeom {
 };
 
 // ---- SVGD step layout ---------------------------------------------------------
-constexpr int kTile = 64;                             // rows/cols of a distance tile
-constexpr int kBins0 = 2048, kBins1 = 2048, kBins2 = 512;  // radix digits 11, 11, 9 bits
+constexpr int kTile = 64;        // rows/cols of a distance tile
+constexpr int kMedBins = 2048;   // bins of one interval-select pass
+constexpr int kMedCols = 64;     // columns of an all-pairs work item (rows: med_rows)
+constexpr int kCandSegs = 64;    // candidate buffer segments (one counter each)
+constexpr int kCandParts = 4;    // workgroups per segment of a candidate pass
 
-// Radix-selection state of the median (one per problem).
+// Median select state (one per problem): the interval [lo, hi] of FP32 bit
+// patterns known to hold the median, its rank inside, the pass bookkeeping,
+// and the resulting bandwidth.
 struct SelState {
-    uint32_t prefix;  // selected high bits so far
-    uint32_t rank;    // 1-based rank still to find inside the current prefix
-    float h;          // resulting bandwidth
-    float m2;         // the median
+    uint32_t lo, hi;     // inclusive interval of bit patterns
+    uint32_t rank;       // 1-based rank of the median among the values in it
+    uint32_t shift;      // histogram bin = (bits - lo) >> shift
+    uint32_t mode;       // 0 done, 1 pass 0 pending, 2 candidate passes, 3 all-pairs passes
+    uint32_t overflow;   // pass 0: a candidate segment overflowed
+    uint32_t seg[kCandSegs];  // pass 0: slots used in each candidate segment
+    float h;             // resulting bandwidth
+    float m2;            // the median
 };
 
 // Byte offsets inside one problem's SVGD workspace.
 struct SvgdLayout {
-    size_t dist_off, dist_floats;   // tile-packed squared distances (i < j)
-    size_t hist_off;                // 3 histograms of the radix select
+    size_t cand_off;                // bracket values of the median select (uint32 bit patterns)
+    uint32_t cand_cap;              // their capacity: kCandSegs segments of cand_cap / kCandSegs
+    size_t cnt_off;                 // per all-pairs item: pairs under, over the bracket
+    int med_rows;                   // rows (one per thread) of an all-pairs item: 64 or 256
+    int med_rb, med_cc;             // all-pairs items: row blocks x column chunks
+    size_t hist_off;                // kMedBins histogram of the median select
     size_t sel_off;                 // SelState
     size_t part_off, part_floats;   // phi partial sums [splits][d][N]
     int splits;                     // column chunks of the phi contraction
@@ -110,10 +123,16 @@ constexpr int kDpClasses = 6;
 constexpr int kDpClass[kDpClasses] = {8, 16, 24, 32, 48, 64};
 
 // Device work lists of one batched SVGD step (built once per solve).
+// Padded dimension of the median's all-pairs items, and the class of an item
+// shape (padded dimension, rows) as a bit index 0..5.
+__host__ __device__ inline int med_dp(int d) { return d <= 16 ? 16 : d <= 32 ? 32 : 64; }
+__host__ __device__ inline int med_class(int dp, int rows) { return (dp == 16 ? 0 : dp == 32 ? 2 : 4) + (rows == 256); }
+
 struct BatchPlan {
     int n_problems;
-    const int4* dist_work;  int n_dist;   // (p, I, J, -)
-    const int4* hist_work;  int n_hist;   // (p, first uint4, end uint4, -)
+    const int4* dist_work;  int n_dist;   // (p, row block, column chunk, -) of the median passes
+    int med_classes;                      // bit med_class(dp, rows) set when a problem has that shape
+    const int4* cand_work;  int n_cand;   // (p, segment, part, -) of the median's candidate passes
     const int4* phi_work[kDpClasses];     // (p, row block, split, -) per class
     int n_phi[kDpClasses];
     // BF16 matrix-core form: (problem, coordinate), (problem, 256-row chunk),

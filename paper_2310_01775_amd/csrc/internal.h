@@ -34,6 +34,13 @@ hipError_t launch_svgd(int N, int d, const float* theta, const float* grad_logp,
 hipError_t launch_svgd_batched(const BatchPlan& P, const ProblemDesc* descs, const float* theta, const float* grad,
                                float* phi, char* ws, uint32_t* status, hipStream_t st);
 
+// Median-heuristic bandwidth into the problem's SelState (median.hip): exact = 1
+// the exact lower median of all pairs, 0 the lower median of a fixed sample.
+hipError_t launch_median(int N, int d, const float* theta, float bandwidth, int exact, void* ws, const SvgdLayout& L,
+                         float* h_out, hipStream_t st);
+hipError_t launch_median_batched(const BatchPlan& P, const ProblemDesc* descs, const float* theta, int exact,
+                                 char* ws, hipStream_t st);
+
 // The same step on the BF16 matrix cores with a sampled median (phi16.hip).
 hipError_t launch_svgd16(int N, int d, const float* theta, const float* grad, float bandwidth, float* phi,
                          float* h_out, void* ws, const SvgdLayout& L, uint32_t* status, hipStream_t st);

@@ -3,7 +3,8 @@
 //
 //   bandwidth: h = max(m2 / ln N, 1e-12) with m2 the lower median of the
 //     squared distances of a fixed sample of kMedSample particle pairs (all
-//     N(N-1)/2 pairs when there are at most that many: then m2 is exact);
+//     N(N-1)/2 pairs when there are at most that many: then m2 is exact;
+//     median.hip, sampled mode);
 //   x~_i = bf16(theta_i - mean theta)   (centring shrinks the Gram cancellation)
 //   D_ij = |x~_i|^2 + |x~_j|^2 - 2 x~_i . x~_j   (Gram on MFMA, FP32 accumulate)
 //   K_ij = exp(-max(D_ij, 0) / h)
@@ -32,15 +33,6 @@ typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f4;
 
-__device__ __forceinline__ uint32_t mix32(uint32_t x) {  // MurmurHash3 finaliser
-    x ^= x >> 16;
-    x *= 0x85ebca6bu;
-    x ^= x >> 13;
-    x *= 0xc2b2ae35u;
-    x ^= x >> 16;
-    return x;
-}
-
 struct View16 {  // one problem's BF16-form workspace
     float* smp;
     float* ctr;
@@ -61,98 +53,6 @@ __device__ __forceinline__ View16 view16(const SvgdLayout& L, char* base) {
     v.p16 = reinterpret_cast<float*>(base + L.p16_off);
     v.sel = reinterpret_cast<SelState*>(base + L.sel_off);
     return v;
-}
-
-// ---- bandwidth from a sample of pairs ----------------------------------------
-// Sample slot t: pair t of the row-major enumeration of i < j when all pairs
-// fit (N <= 128), else a hashed ordered pair i != j.  Slots beyond the sample
-// hold +inf.  Distances in FP32 by direct differences.
-__device__ __forceinline__ float sample_dist(int N, int d, int t, const float* __restrict__ theta) {
-    const uint64_t P = (uint64_t)N * (uint64_t)(N - 1) / 2;
-    const bool all = P <= (uint64_t)kMedSample;
-    if (N < 2 || (all && (uint64_t)t >= P)) return __int_as_float(0x7f800000);
-    int i, j;
-    if (all) {
-        int r = t;
-        i = 0;
-        while (r >= N - 1 - i) {
-            r -= N - 1 - i;
-            ++i;
-        }
-        j = i + 1 + r;
-    } else {
-        i = (int)(mix32(2u * (uint32_t)t + 1u) % (uint32_t)N);
-        j = (int)(mix32((2u * (uint32_t)t + 2u) ^ 0x9e3779b9u) % (uint32_t)(N - 1));
-        if (j >= i) ++j;
-    }
-    const float* ti = theta + i;
-    const float* tj = theta + j;
-    float acc = 0.0f;
-    int l = 0;
-    for (; l + 8 <= d; l += 8) {  // 16 loads in flight
-        float a[8], b[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            a[u] = ti[(int64_t)(l + u) * N];
-            b[u] = tj[(int64_t)(l + u) * N];
-        }
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const float df = a[u] - b[u];
-            acc = fmaf(df, df, acc);
-        }
-    }
-    for (; l < d; ++l) {
-        const float df = ti[(int64_t)l * N] - tj[(int64_t)l * N];
-        acc = fmaf(df, df, acc);
-    }
-    return acc;
-}
-
-// Lower median of the sample (one workgroup of 1024 threads, 8 values each):
-// bisection on the FP32 bit pattern (non-negative floats order like unsigned
-// integers) for the smallest x with #{v <= x} >= rank; that x is a sample
-// value, so the result is the exact order statistic of the sample.
-__device__ void med_sort_body(int N, float fixed_h, const float* __restrict__ smp, SelState* sel, float* h_out) {
-    __shared__ uint32_t part[16];
-    const int tid = threadIdx.x;
-    if (N < 2 || fixed_h > 0.0f) {
-        if (tid == 0) {
-            const float h = N < 2 ? 1.0f : fixed_h;
-            sel->h = h;
-            sel->m2 = -1.0f;
-            if (h_out) *h_out = h;
-        }
-        return;
-    }
-    const uint64_t P = (uint64_t)N * (uint64_t)(N - 1) / 2;
-    const uint32_t S = P <= (uint64_t)kMedSample ? (uint32_t)P : (uint32_t)kMedSample;
-    const uint32_t rank = (S + 1) / 2;
-    uint32_t v[8];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) v[q] = __float_as_uint(smp[tid + 1024 * q]);
-    uint32_t lo = 0, hi = 0x7f800000u;  // [0, +inf]: +inf pads the sample
-    while (lo < hi) {
-        const uint32_t mid = lo + (hi - lo) / 2;
-        uint32_t c = 0;
-#pragma unroll
-        for (int q = 0; q < 8; ++q) c += v[q] <= mid ? 1u : 0u;
-        for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
-        if ((tid & 63) == 0) part[tid >> 6] = c;
-        __syncthreads();
-        uint32_t tot = 0;
-        for (int w = 0; w < 16; ++w) tot += part[w];
-        __syncthreads();
-        if (tot >= rank) hi = mid;
-        else lo = mid + 1;
-    }
-    if (tid == 0) {
-        const float m2 = __uint_as_float(lo);
-        const float h = fmaxf(m2 / logf((float)N), 1e-12f);
-        sel->m2 = m2;
-        sel->h = h;
-        if (h_out) *h_out = h;
-    }
 }
 
 // ---- particle mean of coordinate l (one workgroup of 256) --------------------
@@ -340,17 +240,6 @@ struct One16 {
     float fixed_h;
 };
 
-__global__ __launch_bounds__(256) void k_med_dist(One16 a, const float* theta, char* ws) {
-    const int t = blockIdx.x * 256 + threadIdx.x;
-    if (a.N < 2 || a.fixed_h > 0.0f) return;
-    view16(a.L, ws).smp[t] = sample_dist(a.N, a.d, t, theta);
-}
-
-__global__ __launch_bounds__(1024) void k_med_sort(One16 a, char* ws, float* h_out) {
-    const View16 w = view16(a.L, ws);
-    med_sort_body(a.N, a.fixed_h, w.smp, w.sel, h_out);
-}
-
 __global__ __launch_bounds__(256) void k_center(One16 a, const float* theta, char* ws) {
     center_body(a.N, blockIdx.x, theta, view16(a.L, ws).ctr);
 }
@@ -380,21 +269,6 @@ __global__ __launch_bounds__(256) void k_reduce16(One16 a, const float* g, float
 
 // ---- batched kernels (work-list entries as in svgd.hip) ---------------------------
 __device__ __forceinline__ char* base_of(const ProblemDesc& D, char* ws) { return ws + D.svgd_off; }
-
-// grid (kMedSample / 256, problems)
-__global__ __launch_bounds__(256) void k_med_dist_batched(const ProblemDesc* __restrict__ descs, const float* theta,
-                                                          char* ws) {
-    const ProblemDesc& D = descs[blockIdx.y];
-    if (D.N < 2 || D.fixed_h > 0.0f) return;
-    const int t = blockIdx.x * 256 + threadIdx.x;
-    view16(D.sv, base_of(D, ws)).smp[t] = sample_dist(D.N, D.d, t, theta + D.theta_off);
-}
-
-__global__ __launch_bounds__(1024) void k_med_sort_batched(const ProblemDesc* __restrict__ descs, char* ws) {
-    const ProblemDesc& D = descs[blockIdx.x];
-    const View16 w = view16(D.sv, base_of(D, ws));
-    med_sort_body(D.N, D.fixed_h, w.smp, w.sel, nullptr);
-}
 
 // entry = (problem, coordinate, -, -)
 __global__ __launch_bounds__(256) void k_center_batched(const ProblemDesc* __restrict__ descs,
@@ -447,8 +321,8 @@ hipError_t launch_svgd16(int N, int d, const float* theta, const float* grad, fl
                          float* h_out, void* ws, const SvgdLayout& L, uint32_t* status, hipStream_t st) {
     One16 a{N, d, L, bandwidth > 0.0f ? bandwidth : 0.0f};
     char* b = static_cast<char*>(ws);
-    hipLaunchKernelGGL(k_med_dist, dim3(kMedSample / 256), dim3(256), 0, st, a, theta, b);
-    hipLaunchKernelGGL(k_med_sort, dim3(1), dim3(1024), 0, st, a, b, h_out);
+    hipError_t e = launch_median(N, d, theta, bandwidth, 0, ws, L, h_out, st);
+    if (e != hipSuccess) return e;
     if (N >= 2) {
         hipLaunchKernelGGL(k_center, dim3(d), dim3(256), 0, st, a, theta, b);
         hipLaunchKernelGGL(k_pack16, dim3(L.npad / 256), dim3(256), 0, st, a, theta, grad, b);
@@ -463,8 +337,8 @@ hipError_t launch_svgd16(int N, int d, const float* theta, const float* grad, fl
 
 hipError_t launch_svgd16_batched(const BatchPlan& P, const ProblemDesc* descs, const float* theta, const float* grad,
                                  float* phi, char* ws, uint32_t* status, hipStream_t st) {
-    hipLaunchKernelGGL(k_med_dist_batched, dim3(kMedSample / 256, P.n_problems), dim3(256), 0, st, descs, theta, ws);
-    hipLaunchKernelGGL(k_med_sort_batched, dim3(P.n_problems), dim3(1024), 0, st, descs, ws);
+    hipError_t e = launch_median_batched(P, descs, theta, 0, ws, st);
+    if (e != hipSuccess) return e;
     if (P.n_ctr) hipLaunchKernelGGL(k_center_batched, dim3(P.n_ctr), dim3(256), 0, st, descs, P.ctr_work, theta, ws);
     if (P.n_row16)
         hipLaunchKernelGGL(k_pack16_batched, dim3(P.n_row16), dim3(256), 0, st, descs, P.row16_work, theta, grad, ws);

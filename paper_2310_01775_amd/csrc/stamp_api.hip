@@ -170,11 +170,12 @@ constexpr int kMaxSvgdN = 65536;
 struct SolvePlan {
     std::vector<stamp::ProblemDesc> descs;
     std::vector<int2> roll_tiles;
-    std::vector<int4> dist_work, hist_work, red_work;
+    std::vector<int4> dist_work, cand_work, red_work;
     std::vector<int4> phi_work[kDpClasses];
     std::vector<int4> ctr_work, row16_work, phi16_work[2];  // BF16 form
     int phi_rows = 256;
-    size_t clk_off = 0, desc_off = 0, roll_off = 0, dist_off = 0, hist_off = 0, red_off = 0;
+    int med_classes = 0;  // item shapes among dist_work (bit med_class)
+    size_t clk_off = 0, desc_off = 0, roll_off = 0, dist_off = 0, cand_off = 0, red_off = 0;
     size_t ctr16_off = 0, row16_off = 0, phi16_off[2] = {};
     size_t phi_off[kDpClasses] = {};
     size_t ctr_off = 0, err_off = 0, tape_off = 0, seg_off = 0, grad_off = 0, phi_vec_off = 0, cost_off = 0,
@@ -184,7 +185,6 @@ struct SolvePlan {
     std::string key;  // batch signature (sizes only)
 };
 
-constexpr int kHistChunk = 1024;  // uint4 per workgroup of a histogram pass
 constexpr int kRedChunk = 256;    // elements per workgroup of the phi reduction
 
 // Lay out the workspace and build the work lists.  phi_rows fixes the row
@@ -221,13 +221,15 @@ void build_plan(int n, const stamp_scene* scenes, const int32_t* N, int K, float
         snprintf(buf, sizeof buf, "%d/%d/%d/%d;", N[p], s->H, s->B, s->T);
         P.key += buf;
         for (int i0 = 0; i0 < D.N; i0 += 16) P.roll_tiles.push_back(make_int2(p, i0));
-        if (D.N >= 2 && !(bandwidth > 0.0f)) {
-            const int nt = D.sv.tiles;
-            for (int I = 0; I < nt; ++I)
-                for (int J = I; J < nt; ++J) P.dist_work.push_back(make_int4(p, I, J, 0));
-            const int64_t n4 = (int64_t)D.sv.dist_floats / 4;
-            for (int64_t e = 0; e < n4; e += kHistChunk)
-                P.hist_work.push_back(make_int4(p, (int)e, (int)std::min<int64_t>(e + kHistChunk, n4), 0));
+        // median passes over all pairs, for problems whose pairs exceed the sample:
+        // every (row block, column chunk) item (items without a pair i < j write
+        // zero counts), and (segment, part) of the candidate passes
+        if (D.N >= 2 && !(bandwidth > 0.0f) && (uint64_t)D.N * (uint64_t)(D.N - 1) / 2 > (uint64_t)kMedSample) {
+            for (int rb = 0; rb < D.sv.med_rb; ++rb)
+                for (int cc = 0; cc < D.sv.med_cc; ++cc) P.dist_work.push_back(make_int4(p, rb, cc, 0));
+            P.med_classes |= 1 << med_class(med_dp(D.d), D.sv.med_rows);
+            for (int g = 0; g < kCandSegs; ++g)
+                for (int q = 0; q < kCandParts; ++q) P.cand_work.push_back(make_int4(p, g, q, 0));
         }
         if (D.N >= 2) {
             int c = 0;
@@ -269,7 +271,7 @@ void build_plan(int n, const stamp_scene* scenes, const int32_t* N, int K, float
     P.desc_off = take(P.descs.size() * sizeof(ProblemDesc));
     P.roll_off = take(P.roll_tiles.size() * sizeof(int2));
     P.dist_off = take(P.dist_work.size() * sizeof(int4));
-    P.hist_off = take(P.hist_work.size() * sizeof(int4));
+    P.cand_off = take(P.cand_work.size() * sizeof(int4));
     P.red_off = take(P.red_work.size() * sizeof(int4));
     for (int c = 0; c < kDpClasses; ++c) P.phi_off[c] = take(phi_cap[c] * sizeof(int4));
     P.ctr16_off = take(P.ctr_work.size() * sizeof(int4));
@@ -296,7 +298,7 @@ size_t plan_bytes(int n, const stamp_scene* scenes, const int32_t* N, int K, flo
 // True when two plans place every workspace region at the same offset.
 bool same_layout(const SolvePlan& a, const SolvePlan& b) {
     bool ok = a.total == b.total && a.clk_off == b.clk_off && a.desc_off == b.desc_off && a.roll_off == b.roll_off &&
-              a.dist_off == b.dist_off && a.hist_off == b.hist_off && a.red_off == b.red_off &&
+              a.dist_off == b.dist_off && a.cand_off == b.cand_off && a.red_off == b.red_off &&
               a.ctr_off == b.ctr_off && a.err_off == b.err_off && a.tape_off == b.tape_off && a.seg_off == b.seg_off &&
               a.grad_off == b.grad_off && a.phi_vec_off == b.phi_vec_off && a.cost_off == b.cost_off &&
               a.svgd_off == b.svgd_off;
@@ -573,7 +575,7 @@ static int32_t solve_impl(stamp_ctx* ctx, int32_t n_problems, const stamp_scene*
         if ((r = upload(P.desc_off, P.descs.data(), P.descs.size() * sizeof(ProblemDesc))) != hipSuccess) return r;
         if ((r = upload(P.roll_off, P.roll_tiles.data(), P.roll_tiles.size() * sizeof(int2))) != hipSuccess) return r;
         if ((r = upload(P.dist_off, P.dist_work.data(), P.dist_work.size() * sizeof(int4))) != hipSuccess) return r;
-        if ((r = upload(P.hist_off, P.hist_work.data(), P.hist_work.size() * sizeof(int4))) != hipSuccess) return r;
+        if ((r = upload(P.cand_off, P.cand_work.data(), P.cand_work.size() * sizeof(int4))) != hipSuccess) return r;
         if ((r = upload(P.red_off, P.red_work.data(), P.red_work.size() * sizeof(int4))) != hipSuccess) return r;
         for (int c = 0; c < kDpClasses; ++c)
             if ((r = upload(P.phi_off[c], P.phi_work[c].data(), P.phi_work[c].size() * sizeof(int4))) != hipSuccess)
@@ -593,8 +595,9 @@ static int32_t solve_impl(stamp_ctx* ctx, int32_t n_problems, const stamp_scene*
         B.n_problems = n_problems;
         B.dist_work = (const int4*)(ws + P.dist_off);
         B.n_dist = (int)P.dist_work.size();
-        B.hist_work = (const int4*)(ws + P.hist_off);
-        B.n_hist = (int)P.hist_work.size();
+        B.med_classes = P.med_classes;
+        B.cand_work = (const int4*)(ws + P.cand_off);
+        B.n_cand = (int)P.cand_work.size();
         for (int c = 0; c < kDpClasses; ++c) {
             B.phi_work[c] = (const int4*)(ws + P.phi_off[c]);
             B.n_phi[c] = (int)P.phi_work[c].size();

@@ -5,15 +5,8 @@
 //   h    = max(m2 / ln N, 1e-12)
 //   phi_i = (1/N) sum_j exp(-D_ij/h) [ g_j + (2/h)(theta_i - theta_j) ]
 //
-// The median is an exact order statistic found by radix selection over the
-// FP32 bit patterns of D (non-negative floats order like unsigned integers):
-// pass 0 writes D for every 64x64 tile pair I <= J and histograms bits 30..20,
-// passes 1 and 2 histogram bits 19..9 and 8..0 of the survivors, and after each
-// pass one workgroup finds the bin holding the wanted rank.  Workgroup
-// histograms live in LDS and are flushed with integer atomics (exact, so the
-// result does not depend on scheduling).  Every stage is its own kernel: on the
-// multi-XCD MI355X a kernel boundary publishes L2 contents once, where an
-// in-kernel device-scope fence per workgroup would write back L2 each time.
+// The median (median.hip) is the exact order statistic of the FP32 distances,
+// found by an interval select seeded from a sample of pairs.
 //
 // The contraction recomputes D in (row block x column chunk) tiles with
 // theta_j and g_j staged through LDS, writes per-chunk partial sums, and a
@@ -31,128 +24,8 @@ namespace stamp {
 
 namespace {
 
-constexpr uint32_t kInvalid = 0xFFFFFFFFu;
 
 // ---- bodies -----------------------------------------------------------------
-
-// Squared distances of tile pair (I, J), I <= J, histogram of bits 30..20.
-__device__ __forceinline__ void dist_hist0_tile(int N, int d, int nt, int I, int J, const float* __restrict__ theta,
-                                                uint32_t* __restrict__ dist, uint32_t* __restrict__ hist) {
-    __shared__ float ti[64][kTile + 1];
-    __shared__ float tj[64][kTile + 1];
-    __shared__ uint32_t lh[kBins0];
-    const int tid = threadIdx.x;
-    for (int b = tid; b < kBins0; b += 256) lh[b] = 0;
-    for (int e = tid; e < d * kTile; e += 256) {  // stage both tiles (d <= 64)
-        const int l = e / kTile, r = e % kTile;
-        const int gi = I * kTile + r, gj = J * kTile + r;
-        ti[l][r] = gi < N ? theta[(int64_t)l * N + gi] : 0.0f;
-        tj[l][r] = gj < N ? theta[(int64_t)l * N + gj] : 0.0f;
-    }
-    __syncthreads();
-    const int64_t tile_id = (int64_t)I * nt - (int64_t)I * (I - 1) / 2 + (J - I);
-    uint32_t* out = dist + tile_id * (kTile * kTile);
-    const int jj = tid & (kTile - 1);
-    const int gj = J * kTile + jj;
-    for (int q = 0; q < kTile / 4; ++q) {
-        const int ii = (tid >> 6) + 4 * q;
-        const int gi = I * kTile + ii;
-        uint32_t bits = kInvalid;
-        if (gi < gj && gj < N) {
-            float acc = 0.0f;
-            for (int l = 0; l < d; ++l) {
-                const float df = ti[l][ii] - tj[l][jj];
-                acc = fmaf(df, df, acc);
-            }
-            bits = __float_as_uint(acc);
-            atomicAdd(&lh[bits >> 20], 1u);
-        }
-        out[ii * kTile + jj] = bits;
-    }
-    __syncthreads();
-    for (int b = tid; b < kBins0; b += 256)
-        if (lh[b]) atomicAdd(&hist[b], lh[b]);
-}
-
-// Histogram of bits [shift, shift+log2 NB) of the values in uint4 range
-// [e0, e1) whose bits above equal the selected prefix; thread starts at e0 +
-// first and steps by stride.
-template <int NB>
-__device__ __forceinline__ void hist_pass_range(const uint32_t* __restrict__ dist, int64_t e0, int64_t e1,
-                                                int64_t first, int64_t stride, int shift,
-                                                const SelState* __restrict__ sel, uint32_t* __restrict__ hist) {
-    __shared__ uint32_t lh[NB];
-    for (int b = threadIdx.x; b < NB; b += 256) lh[b] = 0;
-    __syncthreads();
-    const uint32_t want = sel->prefix;
-    const int hi = shift + __builtin_ctz(NB);
-    const uint4* d4 = reinterpret_cast<const uint4*>(dist);
-    for (int64_t e = e0 + first; e < e1; e += stride) {
-        const uint4 v = d4[e];
-        const uint32_t vals[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-            if (vals[q] != kInvalid && (vals[q] >> hi) == want) atomicAdd(&lh[(vals[q] >> shift) & (NB - 1)], 1u);
-    }
-    __syncthreads();
-    for (int b = threadIdx.x; b < NB; b += 256)
-        if (lh[b]) atomicAdd(&hist[b], lh[b]);
-}
-
-// Find the histogram bin that holds the remaining rank and extend the prefix
-// (one radix-selection step).  One full workgroup of 256 threads.
-template <int NB>
-__device__ __forceinline__ void select_body(const uint32_t* __restrict__ hist, SelState* sel, int first, int last,
-                                            int N, float* h_out) {
-    constexpr int PER = NB / 256;
-    __shared__ uint32_t part[256];
-    const int tid = threadIdx.x;
-    uint32_t loc[PER];
-    uint32_t sum = 0;
-    for (int q = 0; q < PER; ++q) {
-        loc[q] = hist[tid * PER + q];
-        sum += loc[q];
-    }
-    part[tid] = sum;
-    __syncthreads();
-    for (int off = 1; off < 256; off <<= 1) {  // inclusive scan of the per-thread sums
-        const uint32_t v = tid >= off ? part[tid - off] : 0;
-        __syncthreads();
-        part[tid] += v;
-        __syncthreads();
-    }
-    const uint32_t incl = part[tid];
-    const uint32_t excl = incl - sum;
-    uint32_t rank, prefix;
-    if (first) {
-        const uint64_t P = (uint64_t)N * (uint64_t)(N - 1) / 2;  // pairs i < j
-        rank = (uint32_t)((P + 1) / 2);                          // lower median
-        prefix = 0;
-    } else {
-        rank = sel->rank;
-        prefix = sel->prefix;
-    }
-    __syncthreads();
-    if (excl < rank && rank <= incl) {
-        uint32_t c = excl;
-        for (int q = 0; q < PER; ++q) {
-            if (c < rank && rank <= c + loc[q]) {
-                const uint32_t np = (prefix << __builtin_ctz(NB)) | (uint32_t)(tid * PER + q);
-                sel->prefix = np;
-                sel->rank = rank - c;
-                if (last) {
-                    const float m2 = __uint_as_float(np);
-                    const float h = fmaxf(m2 / logf((float)N), 1e-12f);
-                    sel->m2 = m2;
-                    sel->h = h;
-                    if (h_out) *h_out = h;
-                }
-                break;
-            }
-            c += loc[q];
-        }
-    }
-}
 
 // partial[split][l][i] = sum_{j in [j0, j1)} K_ij (g_jl + (2/h)(theta_il - theta_jl))
 // for the rows i = row0 + threadIdx.x of this workgroup.
@@ -220,32 +93,6 @@ __device__ __forceinline__ void phi_reduce_elem(int64_t e, int64_t n, int N, int
 
 // ---- single-problem kernels ---------------------------------------------------
 
-__global__ __launch_bounds__(256) void k_dist_hist0(int N, int d, int nt, const float* __restrict__ theta,
-                                                    uint32_t* __restrict__ dist, uint32_t* __restrict__ hist) {
-    const int I = blockIdx.y, J = blockIdx.x;
-    if (I > J) return;
-    dist_hist0_tile(N, d, nt, I, J, theta, dist, hist);
-}
-
-template <int NB>
-__global__ __launch_bounds__(256) void k_hist_pass(const uint32_t* __restrict__ dist, int64_t n, int shift,
-                                                   const SelState* __restrict__ sel, uint32_t* __restrict__ hist) {
-    hist_pass_range<NB>(dist, 0, n / 4, (int64_t)blockIdx.x * 256 + threadIdx.x, (int64_t)gridDim.x * 256, shift,
-                        sel, hist);
-}
-
-template <int NB>
-__global__ __launch_bounds__(256) void k_select(const uint32_t* __restrict__ hist, SelState* sel, int first,
-                                                int last, int N, float* h_out) {
-    select_body<NB>(hist, sel, first, last, N, h_out);
-}
-
-__global__ void k_set_h(SelState* sel, float h, float* h_out) {
-    sel->h = h;
-    sel->m2 = -1.0f;
-    if (h_out) *h_out = h;
-}
-
 template <int DP>
 __global__ __launch_bounds__(256) void k_phi_partial(int N, int d, int chunk, const float* __restrict__ theta,
                                                      const float* __restrict__ g, const SelState* __restrict__ sel,
@@ -271,63 +118,6 @@ __global__ void k_copy(const float* __restrict__ a, float* __restrict__ b, int64
 // Work-list entries are int4 (problem, a, b, c) with a stage-specific meaning.
 
 __device__ __forceinline__ char* svgd_base(const ProblemDesc& D, char* ws) { return ws + D.svgd_off; }
-
-// zero the histograms of every problem; one workgroup per problem
-__global__ __launch_bounds__(256) void k_zero_hist_batched(const ProblemDesc* __restrict__ descs, char* ws) {
-    const ProblemDesc& D = descs[blockIdx.x];
-    if (D.N < 2) return;
-    uint32_t* h = reinterpret_cast<uint32_t*>(svgd_base(D, ws) + D.sv.hist_off);
-    for (int e = threadIdx.x; e < kBins0 + kBins1 + kBins2; e += 256) h[e] = 0;
-}
-
-// entry = (problem, I, J, -)
-__global__ __launch_bounds__(256) void k_dist_hist0_batched(const ProblemDesc* __restrict__ descs,
-                                                            const int4* __restrict__ work, const float* theta,
-                                                            char* ws) {
-    const int4 w = work[blockIdx.x];
-    const ProblemDesc& D = descs[w.x];
-    char* b = svgd_base(D, ws);
-    dist_hist0_tile(D.N, D.d, D.sv.tiles, w.y, w.z, theta + D.theta_off,
-                    reinterpret_cast<uint32_t*>(b + D.sv.dist_off), reinterpret_cast<uint32_t*>(b + D.sv.hist_off));
-}
-
-// one workgroup per problem; pass 0, 1, 2
-template <int NB>
-__global__ __launch_bounds__(256) void k_select_batched(const ProblemDesc* __restrict__ descs, char* ws, int pass) {
-    const ProblemDesc& D = descs[blockIdx.x];
-    if (D.N < 2 || D.fixed_h > 0.0f) return;
-    char* b = svgd_base(D, ws);
-    const int off = pass == 0 ? 0 : pass == 1 ? kBins0 : kBins0 + kBins1;
-    const uint32_t* hist = reinterpret_cast<const uint32_t*>(b + D.sv.hist_off) + off;
-    select_body<NB>(hist, reinterpret_cast<SelState*>(b + D.sv.sel_off), pass == 0, pass == 2, D.N, nullptr);
-}
-
-// entry = (problem, first uint4, end uint4, -)
-template <int NB>
-__global__ __launch_bounds__(256) void k_hist_pass_batched(const ProblemDesc* __restrict__ descs,
-                                                           const int4* __restrict__ work, char* ws, int shift,
-                                                           int pass) {
-    const int4 w = work[blockIdx.x];
-    const ProblemDesc& D = descs[w.x];
-    char* b = svgd_base(D, ws);
-    uint32_t* hist = reinterpret_cast<uint32_t*>(b + D.sv.hist_off) + (pass == 1 ? kBins0 : kBins0 + kBins1);
-    hist_pass_range<NB>(reinterpret_cast<const uint32_t*>(b + D.sv.dist_off), w.y, w.z, threadIdx.x, 256, shift,
-                        reinterpret_cast<const SelState*>(b + D.sv.sel_off), hist);
-}
-
-// fixed bandwidth, and N = 1 (phi = g): one thread per problem
-__global__ void k_set_h_batched(const ProblemDesc* __restrict__ descs, int n, char* ws) {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n) return;
-    const ProblemDesc& D = descs[p];
-    SelState* sel = reinterpret_cast<SelState*>(svgd_base(D, ws) + D.sv.sel_off);
-    if (D.N < 2) {
-        sel->h = 1.0f;
-    } else if (D.fixed_h > 0.0f) {
-        sel->h = D.fixed_h;
-        sel->m2 = -1.0f;
-    }
-}
 
 // entry = (problem, row block, split, -)
 template <int DP>
@@ -430,7 +220,16 @@ SvgdLayout svgd_workspace_layout(int N, int d) {
     SvgdLayout L{};
     const int nt = (N + kTile - 1) / kTile;
     L.tiles = nt;
-    L.dist_floats = (size_t)nt * (nt + 1) / 2 * kTile * kTile;
+    {
+        const uint64_t P = (uint64_t)N * (uint64_t)(N > 0 ? N - 1 : 0) / 2;
+        // the bracket holds about 6.6% of the pairs; slack for partly used blocks
+        uint64_t cap = P / 8 + (uint64_t)kCandSegs * 16384;
+        cap = (cap + kCandSegs - 1) / kCandSegs * kCandSegs;
+        L.cand_cap = (uint32_t)(cap < 0xffff0000ull ? cap : 0xffff0000ull);
+        L.med_rows = N > 4096 ? 256 : 64;  // small problems: more, smaller items
+        L.med_rb = (N + L.med_rows - 1) / L.med_rows;
+        L.med_cc = (N + kMedCols - 1) / kMedCols;
+    }
     // column chunks: about 2048 (256-row block x chunk) tiles, >= 16 columns,
     // at most 64 chunks; depends on N only, so every launch shape sums in the
     // same order
@@ -443,10 +242,12 @@ SvgdLayout svgd_workspace_layout(int N, int d) {
     L.splits = splits;
     L.part_floats = (size_t)splits * d * N;
     size_t off = 0;
-    L.dist_off = off;
-    off = align256(off + (N >= 2 ? L.dist_floats * 4 : 0));
+    L.cand_off = off;
+    off = align256(off + (N >= 2 ? (size_t)L.cand_cap * 4 : 0));
     L.hist_off = off;
-    off = align256(off + (kBins0 + kBins1 + kBins2) * 4);
+    off = align256(off + kMedBins * 4);
+    L.cnt_off = off;
+    off = align256(off + (size_t)L.med_rb * L.med_cc * 2 * 4);
     L.sel_off = off;
     off = align256(off + sizeof(SelState));
     L.part_off = off;
@@ -485,33 +286,11 @@ hipError_t launch_svgd(int N, int d, const float* theta, const float* grad_logp,
                        float* h_out, void* ws, const SvgdLayout& L, int phi_rows, uint32_t* status, hipStream_t st) {
     char* base = static_cast<char*>(ws);
     SelState* sel = reinterpret_cast<SelState*>(base + L.sel_off);
-    hipError_t e;
+    hipError_t e = launch_median(N, d, theta, bandwidth, 1, ws, L, h_out, st);
+    if (e != hipSuccess) return e;
     if (N == 1) {  // phi = g
-        hipLaunchKernelGGL(k_set_h, dim3(1), dim3(1), 0, st, sel, 1.0f, h_out);
         hipLaunchKernelGGL(k_copy, dim3((d + 255) / 256), dim3(256), 0, st, grad_logp, phi, (int64_t)d);
         return hipGetLastError();
-    }
-    if (bandwidth > 0.0f) {
-        hipLaunchKernelGGL(k_set_h, dim3(1), dim3(1), 0, st, sel, bandwidth, h_out);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-    } else {
-        uint32_t* dist = reinterpret_cast<uint32_t*>(base + L.dist_off);
-        uint32_t* h0 = reinterpret_cast<uint32_t*>(base + L.hist_off);
-        uint32_t* h1 = h0 + kBins0;
-        uint32_t* h2 = h1 + kBins1;
-        const int nt = L.tiles;
-        hipLaunchKernelGGL(k_fill_u32, dim3((kBins0 + kBins1 + kBins2 + 255) / 256), dim3(256), 0, st, h0, 0u,
-                           (int64_t)(kBins0 + kBins1 + kBins2));
-        hipLaunchKernelGGL(k_dist_hist0, dim3(nt, nt), dim3(256), 0, st, N, d, nt, theta, dist, h0);
-        hipLaunchKernelGGL(k_select<kBins0>, dim3(1), dim3(256), 0, st, h0, sel, 1, 0, N, h_out);
-        const int64_t n = (int64_t)L.dist_floats;
-        int blocks = (int)((n / 4 + 255) / 256);  // one uint4 per thread
-        if (blocks > 4096) blocks = 4096;
-        hipLaunchKernelGGL(k_hist_pass<kBins1>, dim3(blocks), dim3(256), 0, st, dist, n, 9, sel, h1);
-        hipLaunchKernelGGL(k_select<kBins1>, dim3(1), dim3(256), 0, st, h1, sel, 0, 0, N, h_out);
-        hipLaunchKernelGGL(k_hist_pass<kBins2>, dim3(blocks), dim3(256), 0, st, dist, n, 0, sel, h2);
-        hipLaunchKernelGGL(k_select<kBins2>, dim3(1), dim3(256), 0, st, h2, sel, 0, 1, N, h_out);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     float* partial = reinterpret_cast<float*>(base + L.part_off);
     const int chunk = (N + L.splits - 1) / L.splits;
@@ -533,19 +312,8 @@ hipError_t launch_svgd(int N, int d, const float* theta, const float* grad_logp,
 
 hipError_t launch_svgd_batched(const BatchPlan& P, const ProblemDesc* descs, const float* theta, const float* grad,
                                float* phi, char* ws, uint32_t* status, hipStream_t st) {
-    const int np = P.n_problems;
-    hipLaunchKernelGGL(k_zero_hist_batched, dim3(np), dim3(256), 0, st, descs, ws);
-    hipLaunchKernelGGL(k_set_h_batched, dim3((np + 63) / 64), dim3(64), 0, st, descs, np, ws);
-    if (P.n_dist) {
-        hipLaunchKernelGGL(k_dist_hist0_batched, dim3(P.n_dist), dim3(256), 0, st, descs, P.dist_work, theta, ws);
-        hipLaunchKernelGGL(k_select_batched<kBins0>, dim3(np), dim3(256), 0, st, descs, ws, 0);
-        hipLaunchKernelGGL(k_hist_pass_batched<kBins1>, dim3(P.n_hist), dim3(256), 0, st, descs, P.hist_work, ws, 9,
-                           1);
-        hipLaunchKernelGGL(k_select_batched<kBins1>, dim3(np), dim3(256), 0, st, descs, ws, 1);
-        hipLaunchKernelGGL(k_hist_pass_batched<kBins2>, dim3(P.n_hist), dim3(256), 0, st, descs, P.hist_work, ws, 0,
-                           2);
-        hipLaunchKernelGGL(k_select_batched<kBins2>, dim3(np), dim3(256), 0, st, descs, ws, 2);
-    }
+    hipError_t e = launch_median_batched(P, descs, theta, 1, ws, st);
+    if (e != hipSuccess) return e;
     for (int c = 0; c < kDpClasses; ++c) {
         if (!P.n_phi[c]) continue;
         switch (kDpClass[c]) {

@@ -6,6 +6,7 @@ import numpy as np
 import pytest
 import torch
 
+import workloads as W
 from oracle import svgd
 
 pytestmark = pytest.mark.gpu
@@ -36,6 +37,58 @@ def test_median_bandwidth_is_the_exact_order_statistic(ctx, N, d):
     k = (D.size + 1) // 2
     lo, hi = m2 * (1 - 3e-6), m2 * (1 + 3e-6)
     assert (D < lo).sum() < k <= (D <= hi).sum()
+
+
+def _median_blocked(th):
+    """Exact lower median of the FP64 pair distances over i < j, row by row
+    (no N x N x d array)."""
+    N = th.shape[0]
+    out = []
+    for i in range(N - 1):
+        diff = th[i + 1:] - th[i]
+        out.append((diff * diff).sum(1))
+    D = np.concatenate(out)
+    k = (D.size + 1) // 2
+    return np.partition(D, k - 1)[k - 1], D, k
+
+
+@pytest.mark.parametrize("N,d", [(129, 18), (3000, 30), (6000, 18)])
+def test_median_of_many_pairs_is_exact(ctx, N, d):
+    """Above 8192 pairs the median comes from the interval select (sample
+    bracket, candidate passes): still the exact order statistic."""
+    import paper_2310_01775_amd as S
+    print("case", N, d, flush=True)
+    rng = np.random.default_rng(N * 7 + d)
+    th = rng.standard_normal((N, d)).astype(np.float32).astype(np.float64)
+    th[:, 4::6] *= 0.03
+    h_out = torch.zeros(1, dtype=torch.float32, device="cuda")
+    ctx.svgd_step(S.soa(th), S.soa(rng.standard_normal((N, d))), 0.0, h_out=h_out)
+    torch.cuda.synchronize()
+    m2 = float(h_out.item()) * math.log(N)
+    ref, D, k = _median_blocked(th)
+    assert abs(m2 - ref) <= 3e-6 * ref
+    lo, hi = m2 * (1 - 3e-6), m2 * (1 + 3e-6)
+    assert (D < lo).sum() < k <= (D <= hi).sum()
+
+
+def test_median_with_massive_ties_takes_the_all_pairs_passes(ctx):
+    """Two clusters of identical particles: just under half the pairs are at
+    distance 0 and the rest share one value, the median; the bracket then
+    holds more values than the candidate buffer and the select finishes with
+    passes over all pairs.  The result is that shared distance."""
+    import paper_2310_01775_amd as S
+    N, d = 1000, 12
+    th = np.zeros((N, d))
+    th[N // 2:] = W.f32(np.linspace(0.1, 1.2, d))
+    h_out = torch.zeros(1, dtype=torch.float32, device="cuda")
+    ctx.svgd_step(S.soa(th), S.soa(np.ones((N, d))), 0.0, h_out=h_out)
+    torch.cuda.synchronize()
+    want = np.float32(0.0)
+    for l in range(d):  # FP32 fused multiply-adds in coordinate order, as the kernels add
+        df = np.float64(np.float32(0.0) - np.float32(th[N // 2, l]))
+        want = np.float32(df * df + np.float64(want))
+    m2 = float(h_out.item()) * math.log(N)
+    assert abs(m2 - float(want)) <= 2e-6 * float(want)
 
 
 @pytest.mark.parametrize("N,d,bw", [(1, 6, 0.0), (2, 6, 0.0), (37, 12, 0.0), (65, 18, 2.5), (300, 18, 0.0),
