@@ -367,6 +367,33 @@ def bench_surrogate(args):
         return {"mean": float(c.mean()), "median": float(c.median()), "p10": float(c.quantile(0.1)),
                 "min": float(c.min())}
 
+    tape = torch.empty(ctx.tape_floats(sc, N, 0), dtype=torch.float32, device="cuda")
+
+    def accuracy(th):
+        """The network's cost and gradient against the simulator's (full
+        cost, bound term included) on the particles th [d][N]."""
+        c_true = ctx.rollout_fwd(sc, cw, th, tape=tape, status=status)
+        g_true = ctx.rollout_adj(sc, cw, th, tape, status=status)
+        _, c_sur, g_sur = ctx.mlp_forward(net.params, net.wbf16, th, n_in, 6 * H, x_layout=1, enc=enc,
+                                          want_y=False, want_cost=True, want_grad=True, w=cw)
+        ae = (c_sur.double() - c_true.double()).abs()
+        rel = ae / c_true.double().abs().clamp_min(1e-3)
+        gs, gt = g_sur.double(), g_true.double()
+        cos = (gs * gt).sum(0) / (gs.norm(dim=0) * gt.norm(dim=0)).clamp_min(1e-30)
+        return {"cost_abs_err_mean": float(ae.mean()), "cost_abs_err_median": float(ae.median()),
+                "cost_rel_err_median": float(rel.median()), "grad_cosine_mean": float(cos.mean()),
+                "grad_cosine_median": float(cos.median()), "true_cost_median": float(c_true.double().median())}
+
+    def handoff(phi_bf16):
+        """Accuracy on the particles the surrogate phase hands to the
+        simulator (after its s_iters iterations; the solve is deterministic,
+        so these are the timed run's particles at that point)."""
+        th = S.soa(th0)
+        m, v = torch.zeros_like(th), torch.zeros_like(th)
+        ctx.solve_surrogate([sc], [cw], [N], S.make_cfg(s_iters, lr=lr), s_iters, net.params, net.wbf16, n_in,
+                            enc, th, m, v, check_every=80, phi_bf16=phi_bf16, workspace=work, status=status)
+        return accuracy(th)
+
     out = {"workload": f"surrogate form vs plain: N={N}, B=3, H=5 (d=30), T=200 steps of dt=0.005, "
                        f"{iters} Adam SVGD iterations, surrogate for the first {s_iters}",
            "training": {"rows": ds.n, "seconds": train_s, "steps": log.steps,
@@ -380,6 +407,8 @@ def bench_surrogate(args):
             out[name]["surrogate_iters"] = rep.iters_run
             out[name]["fell_back"] = rep.fell_back
             out[name]["handoff_log_error"] = rep.log_err
+    out["surrogate_accuracy"] = {"initial_particles": accuracy(S.soa(th0)),
+                                 "handoff_bf16_phi": handoff(True), "handoff_fp32_phi": handoff(False)}
     assert int(status.item()) == 0
     for name in ("surrogate_bf16_phi", "surrogate_fp32_phi"):
         out[name]["speedup_vs_plain"] = out["plain"]["wall_s"] / out[name]["wall_s"]
