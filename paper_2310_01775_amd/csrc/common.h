@@ -29,6 +29,9 @@ struct SimConst {
     float cr[kMaxBlocks];      // mu_b m_b g rho_b     (spin friction)
     float ev2[kMaxBlocks];     // eps_v^2
     float ew2[kMaxBlocks];     // eps_w^2
+    float dtm[kMaxBlocks];     // dt / m_b
+    float dtI[kMaxBlocks];     // dt / I_b
+    float crw2[kMaxBlocks];    // cr_b eps_w^2 (spin friction derivative)
     float pose0[kMaxBlocks][3];
     float hsum[kMaxBlocks][kMaxBlocks];  // h_b + h_c
     float h0;                  // half size of the pushed block
@@ -180,7 +183,7 @@ __device__ __forceinline__ float softplus_u(float z, float beta_log2e) {
 }
 __device__ __forceinline__ float softplus(float z, float beta_log2e, float ln2_over_beta) {
     const float u = softplus_u(z, beta_log2e);
-    return fmaxf(z, 0.0f) + hw_log2(1.0f + u) * ln2_over_beta;
+    return fmaf(hw_log2(1.0f + u), ln2_over_beta, fmaxf(z, 0.0f));
 }
 // d sp / dz = 1 / (1 + exp(-beta z)), from u = exp(-beta|z|) without overflow
 __device__ __forceinline__ float softplus_grad(float z, float beta_log2e) {
@@ -193,7 +196,8 @@ __device__ __forceinline__ float relu(float x) { return fmaxf(x, 0.0f); }
 
 // Quintic time scaling of a push: s(tau) = 10 tau^3 - 15 tau^4 + 6 tau^5.
 __device__ __forceinline__ float push_profile(float tau) {
-    return tau * tau * tau * (10.0f + tau * (-15.0f + 6.0f * tau));
+    const float t3 = tau * tau * tau;
+    return t3 * fmaf(fmaf(6.0f, tau, -15.0f), tau, 10.0f);
 }
 
 

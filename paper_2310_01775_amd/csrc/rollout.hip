@@ -25,12 +25,59 @@ struct State {
     float x[B], y[B], ph[B], vx[B], vy[B], om[B];
 };
 
-// Fixed data of one lane during one push phase.
+// Fixed data of one lane during one push phase.  The pusher of side s sits at
+// A + R(A)[(h0 + standoff) n_s + o t_s - D sig n_s] (anchor A = block-0 pose at
+// the phase start), i.e. at P0 + sig V with P0 = A + R(A)((h0 + standoff) n_s
+// + o t_s) and V = -D R(A) n_s, both fixed over the phase.
 struct Push {
     float nx, ny, tx, ty;  // face normal n_s and tangent t_s (block frame)
-    float Ax, Ay, cA, sA;  // anchor: block-0 position and rotation of S_k
-    float o, D;            // contact offset and push depth of phase k
+    float P0x, P0y;        // pusher position at sig = 0 (world frame)
+    float Vx, Vy;          // pusher travel over the phase (world frame)
 };
+
+// Anchor-frame quantities of a phase, kept for the adjoint.
+struct Anchor {
+    float cA, sA;          // rotation of the anchor
+    float q0x, q0y;        // (h0 + standoff) n_s + o t_s (block frame)
+};
+
+// sin and cos by Cody-Waite reduction x = r + k pi/2 (pi/2 in two parts,
+// fused multiply-adds), |r| <= pi/4, and Taylor polynomials in r^2 (sin to
+// r^9, cos to r^10: truncation below 3e-9 on the reduced range); about one
+// FP32 ulp over the block angles a push produces.
+__device__ __forceinline__ void sincos_rd(float x, float& s, float& c) {
+    const float k = rintf(x * 0.636619772f);  // 2/pi
+    float r = fmaf(-k, 1.57079637f, x);       // pi/2 rounded to FP32
+    r = fmaf(-k, -4.37113883e-8f, r);         // pi/2 minus that
+    const float r2 = r * r;
+    float ps = fmaf(r2, 2.75573192e-6f, -1.98412698e-4f);  // 1/9!, -1/7!
+    ps = fmaf(r2, ps, 8.33333333e-3f);                     // 1/5!
+    ps = fmaf(r2, ps, -1.66666667e-1f);                    // -1/3!
+    const float sr = fmaf(r * r2, ps, r);
+    float pc = fmaf(r2, -2.75573192e-7f, 2.48015873e-5f);  // -1/10!, 1/8!
+    pc = fmaf(r2, pc, -1.38888889e-3f);                    // -1/6!
+    pc = fmaf(r2, pc, 4.16666667e-2f);                     // 1/4!
+    pc = fmaf(r2, pc, -0.5f);
+    const float cr = fmaf(r2, pc, 1.0f);
+    const int q = (int)k & 3;  // sin(r + q pi/2), cos(r + q pi/2)
+    const float ss = (q & 1) ? cr : sr;
+    const float cc = (q & 1) ? sr : cr;
+    s = (q & 2) ? -ss : ss;
+    c = ((q + 1) & 2) ? -cc : cc;
+}
+
+// The phase's pusher data from the anchor pose (Ax, Ay, Aph) and (o, D); the
+// forward pass and the adjoint both build it here, so replays match bit for bit.
+__device__ __forceinline__ void phase_push(const SimConst& c, float Ax, float Ay, float Aph, float o, float D,
+                                           Push& p, Anchor& a) {
+    sincos_rd(Aph, a.sA, a.cA);
+    a.q0x = fmaf(c.h0d, p.nx, o * p.tx);
+    a.q0y = fmaf(c.h0d, p.ny, o * p.ty);
+    p.P0x = Ax + fmaf(a.cA, a.q0x, -(a.sA * a.q0y));
+    p.P0y = Ay + fmaf(a.sA, a.q0x, a.cA * a.q0y);
+    p.Vx = -D * fmaf(a.cA, p.nx, -(a.sA * p.ny));
+    p.Vy = -D * fmaf(a.sA, p.nx, a.cA * p.ny);
+}
 
 // Entry e of the tape holds, for every lane, its 6B-float state contiguously.
 template <int B>
@@ -60,17 +107,20 @@ __device__ __forceinline__ void store_state(const State<B>& X, float* __restrict
 }
 
 // One semi-implicit Euler step of the sub-rollout (pusher of this lane's side).
+// Products that feed a sum are fused (fmaf); the reverse below differentiates
+// the same expressions.
 template <int B>
 __device__ __forceinline__ void step_forward(const SimConst& c, State<B>& X, const Push& p, float sig) {
     float Fx[B], Fy[B], Tq[B];
     // regularised Coulomb friction, every block
 #pragma unroll
     for (int b = 0; b < B; ++b) {
-        const float inv = hw_rsq(X.vx[b] * X.vx[b] + X.vy[b] * X.vy[b] + c.ev2[b]);
-        Fx[b] = -c.cf[b] * X.vx[b] * inv;
-        Fy[b] = -c.cf[b] * X.vy[b] * inv;
-        const float invw = hw_rsq(X.om[b] * X.om[b] + c.ew2[b]);
-        Tq[b] = -c.cr[b] * X.om[b] * invw;
+        const float inv = hw_rsq(fmaf(X.vx[b], X.vx[b], fmaf(X.vy[b], X.vy[b], c.ev2[b])));
+        const float k = c.cf[b] * inv;
+        Fx[b] = -k * X.vx[b];
+        Fy[b] = -k * X.vy[b];
+        const float invw = hw_rsq(fmaf(X.om[b], X.om[b], c.ew2[b]));
+        Tq[b] = -(c.cr[b] * invw) * X.om[b];
     }
     // block-block penalty on the inscribed disks, central force
 #pragma unroll
@@ -78,118 +128,91 @@ __device__ __forceinline__ void step_forward(const SimConst& c, State<B>& X, con
 #pragma unroll
         for (int q = b + 1; q < B; ++q) {
             const float dx = X.x[b] - X.x[q], dy = X.y[b] - X.y[q];
-            const float d2 = dx * dx + dy * dy + c.er2;
+            const float d2 = fmaf(dx, dx, fmaf(dy, dy, c.er2));
             const float rinv = hw_rsq(d2);
-            const float r = d2 * rinv;
-            const float f = c.kb * softplus(c.hsum[b][q] - r, c.beta_log2e, c.ln2_over_beta);
-            const float fr = f * rinv;
-            Fx[b] += fr * dx;
-            Fy[b] += fr * dy;
-            Fx[q] -= fr * dx;
-            Fy[q] -= fr * dy;
+            const float pen = fmaf(-d2, rinv, c.hsum[b][q]);  // h_b + h_c - r
+            const float fr = c.kb * softplus(pen, c.beta_log2e, c.ln2_over_beta) * rinv;
+            Fx[b] = fmaf(fr, dx, Fx[b]);
+            Fy[b] = fmaf(fr, dy, Fy[b]);
+            Fx[q] = fmaf(-fr, dx, Fx[q]);
+            Fy[q] = fmaf(-fr, dy, Fy[q]);
         }
     }
-    // the virtual pusher of this side, on block 0
+    // the virtual pusher of this side, on block 0: contact normal e = R(phi0) n
     {
-        const float depth = c.h0d - p.D * sig;
-        const float qx = depth * p.nx + p.o * p.tx, qy = depth * p.ny + p.o * p.ty;
-        const float psx = p.Ax + p.cA * qx - p.sA * qy;
-        const float psy = p.Ay + p.sA * qx + p.cA * qy;
-        const float relx = psx - X.x[0], rely = psy - X.y[0];
+        const float relx = fmaf(sig, p.Vx, p.P0x) - X.x[0];
+        const float rely = fmaf(sig, p.Vy, p.P0y) - X.y[0];
         float s0, c0;
-        sincosf(X.ph[0], &s0, &c0);
-        const float lx = c0 * relx + s0 * rely, ly = -s0 * relx + c0 * rely;
-        const float pen = c.h0 - (p.nx * lx + p.ny * ly);
+        sincos_rd(X.ph[0], s0, c0);
+        const float ex = fmaf(c0, p.nx, -(s0 * p.ny)), ey = fmaf(s0, p.nx, c0 * p.ny);
+        const float pen = c.h0 - fmaf(ex, relx, ey * rely);
         const float f = c.kp * softplus(pen, c.beta_log2e, c.ln2_over_beta);
-        const float ex = c0 * p.nx - s0 * p.ny, ey = s0 * p.nx + c0 * p.ny;
-        const float Fpx = -f * ex, Fpy = -f * ey;
-        Fx[0] += Fpx;
-        Fy[0] += Fpy;
-        Tq[0] += relx * Fpy - rely * Fpx;
+        Fx[0] = fmaf(-f, ex, Fx[0]);
+        Fy[0] = fmaf(-f, ey, Fy[0]);
+        Tq[0] = fmaf(-f, fmaf(relx, ey, -(rely * ex)), Tq[0]);  // rel x (-f e)
     }
     // semi-implicit Euler: velocities, then positions with the new velocities
 #pragma unroll
     for (int b = 0; b < B; ++b) {
-        X.vx[b] = X.vx[b] + c.dt * (Fx[b] * c.inv_m[b]);
-        X.vy[b] = X.vy[b] + c.dt * (Fy[b] * c.inv_m[b]);
-        X.om[b] = X.om[b] + c.dt * (Tq[b] * c.inv_I[b]);
-        X.x[b] = X.x[b] + c.dt * X.vx[b];
-        X.y[b] = X.y[b] + c.dt * X.vy[b];
-        X.ph[b] = X.ph[b] + c.dt * X.om[b];
+        X.vx[b] = fmaf(c.dtm[b], Fx[b], X.vx[b]);
+        X.vy[b] = fmaf(c.dtm[b], Fy[b], X.vy[b]);
+        X.om[b] = fmaf(c.dtI[b], Tq[b], X.om[b]);
+        X.x[b] = fmaf(c.dt, X.vx[b], X.x[b]);
+        X.y[b] = fmaf(c.dt, X.vy[b], X.y[b]);
+        X.ph[b] = fmaf(c.dt, X.om[b], X.ph[b]);
     }
 }
 
 // Reverse of step_forward at pre-step state X.  On entry L is the adjoint of the
 // post-step state; on exit the adjoint of the pre-step state.  Adjoints of the
-// phase data (o, D, anchor) are accumulated.
+// phase's pusher data (P0, V) are accumulated.
 template <int B>
-__device__ __forceinline__ void step_reverse(const SimConst& c, const State<B>& X, State<B>& L,
-                                             const Push& p, float sig, float& o_b, float& D_b,
-                                             float& Ax_b, float& Ay_b, float& cA_b, float& sA_b) {
+__device__ __forceinline__ void step_reverse(const SimConst& c, const State<B>& X, State<B>& L, const Push& p,
+                                             float sig, float& P0xb, float& P0yb, float& Vxb, float& Vyb) {
     float Fxb[B], Fyb[B], Tqb[B];
-    // integrator: x' = x + dt v', v' = v + dt F/m
+    // integrator: x' = x + dt v', v' = v + (dt/m) F
 #pragma unroll
     for (int b = 0; b < B; ++b) {
-        const float vxb = L.vx[b] + c.dt * L.x[b];
-        const float vyb = L.vy[b] + c.dt * L.y[b];
-        const float omb = L.om[b] + c.dt * L.ph[b];
-        L.vx[b] = vxb;
-        L.vy[b] = vyb;
-        L.om[b] = omb;
-        Fxb[b] = c.dt * c.inv_m[b] * vxb;
-        Fyb[b] = c.dt * c.inv_m[b] * vyb;
-        Tqb[b] = c.dt * c.inv_I[b] * omb;
+        L.vx[b] = fmaf(c.dt, L.x[b], L.vx[b]);
+        L.vy[b] = fmaf(c.dt, L.y[b], L.vy[b]);
+        L.om[b] = fmaf(c.dt, L.ph[b], L.om[b]);
+        Fxb[b] = c.dtm[b] * L.vx[b];
+        Fyb[b] = c.dtm[b] * L.vy[b];
+        Tqb[b] = c.dtI[b] * L.om[b];
     }
     // pusher
     {
-        const float depth = c.h0d - p.D * sig;
-        const float qx = depth * p.nx + p.o * p.tx, qy = depth * p.ny + p.o * p.ty;
-        const float psx = p.Ax + p.cA * qx - p.sA * qy;
-        const float psy = p.Ay + p.sA * qx + p.cA * qy;
-        const float relx = psx - X.x[0], rely = psy - X.y[0];
+        const float relx = fmaf(sig, p.Vx, p.P0x) - X.x[0];
+        const float rely = fmaf(sig, p.Vy, p.P0y) - X.y[0];
         float s0, c0;
-        sincosf(X.ph[0], &s0, &c0);
-        const float lx = c0 * relx + s0 * rely, ly = -s0 * relx + c0 * rely;
-        const float pen = c.h0 - (p.nx * lx + p.ny * ly);
-        const float f = c.kp * softplus(pen, c.beta_log2e, c.ln2_over_beta);
-        const float ex = c0 * p.nx - s0 * p.ny, ey = s0 * p.nx + c0 * p.ny;
-        const float Fpx = -f * ex, Fpy = -f * ey;
-
-        float Fpxb = Fxb[0], Fpyb = Fyb[0];
-        const float Tpb = Tqb[0];
-        // T = relx Fpy - rely Fpx
-        float relxb = Tpb * Fpy, relyb = -Tpb * Fpx;
-        Fpyb += Tpb * relx;
-        Fpxb += -Tpb * rely;
-        // Fp = -f e
-        const float fb = -(Fpxb * ex + Fpyb * ey);
-        const float exb = -Fpxb * f, eyb = -Fpyb * f;
-        // e = R(phi0) n
-        float c0b = exb * p.nx + eyb * p.ny;
-        float s0b = -exb * p.ny + eyb * p.nx;
-        // f = kp sp(pen), pen = h0 - n.l
-        const float penb = fb * c.kp * softplus_grad(pen, c.beta_log2e);
-        const float lxb = -penb * p.nx, lyb = -penb * p.ny;
-        // l = R(phi0)^T rel
-        c0b += lxb * relx + lyb * rely;
-        s0b += lxb * rely - lyb * relx;
-        relxb += lxb * c0 - lyb * s0;
-        relyb += lxb * s0 + lyb * c0;
-        L.ph[0] += -c0b * s0 + s0b * c0;
-        // rel = ps - x0
+        sincos_rd(X.ph[0], s0, c0);
+        const float ex = fmaf(c0, p.nx, -(s0 * p.ny)), ey = fmaf(s0, p.nx, c0 * p.ny);
+        const float cross = fmaf(relx, ey, -(rely * ex));
+        const float pen = c.h0 - fmaf(ex, relx, ey * rely);
+        const float u = softplus_u(pen, c.beta_log2e);
+        const float f = c.kp * fmaf(hw_log2(1.0f + u), c.ln2_over_beta, fmaxf(pen, 0.0f));
+        const float rr = hw_rcp(1.0f + u);
+        const float spg = pen >= 0.0f ? rr : u * rr;  // sp'(pen)
+        // F0 += -f e, T0 += -f cross
+        const float fb = -fmaf(cross, Tqb[0], fmaf(ex, Fxb[0], ey * Fyb[0]));
+        const float crossb = -f * Tqb[0];
+        const float penb = fb * c.kp * spg;
+        // cross = relx ey - rely ex, pen = h0 - (ex relx + ey rely)
+        const float exb = fmaf(-f, Fxb[0], -fmaf(crossb, rely, penb * relx));
+        const float eyb = fmaf(-f, Fyb[0], fmaf(crossb, relx, -(penb * rely)));
+        const float relxb = fmaf(crossb, ey, -(penb * ex));
+        const float relyb = -fmaf(crossb, ex, penb * ey);
+        // e = (c0 nx - s0 ny, s0 nx + c0 ny)
+        const float c0b = fmaf(exb, p.nx, eyb * p.ny);
+        const float s0b = fmaf(eyb, p.nx, -(exb * p.ny));
+        L.ph[0] += fmaf(c0, s0b, -(s0 * c0b));
+        // rel = P0 + sig V - x0
         L.x[0] -= relxb;
         L.y[0] -= relyb;
-        // ps = A + R(A) q
-        Ax_b += relxb;
-        Ay_b += relyb;
-        cA_b += relxb * qx + relyb * qy;
-        sA_b += -relxb * qy + relyb * qx;
-        const float qxb = relxb * p.cA + relyb * p.sA;
-        const float qyb = -relxb * p.sA + relyb * p.cA;
-        // q = depth n + o t, depth = h0 + standoff - D s(tau)
-        const float depthb = qxb * p.nx + qyb * p.ny;
-        o_b += qxb * p.tx + qyb * p.ty;
-        D_b += -depthb * sig;
+        P0xb += relxb;
+        P0yb += relyb;
+        Vxb = fmaf(sig, relxb, Vxb);
+        Vyb = fmaf(sig, relyb, Vyb);
     }
     // block-block contacts: F_b += f u, F_c -= f u with u = Delta / r
 #pragma unroll
@@ -197,19 +220,19 @@ __device__ __forceinline__ void step_reverse(const SimConst& c, const State<B>& 
 #pragma unroll
         for (int q = b + 1; q < B; ++q) {
             const float dx = X.x[b] - X.x[q], dy = X.y[b] - X.y[q];
-            const float d2 = dx * dx + dy * dy + c.er2;
+            const float d2 = fmaf(dx, dx, fmaf(dy, dy, c.er2));
             const float rinv = hw_rsq(d2);
-            const float r = d2 * rinv;
-            const float pen = c.hsum[b][q] - r;
-            const float f = c.kb * softplus(pen, c.beta_log2e, c.ln2_over_beta);
+            const float pen = fmaf(-d2, rinv, c.hsum[b][q]);
+            const float u = softplus_u(pen, c.beta_log2e);
+            const float fr = c.kb * fmaf(hw_log2(1.0f + u), c.ln2_over_beta, fmaxf(pen, 0.0f)) * rinv;
+            const float rr = hw_rcp(1.0f + u);
+            const float fp = c.kb * (pen >= 0.0f ? rr : u * rr);  // f'(pen)
             const float gx = Fxb[b] - Fxb[q], gy = Fyb[b] - Fyb[q];
-            const float gu = (gx * dx + gy * dy) * rinv;   // adjoint of f
-            // d(f u)/dDelta = f/r (I - u u^T) + f'(pen)(-u) u^T, f' = kb sp'(pen)
-            const float fp = c.kb * softplus_grad(pen, c.beta_log2e);
-            const float fr = f * rinv;
+            const float gu = fmaf(gx, dx, gy * dy) * rinv;   // adjoint of f
+            // d(f u)/dDelta = f/r (I - u u^T) + f'(pen)(-u) u^T
             const float k2 = (fr + fp) * gu * rinv;  // coefficient of Delta
-            const float dxb = fr * gx - k2 * dx;
-            const float dyb = fr * gy - k2 * dy;
+            const float dxb = fmaf(fr, gx, -(k2 * dx));
+            const float dyb = fmaf(fr, gy, -(k2 * dy));
             L.x[b] += dxb;
             L.x[q] -= dxb;
             L.y[b] += dyb;
@@ -219,13 +242,13 @@ __device__ __forceinline__ void step_reverse(const SimConst& c, const State<B>& 
     // friction
 #pragma unroll
     for (int b = 0; b < B; ++b) {
-        const float inv = hw_rsq(X.vx[b] * X.vx[b] + X.vy[b] * X.vy[b] + c.ev2[b]);
-        const float inv3 = inv * inv * inv;
-        const float dotF = Fxb[b] * X.vx[b] + Fyb[b] * X.vy[b];
-        L.vx[b] += -c.cf[b] * inv * Fxb[b] + c.cf[b] * inv3 * X.vx[b] * dotF;
-        L.vy[b] += -c.cf[b] * inv * Fyb[b] + c.cf[b] * inv3 * X.vy[b] * dotF;
-        const float invw = hw_rsq(X.om[b] * X.om[b] + c.ew2[b]);
-        L.om[b] += -c.cr[b] * Tqb[b] * c.ew2[b] * invw * invw * invw;
+        const float inv = hw_rsq(fmaf(X.vx[b], X.vx[b], fmaf(X.vy[b], X.vy[b], c.ev2[b])));
+        const float k = c.cf[b] * inv;
+        const float kd = k * inv * inv * fmaf(Fxb[b], X.vx[b], Fyb[b] * X.vy[b]);
+        L.vx[b] = fmaf(kd, X.vx[b], fmaf(-k, Fxb[b], L.vx[b]));
+        L.vy[b] = fmaf(kd, X.vy[b], fmaf(-k, Fyb[b], L.vy[b]));
+        const float invw = hw_rsq(fmaf(X.om[b], X.om[b], c.ew2[b]));
+        L.om[b] = fmaf(-(c.crw2[b] * (invw * invw * invw)), Tqb[b], L.om[b]);
     }
 }
 
@@ -279,14 +302,13 @@ __device__ __forceinline__ void rollout_fwd_lane(const SimConst& c, int N, const
         const float invL = 1.0f / (float)(tk1 - tk);
         Px[k] = S.x[0];
         Py[k] = S.y[0];
-        p.Ax = S.x[0];
-        p.Ay = S.y[0];
-        sincosf(S.ph[0], &p.sA, &p.cA);
         const float z = side_weight(theta, N, i, k, s);
-        p.o = theta[(int64_t)(6 * k + 4) * N + i];
-        p.D = theta[(int64_t)(6 * k + 5) * N + i];
-        Lbound += relu(fabsf(p.o) - c.omax) * relu(fabsf(p.o) - c.omax) + relu(-p.D) * relu(-p.D) +
-                  relu(p.D - c.dmax) * relu(p.D - c.dmax);
+        const float o = theta[(int64_t)(6 * k + 4) * N + i];
+        const float D = theta[(int64_t)(6 * k + 5) * N + i];
+        Anchor an;
+        phase_push(c, S.x[0], S.y[0], S.ph[0], o, D, p, an);
+        Lbound += relu(fabsf(o) - c.omax) * relu(fabsf(o) - c.omax) + relu(-D) * relu(-D) +
+                  relu(D - c.dmax) * relu(D - c.dmax);
         State<B> X = S;
         for (int t = tk; t < tk1; ++t) {
             if (tape) {
@@ -404,8 +426,8 @@ __device__ __forceinline__ void rollout_adj_lane(const SimConst& c, int N, const
         const int tk = phase_start(k, T, H), tk1 = phase_start(k + 1, T, H);
         const float invL = 1.0f / (float)(tk1 - tk);
         const float z = side_weight(theta, N, i, k, s);
-        p.o = theta[(int64_t)(6 * k + 4) * N + i];
-        p.D = theta[(int64_t)(6 * k + 5) * N + i];
+        const float o = theta[(int64_t)(6 * k + 4) * N + i];
+        const float D = theta[(int64_t)(6 * k + 5) * N + i];
         // phase end: S_{k+1} = sum_s z_s X_s
         State<B> Xe, L;
         load_state(Xe, tape + g.ends_off + (int64_t)k * stride, lane);
@@ -424,11 +446,9 @@ __device__ __forceinline__ void rollout_adj_lane(const SimConst& c, int N, const
         const float ab = z * (zb - quad_sum(z * zb));  // softmax VJP
         // anchor of the phase
         const float* ea = tape + ent[k] * stride + lane * 6 * B;
-        p.Ax = ea[0];
-        p.Ay = ea[1];
-        const float Aph = ea[2];
-        sincosf(Aph, &p.sA, &p.cA);
-        float ob = 0.0f, Db = 0.0f, Axb = 0.0f, Ayb = 0.0f, cAb = 0.0f, sAb = 0.0f;
+        Anchor an;
+        phase_push(c, ea[0], ea[1], ea[2], o, D, p, an);
+        float P0xb = 0.0f, P0yb = 0.0f, Vxb = 0.0f, Vyb = 0.0f;
         if (g.ckpt == 0) {
             // reverse sweep over the full tape; the next (earlier) state is
             // fetched while the current step is reversed
@@ -437,8 +457,7 @@ __device__ __forceinline__ void rollout_adj_lane(const SimConst& c, int N, const
             for (int t = tk1 - 1; t >= tk; --t) {
                 const State<B> X = Xn;
                 if (t > tk) load_state(Xn, tape + (int64_t)(t - 1) * stride, lane);
-                step_reverse<B>(c, X, L, p, push_profile((float)(t - tk + 1) * invL), ob, Db, Axb, Ayb, cAb,
-                                sAb);
+                step_reverse<B>(c, X, L, p, push_profile((float)(t - tk + 1) * invL), P0xb, P0yb, Vxb, Vyb);
             }
         } else {
             const int nseg = (tk1 - tk + g.ckpt - 1) / g.ckpt;
@@ -453,12 +472,22 @@ __device__ __forceinline__ void rollout_adj_lane(const SimConst& c, int N, const
                 }
                 for (int t = te - 1; t >= ts; --t) {
                     load_state(X, seg + (int64_t)(t - ts) * stride, lane);
-                    step_reverse<B>(c, X, L, p, push_profile((float)(t - tk + 1) * invL), ob, Db, Axb, Ayb,
-                                    cAb, sAb);
+                    step_reverse<B>(c, X, L, p, push_profile((float)(t - tk + 1) * invL), P0xb, P0yb, Vxb,
+                                    Vyb);
                 }
             }
         }
-        const float Aphb = -cAb * p.sA + sAb * p.cA;
+        // back to the anchor and (o, D): P0 = A + R(A) q0, q0 = (h0 + standoff) n + o t,
+        // V = -D e_A, e_A = R(A) n
+        const float eAx = fmaf(an.cA, p.nx, -(an.sA * p.ny)), eAy = fmaf(an.sA, p.nx, an.cA * p.ny);
+        const float Db = -fmaf(Vxb, eAx, Vyb * eAy);
+        const float eAxb = -D * Vxb, eAyb = -D * Vyb;
+        const float cAb = fmaf(eAxb, p.nx, eAyb * p.ny) + fmaf(P0xb, an.q0x, P0yb * an.q0y);
+        const float sAb = fmaf(eAyb, p.nx, -(eAxb * p.ny)) + fmaf(P0yb, an.q0x, -(P0xb * an.q0y));
+        const float q0xb = fmaf(an.cA, P0xb, an.sA * P0yb), q0yb = fmaf(an.cA, P0yb, -(an.sA * P0xb));
+        const float ob = fmaf(q0xb, p.tx, q0yb * p.ty);
+        const float Axb = P0xb, Ayb = P0yb;
+        const float Aphb = fmaf(an.cA, sAb, -(an.sA * cAb));
         // adjoint of S_k: the four sub-rollouts share it
 #pragma unroll
         for (int b = 0; b < B; ++b) {
@@ -474,8 +503,8 @@ __device__ __forceinline__ void rollout_adj_lane(const SimConst& c, int N, const
         Ls.ph[0] += quad_sum(Aphb);
         // bound loss on o_k, D_k
         const float wb2 = 2.0f * cb * c.wb;
-        const float obt = quad_sum(ob) + wb2 * relu(fabsf(p.o) - c.omax) * copysignf(1.0f, p.o);
-        const float Dbt = quad_sum(Db) + wb2 * (relu(p.D - c.dmax) - relu(-p.D));
+        const float obt = quad_sum(ob) + wb2 * relu(fabsf(o) - c.omax) * copysignf(1.0f, o);
+        const float Dbt = quad_sum(Db) + wb2 * (relu(D - c.dmax) - relu(-D));
         grad[(int64_t)(6 * k + s) * N + i] = ab;
         if (s == 0) grad[(int64_t)(6 * k + 4) * N + i] = obt;
         if (s == 1) grad[(int64_t)(6 * k + 5) * N + i] = Dbt;

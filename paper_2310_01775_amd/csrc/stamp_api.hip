@@ -103,6 +103,9 @@ int derive(stamp_ctx* ctx, const stamp_scene* s, const stamp_cost_w* w, SimConst
         c->cr[b] = (float)(mu * m * g * rho);
         c->ev2[b] = (float)(ev * ev);
         c->ew2[b] = (float)(ew * ew);
+        c->dtm[b] = (float)((double)s->dt / m);
+        c->dtI[b] = (float)((double)s->dt / I);
+        c->crw2[b] = (float)(mu * m * g * rho * ew * ew);
         for (int q = 0; q < 3; ++q) c->pose0[b][q] = s->pose0[b][q];
         for (int q = 0; q < s->B; ++q) c->hsum[b][q] = (float)((double)s->half[b] + (double)s->half[q]);
     }
