@@ -15,6 +15,8 @@ hipError_t launch_rollout_adj(const SimConst& c, int N, const float* theta, cons
                               const TapeGeom& g, const float* cost_bar, float cb_scalar, float* grad,
                               float* seg, uint32_t* status, hipStream_t st);
 
+// Particles per 64-lane rollout tile of a problem with B blocks.
+int rollout_tile_particles(int B);
 hipError_t launch_rollout_fwd_batched(const ProblemDesc* descs, const int2* tiles, int ntiles, int block,
                                       int grid, const float* theta, float* cost, float* tape, uint32_t* status,
                                       hipStream_t st);

@@ -3,9 +3,15 @@
 // Model (Sec. III-B: semi-implicit Euler with spring-based penalty contacts;
 // Sec. IV-A and Appendix E: pushing from the N/E/S/W faces of block 0).
 // Push phase k runs once per side s from the shared phase-start state S_k; the
-// next phase starts from S_{k+1} = sum_s softmax(a_k)_s X_s(t_{k+1}).  One lane
-// per (particle, side): lane 4i+s integrates X_s of particle i in registers;
-// the quad of a particle meets only at phase boundaries (DPP).
+// next phase starts from S_{k+1} = sum_s softmax(a_k)_s X_s(t_{k+1}).
+//
+// Lanes: one per (particle i, side s, block b).  The SL = 1, 2 or 4 block
+// slots of a (particle, side) sub-rollout sit in one DPP quad (SL = B rounded
+// up; slots b >= B are idle copies), so a lane integrates one block and reads
+// the other blocks' positions (and, in the reverse, force adjoints) by
+// quad_perm moves each step; the sides of a particle meet only at phase
+// boundaries.  A step thus costs one block's friction and integration, B-1
+// pair terms and the pusher per lane, instead of all blocks' work.
 //
 // The adjoint is the exact reverse of the forward arithmetic (Sec. III-B:
 // gradients back-propagated through the whole trajectory), either from a full
@@ -20,9 +26,16 @@ namespace stamp {
 // has waves instead of stacking four waves on one CU.
 constexpr int kRolloutBlock = 64;
 
+// Block slots per (particle, side) sub-rollout, and lanes per particle.
 template <int B>
-struct State {
-    float x[B], y[B], ph[B], vx[B], vy[B], om[B];
+struct Slots {
+    static constexpr int SL = B == 1 ? 1 : (B == 2 ? 2 : 4);
+    static constexpr int LANES = 4 * SL;
+};
+
+// State of one block: position, angle, velocities.
+struct Blk {
+    float x, y, ph, vx, vy, om;
 };
 
 // Fixed data of one lane during one push phase.  The pusher of side s sits at
@@ -79,113 +92,212 @@ __device__ __forceinline__ void phase_push(const SimConst& c, float Ax, float Ay
     p.Vy = -D * fmaf(a.sA, p.nx, a.cA * p.ny);
 }
 
-// Entry e of the tape holds, for every lane, its 6B-float state contiguously.
-template <int B>
-__device__ __forceinline__ void load_state(State<B>& X, const float* __restrict__ entry, int64_t lane) {
-    const float2* p = reinterpret_cast<const float2*>(entry + lane * (6 * B));
-#pragma unroll
-    for (int b = 0; b < B; ++b) {
-        const float2 a = p[3 * b + 0], c = p[3 * b + 1], e = p[3 * b + 2];
-        X.x[b] = a.x;
-        X.y[b] = a.y;
-        X.ph[b] = c.x;
-        X.vx[b] = c.y;
-        X.vy[b] = e.x;
-        X.om[b] = e.y;
+
+// Tape entries hold, per (particle, side) sub-rollout, its blocks' states one
+// after another: block b of sub-rollout 4i+s is slot (4i+s)B+b, 6 floats
+// (x, y, phi, vx, vy, omega).
+__device__ __forceinline__ void load_blk(Blk& X, const float* __restrict__ entry, int64_t slot) {
+    const float2* p = reinterpret_cast<const float2*>(entry + slot * 6);
+    const float2 a = p[0], c = p[1], e = p[2];
+    X.x = a.x;
+    X.y = a.y;
+    X.ph = c.x;
+    X.vx = c.y;
+    X.vy = e.x;
+    X.om = e.y;
+}
+
+__device__ __forceinline__ void store_blk(const Blk& X, float* __restrict__ entry, int64_t slot) {
+    float2* p = reinterpret_cast<float2*>(entry + slot * 6);
+    p[0] = make_float2(X.x, X.y);
+    p[1] = make_float2(X.ph, X.vx);
+    p[2] = make_float2(X.vy, X.om);
+}
+
+// Index of the K-th block other than b (increasing order).
+__host__ __device__ constexpr int other_block(int K, int b) { return K < b ? K : K + 1; }
+
+// quad_perm control that hands lane slot b the value of slot other_block(K, b)
+// of its own group of SL slots.
+template <int SL, int K>
+constexpr int other_sel() {
+    int sel = 0;
+    for (int p = 0; p < 4; ++p) {
+        const int b = p % SL, base = p - b;
+        int q = other_block(K, b);
+        if (q >= SL) q = 0;
+        sel |= (base + q) << (2 * p);
+    }
+    return sel;
+}
+
+template <int SL, int K>
+__device__ __forceinline__ float from_other_k(float v) {
+    constexpr int sel = other_sel<SL, K>();
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), sel, 0xF, 0xF, false));
+}
+
+// K is a constant of an unrolled loop (0..2).
+template <int SL>
+__device__ __forceinline__ float from_other(float v, int K) {
+    if (K == 0) return from_other_k<SL, 0>(v);
+    if (K == 1) return from_other_k<SL, 1>(v);
+    return from_other_k<SL, 2>(v);
+}
+
+// Sum over the four sides of a particle (lanes SL apart): (v0+v1)+(v2+v3) on
+// every lane, bit-identical.
+template <int SL>
+__device__ __forceinline__ float side_sum(float v) {
+    if constexpr (SL == 1) {
+        return quad_sum(v);
+    } else {
+        v = v + __shfl_xor(v, SL);
+        return v + __shfl_xor(v, 2 * SL);
     }
 }
 
-template <int B>
-__device__ __forceinline__ void store_state(const State<B>& X, float* __restrict__ entry, int64_t lane) {
-    float2* p = reinterpret_cast<float2*>(entry + lane * (6 * B));
-#pragma unroll
-    for (int b = 0; b < B; ++b) {
-        p[3 * b + 0] = make_float2(X.x[b], X.y[b]);
-        p[3 * b + 1] = make_float2(X.ph[b], X.vx[b]);
-        p[3 * b + 2] = make_float2(X.vy[b], X.om[b]);
-    }
+// Sum over the block slots of a sub-rollout.
+template <int SL>
+__device__ __forceinline__ float slot_sum(float v) {
+    if constexpr (SL >= 2) v = v + quad_xor1(v);
+    if constexpr (SL == 4) v = v + quad_xor2(v);
+    return v;
 }
 
-// One semi-implicit Euler step of the sub-rollout (pusher of this lane's side).
-// Products that feed a sum are fused (fmaf); the reverse below differentiates
-// the same expressions.
+// Constants of this lane's block b (slots b >= B take block 0's).
 template <int B>
-__device__ __forceinline__ void step_forward(const SimConst& c, State<B>& X, const Push& p, float sig) {
-    float Fx[B], Fy[B], Tq[B];
-    // regularised Coulomb friction, every block
+struct BlkConst {
+    float cf, cr, ev2, ew2, dtm, dtI, crw2;
+    float hs[B > 1 ? B - 1 : 1];  // h_b + h_q of the other blocks, increasing q
+    float x0, y0, ph0;            // initial pose
+};
+
+template <int B>
+__device__ __forceinline__ float pick(const float* a, int b) {
+    float v = a[0];
 #pragma unroll
-    for (int b = 0; b < B; ++b) {
-        const float inv = hw_rsq(fmaf(X.vx[b], X.vx[b], fmaf(X.vy[b], X.vy[b], c.ev2[b])));
-        const float k = c.cf[b] * inv;
-        Fx[b] = -k * X.vx[b];
-        Fy[b] = -k * X.vy[b];
-        const float invw = hw_rsq(fmaf(X.om[b], X.om[b], c.ew2[b]));
-        Tq[b] = -(c.cr[b] * invw) * X.om[b];
+    for (int q = 1; q < B; ++q) v = (b == q) ? a[q] : v;
+    return v;
+}
+
+template <int B>
+__device__ __forceinline__ BlkConst<B> blk_const(const SimConst& c, int b) {
+    BlkConst<B> k;
+    k.cf = pick<B>(c.cf, b);
+    k.cr = pick<B>(c.cr, b);
+    k.ev2 = pick<B>(c.ev2, b);
+    k.ew2 = pick<B>(c.ew2, b);
+    k.dtm = pick<B>(c.dtm, b);
+    k.dtI = pick<B>(c.dtI, b);
+    k.crw2 = pick<B>(c.crw2, b);
+    float px[kMaxBlocks], py[kMaxBlocks], pp[kMaxBlocks];
+#pragma unroll
+    for (int q = 0; q < kMaxBlocks; ++q) {
+        px[q] = c.pose0[q][0];
+        py[q] = c.pose0[q][1];
+        pp[q] = c.pose0[q][2];
     }
+    k.x0 = pick<B>(px, b);
+    k.y0 = pick<B>(py, b);
+    k.ph0 = pick<B>(pp, b);
+#pragma unroll
+    for (int K = 0; K < (B > 1 ? B - 1 : 1); ++K) {
+        float v = 0.0f;
+#pragma unroll
+        for (int bb = 0; bb < B; ++bb) v = (b == bb && B > 1) ? c.hsum[bb][other_block(K, bb)] : v;
+        k.hs[K] = v;
+    }
+    return k;
+}
+
+// One semi-implicit Euler step of block b of the sub-rollout (pusher of this
+// lane's side on block 0).  Products that feed a sum are fused (fmaf); the
+// reverse below differentiates the same expressions.  Forces on a block sum in
+// the order friction, pairs by increasing partner, pusher.
+template <int B>
+__device__ __forceinline__ void step_forward(const SimConst& c, const BlkConst<B>& k, int b, Blk& X, const Push& p,
+                                             float sig) {
+    constexpr int SL = Slots<B>::SL;
+    constexpr int NO = B - 1;
+    float ox[NO > 0 ? NO : 1], oy[NO > 0 ? NO : 1];
+#pragma unroll
+    for (int K = 0; K < NO; ++K) {
+        ox[K] = from_other<SL>(X.x, K);
+        oy[K] = from_other<SL>(X.y, K);
+    }
+    // regularised Coulomb friction
+    const float inv = hw_rsq(fmaf(X.vx, X.vx, fmaf(X.vy, X.vy, k.ev2)));
+    const float kf = k.cf * inv;
+    float Fx = -kf * X.vx;
+    float Fy = -kf * X.vy;
+    const float invw = hw_rsq(fmaf(X.om, X.om, k.ew2));
+    float Tq = -(k.cr * invw) * X.om;
     // block-block penalty on the inscribed disks, central force
 #pragma unroll
-    for (int b = 0; b < B; ++b) {
-#pragma unroll
-        for (int q = b + 1; q < B; ++q) {
-            const float dx = X.x[b] - X.x[q], dy = X.y[b] - X.y[q];
-            const float d2 = fmaf(dx, dx, fmaf(dy, dy, c.er2));
-            const float rinv = hw_rsq(d2);
-            const float pen = fmaf(-d2, rinv, c.hsum[b][q]);  // h_b + h_c - r
-            const float fr = c.kb * softplus(pen, c.beta_log2e, c.ln2_over_beta) * rinv;
-            Fx[b] = fmaf(fr, dx, Fx[b]);
-            Fy[b] = fmaf(fr, dy, Fy[b]);
-            Fx[q] = fmaf(-fr, dx, Fx[q]);
-            Fy[q] = fmaf(-fr, dy, Fy[q]);
-        }
+    for (int K = 0; K < NO; ++K) {
+        const float dx = X.x - ox[K], dy = X.y - oy[K];
+        const float d2 = fmaf(dx, dx, fmaf(dy, dy, c.er2));
+        const float rinv = hw_rsq(d2);
+        const float pen = fmaf(-d2, rinv, k.hs[K]);  // h_b + h_q - r
+        const float fr = c.kb * softplus(pen, c.beta_log2e, c.ln2_over_beta) * rinv;
+        Fx = fmaf(fr, dx, Fx);
+        Fy = fmaf(fr, dy, Fy);
     }
     // the virtual pusher of this side, on block 0: contact normal e = R(phi0) n
     {
-        const float relx = fmaf(sig, p.Vx, p.P0x) - X.x[0];
-        const float rely = fmaf(sig, p.Vy, p.P0y) - X.y[0];
+        const float relx = fmaf(sig, p.Vx, p.P0x) - X.x;
+        const float rely = fmaf(sig, p.Vy, p.P0y) - X.y;
         float s0, c0;
-        sincos_rd(X.ph[0], s0, c0);
+        sincos_rd(X.ph, s0, c0);
         const float ex = fmaf(c0, p.nx, -(s0 * p.ny)), ey = fmaf(s0, p.nx, c0 * p.ny);
         const float pen = c.h0 - fmaf(ex, relx, ey * rely);
         const float f = c.kp * softplus(pen, c.beta_log2e, c.ln2_over_beta);
-        Fx[0] = fmaf(-f, ex, Fx[0]);
-        Fy[0] = fmaf(-f, ey, Fy[0]);
-        Tq[0] = fmaf(-f, fmaf(relx, ey, -(rely * ex)), Tq[0]);  // rel x (-f e)
+        if (b == 0) {
+            Fx = fmaf(-f, ex, Fx);
+            Fy = fmaf(-f, ey, Fy);
+            Tq = fmaf(-f, fmaf(relx, ey, -(rely * ex)), Tq);  // rel x (-f e)
+        }
     }
     // semi-implicit Euler: velocities, then positions with the new velocities
-#pragma unroll
-    for (int b = 0; b < B; ++b) {
-        X.vx[b] = fmaf(c.dtm[b], Fx[b], X.vx[b]);
-        X.vy[b] = fmaf(c.dtm[b], Fy[b], X.vy[b]);
-        X.om[b] = fmaf(c.dtI[b], Tq[b], X.om[b]);
-        X.x[b] = fmaf(c.dt, X.vx[b], X.x[b]);
-        X.y[b] = fmaf(c.dt, X.vy[b], X.y[b]);
-        X.ph[b] = fmaf(c.dt, X.om[b], X.ph[b]);
-    }
+    X.vx = fmaf(k.dtm, Fx, X.vx);
+    X.vy = fmaf(k.dtm, Fy, X.vy);
+    X.om = fmaf(k.dtI, Tq, X.om);
+    X.x = fmaf(c.dt, X.vx, X.x);
+    X.y = fmaf(c.dt, X.vy, X.y);
+    X.ph = fmaf(c.dt, X.om, X.ph);
 }
 
-// Reverse of step_forward at pre-step state X.  On entry L is the adjoint of the
-// post-step state; on exit the adjoint of the pre-step state.  Adjoints of the
-// phase's pusher data (P0, V) are accumulated.
+// Reverse of step_forward at pre-step state X of block b.  On entry L is the
+// adjoint of the block's post-step state; on exit that of its pre-step state.
+// Adjoints of the phase's pusher data (P0, V) are accumulated on block 0.
 template <int B>
-__device__ __forceinline__ void step_reverse(const SimConst& c, const State<B>& X, State<B>& L, const Push& p,
-                                             float sig, float& P0xb, float& P0yb, float& Vxb, float& Vyb) {
-    float Fxb[B], Fyb[B], Tqb[B];
+__device__ __forceinline__ void step_reverse(const SimConst& c, const BlkConst<B>& k, int b, const Blk& X, Blk& L,
+                                             const Push& p, float sig, float& P0xb, float& P0yb, float& Vxb,
+                                             float& Vyb) {
+    constexpr int SL = Slots<B>::SL;
+    constexpr int NO = B - 1;
     // integrator: x' = x + dt v', v' = v + (dt/m) F
+    L.vx = fmaf(c.dt, L.x, L.vx);
+    L.vy = fmaf(c.dt, L.y, L.vy);
+    L.om = fmaf(c.dt, L.ph, L.om);
+    const float Fxb = k.dtm * L.vx;
+    const float Fyb = k.dtm * L.vy;
+    const float Tqb = k.dtI * L.om;
+    float ox[NO > 0 ? NO : 1], oy[NO > 0 ? NO : 1], ofx[NO > 0 ? NO : 1], ofy[NO > 0 ? NO : 1];
 #pragma unroll
-    for (int b = 0; b < B; ++b) {
-        L.vx[b] = fmaf(c.dt, L.x[b], L.vx[b]);
-        L.vy[b] = fmaf(c.dt, L.y[b], L.vy[b]);
-        L.om[b] = fmaf(c.dt, L.ph[b], L.om[b]);
-        Fxb[b] = c.dtm[b] * L.vx[b];
-        Fyb[b] = c.dtm[b] * L.vy[b];
-        Tqb[b] = c.dtI[b] * L.om[b];
+    for (int K = 0; K < NO; ++K) {
+        ox[K] = from_other<SL>(X.x, K);
+        oy[K] = from_other<SL>(X.y, K);
+        ofx[K] = from_other<SL>(Fxb, K);
+        ofy[K] = from_other<SL>(Fyb, K);
     }
     // pusher
     {
-        const float relx = fmaf(sig, p.Vx, p.P0x) - X.x[0];
-        const float rely = fmaf(sig, p.Vy, p.P0y) - X.y[0];
+        const float relx = fmaf(sig, p.Vx, p.P0x) - X.x;
+        const float rely = fmaf(sig, p.Vy, p.P0y) - X.y;
         float s0, c0;
-        sincos_rd(X.ph[0], s0, c0);
+        sincos_rd(X.ph, s0, c0);
         const float ex = fmaf(c0, p.nx, -(s0 * p.ny)), ey = fmaf(s0, p.nx, c0 * p.ny);
         const float cross = fmaf(relx, ey, -(rely * ex));
         const float pen = c.h0 - fmaf(ex, relx, ey * rely);
@@ -194,62 +306,54 @@ __device__ __forceinline__ void step_reverse(const SimConst& c, const State<B>& 
         const float rr = hw_rcp(1.0f + u);
         const float spg = pen >= 0.0f ? rr : u * rr;  // sp'(pen)
         // F0 += -f e, T0 += -f cross
-        const float fb = -fmaf(cross, Tqb[0], fmaf(ex, Fxb[0], ey * Fyb[0]));
-        const float crossb = -f * Tqb[0];
+        const float fb = -fmaf(cross, Tqb, fmaf(ex, Fxb, ey * Fyb));
+        const float crossb = -f * Tqb;
         const float penb = fb * c.kp * spg;
         // cross = relx ey - rely ex, pen = h0 - (ex relx + ey rely)
-        const float exb = fmaf(-f, Fxb[0], -fmaf(crossb, rely, penb * relx));
-        const float eyb = fmaf(-f, Fyb[0], fmaf(crossb, relx, -(penb * rely)));
+        const float exb = fmaf(-f, Fxb, -fmaf(crossb, rely, penb * relx));
+        const float eyb = fmaf(-f, Fyb, fmaf(crossb, relx, -(penb * rely)));
         const float relxb = fmaf(crossb, ey, -(penb * ex));
         const float relyb = -fmaf(crossb, ex, penb * ey);
         // e = (c0 nx - s0 ny, s0 nx + c0 ny)
         const float c0b = fmaf(exb, p.nx, eyb * p.ny);
         const float s0b = fmaf(eyb, p.nx, -(exb * p.ny));
-        L.ph[0] += fmaf(c0, s0b, -(s0 * c0b));
-        // rel = P0 + sig V - x0
-        L.x[0] -= relxb;
-        L.y[0] -= relyb;
-        P0xb += relxb;
-        P0yb += relyb;
-        Vxb = fmaf(sig, relxb, Vxb);
-        Vyb = fmaf(sig, relyb, Vyb);
-    }
-    // block-block contacts: F_b += f u, F_c -= f u with u = Delta / r
-#pragma unroll
-    for (int b = 0; b < B; ++b) {
-#pragma unroll
-        for (int q = b + 1; q < B; ++q) {
-            const float dx = X.x[b] - X.x[q], dy = X.y[b] - X.y[q];
-            const float d2 = fmaf(dx, dx, fmaf(dy, dy, c.er2));
-            const float rinv = hw_rsq(d2);
-            const float pen = fmaf(-d2, rinv, c.hsum[b][q]);
-            const float u = softplus_u(pen, c.beta_log2e);
-            const float fr = c.kb * fmaf(hw_log2(1.0f + u), c.ln2_over_beta, fmaxf(pen, 0.0f)) * rinv;
-            const float rr = hw_rcp(1.0f + u);
-            const float fp = c.kb * (pen >= 0.0f ? rr : u * rr);  // f'(pen)
-            const float gx = Fxb[b] - Fxb[q], gy = Fyb[b] - Fyb[q];
-            const float gu = fmaf(gx, dx, gy * dy) * rinv;   // adjoint of f
-            // d(f u)/dDelta = f/r (I - u u^T) + f'(pen)(-u) u^T
-            const float k2 = (fr + fp) * gu * rinv;  // coefficient of Delta
-            const float dxb = fmaf(fr, gx, -(k2 * dx));
-            const float dyb = fmaf(fr, gy, -(k2 * dy));
-            L.x[b] += dxb;
-            L.x[q] -= dxb;
-            L.y[b] += dyb;
-            L.y[q] -= dyb;
+        if (b == 0) {
+            L.ph += fmaf(c0, s0b, -(s0 * c0b));
+            // rel = P0 + sig V - x0
+            L.x -= relxb;
+            L.y -= relyb;
+            P0xb += relxb;
+            P0yb += relyb;
+            Vxb = fmaf(sig, relxb, Vxb);
+            Vyb = fmaf(sig, relyb, Vyb);
         }
     }
-    // friction
+    // block-block contacts: F_b += f u with u = Delta / r, Delta = x_b - x_q
 #pragma unroll
-    for (int b = 0; b < B; ++b) {
-        const float inv = hw_rsq(fmaf(X.vx[b], X.vx[b], fmaf(X.vy[b], X.vy[b], c.ev2[b])));
-        const float k = c.cf[b] * inv;
-        const float kd = k * inv * inv * fmaf(Fxb[b], X.vx[b], Fyb[b] * X.vy[b]);
-        L.vx[b] = fmaf(kd, X.vx[b], fmaf(-k, Fxb[b], L.vx[b]));
-        L.vy[b] = fmaf(kd, X.vy[b], fmaf(-k, Fyb[b], L.vy[b]));
-        const float invw = hw_rsq(fmaf(X.om[b], X.om[b], c.ew2[b]));
-        L.om[b] = fmaf(-(c.crw2[b] * (invw * invw * invw)), Tqb[b], L.om[b]);
+    for (int K = 0; K < NO; ++K) {
+        const float dx = X.x - ox[K], dy = X.y - oy[K];
+        const float d2 = fmaf(dx, dx, fmaf(dy, dy, c.er2));
+        const float rinv = hw_rsq(d2);
+        const float pen = fmaf(-d2, rinv, k.hs[K]);
+        const float u = softplus_u(pen, c.beta_log2e);
+        const float fr = c.kb * fmaf(hw_log2(1.0f + u), c.ln2_over_beta, fmaxf(pen, 0.0f)) * rinv;
+        const float rr = hw_rcp(1.0f + u);
+        const float fp = c.kb * (pen >= 0.0f ? rr : u * rr);  // f'(pen)
+        const float gx = Fxb - ofx[K], gy = Fyb - ofy[K];
+        const float gu = fmaf(gx, dx, gy * dy) * rinv;  // adjoint of f
+        // d(f u)/dDelta = f/r (I - u u^T) + f'(pen)(-u) u^T
+        const float k2 = (fr + fp) * gu * rinv;  // coefficient of Delta
+        L.x += fmaf(fr, gx, -(k2 * dx));
+        L.y += fmaf(fr, gy, -(k2 * dy));
     }
+    // friction
+    const float inv = hw_rsq(fmaf(X.vx, X.vx, fmaf(X.vy, X.vy, k.ev2)));
+    const float kf = k.cf * inv;
+    const float kd = kf * inv * inv * fmaf(Fxb, X.vx, Fyb * X.vy);
+    L.vx = fmaf(kd, X.vx, fmaf(-kf, Fxb, L.vx));
+    L.vy = fmaf(kd, X.vy, fmaf(-kf, Fyb, L.vy));
+    const float invw = hw_rsq(fmaf(X.om, X.om, k.ew2));
+    L.om = fmaf(-(k.crw2 * (invw * invw * invw)), Tqb, L.om);
 }
 
 __device__ __forceinline__ void side_frame(int s, Push& p) {
@@ -274,82 +378,81 @@ __device__ __forceinline__ float side_weight(const float* __restrict__ theta, in
 __device__ __forceinline__ float smooth_abs(float u, float ea2) { return sqrtf(u * u + ea2); }
 
 // ---------------------------------------------------------------------------
-// Forward rollout of one lane (particle i = lane/4, side s = lane%4).  The four
-// lanes of a quad must all run it (phase mixture by DPP).
+// Forward rollout of one lane: particle i, side s, block slot b.  All lanes of
+// a particle must run it together (DPP exchange every step).
 template <int B>
 __device__ __forceinline__ void rollout_fwd_lane(const SimConst& c, int N, const float* __restrict__ theta,
                                                  float* __restrict__ cost, float* __restrict__ tape,
                                                  const TapeGeom& g, uint32_t* status, int64_t lane) {
-    const int i = (int)(lane >> 2);
-    const int s = (int)(lane & 3);
+    constexpr int SL = Slots<B>::SL;
+    const int i = (int)(lane / (4 * SL));
+    const int r = (int)(lane % (4 * SL));
+    const int s = r / SL, b = r % SL;
+    const bool real = b < B;
+    const int64_t slot = ((int64_t)4 * i + s) * B + b;
+    const int64_t stride = 6 * B * g.lanes;  // floats per tape entry
     const int H = c.H, T = c.T;
+    const BlkConst<B> k = blk_const<B>(c, b);
 
-    State<B> S;
-#pragma unroll
-    for (int b = 0; b < B; ++b) {
-        S.x[b] = c.pose0[b][0];
-        S.y[b] = c.pose0[b][1];
-        S.ph[b] = c.pose0[b][2];
-        S.vx[b] = S.vy[b] = S.om[b] = 0.0f;
-    }
-    float Px[kMaxPushes + 1], Py[kMaxPushes + 1];
+    Blk S;
+    S.x = k.x0;
+    S.y = k.y0;
+    S.ph = k.ph0;
+    S.vx = S.vy = S.om = 0.0f;
+    float Px[kMaxPushes + 1], Py[kMaxPushes + 1];  // block 0's, on slot 0
     float Lbound = 0.0f;
     Push p;
     side_frame(s, p);
     int64_t entry = 0;
-    for (int k = 0; k < H; ++k) {
-        const int tk = phase_start(k, T, H), tk1 = phase_start(k + 1, T, H);
+    for (int kk = 0; kk < H; ++kk) {
+        const int tk = phase_start(kk, T, H), tk1 = phase_start(kk + 1, T, H);
         const float invL = 1.0f / (float)(tk1 - tk);
-        Px[k] = S.x[0];
-        Py[k] = S.y[0];
-        const float z = side_weight(theta, N, i, k, s);
-        const float o = theta[(int64_t)(6 * k + 4) * N + i];
-        const float D = theta[(int64_t)(6 * k + 5) * N + i];
+        Px[kk] = S.x;
+        Py[kk] = S.y;
+        const float z = side_weight(theta, N, i, kk, s);
+        const float o = theta[(int64_t)(6 * kk + 4) * N + i];
+        const float D = theta[(int64_t)(6 * kk + 5) * N + i];
         Anchor an;
-        phase_push(c, S.x[0], S.y[0], S.ph[0], o, D, p, an);
+        phase_push(c, S.x, S.y, S.ph, o, D, p, an);  // block 0's anchor on slot 0
         Lbound += relu(fabsf(o) - c.omax) * relu(fabsf(o) - c.omax) + relu(-D) * relu(-D) +
                   relu(D - c.dmax) * relu(D - c.dmax);
-        State<B> X = S;
+        Blk X = S;
         for (int t = tk; t < tk1; ++t) {
-            if (tape) {
+            if (tape && real) {
                 if (g.ckpt == 0) {
-                    store_state(X, tape + (int64_t)t * 6 * B * g.lanes, lane);
+                    store_blk(X, tape + (int64_t)t * stride, slot);
                 } else if ((t - tk) % g.ckpt == 0) {
-                    store_state(X, tape + entry * 6 * B * g.lanes, lane);
-                    ++entry;
+                    store_blk(X, tape + entry * stride, slot);
                 }
             }
-            step_forward<B>(c, X, p, push_profile((float)(t - tk + 1) * invL));
+            if (g.ckpt != 0 && (t - tk) % g.ckpt == 0) ++entry;
+            step_forward<B>(c, k, b, X, p, push_profile((float)(t - tk + 1) * invL));
         }
-        if (tape) store_state(X, tape + g.ends_off + (int64_t)k * 6 * B * g.lanes, lane);
-        // phase mixture
-#pragma unroll
-        for (int b = 0; b < B; ++b) {
-            S.x[b] = quad_sum(z * X.x[b]);
-            S.y[b] = quad_sum(z * X.y[b]);
-            S.ph[b] = quad_sum(z * X.ph[b]);
-            S.vx[b] = quad_sum(z * X.vx[b]);
-            S.vy[b] = quad_sum(z * X.vy[b]);
-            S.om[b] = quad_sum(z * X.om[b]);
-        }
+        if (tape && real) store_blk(X, tape + g.ends_off + (int64_t)kk * stride, slot);
+        // phase mixture over the sides
+        S.x = side_sum<SL>(z * X.x);
+        S.y = side_sum<SL>(z * X.y);
+        S.ph = side_sum<SL>(z * X.ph);
+        S.vx = side_sum<SL>(z * X.vx);
+        S.vy = side_sum<SL>(z * X.vy);
+        S.om = side_sum<SL>(z * X.om);
     }
-    Px[H] = S.x[0];
-    Py[H] = S.y[0];
-    // cost (Appendix E-B)
+    Px[H] = S.x;
+    Py[H] = S.y;
+    if (s != 0 || b != 0) return;
+    // cost (Appendix E-B), on slot 0 of side 0
     const float dxg = fabsf(Px[H] - c.goal[0]) - c.tol, dyg = fabsf(Py[H] - c.goal[1]) - c.tol;
     const float Ltarget = relu(dxg) * relu(dxg) + relu(dyg) * relu(dyg);
-    const float Lrot = 1.0f - cosf(S.ph[0] - c.goal[2]);
+    const float Lrot = 1.0f - cosf(S.ph - c.goal[2]);
     float Ltraj = 0.0f;
-    for (int k = 1; k <= H; ++k) {
-        Ltraj += smooth_abs(Px[k - 1] - Px[k], c.ea2) + smooth_abs(Py[k - 1] - Py[k], c.ea2);
-        Ltraj += smooth_abs(Px[k] - Px[H], c.ea2) + smooth_abs(Py[k] - Py[H], c.ea2);
-        Ltraj -= smooth_abs(Px[k - 1] - Px[H], c.ea2) + smooth_abs(Py[k - 1] - Py[H], c.ea2);
+    for (int kk = 1; kk <= H; ++kk) {
+        Ltraj += smooth_abs(Px[kk - 1] - Px[kk], c.ea2) + smooth_abs(Py[kk - 1] - Py[kk], c.ea2);
+        Ltraj += smooth_abs(Px[kk] - Px[H], c.ea2) + smooth_abs(Py[kk] - Py[H], c.ea2);
+        Ltraj -= smooth_abs(Px[kk - 1] - Px[H], c.ea2) + smooth_abs(Py[kk - 1] - Py[H], c.ea2);
     }
     const float C = c.wt * Ltarget + c.wr * Lrot + c.wtr * Ltraj + c.wb * Lbound;
-    if (s == 0) {
-        cost[i] = C;
-        if (status && !isfinite(C)) atomicOr(status, STAMP_STATUS_NONFINITE_COST);
-    }
+    cost[i] = C;
+    if (status && !isfinite(C)) atomicOr(status, STAMP_STATUS_NONFINITE_COST);
 }
 
 // ---------------------------------------------------------------------------
@@ -360,40 +463,47 @@ __device__ __forceinline__ void rollout_adj_lane(const SimConst& c, int N, const
                                                  const float* __restrict__ cost_bar, float cb_scalar,
                                                  float* __restrict__ grad, float* __restrict__ seg,
                                                  uint32_t* status, int64_t lane) {
-    const int i = (int)(lane >> 2);
-    const int s = (int)(lane & 3);
+    constexpr int SL = Slots<B>::SL;
+    const int i = (int)(lane / (4 * SL));
+    const int r = (int)(lane % (4 * SL));
+    const int s = r / SL, b = r % SL;
+    const bool real = b < B;
+    const int64_t slot = ((int64_t)4 * i + s) * B + b;
+    const int64_t slot0 = ((int64_t)4 * i + s) * B;  // block 0 of this sub-rollout
+    const int64_t lslot = real ? slot : slot0;        // idle slots read block 0's data
     const int H = c.H, T = c.T;
     const int64_t stride = 6 * B * g.lanes;  // floats per tape entry
+    const BlkConst<B> k = blk_const<B>(c, b);
 
     // entry index of each phase start
     int ent[kMaxPushes];
     {
         int e = 0;
-        for (int k = 0; k < H; ++k) {
-            const int tk = phase_start(k, T, H), tk1 = phase_start(k + 1, T, H);
-            ent[k] = (g.ckpt == 0) ? tk : e;
+        for (int kk = 0; kk < H; ++kk) {
+            const int tk = phase_start(kk, T, H), tk1 = phase_start(kk + 1, T, H);
+            ent[kk] = (g.ckpt == 0) ? tk : e;
             if (g.ckpt) e += (tk1 - tk + g.ckpt - 1) / g.ckpt;
         }
     }
     // phase-start positions P_k and the final block-0 pose
     float Px[kMaxPushes + 1], Py[kMaxPushes + 1];
-    for (int k = 0; k < H; ++k) {
-        Px[k] = tape[ent[k] * stride + lane * 6 * B + 0];
-        Py[k] = tape[ent[k] * stride + lane * 6 * B + 1];
+    for (int kk = 0; kk < H; ++kk) {
+        Px[kk] = tape[ent[kk] * stride + slot0 * 6 + 0];
+        Py[kk] = tape[ent[kk] * stride + slot0 * 6 + 1];
     }
     float phT;
     {
         const float z = side_weight(theta, N, i, H - 1, s);
-        const float* e = tape + g.ends_off + (int64_t)(H - 1) * stride + lane * 6 * B;
-        Px[H] = quad_sum(z * e[0]);
-        Py[H] = quad_sum(z * e[1]);
-        phT = quad_sum(z * e[2]);
+        const float* e = tape + g.ends_off + (int64_t)(H - 1) * stride + slot0 * 6;
+        Px[H] = side_sum<SL>(z * e[0]);
+        Py[H] = side_sum<SL>(z * e[1]);
+        phT = side_sum<SL>(z * e[2]);
     }
     const float cb = cost_bar ? cost_bar[i] : cb_scalar;
 
     // dC/dP_k and dC/dphi_T, scaled by cost_bar
     float Pxb[kMaxPushes + 1], Pyb[kMaxPushes + 1];
-    for (int k = 0; k <= H; ++k) Pxb[k] = Pyb[k] = 0.0f;
+    for (int kk = 0; kk <= H; ++kk) Pxb[kk] = Pyb[kk] = 0.0f;
     {
         const float ux = Px[H] - c.goal[0], uy = Py[H] - c.goal[1];
         Pxb[H] += cb * c.wt * 2.0f * relu(fabsf(ux) - c.tol) * copysignf(1.0f, ux);
@@ -401,84 +511,82 @@ __device__ __forceinline__ void rollout_adj_lane(const SimConst& c, int N, const
     }
     const float phTb = cb * c.wr * sinf(phT - c.goal[2]);
     const float wtr = cb * c.wtr;
-    for (int k = 1; k <= H; ++k) {
-        float u, d;
-        u = Px[k - 1] - Px[k];  d = wtr * u / smooth_abs(u, c.ea2);  Pxb[k - 1] += d; Pxb[k] -= d;
-        u = Py[k - 1] - Py[k];  d = wtr * u / smooth_abs(u, c.ea2);  Pyb[k - 1] += d; Pyb[k] -= d;
-        u = Px[k] - Px[H];      d = wtr * u / smooth_abs(u, c.ea2);  Pxb[k] += d;     Pxb[H] -= d;
-        u = Py[k] - Py[H];      d = wtr * u / smooth_abs(u, c.ea2);  Pyb[k] += d;     Pyb[H] -= d;
-        u = Px[k - 1] - Px[H];  d = wtr * u / smooth_abs(u, c.ea2);  Pxb[k - 1] -= d; Pxb[H] += d;
-        u = Py[k - 1] - Py[H];  d = wtr * u / smooth_abs(u, c.ea2);  Pyb[k - 1] -= d; Pyb[H] += d;
+    for (int kk = 1; kk <= H; ++kk) {
+        float u, dd;
+        u = Px[kk - 1] - Px[kk];  dd = wtr * u / smooth_abs(u, c.ea2);  Pxb[kk - 1] += dd; Pxb[kk] -= dd;
+        u = Py[kk - 1] - Py[kk];  dd = wtr * u / smooth_abs(u, c.ea2);  Pyb[kk - 1] += dd; Pyb[kk] -= dd;
+        u = Px[kk] - Px[H];       dd = wtr * u / smooth_abs(u, c.ea2);  Pxb[kk] += dd;     Pxb[H] -= dd;
+        u = Py[kk] - Py[H];       dd = wtr * u / smooth_abs(u, c.ea2);  Pyb[kk] += dd;     Pyb[H] -= dd;
+        u = Px[kk - 1] - Px[H];   dd = wtr * u / smooth_abs(u, c.ea2);  Pxb[kk - 1] -= dd; Pxb[H] += dd;
+        u = Py[kk - 1] - Py[H];   dd = wtr * u / smooth_abs(u, c.ea2);  Pyb[kk - 1] -= dd; Pyb[H] += dd;
     }
 
-    // adjoint of S_H
-    State<B> Ls;
-#pragma unroll
-    for (int b = 0; b < B; ++b) Ls.x[b] = Ls.y[b] = Ls.ph[b] = Ls.vx[b] = Ls.vy[b] = Ls.om[b] = 0.0f;
-    Ls.x[0] = Pxb[H];
-    Ls.y[0] = Pyb[H];
-    Ls.ph[0] = phTb;
+    // adjoint of S_H (block 0 carries the cost's terms)
+    Blk Ls;
+    Ls.x = Ls.y = Ls.ph = Ls.vx = Ls.vy = Ls.om = 0.0f;
+    if (b == 0) {
+        Ls.x = Pxb[H];
+        Ls.y = Pyb[H];
+        Ls.ph = phTb;
+    }
 
     Push p;
     side_frame(s, p);
     bool bad = false;
-    for (int k = H - 1; k >= 0; --k) {
-        const int tk = phase_start(k, T, H), tk1 = phase_start(k + 1, T, H);
+    for (int kk = H - 1; kk >= 0; --kk) {
+        const int tk = phase_start(kk, T, H), tk1 = phase_start(kk + 1, T, H);
         const float invL = 1.0f / (float)(tk1 - tk);
-        const float z = side_weight(theta, N, i, k, s);
-        const float o = theta[(int64_t)(6 * k + 4) * N + i];
-        const float D = theta[(int64_t)(6 * k + 5) * N + i];
+        const float z = side_weight(theta, N, i, kk, s);
+        const float o = theta[(int64_t)(6 * kk + 4) * N + i];
+        const float D = theta[(int64_t)(6 * kk + 5) * N + i];
         // phase end: S_{k+1} = sum_s z_s X_s
-        State<B> Xe, L;
-        load_state(Xe, tape + g.ends_off + (int64_t)k * stride, lane);
-        float zb = 0.0f;
-#pragma unroll
-        for (int b = 0; b < B; ++b) {
-            zb += Ls.x[b] * Xe.x[b] + Ls.y[b] * Xe.y[b] + Ls.ph[b] * Xe.ph[b] + Ls.vx[b] * Xe.vx[b] +
-                  Ls.vy[b] * Xe.vy[b] + Ls.om[b] * Xe.om[b];
-            L.x[b] = z * Ls.x[b];
-            L.y[b] = z * Ls.y[b];
-            L.ph[b] = z * Ls.ph[b];
-            L.vx[b] = z * Ls.vx[b];
-            L.vy[b] = z * Ls.vy[b];
-            L.om[b] = z * Ls.om[b];
-        }
-        const float ab = z * (zb - quad_sum(z * zb));  // softmax VJP
-        // anchor of the phase
-        const float* ea = tape + ent[k] * stride + lane * 6 * B;
+        Blk Xe, L;
+        load_blk(Xe, tape + g.ends_off + (int64_t)kk * stride, lslot);
+        const float zp = Ls.x * Xe.x + Ls.y * Xe.y + Ls.ph * Xe.ph + Ls.vx * Xe.vx + Ls.vy * Xe.vy + Ls.om * Xe.om;
+        const float zb = slot_sum<SL>(real ? zp : 0.0f);
+        L.x = z * Ls.x;
+        L.y = z * Ls.y;
+        L.ph = z * Ls.ph;
+        L.vx = z * Ls.vx;
+        L.vy = z * Ls.vy;
+        L.om = z * Ls.om;
+        const float ab = z * (zb - side_sum<SL>(z * zb));  // softmax VJP
+        // anchor of the phase (block 0's pose, on slot 0)
+        Blk A;
+        load_blk(A, tape + ent[kk] * stride, lslot);
         Anchor an;
-        phase_push(c, ea[0], ea[1], ea[2], o, D, p, an);
+        phase_push(c, A.x, A.y, A.ph, o, D, p, an);
         float P0xb = 0.0f, P0yb = 0.0f, Vxb = 0.0f, Vyb = 0.0f;
         if (g.ckpt == 0) {
             // reverse sweep over the full tape; the next (earlier) state is
             // fetched while the current step is reversed
-            State<B> Xn;
-            load_state(Xn, tape + (int64_t)(tk1 - 1) * stride, lane);
+            Blk Xn;
+            load_blk(Xn, tape + (int64_t)(tk1 - 1) * stride, lslot);
             for (int t = tk1 - 1; t >= tk; --t) {
-                const State<B> X = Xn;
-                if (t > tk) load_state(Xn, tape + (int64_t)(t - 1) * stride, lane);
-                step_reverse<B>(c, X, L, p, push_profile((float)(t - tk + 1) * invL), P0xb, P0yb, Vxb, Vyb);
+                const Blk X = Xn;
+                if (t > tk) load_blk(Xn, tape + (int64_t)(t - 1) * stride, lslot);
+                step_reverse<B>(c, k, b, X, L, p, push_profile((float)(t - tk + 1) * invL), P0xb, P0yb, Vxb, Vyb);
             }
         } else {
             const int nseg = (tk1 - tk + g.ckpt - 1) / g.ckpt;
             for (int j = nseg - 1; j >= 0; --j) {
                 const int ts = tk + j * g.ckpt;
                 const int te = min(ts + g.ckpt, tk1);
-                State<B> X;
-                load_state(X, tape + (int64_t)(ent[k] + j) * stride, lane);
+                Blk X;
+                load_blk(X, tape + (int64_t)(ent[kk] + j) * stride, lslot);
                 for (int t = ts; t < te; ++t) {  // replay the segment
-                    store_state(X, seg + (int64_t)(t - ts) * stride, lane);
-                    step_forward<B>(c, X, p, push_profile((float)(t - tk + 1) * invL));
+                    if (real) store_blk(X, seg + (int64_t)(t - ts) * stride, slot);
+                    step_forward<B>(c, k, b, X, p, push_profile((float)(t - tk + 1) * invL));
                 }
                 for (int t = te - 1; t >= ts; --t) {
-                    load_state(X, seg + (int64_t)(t - ts) * stride, lane);
-                    step_reverse<B>(c, X, L, p, push_profile((float)(t - tk + 1) * invL), P0xb, P0yb, Vxb,
+                    if (real) load_blk(X, seg + (int64_t)(t - ts) * stride, slot);  // a lane reads its own writes
+                    step_reverse<B>(c, k, b, X, L, p, push_profile((float)(t - tk + 1) * invL), P0xb, P0yb, Vxb,
                                     Vyb);
                 }
             }
         }
         // back to the anchor and (o, D): P0 = A + R(A) q0, q0 = (h0 + standoff) n + o t,
-        // V = -D e_A, e_A = R(A) n
+        // V = -D e_A, e_A = R(A) n (meaningful on slot 0, zero elsewhere)
         const float eAx = fmaf(an.cA, p.nx, -(an.sA * p.ny)), eAy = fmaf(an.sA, p.nx, an.cA * p.ny);
         const float Db = -fmaf(Vxb, eAx, Vyb * eAy);
         const float eAxb = -D * Vxb, eAyb = -D * Vyb;
@@ -486,29 +594,29 @@ __device__ __forceinline__ void rollout_adj_lane(const SimConst& c, int N, const
         const float sAb = fmaf(eAyb, p.nx, -(eAxb * p.ny)) + fmaf(P0yb, an.q0x, -(P0xb * an.q0y));
         const float q0xb = fmaf(an.cA, P0xb, an.sA * P0yb), q0yb = fmaf(an.cA, P0yb, -(an.sA * P0xb));
         const float ob = fmaf(q0xb, p.tx, q0yb * p.ty);
-        const float Axb = P0xb, Ayb = P0yb;
         const float Aphb = fmaf(an.cA, sAb, -(an.sA * cAb));
         // adjoint of S_k: the four sub-rollouts share it
-#pragma unroll
-        for (int b = 0; b < B; ++b) {
-            Ls.x[b] = quad_sum(L.x[b]);
-            Ls.y[b] = quad_sum(L.y[b]);
-            Ls.ph[b] = quad_sum(L.ph[b]);
-            Ls.vx[b] = quad_sum(L.vx[b]);
-            Ls.vy[b] = quad_sum(L.vy[b]);
-            Ls.om[b] = quad_sum(L.om[b]);
+        Ls.x = side_sum<SL>(L.x);
+        Ls.y = side_sum<SL>(L.y);
+        Ls.ph = side_sum<SL>(L.ph);
+        Ls.vx = side_sum<SL>(L.vx);
+        Ls.vy = side_sum<SL>(L.vy);
+        Ls.om = side_sum<SL>(L.om);
+        const float Axs = side_sum<SL>(P0xb), Ays = side_sum<SL>(P0yb), Aphs = side_sum<SL>(Aphb);
+        const float obs = side_sum<SL>(ob), Dbs = side_sum<SL>(Db);
+        if (b == 0) {
+            Ls.x += Axs + Pxb[kk];
+            Ls.y += Ays + Pyb[kk];
+            Ls.ph += Aphs;
+            // bound loss on o_k, D_k
+            const float wb2 = 2.0f * cb * c.wb;
+            const float obt = obs + wb2 * relu(fabsf(o) - c.omax) * copysignf(1.0f, o);
+            const float Dbt = Dbs + wb2 * (relu(D - c.dmax) - relu(-D));
+            grad[(int64_t)(6 * kk + s) * N + i] = ab;
+            if (s == 0) grad[(int64_t)(6 * kk + 4) * N + i] = obt;
+            if (s == 1) grad[(int64_t)(6 * kk + 5) * N + i] = Dbt;
+            bad = bad || !isfinite(ab) || !isfinite(obt) || !isfinite(Dbt);
         }
-        Ls.x[0] += quad_sum(Axb) + Pxb[k];
-        Ls.y[0] += quad_sum(Ayb) + Pyb[k];
-        Ls.ph[0] += quad_sum(Aphb);
-        // bound loss on o_k, D_k
-        const float wb2 = 2.0f * cb * c.wb;
-        const float obt = quad_sum(ob) + wb2 * relu(fabsf(o) - c.omax) * copysignf(1.0f, o);
-        const float Dbt = quad_sum(Db) + wb2 * (relu(D - c.dmax) - relu(-D));
-        grad[(int64_t)(6 * k + s) * N + i] = ab;
-        if (s == 0) grad[(int64_t)(6 * k + 4) * N + i] = obt;
-        if (s == 1) grad[(int64_t)(6 * k + 5) * N + i] = Dbt;
-        bad = bad || !isfinite(ab) || !isfinite(obt) || !isfinite(Dbt);
     }
     if (status && bad) atomicOr(status, STAMP_STATUS_NONFINITE_GRAD);
 }
@@ -519,7 +627,7 @@ __global__ __launch_bounds__(kRolloutBlock) void k_rollout_fwd(SimConst c, int N
                                                                float* __restrict__ cost, float* __restrict__ tape,
                                                                TapeGeom g, uint32_t* status) {
     const int64_t lane = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if ((lane >> 2) >= N) return;  // whole quads leave together
+    if (lane / Slots<B>::LANES >= N) return;  // whole particles leave together
     rollout_fwd_lane<B>(c, N, theta, cost, tape, g, status, lane);
 }
 
@@ -530,15 +638,33 @@ __global__ __launch_bounds__(kRolloutBlock) void k_rollout_adj(SimConst c, int N
                                                                float* __restrict__ grad, float* __restrict__ seg,
                                                                uint32_t* status) {
     const int64_t lane = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if ((lane >> 2) >= N) return;
+    if (lane / Slots<B>::LANES >= N) return;
     rollout_adj_lane<B>(c, N, theta, tape, g, cost_bar, cb_scalar, grad, seg, status, lane);
 }
 
 // ---------------------------------------------------------------------------
 // Batched rollouts: one launch over the wave tiles of many problems.  Tile t is
-// (problem p, first particle i0) and covers particles i0..i0+15 (64 lanes); each
-// wave takes tiles in a grid-stride loop.  The block count B of the problem
-// selects the compiled body at run time.
+// (problem p, first particle i0) and covers 64 lanes: 64 / (4 SL) particles
+// (rollout_tile_particles); each wave takes tiles in a grid-stride loop.  The
+// block count B of the problem selects the compiled body at run time.
+template <int B>
+__device__ __forceinline__ void fwd_tile(const ProblemDesc& D, int i0, int l, const float* theta, float* cost,
+                                         float* tape, uint32_t* status) {
+    const int64_t lane = (int64_t)Slots<B>::LANES * i0 + l;
+    if (lane / Slots<B>::LANES >= D.N) return;
+    rollout_fwd_lane<B>(D.c, D.N, theta + D.theta_off, cost + D.cost_off, tape ? tape + D.tape_off : nullptr, D.g,
+                        status, lane);
+}
+
+template <int B>
+__device__ __forceinline__ void adj_tile(const ProblemDesc& D, int i0, int l, const float* theta, const float* tape,
+                                         float cb_scalar, float* grad, float* seg, uint32_t* status) {
+    const int64_t lane = (int64_t)Slots<B>::LANES * i0 + l;
+    if (lane / Slots<B>::LANES >= D.N) return;
+    rollout_adj_lane<B>(D.c, D.N, theta + D.theta_off, tape + D.tape_off, D.g, nullptr, cb_scalar,
+                        grad + D.theta_off, seg + D.seg_off, status, lane);
+}
+
 __global__ __launch_bounds__(256) void k_rollout_fwd_batched(const ProblemDesc* __restrict__ descs,
                                                              const int2* __restrict__ tiles, int ntiles,
                                                              const float* __restrict__ theta, float* __restrict__ cost,
@@ -548,16 +674,11 @@ __global__ __launch_bounds__(256) void k_rollout_fwd_batched(const ProblemDesc* 
     for (int t = blockIdx.x * waves + wave; t < ntiles; t += gridDim.x * waves) {
         const int2 tl = tiles[t];
         const ProblemDesc& D = descs[tl.x];
-        const int64_t lane = 4 * (int64_t)tl.y + l;
-        if ((lane >> 2) >= D.N) continue;
-        const float* th = theta + D.theta_off;
-        float* co = cost + D.cost_off;
-        float* tp = tape ? tape + D.tape_off : nullptr;
         switch (D.c.B) {
-            case 1: rollout_fwd_lane<1>(D.c, D.N, th, co, tp, D.g, status, lane); break;
-            case 2: rollout_fwd_lane<2>(D.c, D.N, th, co, tp, D.g, status, lane); break;
-            case 3: rollout_fwd_lane<3>(D.c, D.N, th, co, tp, D.g, status, lane); break;
-            default: rollout_fwd_lane<4>(D.c, D.N, th, co, tp, D.g, status, lane); break;
+            case 1: fwd_tile<1>(D, tl.y, l, theta, cost, tape, status); break;
+            case 2: fwd_tile<2>(D, tl.y, l, theta, cost, tape, status); break;
+            case 3: fwd_tile<3>(D, tl.y, l, theta, cost, tape, status); break;
+            default: fwd_tile<4>(D, tl.y, l, theta, cost, tape, status); break;
         }
     }
 }
@@ -573,20 +694,16 @@ __global__ __launch_bounds__(256) void k_rollout_adj_batched(const ProblemDesc* 
     for (int t = blockIdx.x * waves + wave; t < ntiles; t += gridDim.x * waves) {
         const int2 tl = tiles[t];
         const ProblemDesc& D = descs[tl.x];
-        const int64_t lane = 4 * (int64_t)tl.y + l;
-        if ((lane >> 2) >= D.N) continue;
-        const float* th = theta + D.theta_off;
-        const float* tp = tape + D.tape_off;
-        float* gr = grad + D.theta_off;
-        float* sg = seg + D.seg_off;
         switch (D.c.B) {
-            case 1: rollout_adj_lane<1>(D.c, D.N, th, tp, D.g, nullptr, cb_scalar, gr, sg, status, lane); break;
-            case 2: rollout_adj_lane<2>(D.c, D.N, th, tp, D.g, nullptr, cb_scalar, gr, sg, status, lane); break;
-            case 3: rollout_adj_lane<3>(D.c, D.N, th, tp, D.g, nullptr, cb_scalar, gr, sg, status, lane); break;
-            default: rollout_adj_lane<4>(D.c, D.N, th, tp, D.g, nullptr, cb_scalar, gr, sg, status, lane); break;
+            case 1: adj_tile<1>(D, tl.y, l, theta, tape, cb_scalar, grad, seg, status); break;
+            case 2: adj_tile<2>(D, tl.y, l, theta, tape, cb_scalar, grad, seg, status); break;
+            case 3: adj_tile<3>(D, tl.y, l, theta, tape, cb_scalar, grad, seg, status); break;
+            default: adj_tile<4>(D, tl.y, l, theta, tape, cb_scalar, grad, seg, status); break;
         }
     }
 }
+
+int rollout_tile_particles(int B) { return 64 / (4 * (B == 1 ? 1 : (B == 2 ? 2 : 4))); }
 
 hipError_t launch_rollout_fwd_batched(const ProblemDesc* descs, const int2* tiles, int ntiles, int block,
                                       int grid, const float* theta, float* cost, float* tape, uint32_t* status,
@@ -608,7 +725,7 @@ hipError_t launch_rollout_adj_batched(const ProblemDesc* descs, const int2* tile
 template <int B>
 static hipError_t launch_fwd_b(const SimConst& c, int N, const float* theta, float* cost, float* tape,
                                const TapeGeom& g, uint32_t* status, hipStream_t st) {
-    const int64_t lanes = 4 * (int64_t)N;
+    const int64_t lanes = (int64_t)Slots<B>::LANES * N;
     const unsigned grid = (unsigned)((lanes + kRolloutBlock - 1) / kRolloutBlock);
     hipLaunchKernelGGL(k_rollout_fwd<B>, dim3(grid), dim3(kRolloutBlock), 0, st, c, N, theta, cost, tape, g,
                        status);
@@ -619,7 +736,7 @@ template <int B>
 static hipError_t launch_adj_b(const SimConst& c, int N, const float* theta, const float* tape,
                                const TapeGeom& g, const float* cost_bar, float cb_scalar, float* grad,
                                float* seg, uint32_t* status, hipStream_t st) {
-    const int64_t lanes = 4 * (int64_t)N;
+    const int64_t lanes = (int64_t)Slots<B>::LANES * N;
     const unsigned grid = (unsigned)((lanes + kRolloutBlock - 1) / kRolloutBlock);
     hipLaunchKernelGGL(k_rollout_adj<B>, dim3(grid), dim3(kRolloutBlock), 0, st, c, N, theta, tape, g, cost_bar,
                        cb_scalar, grad, seg, status);

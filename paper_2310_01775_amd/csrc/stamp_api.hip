@@ -223,7 +223,7 @@ void build_plan(int n, const stamp_scene* scenes, const int32_t* N, int K, float
         sv += align256(D.sv.total);
         snprintf(buf, sizeof buf, "%d/%d/%d/%d;", N[p], s->H, s->B, s->T);
         P.key += buf;
-        for (int i0 = 0; i0 < D.N; i0 += 16) P.roll_tiles.push_back(make_int2(p, i0));
+        for (int i0 = 0; i0 < D.N; i0 += rollout_tile_particles(s->B)) P.roll_tiles.push_back(make_int2(p, i0));
         // median passes over all pairs, for problems whose pairs exceed the sample:
         // every (row block, column chunk) item (items without a pair i < j write
         // zero counts), and (segment, part) of the candidate passes

@@ -222,7 +222,8 @@ SvgdLayout svgd_workspace_layout(int N, int d) {
     L.tiles = nt;
     {
         const uint64_t P = (uint64_t)N * (uint64_t)(N > 0 ? N - 1 : 0) / 2;
-        // the bracket holds about 6.6% of the pairs; slack for partly used blocks
+        // the sample bracket holds about 6.6% of the pairs: P/8 leaves room for
+        // uneven segments (an overflow falls back to passes over every pair)
         uint64_t cap = P / 8 + (uint64_t)kCandSegs * 16384;
         cap = (cap + kCandSegs - 1) / kCandSegs * kCandSegs;
         L.cand_cap = (uint32_t)(cap < 0xffff0000ull ? cap : 0xffff0000ull);
