@@ -107,12 +107,54 @@ __device__ __forceinline__ void load_blk(Blk& X, const float* __restrict__ entry
     X.om = e.y;
 }
 
+// The same at a 32-bit float offset from a wave-uniform entry pointer (a
+// scalar base plus a vector offset in the memory instruction).
+__device__ __forceinline__ void load_blk_at(Blk& X, const float* __restrict__ entry, uint32_t off) {
+    const float2* p = reinterpret_cast<const float2*>(entry + off);
+    const float2 a = p[0], c = p[1], e = p[2];
+    X.x = a.x;
+    X.y = a.y;
+    X.ph = c.x;
+    X.vx = c.y;
+    X.vy = e.x;
+    X.om = e.y;
+}
+
 __device__ __forceinline__ void store_blk(const Blk& X, float* __restrict__ entry, int64_t slot) {
     float2* p = reinterpret_cast<float2*>(entry + slot * 6);
     p[0] = make_float2(X.x, X.y);
     p[1] = make_float2(X.ph, X.vx);
     p[2] = make_float2(X.vy, X.om);
 }
+
+__device__ __forceinline__ void store_blk_at(const Blk& X, float* __restrict__ entry, uint32_t off) {
+    float2* p = reinterpret_cast<float2*>(entry + off);
+    p[0] = make_float2(X.x, X.y);
+    p[1] = make_float2(X.ph, X.vx);
+    p[2] = make_float2(X.vy, X.om);
+}
+
+// Push profile s((j + 1) / L) of step j of a phase: the wave evaluates 64
+// consecutive steps at once (one per lane) and each step reads its value back
+// with readlane, so a step costs one instruction instead of the polynomial.
+// Every pass (forward, replay, reverse) takes the same per-lane expression.
+struct Profile {
+    float invL;
+    int base;
+    float v;
+    __device__ __forceinline__ void reset(float inv) {
+        invL = inv;
+        base = -1;
+    }
+    __device__ __forceinline__ float at(int j) {
+        const int b0 = j & ~63;
+        if (b0 != base) {
+            base = b0;
+            v = push_profile((float)(b0 + 1 + (int)__lane_id()) * invL);
+        }
+        return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), j & 63));
+    }
+};
 
 // Index of the K-th block other than b (increasing order).
 __host__ __device__ constexpr int other_block(int K, int b) { return K < b ? K : K + 1; }
@@ -378,18 +420,22 @@ __device__ __forceinline__ float side_weight(const float* __restrict__ theta, in
 __device__ __forceinline__ float smooth_abs(float u, float ea2) { return sqrtf(u * u + ea2); }
 
 // ---------------------------------------------------------------------------
-// Forward rollout of one lane: particle i, side s, block slot b.  All lanes of
-// a particle must run it together (DPP exchange every step).
+// Forward rollout of one lane: particle i, side s, block slot b.  Every lane of
+// the wave runs it (cross-lane moves and readlane need all lanes): lanes past
+// the last particle repeat particle N-1 and write nothing.
 template <int B>
 __device__ __forceinline__ void rollout_fwd_lane(const SimConst& c, int N, const float* __restrict__ theta,
                                                  float* __restrict__ cost, float* __restrict__ tape,
                                                  const TapeGeom& g, uint32_t* status, int64_t lane) {
     constexpr int SL = Slots<B>::SL;
-    const int i = (int)(lane / (4 * SL));
+    const int64_t iw = lane / (4 * SL);
+    const bool live = iw < N;
+    const int i = live ? (int)iw : N - 1;
     const int r = (int)(lane % (4 * SL));
     const int s = r / SL, b = r % SL;
-    const bool real = b < B;
+    const bool real = b < B && live;  // writes its block's states
     const int64_t slot = ((int64_t)4 * i + s) * B + b;
+    const uint32_t off = (uint32_t)(slot * 6);  // within an entry (< 2^32 floats)
     const int64_t stride = 6 * B * g.lanes;  // floats per tape entry
     const int H = c.H, T = c.T;
     const BlkConst<B> k = blk_const<B>(c, b);
@@ -417,18 +463,28 @@ __device__ __forceinline__ void rollout_fwd_lane(const SimConst& c, int N, const
         Lbound += relu(fabsf(o) - c.omax) * relu(fabsf(o) - c.omax) + relu(-D) * relu(-D) +
                   relu(D - c.dmax) * relu(D - c.dmax);
         Blk X = S;
-        for (int t = tk; t < tk1; ++t) {
-            if (tape && real) {
-                if (g.ckpt == 0) {
-                    store_blk(X, tape + (int64_t)t * stride, slot);
-                } else if ((t - tk) % g.ckpt == 0) {
-                    store_blk(X, tape + entry * stride, slot);
-                }
+        Profile prof;
+        prof.reset(invL);
+        const int nst = tk1 - tk;
+        if (tape && g.ckpt == 0) {
+            float* e = tape + (int64_t)tk * stride;
+            for (int j = 0; j < nst; ++j, e += stride) {
+                if (real) store_blk_at(X, e, off);
+                step_forward<B>(c, k, b, X, p, prof.at(j));
             }
-            if (g.ckpt != 0 && (t - tk) % g.ckpt == 0) ++entry;
-            step_forward<B>(c, k, b, X, p, push_profile((float)(t - tk + 1) * invL));
+        } else {
+            int until = 0;  // steps to the next checkpoint
+            for (int j = 0; j < nst; ++j) {
+                if (tape && until == 0) {
+                    if (real) store_blk_at(X, tape + entry * stride, off);
+                    ++entry;
+                    until = g.ckpt;
+                }
+                --until;
+                step_forward<B>(c, k, b, X, p, prof.at(j));
+            }
         }
-        if (tape && real) store_blk(X, tape + g.ends_off + (int64_t)kk * stride, slot);
+        if (tape && real) store_blk_at(X, tape + g.ends_off + (int64_t)kk * stride, off);
         // phase mixture over the sides
         S.x = side_sum<SL>(z * X.x);
         S.y = side_sum<SL>(z * X.y);
@@ -439,7 +495,7 @@ __device__ __forceinline__ void rollout_fwd_lane(const SimConst& c, int N, const
     }
     Px[H] = S.x;
     Py[H] = S.y;
-    if (s != 0 || b != 0) return;
+    if (s != 0 || b != 0 || !live) return;
     // cost (Appendix E-B), on slot 0 of side 0
     const float dxg = fabsf(Px[H] - c.goal[0]) - c.tol, dyg = fabsf(Py[H] - c.goal[1]) - c.tol;
     const float Ltarget = relu(dxg) * relu(dxg) + relu(dyg) * relu(dyg);
@@ -464,13 +520,17 @@ __device__ __forceinline__ void rollout_adj_lane(const SimConst& c, int N, const
                                                  float* __restrict__ grad, float* __restrict__ seg,
                                                  uint32_t* status, int64_t lane) {
     constexpr int SL = Slots<B>::SL;
-    const int i = (int)(lane / (4 * SL));
+    const int64_t iw = lane / (4 * SL);
+    const bool live = iw < N;  // lanes past the last particle repeat particle N-1, write nothing
+    const int i = live ? (int)iw : N - 1;
     const int r = (int)(lane % (4 * SL));
     const int s = r / SL, b = r % SL;
-    const bool real = b < B;
+    const bool blk = b < B;        // a block slot (not an idle one)
+    const bool real = blk && live;  // writes scratch and results
     const int64_t slot = ((int64_t)4 * i + s) * B + b;
     const int64_t slot0 = ((int64_t)4 * i + s) * B;  // block 0 of this sub-rollout
-    const int64_t lslot = real ? slot : slot0;        // idle slots read block 0's data
+    const int64_t lslot = blk ? slot : slot0;         // idle slots read block 0's data
+    const uint32_t off = (uint32_t)(slot * 6), loff = (uint32_t)(lslot * 6);
     const int H = c.H, T = c.T;
     const int64_t stride = 6 * B * g.lanes;  // floats per tape entry
     const BlkConst<B> k = blk_const<B>(c, b);
@@ -541,9 +601,9 @@ __device__ __forceinline__ void rollout_adj_lane(const SimConst& c, int N, const
         const float D = theta[(int64_t)(6 * kk + 5) * N + i];
         // phase end: S_{k+1} = sum_s z_s X_s
         Blk Xe, L;
-        load_blk(Xe, tape + g.ends_off + (int64_t)kk * stride, lslot);
+        load_blk_at(Xe, tape + g.ends_off + (int64_t)kk * stride, loff);
         const float zp = Ls.x * Xe.x + Ls.y * Xe.y + Ls.ph * Xe.ph + Ls.vx * Xe.vx + Ls.vy * Xe.vy + Ls.om * Xe.om;
-        const float zb = slot_sum<SL>(real ? zp : 0.0f);
+        const float zb = slot_sum<SL>(blk ? zp : 0.0f);
         L.x = z * Ls.x;
         L.y = z * Ls.y;
         L.ph = z * Ls.ph;
@@ -553,35 +613,43 @@ __device__ __forceinline__ void rollout_adj_lane(const SimConst& c, int N, const
         const float ab = z * (zb - side_sum<SL>(z * zb));  // softmax VJP
         // anchor of the phase (block 0's pose, on slot 0)
         Blk A;
-        load_blk(A, tape + ent[kk] * stride, lslot);
+        load_blk_at(A, tape + ent[kk] * stride, loff);
         Anchor an;
         phase_push(c, A.x, A.y, A.ph, o, D, p, an);
         float P0xb = 0.0f, P0yb = 0.0f, Vxb = 0.0f, Vyb = 0.0f;
+        Profile prof;
+        prof.reset(invL);
         if (g.ckpt == 0) {
-            // reverse sweep over the full tape; the next (earlier) state is
-            // fetched while the current step is reversed
-            Blk Xn;
-            load_blk(Xn, tape + (int64_t)(tk1 - 1) * stride, lslot);
-            for (int t = tk1 - 1; t >= tk; --t) {
-                const Blk X = Xn;
-                if (t > tk) load_blk(Xn, tape + (int64_t)(t - 1) * stride, lslot);
-                step_reverse<B>(c, k, b, X, L, p, push_profile((float)(t - tk + 1) * invL), P0xb, P0yb, Vxb, Vyb);
+            // reverse sweep over the full tape; the states of the next two
+            // (earlier) steps are in flight while a step is reversed
+            const float* base = tape + (int64_t)tk * stride;  // step j's entry: base + j stride
+            int j = tk1 - tk - 1;
+            Blk XA, XB;
+            load_blk_at(XA, base + (int64_t)j * stride, loff);
+            if (j >= 1) load_blk_at(XB, base + (int64_t)(j - 1) * stride, loff);
+            for (; j >= 1; j -= 2) {
+                Blk X = XA;
+                if (j >= 2) load_blk_at(XA, base + (int64_t)(j - 2) * stride, loff);
+                step_reverse<B>(c, k, b, X, L, p, prof.at(j), P0xb, P0yb, Vxb, Vyb);
+                X = XB;
+                if (j >= 3) load_blk_at(XB, base + (int64_t)(j - 3) * stride, loff);
+                step_reverse<B>(c, k, b, X, L, p, prof.at(j - 1), P0xb, P0yb, Vxb, Vyb);
             }
+            if (j == 0) step_reverse<B>(c, k, b, XA, L, p, prof.at(0), P0xb, P0yb, Vxb, Vyb);
         } else {
             const int nseg = (tk1 - tk + g.ckpt - 1) / g.ckpt;
-            for (int j = nseg - 1; j >= 0; --j) {
-                const int ts = tk + j * g.ckpt;
-                const int te = min(ts + g.ckpt, tk1);
+            for (int q = nseg - 1; q >= 0; --q) {
+                const int js = q * g.ckpt;
+                const int je = min(js + g.ckpt, tk1 - tk);
                 Blk X;
-                load_blk(X, tape + (int64_t)(ent[kk] + j) * stride, lslot);
-                for (int t = ts; t < te; ++t) {  // replay the segment
-                    if (real) store_blk(X, seg + (int64_t)(t - ts) * stride, slot);
-                    step_forward<B>(c, k, b, X, p, push_profile((float)(t - tk + 1) * invL));
+                load_blk_at(X, tape + (int64_t)(ent[kk] + q) * stride, loff);
+                for (int j = js; j < je; ++j) {  // replay the segment
+                    if (real) store_blk_at(X, seg + (int64_t)(j - js) * stride, off);
+                    step_forward<B>(c, k, b, X, p, prof.at(j));
                 }
-                for (int t = te - 1; t >= ts; --t) {
-                    if (real) load_blk(X, seg + (int64_t)(t - ts) * stride, slot);  // a lane reads its own writes
-                    step_reverse<B>(c, k, b, X, L, p, push_profile((float)(t - tk + 1) * invL), P0xb, P0yb, Vxb,
-                                    Vyb);
+                for (int j = je - 1; j >= js; --j) {
+                    if (real) load_blk_at(X, seg + (int64_t)(j - js) * stride, off);  // a lane reads its own writes
+                    step_reverse<B>(c, k, b, X, L, p, prof.at(j), P0xb, P0yb, Vxb, Vyb);
                 }
             }
         }
@@ -612,10 +680,12 @@ __device__ __forceinline__ void rollout_adj_lane(const SimConst& c, int N, const
             const float wb2 = 2.0f * cb * c.wb;
             const float obt = obs + wb2 * relu(fabsf(o) - c.omax) * copysignf(1.0f, o);
             const float Dbt = Dbs + wb2 * (relu(D - c.dmax) - relu(-D));
-            grad[(int64_t)(6 * kk + s) * N + i] = ab;
-            if (s == 0) grad[(int64_t)(6 * kk + 4) * N + i] = obt;
-            if (s == 1) grad[(int64_t)(6 * kk + 5) * N + i] = Dbt;
-            bad = bad || !isfinite(ab) || !isfinite(obt) || !isfinite(Dbt);
+            if (live) {
+                grad[(int64_t)(6 * kk + s) * N + i] = ab;
+                if (s == 0) grad[(int64_t)(6 * kk + 4) * N + i] = obt;
+                if (s == 1) grad[(int64_t)(6 * kk + 5) * N + i] = Dbt;
+                bad = bad || !isfinite(ab) || !isfinite(obt) || !isfinite(Dbt);
+            }
         }
     }
     if (status && bad) atomicOr(status, STAMP_STATUS_NONFINITE_GRAD);
@@ -627,7 +697,6 @@ __global__ __launch_bounds__(kRolloutBlock) void k_rollout_fwd(SimConst c, int N
                                                                float* __restrict__ cost, float* __restrict__ tape,
                                                                TapeGeom g, uint32_t* status) {
     const int64_t lane = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (lane / Slots<B>::LANES >= N) return;  // whole particles leave together
     rollout_fwd_lane<B>(c, N, theta, cost, tape, g, status, lane);
 }
 
@@ -638,7 +707,6 @@ __global__ __launch_bounds__(kRolloutBlock) void k_rollout_adj(SimConst c, int N
                                                                float* __restrict__ grad, float* __restrict__ seg,
                                                                uint32_t* status) {
     const int64_t lane = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (lane / Slots<B>::LANES >= N) return;
     rollout_adj_lane<B>(c, N, theta, tape, g, cost_bar, cb_scalar, grad, seg, status, lane);
 }
 
@@ -651,7 +719,6 @@ template <int B>
 __device__ __forceinline__ void fwd_tile(const ProblemDesc& D, int i0, int l, const float* theta, float* cost,
                                          float* tape, uint32_t* status) {
     const int64_t lane = (int64_t)Slots<B>::LANES * i0 + l;
-    if (lane / Slots<B>::LANES >= D.N) return;
     rollout_fwd_lane<B>(D.c, D.N, theta + D.theta_off, cost + D.cost_off, tape ? tape + D.tape_off : nullptr, D.g,
                         status, lane);
 }
@@ -660,7 +727,6 @@ template <int B>
 __device__ __forceinline__ void adj_tile(const ProblemDesc& D, int i0, int l, const float* theta, const float* tape,
                                          float cb_scalar, float* grad, float* seg, uint32_t* status) {
     const int64_t lane = (int64_t)Slots<B>::LANES * i0 + l;
-    if (lane / Slots<B>::LANES >= D.N) return;
     rollout_adj_lane<B>(D.c, D.N, theta + D.theta_off, tape + D.tape_off, D.g, nullptr, cb_scalar,
                         grad + D.theta_off, seg + D.seg_off, status, lane);
 }
