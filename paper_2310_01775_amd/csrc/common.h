@@ -63,6 +63,7 @@ constexpr int kMedBins = 2048;   // bins of one interval-select pass
 constexpr int kMedCols = 64;     // columns of an all-pairs work item (rows: med_rows)
 constexpr int kCandSegs = 64;    // candidate buffer segments (one counter each)
 constexpr int kCandParts = 4;    // workgroups per segment of a candidate pass
+constexpr uint32_t kCandSegMin = 16384;  // candidate slots per segment at least
 
 // Median select state (one per problem): the interval [lo, hi] of FP32 bit
 // patterns known to hold the median, its rank inside, the pass bookkeeping,

@@ -22,9 +22,9 @@
 // exact order statistic, independent of scheduling.
 //
 // Problems with at most 2^20 pairs finish after pass 0 in one workgroup of
-// 1024: the candidates are read once into registers, one histogram pass picks
-// a bin, the bin's values move to LDS and the select ends there (or, rarely,
-// histogram passes run over every pair), so their select takes four kernels.
+// 1024 that reads the candidates once into registers and histograms them there
+// (or, rarely, runs the passes over every pair), so their select takes four
+// kernels.
 //
 // An all-pairs work item is (ROWS-row block, 64-column chunk) in a workgroup of
 // 256: each thread keeps its row's coordinates in registers and reads the
@@ -61,10 +61,11 @@ __device__ __forceinline__ uint32_t mix32(uint32_t x) {  // MurmurHash3 finalise
 __host__ __device__ __forceinline__ uint64_t pair_count(int N) { return (uint64_t)N * (uint64_t)(N - 1) / 2; }
 
 // Bin shift so that an interval of `width` bit patterns fits 2048 bins.
+// The smallest s with ceil(width / 2^s) <= 2048, i.e. bitlen(width - 1) - 11.
 __device__ __forceinline__ uint32_t shift_for(uint64_t width) {
-    uint32_t s = 0;
-    while ((width + ((uint64_t)1 << s) - 1) >> s > (uint64_t)kMedBins) ++s;
-    return s;
+    const uint64_t m = width - 1;
+    const int bl = m ? 64 - __clzll((long long)m) : 0;
+    return bl > 11 ? (uint32_t)(bl - 11) : 0u;
 }
 
 // One problem's select workspace.
@@ -159,11 +160,16 @@ __device__ __forceinline__ void set_bandwidth(SelState* sel, int N, uint32_t m2_
 // Sum over the workgroup (every thread gets the total); wt: NT/64 words of LDS.
 template <int NT>
 __device__ __forceinline__ uint32_t wg_sum(uint32_t c, uint32_t* wt) {
+    static_assert(NT % 256 == 0, "wave totals are read four at a time");
     for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
     if ((threadIdx.x & 63) == 0) wt[threadIdx.x >> 6] = c;
     __syncthreads();
     uint32_t t = 0;
-    for (int w = 0; w < NT / 64; ++w) t += wt[w];
+#pragma unroll
+    for (int w = 0; w < NT / 64; w += 4) {
+        const uint4 v = *reinterpret_cast<const uint4*>(&wt[w]);
+        t += (v.x + v.y) + (v.z + v.w);
+    }
     __syncthreads();
     return t;
 }
@@ -171,6 +177,7 @@ __device__ __forceinline__ uint32_t wg_sum(uint32_t c, uint32_t* wt) {
 // Inclusive prefix sum over the workgroup in thread order.
 template <int NT>
 __device__ __forceinline__ uint32_t wg_scan(uint32_t x, uint32_t* wt) {
+    static_assert(NT % 256 == 0, "wave totals are read four at a time");
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     for (int off = 1; off < 64; off <<= 1) {
         const uint32_t y = __shfl_up(x, off);
@@ -179,7 +186,11 @@ __device__ __forceinline__ uint32_t wg_scan(uint32_t x, uint32_t* wt) {
     if (lane == 63) wt[w] = x;
     __syncthreads();
     uint32_t base = 0;
-    for (int q = 0; q < w; ++q) base += wt[q];
+#pragma unroll
+    for (int q = 0; q < NT / 64; q += 4) {  // every wave total at once, 16-byte reads
+        const uint4 t = *reinterpret_cast<const uint4*>(&wt[q]);
+        base += (q + 0 < w ? t.x : 0u) + (q + 1 < w ? t.y : 0u) + (q + 2 < w ? t.z : 0u) + (q + 3 < w ? t.w : 0u);
+    }
     __syncthreads();
     return x + base;
 }
@@ -190,18 +201,19 @@ __device__ __forceinline__ uint32_t wg_scan(uint32_t x, uint32_t* wt) {
 template <int T>
 __device__ __forceinline__ void strided_hist(const uint32_t* __restrict__ a, uint32_t n, int sub, uint32_t lo,
                                              uint32_t hi, uint32_t s, uint32_t* lh) {
+    const uint32_t w = hi - lo;  // x in [lo, hi] iff x - lo <= w (unsigned)
     uint32_t e = (uint32_t)sub;
     for (; e + 7 * T < n; e += 8 * T) {
         uint32_t x[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) x[u] = a[e + T * u];
+        for (int u = 0; u < 8; ++u) x[u] = a[e + T * u] - lo;
 #pragma unroll
         for (int u = 0; u < 8; ++u)
-            if (x[u] >= lo && x[u] <= hi) atomicAdd(&lh[(x[u] - lo) >> s], 1u);
+            if (x[u] <= w) atomicAdd(&lh[x[u] >> s], 1u);
     }
     for (; e < n; e += T) {
-        const uint32_t x = a[e];
-        if (x >= lo && x <= hi) atomicAdd(&lh[(x - lo) >> s], 1u);
+        const uint32_t x = a[e] - lo;
+        if (x <= w) atomicAdd(&lh[x >> s], 1u);
     }
 }
 
@@ -273,7 +285,7 @@ __device__ void sample_select_body(const MedView& v, int exact, float* h_out) {
     constexpr int NT = kSelThreads;
     __shared__ uint32_t xs[kMedSample];
     __shared__ uint32_t lh[kMedBins];
-    __shared__ uint32_t wt[NT / 64];
+    __shared__ __align__(16) uint32_t wt[NT / 64];
     __shared__ uint32_t part[4];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     SelState* sel = v.sel;
@@ -332,25 +344,15 @@ __device__ void sample_select_body(const MedView& v, int exact, float* h_out) {
     if (!exact || all) {
         m = wg_select_array<NT>(xs, kMedSample, mn, mx, rank[1], lh, wt, part);
     } else {
-        // bracket ends: the bins holding ranks r0 and r2 after two histogram
-        // passes (at least as wide as the sample's exact quantiles); the
-        // first pass is shared
+        // bracket ends: the bins of one histogram of the sample's range that
+        // hold ranks r0 and r2 (at least as wide as the sample's exact
+        // quantiles, by at most a bin, 1/2048 of the range, on each side)
         uint32_t a0 = mn, z0 = mx, r0 = rank[0];
         uint32_t a2 = a0, z2 = z0, r2 = rank[2];
         const uint32_t s1 = shift_for((uint64_t)z0 - a0 + 1);
         wg_hist<NT>(xs, kMedSample, a0, z0, s1, lh);
         wg_narrow<NT>(lh, wt, part, s1, a0, z0, r0, false);
         wg_narrow<NT>(lh, wt, part, s1, a2, z2, r2, true);
-        if (a0 < z0) {
-            const uint32_t s2 = shift_for((uint64_t)z0 - a0 + 1);
-            wg_hist<NT>(xs, kMedSample, a0, z0, s2, lh);
-            wg_narrow<NT>(lh, wt, part, s2, a0, z0, r0);
-        }
-        if (a2 < z2) {
-            const uint32_t s2 = shift_for((uint64_t)z2 - a2 + 1);
-            wg_hist<NT>(xs, kMedSample, a2, z2, s2, lh);
-            wg_narrow<NT>(lh, wt, part, s2, a2, z2, r2);
-        }
         lo0 = a0;
         hi2 = z2;
     }
@@ -630,22 +632,20 @@ __device__ void med_select_body(const MedView& v, float* h_out) {
 
 // Small problems (P <= kFinishPairs): everything after pass 0 in one
 // workgroup of kFinishThreads.  The counts decide where rank k lies.  Inside
-// the bracket (and without overflow) one histogram pass over the candidates
-// narrows it to a bin; a second pass copies that bin's values into LDS (when
-// they fit), where the select ends.  Else (rare) histogram passes run over
-// every pair, recomputed here.
+// the bracket (and without overflow) the candidates are read into registers
+// once and histogram passes over them narrow the interval (two, for the usual
+// bracket width).  Else (rare) histogram passes run over every pair,
+// recomputed here.
 constexpr uint64_t kFinishPairs = 1ull << 20;
 constexpr int kFinishThreads = 1024;
-constexpr uint32_t kFinishLds = 8192;   // values of the final bin kept in LDS
-constexpr int kFinishRegs = 64;         // candidate slots per thread held in registers
+constexpr int kFinishRegs = 40;         // candidate slots per thread held in registers
 constexpr int kSegThreads = kFinishThreads / kCandSegs;
 static_assert(kFinishThreads % kCandSegs == 0, "whole thread groups per candidate segment");
 
 __device__ void med_finish_body(const MedView& v, const float* __restrict__ theta, float* h_out) {
     constexpr int NT = kFinishThreads;
     __shared__ uint32_t lh[kMedBins];
-    __shared__ uint32_t buf[kFinishLds];
-    __shared__ uint32_t wt[NT / 64];
+    __shared__ __align__(16) uint32_t wt[NT / 64];
     __shared__ uint32_t part[4];
     const int tid = threadIdx.x;
     SelState* sel = v.sel;
@@ -672,49 +672,28 @@ __device__ void med_finish_body(const MedView& v, const float* __restrict__ thet
         // the first kFinishRegs * kSegThreads slots of each segment stay in
         // registers (one load round trip); longer segments stream the rest
         constexpr uint32_t nreg = kFinishRegs * kSegThreads;
+        // slots past n lie inside the segment (at least kCandSegMin slots) and
+        // read as sentinels
+        static_assert(kFinishRegs * kSegThreads <= (int)kCandSegMin, "register slots inside every segment");
         uint32_t xr[kFinishRegs];
 #pragma unroll
-        for (int u = 0; u < kFinishRegs; ++u) {
-            const uint32_t e = (uint32_t)(sub + kSegThreads * u);
-            xr[u] = e < n ? sb[e] : kSentinel;
-        }
-        auto hist_pass = [&](uint32_t s) {
+        for (int u = 0; u < kFinishRegs; ++u) xr[u] = sb[sub + kSegThreads * u];
 #pragma unroll
-            for (int u = 0; u < kFinishRegs; ++u)
-                if (xr[u] >= lo && xr[u] <= hi) atomicAdd(&lh[(xr[u] - lo) >> s], 1u);
+        for (int u = 0; u < kFinishRegs; ++u)
+            if ((uint32_t)(sub + kSegThreads * u) >= n) xr[u] = kSentinel;
+        auto hist_pass = [&](uint32_t s) {
+            const uint32_t w = hi - lo;
+#pragma unroll
+            for (int u = 0; u < kFinishRegs; ++u) {
+                const uint32_t dx = xr[u] - lo;  // in [lo, hi] iff dx <= hi - lo (unsigned)
+                if (dx <= w) atomicAdd(&lh[dx >> s], 1u);
+            }
             if (n > nreg) strided_hist<kSegThreads>(sb + nreg, n - nreg, sub, lo, hi, s, lh);
         };
-        uint32_t s = shift_for((uint64_t)hi - lo + 1);
-        hist_pass(s);
-        const uint32_t nbin = wg_narrow<NT>(lh, wt, part, s, lo, hi, r);
-        if (lo < hi && nbin <= kFinishLds) {
-            // copy the bin's values into LDS: per wave, one slot reservation
-            if (tid == 0) part[3] = 0;
-            __syncthreads();
-            const int lane = tid & 63;
-            const uint64_t lt = (1ull << lane) - 1ull;
-            auto keep = [&](uint32_t x) {
-                const bool in = x >= lo && x <= hi;
-                const uint64_t mi = __ballot(in);
-                if (mi) {
-                    const int lead = __ffsll((unsigned long long)mi) - 1;
-                    uint32_t base = 0;
-                    if (lane == lead) base = atomicAdd(&part[3], (uint32_t)__popcll(mi));
-                    base = __shfl(base, lead);
-                    if (in) buf[base + (uint32_t)__popcll(mi & lt)] = x;
-                }
-            };
-#pragma unroll
-            for (int u = 0; u < kFinishRegs; ++u) keep(xr[u]);
-            for (uint32_t e = nreg + (uint32_t)sub; e < n; e += kSegThreads) keep(sb[e]);
-            __syncthreads();
-            lo = wg_select_array<NT>(buf, nbin, lo, hi, r, lh, wt, part);
-        } else {
-            while (lo < hi) {
-                s = shift_for((uint64_t)hi - lo + 1);
-                hist_pass(s);
-                wg_narrow<NT>(lh, wt, part, s, lo, hi, r);
-            }
+        while (lo < hi) {  // each pass narrows the width 2048-fold: two passes, usually
+            const uint32_t s = shift_for((uint64_t)hi - lo + 1);
+            hist_pass(s);
+            wg_narrow<NT>(lh, wt, part, s, lo, hi, r);
         }
         if (tid == 0) set_bandwidth(sel, N, lo, h_out);
         return;

@@ -224,7 +224,7 @@ SvgdLayout svgd_workspace_layout(int N, int d) {
         const uint64_t P = (uint64_t)N * (uint64_t)(N > 0 ? N - 1 : 0) / 2;
         // the sample bracket holds about 6.6% of the pairs: P/8 leaves room for
         // uneven segments (an overflow falls back to passes over every pair)
-        uint64_t cap = P / 8 + (uint64_t)kCandSegs * 16384;
+        uint64_t cap = P / 8 + (uint64_t)kCandSegs * kCandSegMin;
         cap = (cap + kCandSegs - 1) / kCandSegs * kCandSegs;
         L.cand_cap = (uint32_t)(cap < 0xffff0000ull ? cap : 0xffff0000ull);
         L.med_rows = N > 4096 ? 256 : 64;  // small problems: more, smaller items
