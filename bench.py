@@ -114,10 +114,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--workload", default="plain", choices=["plain", "batched", "long", "surrogate"],
+    ap.add_argument("--workload", default="plain", choices=["plain", "batched", "long", "surrogate", "refine"],
                     help="plain: the metric's workload; batched: 64 uneven problems in one graph-replayed "
                          "solve; long: checkpointed differentiation (report only); surrogate: the learned "
-                         "surrogate form against the plain method at N=16384 (report only)")
+                         "surrogate form against the plain method at N=16384 (report only); refine: SVGD "
+                         "alone against SVGD followed by SGD refinement, with the plan read-out (report only)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -149,6 +150,8 @@ def main():
         return bench_long(args)
     if args.workload == "surrogate":
         return bench_surrogate(args)
+    if args.workload == "refine":
+        return bench_refine(args)
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     cfg = W.CONFIGS[2]
@@ -414,6 +417,49 @@ def bench_surrogate(args):
         out[name]["speedup_vs_plain"] = out["plain"]["wall_s"] / out[name]["wall_s"]
         out[name]["median_cost_vs_plain"] = (out[name]["final_true_cost"]["median"] /
                                              out["plain"]["final_true_cost"]["median"])
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+def bench_refine(args):
+    """Algorithm 1's two phases on the N=1024, B=3, H=3, T=200 scene: 300 SVGD
+    iterations against 200 SVGD + 100 SGD refinement iterations (the paper's
+    question whether refinement is needed), each one graph-replayed
+    stamp_solve, then the plan read-out: the discrete plan of every particle,
+    the cost of executing it, and the solutions (executed cost below the
+    threshold) per plan."""
+    import numpy as np
+    import torch
+
+    import paper_2310_01775_amd as S
+    import workloads as W
+    from paper_2310_01775_amd import readout
+
+    scene, w, th = W.config_problem(2)
+    N = th.shape[0]
+    ctx = S.Context(0)
+    sc, cw = S.make_scene(scene), S.make_cost(w)
+    lr = W.DEFAULT_ADAM["lr"]
+    status = ctx.status_word()
+    out = {"workload": f"refinement: N={N}, B=3, H=3 (d=18), T=200 steps of dt=0.005, 300 iterations, "
+                       f"solutions = executed discrete-plan cost < {W.SOLUTION_COST}"}
+    for name, (it, sgd) in (("svgd300", (300, 0)), ("svgd200_sgd100", (200, 100))):
+        cfg = S.make_cfg(it, lr=lr, sgd_iters=sgd)
+        work = ctx._bytes(ctx.solve_workspace_bytes([sc], [N], cfg))
+        for rep in range(2):  # the first run tunes and captures
+            theta = S.soa(th)
+            m, v = torch.zeros_like(theta), torch.zeros_like(theta)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            cost = ctx.solve([sc], [cw], [N], cfg, theta, m, v, workspace=work, status=status)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t
+        c = cost.double()
+        rd = readout.report(ctx, sc, cw, theta, W.SOLUTION_COST)
+        out[name] = {"wall_s": wall, "particle_iters_per_s": N * (it + sgd) / wall,
+                     "relaxed_cost_median": float(c.median()), "relaxed_cost_p10": float(c.quantile(0.1)),
+                     "readout": rd}
+    assert int(status.item()) == 0
     print(json.dumps(out), flush=True)
     ctx.close()
 

@@ -99,7 +99,8 @@ typedef struct stamp_cost_w {
     float target, rot, traj, bound, o_max, d_max, traj_eps;
 } stamp_cost_w;
 
-/* Solver settings (Algorithm 1, SVGD phase, a fixed number of iterations). */
+/* Solver settings (Algorithm 1: an SVGD phase, then an SGD refinement phase,
+ * each a fixed number of iterations). */
 typedef struct stamp_solver_cfg {
     int32_t iters;     /* SVGD iterations (>= 0) */
     int32_t t0;        /* Adam steps already taken (resume); step t = t0+1.. */
@@ -108,7 +109,9 @@ typedef struct stamp_solver_cfg {
     int32_t use_adam;  /* 1: Adam on -phi; 0: plain step */
     float bandwidth;   /* > 0: fixed h; <= 0: median heuristic every iteration */
     int32_t ckpt_every;/* tape mode inside the solve: 0 full tape, K>0 checkpoints */
-    int32_t reserved;
+    int32_t sgd_iters; /* SGD refinement iterations after the SVGD ones (>= 0; Algorithm 1's
+                          second phase, Sec. III-C): the update takes phi = grad log rho of
+                          each particle alone, with the same step rule and step counter */
 } stamp_solver_cfg;
 
 /* ---- context ----------------------------------------------------------- */
@@ -208,8 +211,9 @@ int32_t stamp_adam_step(stamp_ctx* ctx, int64_t n, float* theta, const float* ph
                         float* v, int32_t t, float lr, float beta1, float beta2, float eps,
                         int32_t use_adam, void* stream);
 
-/* Algorithm 1 (SVGD phase) for cfg->iters iterations over n_problems
- * independent problems: rollout -> adjoint -> bandwidth -> phi -> update.
+/* Algorithm 1 for cfg->iters SVGD iterations (rollout -> adjoint -> bandwidth
+ * -> phi -> update), then cfg->sgd_iters SGD iterations (rollout -> adjoint ->
+ * update with phi = grad log rho), over n_problems independent problems.
  * Problem p has N[p] particles and scene scenes[p]; its particles, Adam moments
  * and outputs are packed one after another:
  *   theta, adam_m, adam_v: sum_p 6*H_p*N_p floats, problem p's block [d_p][N_p];
@@ -231,6 +235,19 @@ int32_t stamp_solve(stamp_ctx* ctx, int32_t n_problems, const stamp_scene* scene
                     int32_t* modes_out, float* solve_time_us, void* workspace,
                     size_t ws_bytes, uint32_t* status, void* stream);
 
+
+/* Plan read-out (Algorithm 1's result, Eq. 5): the discrete plan Gamma of
+ * each particle (argmax side per push, lowest index on ties) into modes [H][N]
+ * int32, and the cost of executing that discrete plan with the particle's
+ * offsets and depths into cost [N]: the rollout of theta with each push's
+ * logits replaced by 40 e_Gamma - 20, whose softmax weight of the chosen side
+ * is 1 in FP32.  workspace (>= stamp_readout_workspace_bytes floats' bytes)
+ * holds that plan vector.  Errors: as stamp_rollout_fwd; STAMP_EINVAL for
+ * null modes or cost; STAMP_ENOSPACE if ws_bytes is too small. */
+size_t stamp_readout_workspace_bytes(const stamp_scene* scene, int32_t N);
+int32_t stamp_plan_readout(stamp_ctx* ctx, const stamp_scene* scene, const stamp_cost_w* w, int32_t N,
+                           const float* theta, int32_t* modes, float* cost, void* workspace, size_t ws_bytes,
+                           uint32_t* status, void* stream);
 
 /* ---- learned cost surrogate ------------------------------------------------
  * A network that predicts the rollout part of a plan's cost from the plan and

@@ -79,6 +79,18 @@ def discrete_plan(theta: np.ndarray, H: int) -> np.ndarray:
     return np.argmax(a, axis=2).astype(np.int32)  # argmax returns the first max
 
 
+def discrete_particles(theta: np.ndarray, H: int) -> np.ndarray:
+    """The discrete plans Gamma of theta [N][6H] as particles: each push's logits
+    become 40 e_Gamma - 20 (softmax weight of the chosen side 1 - O(e^-40)),
+    offsets and depths kept."""
+    th = np.array(theta, dtype=np.float64, copy=True)
+    modes = discrete_plan(th, H)
+    for k in range(H):
+        th[:, 6 * k:6 * k + 4] = -20.0
+        th[np.arange(th.shape[0]), 6 * k + modes[:, k]] = 20.0
+    return th
+
+
 def block_inertia(half, mass):
     return mass * (2.0 * half) ** 2 / 6.0
 
@@ -266,6 +278,12 @@ def cost_np(scene, w, theta, **kw):
     """Cost [N] of particles theta [N][d] (numpy in, numpy out)."""
     with torch.no_grad():
         return rollout(scene, w, torch.as_tensor(np.asarray(theta, dtype=np.float64)), **kw)["cost"].numpy()
+
+
+def readout(scene, w, theta):
+    """Plan read-out: (modes [N][H], cost of executing each discrete plan [N])."""
+    H = int(scene["H"])
+    return discrete_plan(theta, H), cost_np(scene, w, discrete_particles(theta, H))
 
 
 def cost_and_grad(scene, w, theta, cost_bar=None):

@@ -85,8 +85,11 @@ def plain_step(theta, phi, lr):
 
 def solve(scene, w, theta0, iters, t0=0, lr=1e-2, beta1=0.9, beta2=0.999, eps=1e-8,
           use_adam=True, fixed_bandwidth=0.0, m0=None, v0=None, grad_fn=None,
-          history=False):
-    """SVGD phase of Algorithm 1 for a fixed number of iterations.
+          history=False, sgd_iters=0):
+    """Algorithm 1 for fixed iteration counts: `iters` SVGD iterations, then
+    `sgd_iters` SGD refinement iterations whose update takes each particle's
+    own gradient of log rho (the second phase of Algorithm 1, Sec. III-C),
+    with the same step rule and a continuing step counter.
 
     grad_fn(theta) -> (cost, dC/dtheta) defaults to the simulator rollout.
     Returns dict(theta, m, v, cost, modes, h, [hist]).
@@ -99,11 +102,14 @@ def solve(scene, w, theta0, iters, t0=0, lr=1e-2, beta1=0.9, beta2=0.999, eps=1e
             return sim.cost_and_grad(scene, w, x)
     hist = []
     h = float("nan")
-    for it in range(iters):
+    for it in range(iters + sgd_iters):
         c, dC = grad_fn(th)
         g = -dC
-        h = bandwidth(th, fixed_bandwidth)
-        phi = g if th.shape[0] == 1 else svgd_phi(th, g, h)
+        if it < iters:
+            h = bandwidth(th, fixed_bandwidth)
+            phi = g if th.shape[0] == 1 else svgd_phi(th, g, h)
+        else:
+            phi = g
         if use_adam:
             th, m, v = adam_step(th, phi, m, v, t0 + it + 1, lr, beta1, beta2, eps)
         else:

@@ -46,7 +46,7 @@ class CostW(C.Structure):
 class SolverCfg(C.Structure):
     _fields_ = [("iters", C.c_int32), ("t0", C.c_int32), ("lr", C.c_float), ("beta1", C.c_float),
                 ("beta2", C.c_float), ("adam_eps", C.c_float), ("use_adam", C.c_int32),
-                ("bandwidth", C.c_float), ("ckpt_every", C.c_int32), ("reserved", C.c_int32)]
+                ("bandwidth", C.c_float), ("ckpt_every", C.c_int32), ("sgd_iters", C.c_int32)]
 
 
 class Surrogate(C.Structure):
@@ -71,6 +71,8 @@ _sig = {
     "stamp_set_launch_shape": (_i32, [_vp, _i32, _i32, _i32]),
     "stamp_tape_floats": (_sz, [_P(Scene), _i32, _i32]),
     "stamp_adj_workspace_bytes": (_sz, [_P(Scene), _i32, _i32]),
+    "stamp_readout_workspace_bytes": (_sz, [_P(Scene), _i32]),
+    "stamp_plan_readout": (_i32, [_vp, _P(Scene), _P(CostW), _i32, _vp, _vp, _vp, _vp, _sz, _vp, _vp]),
     "stamp_svgd_workspace_bytes": (_sz, [_i32, _i32]),
     "stamp_solve_workspace_bytes": (_sz, [_i32, _P(Scene), _P(_i32), _P(SolverCfg)]),
     "stamp_rollout_fwd": (_i32, [_vp, _P(Scene), _P(CostW), _i32, _vp, _vp, _vp, _i32, _vp, _vp]),
@@ -137,9 +139,9 @@ def make_cost(w: dict) -> CostW:
 
 
 def make_cfg(iters, t0=0, lr=1e-3, beta1=0.9, beta2=0.999, adam_eps=1e-8, use_adam=True,
-             bandwidth=0.0, ckpt_every=0) -> SolverCfg:
+             bandwidth=0.0, ckpt_every=0, sgd_iters=0) -> SolverCfg:
     return SolverCfg(int(iters), int(t0), lr, beta1, beta2, adam_eps, int(bool(use_adam)), bandwidth,
-                     int(ckpt_every), 0)
+                     int(ckpt_every), int(sgd_iters))
 
 
 def soa(theta_nd, device="cuda") -> torch.Tensor:
@@ -273,6 +275,22 @@ class Context:
         self._check(_lib.stamp_rollout_fwd(self._h, C.byref(scene), C.byref(w), N, _ptr(theta), _ptr(cost),
                                            _ptr(tape), ckpt_every, _ptr(status), _stream(stream)))
         return cost
+
+    def plan_readout(self, scene: Scene, w: CostW, theta: torch.Tensor, modes=None, cost=None, workspace=None,
+                     status=None, stream=None):
+        """stamp_plan_readout: (modes [H][N] int32, cost [N] of the discrete plans)."""
+        N = theta.shape[1]
+        H = int(scene.H)
+        if modes is None:
+            modes = torch.empty((H, N), dtype=torch.int32, device=self.device)
+        if cost is None:
+            cost = torch.empty(N, dtype=torch.float32, device=self.device)
+        if workspace is None:
+            workspace = self._bytes(int(_lib.stamp_readout_workspace_bytes(C.byref(scene), N)))
+        self._check(_lib.stamp_plan_readout(self._h, C.byref(scene), C.byref(w), N, _ptr(theta), _ptr(modes),
+                                            _ptr(cost), _ptr(workspace), workspace.numel(), _ptr(status),
+                                            _stream(stream)))
+        return modes, cost
 
     def rollout_adj(self, scene: Scene, w: CostW, theta: torch.Tensor, tape: torch.Tensor,
                     ckpt_every: int = 0, cost_bar=None, grad=None, workspace=None, status=None, stream=None):

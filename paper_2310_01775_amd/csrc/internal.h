@@ -59,6 +59,7 @@ hipError_t launch_update(int64_t n, float* theta, const float* phi, float* m, fl
 hipError_t launch_modes(int N, int H, const float* theta, int32_t* modes, hipStream_t st);
 
 // tiny device helpers
+hipError_t launch_onehot(int N, int H, const float* theta, float* out, hipStream_t st);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st);
 hipError_t launch_incr(int* p, hipStream_t st);
 

@@ -38,6 +38,9 @@ struct stamp_ctx {
     // the same for the surrogate-phase iteration
     hipGraphExec_t graph_sur = nullptr;
     std::string graph_sur_key;
+    // the same for the SGD refinement iteration
+    hipGraphExec_t graph_sgd = nullptr;
+    std::string graph_sgd_key;
 };
 
 namespace stamp {
@@ -366,6 +369,7 @@ void stamp_destroy(stamp_ctx* ctx) {
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
     if (ctx->graph) (void)hipGraphExecDestroy(ctx->graph);
     if (ctx->graph_sur) (void)hipGraphExecDestroy(ctx->graph_sur);
+    if (ctx->graph_sgd) (void)hipGraphExecDestroy(ctx->graph_sgd);
     if (ctx->ev_in) (void)hipEventDestroy(ctx->ev_in);
     if (ctx->ev_out) (void)hipEventDestroy(ctx->ev_out);
     if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
@@ -432,6 +436,30 @@ int32_t stamp_rollout_fwd(stamp_ctx* ctx, const stamp_scene* scene, const stamp_
     const TapeGeom g = tape_geom(scene, N, ckpt_every);
     hipError_t e = launch_rollout_fwd(c, N, theta, cost, tape, g, status, (hipStream_t)stream);
     return e == hipSuccess ? STAMP_OK : hip_fail(ctx, e, "rollout_fwd");
+}
+
+size_t stamp_readout_workspace_bytes(const stamp_scene* scene, int32_t N) {
+    if (!scene || N < 1 || scene->H < 1 || scene->H > kMaxPushes) return 0;
+    return (size_t)6 * scene->H * N * sizeof(float);
+}
+
+int32_t stamp_plan_readout(stamp_ctx* ctx, const stamp_scene* scene, const stamp_cost_w* w, int32_t N,
+                           const float* theta, int32_t* modes, float* cost, void* workspace, size_t ws_bytes,
+                           uint32_t* status, void* stream) {
+    if (!ctx) return STAMP_EINVAL;
+    if (!theta || !modes || !cost) return fail(ctx, STAMP_EINVAL, "null theta, modes or cost");
+    if (N < 1) return fail(ctx, STAMP_EINVAL, "N=%d < 1", N);
+    SimConst c;
+    int r = derive(ctx, scene, w, &c);
+    if (r) return r;
+    const size_t need = stamp_readout_workspace_bytes(scene, N);
+    if (!workspace || ws_bytes < need) return fail(ctx, STAMP_ENOSPACE, "read-out workspace %zu < %zu", ws_bytes, need);
+    hipStream_t st = (hipStream_t)stream;
+    float* plan = (float*)workspace;
+    hipError_t e = launch_modes(N, scene->H, theta, modes, st);
+    if (e == hipSuccess) e = launch_onehot(N, scene->H, theta, plan, st);
+    if (e == hipSuccess) e = launch_rollout_fwd(c, N, plan, cost, nullptr, tape_geom(scene, N, 0), status, st);
+    return e == hipSuccess ? STAMP_OK : hip_fail(ctx, e, "plan_readout");
 }
 
 int32_t stamp_rollout_adj(stamp_ctx* ctx, const stamp_scene* scene, const stamp_cost_w* w, int32_t N,
@@ -512,7 +540,8 @@ static int32_t solve_impl(stamp_ctx* ctx, int32_t n_problems, const stamp_scene*
     if (!ctx) return STAMP_EINVAL;
     if (n_problems < 1 || !scenes || !w || !N || !cfg) return fail(ctx, STAMP_EINVAL, "null problem arrays");
     if (!theta || !cost_out) return fail(ctx, STAMP_EINVAL, "null theta or cost_out");
-    if (cfg->iters < 0 || cfg->ckpt_every < 0 || cfg->t0 < 0) return fail(ctx, STAMP_EINVAL, "bad solver cfg");
+    if (cfg->iters < 0 || cfg->ckpt_every < 0 || cfg->t0 < 0 || cfg->sgd_iters < 0)
+        return fail(ctx, STAMP_EINVAL, "bad solver cfg");
     if (cfg->use_adam && (!adam_m || !adam_v)) return fail(ctx, STAMP_EINVAL, "Adam needs m and v");
     if (!isfinite(cfg->lr) || !isfinite(cfg->bandwidth)) return fail(ctx, STAMP_EINVAL, "non-finite lr/bandwidth");
     if (cfg->use_adam && !(cfg->beta1 >= 0 && cfg->beta1 < 1 && cfg->beta2 >= 0 && cfg->beta2 < 1 &&
@@ -624,7 +653,7 @@ static int32_t solve_impl(stamp_ctx* ctx, int32_t n_problems, const stamp_scene*
         return t.roll_grid > 0 ? std::min(t.roll_grid, full) : full;
     };
 
-    if (!have_tune && ctx->autotune && cfg->iters > 0) {
+    if (!have_tune && ctx->autotune && cfg->iters + cfg->sgd_iters > 0) {
         {
             // time the rollout shapes and the contraction row blocks on this batch
             hipEvent_t a, b;
@@ -696,6 +725,20 @@ static int32_t solve_impl(stamp_ctx* ctx, int32_t n_problems, const stamp_scene*
             return r;
         if ((r = launch_svgd_batched(B, d_desc, theta, d_grad, d_phi, d_svgd, status, st)) != hipSuccess) return r;
         if ((r = launch_update(P.n_theta, theta, d_phi, adam_m, adam_v, cfg->t0, d_ctr, cfg->lr, cfg->beta1,
+                               cfg->beta2, cfg->adam_eps, cfg->use_adam, st)) != hipSuccess)
+            return r;
+        return launch_incr(d_ctr, st);
+    };
+    // one SGD refinement iteration: the update takes phi = grad log rho
+    auto sgd_iteration = [&]() -> hipError_t {
+        hipError_t r;
+        if ((r = launch_rollout_fwd_batched(d_desc, d_roll, ntiles, tune.roll_block, rgrid, theta,
+                                            (float*)(ws + P.cost_off), d_tape, status, st)) != hipSuccess)
+            return r;
+        if ((r = launch_rollout_adj_batched(d_desc, d_roll, ntiles, tune.roll_block, rgrid, theta, d_tape, -1.0f,
+                                            d_grad, d_seg, status, st)) != hipSuccess)
+            return r;
+        if ((r = launch_update(P.n_theta, theta, d_grad, adam_m, adam_v, cfg->t0, d_ctr, cfg->lr, cfg->beta1,
                                cfg->beta2, cfg->adam_eps, cfg->use_adam, st)) != hipSuccess)
             return r;
         return launch_incr(d_ctr, st);
@@ -807,6 +850,11 @@ static int32_t solve_impl(stamp_ctx* ctx, int32_t n_problems, const stamp_scene*
         int32_t r = ensure_graph(ctx->graph, ctx->graph_key, full_key, iteration);
         if (r) return r;
         for (int it = run; it < cfg->iters; ++it) STAMP_TRY(hipGraphLaunch(ctx->graph, st), "graph launch");
+    }
+    if (cfg->sgd_iters > 0) {  // refinement: the step counter runs on
+        int32_t r = ensure_graph(ctx->graph_sgd, ctx->graph_sgd_key, full_key, sgd_iteration);
+        if (r) return r;
+        for (int it = 0; it < cfg->sgd_iters; ++it) STAMP_TRY(hipGraphLaunch(ctx->graph_sgd, st), "graph launch");
     }
     // final true cost and discrete plan of every particle
     STAMP_TRY(launch_rollout_fwd_batched(d_desc, d_roll, ntiles, tune.roll_block, rgrid, theta, cost_out, nullptr,

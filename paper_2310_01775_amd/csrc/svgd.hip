@@ -344,6 +344,32 @@ hipError_t launch_modes(int N, int H, const float* theta, int32_t* modes, hipStr
     return hipGetLastError();
 }
 
+// The discrete plan as a particle: logits 40 e_Gamma - 20 per push (Gamma the
+// argmax side, lowest index on ties), offsets and depths copied.
+__global__ void k_onehot(int N, int H, const float* __restrict__ theta, float* __restrict__ out) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= (int64_t)N * H) return;
+    const int k = (int)(e / N), i = (int)(e % N);
+    int best = 0;
+    float bv = theta[(int64_t)(6 * k) * N + i];
+    for (int s = 1; s < kModes; ++s) {
+        const float a = theta[(int64_t)(6 * k + s) * N + i];
+        if (a > bv) {
+            bv = a;
+            best = s;
+        }
+    }
+    for (int s = 0; s < kModes; ++s) out[(int64_t)(6 * k + s) * N + i] = s == best ? 20.0f : -20.0f;
+    out[(int64_t)(6 * k + 4) * N + i] = theta[(int64_t)(6 * k + 4) * N + i];
+    out[(int64_t)(6 * k + 5) * N + i] = theta[(int64_t)(6 * k + 5) * N + i];
+}
+
+hipError_t launch_onehot(int N, int H, const float* theta, float* out, hipStream_t st) {
+    const int64_t n = (int64_t)N * H;
+    hipLaunchKernelGGL(k_onehot, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, N, H, theta, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st) {
     hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, v, n);
     return hipGetLastError();

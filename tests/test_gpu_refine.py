@@ -1,0 +1,98 @@
+"""Algorithm 1's SGD refinement phase and the plan read-out, through the C ABI.
+
+The refinement iterations of stamp_solve must equal the per-call loop (rollout,
+adjoint, update with phi = grad log rho) bit for bit and follow the FP64
+oracle's two-phase solve to the solve's bar; the read-out's discrete plans
+must equal the oracle's argmax exactly and their executed costs agree to the
+rollout's FP32 bar (1e-4 relative)."""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import sim, svgd
+
+pytestmark = pytest.mark.gpu
+
+
+def _loop(ctx, S, scene, w, th, iters, sgd_iters, lr):
+    sc, cw = S.make_scene(scene), S.make_cost(w)
+    N = th.shape[0]
+    theta = S.soa(th)
+    m, v = torch.zeros_like(theta), torch.zeros_like(theta)
+    tape = torch.empty(ctx.tape_floats(sc, N, 0), dtype=torch.float32, device="cuda")
+    minus = torch.full((N,), -1.0, device="cuda")
+    for t in range(1, iters + sgd_iters + 1):
+        ctx.rollout_fwd(sc, cw, theta, tape=tape)
+        g = ctx.rollout_adj(sc, cw, theta, tape, cost_bar=minus)
+        phi = ctx.svgd_step(theta, g) if t <= iters else g
+        ctx.adam_step(theta, phi, m, v, t, lr=lr)
+    return theta
+
+
+@pytest.mark.parametrize("iters,sgd_iters", [(3, 4), (0, 3)])
+def test_refinement_phase_equals_the_per_call_loop(ctx, iters, sgd_iters):
+    import paper_2310_01775_amd as S
+    sizes = [(70, 3, 3), (33, 2, 1)]
+    probs = [(W.make_scene(60, p, B, H, 40, 0.005), W.cost_weights(rot=0.5), W.make_particles(60, p, N, H))
+             for p, (N, H, B) in enumerate(sizes)]
+    flat = torch.cat([S.soa(th).reshape(-1) for _, _, th in probs]).contiguous()
+    m, v = torch.zeros_like(flat), torch.zeros_like(flat)
+    st = ctx.status_word()
+    ctx.solve([S.make_scene(s) for s, _, _ in probs], [S.make_cost(w) for _, w, _ in probs],
+              [th.shape[0] for _, _, th in probs], S.make_cfg(iters, lr=1e-3, sgd_iters=sgd_iters), flat, m, v,
+              status=st)
+    torch.cuda.synchronize()
+    assert int(st.item()) == 0
+    off = 0
+    for scene, w, th in probs:
+        ref = _loop(ctx, S, scene, w, th, iters, sgd_iters, 1e-3)
+        torch.cuda.synchronize()
+        assert torch.equal(flat[off:off + th.size].view(th.shape[1], th.shape[0]), ref)
+        off += th.size
+
+
+def test_two_phase_solve_matches_oracle(ctx):
+    import paper_2310_01775_amd as S
+    scene, w, th = W.config_problem(1)
+    N = th.shape[0]
+    theta = S.soa(th)
+    m, v = torch.zeros_like(theta), torch.zeros_like(theta)
+    ctx.solve([S.make_scene(scene)], [S.make_cost(w)], [N], S.make_cfg(30, lr=1e-3, sgd_iters=30), theta, m, v)
+    torch.cuda.synchronize()
+    ref = svgd.solve(scene, w, th, 30, lr=1e-3, sgd_iters=30)
+    got = S.aos(theta)
+    scale = np.abs(ref["theta"]).max(axis=0, keepdims=True)
+    err = (np.abs(got - ref["theta"]) / scale).max()
+    norm = np.linalg.norm(got - ref["theta"]) / np.linalg.norm(ref["theta"])
+    print("two-phase state error: worst", err, "normwise", norm, flush=True)
+    assert norm < 1e-4 and err < 1e-3
+
+
+@pytest.mark.parametrize("N,H,B", [(200, 3, 3), (37, 5, 1), (1, 2, 2)])
+def test_plan_readout_matches_oracle(ctx, N, H, B):
+    import paper_2310_01775_amd as S
+    scene = W.make_scene(61, N, B, H, 60, 0.005)
+    w = W.cost_weights(rot=0.5)
+    th = W.make_particles(61, N, N, H)
+    modes, cost = ctx.plan_readout(S.make_scene(scene), S.make_cost(w), S.soa(th))
+    torch.cuda.synchronize()
+    ref_modes, ref_cost = sim.readout(scene, w, th)
+    assert np.array_equal(modes.cpu().numpy().T, ref_modes)
+    c = cost.cpu().double().numpy()
+    rel = np.abs(c - ref_cost) / np.maximum(np.abs(ref_cost), 1e-3)
+    print("read-out cost rel err", rel.max(), flush=True)
+    assert rel.max() < 1e-4
+
+
+def test_readout_argument_errors(ctx):
+    import paper_2310_01775_amd as S
+    scene = W.make_scene(61, 0, 2, 2, 20, 0.005)
+    sc, cw = S.make_scene(scene), S.make_cost(W.cost_weights())
+    th = S.soa(W.make_particles(61, 0, 8, 2))
+    small = torch.empty(16, dtype=torch.uint8, device="cuda")
+    with pytest.raises(S.StampError):
+        ctx.plan_readout(sc, cw, th, workspace=small)
+    with pytest.raises(S.StampError):
+        ctx.solve([sc], [cw], [8], S.make_cfg(1, sgd_iters=-1), th.clone().reshape(-1), torch.zeros(th.numel(), device="cuda"),
+                  torch.zeros(th.numel(), device="cuda"))

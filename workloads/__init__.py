@@ -252,5 +252,10 @@ def surrogate_training_plans(p: int, per: int, H: int = 5, cfg_id: int = 5) -> n
 # surrogate solver on 64 scenes x 2048 particles labelled at iterations 80,
 # 160 and 240 (3 x 131072 rows per round); Adam steps on minibatches of 8192
 # after the random phase and after each round.
+# A plan counts as a solution when executing its discrete plan costs less than
+# this: with the default weights, about 2 cm past the goal's dead zone on one
+# axis (1000 * 0.022^2 = 0.48) on a near-monotone path.
+SOLUTION_COST = 0.5
+
 SURROGATE_RECIPE = dict(random_scenes=128, per=2048, rounds=2, round_scenes=64, round_iters=240,
                         snapshot_every=80, steps=4000, round_steps=2000, batch=8192, lr=1e-3, seed=0)
