@@ -39,9 +39,33 @@ constexpr int kRows = 64;      // samples per workgroup
 constexpr int kLdU = kIn + 8;  // LDS row strides (bf16), padded against bank conflicts
 constexpr int kLdH = kW + 8;
 
-__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+// GELU z Phi(z) and its derivative Phi(z) + z phi(z) from one exponential:
+// erf by Abramowitz & Stegun 7.1.26 (|error| <= 1.5e-7, far below the BF16
+// rounding of the activations), erf(x) = 1 - t (a1 + t (a2 + ... a5 t)) e^{-x^2},
+// t = 1 / (1 + p x), x = |z| / sqrt 2, so that e^{-x^2} = e^{-z^2/2} is also
+// sqrt(2 pi) phi(z).
+__device__ __forceinline__ void gelu_pair(float z, float& g, float& gp) {
+    const float x = fabsf(z) * 0.70710678118654752f;
+    const float t = hw_rcp(fmaf(0.3275911f, x, 1.0f));
+    const float e = hw_exp2(-0.72134752044448170f * z * z);  // e^{-z^2/2}
+    float q = fmaf(1.061405429f, t, -1.453152027f);
+    q = fmaf(q, t, 1.421413741f);
+    q = fmaf(q, t, -0.284496736f);
+    q = fmaf(q, t, 0.254829592f);
+    const float erf_abs = fmaf(-q * t, e, 1.0f);
+    const float Phi = 0.5f + 0.5f * copysignf(erf_abs, z);
+    g = z * Phi;
+    gp = fmaf(z * 0.39894228040143268f, e, Phi);
+}
+__device__ __forceinline__ float gelu(float z) {
+    float g, gp;
+    gelu_pair(z, g, gp);
+    return g;
+}
 __device__ __forceinline__ float gelu_grad(float z) {
-    return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * 0.39894228040143268f * expf(-0.5f * z * z);
+    float g, gp;
+    gelu_pair(z, g, gp);
+    return gp;
 }
 
 // acc += A (16 rows x K, LDS, row stride lda) * B where B[k][n] = Bt[n][k]
@@ -167,96 +191,150 @@ __device__ __forceinline__ float bound_grad(const BoundTerm& bt, int f, float x)
 // Inference: y (and cost = expm1 y) and grad_out[f][i] = scale * e^y * dy/dx_f
 // for f < d (structure of arrays, the SVGD gradient layout; grad_out holds
 // exactly d rows of M, in either input layout).
-__global__ __launch_bounds__(256) void k_mlp_infer(const float* __restrict__ P, const __bf16* __restrict__ Wb,
-                                                   const float* __restrict__ X, int x_mode, int M, int n_in, int d,
-                                                   const float* __restrict__ enc, BoundTerm bt,
-                                                   float* __restrict__ y_out, float* __restrict__ cost_out,
-                                                   float* __restrict__ grad_out, float grad_scale) {
-    __shared__ __bf16 sU[4][16 * kLdU];
-    __shared__ __bf16 sH[4][16 * kLdH];
-    __shared__ __bf16 sD[4][16 * kLdH];
+//
+// A wave takes kInfRB blocks of 16 samples: each weight fragment it loads (16
+// output columns x 256 inputs, eight 16-byte loads in flight) feeds kInfRB
+// matrix products, and delta2 = w3 gelu'(z2) goes to LDS as layer 2 runs.
+constexpr int kInfRB = 2;     // 16-sample blocks per wave
+constexpr int kInfWaves = 1;  // waves per workgroup
+constexpr int kInfRows = 16 * kInfRB * kInfWaves;
+
+// acc[rb] += A_rb (16 rows x 32 KS, LDS) * B for KS k-steps, B fragments given.
+template <int KS>
+__device__ __forceinline__ void mma_blocks(const __bf16* A, int lda, const bf16x8 (&bv)[KS], f4 (&acc)[kInfRB]) {
+    const int l = threadIdx.x & 63;
+    const int r = l & 15, kq = l >> 4;
+#pragma unroll
+    for (int rb = 0; rb < kInfRB; ++rb) {
+        const __bf16* a = A + (rb * 16 + r) * lda + 8 * kq;
+#pragma unroll
+        for (int k = 0; k < KS; ++k)
+            acc[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(*reinterpret_cast<const bf16x8*>(a + 32 * k), bv[k],
+                                                              acc[rb], 0, 0, 0);
+    }
+}
+
+// The KS k-step B fragments of output columns n0..n0+15 of Bt [n][ldb].
+template <int KS>
+__device__ __forceinline__ void load_frags(const __bf16* __restrict__ Bt, int ldb, int n0, bf16x8 (&bv)[KS]) {
+    const int l = threadIdx.x & 63;
+    const __bf16* b = Bt + (int64_t)(n0 + (l & 15)) * ldb + 8 * (l >> 4);
+#pragma unroll
+    for (int k = 0; k < KS; ++k) bv[k] = *reinterpret_cast<const bf16x8*>(b + 32 * k);
+}
+
+__global__ __launch_bounds__(64 * kInfWaves) void k_mlp_infer(const float* __restrict__ P,
+                                                                const __bf16* __restrict__ Wb,
+                                                                const float* __restrict__ X, int x_mode, int M,
+                                                                int n_in, int d, const float* __restrict__ enc,
+                                                                BoundTerm bt, float* __restrict__ y_out,
+                                                                float* __restrict__ cost_out,
+                                                                float* __restrict__ grad_out, float grad_scale) {
+    constexpr int R = 16 * kInfRB;  // samples per wave
+    __shared__ __bf16 sU[kInfWaves][R * kLdU];
+    __shared__ __bf16 sH[kInfWaves][R * kLdH];
+    __shared__ __bf16 sD[kInfWaves][R * kLdH];
     const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
     const int kq = l >> 4, col = l & 15;
-    const int row0 = blockIdx.x * kRows + wave * 16;
+    const int row0 = blockIdx.x * kInfRows + wave * R;
     __bf16* U = sU[wave];
     __bf16* Hb = sH[wave];
     __bf16* Db = sD[wave];
     const MlpPtrs m = mlp_ptrs(P, Wb);
+    const bool want_grad = grad_out != nullptr;
 
-    stage_inputs(U, m, X, x_mode, M, n_in, d, enc, row0);
+#pragma unroll
+    for (int rb = 0; rb < kInfRB; ++rb) stage_inputs(U + rb * 16 * kLdU, m, X, x_mode, M, n_in, d, enc, row0 + rb * 16);
     __syncthreads();
     // layer 1
     for (int cb = 0; cb < kW / 16; ++cb) {
-        f4 acc = {0.f, 0.f, 0.f, 0.f};
-        acc = mma_rows(U, kLdU, m.W1, kIn, cb * 16, kIn, acc);
+        bf16x8 bv[kIn / 32];
+        load_frags<kIn / 32>(m.W1, kIn, cb * 16, bv);
+        f4 acc[kInfRB] = {};
+        mma_blocks<kIn / 32>(U, kLdU, bv, acc);
         const int c = cb * 16 + col;
-        for (int j = 0; j < 4; ++j) Hb[(4 * kq + j) * kLdH + c] = (__bf16)gelu(acc[j] + m.b1[c]);
+        const float b1 = m.b1[c];
+#pragma unroll
+        for (int rb = 0; rb < kInfRB; ++rb)
+            for (int j = 0; j < 4; ++j) Hb[(rb * 16 + 4 * kq + j) * kLdH + c] = (__bf16)gelu(acc[rb][j] + b1);
     }
     __syncthreads();
-    // layer 2, pre-activations kept in registers
-    f4 z2[kW / 16];
-    float yp[4] = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
+    // layer 2, the output dot and delta2 = w3 gelu'(z2)
+    float yp[kInfRB][4] = {};
     for (int cb = 0; cb < kW / 16; ++cb) {
-        f4 acc = {0.f, 0.f, 0.f, 0.f};
-        acc = mma_rows(Hb, kLdH, m.W2, kW, cb * 16, kW, acc);
+        bf16x8 bv[kW / 32];
+        load_frags<kW / 32>(m.W2, kW, cb * 16, bv);
+        f4 acc[kInfRB] = {};
+        mma_blocks<kW / 32>(Hb, kLdH, bv, acc);
         const int c = cb * 16 + col;
-        for (int j = 0; j < 4; ++j) {
-            acc[j] += m.b2[c];
-            yp[j] += m.w3[c] * gelu(acc[j]);
-        }
-        z2[cb] = acc;
-    }
-    float y[4];
-    for (int j = 0; j < 4; ++j) y[j] = sum16(yp[j]) + m.b3;
-    const bool want_grad = grad_out != nullptr;
-    if (want_grad) {
-        // delta2 = w3 * gelu'(z2)
+        const float b2 = m.b2[c], w3 = m.w3[c];
 #pragma unroll
-        for (int cb = 0; cb < kW / 16; ++cb) {
-            const int c = cb * 16 + col;
-            for (int j = 0; j < 4; ++j) Db[(4 * kq + j) * kLdH + c] = (__bf16)(m.w3[c] * gelu_grad(z2[cb][j]));
-        }
+        for (int rb = 0; rb < kInfRB; ++rb)
+            for (int j = 0; j < 4; ++j) {
+                float g, gp;
+                gelu_pair(acc[rb][j] + b2, g, gp);
+                yp[rb][j] = fmaf(w3, g, yp[rb][j]);
+                if (want_grad) Db[(rb * 16 + 4 * kq + j) * kLdH + c] = (__bf16)(w3 * gp);
+            }
     }
+    float y[kInfRB][4];
+#pragma unroll
+    for (int rb = 0; rb < kInfRB; ++rb)
+        for (int j = 0; j < 4; ++j) y[rb][j] = sum16(yp[rb][j]) + m.b3;
     __syncthreads();
     if (want_grad) {
         // delta1 = (delta2 W2) * gelu'(z1), z1 recomputed
         for (int kb = 0; kb < kW / 16; ++kb) {
-            f4 t = {0.f, 0.f, 0.f, 0.f};
-            t = mma_rows(Db, kLdH, m.W2T, kW, kb * 16, kW, t);
-            f4 z1 = {0.f, 0.f, 0.f, 0.f};
-            z1 = mma_rows(U, kLdU, m.W1, kIn, kb * 16, kIn, z1);
+            bf16x8 bt2[kW / 32], bw1[kIn / 32];
+            load_frags<kW / 32>(m.W2T, kW, kb * 16, bt2);
+            load_frags<kIn / 32>(m.W1, kIn, kb * 16, bw1);
+            f4 t[kInfRB] = {}, z1[kInfRB] = {};
+            mma_blocks<kW / 32>(Db, kLdH, bt2, t);
+            mma_blocks<kIn / 32>(U, kLdU, bw1, z1);
             const int k = kb * 16 + col;
-            for (int j = 0; j < 4; ++j) Hb[(4 * kq + j) * kLdH + k] = (__bf16)(t[j] * gelu_grad(z1[j] + m.b1[k]));
+            const float b1 = m.b1[k];
+#pragma unroll
+            for (int rb = 0; rb < kInfRB; ++rb)
+                for (int j = 0; j < 4; ++j)
+                    Hb[(rb * 16 + 4 * kq + j) * kLdH + k] = (__bf16)(t[rb][j] * gelu_grad(z1[rb][j] + b1));
         }
     }
     __syncthreads();
     if (want_grad) {
         // dy/dx = delta1 W1, then the chain through the standardisation
         for (int fb = 0; fb < kIn / 16; ++fb) {
-            f4 g = {0.f, 0.f, 0.f, 0.f};
-            g = mma_rows(Hb, kLdH, m.W1T, kW, fb * 16, kW, g);
             const int f = fb * 16 + col;
+            if (fb * 16 >= d) break;  // only the first d inputs are asked for
+            bf16x8 bv[kW / 32];
+            load_frags<kW / 32>(m.W1T, kW, fb * 16, bv);
+            f4 g[kInfRB] = {};
+            mma_blocks<kW / 32>(Hb, kLdH, bv, g);
             if (f < d) {
-                for (int j = 0; j < 4; ++j) {
-                    const int i = row0 + 4 * kq + j;
-                    if (i < M) {
-                        float gi = expf(y[j]) * g[j] * m.isig[f];
-                        if (bt.H) gi += bound_grad(bt, f, x_raw(X, x_mode, M, n_in, i, f));
-                        grad_out[(int64_t)f * M + i] = grad_scale * gi;
+                const float is = m.isig[f];
+#pragma unroll
+                for (int rb = 0; rb < kInfRB; ++rb)
+                    for (int j = 0; j < 4; ++j) {
+                        const int i = row0 + rb * 16 + 4 * kq + j;
+                        if (i < M) {
+                            float gi = expf(y[rb][j]) * g[rb][j] * is;
+                            if (bt.H) gi += bound_grad(bt, f, x_raw(X, x_mode, M, n_in, i, f));
+                            grad_out[(int64_t)f * M + i] = grad_scale * gi;
+                        }
                     }
-                }
             }
         }
     }
     if (col == 0) {
-        for (int j = 0; j < 4; ++j) {
-            const int i = row0 + 4 * kq + j;
-            if (i < M) {
-                if (y_out) y_out[i] = y[j];
-                if (cost_out) cost_out[i] = expm1f(y[j]) + (bt.H ? bound_cost(bt, X, x_mode, M, n_in, i) : 0.0f);
+#pragma unroll
+        for (int rb = 0; rb < kInfRB; ++rb)
+            for (int j = 0; j < 4; ++j) {
+                const int i = row0 + rb * 16 + 4 * kq + j;
+                if (i < M) {
+                    if (y_out) y_out[i] = y[rb][j];
+                    if (cost_out)
+                        cost_out[i] = expm1f(y[rb][j]) + (bt.H ? bound_cost(bt, X, x_mode, M, n_in, i) : 0.0f);
+                }
             }
-        }
     }
 }
 
@@ -557,8 +635,8 @@ hipError_t launch_mlp_infer(const float* P, const __bf16* Wb, const float* X, in
                             const float* enc, int bound_H, float wb, float omax, float dmax, float* y_out,
                             float* cost_out, float* grad_out, float grad_scale, hipStream_t st) {
     const BoundTerm bt{bound_H, wb, omax, dmax};
-    hipLaunchKernelGGL(k_mlp_infer, dim3((M + kRows - 1) / kRows), dim3(256), 0, st, P, Wb, X, x_mode, M, n_in, d,
-                       enc, bt, y_out, cost_out, grad_out, grad_scale);
+    hipLaunchKernelGGL(k_mlp_infer, dim3((M + kInfRows - 1) / kInfRows), dim3(64 * kInfWaves), 0, st, P, Wb, X,
+                       x_mode, M, n_in, d, enc, bt, y_out, cost_out, grad_out, grad_scale);
     return hipGetLastError();
 }
 
