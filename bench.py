@@ -424,10 +424,11 @@ def bench_surrogate(args):
 def bench_refine(args):
     """Algorithm 1's two phases on the N=1024, B=3, H=3, T=200 scene: 300 SVGD
     iterations against 200 SVGD + 100 SGD refinement iterations (the paper's
-    question whether refinement is needed), each one graph-replayed
-    stamp_solve, then the plan read-out: the discrete plan of every particle,
-    the cost of executing it, and the solutions (executed cost below the
-    threshold) per plan."""
+    question whether refinement is needed), and the same with the importance
+    weights of Eq. (4) in the SVGD phase; each one graph-replayed stamp_solve,
+    then the plan read-out: the discrete plan of every particle, the cost of
+    executing it, and the solutions (executed cost below the threshold) per
+    plan."""
     import numpy as np
     import torch
 
@@ -443,8 +444,9 @@ def bench_refine(args):
     status = ctx.status_word()
     out = {"workload": f"refinement: N={N}, B=3, H=3 (d=18), T=200 steps of dt=0.005, 300 iterations, "
                        f"solutions = executed discrete-plan cost < {W.SOLUTION_COST}"}
-    for name, (it, sgd) in (("svgd300", (300, 0)), ("svgd200_sgd100", (200, 100))):
-        cfg = S.make_cfg(it, lr=lr, sgd_iters=sgd)
+    for name, (it, sgd, ds) in (("svgd300", (300, 0, False)), ("svgd200_sgd100", (200, 100, False)),
+                                ("dsvgd200_sgd100", (200, 100, True))):
+        cfg = S.make_cfg(it, lr=lr, sgd_iters=sgd, dsvgd=ds)
         work = ctx._bytes(ctx.solve_workspace_bytes([sc], [N], cfg))
         for rep in range(2):  # the first run tunes and captures
             theta = S.soa(th)

@@ -112,6 +112,10 @@ typedef struct stamp_solver_cfg {
     int32_t sgd_iters; /* SGD refinement iterations after the SVGD ones (>= 0; Algorithm 1's
                           second phase, Sec. III-C): the update takes phi = grad log rho of
                           each particle alone, with the same step rule and step counter */
+    int32_t dsvgd;     /* 1: weight the SVGD sum by the importance weights of Eq. (4)
+                          (stamp_dsvgd_weights of the relaxed and the discrete plan's cost,
+                          one extra rollout per particle and iteration); 0: w_j = 1 */
+    int32_t reserved;  /* 0 */
 } stamp_solver_cfg;
 
 /* ---- context ----------------------------------------------------------- */
@@ -203,6 +207,25 @@ int32_t stamp_svgd_step(stamp_ctx* ctx, int32_t N, int32_t d, const float* theta
 int32_t stamp_svgd_step_bf16(stamp_ctx* ctx, int32_t N, int32_t d, const float* theta,
                              const float* grad_logp, float bandwidth, float* phi, float* h_out,
                              void* workspace, size_t ws_bytes, void* stream);
+
+/* The SVGD direction of Eq. (4) with importance weights: as stamp_svgd_step,
+ * phi_i = (1/N) sum_j w_j k(theta_j, theta_i) [g_j + (2/h)(theta_i - theta_j)]
+ * for weights [N] (device, non-negative, mean 1 so that w_j / N = w_j / sum w);
+ * the bandwidth is the unweighted median heuristic.  Errors: as
+ * stamp_svgd_step; STAMP_EINVAL for null weights. */
+int32_t stamp_svgd_step_weighted(stamp_ctx* ctx, int32_t N, int32_t d, const float* theta,
+                                 const float* grad_logp, const float* weights, float bandwidth, float* phi,
+                                 float* h_out, void* workspace, size_t ws_bytes, void* stream);
+
+/* Importance weights of Eq. (4) (discrete SVGD): the relaxed plan's likelihood
+ * over the discrete plan's, w_j proportional to exp(-C_relaxed,j) /
+ * exp(-C_discrete,j), scaled to mean 1 (max-subtracted in the exponent; a
+ * non-finite cost gives weight 0; if every one is non-finite, all weights are
+ * 1).  cost_relaxed from stamp_rollout_fwd, cost_discrete from
+ * stamp_plan_readout; all device [N].  Errors: STAMP_EINVAL for null arrays
+ * or N < 1. */
+int32_t stamp_dsvgd_weights(stamp_ctx* ctx, int32_t N, const float* cost_relaxed, const float* cost_discrete,
+                            float* weights, void* stream);
 
 /* Update of Algorithm 1 on n = d*N floats, in place:
  *   use_adam = 1: Adam minimising -phi at step t (>= 1), bias-corrected;

@@ -59,13 +59,29 @@ def kernel_matrix(theta: np.ndarray, h: float) -> np.ndarray:
     return np.exp(-pairwise_sqdist(theta) / h)
 
 
-def svgd_phi(theta: np.ndarray, g: np.ndarray, h: float) -> np.ndarray:
-    """phi_i = (1/N) sum_j K_ij [ g_j + (2/h)(theta_i - theta_j) ]  (Eq. 1)."""
+def svgd_phi(theta: np.ndarray, g: np.ndarray, h: float, w: np.ndarray | None = None) -> np.ndarray:
+    """phi_i = (1/N) sum_j K_ij [ g_j + (2/h)(theta_i - theta_j) ]  (Eq. 1);
+    with importance weights w (mean 1) each term j is scaled by w_j, which is
+    Eq. (4)'s sum of (w_j / sum w) [...]."""
     N = theta.shape[0]
     K = kernel_matrix(theta, h)
+    if w is not None:
+        K = K * np.asarray(w, dtype=np.float64)[None, :]
     drive = K @ g
     repulse = (2.0 / h) * (theta * K.sum(axis=1, keepdims=True) - K @ theta)
     return (drive + repulse) / N
+
+
+def dsvgd_weights(c_relaxed: np.ndarray, c_discrete: np.ndarray) -> np.ndarray:
+    """Importance weights of Eq. (4): the relaxed plan's likelihood over the
+    discrete plan's, exp(-C_rel) / exp(-C_disc), scaled to mean 1.  A
+    non-finite log-weight gives weight 0; all non-finite gives weights 1."""
+    lw = np.asarray(c_discrete, dtype=np.float64) - np.asarray(c_relaxed, dtype=np.float64)
+    ok = np.isfinite(lw)
+    if not ok.any():
+        return np.ones_like(lw)
+    e = np.where(ok, np.exp(np.where(ok, lw, 0.0) - lw[ok].max()), 0.0)
+    return e * (lw.size / e.sum())
 
 
 def adam_step(theta, phi, m, v, t, lr=1e-2, beta1=0.9, beta2=0.999, eps=1e-8):
@@ -85,11 +101,13 @@ def plain_step(theta, phi, lr):
 
 def solve(scene, w, theta0, iters, t0=0, lr=1e-2, beta1=0.9, beta2=0.999, eps=1e-8,
           use_adam=True, fixed_bandwidth=0.0, m0=None, v0=None, grad_fn=None,
-          history=False, sgd_iters=0):
+          history=False, sgd_iters=0, dsvgd=False):
     """Algorithm 1 for fixed iteration counts: `iters` SVGD iterations, then
     `sgd_iters` SGD refinement iterations whose update takes each particle's
     own gradient of log rho (the second phase of Algorithm 1, Sec. III-C),
-    with the same step rule and a continuing step counter.
+    with the same step rule and a continuing step counter.  dsvgd: the SVGD
+    iterations weight the sum by the importance weights of Eq. (4), from the
+    relaxed cost and the cost of executing each particle's discrete plan.
 
     grad_fn(theta) -> (cost, dC/dtheta) defaults to the simulator rollout.
     Returns dict(theta, m, v, cost, modes, h, [hist]).
@@ -107,7 +125,8 @@ def solve(scene, w, theta0, iters, t0=0, lr=1e-2, beta1=0.9, beta2=0.999, eps=1e
         g = -dC
         if it < iters:
             h = bandwidth(th, fixed_bandwidth)
-            phi = g if th.shape[0] == 1 else svgd_phi(th, g, h)
+            wts = dsvgd_weights(c, sim.readout(scene, w, th)[1]) if dsvgd else None
+            phi = g if th.shape[0] == 1 else svgd_phi(th, g, h, wts)
         else:
             phi = g
         if use_adam:

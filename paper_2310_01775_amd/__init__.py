@@ -46,7 +46,8 @@ class CostW(C.Structure):
 class SolverCfg(C.Structure):
     _fields_ = [("iters", C.c_int32), ("t0", C.c_int32), ("lr", C.c_float), ("beta1", C.c_float),
                 ("beta2", C.c_float), ("adam_eps", C.c_float), ("use_adam", C.c_int32),
-                ("bandwidth", C.c_float), ("ckpt_every", C.c_int32), ("sgd_iters", C.c_int32)]
+                ("bandwidth", C.c_float), ("ckpt_every", C.c_int32), ("sgd_iters", C.c_int32),
+                ("dsvgd", C.c_int32), ("reserved", C.c_int32)]
 
 
 class Surrogate(C.Structure):
@@ -72,6 +73,8 @@ _sig = {
     "stamp_tape_floats": (_sz, [_P(Scene), _i32, _i32]),
     "stamp_adj_workspace_bytes": (_sz, [_P(Scene), _i32, _i32]),
     "stamp_readout_workspace_bytes": (_sz, [_P(Scene), _i32]),
+    "stamp_dsvgd_weights": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp]),
+    "stamp_svgd_step_weighted": (_i32, [_vp, _i32, _i32, _vp, _vp, _vp, C.c_float, _vp, _vp, _vp, _sz, _vp]),
     "stamp_plan_readout": (_i32, [_vp, _P(Scene), _P(CostW), _i32, _vp, _vp, _vp, _vp, _sz, _vp, _vp]),
     "stamp_svgd_workspace_bytes": (_sz, [_i32, _i32]),
     "stamp_solve_workspace_bytes": (_sz, [_i32, _P(Scene), _P(_i32), _P(SolverCfg)]),
@@ -139,9 +142,9 @@ def make_cost(w: dict) -> CostW:
 
 
 def make_cfg(iters, t0=0, lr=1e-3, beta1=0.9, beta2=0.999, adam_eps=1e-8, use_adam=True,
-             bandwidth=0.0, ckpt_every=0, sgd_iters=0) -> SolverCfg:
+             bandwidth=0.0, ckpt_every=0, sgd_iters=0, dsvgd=False) -> SolverCfg:
     return SolverCfg(int(iters), int(t0), lr, beta1, beta2, adam_eps, int(bool(use_adam)), bandwidth,
-                     int(ckpt_every), int(sgd_iters))
+                     int(ckpt_every), int(sgd_iters), int(bool(dsvgd)), 0)
 
 
 def soa(theta_nd, device="cuda") -> torch.Tensor:
@@ -275,6 +278,34 @@ class Context:
         self._check(_lib.stamp_rollout_fwd(self._h, C.byref(scene), C.byref(w), N, _ptr(theta), _ptr(cost),
                                            _ptr(tape), ckpt_every, _ptr(status), _stream(stream)))
         return cost
+
+    def dsvgd_weights(self, cost_relaxed, cost_discrete, weights=None, stream=None):
+        """stamp_dsvgd_weights: importance weights [N] (mean 1) of Eq. (4)."""
+        for t in (cost_relaxed, cost_discrete):
+            if t.dtype != torch.float32 or not t.is_contiguous():
+                raise ValueError("costs must be contiguous float32")
+        N = cost_relaxed.numel()
+        if cost_discrete.numel() != N:
+            raise ValueError("cost arrays differ in length")
+        if weights is None:
+            weights = torch.empty(N, dtype=torch.float32, device=self.device)
+        self._check(_lib.stamp_dsvgd_weights(self._h, N, _ptr(cost_relaxed), _ptr(cost_discrete), _ptr(weights),
+                                             _stream(stream)))
+        return weights
+
+    def svgd_step_weighted(self, theta, grad_logp, weights, bandwidth: float = 0.0, phi=None, h_out=None,
+                           workspace=None, stream=None):
+        d, N = theta.shape
+        if weights.dtype != torch.float32 or weights.numel() != N or not weights.is_contiguous():
+            raise ValueError("weights must be N contiguous float32")
+        if phi is None:
+            phi = torch.empty_like(theta)
+        if workspace is None:
+            workspace = self._bytes(self.svgd_workspace_bytes(N, d))
+        self._check(_lib.stamp_svgd_step_weighted(self._h, N, d, _ptr(theta), _ptr(grad_logp), _ptr(weights),
+                                                  float(bandwidth), _ptr(phi), _ptr(h_out), _ptr(workspace),
+                                                  workspace.numel(), _stream(stream)))
+        return phi
 
     def plan_readout(self, scene: Scene, w: CostW, theta: torch.Tensor, modes=None, cost=None, workspace=None,
                      status=None, stream=None):

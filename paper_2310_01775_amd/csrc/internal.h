@@ -29,12 +29,18 @@ hipError_t launch_rollout_adj_batched(const ProblemDesc* descs, const int2* tile
 // non-null).  phi_rows: rows per contraction workgroup (0 = 256).
 SvgdLayout svgd_workspace_layout(int N, int d);
 int svgd_dp_class(int d);
+// wts: null, or per-particle importance weights (mean 1) of Eq. (4).
 hipError_t launch_svgd(int N, int d, const float* theta, const float* grad_logp, float bandwidth, float* phi,
                        float* h_out, void* ws, const SvgdLayout& L, int phi_rows, uint32_t* status,
-                       hipStream_t st);
-// The same step for every problem of a batch (work lists in P).
+                       hipStream_t st, const float* wts = nullptr);
+// The same step for every problem of a batch (work lists in P); wts packed
+// like the costs (problem p at its cost offset), or null.
 hipError_t launch_svgd_batched(const BatchPlan& P, const ProblemDesc* descs, const float* theta, const float* grad,
-                               float* phi, char* ws, uint32_t* status, hipStream_t st);
+                               float* phi, char* ws, uint32_t* status, hipStream_t st, const float* wts = nullptr);
+// Importance weights of Eq. (4): w_j = N softmax_j(C_disc - C_rel), mean 1.
+hipError_t launch_dsvgd_weights(int N, const float* c_rel, const float* c_disc, float* w, hipStream_t st);
+hipError_t launch_dsvgd_weights_batched(int n_problems, const ProblemDesc* descs, const float* c_rel,
+                                        const float* c_disc, float* w, hipStream_t st);
 
 // Median-heuristic bandwidth into the problem's SelState (median.hip): exact = 1
 // the exact lower median of all pairs, 0 the lower median of a fixed sample.

@@ -185,7 +185,7 @@ struct SolvePlan {
     size_t ctr16_off = 0, row16_off = 0, phi16_off[2] = {};
     size_t phi_off[kDpClasses] = {};
     size_t ctr_off = 0, err_off = 0, tape_off = 0, seg_off = 0, grad_off = 0, phi_vec_off = 0, cost_off = 0,
-           svgd_off = 0;
+           cdisc_off = 0, wts_off = 0, svgd_off = 0;
     size_t total = 0;
     int64_t n_theta = 0, n_part = 0;
     std::string key;  // batch signature (sizes only)
@@ -290,6 +290,8 @@ void build_plan(int n, const stamp_scene* scenes, const int32_t* N, int K, float
     P.grad_off = take((size_t)th * 4);
     P.phi_vec_off = take((size_t)th * 4);
     P.cost_off = take((size_t)co * 4);
+    P.cdisc_off = take((size_t)co * 4);  // discrete-plan costs (importance weights)
+    P.wts_off = take((size_t)co * 4);    // importance weights
     P.svgd_off = take(sv);
     P.total = off;
 }
@@ -307,7 +309,7 @@ bool same_layout(const SolvePlan& a, const SolvePlan& b) {
               a.dist_off == b.dist_off && a.cand_off == b.cand_off && a.red_off == b.red_off &&
               a.ctr_off == b.ctr_off && a.err_off == b.err_off && a.tape_off == b.tape_off && a.seg_off == b.seg_off &&
               a.grad_off == b.grad_off && a.phi_vec_off == b.phi_vec_off && a.cost_off == b.cost_off &&
-              a.svgd_off == b.svgd_off;
+              a.cdisc_off == b.cdisc_off && a.wts_off == b.wts_off && a.svgd_off == b.svgd_off;
     for (int c = 0; c < kDpClasses; ++c) ok = ok && a.phi_off[c] == b.phi_off[c];
     ok = ok && a.ctr16_off == b.ctr16_off && a.row16_off == b.row16_off && a.phi16_off[0] == b.phi16_off[0] &&
          a.phi16_off[1] == b.phi16_off[1];
@@ -438,6 +440,15 @@ int32_t stamp_rollout_fwd(stamp_ctx* ctx, const stamp_scene* scene, const stamp_
     return e == hipSuccess ? STAMP_OK : hip_fail(ctx, e, "rollout_fwd");
 }
 
+int32_t stamp_dsvgd_weights(stamp_ctx* ctx, int32_t N, const float* cost_relaxed, const float* cost_discrete,
+                            float* weights, void* stream) {
+    if (!ctx) return STAMP_EINVAL;
+    if (!cost_relaxed || !cost_discrete || !weights) return fail(ctx, STAMP_EINVAL, "null cost or weights");
+    if (N < 1) return fail(ctx, STAMP_EINVAL, "N=%d < 1", N);
+    hipError_t e = launch_dsvgd_weights(N, cost_relaxed, cost_discrete, weights, (hipStream_t)stream);
+    return e == hipSuccess ? STAMP_OK : hip_fail(ctx, e, "dsvgd_weights");
+}
+
 size_t stamp_readout_workspace_bytes(const stamp_scene* scene, int32_t N) {
     if (!scene || N < 1 || scene->H < 1 || scene->H > kMaxPushes) return 0;
     return (size_t)6 * scene->H * N * sizeof(float);
@@ -498,6 +509,24 @@ int32_t stamp_svgd_step(stamp_ctx* ctx, int32_t N, int32_t d, const float* theta
     return e == hipSuccess ? STAMP_OK : hip_fail(ctx, e, "svgd_step");
 }
 
+int32_t stamp_svgd_step_weighted(stamp_ctx* ctx, int32_t N, int32_t d, const float* theta, const float* grad_logp,
+                                 const float* weights, float bandwidth, float* phi, float* h_out, void* workspace,
+                                 size_t ws_bytes, void* stream) {
+    if (!ctx) return STAMP_EINVAL;
+    if (!theta || !grad_logp || !phi || !weights)
+        return fail(ctx, STAMP_EINVAL, "null theta, grad_logp, weights or phi");
+    if (N < 1 || d < 1) return fail(ctx, STAMP_EINVAL, "N=%d, d=%d must be >= 1", N, d);
+    if (d > kMaxSvgdDim || N > kMaxSvgdN)
+        return fail(ctx, STAMP_EUNSUPPORTED, "svgd step supports d <= %d, N <= %d", kMaxSvgdDim, kMaxSvgdN);
+    if (!isfinite(bandwidth)) return fail(ctx, STAMP_EINVAL, "non-finite bandwidth");
+    const SvgdLayout L = svgd_workspace_layout(N, d);
+    if (!workspace || ws_bytes < L.total)
+        return fail(ctx, STAMP_ENOSPACE, "svgd workspace %zu < %zu bytes", ws_bytes, L.total);
+    hipError_t e = launch_svgd(N, d, theta, grad_logp, bandwidth, phi, h_out, workspace, L, 0, nullptr,
+                               (hipStream_t)stream, weights);
+    return e == hipSuccess ? STAMP_OK : hip_fail(ctx, e, "svgd_step_weighted");
+}
+
 int32_t stamp_svgd_step_bf16(stamp_ctx* ctx, int32_t N, int32_t d, const float* theta, const float* grad_logp,
                              float bandwidth, float* phi, float* h_out, void* workspace, size_t ws_bytes,
                              void* stream) {
@@ -540,8 +569,10 @@ static int32_t solve_impl(stamp_ctx* ctx, int32_t n_problems, const stamp_scene*
     if (!ctx) return STAMP_EINVAL;
     if (n_problems < 1 || !scenes || !w || !N || !cfg) return fail(ctx, STAMP_EINVAL, "null problem arrays");
     if (!theta || !cost_out) return fail(ctx, STAMP_EINVAL, "null theta or cost_out");
-    if (cfg->iters < 0 || cfg->ckpt_every < 0 || cfg->t0 < 0 || cfg->sgd_iters < 0)
+    if (cfg->iters < 0 || cfg->ckpt_every < 0 || cfg->t0 < 0 || cfg->sgd_iters < 0 || cfg->dsvgd < 0 ||
+        cfg->dsvgd > 1)
         return fail(ctx, STAMP_EINVAL, "bad solver cfg");
+    if (cfg->dsvgd && sur) return fail(ctx, STAMP_EINVAL, "importance weights apply to the simulator iterations only");
     if (cfg->use_adam && (!adam_m || !adam_v)) return fail(ctx, STAMP_EINVAL, "Adam needs m and v");
     if (!isfinite(cfg->lr) || !isfinite(cfg->bandwidth)) return fail(ctx, STAMP_EINVAL, "non-finite lr/bandwidth");
     if (cfg->use_adam && !(cfg->beta1 >= 0 && cfg->beta1 < 1 && cfg->beta2 >= 0 && cfg->beta2 < 1 &&
@@ -714,7 +745,12 @@ static int32_t solve_impl(stamp_ctx* ctx, int32_t n_problems, const stamp_scene*
     const BatchPlan B = batch_plan();
     const int rgrid = roll_grid(tune);
 
-    // one SVGD iteration over every problem, captured once and replayed
+    // one SVGD iteration over every problem, captured once and replayed; with
+    // importance weights (Eq. 4) each particle's discrete plan is rolled out
+    // too (its one-hot particle built in the phi buffer, which the step
+    // overwrites afterwards)
+    float* d_cdisc = (float*)(ws + P.cdisc_off);
+    float* d_wts = (float*)(ws + P.wts_off);
     auto iteration = [&]() -> hipError_t {
         hipError_t r;
         if ((r = launch_rollout_fwd_batched(d_desc, d_roll, ntiles, tune.roll_block, rgrid, theta,
@@ -723,7 +759,22 @@ static int32_t solve_impl(stamp_ctx* ctx, int32_t n_problems, const stamp_scene*
         if ((r = launch_rollout_adj_batched(d_desc, d_roll, ntiles, tune.roll_block, rgrid, theta, d_tape, -1.0f,
                                             d_grad, d_seg, status, st)) != hipSuccess)
             return r;
-        if ((r = launch_svgd_batched(B, d_desc, theta, d_grad, d_phi, d_svgd, status, st)) != hipSuccess) return r;
+        if (cfg->dsvgd) {
+            for (int p = 0; p < n_problems; ++p) {
+                const ProblemDesc& D = P.descs[p];
+                if ((r = launch_onehot(D.N, scenes[p].H, theta + D.theta_off, d_phi + D.theta_off, st)) != hipSuccess)
+                    return r;
+            }
+            if ((r = launch_rollout_fwd_batched(d_desc, d_roll, ntiles, tune.roll_block, rgrid, d_phi, d_cdisc,
+                                                nullptr, status, st)) != hipSuccess)
+                return r;
+            if ((r = launch_dsvgd_weights_batched(n_problems, d_desc, (const float*)(ws + P.cost_off), d_cdisc,
+                                                  d_wts, st)) != hipSuccess)
+                return r;
+        }
+        if ((r = launch_svgd_batched(B, d_desc, theta, d_grad, d_phi, d_svgd, status, st,
+                                     cfg->dsvgd ? d_wts : nullptr)) != hipSuccess)
+            return r;
         if ((r = launch_update(P.n_theta, theta, d_phi, adam_m, adam_v, cfg->t0, d_ctr, cfg->lr, cfg->beta1,
                                cfg->beta2, cfg->adam_eps, cfg->use_adam, st)) != hipSuccess)
             return r;
@@ -769,9 +820,9 @@ static int32_t solve_impl(stamp_ctx* ctx, int32_t n_problems, const stamp_scene*
         return launch_incr(d_ctr, st);
     };
     char gkey[512];
-    snprintf(gkey, sizeof gkey, "|%p|%p|%p|%p|%p|%d|%d|%.9g|%.9g|%.9g|%.9g|%d|%d|%d|", (void*)ws, (void*)theta,
+    snprintf(gkey, sizeof gkey, "|%p|%p|%p|%p|%p|%d|%d|%.9g|%.9g|%.9g|%.9g|%d|%d|%d|%d|", (void*)ws, (void*)theta,
              (void*)adam_m, (void*)adam_v, (void*)status, cfg->t0, cfg->use_adam, cfg->lr, cfg->beta1, cfg->beta2,
-             cfg->adam_eps, tune.roll_block, rgrid, tune.phi_rows);
+             cfg->adam_eps, tune.roll_block, rgrid, tune.phi_rows, cfg->dsvgd);
     const std::string full_key = tkey + gkey;
     // capture `body` into `graph` unless the cached one was made for `key`
     auto ensure_graph = [&](hipGraphExec_t& graph, std::string& have_key, const std::string& key,

@@ -27,15 +27,18 @@ namespace {
 
 // ---- bodies -----------------------------------------------------------------
 
-// partial[split][l][i] = sum_{j in [j0, j1)} K_ij (g_jl + (2/h)(theta_il - theta_jl))
-// for the rows i = row0 + threadIdx.x of this workgroup.
+// partial[split][l][i] = sum_{j in [j0, j1)} w_j K_ij (g_jl + (2/h)(theta_il - theta_jl))
+// for the rows i = row0 + threadIdx.x of this workgroup; w_j = wts[j], or 1
+// when wts is null (the importance weights of Eq. 4, scaled to mean 1).
 template <int DP>
 __device__ __forceinline__ void phi_partial_body(int N, int d, int row0, int j0, int j1, int split,
                                                  const float* __restrict__ theta, const float* __restrict__ g,
-                                                 const SelState* __restrict__ sel, float* __restrict__ partial) {
+                                                 const float* __restrict__ wts, const SelState* __restrict__ sel,
+                                                 float* __restrict__ partial) {
     constexpr int JT = 64;  // columns staged per round
     __shared__ float tj[JT][DP];
     __shared__ float gj[JT][DP];
+    __shared__ float wj[JT];
     const int i = row0 + threadIdx.x;
     const float inv_h = 1.0f / sel->h;
     const float c2 = 2.0f * inv_h;
@@ -49,12 +52,13 @@ __device__ __forceinline__ void phi_partial_body(int N, int d, int row0, int j0,
     for (int jb = j0; jb < j1; jb += JT) {
         const int nj = min(JT, j1 - jb);
         __syncthreads();
-        for (int e = threadIdx.x; e < JT * DP; e += blockDim.x) {
-            const int jj = e / DP, l = e % DP;
+        for (int e = threadIdx.x; e < JT * DP; e += blockDim.x) {  // consecutive threads, consecutive columns
+            const int jj = e % JT, l = e / JT;
             const bool ok = jj < nj && l < d;
             tj[jj][l] = ok ? theta[(int64_t)l * N + jb + jj] : 0.0f;
             gj[jj][l] = ok ? g[(int64_t)l * N + jb + jj] : 0.0f;
         }
+        for (int jj = threadIdx.x; jj < JT; jj += blockDim.x) wj[jj] = (wts && jj < nj) ? wts[jb + jj] : 1.0f;
         __syncthreads();
         for (int jj = 0; jj < nj; ++jj) {
             float D = 0.0f;
@@ -63,7 +67,7 @@ __device__ __forceinline__ void phi_partial_body(int N, int d, int row0, int j0,
                 const float df = ti[l] - tj[jj][l];
                 D = fmaf(df, df, D);
             }
-            const float k = expf(-D * inv_h);
+            const float k = wts ? expf(-D * inv_h) * wj[jj] : expf(-D * inv_h);
 #pragma unroll
             for (int l = 0; l < DP; ++l) acc[l] = fmaf(k, fmaf(c2, ti[l] - tj[jj][l], gj[jj][l]), acc[l]);
         }
@@ -95,11 +99,11 @@ __device__ __forceinline__ void phi_reduce_elem(int64_t e, int64_t n, int N, int
 
 template <int DP>
 __global__ __launch_bounds__(256) void k_phi_partial(int N, int d, int chunk, const float* __restrict__ theta,
-                                                     const float* __restrict__ g, const SelState* __restrict__ sel,
-                                                     float* __restrict__ partial) {
+                                                     const float* __restrict__ g, const float* __restrict__ wts,
+                                                     const SelState* __restrict__ sel, float* __restrict__ partial) {
     const int split = blockIdx.y;
     const int j0 = split * chunk, j1 = min(j0 + chunk, N);
-    phi_partial_body<DP>(N, d, blockIdx.x * blockDim.x, j0, j1, split, theta, g, sel, partial);
+    phi_partial_body<DP>(N, d, blockIdx.x * blockDim.x, j0, j1, split, theta, g, wts, sel, partial);
 }
 
 __global__ __launch_bounds__(256) void k_phi_reduce(int N, int d, int splits, const float* __restrict__ partial,
@@ -120,18 +124,73 @@ __global__ void k_copy(const float* __restrict__ a, float* __restrict__ b, int64
 __device__ __forceinline__ char* svgd_base(const ProblemDesc& D, char* ws) { return ws + D.svgd_off; }
 
 // entry = (problem, row block, split, -)
+// wts: per-particle weights packed like the costs (problem p at cost_off), or null
 template <int DP>
 __global__ __launch_bounds__(256) void k_phi_partial_batched(const ProblemDesc* __restrict__ descs,
                                                              const int4* __restrict__ work, const float* theta,
-                                                             const float* grad, char* ws) {
+                                                             const float* grad, const float* wts, char* ws) {
     const int4 w = work[blockIdx.x];
     const ProblemDesc& D = descs[w.x];
     char* b = svgd_base(D, ws);
     const int chunk = (D.N + D.sv.splits - 1) / D.sv.splits;
     const int j0 = w.z * chunk, j1 = min(j0 + chunk, D.N);
     phi_partial_body<DP>(D.N, D.d, w.y * (int)blockDim.x, j0, j1, w.z, theta + D.theta_off, grad + D.theta_off,
-                         reinterpret_cast<const SelState*>(b + D.sv.sel_off),
+                         wts ? wts + D.cost_off : nullptr, reinterpret_cast<const SelState*>(b + D.sv.sel_off),
                          reinterpret_cast<float*>(b + D.sv.part_off));
+}
+
+// Importance weights of Eq. (4) for one problem (one workgroup of 256):
+// w_j proportional to exp(C_disc,j - C_rel,j), the relaxed over the discrete
+// plan's likelihood, scaled to mean 1 (max-subtracted; a non-finite log-weight
+// gives weight 0; all non-finite gives equal weights).
+__device__ void dsvgd_weights_body(int N, const float* __restrict__ c_rel, const float* __restrict__ c_disc,
+                                   float* __restrict__ w) {
+    __shared__ float red[256];
+    const int tid = threadIdx.x;
+    float m = -INFINITY;
+    for (int j = tid; j < N; j += 256) {
+        const float lw = c_disc[j] - c_rel[j];
+        if (isfinite(lw)) m = fmaxf(m, lw);
+    }
+    red[tid] = m;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (tid < s) red[tid] = fmaxf(red[tid], red[tid + s]);
+        __syncthreads();
+    }
+    m = red[0];
+    __syncthreads();
+    if (!isfinite(m)) {
+        for (int j = tid; j < N; j += 256) w[j] = 1.0f;
+        return;
+    }
+    double sum = 0.0;
+    for (int j = tid; j < N; j += 256) {
+        const float lw = c_disc[j] - c_rel[j];
+        sum += isfinite(lw) ? (double)expf(lw - m) : 0.0;
+    }
+    __shared__ double rs[256];
+    rs[tid] = sum;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (tid < s) rs[tid] += rs[tid + s];
+        __syncthreads();
+    }
+    const float scale = (float)((double)N / rs[0]);
+    for (int j = tid; j < N; j += 256) {
+        const float lw = c_disc[j] - c_rel[j];
+        w[j] = isfinite(lw) ? expf(lw - m) * scale : 0.0f;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_dsvgd_weights(int N, const float* c_rel, const float* c_disc, float* w) {
+    dsvgd_weights_body(N, c_rel, c_disc, w);
+}
+
+__global__ __launch_bounds__(256) void k_dsvgd_weights_batched(const ProblemDesc* __restrict__ descs,
+                                                               const float* c_rel, const float* c_disc, float* w) {
+    const ProblemDesc& D = descs[blockIdx.x];
+    dsvgd_weights_body(D.N, c_rel + D.cost_off, c_disc + D.cost_off, w + D.cost_off);
 }
 
 // entry = (problem, first element, end element, -) of the problem's d*N block
@@ -200,16 +259,16 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 template <int DP>
 hipError_t launch_phi_partial(int N, int d, int chunk, int splits, int rows, const float* theta, const float* g,
-                              const SelState* sel, float* partial, hipStream_t st) {
+                              const float* wts, const SelState* sel, float* partial, hipStream_t st) {
     dim3 grid((N + rows - 1) / rows, splits);
-    hipLaunchKernelGGL(k_phi_partial<DP>, grid, dim3(rows), 0, st, N, d, chunk, theta, g, sel, partial);
+    hipLaunchKernelGGL(k_phi_partial<DP>, grid, dim3(rows), 0, st, N, d, chunk, theta, g, wts, sel, partial);
     return hipGetLastError();
 }
 
 template <int DP>
 void launch_phi_partial_batched(int n, int rows, const ProblemDesc* descs, const int4* work, const float* theta,
-                                const float* grad, char* ws, hipStream_t st) {
-    hipLaunchKernelGGL(k_phi_partial_batched<DP>, dim3(n), dim3(rows), 0, st, descs, work, theta, grad, ws);
+                                const float* grad, const float* wts, char* ws, hipStream_t st) {
+    hipLaunchKernelGGL(k_phi_partial_batched<DP>, dim3(n), dim3(rows), 0, st, descs, work, theta, grad, wts, ws);
 }
 
 }  // namespace
@@ -284,7 +343,8 @@ SvgdLayout svgd_workspace_layout(int N, int d) {
 }
 
 hipError_t launch_svgd(int N, int d, const float* theta, const float* grad_logp, float bandwidth, float* phi,
-                       float* h_out, void* ws, const SvgdLayout& L, int phi_rows, uint32_t* status, hipStream_t st) {
+                       float* h_out, void* ws, const SvgdLayout& L, int phi_rows, uint32_t* status, hipStream_t st,
+                       const float* wts) {
     char* base = static_cast<char*>(ws);
     SelState* sel = reinterpret_cast<SelState*>(base + L.sel_off);
     hipError_t e = launch_median(N, d, theta, bandwidth, 1, ws, L, h_out, st);
@@ -297,12 +357,12 @@ hipError_t launch_svgd(int N, int d, const float* theta, const float* grad_logp,
     const int chunk = (N + L.splits - 1) / L.splits;
     const int rows = phi_rows > 0 ? phi_rows : 256;
     switch (svgd_dp_class(d)) {
-        case 8: e = launch_phi_partial<8>(N, d, chunk, L.splits, rows, theta, grad_logp, sel, partial, st); break;
-        case 16: e = launch_phi_partial<16>(N, d, chunk, L.splits, rows, theta, grad_logp, sel, partial, st); break;
-        case 24: e = launch_phi_partial<24>(N, d, chunk, L.splits, rows, theta, grad_logp, sel, partial, st); break;
-        case 32: e = launch_phi_partial<32>(N, d, chunk, L.splits, rows, theta, grad_logp, sel, partial, st); break;
-        case 48: e = launch_phi_partial<48>(N, d, chunk, L.splits, rows, theta, grad_logp, sel, partial, st); break;
-        default: e = launch_phi_partial<64>(N, d, chunk, L.splits, rows, theta, grad_logp, sel, partial, st); break;
+        case 8: e = launch_phi_partial<8>(N, d, chunk, L.splits, rows, theta, grad_logp, wts, sel, partial, st); break;
+        case 16: e = launch_phi_partial<16>(N, d, chunk, L.splits, rows, theta, grad_logp, wts, sel, partial, st); break;
+        case 24: e = launch_phi_partial<24>(N, d, chunk, L.splits, rows, theta, grad_logp, wts, sel, partial, st); break;
+        case 32: e = launch_phi_partial<32>(N, d, chunk, L.splits, rows, theta, grad_logp, wts, sel, partial, st); break;
+        case 48: e = launch_phi_partial<48>(N, d, chunk, L.splits, rows, theta, grad_logp, wts, sel, partial, st); break;
+        default: e = launch_phi_partial<64>(N, d, chunk, L.splits, rows, theta, grad_logp, wts, sel, partial, st); break;
     }
     if (e != hipSuccess) return e;
     const int64_t n = (int64_t)d * N;
@@ -312,22 +372,33 @@ hipError_t launch_svgd(int N, int d, const float* theta, const float* grad_logp,
 }
 
 hipError_t launch_svgd_batched(const BatchPlan& P, const ProblemDesc* descs, const float* theta, const float* grad,
-                               float* phi, char* ws, uint32_t* status, hipStream_t st) {
+                               float* phi, char* ws, uint32_t* status, hipStream_t st, const float* wts) {
     hipError_t e = launch_median_batched(P, descs, theta, 1, ws, st);
     if (e != hipSuccess) return e;
     for (int c = 0; c < kDpClasses; ++c) {
         if (!P.n_phi[c]) continue;
         switch (kDpClass[c]) {
-            case 8: launch_phi_partial_batched<8>(P.n_phi[c], P.phi_rows, descs, P.phi_work[c], theta, grad, ws, st); break;
-            case 16: launch_phi_partial_batched<16>(P.n_phi[c], P.phi_rows, descs, P.phi_work[c], theta, grad, ws, st); break;
-            case 24: launch_phi_partial_batched<24>(P.n_phi[c], P.phi_rows, descs, P.phi_work[c], theta, grad, ws, st); break;
-            case 32: launch_phi_partial_batched<32>(P.n_phi[c], P.phi_rows, descs, P.phi_work[c], theta, grad, ws, st); break;
-            case 48: launch_phi_partial_batched<48>(P.n_phi[c], P.phi_rows, descs, P.phi_work[c], theta, grad, ws, st); break;
-            default: launch_phi_partial_batched<64>(P.n_phi[c], P.phi_rows, descs, P.phi_work[c], theta, grad, ws, st); break;
+            case 8: launch_phi_partial_batched<8>(P.n_phi[c], P.phi_rows, descs, P.phi_work[c], theta, grad, wts, ws, st); break;
+            case 16: launch_phi_partial_batched<16>(P.n_phi[c], P.phi_rows, descs, P.phi_work[c], theta, grad, wts, ws, st); break;
+            case 24: launch_phi_partial_batched<24>(P.n_phi[c], P.phi_rows, descs, P.phi_work[c], theta, grad, wts, ws, st); break;
+            case 32: launch_phi_partial_batched<32>(P.n_phi[c], P.phi_rows, descs, P.phi_work[c], theta, grad, wts, ws, st); break;
+            case 48: launch_phi_partial_batched<48>(P.n_phi[c], P.phi_rows, descs, P.phi_work[c], theta, grad, wts, ws, st); break;
+            default: launch_phi_partial_batched<64>(P.n_phi[c], P.phi_rows, descs, P.phi_work[c], theta, grad, wts, ws, st); break;
         }
     }
     hipLaunchKernelGGL(k_phi_reduce_batched, dim3(P.n_red), dim3(256), 0, st, descs, P.red_work, grad, phi, ws,
                        status);
+    return hipGetLastError();
+}
+
+hipError_t launch_dsvgd_weights(int N, const float* c_rel, const float* c_disc, float* w, hipStream_t st) {
+    hipLaunchKernelGGL(k_dsvgd_weights, dim3(1), dim3(256), 0, st, N, c_rel, c_disc, w);
+    return hipGetLastError();
+}
+
+hipError_t launch_dsvgd_weights_batched(int n_problems, const ProblemDesc* descs, const float* c_rel,
+                                        const float* c_disc, float* w, hipStream_t st) {
+    hipLaunchKernelGGL(k_dsvgd_weights_batched, dim3(n_problems), dim3(256), 0, st, descs, c_rel, c_disc, w);
     return hipGetLastError();
 }
 

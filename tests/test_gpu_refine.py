@@ -96,3 +96,81 @@ def test_readout_argument_errors(ctx):
     with pytest.raises(S.StampError):
         ctx.solve([sc], [cw], [8], S.make_cfg(1, sgd_iters=-1), th.clone().reshape(-1), torch.zeros(th.numel(), device="cuda"),
                   torch.zeros(th.numel(), device="cuda"))
+
+
+def test_importance_weights_match_oracle(ctx):
+    import paper_2310_01775_amd as S
+    rng = np.random.default_rng(4)
+    c_rel = rng.uniform(0.0, 50.0, 3000)
+    c_disc = c_rel + rng.normal(0.0, 5.0, 3000)
+    c_disc[7] = np.inf
+    w = ctx.dsvgd_weights(torch.tensor(W.f32(c_rel), dtype=torch.float32, device="cuda"),
+                          torch.tensor(W.f32(c_disc), dtype=torch.float32, device="cuda"))
+    torch.cuda.synchronize()
+    ref = svgd.dsvgd_weights(W.f32(c_rel).astype(np.float64), W.f32(c_disc).astype(np.float64))
+    got = w.cpu().double().numpy()
+    assert got[7] == 0.0
+    assert np.allclose(got, ref, rtol=2e-5, atol=1e-7 * ref.max())
+
+
+@pytest.mark.parametrize("N,d", [(300, 18), (1000, 30), (2, 12)])
+def test_weighted_direction_matches_oracle(ctx, N, d):
+    import paper_2310_01775_amd as S
+    rng = np.random.default_rng(N)
+    th = W.f32(rng.standard_normal((N, d)))
+    g = W.f32(rng.standard_normal((N, d)) * 5.0)
+    w = rng.uniform(0.0, 3.0, N)
+    w = W.f32(w * N / w.sum())
+    h = torch.zeros(1, device="cuda")
+    phi = ctx.svgd_step_weighted(S.soa(th), S.soa(g), torch.tensor(w, dtype=torch.float32, device="cuda"), h_out=h)
+    torch.cuda.synchronize()
+    ref = svgd.svgd_phi(th, g, float(h.item()), w.astype(np.float64))
+    err = (np.abs(S.aos(phi) - ref) / np.abs(ref).max(axis=0, keepdims=True)).max()
+    print("weighted phi err", err, flush=True)
+    assert err < 2e-5
+
+
+def test_dsvgd_solve_equals_the_per_call_loop(ctx):
+    import paper_2310_01775_amd as S
+    scene = W.make_scene(63, 0, 3, 3, 40, 0.005)
+    w = W.cost_weights(rot=0.5)
+    th = W.make_particles(63, 0, 90, 3)
+    sc, cw = S.make_scene(scene), S.make_cost(w)
+    N = th.shape[0]
+    flat = S.soa(th)
+    m, v = torch.zeros_like(flat), torch.zeros_like(flat)
+    st = ctx.status_word()
+    ctx.solve([sc], [cw], [N], S.make_cfg(4, lr=1e-3, dsvgd=True, sgd_iters=2), flat, m, v, status=st)
+    torch.cuda.synchronize()
+    assert int(st.item()) == 0
+    theta = S.soa(th)
+    mm, vv = torch.zeros_like(theta), torch.zeros_like(theta)
+    tape = torch.empty(ctx.tape_floats(sc, N, 0), dtype=torch.float32, device="cuda")
+    minus = torch.full((N,), -1.0, device="cuda")
+    for t in range(1, 7):
+        c_rel = ctx.rollout_fwd(sc, cw, theta, tape=tape)
+        gr = ctx.rollout_adj(sc, cw, theta, tape, cost_bar=minus)
+        if t <= 4:
+            _, c_disc = ctx.plan_readout(sc, cw, theta)
+            phi = ctx.svgd_step_weighted(theta, gr, ctx.dsvgd_weights(c_rel, c_disc))
+        else:
+            phi = gr
+        ctx.adam_step(theta, phi, mm, vv, t, lr=1e-3)
+    torch.cuda.synchronize()
+    assert torch.equal(flat, theta)
+
+
+def test_dsvgd_solve_matches_oracle(ctx):
+    import paper_2310_01775_amd as S
+    scene, w, th = W.config_problem(1)
+    N = th.shape[0]
+    theta = S.soa(th)
+    m, v = torch.zeros_like(theta), torch.zeros_like(theta)
+    ctx.solve([S.make_scene(scene)], [S.make_cost(w)], [N], S.make_cfg(20, lr=1e-3, dsvgd=True), theta, m, v)
+    torch.cuda.synchronize()
+    ref = svgd.solve(scene, w, th, 20, lr=1e-3, dsvgd=True)
+    got = S.aos(theta)
+    err = (np.abs(got - ref["theta"]) / np.abs(ref["theta"]).max(axis=0, keepdims=True)).max()
+    norm = np.linalg.norm(got - ref["theta"]) / np.linalg.norm(ref["theta"])
+    print("dsvgd solve state error: worst", err, "normwise", norm, flush=True)
+    assert norm < 1e-4 and err < 1e-3

@@ -1,5 +1,7 @@
 """Host side of the plan read-out, and the oracle's two-phase solve and
 discrete read-out (CPU only)."""
+import math
+
 import numpy as np
 
 import workloads as W
@@ -44,3 +46,30 @@ def test_oracle_readout_executes_the_discrete_plan():
     got_modes, cost = sim.readout(scene, W.cost_weights(), th)
     assert list(got_modes[0]) == list(modes)
     assert np.isfinite(cost).all()
+
+
+def test_importance_weights_closed_form():
+    c_rel = np.array([1.0, 2.0, 0.5, 4.0])
+    c_disc = np.array([3.0, 2.0, 0.5, np.inf])
+    w = svgd.dsvgd_weights(c_rel, c_disc)
+    assert abs(w.mean() - 1.0) < 1e-15
+    assert w[3] == 0.0
+    # w_j / w_k = exp((C_disc,j - C_rel,j) - (C_disc,k - C_rel,k))
+    assert abs(w[0] / w[1] - np.exp(2.0)) < 1e-12 and abs(w[1] / w[2] - 1.0) < 1e-15
+    assert np.array_equal(svgd.dsvgd_weights(c_rel, c_rel), np.ones(4))
+
+
+def test_weighted_direction_against_a_double_loop():
+    rng = np.random.default_rng(3)
+    N, d, h = 5, 3, 0.7
+    th, g = rng.normal(size=(N, d)), rng.normal(size=(N, d))
+    w = rng.uniform(0.0, 2.0, N)
+    w *= N / w.sum()
+    ref = np.zeros((N, d))
+    for i in range(N):
+        for j in range(N):
+            k = math.exp(-((th[i] - th[j]) ** 2).sum() / h)
+            ref[i] += (w[j] / w.sum()) * k * (g[j] + (2.0 / h) * (th[i] - th[j]))
+    assert np.allclose(svgd.svgd_phi(th, g, h, w), ref, rtol=0, atol=1e-14)
+    # equal weights are the unweighted direction
+    assert np.allclose(svgd.svgd_phi(th, g, h, np.ones(N)), svgd.svgd_phi(th, g, h), rtol=0, atol=1e-15)
