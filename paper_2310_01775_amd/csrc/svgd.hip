@@ -215,20 +215,27 @@ __global__ __launch_bounds__(256) void k_update(int64_t n, float* __restrict__ t
                                                 const int* __restrict__ t_dev, float lr, float b1, float b2,
                                                 float eps, int use_adam) {
     const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (e >= n) return;
-    const float f = phi[e];
     if (!use_adam) {
-        theta[e] = theta[e] + lr * f;
+        if (e < n) theta[e] = theta[e] + lr * phi[e];
         return;
     }
-    const int t = t_dev ? t0 + *t_dev + 1 : t0;
-    const float gr = -f;
+    // bias-correction denominators, once per workgroup (the same expressions
+    // every thread would evaluate)
+    __shared__ float den[2];
+    if (threadIdx.x == 0) {
+        const int t = t_dev ? t0 + *t_dev + 1 : t0;
+        den[0] = 1.0f - powf(b1, (float)t);
+        den[1] = 1.0f - powf(b2, (float)t);
+    }
+    __syncthreads();
+    if (e >= n) return;
+    const float gr = -phi[e];
     const float mm = b1 * m[e] + (1.0f - b1) * gr;
     const float vv = b2 * v[e] + (1.0f - b2) * gr * gr;
     m[e] = mm;
     v[e] = vv;
-    const float mhat = mm / (1.0f - powf(b1, (float)t));
-    const float vhat = vv / (1.0f - powf(b2, (float)t));
+    const float mhat = mm / den[0];
+    const float vhat = vv / den[1];
     theta[e] = theta[e] - lr * mhat / (sqrtf(vhat) + eps);
 }
 
