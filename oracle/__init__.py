@@ -16,10 +16,13 @@ What it computes, step by step in the paper's order (Algorithm 1):
 * ``svgd``  -- squared pairwise distances, the median-heuristic bandwidth
   (Appendix D-B), the RBF kernel and the SVGD direction of Eq. (1), the Adam
   or plain update, and the solve loop.
+* ``structured`` -- the structured pusher kernel of Appendix E-C (per-action
+  RBF terms on the continuous parameters and on softmax(a_k), von Mises terms
+  on angles) and the SVGD direction under it, the kernel gradient by autodiff.
 * ``mlp``   -- the surrogate network (3 dense layers, GELU) with its input
   gradient and a training step, by autodiff in FP64.
 
 All arithmetic is float64.  Parity pins live in ``tests/test_oracle_*.py``.
 Functions without an external pin say "parity unpinned" in their docstring.
 """
-from . import sim, svgd  # noqa: F401
+from . import sim, structured, svgd  # noqa: F401
