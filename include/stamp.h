@@ -116,6 +116,9 @@ typedef struct stamp_solver_cfg {
                           (stamp_dsvgd_weights of the relaxed and the discrete plan's cost,
                           one extra rollout per particle and iteration); 0: w_j = 1 */
     int32_t reserved;  /* 0 */
+    const struct stamp_struct_kernel* kernel; /* NULL: the RBF kernel on theta; else the
+                          structured kernel (push layout; K is taken from each scene's H,
+                          the field itself is ignored) in every SVGD iteration */
 } stamp_solver_cfg;
 
 /* ---- context ----------------------------------------------------------- */
@@ -216,6 +219,42 @@ int32_t stamp_svgd_step_bf16(stamp_ctx* ctx, int32_t N, int32_t d, const float* 
 int32_t stamp_svgd_step_weighted(stamp_ctx* ctx, int32_t N, int32_t d, const float* theta,
                                  const float* grad_logp, const float* weights, float bandwidth, float* phi,
                                  float* h_out, void* workspace, size_t ws_bytes, void* stream);
+
+/* The structured pusher kernel of Appendix E-C, a sum over actions k of
+ *   alpha_g exp(-|g_k - g_k'|^2 / h_g)                 (RBF on the continuous part)
+ * + alpha_z exp(-|softmax(a_k) - softmax(a_k')|^2 / h_z) (RBF on the relaxed action)
+ * + alpha_p exp(kappa (cos(p_k - p_k') - 1))          (von Mises on an angle)
+ * over one of two particle layouts:
+ *   STAMP_KERNEL_PUSH: per action [a_k (4 logits), o_k, D_k], g_k = (o_k, D_k),
+ *                      no angle; d = 6K (the rollout's particle layout);
+ *   STAMP_KERNEL_POSE: [a_1..a_K, (x, y, phi)_1..K], g_k = (x, y), p_k = phi;
+ *                      d = 7K (the paper's goal-pose particles).
+ * h_g, h_z <= 0 select the median heuristic per component: h_c = max(m2_c /
+ * ln N, 1e-12) / K with m2_c the exact lower median over pairs i < j of
+ * sum_k |c_ik - c_jk|^2 on that component's features (softmax(a_k) or g_k). */
+#define STAMP_KERNEL_PUSH 0
+#define STAMP_KERNEL_POSE 1
+typedef struct stamp_struct_kernel {
+    int32_t layout;   /* STAMP_KERNEL_PUSH or STAMP_KERNEL_POSE */
+    int32_t K;        /* actions, 1..8 */
+    float alpha_g, alpha_z, alpha_p;  /* term weights (finite, >= 0) */
+    float h_g, h_z;   /* RBF bandwidths: > 0 fixed, <= 0 median heuristic */
+    float kappa;      /* von Mises concentration (finite, >= 0) */
+} stamp_struct_kernel;
+
+/* The SVGD direction of Eq. (1) (Eq. (4) with weights) under the structured
+ * kernel: phi_i = (1/N) sum_j w_j [ K(theta_j, theta_i) grad_logp_j
+ * + grad_{theta_j} K(theta_j, theta_i) ], the softmax term differentiated
+ * through the softmax.  theta, grad_logp, phi: [d][N] device; weights: [N]
+ * device or NULL (all 1); h_out: two device floats (h_g, h_z) or NULL.  N = 1
+ * gives phi = grad_logp.  Workspace: stamp_svgd_workspace_bytes(N, d).
+ * Errors: STAMP_EINVAL for null pointers, N < 1, a bad layout or K, d not
+ * matching the layout, or negative / non-finite term weights, kappa or bandwidths;
+ * STAMP_EUNSUPPORTED for N > 65536; STAMP_ENOSPACE. */
+int32_t stamp_svgd_step_structured(stamp_ctx* ctx, int32_t N, int32_t d, const float* theta,
+                                   const float* grad_logp, const float* weights,
+                                   const stamp_struct_kernel* kernel, float* phi, float* h_out,
+                                   void* workspace, size_t ws_bytes, void* stream);
 
 /* Importance weights of Eq. (4) (discrete SVGD): the relaxed plan's likelihood
  * over the discrete plan's, w_j proportional to exp(-C_relaxed,j) /

@@ -101,13 +101,17 @@ def plain_step(theta, phi, lr):
 
 def solve(scene, w, theta0, iters, t0=0, lr=1e-2, beta1=0.9, beta2=0.999, eps=1e-8,
           use_adam=True, fixed_bandwidth=0.0, m0=None, v0=None, grad_fn=None,
-          history=False, sgd_iters=0, dsvgd=False):
+          history=False, sgd_iters=0, dsvgd=False, kernel=None):
     """Algorithm 1 for fixed iteration counts: `iters` SVGD iterations, then
     `sgd_iters` SGD refinement iterations whose update takes each particle's
     own gradient of log rho (the second phase of Algorithm 1, Sec. III-C),
     with the same step rule and a continuing step counter.  dsvgd: the SVGD
     iterations weight the sum by the importance weights of Eq. (4), from the
     relaxed cost and the cost of executing each particle's discrete plan.
+
+    kernel: None for the RBF kernel on theta, or a structured-kernel spec
+    (``oracle.structured``, push layout; K is the scene's H) for the kernel of
+    Appendix E-C in every SVGD iteration.
 
     grad_fn(theta) -> (cost, dC/dtheta) defaults to the simulator rollout.
     Returns dict(theta, m, v, cost, modes, h, [hist]).
@@ -124,9 +128,13 @@ def solve(scene, w, theta0, iters, t0=0, lr=1e-2, beta1=0.9, beta2=0.999, eps=1e
         c, dC = grad_fn(th)
         g = -dC
         if it < iters:
-            h = bandwidth(th, fixed_bandwidth)
             wts = dsvgd_weights(c, sim.readout(scene, w, th)[1]) if dsvgd else None
-            phi = g if th.shape[0] == 1 else svgd_phi(th, g, h, wts)
+            if kernel is not None:
+                from . import structured
+                phi = structured.phi(th, g, dict(kernel, K=int(scene["H"])), w=wts)
+            else:
+                h = bandwidth(th, fixed_bandwidth)
+                phi = g if th.shape[0] == 1 else svgd_phi(th, g, h, wts)
         else:
             phi = g
         if use_adam:

@@ -43,11 +43,26 @@ class CostW(C.Structure):
                 ("o_max", C.c_float), ("d_max", C.c_float), ("traj_eps", C.c_float)]
 
 
+KERNEL_PUSH = 0  # per action [a_k (4 logits), o_k, D_k]; d = 6K
+KERNEL_POSE = 1  # [a_1..a_K, (x, y, phi)_1..K]; d = 7K
+
+
+class StructKernel(C.Structure):
+    _fields_ = [("layout", C.c_int32), ("K", C.c_int32), ("alpha_g", C.c_float), ("alpha_z", C.c_float),
+                ("alpha_p", C.c_float), ("h_g", C.c_float), ("h_z", C.c_float), ("kappa", C.c_float)]
+
+
+def struct_kernel(layout=KERNEL_PUSH, K=1, alpha_g=1.0, alpha_z=1.0, alpha_p=1.0, h_g=0.0, h_z=0.0,
+                  kappa=1.0) -> StructKernel:
+    """stamp_struct_kernel; h <= 0 selects the per-component median heuristic."""
+    return StructKernel(int(layout), int(K), alpha_g, alpha_z, alpha_p, h_g, h_z, kappa)
+
+
 class SolverCfg(C.Structure):
     _fields_ = [("iters", C.c_int32), ("t0", C.c_int32), ("lr", C.c_float), ("beta1", C.c_float),
                 ("beta2", C.c_float), ("adam_eps", C.c_float), ("use_adam", C.c_int32),
                 ("bandwidth", C.c_float), ("ckpt_every", C.c_int32), ("sgd_iters", C.c_int32),
-                ("dsvgd", C.c_int32), ("reserved", C.c_int32)]
+                ("dsvgd", C.c_int32), ("reserved", C.c_int32), ("kernel", C.POINTER(StructKernel))]
 
 
 class Surrogate(C.Structure):
@@ -75,6 +90,8 @@ _sig = {
     "stamp_readout_workspace_bytes": (_sz, [_P(Scene), _i32]),
     "stamp_dsvgd_weights": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp]),
     "stamp_svgd_step_weighted": (_i32, [_vp, _i32, _i32, _vp, _vp, _vp, C.c_float, _vp, _vp, _vp, _sz, _vp]),
+    "stamp_svgd_step_structured": (_i32, [_vp, _i32, _i32, _vp, _vp, _vp, _P(StructKernel), _vp, _vp, _vp, _sz,
+                                          _vp]),
     "stamp_plan_readout": (_i32, [_vp, _P(Scene), _P(CostW), _i32, _vp, _vp, _vp, _vp, _sz, _vp, _vp]),
     "stamp_svgd_workspace_bytes": (_sz, [_i32, _i32]),
     "stamp_solve_workspace_bytes": (_sz, [_i32, _P(Scene), _P(_i32), _P(SolverCfg)]),
@@ -142,9 +159,14 @@ def make_cost(w: dict) -> CostW:
 
 
 def make_cfg(iters, t0=0, lr=1e-3, beta1=0.9, beta2=0.999, adam_eps=1e-8, use_adam=True,
-             bandwidth=0.0, ckpt_every=0, sgd_iters=0, dsvgd=False) -> SolverCfg:
-    return SolverCfg(int(iters), int(t0), lr, beta1, beta2, adam_eps, int(bool(use_adam)), bandwidth,
-                     int(ckpt_every), int(sgd_iters), int(bool(dsvgd)), 0)
+             bandwidth=0.0, ckpt_every=0, sgd_iters=0, dsvgd=False, kernel=None) -> SolverCfg:
+    """stamp_solver_cfg; kernel: a StructKernel (push layout) or None for the RBF kernel on theta."""
+    cfg = SolverCfg(int(iters), int(t0), lr, beta1, beta2, adam_eps, int(bool(use_adam)), bandwidth,
+                    int(ckpt_every), int(sgd_iters), int(bool(dsvgd)), 0)
+    if kernel is not None:
+        cfg.kernel = C.pointer(kernel)
+        cfg._kernel_ref = kernel  # keeps the pointed-to struct alive with the cfg
+    return cfg
 
 
 def soa(theta_nd, device="cuda") -> torch.Tensor:
@@ -305,6 +327,24 @@ class Context:
         self._check(_lib.stamp_svgd_step_weighted(self._h, N, d, _ptr(theta), _ptr(grad_logp), _ptr(weights),
                                                   float(bandwidth), _ptr(phi), _ptr(h_out), _ptr(workspace),
                                                   workspace.numel(), _stream(stream)))
+        return phi
+
+    def svgd_step_structured(self, theta, grad_logp, kernel: StructKernel, weights=None, phi=None, h_out=None,
+                             workspace=None, stream=None):
+        """stamp_svgd_step_structured: phi [d][N]; h_out (2 floats) receives (h_g, h_z)."""
+        d, N = theta.shape
+        for t in (theta, grad_logp) + ((weights,) if weights is not None else ()):
+            if t.dtype != torch.float32:
+                raise ValueError("theta, grad_logp and weights must be float32")
+        if weights is not None and weights.numel() != N:
+            raise ValueError("weights must hold N floats")
+        if phi is None:
+            phi = torch.empty_like(theta)
+        if workspace is None:
+            workspace = self._bytes(self.svgd_workspace_bytes(N, d))
+        self._check(_lib.stamp_svgd_step_structured(self._h, N, d, _ptr(theta), _ptr(grad_logp), _ptr(weights),
+                                                    C.byref(kernel), _ptr(phi), _ptr(h_out), _ptr(workspace),
+                                                    workspace.numel(), _stream(stream)))
         return phi
 
     def plan_readout(self, scene: Scene, w: CostW, theta: torch.Tensor, modes=None, cost=None, workspace=None,

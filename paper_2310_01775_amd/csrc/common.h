@@ -101,7 +101,21 @@ struct SvgdLayout {
     size_t xb_off;                  // npad x kd bf16: centred particles, row-major
     size_t vt_off;                  // vc x npad bf16: V = [g | x~ | 1 | 0], chunked
     size_t p16_off;                 // splits16 x vc x npad floats: partial sums
+    // structured kernel: per-particle features (at most 2d rows of N floats)
+    // and the two RBF bandwidths
+    size_t sfeat_off, sh_off;
     size_t total;
+};
+
+// The structured pusher kernel (Appendix E-C), as the caller configures it.
+constexpr int kStructPush = 0;  // per action [a_k (4), o_k, D_k]; d = 6K
+constexpr int kStructPose = 1;  // [a_1..a_K, (x, y, phi)_1..K]; d = 7K
+constexpr int kStructMaxK = 8;
+struct StructKernel {
+    int layout, K;
+    float alpha_g, alpha_z, alpha_p;
+    float h_g, h_z;  // > 0 fixed, else the per-component median heuristic
+    float kappa;
 };
 
 constexpr int kMedSample = 8192;  // distances drawn for the sampled median

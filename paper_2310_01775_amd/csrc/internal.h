@@ -37,6 +37,14 @@ hipError_t launch_svgd(int N, int d, const float* theta, const float* grad_logp,
 // like the costs (problem p at its cost offset), or null.
 hipError_t launch_svgd_batched(const BatchPlan& P, const ProblemDesc* descs, const float* theta, const float* grad,
                                float* phi, char* ws, uint32_t* status, hipStream_t st, const float* wts = nullptr);
+// phi = (sum over the splits of partial[q][d][N], in split order) / N.
+hipError_t launch_phi_reduce(int N, int d, int splits, const float* partial, float* phi, uint32_t* status,
+                             hipStream_t st);
+// SVGD step under the structured pusher kernel (structured.hip); wts null or
+// importance weights; h_out (nullable) receives (h_g, h_z).
+hipError_t launch_svgd_structured(int N, int d, const float* theta, const float* grad, const float* wts,
+                                  const StructKernel& sk, float* phi, float* h_out, void* ws, const SvgdLayout& L,
+                                  uint32_t* status, hipStream_t st);
 // Importance weights of Eq. (4): w_j = N softmax_j(C_disc - C_rel), mean 1.
 hipError_t launch_dsvgd_weights(int N, const float* c_rel, const float* c_disc, float* w, hipStream_t st);
 hipError_t launch_dsvgd_weights_batched(int n_problems, const ProblemDesc* descs, const float* c_rel,

@@ -527,6 +527,40 @@ int32_t stamp_svgd_step_weighted(stamp_ctx* ctx, int32_t N, int32_t d, const flo
     return e == hipSuccess ? STAMP_OK : hip_fail(ctx, e, "svgd_step_weighted");
 }
 
+// validates a caller's structured kernel for particles of dimension d
+static int32_t check_struct(stamp_ctx* ctx, const stamp_struct_kernel* k, int d, StructKernel* out) {
+    if (!k) return fail(ctx, STAMP_EINVAL, "null structured kernel");
+    if (k->layout != STAMP_KERNEL_PUSH && k->layout != STAMP_KERNEL_POSE)
+        return fail(ctx, STAMP_EINVAL, "unknown kernel layout %d", k->layout);
+    if (k->K < 1 || k->K > kStructMaxK) return fail(ctx, STAMP_EINVAL, "kernel K=%d outside 1..%d", k->K, kStructMaxK);
+    const int want = (k->layout == STAMP_KERNEL_PUSH ? 6 : 7) * k->K;
+    if (d != want) return fail(ctx, STAMP_EINVAL, "d=%d, the kernel layout needs %d", d, want);
+    const float v[] = {k->alpha_g, k->alpha_z, k->alpha_p, k->kappa};
+    for (float x : v)
+        if (!isfinite(x) || x < 0.0f) return fail(ctx, STAMP_EINVAL, "kernel weights and kappa must be finite, >= 0");
+    if (!isfinite(k->h_g) || !isfinite(k->h_z)) return fail(ctx, STAMP_EINVAL, "non-finite kernel bandwidth");
+    *out = StructKernel{k->layout, k->K, k->alpha_g, k->alpha_z, k->alpha_p, k->h_g, k->h_z, k->kappa};
+    return STAMP_OK;
+}
+
+int32_t stamp_svgd_step_structured(stamp_ctx* ctx, int32_t N, int32_t d, const float* theta,
+                                   const float* grad_logp, const float* weights, const stamp_struct_kernel* kernel,
+                                   float* phi, float* h_out, void* workspace, size_t ws_bytes, void* stream) {
+    if (!ctx) return STAMP_EINVAL;
+    if (!theta || !grad_logp || !phi) return fail(ctx, STAMP_EINVAL, "null theta, grad_logp or phi");
+    if (N < 1 || d < 1) return fail(ctx, STAMP_EINVAL, "N=%d, d=%d must be >= 1", N, d);
+    StructKernel sk;
+    int32_t r = check_struct(ctx, kernel, d, &sk);
+    if (r) return r;
+    if (N > kMaxSvgdN) return fail(ctx, STAMP_EUNSUPPORTED, "svgd step supports N <= %d", kMaxSvgdN);
+    const SvgdLayout L = svgd_workspace_layout(N, d);
+    if (!workspace || ws_bytes < L.total)
+        return fail(ctx, STAMP_ENOSPACE, "svgd workspace %zu < %zu bytes", ws_bytes, L.total);
+    hipError_t e = launch_svgd_structured(N, d, theta, grad_logp, weights, sk, phi, h_out, workspace, L, nullptr,
+                                          (hipStream_t)stream);
+    return e == hipSuccess ? STAMP_OK : hip_fail(ctx, e, "svgd_step_structured");
+}
+
 int32_t stamp_svgd_step_bf16(stamp_ctx* ctx, int32_t N, int32_t d, const float* theta, const float* grad_logp,
                              float bandwidth, float* phi, float* h_out, void* workspace, size_t ws_bytes,
                              void* stream) {
@@ -573,6 +607,21 @@ static int32_t solve_impl(stamp_ctx* ctx, int32_t n_problems, const stamp_scene*
         cfg->dsvgd > 1)
         return fail(ctx, STAMP_EINVAL, "bad solver cfg");
     if (cfg->dsvgd && sur) return fail(ctx, STAMP_EINVAL, "importance weights apply to the simulator iterations only");
+    if (cfg->reserved != 0) return fail(ctx, STAMP_EINVAL, "cfg->reserved must be 0");
+    // structured kernel: the push layout with K = each problem's H
+    std::vector<StructKernel> skern;
+    if (cfg->kernel) {
+        if (cfg->kernel->layout != STAMP_KERNEL_PUSH)
+            return fail(ctx, STAMP_EINVAL, "the solve's particles take the push kernel layout");
+        if (sur && sur->phi_bf16) return fail(ctx, STAMP_EINVAL, "the structured kernel has no BF16 form");
+        skern.resize(n_problems);
+        for (int p = 0; p < n_problems; ++p) {
+            stamp_struct_kernel k = *cfg->kernel;
+            k.K = scenes[p].H;
+            int32_t r = check_struct(ctx, &k, 6 * scenes[p].H, &skern[p]);
+            if (r) return r;
+        }
+    }
     if (cfg->use_adam && (!adam_m || !adam_v)) return fail(ctx, STAMP_EINVAL, "Adam needs m and v");
     if (!isfinite(cfg->lr) || !isfinite(cfg->bandwidth)) return fail(ctx, STAMP_EINVAL, "non-finite lr/bandwidth");
     if (cfg->use_adam && !(cfg->beta1 >= 0 && cfg->beta1 < 1 && cfg->beta2 >= 0 && cfg->beta2 < 1 &&
@@ -751,6 +800,19 @@ static int32_t solve_impl(stamp_ctx* ctx, int32_t n_problems, const stamp_scene*
     // overwrites afterwards)
     float* d_cdisc = (float*)(ws + P.cdisc_off);
     float* d_wts = (float*)(ws + P.wts_off);
+    // the SVGD direction of every problem: the batched RBF step, or the
+    // structured kernel problem by problem
+    auto phi_step = [&](const float* wts) -> hipError_t {
+        if (skern.empty()) return launch_svgd_batched(B, d_desc, theta, d_grad, d_phi, d_svgd, status, st, wts);
+        for (int p = 0; p < n_problems; ++p) {
+            const ProblemDesc& D = P.descs[p];
+            hipError_t r = launch_svgd_structured(D.N, D.d, theta + D.theta_off, d_grad + D.theta_off,
+                                                  wts ? wts + D.cost_off : nullptr, skern[p], d_phi + D.theta_off,
+                                                  nullptr, d_svgd + D.svgd_off, D.sv, status, st);
+            if (r != hipSuccess) return r;
+        }
+        return hipSuccess;
+    };
     auto iteration = [&]() -> hipError_t {
         hipError_t r;
         if ((r = launch_rollout_fwd_batched(d_desc, d_roll, ntiles, tune.roll_block, rgrid, theta,
@@ -772,9 +834,7 @@ static int32_t solve_impl(stamp_ctx* ctx, int32_t n_problems, const stamp_scene*
                                                   d_wts, st)) != hipSuccess)
                 return r;
         }
-        if ((r = launch_svgd_batched(B, d_desc, theta, d_grad, d_phi, d_svgd, status, st,
-                                     cfg->dsvgd ? d_wts : nullptr)) != hipSuccess)
-            return r;
+        if ((r = phi_step(cfg->dsvgd ? d_wts : nullptr)) != hipSuccess) return r;
         if ((r = launch_update(P.n_theta, theta, d_phi, adam_m, adam_v, cfg->t0, d_ctr, cfg->lr, cfg->beta1,
                                cfg->beta2, cfg->adam_eps, cfg->use_adam, st)) != hipSuccess)
             return r;
@@ -812,7 +872,7 @@ static int32_t solve_impl(stamp_ctx* ctx, int32_t n_problems, const stamp_scene*
         for (int p = 0; p < n_problems; ++p)
             if ((r = sur_infer(p, nullptr, d_grad, -1.0f)) != hipSuccess) return r;
         r = sur->phi_bf16 ? launch_svgd16_batched(B, d_desc, theta, d_grad, d_phi, d_svgd, status, st)
-                          : launch_svgd_batched(B, d_desc, theta, d_grad, d_phi, d_svgd, status, st);
+                          : phi_step(nullptr);
         if (r != hipSuccess) return r;
         if ((r = launch_update(P.n_theta, theta, d_phi, adam_m, adam_v, cfg->t0, d_ctr, cfg->lr, cfg->beta1,
                                cfg->beta2, cfg->adam_eps, cfg->use_adam, st)) != hipSuccess)
@@ -823,7 +883,13 @@ static int32_t solve_impl(stamp_ctx* ctx, int32_t n_problems, const stamp_scene*
     snprintf(gkey, sizeof gkey, "|%p|%p|%p|%p|%p|%d|%d|%.9g|%.9g|%.9g|%.9g|%d|%d|%d|%d|", (void*)ws, (void*)theta,
              (void*)adam_m, (void*)adam_v, (void*)status, cfg->t0, cfg->use_adam, cfg->lr, cfg->beta1, cfg->beta2,
              cfg->adam_eps, tune.roll_block, rgrid, tune.phi_rows, cfg->dsvgd);
-    const std::string full_key = tkey + gkey;
+    std::string full_key = tkey + gkey;
+    if (cfg->kernel) {  // the kernel's parameters are arguments of the captured launches
+        const stamp_struct_kernel& k = *cfg->kernel;
+        snprintf(gkey, sizeof gkey, "struct|%.9g|%.9g|%.9g|%.9g|%.9g|%.9g|", k.alpha_g, k.alpha_z, k.alpha_p, k.h_g,
+                 k.h_z, k.kappa);
+        full_key += gkey;
+    }
     // capture `body` into `graph` unless the cached one was made for `key`
     auto ensure_graph = [&](hipGraphExec_t& graph, std::string& have_key, const std::string& key,
                             auto&& body) -> int32_t {

@@ -1,0 +1,267 @@
+// SVGD direction under the structured pusher kernel (Appendix E-C):
+//
+//   K(theta, theta') = sum_k [ alpha_g exp(-|g_k - g_k'|^2 / h_g)
+//                             + alpha_z exp(-|s_k - s_k'|^2 / h_z),  s_k = softmax(a_k)
+//                             + alpha_p exp(kappa (cos(p_k - p_k') - 1)) ]
+//   phi_i = (1/N) sum_j w_j [ K(theta_j, theta_i) g_j + grad_{theta_j} K(theta_j, theta_i) ]
+//
+// with the per-pair kernel gradient written out term by term:
+//   RBF on g:       (2 alpha_g / h_g) (g_i - g_j) e_g
+//   RBF on softmax: J(a_j) (2 alpha_z / h_z) (s_i - s_j) e_z,  J = diag(s_j) - s_j s_j^T,
+//                   so J u = s_j (u - s_j . u)
+//   von Mises:      alpha_p kappa sin(p_i - p_j) e_p,  the angle difference from
+//                   the cosines and sines of both angles.
+//
+// Layouts: push = per action [a_k (4 logits), o_k, D_k] with g_k = (o_k, D_k)
+// and no angle (d = 6K); pose = [a_1..a_K, (x, y, phi)_1..K] with g_k = (x, y)
+// and p_k = phi (d = 7K).  Bandwidths: per component, the median heuristic on
+// the features of every action, h_c = max(m2_c / ln N, 1e-12) / K (the exact
+// lower median from median.hip), unless the caller fixes them.
+//
+// Data flow: a prep kernel writes the features in structure-of-arrays form
+// (rows 4k+c: softmax; 4K+2k+c: g; 6K+2k, 6K+2k+1: cos p, sin p); the two
+// medians run on the softmax and g rows; the contraction (one thread per row
+// i, columns staged through LDS, the layout fixed at compile time so every
+// accumulator index is a constant) writes per-chunk partial sums that the
+// plain step's reduce kernel sums in a fixed order.
+#include <math.h>
+
+#include "common.h"
+#include "internal.h"
+
+namespace stamp {
+
+namespace {
+
+template <int LAYOUT>
+struct Lay;
+
+template <>
+struct Lay<kStructPush> {
+    static constexpr int per = 6, angles = 0;
+    __host__ __device__ static constexpr int a(int, int k, int c) { return 6 * k + c; }
+    __host__ __device__ static constexpr int g(int, int k, int c) { return 6 * k + 4 + c; }
+    __host__ __device__ static constexpr int p(int, int) { return -1; }
+};
+
+template <>
+struct Lay<kStructPose> {
+    static constexpr int per = 7, angles = 1;
+    __host__ __device__ static constexpr int a(int, int k, int c) { return 4 * k + c; }
+    __host__ __device__ static constexpr int g(int K, int k, int c) { return 4 * K + 3 * k + c; }
+    __host__ __device__ static constexpr int p(int K, int k) { return 4 * K + 3 * k + 2; }
+};
+
+// ---- features, one thread per particle -----------------------------------------
+template <int LAYOUT>
+__global__ __launch_bounds__(256) void k_struct_prep(int N, int K, const float* __restrict__ theta,
+                                                     float* __restrict__ feat) {
+    using L = Lay<LAYOUT>;
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= N) return;
+    for (int k = 0; k < K; ++k) {
+        float a[4], m = -INFINITY;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            a[c] = theta[(int64_t)L::a(K, k, c) * N + i];
+            m = fmaxf(m, a[c]);
+        }
+        float e[4], s = 0.0f;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            e[c] = expf(a[c] - m);
+            s += e[c];
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) feat[(int64_t)(4 * k + c) * N + i] = e[c] / s;
+#pragma unroll
+        for (int c = 0; c < 2; ++c) feat[(int64_t)(4 * K + 2 * k + c) * N + i] = theta[(int64_t)L::g(K, k, c) * N + i];
+        if constexpr (L::angles != 0) {
+            const float p = theta[(int64_t)L::p(K, k) * N + i];
+            feat[(int64_t)(6 * K + 2 * k) * N + i] = cosf(p);
+            feat[(int64_t)(6 * K + 2 * k + 1) * N + i] = sinf(p);
+        }
+    }
+}
+
+// hs[c] = the fixed bandwidth, or the median heuristic's m2 / ln N (floored) / K
+__global__ void k_struct_h(const SelState* __restrict__ sel, float* __restrict__ hs, int c, int K, float fixed) {
+    if (threadIdx.x == 0) hs[c] = fixed > 0.0f ? fixed : sel->h / (float)K;
+}
+
+// N = 1: phi = g, and the bandwidths a lone particle reports (fixed, else 1)
+__global__ void k_struct_single(int d, const float* __restrict__ g, float* __restrict__ phi, float* __restrict__ hs,
+                                float hg, float hz) {
+    for (int l = threadIdx.x; l < d; l += blockDim.x) phi[l] = g[l];
+    if (threadIdx.x == 0) {
+        hs[0] = hg > 0.0f ? hg : 1.0f;
+        hs[1] = hz > 0.0f ? hz : 1.0f;
+    }
+}
+
+__global__ void k_copy2(const float* __restrict__ a, float* __restrict__ b) {
+    if (threadIdx.x < 2) b[threadIdx.x] = a[threadIdx.x];
+}
+
+struct StructArgs {
+    int N, chunk;
+    float alpha_g, alpha_z, alpha_p, kappa;
+    const float* feat;
+    const float* grad;
+    const float* wts;
+    const float* hs;
+    float* partial;
+};
+
+// ---- contraction: partial sums over the columns of one chunk --------------------
+template <int KA, int LAYOUT>
+__global__ __launch_bounds__(256) void k_struct_partial(StructArgs a) {
+    using L = Lay<LAYOUT>;
+    constexpr int NA = L::angles;
+    constexpr int NF = KA * (6 + 2 * NA);  // staged features per column
+    constexpr int D = KA * L::per;         // coordinates
+    constexpr int JT = 64;
+    constexpr float kLog2e = 1.44269504088896341f;
+    __shared__ float fj[JT][NF];
+    __shared__ float gj[JT][D];
+    __shared__ float wj[JT];
+    const int N = a.N;
+    const int split = blockIdx.y;
+    const int j0 = split * a.chunk, j1 = min(j0 + a.chunk, N);
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int ii = min(i, N - 1);
+    const float hg = a.hs[0], hz = a.hs[1];
+    const float cg = -kLog2e / hg, cz = -kLog2e / hz, cp = a.kappa * kLog2e;
+    const float rg0 = 2.0f * a.alpha_g / hg, rz0 = 2.0f * a.alpha_z / hz, rp0 = a.alpha_p * a.kappa;
+    float fi[NF], acc[D];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) fi[f] = a.feat[(int64_t)f * N + ii];
+#pragma unroll
+    for (int l = 0; l < D; ++l) acc[l] = 0.0f;
+    for (int jb = j0; jb < j1; jb += JT) {
+        const int njc = min(JT, j1 - jb);
+        __syncthreads();
+        for (int e = threadIdx.x; e < JT * NF; e += blockDim.x) {  // consecutive threads, consecutive columns
+            const int jj = e % JT, f = e / JT;
+            fj[jj][f] = jj < njc ? a.feat[(int64_t)f * N + jb + jj] : 0.0f;
+        }
+        for (int e = threadIdx.x; e < JT * D; e += blockDim.x) {
+            const int jj = e % JT, l = e / JT;
+            gj[jj][l] = jj < njc ? a.grad[(int64_t)l * N + jb + jj] : 0.0f;
+        }
+        for (int jj = threadIdx.x; jj < JT; jj += blockDim.x) wj[jj] = (a.wts && jj < njc) ? a.wts[jb + jj] : 1.0f;
+        __syncthreads();
+        for (int jj = 0; jj < njc; ++jj) {
+            const float w = wj[jj];
+            const float rz1 = rz0 * w, rg1 = rg0 * w, rp1 = rp0 * w;
+            float ksum = 0.0f;
+#pragma unroll
+            for (int k = 0; k < KA; ++k) {
+                // RBF on softmax(a_k), its gradient through the softmax at a_j
+                float u[4], dz = 0.0f, su = 0.0f;
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    u[c] = fi[4 * k + c] - fj[jj][4 * k + c];
+                    dz = fmaf(u[c], u[c], dz);
+                    su = fmaf(fj[jj][4 * k + c], u[c], su);
+                }
+                const float ez = hw_exp2(cz * dz);
+                const float rz = rz1 * ez;
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+                    acc[L::a(KA, k, c)] = fmaf(rz * fj[jj][4 * k + c], u[c] - su, acc[L::a(KA, k, c)]);
+                // RBF on g_k
+                const float v0 = fi[4 * KA + 2 * k] - fj[jj][4 * KA + 2 * k];
+                const float v1 = fi[4 * KA + 2 * k + 1] - fj[jj][4 * KA + 2 * k + 1];
+                const float eg = hw_exp2(cg * fmaf(v0, v0, v1 * v1));
+                const float rg = rg1 * eg;
+                acc[L::g(KA, k, 0)] = fmaf(rg, v0, acc[L::g(KA, k, 0)]);
+                acc[L::g(KA, k, 1)] = fmaf(rg, v1, acc[L::g(KA, k, 1)]);
+                ksum = fmaf(a.alpha_z, ez, fmaf(a.alpha_g, eg, ksum));
+                if constexpr (NA != 0) {  // von Mises on p_k
+                    const float ci = fi[6 * KA + 2 * k], si = fi[6 * KA + 2 * k + 1];
+                    const float cj = fj[jj][6 * KA + 2 * k], sj = fj[jj][6 * KA + 2 * k + 1];
+                    const float cd = fmaf(ci, cj, si * sj);   // cos(p_i - p_j)
+                    const float sd = fmaf(si, cj, -ci * sj);  // sin(p_i - p_j)
+                    const float ep = hw_exp2(cp * (cd - 1.0f));
+                    acc[L::p(KA, k)] = fmaf(rp1 * ep, sd, acc[L::p(KA, k)]);
+                    ksum = fmaf(a.alpha_p, ep, ksum);
+                }
+            }
+            const float kw = ksum * w;
+#pragma unroll
+            for (int l = 0; l < D; ++l) acc[l] = fmaf(kw, gj[jj][l], acc[l]);
+        }
+    }
+    if (i < N) {
+        float* out = a.partial + (int64_t)split * D * N;
+#pragma unroll
+        for (int l = 0; l < D; ++l) out[(int64_t)l * N + i] = acc[l];
+    }
+}
+
+template <int LAYOUT>
+void launch_partial(int K, dim3 grid, const StructArgs& a, hipStream_t st) {
+    switch (K) {
+        case 1: hipLaunchKernelGGL((k_struct_partial<1, LAYOUT>), grid, dim3(256), 0, st, a); break;
+        case 2: hipLaunchKernelGGL((k_struct_partial<2, LAYOUT>), grid, dim3(256), 0, st, a); break;
+        case 3: hipLaunchKernelGGL((k_struct_partial<3, LAYOUT>), grid, dim3(256), 0, st, a); break;
+        case 4: hipLaunchKernelGGL((k_struct_partial<4, LAYOUT>), grid, dim3(256), 0, st, a); break;
+        case 5: hipLaunchKernelGGL((k_struct_partial<5, LAYOUT>), grid, dim3(256), 0, st, a); break;
+        case 6: hipLaunchKernelGGL((k_struct_partial<6, LAYOUT>), grid, dim3(256), 0, st, a); break;
+        case 7: hipLaunchKernelGGL((k_struct_partial<7, LAYOUT>), grid, dim3(256), 0, st, a); break;
+        default: hipLaunchKernelGGL((k_struct_partial<8, LAYOUT>), grid, dim3(256), 0, st, a); break;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_svgd_structured(int N, int d, const float* theta, const float* grad, const float* wts,
+                                  const StructKernel& sk, float* phi, float* h_out, void* ws, const SvgdLayout& L,
+                                  uint32_t* status, hipStream_t st) {
+    char* base = static_cast<char*>(ws);
+    float* feat = reinterpret_cast<float*>(base + L.sfeat_off);
+    float* hs = reinterpret_cast<float*>(base + L.sh_off);
+    const SelState* sel = reinterpret_cast<const SelState*>(base + L.sel_off);
+    const int K = sk.K;
+    hipError_t e;
+    if (N == 1) {
+        hipLaunchKernelGGL(k_struct_single, dim3(1), dim3(64), 0, st, d, grad, phi, hs, sk.h_g, sk.h_z);
+    } else {
+        if (sk.layout == kStructPush)
+            hipLaunchKernelGGL(k_struct_prep<kStructPush>, dim3((N + 255) / 256), dim3(256), 0, st, N, K, theta, feat);
+        else
+            hipLaunchKernelGGL(k_struct_prep<kStructPose>, dim3((N + 255) / 256), dim3(256), 0, st, N, K, theta, feat);
+        // bandwidths: c = 0 the g rows (2K), c = 1 the softmax rows (4K)
+        for (int c = 0; c < 2; ++c) {
+            const float fixed = c == 0 ? sk.h_g : sk.h_z;
+            if (!(fixed > 0.0f)) {
+                const float* rows = c == 0 ? feat + (int64_t)4 * K * N : feat;
+                if ((e = launch_median(N, c == 0 ? 2 * K : 4 * K, rows, 0.0f, 1, ws, L, nullptr, st)) != hipSuccess)
+                    return e;
+            }
+            hipLaunchKernelGGL(k_struct_h, dim3(1), dim3(64), 0, st, sel, hs, c, K, fixed);
+        }
+        StructArgs a;
+        a.N = N;
+        a.chunk = (N + L.splits - 1) / L.splits;
+        a.alpha_g = sk.alpha_g;
+        a.alpha_z = sk.alpha_z;
+        a.alpha_p = sk.alpha_p;
+        a.kappa = sk.kappa;
+        a.feat = feat;
+        a.grad = grad;
+        a.wts = wts;
+        a.hs = hs;
+        a.partial = reinterpret_cast<float*>(base + L.part_off);
+        const dim3 grid((N + 255) / 256, L.splits);
+        if (sk.layout == kStructPush) launch_partial<kStructPush>(K, grid, a, st);
+        else launch_partial<kStructPose>(K, grid, a, st);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if ((e = launch_phi_reduce(N, d, L.splits, a.partial, phi, status, st)) != hipSuccess) return e;
+    }
+    if (h_out) hipLaunchKernelGGL(k_copy2, dim3(1), dim3(64), 0, st, hs, h_out);
+    return hipGetLastError();
+}
+
+}  // namespace stamp

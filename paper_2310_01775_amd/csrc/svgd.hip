@@ -345,6 +345,10 @@ SvgdLayout svgd_workspace_layout(int N, int d) {
     off = align256(off + (size_t)L.vc * L.npad * 2);
     L.p16_off = off;
     off = align256(off + (size_t)L.splits16 * L.vc * L.npad * 4);
+    L.sfeat_off = off;
+    off = align256(off + (size_t)2 * d * N * 4);
+    L.sh_off = off;
+    off = align256(off + 2 * 4);
     L.total = off;
     return L;
 }
@@ -394,6 +398,14 @@ hipError_t launch_svgd_batched(const BatchPlan& P, const ProblemDesc* descs, con
         }
     }
     hipLaunchKernelGGL(k_phi_reduce_batched, dim3(P.n_red), dim3(256), 0, st, descs, P.red_work, grad, phi, ws,
+                       status);
+    return hipGetLastError();
+}
+
+hipError_t launch_phi_reduce(int N, int d, int splits, const float* partial, float* phi, uint32_t* status,
+                             hipStream_t st) {
+    const int64_t n = (int64_t)d * N;
+    hipLaunchKernelGGL(k_phi_reduce, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, N, d, splits, partial, phi,
                        status);
     return hipGetLastError();
 }

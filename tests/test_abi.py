@@ -42,14 +42,17 @@ def test_struct_layouts_match_the_header(tmp_path):
                     ' sizeof(stamp_cost_w), sizeof(stamp_solver_cfg), offsetof(stamp_scene, goal),'
                     ' offsetof(stamp_scene, eps_r), offsetof(stamp_solver_cfg, ckpt_every),'
                     ' sizeof(stamp_surrogate), offsetof(stamp_surrogate, params), offsetof(stamp_surrogate, enc),'
-                    ' sizeof(stamp_surrogate_report));return 0;}\n')
+                    ' sizeof(stamp_surrogate_report));'
+                    'printf("%zu %zu %zu\\n", sizeof(stamp_struct_kernel), offsetof(stamp_struct_kernel, kappa),'
+                    ' offsetof(stamp_solver_cfg, kernel));return 0;}\n')
     exe = tmp_path / "sz"
     subprocess.run(["gcc", "-I" + os.path.join(ROOT, "include"), str(prog), "-o", str(exe)], check=True)
     got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
     want = [ctypes.sizeof(S.Scene), ctypes.sizeof(S.CostW), ctypes.sizeof(S.SolverCfg),
             S.Scene.goal.offset, S.Scene.eps_r.offset, S.SolverCfg.ckpt_every.offset,
             ctypes.sizeof(S.Surrogate), S.Surrogate.params.offset, S.Surrogate.enc.offset,
-            ctypes.sizeof(S.SurrogateReport)]
+            ctypes.sizeof(S.SurrogateReport), ctypes.sizeof(S.StructKernel), S.StructKernel.kappa.offset,
+            S.SolverCfg.kernel.offset]
     assert got == want
 
 
