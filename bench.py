@@ -114,11 +114,14 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--workload", default="plain", choices=["plain", "batched", "long", "surrogate", "refine"],
+    ap.add_argument("--workload", default="plain", choices=["plain", "batched", "long", "surrogate", "refine",
+                                                              "structured"],
                     help="plain: the metric's workload; batched: 64 uneven problems in one graph-replayed "
                          "solve; long: checkpointed differentiation (report only); surrogate: the learned "
                          "surrogate form against the plain method at N=16384 (report only); refine: SVGD "
-                         "alone against SVGD followed by SGD refinement, with the plan read-out (report only)")
+                         "alone against SVGD followed by SGD refinement, with the plan read-out (report only); "
+                         "structured: the structured pusher kernel against the RBF kernel (step time, and "
+                         "solutions per plan after a solve; report only)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -152,6 +155,8 @@ def main():
         return bench_surrogate(args)
     if args.workload == "refine":
         return bench_refine(args)
+    if args.workload == "structured":
+        return bench_structured(args)
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     cfg = W.CONFIGS[2]
@@ -461,6 +466,69 @@ def bench_refine(args):
         out[name] = {"wall_s": wall, "particle_iters_per_s": N * (it + sgd) / wall,
                      "relaxed_cost_median": float(c.median()), "relaxed_cost_p10": float(c.quantile(0.1)),
                      "readout": rd}
+    assert int(status.item()) == 0
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+def bench_structured(args):
+    """The structured pusher kernel (Appendix E-C: per-action RBF terms on
+    (o_k, D_k) and on softmax(a_k)) against the RBF kernel on theta: the SVGD
+    step's time at N=1024, H=3 and N=16384, H=5 (median-heuristic bandwidths,
+    HIP events around 20 steps), then 300 graph-replayed SVGD iterations with
+    each kernel on the N=1024, B=3, H=3 scene and the plan read-out."""
+    import numpy as np
+    import torch
+
+    import paper_2310_01775_amd as S
+    import workloads as W
+    from paper_2310_01775_amd import readout
+
+    ctx = S.Context(0)
+    out = {"workload": "structured kernel vs RBF on theta: step time at N=1024/H=3 and N=16384/H=5; "
+                       f"300-iteration solves at N=1024, B=3, H=3, solutions = executed cost < {W.SOLUTION_COST}"}
+    for cfg_i in (2, 5):
+        scene, w, th = W.config_problem(cfg_i)
+        N, d = th.shape
+        H = int(scene["H"])
+        theta = S.soa(th)
+        g = S.soa(np.random.default_rng(cfg_i).normal(0.0, 20.0, (N, d)))
+        ws = ctx._bytes(ctx.svgd_workspace_bytes(N, d))
+        phi = torch.empty_like(theta)
+        kern = S.struct_kernel(S.KERNEL_PUSH, H)
+        row = {}
+        for name, fn in (("rbf_ms", lambda: ctx.svgd_step(theta, g, 0.0, phi=phi, workspace=ws)),
+                         ("structured_ms", lambda: ctx.svgd_step_structured(theta, g, kern, phi=phi, workspace=ws))):
+            for _ in range(3):
+                fn()
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(20):
+                fn()
+            b.record()
+            torch.cuda.synchronize()
+            row[name] = a.elapsed_time(b) / 20
+        out[f"step_N{N}_H{H}"] = row
+    scene, w, th = W.config_problem(2)
+    N, H = th.shape[0], int(scene["H"])
+    sc, cw = S.make_scene(scene), S.make_cost(w)
+    status = ctx.status_word()
+    for name, kern in (("rbf", None), ("structured", S.struct_kernel(S.KERNEL_PUSH, H))):
+        cfg = S.make_cfg(300, lr=W.DEFAULT_ADAM["lr"], kernel=kern)
+        work = ctx._bytes(ctx.solve_workspace_bytes([sc], [N], cfg))
+        for rep in range(2):  # the first run tunes and captures
+            theta = S.soa(th)
+            m, v = torch.zeros_like(theta), torch.zeros_like(theta)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            cost = ctx.solve([sc], [cw], [N], cfg, theta, m, v, workspace=work, status=status)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t
+        c = cost.double()
+        out[f"solve_{name}"] = {"wall_s": wall, "particle_iters_per_s": N * 300 / wall,
+                                "relaxed_cost_median": float(c.median()),
+                                "readout": readout.report(ctx, sc, cw, theta, W.SOLUTION_COST)}
     assert int(status.item()) == 0
     print(json.dumps(out), flush=True)
     ctx.close()

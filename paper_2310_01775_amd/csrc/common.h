@@ -102,7 +102,7 @@ struct SvgdLayout {
     size_t vt_off;                  // vc x npad bf16: V = [g | x~ | 1 | 0], chunked
     size_t p16_off;                 // splits16 x vc x npad floats: partial sums
     // structured kernel: per-particle features (at most 2d rows of N floats)
-    // and the two RBF bandwidths
+    // and the selection state of its second median
     size_t sfeat_off, sh_off;
     size_t total;
 };

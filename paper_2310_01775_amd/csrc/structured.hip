@@ -20,7 +20,8 @@
 //
 // Data flow: a prep kernel writes the features in structure-of-arrays form
 // (rows 4k+c: softmax; 4K+2k+c: g; 6K+2k, 6K+2k+1: cos p, sin p); the two
-// medians run on the softmax and g rows; the contraction (one thread per row
+// medians run on the softmax and g rows, each into its own selection state,
+// which the contraction reads; the contraction (one thread per row
 // i, columns staged through LDS, the layout fixed at compile time so every
 // accumulator index is a constant) writes per-chunk partial sums that the
 // plain step's reduce kernel sums in a fixed order.
@@ -84,23 +85,26 @@ __global__ __launch_bounds__(256) void k_struct_prep(int N, int K, const float* 
     }
 }
 
-// hs[c] = the fixed bandwidth, or the median heuristic's m2 / ln N (floored) / K
-__global__ void k_struct_h(const SelState* __restrict__ sel, float* __restrict__ hs, int c, int K, float fixed) {
-    if (threadIdx.x == 0) hs[c] = fixed > 0.0f ? fixed : sel->h / (float)K;
-}
+// Bandwidth c: the fixed value, or the median heuristic's m2 / ln N (floored)
+// over K, from that component's own median state.
+struct StructBw {
+    const SelState* sel[2];  // g, softmax
+    float fixed[2];
+    int K;
+    __device__ __forceinline__ float h(int c) const { return fixed[c] > 0.0f ? fixed[c] : sel[c]->h / (float)K; }
+};
 
-// N = 1: phi = g, and the bandwidths a lone particle reports (fixed, else 1)
-__global__ void k_struct_single(int d, const float* __restrict__ g, float* __restrict__ phi, float* __restrict__ hs,
-                                float hg, float hz) {
+// N = 1: phi = g
+__global__ void k_struct_single(int d, const float* __restrict__ g, float* __restrict__ phi) {
     for (int l = threadIdx.x; l < d; l += blockDim.x) phi[l] = g[l];
-    if (threadIdx.x == 0) {
-        hs[0] = hg > 0.0f ? hg : 1.0f;
-        hs[1] = hz > 0.0f ? hz : 1.0f;
-    }
 }
 
-__global__ void k_copy2(const float* __restrict__ a, float* __restrict__ b) {
-    if (threadIdx.x < 2) b[threadIdx.x] = a[threadIdx.x];
+// the bandwidths for the caller (a lone particle reports the fixed ones, else 1)
+__global__ void k_struct_hout(StructBw bw, int N, float* __restrict__ h_out) {
+    if (threadIdx.x < 2) {
+        const int c = threadIdx.x;
+        h_out[c] = N > 1 ? bw.h(c) : (bw.fixed[c] > 0.0f ? bw.fixed[c] : 1.0f);
+    }
 }
 
 struct StructArgs {
@@ -109,7 +113,7 @@ struct StructArgs {
     const float* feat;
     const float* grad;
     const float* wts;
-    const float* hs;
+    StructBw bw;
     float* partial;
 };
 
@@ -130,7 +134,7 @@ __global__ __launch_bounds__(256) void k_struct_partial(StructArgs a) {
     const int j0 = split * a.chunk, j1 = min(j0 + a.chunk, N);
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int ii = min(i, N - 1);
-    const float hg = a.hs[0], hz = a.hs[1];
+    const float hg = a.bw.h(0), hz = a.bw.h(1);
     const float cg = -kLog2e / hg, cz = -kLog2e / hz, cp = a.kappa * kLog2e;
     const float rg0 = 2.0f * a.alpha_g / hg, rz0 = 2.0f * a.alpha_z / hz, rp0 = a.alpha_p * a.kappa;
     float fi[NF], acc[D];
@@ -221,27 +225,31 @@ hipError_t launch_svgd_structured(int N, int d, const float* theta, const float*
                                   uint32_t* status, hipStream_t st) {
     char* base = static_cast<char*>(ws);
     float* feat = reinterpret_cast<float*>(base + L.sfeat_off);
-    float* hs = reinterpret_cast<float*>(base + L.sh_off);
-    const SelState* sel = reinterpret_cast<const SelState*>(base + L.sel_off);
     const int K = sk.K;
+    // each component's median keeps its own state: the g one in the
+    // structured region, the softmax one at the plain step's place
+    SvgdLayout Lg = L;
+    Lg.sel_off = L.sh_off;
+    StructBw bw;
+    bw.sel[0] = reinterpret_cast<const SelState*>(base + Lg.sel_off);
+    bw.sel[1] = reinterpret_cast<const SelState*>(base + L.sel_off);
+    bw.fixed[0] = sk.h_g;
+    bw.fixed[1] = sk.h_z;
+    bw.K = K;
     hipError_t e;
     if (N == 1) {
-        hipLaunchKernelGGL(k_struct_single, dim3(1), dim3(64), 0, st, d, grad, phi, hs, sk.h_g, sk.h_z);
+        hipLaunchKernelGGL(k_struct_single, dim3(1), dim3(64), 0, st, d, grad, phi);
     } else {
         if (sk.layout == kStructPush)
             hipLaunchKernelGGL(k_struct_prep<kStructPush>, dim3((N + 255) / 256), dim3(256), 0, st, N, K, theta, feat);
         else
             hipLaunchKernelGGL(k_struct_prep<kStructPose>, dim3((N + 255) / 256), dim3(256), 0, st, N, K, theta, feat);
-        // bandwidths: c = 0 the g rows (2K), c = 1 the softmax rows (4K)
-        for (int c = 0; c < 2; ++c) {
-            const float fixed = c == 0 ? sk.h_g : sk.h_z;
-            if (!(fixed > 0.0f)) {
-                const float* rows = c == 0 ? feat + (int64_t)4 * K * N : feat;
-                if ((e = launch_median(N, c == 0 ? 2 * K : 4 * K, rows, 0.0f, 1, ws, L, nullptr, st)) != hipSuccess)
-                    return e;
-            }
-            hipLaunchKernelGGL(k_struct_h, dim3(1), dim3(64), 0, st, sel, hs, c, K, fixed);
-        }
+        // medians: the g rows (2K) and the softmax rows (4K)
+        if (!(sk.h_g > 0.0f) &&
+            (e = launch_median(N, 2 * K, feat + (int64_t)4 * K * N, 0.0f, 1, ws, Lg, nullptr, st)) != hipSuccess)
+            return e;
+        if (!(sk.h_z > 0.0f) && (e = launch_median(N, 4 * K, feat, 0.0f, 1, ws, L, nullptr, st)) != hipSuccess)
+            return e;
         StructArgs a;
         a.N = N;
         a.chunk = (N + L.splits - 1) / L.splits;
@@ -252,7 +260,7 @@ hipError_t launch_svgd_structured(int N, int d, const float* theta, const float*
         a.feat = feat;
         a.grad = grad;
         a.wts = wts;
-        a.hs = hs;
+        a.bw = bw;
         a.partial = reinterpret_cast<float*>(base + L.part_off);
         const dim3 grid((N + 255) / 256, L.splits);
         if (sk.layout == kStructPush) launch_partial<kStructPush>(K, grid, a, st);
@@ -260,7 +268,7 @@ hipError_t launch_svgd_structured(int N, int d, const float* theta, const float*
         if ((e = hipGetLastError()) != hipSuccess) return e;
         if ((e = launch_phi_reduce(N, d, L.splits, a.partial, phi, status, st)) != hipSuccess) return e;
     }
-    if (h_out) hipLaunchKernelGGL(k_copy2, dim3(1), dim3(64), 0, st, hs, h_out);
+    if (h_out) hipLaunchKernelGGL(k_struct_hout, dim3(1), dim3(64), 0, st, bw, N, h_out);
     return hipGetLastError();
 }
 

@@ -348,7 +348,7 @@ SvgdLayout svgd_workspace_layout(int N, int d) {
     L.sfeat_off = off;
     off = align256(off + (size_t)2 * d * N * 4);
     L.sh_off = off;
-    off = align256(off + 2 * 4);
+    off = align256(off + sizeof(SelState));
     L.total = off;
     return L;
 }
