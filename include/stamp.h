@@ -196,6 +196,21 @@ int32_t stamp_svgd_step(stamp_ctx* ctx, int32_t N, int32_t d, const float* theta
                         const float* grad_logp, float bandwidth, float* phi, float* h_out,
                         void* workspace, size_t ws_bytes, void* stream);
 
+/* stamp_svgd_step in two halves, for callers that overlap the bandwidth with
+ * the rollout (it depends on theta only):
+ *   stamp_svgd_bandwidth: h (median heuristic, or bandwidth if > 0) into the
+ *     workspace (and h_out if not NULL);
+ *   stamp_svgd_direction: phi from theta, grad_logp and the h that the
+ *     workspace holds, i.e. from the last stamp_svgd_bandwidth call on this
+ *     workspace for the same theta; weights [N] device or NULL (Eq. (4)).
+ * The caller orders the two calls (same stream, or an event between streams)
+ * and must not run another call on the same workspace in between.  Arguments,
+ * layouts and errors as stamp_svgd_step. */
+int32_t stamp_svgd_bandwidth(stamp_ctx* ctx, int32_t N, int32_t d, const float* theta, float bandwidth,
+                             float* h_out, void* workspace, size_t ws_bytes, void* stream);
+int32_t stamp_svgd_direction(stamp_ctx* ctx, int32_t N, int32_t d, const float* theta, const float* grad_logp,
+                             const float* weights, float* phi, void* workspace, size_t ws_bytes, void* stream);
+
 /* The SVGD direction of stamp_svgd_step in reduced precision on the BF16
  * matrix cores, for iterations whose gradients are approximate anyway (the
  * surrogate phase).  Differences from stamp_svgd_step:

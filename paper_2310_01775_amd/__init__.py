@@ -90,6 +90,8 @@ _sig = {
     "stamp_readout_workspace_bytes": (_sz, [_P(Scene), _i32]),
     "stamp_dsvgd_weights": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp]),
     "stamp_svgd_step_weighted": (_i32, [_vp, _i32, _i32, _vp, _vp, _vp, C.c_float, _vp, _vp, _vp, _sz, _vp]),
+    "stamp_svgd_bandwidth": (_i32, [_vp, _i32, _i32, _vp, _f32, _vp, _vp, _sz, _vp]),
+    "stamp_svgd_direction": (_i32, [_vp, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
     "stamp_svgd_step_structured": (_i32, [_vp, _i32, _i32, _vp, _vp, _vp, _P(StructKernel), _vp, _vp, _vp, _sz,
                                           _vp]),
     "stamp_plan_readout": (_i32, [_vp, _P(Scene), _P(CostW), _i32, _vp, _vp, _vp, _vp, _sz, _vp, _vp]),
@@ -327,6 +329,24 @@ class Context:
         self._check(_lib.stamp_svgd_step_weighted(self._h, N, d, _ptr(theta), _ptr(grad_logp), _ptr(weights),
                                                   float(bandwidth), _ptr(phi), _ptr(h_out), _ptr(workspace),
                                                   workspace.numel(), _stream(stream)))
+        return phi
+
+    def svgd_bandwidth(self, theta, bandwidth: float = 0.0, h_out=None, workspace=None, stream=None):
+        """stamp_svgd_bandwidth: the first half of svgd_step; returns the workspace."""
+        d, N = theta.shape
+        if workspace is None:
+            workspace = self._bytes(self.svgd_workspace_bytes(N, d))
+        self._check(_lib.stamp_svgd_bandwidth(self._h, N, d, _ptr(theta), float(bandwidth), _ptr(h_out),
+                                              _ptr(workspace), workspace.numel(), _stream(stream)))
+        return workspace
+
+    def svgd_direction(self, theta, grad_logp, workspace, weights=None, phi=None, stream=None):
+        """stamp_svgd_direction: phi from the bandwidth the workspace holds."""
+        d, N = theta.shape
+        if phi is None:
+            phi = torch.empty_like(theta)
+        self._check(_lib.stamp_svgd_direction(self._h, N, d, _ptr(theta), _ptr(grad_logp), _ptr(weights), _ptr(phi),
+                                              _ptr(workspace), workspace.numel(), _stream(stream)))
         return phi
 
     def svgd_step_structured(self, theta, grad_logp, kernel: StructKernel, weights=None, phi=None, h_out=None,

@@ -33,6 +33,15 @@ int svgd_dp_class(int d);
 hipError_t launch_svgd(int N, int d, const float* theta, const float* grad_logp, float bandwidth, float* phi,
                        float* h_out, void* ws, const SvgdLayout& L, int phi_rows, uint32_t* status,
                        hipStream_t st, const float* wts = nullptr);
+// The step's second half: phi from the bandwidth the workspace holds (written
+// by launch_median on the same workspace, which depends on theta only and may
+// therefore run concurrently with the rollout that produces grad_logp).
+hipError_t launch_svgd_direction(int N, int d, const float* theta, const float* grad_logp, float* phi, void* ws,
+                                 const SvgdLayout& L, int phi_rows, uint32_t* status, hipStream_t st,
+                                 const float* wts = nullptr);
+hipError_t launch_svgd_direction_batched(const BatchPlan& P, const ProblemDesc* descs, const float* theta,
+                                         const float* grad, float* phi, char* ws, uint32_t* status, hipStream_t st,
+                                         const float* wts = nullptr);
 // The same step for every problem of a batch (work lists in P); wts packed
 // like the costs (problem p at its cost offset), or null.
 hipError_t launch_svgd_batched(const BatchPlan& P, const ProblemDesc* descs, const float* theta, const float* grad,
@@ -45,6 +54,12 @@ hipError_t launch_phi_reduce(int N, int d, int splits, const float* partial, flo
 hipError_t launch_svgd_structured(int N, int d, const float* theta, const float* grad, const float* wts,
                                   const StructKernel& sk, float* phi, float* h_out, void* ws, const SvgdLayout& L,
                                   uint32_t* status, hipStream_t st);
+// its two halves: features + medians (theta only), then the contraction
+hipError_t launch_struct_bandwidth(int N, const float* theta, const StructKernel& sk, void* ws, const SvgdLayout& L,
+                                   hipStream_t st);
+hipError_t launch_struct_direction(int N, int d, const float* grad, const float* wts, const StructKernel& sk,
+                                   float* phi, float* h_out, void* ws, const SvgdLayout& L, uint32_t* status,
+                                   hipStream_t st);
 // Importance weights of Eq. (4): w_j = N softmax_j(C_disc - C_rel), mean 1.
 hipError_t launch_dsvgd_weights(int N, const float* c_rel, const float* c_disc, float* w, hipStream_t st);
 hipError_t launch_dsvgd_weights_batched(int n_problems, const ProblemDesc* descs, const float* c_rel,
@@ -62,6 +77,10 @@ hipError_t launch_svgd16(int N, int d, const float* theta, const float* grad, fl
                          float* h_out, void* ws, const SvgdLayout& L, uint32_t* status, hipStream_t st);
 hipError_t launch_svgd16_batched(const BatchPlan& P, const ProblemDesc* descs, const float* theta, const float* grad,
                                  float* phi, char* ws, uint32_t* status, hipStream_t st);
+// its second half (after launch_median_batched with exact = 0)
+hipError_t launch_svgd16_direction_batched(const BatchPlan& P, const ProblemDesc* descs, const float* theta,
+                                           const float* grad, float* phi, char* ws, uint32_t* status,
+                                           hipStream_t st);
 
 // Adam (use_adam=1) or plain step, n elements.  t_dev: if non-null, the step
 // count is read as t0 + *t_dev + 1 on the device (graph replay); else t0 is t.

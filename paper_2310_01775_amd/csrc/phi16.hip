@@ -339,6 +339,12 @@ hipError_t launch_svgd16_batched(const BatchPlan& P, const ProblemDesc* descs, c
                                  float* phi, char* ws, uint32_t* status, hipStream_t st) {
     hipError_t e = launch_median_batched(P, descs, theta, 0, ws, st);
     if (e != hipSuccess) return e;
+    return launch_svgd16_direction_batched(P, descs, theta, grad, phi, ws, status, st);
+}
+
+hipError_t launch_svgd16_direction_batched(const BatchPlan& P, const ProblemDesc* descs, const float* theta,
+                                           const float* grad, float* phi, char* ws, uint32_t* status,
+                                           hipStream_t st) {
     if (P.n_ctr) hipLaunchKernelGGL(k_center_batched, dim3(P.n_ctr), dim3(256), 0, st, descs, P.ctr_work, theta, ws);
     if (P.n_row16)
         hipLaunchKernelGGL(k_pack16_batched, dim3(P.n_row16), dim3(256), 0, st, descs, P.row16_work, theta, grad, ws);

@@ -27,7 +27,8 @@ struct stamp_ctx {
     int num_cus = 256;
     std::string err;
     hipStream_t stream = nullptr;  // library stream: solves are captured and replayed here
-    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    hipStream_t side = nullptr;    // the bandwidth stage runs here, beside the rollout
+    hipEvent_t ev_in = nullptr, ev_out = nullptr, ev_fork = nullptr, ev_join = nullptr;
     std::map<std::string, StampTune> tune;  // autotune cache, keyed by batch signature
     int autotune = 1;
     StampTune pinned;                        // used when pinned.roll_block > 0
@@ -357,8 +358,11 @@ int32_t stamp_create(stamp_ctx** ctx, int32_t device) {
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && v > 0) c->num_cus = v;
     // default-priority stream of our own: solves are captured into graphs here
     if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming) != hipSuccess) {
+        hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
         delete c;
         return STAMP_EHIP;
     }
@@ -374,6 +378,10 @@ void stamp_destroy(stamp_ctx* ctx) {
     if (ctx->graph_sgd) (void)hipGraphExecDestroy(ctx->graph_sgd);
     if (ctx->ev_in) (void)hipEventDestroy(ctx->ev_in);
     if (ctx->ev_out) (void)hipEventDestroy(ctx->ev_out);
+    if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
+    if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
+    if (ctx->side) (void)hipStreamSynchronize(ctx->side);
+    if (ctx->side) (void)hipStreamDestroy(ctx->side);
     if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
 }
@@ -507,6 +515,36 @@ int32_t stamp_svgd_step(stamp_ctx* ctx, int32_t N, int32_t d, const float* theta
     hipError_t e = launch_svgd(N, d, theta, grad_logp, bandwidth, phi, h_out, workspace, L, 0, nullptr,
                                (hipStream_t)stream);
     return e == hipSuccess ? STAMP_OK : hip_fail(ctx, e, "svgd_step");
+}
+
+int32_t stamp_svgd_bandwidth(stamp_ctx* ctx, int32_t N, int32_t d, const float* theta, float bandwidth, float* h_out,
+                             void* workspace, size_t ws_bytes, void* stream) {
+    if (!ctx) return STAMP_EINVAL;
+    if (!theta) return fail(ctx, STAMP_EINVAL, "null theta");
+    if (N < 1 || d < 1) return fail(ctx, STAMP_EINVAL, "N=%d, d=%d must be >= 1", N, d);
+    if (d > kMaxSvgdDim || N > kMaxSvgdN)
+        return fail(ctx, STAMP_EUNSUPPORTED, "svgd step supports d <= %d, N <= %d", kMaxSvgdDim, kMaxSvgdN);
+    if (!isfinite(bandwidth)) return fail(ctx, STAMP_EINVAL, "non-finite bandwidth");
+    const SvgdLayout L = svgd_workspace_layout(N, d);
+    if (!workspace || ws_bytes < L.total)
+        return fail(ctx, STAMP_ENOSPACE, "svgd workspace %zu < %zu bytes", ws_bytes, L.total);
+    hipError_t e = launch_median(N, d, theta, bandwidth, 1, workspace, L, h_out, (hipStream_t)stream);
+    return e == hipSuccess ? STAMP_OK : hip_fail(ctx, e, "svgd_bandwidth");
+}
+
+int32_t stamp_svgd_direction(stamp_ctx* ctx, int32_t N, int32_t d, const float* theta, const float* grad_logp,
+                             const float* weights, float* phi, void* workspace, size_t ws_bytes, void* stream) {
+    if (!ctx) return STAMP_EINVAL;
+    if (!theta || !grad_logp || !phi) return fail(ctx, STAMP_EINVAL, "null theta, grad_logp or phi");
+    if (N < 1 || d < 1) return fail(ctx, STAMP_EINVAL, "N=%d, d=%d must be >= 1", N, d);
+    if (d > kMaxSvgdDim || N > kMaxSvgdN)
+        return fail(ctx, STAMP_EUNSUPPORTED, "svgd step supports d <= %d, N <= %d", kMaxSvgdDim, kMaxSvgdN);
+    const SvgdLayout L = svgd_workspace_layout(N, d);
+    if (!workspace || ws_bytes < L.total)
+        return fail(ctx, STAMP_ENOSPACE, "svgd workspace %zu < %zu bytes", ws_bytes, L.total);
+    hipError_t e = launch_svgd_direction(N, d, theta, grad_logp, phi, workspace, L, 0, nullptr, (hipStream_t)stream,
+                                         weights);
+    return e == hipSuccess ? STAMP_OK : hip_fail(ctx, e, "svgd_direction");
 }
 
 int32_t stamp_svgd_step_weighted(stamp_ctx* ctx, int32_t N, int32_t d, const float* theta, const float* grad_logp,
@@ -800,21 +838,41 @@ static int32_t solve_impl(stamp_ctx* ctx, int32_t n_problems, const stamp_scene*
     // overwrites afterwards)
     float* d_cdisc = (float*)(ws + P.cdisc_off);
     float* d_wts = (float*)(ws + P.wts_off);
-    // the SVGD direction of every problem: the batched RBF step, or the
-    // structured kernel problem by problem
-    auto phi_step = [&](const float* wts) -> hipError_t {
-        if (skern.empty()) return launch_svgd_batched(B, d_desc, theta, d_grad, d_phi, d_svgd, status, st, wts);
+    // The SVGD step in two halves.  The bandwidth stage (medians, and the
+    // structured kernel's features) depends on theta only, so it runs on the
+    // side stream while the rollout produces the gradient; the direction stage
+    // joins it.  exact = 0: the BF16 form's sampled median.
+    auto bandwidth_stage = [&](hipStream_t s, int exact) -> hipError_t {
+        if (skern.empty()) return launch_median_batched(B, d_desc, theta, exact, d_svgd, s);
         for (int p = 0; p < n_problems; ++p) {
             const ProblemDesc& D = P.descs[p];
-            hipError_t r = launch_svgd_structured(D.N, D.d, theta + D.theta_off, d_grad + D.theta_off,
-                                                  wts ? wts + D.cost_off : nullptr, skern[p], d_phi + D.theta_off,
-                                                  nullptr, d_svgd + D.svgd_off, D.sv, status, st);
+            hipError_t r = launch_struct_bandwidth(D.N, theta + D.theta_off, skern[p], d_svgd + D.svgd_off, D.sv, s);
+            if (r != hipSuccess) return r;
+        }
+        return hipSuccess;
+    };
+    auto fork = [&](int exact) -> hipError_t {
+        hipError_t r;
+        if ((r = hipEventRecord(ctx->ev_fork, st)) != hipSuccess) return r;
+        if ((r = hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0)) != hipSuccess) return r;
+        if ((r = bandwidth_stage(ctx->side, exact)) != hipSuccess) return r;
+        return hipEventRecord(ctx->ev_join, ctx->side);
+    };
+    auto join = [&]() -> hipError_t { return hipStreamWaitEvent(st, ctx->ev_join, 0); };
+    auto direction_stage = [&](const float* wts) -> hipError_t {
+        if (skern.empty()) return launch_svgd_direction_batched(B, d_desc, theta, d_grad, d_phi, d_svgd, status, st, wts);
+        for (int p = 0; p < n_problems; ++p) {
+            const ProblemDesc& D = P.descs[p];
+            hipError_t r = launch_struct_direction(D.N, D.d, d_grad + D.theta_off, wts ? wts + D.cost_off : nullptr,
+                                                   skern[p], d_phi + D.theta_off, nullptr, d_svgd + D.svgd_off, D.sv,
+                                                   status, st);
             if (r != hipSuccess) return r;
         }
         return hipSuccess;
     };
     auto iteration = [&]() -> hipError_t {
         hipError_t r;
+        if ((r = fork(1)) != hipSuccess) return r;
         if ((r = launch_rollout_fwd_batched(d_desc, d_roll, ntiles, tune.roll_block, rgrid, theta,
                                             (float*)(ws + P.cost_off), d_tape, status, st)) != hipSuccess)
             return r;
@@ -834,7 +892,8 @@ static int32_t solve_impl(stamp_ctx* ctx, int32_t n_problems, const stamp_scene*
                                                   d_wts, st)) != hipSuccess)
                 return r;
         }
-        if ((r = phi_step(cfg->dsvgd ? d_wts : nullptr)) != hipSuccess) return r;
+        if ((r = join()) != hipSuccess) return r;
+        if ((r = direction_stage(cfg->dsvgd ? d_wts : nullptr)) != hipSuccess) return r;
         if ((r = launch_update(P.n_theta, theta, d_phi, adam_m, adam_v, cfg->t0, d_ctr, cfg->lr, cfg->beta1,
                                cfg->beta2, cfg->adam_eps, cfg->use_adam, st)) != hipSuccess)
             return r;
@@ -869,10 +928,12 @@ static int32_t solve_impl(stamp_ctx* ctx, int32_t n_problems, const stamp_scene*
     };
     auto sur_iteration = [&]() -> hipError_t {
         hipError_t r;
+        if ((r = fork(sur->phi_bf16 ? 0 : 1)) != hipSuccess) return r;
         for (int p = 0; p < n_problems; ++p)
             if ((r = sur_infer(p, nullptr, d_grad, -1.0f)) != hipSuccess) return r;
-        r = sur->phi_bf16 ? launch_svgd16_batched(B, d_desc, theta, d_grad, d_phi, d_svgd, status, st)
-                          : phi_step(nullptr);
+        if ((r = join()) != hipSuccess) return r;
+        r = sur->phi_bf16 ? launch_svgd16_direction_batched(B, d_desc, theta, d_grad, d_phi, d_svgd, status, st)
+                          : direction_stage(nullptr);
         if (r != hipSuccess) return r;
         if ((r = launch_update(P.n_theta, theta, d_phi, adam_m, adam_v, cfg->t0, d_ctr, cfg->lr, cfg->beta1,
                                cfg->beta2, cfg->adam_eps, cfg->use_adam, st)) != hipSuccess)

@@ -220,36 +220,59 @@ void launch_partial(int K, dim3 grid, const StructArgs& a, hipStream_t st) {
 
 }  // namespace
 
-hipError_t launch_svgd_structured(int N, int d, const float* theta, const float* grad, const float* wts,
-                                  const StructKernel& sk, float* phi, float* h_out, void* ws, const SvgdLayout& L,
-                                  uint32_t* status, hipStream_t st) {
-    char* base = static_cast<char*>(ws);
-    float* feat = reinterpret_cast<float*>(base + L.sfeat_off);
-    const int K = sk.K;
-    // each component's median keeps its own state: the g one in the
-    // structured region, the softmax one at the plain step's place
-    SvgdLayout Lg = L;
-    Lg.sel_off = L.sh_off;
+namespace {
+
+struct StructView {
+    float* feat;
+    SvgdLayout Lg;  // the layout of the g median: its selection state in the structured region
     StructBw bw;
-    bw.sel[0] = reinterpret_cast<const SelState*>(base + Lg.sel_off);
-    bw.sel[1] = reinterpret_cast<const SelState*>(base + L.sel_off);
-    bw.fixed[0] = sk.h_g;
-    bw.fixed[1] = sk.h_z;
-    bw.K = K;
+};
+
+StructView struct_view(void* ws, const SvgdLayout& L, const StructKernel& sk) {
+    char* base = static_cast<char*>(ws);
+    StructView v;
+    v.feat = reinterpret_cast<float*>(base + L.sfeat_off);
+    v.Lg = L;
+    v.Lg.sel_off = L.sh_off;
+    v.bw.sel[0] = reinterpret_cast<const SelState*>(base + v.Lg.sel_off);
+    v.bw.sel[1] = reinterpret_cast<const SelState*>(base + L.sel_off);
+    v.bw.fixed[0] = sk.h_g;
+    v.bw.fixed[1] = sk.h_z;
+    v.bw.K = sk.K;
+    return v;
+}
+
+}  // namespace
+
+// features and the two medians: the g rows (2K) and the softmax rows (4K),
+// each into its own selection state
+hipError_t launch_struct_bandwidth(int N, const float* theta, const StructKernel& sk, void* ws, const SvgdLayout& L,
+                                   hipStream_t st) {
+    if (N < 2) return hipSuccess;
+    const StructView v = struct_view(ws, L, sk);
+    const int K = sk.K;
+    hipError_t e;
+    if (sk.layout == kStructPush)
+        hipLaunchKernelGGL(k_struct_prep<kStructPush>, dim3((N + 255) / 256), dim3(256), 0, st, N, K, theta, v.feat);
+    else
+        hipLaunchKernelGGL(k_struct_prep<kStructPose>, dim3((N + 255) / 256), dim3(256), 0, st, N, K, theta, v.feat);
+    if (!(sk.h_g > 0.0f) &&
+        (e = launch_median(N, 2 * K, v.feat + (int64_t)4 * K * N, 0.0f, 1, ws, v.Lg, nullptr, st)) != hipSuccess)
+        return e;
+    if (!(sk.h_z > 0.0f) && (e = launch_median(N, 4 * K, v.feat, 0.0f, 1, ws, L, nullptr, st)) != hipSuccess)
+        return e;
+    return hipGetLastError();
+}
+
+// the contraction from the features and bandwidths the workspace holds
+hipError_t launch_struct_direction(int N, int d, const float* grad, const float* wts, const StructKernel& sk,
+                                   float* phi, float* h_out, void* ws, const SvgdLayout& L, uint32_t* status,
+                                   hipStream_t st) {
+    const StructView v = struct_view(ws, L, sk);
     hipError_t e;
     if (N == 1) {
         hipLaunchKernelGGL(k_struct_single, dim3(1), dim3(64), 0, st, d, grad, phi);
     } else {
-        if (sk.layout == kStructPush)
-            hipLaunchKernelGGL(k_struct_prep<kStructPush>, dim3((N + 255) / 256), dim3(256), 0, st, N, K, theta, feat);
-        else
-            hipLaunchKernelGGL(k_struct_prep<kStructPose>, dim3((N + 255) / 256), dim3(256), 0, st, N, K, theta, feat);
-        // medians: the g rows (2K) and the softmax rows (4K)
-        if (!(sk.h_g > 0.0f) &&
-            (e = launch_median(N, 2 * K, feat + (int64_t)4 * K * N, 0.0f, 1, ws, Lg, nullptr, st)) != hipSuccess)
-            return e;
-        if (!(sk.h_z > 0.0f) && (e = launch_median(N, 4 * K, feat, 0.0f, 1, ws, L, nullptr, st)) != hipSuccess)
-            return e;
         StructArgs a;
         a.N = N;
         a.chunk = (N + L.splits - 1) / L.splits;
@@ -257,19 +280,27 @@ hipError_t launch_svgd_structured(int N, int d, const float* theta, const float*
         a.alpha_z = sk.alpha_z;
         a.alpha_p = sk.alpha_p;
         a.kappa = sk.kappa;
-        a.feat = feat;
+        a.feat = v.feat;
         a.grad = grad;
         a.wts = wts;
-        a.bw = bw;
-        a.partial = reinterpret_cast<float*>(base + L.part_off);
+        a.bw = v.bw;
+        a.partial = reinterpret_cast<float*>(static_cast<char*>(ws) + L.part_off);
         const dim3 grid((N + 255) / 256, L.splits);
-        if (sk.layout == kStructPush) launch_partial<kStructPush>(K, grid, a, st);
-        else launch_partial<kStructPose>(K, grid, a, st);
+        if (sk.layout == kStructPush) launch_partial<kStructPush>(sk.K, grid, a, st);
+        else launch_partial<kStructPose>(sk.K, grid, a, st);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         if ((e = launch_phi_reduce(N, d, L.splits, a.partial, phi, status, st)) != hipSuccess) return e;
     }
-    if (h_out) hipLaunchKernelGGL(k_struct_hout, dim3(1), dim3(64), 0, st, bw, N, h_out);
+    if (h_out) hipLaunchKernelGGL(k_struct_hout, dim3(1), dim3(64), 0, st, v.bw, N, h_out);
     return hipGetLastError();
+}
+
+hipError_t launch_svgd_structured(int N, int d, const float* theta, const float* grad, const float* wts,
+                                  const StructKernel& sk, float* phi, float* h_out, void* ws, const SvgdLayout& L,
+                                  uint32_t* status, hipStream_t st) {
+    hipError_t e = launch_struct_bandwidth(N, theta, sk, ws, L, st);
+    if (e != hipSuccess) return e;
+    return launch_struct_direction(N, d, grad, wts, sk, phi, h_out, ws, L, status, st);
 }
 
 }  // namespace stamp

@@ -356,10 +356,17 @@ SvgdLayout svgd_workspace_layout(int N, int d) {
 hipError_t launch_svgd(int N, int d, const float* theta, const float* grad_logp, float bandwidth, float* phi,
                        float* h_out, void* ws, const SvgdLayout& L, int phi_rows, uint32_t* status, hipStream_t st,
                        const float* wts) {
-    char* base = static_cast<char*>(ws);
-    SelState* sel = reinterpret_cast<SelState*>(base + L.sel_off);
     hipError_t e = launch_median(N, d, theta, bandwidth, 1, ws, L, h_out, st);
     if (e != hipSuccess) return e;
+    return launch_svgd_direction(N, d, theta, grad_logp, phi, ws, L, phi_rows, status, st, wts);
+}
+
+hipError_t launch_svgd_direction(int N, int d, const float* theta, const float* grad_logp, float* phi, void* ws,
+                                 const SvgdLayout& L, int phi_rows, uint32_t* status, hipStream_t st,
+                                 const float* wts) {
+    char* base = static_cast<char*>(ws);
+    SelState* sel = reinterpret_cast<SelState*>(base + L.sel_off);
+    hipError_t e;
     if (N == 1) {  // phi = g
         hipLaunchKernelGGL(k_copy, dim3((d + 255) / 256), dim3(256), 0, st, grad_logp, phi, (int64_t)d);
         return hipGetLastError();
@@ -386,6 +393,12 @@ hipError_t launch_svgd_batched(const BatchPlan& P, const ProblemDesc* descs, con
                                float* phi, char* ws, uint32_t* status, hipStream_t st, const float* wts) {
     hipError_t e = launch_median_batched(P, descs, theta, 1, ws, st);
     if (e != hipSuccess) return e;
+    return launch_svgd_direction_batched(P, descs, theta, grad, phi, ws, status, st, wts);
+}
+
+hipError_t launch_svgd_direction_batched(const BatchPlan& P, const ProblemDesc* descs, const float* theta,
+                                         const float* grad, float* phi, char* ws, uint32_t* status, hipStream_t st,
+                                         const float* wts) {
     for (int c = 0; c < kDpClasses; ++c) {
         if (!P.n_phi[c]) continue;
         switch (kDpClass[c]) {

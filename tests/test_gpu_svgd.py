@@ -144,3 +144,29 @@ def test_svgd_argument_errors(ctx):
     with pytest.raises(S.StampError) as e:
         ctx.svgd_step(th, th, 0.0, workspace=small)
     assert e.value.code == S.ENOSPACE
+
+
+@pytest.mark.parametrize("N,d", [(1, 6), (300, 18), (4096, 30)])
+def test_two_half_step_on_two_streams_equals_the_step(ctx, N, d):
+    """stamp_svgd_bandwidth on a side stream (as beside a rollout) and
+    stamp_svgd_direction on the main stream after an event give the step's
+    phi and h bit for bit."""
+    import paper_2310_01775_amd as S
+    print("case", N, d, flush=True)
+    rng = np.random.default_rng(N + d)
+    th = S.soa(W.f32(rng.standard_normal((N, d))))
+    g = S.soa(W.f32(rng.standard_normal((N, d)) * 3.0))
+    h1, h2 = torch.zeros(1, device="cuda"), torch.zeros(1, device="cuda")
+    ref = ctx.svgd_step(th, g, 0.0, h_out=h1)
+    ws = torch.empty(ctx.svgd_workspace_bytes(N, d), dtype=torch.uint8, device="cuda")
+    main, side = torch.cuda.current_stream(), torch.cuda.Stream()
+    ev0, ev1 = torch.cuda.Event(), torch.cuda.Event()
+    for _ in range(2):  # the second round reuses the workspace
+        ev0.record(main)
+        side.wait_event(ev0)
+        ctx.svgd_bandwidth(th, 0.0, h_out=h2, workspace=ws, stream=side)
+        ev1.record(side)
+        main.wait_event(ev1)
+        got = ctx.svgd_direction(th, g, ws)
+    torch.cuda.synchronize()
+    assert torch.equal(got, ref) and torch.equal(h1, h2)
