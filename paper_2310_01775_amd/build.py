@@ -14,7 +14,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libstamp.so")
-SOURCES = ["stamp_api.hip", "rollout.hip", "svgd.hip", "median.hip", "phi16.hip", "mlp.hip", "structured.hip"]
+SOURCES = ["stamp_api.hip", "rollout.hip", "svgd.hip", "median.hip", "phi16.hip", "mlp.hip", "structured.hip", "phi32.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -93,6 +93,12 @@ struct SvgdLayout {
     int tiles;                      // 64-row tiles
     // BF16 matrix-core form (sampled median, centred Gram distances)
     int npad;                       // N rounded up to the 256-row block
+    // FP32 matrix-core form of the contraction (phi32.hip)
+    int ks32, ot32;                 // Gram k-steps (4 coordinates each), 16-column tiles of V
+    int splits32, chunk32;          // column splits and their width (a multiple of 16)
+    size_t x32_off;                 // npad x 4 ks32 floats: centred rows in MFMA operand order
+    size_t n32_off;                 // npad floats: their squared norms
+    size_t v32_off;                 // npad x 16 ot32 floats: V = w [g - (2/h) x | 1 | 0], tiled
     int kd, vc;                     // padded dimension (32 or 64) and V columns (2 kd)
     int splits16, chunk16;          // column splits of its contraction and their width
     size_t smp_off;                 // kMedSample floats: the sampled distances
@@ -137,8 +143,11 @@ struct ProblemDesc {
 };
 
 // Classes of the padded particle dimension of the contraction kernel.
-constexpr int kDpClasses = 6;
-constexpr int kDpClass[kDpClasses] = {8, 16, 24, 32, 48, 64};
+// Shape classes of the FP32 matrix-core contraction: Gram k-steps (an even
+// count of 4-coordinate steps) and 16-column tiles of V = [.. d .. | 1].
+constexpr int kPhi32Classes = 12;
+__host__ __device__ inline int phi32_ks(int d) { return 2 * ((d + 7) / 8); }
+__host__ __device__ inline int phi32_ot(int d) { return (d + 16) / 16; }
 
 // Device work lists of one batched SVGD step (built once per solve).
 // Padded dimension of the median's all-pairs items, and the class of an item
@@ -151,8 +160,8 @@ struct BatchPlan {
     const int4* dist_work;  int n_dist;   // (p, row block, column chunk, -) of the median passes
     int med_classes;                      // bit med_class(dp, rows) set when a problem has that shape
     const int4* cand_work;  int n_cand;   // (p, segment, part, -) of the median's candidate passes
-    const int4* phi_work[kDpClasses];     // (p, row block, split, -) per class
-    int n_phi[kDpClasses];
+    const int4* phi_work[kPhi32Classes];  // (p, 256-row block, split, -) per FP32 matrix-core class
+    int n_phi[kPhi32Classes];
     // BF16 matrix-core form: (problem, coordinate), (problem, 256-row chunk),
     // and (problem, row block, split) per padded dimension 32 / 64
     const int4* ctr_work;

@@ -28,14 +28,25 @@ hipError_t launch_rollout_adj_batched(const ProblemDesc* descs, const int2* tile
 // the median heuristic runs and writes h into the workspace (and h_out if
 // non-null).  phi_rows: rows per contraction workgroup (0 = 256).
 SvgdLayout svgd_workspace_layout(int N, int d);
-int svgd_dp_class(int d);
+// class index (0 .. kPhi32Classes-1) of the FP32 matrix-core contraction for dimension d
+int phi32_class(int d);
 // wts: null, or per-particle importance weights (mean 1) of Eq. (4).
 hipError_t launch_svgd(int N, int d, const float* theta, const float* grad_logp, float bandwidth, float* phi,
                        float* h_out, void* ws, const SvgdLayout& L, int phi_rows, uint32_t* status,
                        hipStream_t st, const float* wts = nullptr);
-// The step's second half: phi from the bandwidth the workspace holds (written
-// by launch_median on the same workspace, which depends on theta only and may
-// therefore run concurrently with the rollout that produces grad_logp).
+// The step's first half, which depends on theta only (and may therefore run
+// concurrently with the rollout that produces grad_logp): the median into the
+// workspace's selection state, then the FP32 form's theta operands (particle
+// mean, centred rows, norms, X = -(2/h) x).
+hipError_t launch_svgd_bandwidth(int N, int d, const float* theta, float bandwidth, float* h_out, void* ws,
+                                 const SvgdLayout& L, hipStream_t st);
+hipError_t launch_svgd_bandwidth_batched(const BatchPlan& P, const ProblemDesc* descs, const float* theta, int exact,
+                                         char* ws, hipStream_t st);
+hipError_t launch_operands32(int N, int d, const float* theta, void* ws, const SvgdLayout& L, hipStream_t st);
+hipError_t launch_operands32_batched(const BatchPlan& P, const ProblemDesc* descs, const float* theta, char* ws,
+                                     hipStream_t st);
+// The step's second half: phi from the bandwidth and centre the workspace
+// holds (FP32 matrix cores, phi32.hip).
 hipError_t launch_svgd_direction(int N, int d, const float* theta, const float* grad_logp, float* phi, void* ws,
                                  const SvgdLayout& L, int phi_rows, uint32_t* status, hipStream_t st,
                                  const float* wts = nullptr);

@@ -1,0 +1,401 @@
+// FP32 SVGD direction on the matrix cores (v_mfma_f32_16x16x4f32), the
+// contraction of Eq. (1) (Eq. (4) with importance weights):
+//
+//   x_i = theta_i - mean theta                  (FP32; centring shrinks the Gram cancellation)
+//   D_ij = |x_i|^2 + |x_j|^2 - 2 x_i . x_j      (Gram on MFMA, FP32)
+//   K_ij = exp(-max(D_ij, 0) / h)
+//   V_j = w_j [ g_j - (2/h) x_j | 1 ]           (w_j = 1 without weights)
+//   A_i = sum_j K_ij V_j                         (MFMA, FP32)
+//   phi_i = ( A_i[0..d) + (2/h) x_i A_i[d] ) / N
+//
+// which is (1/N) sum_j w_j K_ij [g_j + (2/h)(theta_i - theta_j)] with
+// theta_i - theta_j = x_i - x_j.
+//
+// Stages: everything that depends on theta only runs with the median (the
+// bandwidth stage, which can overlap the rollout): the particle mean, then the
+// pack kernel (it needs h) writing the centred rows in the MFMA operand order,
+// their norms, and X = [-(2/h) x | 1 | 0] chunk-tiled.  The contraction adds g
+// (read straight from its [d][N] layout) and the weights to X to form V; it (64, 128 or 256 rows per workgroup, 64 per wave as four 16-row
+// tiles, one column split) runs per 16 columns the Gram MFMAs of every row tile, turns
+// them into K in registers and feeds K as the A operand of the K.V MFMAs: the
+// Gram output (lane holds columns j = 4(l/16)+t of row l%16) is an A operand
+// whose k index runs over (l/16, t), and V is stored in that order, so each
+// lane reads its four V values of an output tile with one 16-byte load.  The
+// reduce sums the splits in a fixed order.  Splits depend on N only.
+#include <math.h>
+
+#include <type_traits>
+
+#include "common.h"
+#include "internal.h"
+
+namespace stamp {
+
+namespace {
+
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f4;
+
+struct View32 {  // one problem's FP32 matrix-core workspace
+    const float* ctr;
+    float* xr;   // [npad][4 ks]: row i, lane group q holds coordinates q ks .. q ks + ks - 1
+    float* nrm;  // [npad]: |x_i|^2
+    float* vt;   // [npad / 16][ot][16 columns n][16 rows j]: X[j][16 o + n] at 16 n + j of tile (j/16, o)
+    float* part; // [splits32][16 ot][npad]
+    const SelState* sel;
+};
+
+__device__ __forceinline__ View32 view32(const SvgdLayout& L, char* base) {
+    View32 v;
+    v.ctr = reinterpret_cast<const float*>(base + L.ctr_off);
+    v.xr = reinterpret_cast<float*>(base + L.x32_off);
+    v.nrm = reinterpret_cast<float*>(base + L.n32_off);
+    v.vt = reinterpret_cast<float*>(base + L.v32_off);
+    v.part = reinterpret_cast<float*>(base + L.part_off);
+    v.sel = reinterpret_cast<const SelState*>(base + L.sel_off);
+    return v;
+}
+
+// ---- particle mean of coordinate l (one workgroup of 256) ----------------------
+__device__ void mean_body(int N, int l, const float* __restrict__ theta, float* __restrict__ ctr) {
+    __shared__ float red[256];
+    float s = 0.0f;
+    for (int i = threadIdx.x; i < N; i += 256) s += theta[(int64_t)l * N + i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) ctr[l] = red[0] / (float)N;
+}
+
+// ---- operands: 64 rows per 256 threads, lane group q = threadIdx.x / 64 takes
+// the coordinates l = 4 s + q (its MFMA lane group's values), so a thread's
+// stores of xr are contiguous and its loop is a quarter of the dimension
+__device__ void pack32_rows(int N, int d, int ks, int ot, int row0, const float* __restrict__ theta,
+                            const View32& v) {
+    __shared__ float part[4][64];
+    const int r = threadIdx.x & 63, q = threadIdx.x >> 6;
+    const int i = row0 + r;
+    const float c2 = 2.0f / v.sel->h;
+    const int kd = 4 * ks;
+    float* vt = v.vt + (int64_t)(i >> 4) * ot * 256 + (i & 15);
+    float nrm = 0.0f;
+    for (int s = 0; s < ks; ++s) {
+        const int l = 4 * s + q;
+        const float x = (i < N && l < d) ? theta[(int64_t)l * N + i] - v.ctr[l] : 0.0f;
+        nrm = fmaf(x, x, nrm);
+        v.xr[(int64_t)i * kd + q * ks + s] = x;
+        if (l < d) vt[(l >> 4) * 256 + (l & 15) * 16] = -c2 * x;
+    }
+    for (int n = d + ((q - d) & 3); n < 16 * ot; n += 4)
+        vt[(n >> 4) * 256 + (n & 15) * 16] = (n == d && i < N) ? 1.0f : 0.0f;
+    part[q][r] = nrm;
+    __syncthreads();
+    if (q == 0) v.nrm[i] = (part[0][r] + part[1][r]) + (part[2][r] + part[3][r]);
+    __syncthreads();
+}
+
+// ---- contraction: partial sums of K V over the columns [j0, j1) -------------------
+// V[j][n] = w_j (X[j][n] + g[n][j]) for the lane's j = jc + 4 kq + t and
+// n = 16 o + col: X from its tile, g from [d][N] (one 16-byte load when the
+// four columns are in range and aligned), w_j = 1 without weights
+template <int OT>
+__device__ __forceinline__ void load_v(int jc, int col, int kq, int N, int d, bool g4, const float* __restrict__ g,
+                                       const float* __restrict__ wts, const View32& v, f4 (&vv)[OT]) {
+    const int j = jc + 4 * kq;
+    const float* vp = v.vt + (int64_t)(jc >> 4) * OT * 256 + col * 16 + kq * 4;
+    const bool full = g4 && j + 4 <= N;
+#pragma unroll
+    for (int o = 0; o < OT; ++o) {
+        f4 x = *reinterpret_cast<const f4*>(vp + o * 256);
+        const int n = 16 * o + col;
+        const int nc = min(n, d - 1);
+        const float* gp = g + (int64_t)nc * N;
+        f4 gv;
+        if (full) {
+            gv = *reinterpret_cast<const f4*>(gp + j);
+        } else {
+#pragma unroll
+            for (int t = 0; t < 4; ++t) gv[t] = gp[min(j + t, N - 1)] * (j + t < N ? 1.0f : 0.0f);
+        }
+        if (n >= d) gv = f4{0.f, 0.f, 0.f, 0.f};
+        vv[o] = x + gv;
+    }
+    if (wts) {
+        f4 w;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) w[t] = j + t < N ? wts[j + t] : 0.0f;
+#pragma unroll
+        for (int o = 0; o < OT; ++o) vv[o] *= w;
+    }
+}
+
+template <int KS, int OT>
+__device__ void phi32_body(int N, int d, int row0, int j0, int j1, int split, int npad, const float* __restrict__ g,
+                           const float* __restrict__ wts, const View32& v) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int col = lane & 15, kq = lane >> 4;
+    const int rbase = row0 + wave * 64;
+    const float c = -1.44269504088896341f / v.sel->h;  // K = 2^(c D)
+    // 16-byte loads of g need every row start aligned
+    const bool g4 = (N & 3) == 0 && (reinterpret_cast<uintptr_t>(g) & 15) == 0;
+    const float m2c = -2.0f * c;
+    float xi[4][KS], ni[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const float* p = v.xr + (int64_t)(rbase + 16 * r + col) * (4 * KS) + kq * KS;
+#pragma unroll
+        for (int s = 0; s < KS; ++s) xi[r][s] = p[s];
+        ni[r] = c * v.nrm[rbase + 16 * r + col];
+    }
+    f4 acc[4][OT];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int o = 0; o < OT; ++o) acc[r][o] = f4{0.f, 0.f, 0.f, 0.f};
+    // the next 16 columns' operands load while these compute
+    float xj[KS], xn[KS];
+    f4 nj, nn, vb[OT], vn[OT];
+    auto load = [&](int jc, float (&x)[KS], f4& n, f4 (&vv)[OT]) {
+        const float* p = v.xr + (int64_t)(jc + col) * (4 * KS) + kq * KS;
+#pragma unroll
+        for (int s = 0; s < KS; ++s) x[s] = p[s];
+        n = *reinterpret_cast<const f4*>(v.nrm + jc + 4 * kq);
+        load_v<OT>(jc, col, kq, N, d, g4, g, wts, v, vv);
+    };
+    if (j0 < j1) load(j0, xj, nj, vb);
+    for (int jc = j0; jc < j1; jc += 16) {
+        if (jc + 16 < j1) load(jc + 16, xn, nn, vn);
+        float cn[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) cn[t] = c * nj[t];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            f4 s = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int k = 0; k < KS; ++k) s = __builtin_amdgcn_mfma_f32_16x16x4f32(xj[k], xi[r][k], s, 0, 0, 0);
+            float kv[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) kv[t] = hw_exp2(fminf(fmaf(m2c, s[t], ni[r] + cn[t]), 0.0f));
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+#pragma unroll
+                for (int o = 0; o < OT; ++o)
+                    acc[r][o] = __builtin_amdgcn_mfma_f32_16x16x4f32(kv[t], vb[o][t], acc[r][o], 0, 0, 0);
+        }
+#pragma unroll
+        for (int s = 0; s < KS; ++s) xj[s] = xn[s];
+        nj = nn;
+#pragma unroll
+        for (int o = 0; o < OT; ++o) vb[o] = vn[o];
+    }
+    float* out = v.part + (int64_t)split * (16 * OT) * npad;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int o = 0; o < OT; ++o)
+            *reinterpret_cast<f4*>(out + (int64_t)(16 * o + col) * npad + rbase + 16 * r + 4 * kq) = acc[r][o];
+}
+
+// ---- phi from the split sums (fixed split order) ----------------------------------
+// the coordinate's row and the row-sum row of every split, 16 loads in flight
+__device__ void reduce32_elem(int N, int d, const SvgdLayout& L, int l, int i, const float* __restrict__ theta,
+                              float* __restrict__ phi, const View32& v, uint32_t* status) {
+    const int64_t sstride = (int64_t)16 * L.ot32 * L.npad;
+    const float* pa = v.part + (int64_t)l * L.npad + i;
+    const float* p1 = v.part + (int64_t)d * L.npad + i;
+    float a = 0.0f, a1 = 0.0f;
+    for (int q0 = 0; q0 < L.splits32; q0 += 8) {
+        float u[8], u1[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const bool ok = q0 + k < L.splits32;
+            u[k] = ok ? pa[(q0 + k) * sstride] : 0.0f;
+            u1[k] = ok ? p1[(q0 + k) * sstride] : 0.0f;
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            a += u[k];
+            a1 += u1[k];
+        }
+    }
+    const float x = theta[(int64_t)l * N + i] - v.ctr[l];
+    const float r = fmaf(2.0f / v.sel->h * x, a1, a) / (float)N;
+    phi[(int64_t)l * N + i] = r;
+    if (status && !isfinite(r)) atomicOr(status, STAMP_STATUS_NONFINITE_PHI);
+}
+
+// ---- single-problem kernels -------------------------------------------------------
+struct One32 {
+    int N, d;
+    SvgdLayout L;
+};
+
+__global__ __launch_bounds__(256) void k_mean(One32 a, const float* theta, char* ws) {
+    mean_body(a.N, blockIdx.x, theta, reinterpret_cast<float*>(ws + a.L.ctr_off));
+}
+
+__global__ __launch_bounds__(256) void k_pack32(One32 a, const float* theta, char* ws) {
+    pack32_rows(a.N, a.d, a.L.ks32, a.L.ot32, blockIdx.x * 64, theta, view32(a.L, ws));
+}
+
+template <int KS, int OT>
+__global__ __launch_bounds__(256) void k_phi32(One32 a, const float* g, const float* wts, char* ws) {
+    const int split = blockIdx.y;
+    const int j0 = split * a.L.chunk32, j1 = min(j0 + a.L.chunk32, a.L.npad);
+    phi32_body<KS, OT>(a.N, a.d, blockIdx.x * blockDim.x, j0, j1, split, a.L.npad, g, wts, view32(a.L, ws));
+}
+
+__global__ __launch_bounds__(256) void k_reduce32(One32 a, const float* theta, const float* g, float* phi, char* ws,
+                                                  uint32_t* status) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= (int64_t)a.d * a.N) return;
+    if (a.N == 1) {
+        phi[e] = g[e];
+        return;
+    }
+    reduce32_elem(a.N, a.d, a.L, (int)(e / a.N), (int)(e % a.N), theta, phi, view32(a.L, ws), status);
+}
+
+// ---- batched kernels (work-list entries as in svgd.hip) ------------------------------
+__device__ __forceinline__ char* base32(const ProblemDesc& D, char* ws) { return ws + D.svgd_off; }
+
+// entry = (problem, coordinate, -, -)
+__global__ __launch_bounds__(256) void k_mean_batched(const ProblemDesc* __restrict__ descs,
+                                                      const int4* __restrict__ work, const float* theta, char* ws) {
+    const int4 e = work[blockIdx.x];
+    const ProblemDesc& D = descs[e.x];
+    mean_body(D.N, e.y, theta + D.theta_off, reinterpret_cast<float*>(base32(D, ws) + D.sv.ctr_off));
+}
+
+// entry = (problem, first row of a 256-row chunk, -, -)
+__global__ __launch_bounds__(256) void k_pack32_batched(const ProblemDesc* __restrict__ descs,
+                                                        const int4* __restrict__ work, const float* theta, char* ws) {
+    const int4 e = work[blockIdx.x];
+    const ProblemDesc& D = descs[e.x];
+    if (D.N < 2) return;
+    const View32 v = view32(D.sv, base32(D, ws));
+    for (int r0 = e.y; r0 < e.y + 256; r0 += 64) pack32_rows(D.N, D.d, D.sv.ks32, D.sv.ot32, r0, theta + D.theta_off, v);
+}
+
+// entry = (problem, row block of blockDim.x rows, split, -)
+template <int KS, int OT>
+__global__ __launch_bounds__(256) void k_phi32_batched(const ProblemDesc* __restrict__ descs,
+                                                       const int4* __restrict__ work, const float* grad,
+                                                       const float* wts, char* ws) {
+    const int4 e = work[blockIdx.x];
+    const ProblemDesc& D = descs[e.x];
+    const int j0 = e.z * D.sv.chunk32, j1 = min(j0 + D.sv.chunk32, D.sv.npad);
+    phi32_body<KS, OT>(D.N, D.d, e.y * (int)blockDim.x, j0, j1, e.z, D.sv.npad, grad + D.theta_off,
+                       wts ? wts + D.cost_off : nullptr, view32(D.sv, base32(D, ws)));
+}
+
+// entry = (problem, first element, end element, -) of the problem's d*N block
+__global__ __launch_bounds__(256) void k_reduce32_batched(const ProblemDesc* __restrict__ descs,
+                                                          const int4* __restrict__ work, const float* theta,
+                                                          const float* grad, float* phi, char* ws,
+                                                          uint32_t* status) {
+    const int4 w = work[blockIdx.x];
+    const ProblemDesc& D = descs[w.x];
+    const int64_t e = w.y + threadIdx.x;
+    if (e >= w.z) return;
+    if (D.N == 1) {
+        phi[D.theta_off + e] = grad[D.theta_off + e];
+        return;
+    }
+    reduce32_elem(D.N, D.d, D.sv, (int)(e / D.N), (int)(e % D.N), theta + D.theta_off, phi + D.theta_off,
+                  view32(D.sv, base32(D, ws)), status);
+}
+
+// (ks, ot) of each class, in the order of phi32_class
+constexpr int kCls[kPhi32Classes][2] = {{2, 1},  {4, 1},  {4, 2},  {6, 2},  {8, 2},  {8, 3},
+                                        {10, 3}, {12, 3}, {12, 4}, {14, 4}, {16, 4}, {16, 5}};
+
+template <int C>
+void launch_class(dim3 grid, int rows, hipStream_t st, const One32& a, const float* g, const float* wts, char* ws) {
+    hipLaunchKernelGGL((k_phi32<kCls[C][0], kCls[C][1]>), grid, dim3(rows), 0, st, a, g, wts, ws);
+}
+
+template <int C>
+void launch_class_batched(int n, int rows, hipStream_t st, const ProblemDesc* descs, const int4* work,
+                          const float* grad, const float* wts, char* ws) {
+    hipLaunchKernelGGL((k_phi32_batched<kCls[C][0], kCls[C][1]>), dim3(n), dim3(rows), 0, st, descs, work, grad, wts,
+                       ws);
+}
+
+template <typename F>
+void by_class(int c, F&& f) {
+    switch (c) {
+        case 0: f(std::integral_constant<int, 0>()); break;
+        case 1: f(std::integral_constant<int, 1>()); break;
+        case 2: f(std::integral_constant<int, 2>()); break;
+        case 3: f(std::integral_constant<int, 3>()); break;
+        case 4: f(std::integral_constant<int, 4>()); break;
+        case 5: f(std::integral_constant<int, 5>()); break;
+        case 6: f(std::integral_constant<int, 6>()); break;
+        case 7: f(std::integral_constant<int, 7>()); break;
+        case 8: f(std::integral_constant<int, 8>()); break;
+        case 9: f(std::integral_constant<int, 9>()); break;
+        case 10: f(std::integral_constant<int, 10>()); break;
+        default: f(std::integral_constant<int, 11>()); break;
+    }
+}
+
+}  // namespace
+
+int phi32_class(int d) {
+    const int ks = phi32_ks(d), ot = phi32_ot(d);
+    for (int c = 0; c < kPhi32Classes; ++c)
+        if (kCls[c][0] == ks && kCls[c][1] == ot) return c;
+    return -1;
+}
+
+hipError_t launch_operands32(int N, int d, const float* theta, void* ws, const SvgdLayout& L, hipStream_t st) {
+    if (N < 2) return hipSuccess;
+    One32 a{N, d, L};
+    char* b = static_cast<char*>(ws);
+    hipLaunchKernelGGL(k_mean, dim3(d), dim3(256), 0, st, a, theta, b);
+    hipLaunchKernelGGL(k_pack32, dim3(L.npad / 64), dim3(256), 0, st, a, theta, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_operands32_batched(const BatchPlan& P, const ProblemDesc* descs, const float* theta, char* ws,
+                                     hipStream_t st) {
+    if (P.n_ctr) hipLaunchKernelGGL(k_mean_batched, dim3(P.n_ctr), dim3(256), 0, st, descs, P.ctr_work, theta, ws);
+    if (P.n_row16)
+        hipLaunchKernelGGL(k_pack32_batched, dim3(P.n_row16), dim3(256), 0, st, descs, P.row16_work, theta, ws);
+    return hipGetLastError();
+}
+
+hipError_t launch_svgd_direction(int N, int d, const float* theta, const float* grad_logp, float* phi, void* ws,
+                                 const SvgdLayout& L, int phi_rows, uint32_t* status, hipStream_t st,
+                                 const float* wts) {
+    One32 a{N, d, L};
+    char* b = static_cast<char*>(ws);
+    if (N >= 2) {
+        const int rows = phi_rows > 0 ? phi_rows : 256;
+        const dim3 grid(L.npad / rows, L.splits32);
+        by_class(phi32_class(d), [&](auto c) { launch_class<decltype(c)::value>(grid, rows, st, a, grad_logp, wts, b); });
+    }
+    const int64_t n = (int64_t)d * N;
+    hipLaunchKernelGGL(k_reduce32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a, theta, grad_logp, phi, b,
+                       status);
+    return hipGetLastError();
+}
+
+hipError_t launch_svgd_direction_batched(const BatchPlan& P, const ProblemDesc* descs, const float* theta,
+                                         const float* grad, float* phi, char* ws, uint32_t* status, hipStream_t st,
+                                         const float* wts) {
+    for (int c = 0; c < kPhi32Classes; ++c)
+        if (P.n_phi[c])
+            by_class(c, [&](auto k) {
+                launch_class_batched<decltype(k)::value>(P.n_phi[c], P.phi_rows, st, descs, P.phi_work[c], grad, wts,
+                                                         ws);
+            });
+    hipLaunchKernelGGL(k_reduce32_batched, dim3(P.n_red), dim3(256), 0, st, descs, P.red_work, theta, grad, phi, ws,
+                       status);
+    return hipGetLastError();
+}
+
+}  // namespace stamp

@@ -178,13 +178,13 @@ struct SolvePlan {
     std::vector<stamp::ProblemDesc> descs;
     std::vector<int2> roll_tiles;
     std::vector<int4> dist_work, cand_work, red_work;
-    std::vector<int4> phi_work[kDpClasses];
+    std::vector<int4> phi_work[kPhi32Classes];
     std::vector<int4> ctr_work, row16_work, phi16_work[2];  // BF16 form
     int phi_rows = 256;
     int med_classes = 0;  // item shapes among dist_work (bit med_class)
     size_t clk_off = 0, desc_off = 0, roll_off = 0, dist_off = 0, cand_off = 0, red_off = 0;
     size_t ctr16_off = 0, row16_off = 0, phi16_off[2] = {};
-    size_t phi_off[kDpClasses] = {};
+    size_t phi_off[kPhi32Classes] = {};
     size_t ctr_off = 0, err_off = 0, tape_off = 0, seg_off = 0, grad_off = 0, phi_vec_off = 0, cost_off = 0,
            cdisc_off = 0, wts_off = 0, svgd_off = 0;
     size_t total = 0;
@@ -239,10 +239,9 @@ void build_plan(int n, const stamp_scene* scenes, const int32_t* N, int K, float
                 for (int q = 0; q < kCandParts; ++q) P.cand_work.push_back(make_int4(p, g, q, 0));
         }
         if (D.N >= 2) {
-            int c = 0;
-            while (kDpClass[c] != svgd_dp_class(D.d)) ++c;
-            for (int rb = 0; rb * phi_rows < D.N; ++rb)
-                for (int q = 0; q < D.sv.splits; ++q) P.phi_work[c].push_back(make_int4(p, rb, q, 0));
+            const int c = phi32_class(D.d);
+            for (int rb = 0; rb * phi_rows < D.sv.npad; ++rb)
+                for (int q = 0; q < D.sv.splits32; ++q) P.phi_work[c].push_back(make_int4(p, rb, q, 0));
         }
         // BF16 form: its lists do not depend on the row block of the FP32 form
         for (int r0 = 0; r0 < D.N; r0 += kRows16) P.row16_work.push_back(make_int4(p, r0, 0, 0));
@@ -260,13 +259,11 @@ void build_plan(int n, const stamp_scene* scenes, const int32_t* N, int K, float
     // The contraction lists get the room of their longest form (64-row
     // blocks), so that no region of the workspace moves when the row block
     // changes: pointers into it stay valid across every launch shape.
-    size_t phi_cap[kDpClasses] = {};
+    size_t phi_cap[kPhi32Classes] = {};
     for (int p = 0; p < n; ++p) {
         const ProblemDesc& D = P.descs[p];
         if (D.N < 2) continue;
-        int c = 0;
-        while (kDpClass[c] != svgd_dp_class(D.d)) ++c;
-        phi_cap[c] += (size_t)((D.N + 63) / 64) * D.sv.splits;
+        phi_cap[phi32_class(D.d)] += (size_t)(D.sv.npad / 64) * D.sv.splits32;
     }
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -280,7 +277,7 @@ void build_plan(int n, const stamp_scene* scenes, const int32_t* N, int K, float
     P.dist_off = take(P.dist_work.size() * sizeof(int4));
     P.cand_off = take(P.cand_work.size() * sizeof(int4));
     P.red_off = take(P.red_work.size() * sizeof(int4));
-    for (int c = 0; c < kDpClasses; ++c) P.phi_off[c] = take(phi_cap[c] * sizeof(int4));
+    for (int c = 0; c < kPhi32Classes; ++c) P.phi_off[c] = take(phi_cap[c] * sizeof(int4));
     P.ctr16_off = take(P.ctr_work.size() * sizeof(int4));
     P.row16_off = take(P.row16_work.size() * sizeof(int4));
     for (int c = 0; c < 2; ++c) P.phi16_off[c] = take(P.phi16_work[c].size() * sizeof(int4));
@@ -311,7 +308,7 @@ bool same_layout(const SolvePlan& a, const SolvePlan& b) {
               a.ctr_off == b.ctr_off && a.err_off == b.err_off && a.tape_off == b.tape_off && a.seg_off == b.seg_off &&
               a.grad_off == b.grad_off && a.phi_vec_off == b.phi_vec_off && a.cost_off == b.cost_off &&
               a.cdisc_off == b.cdisc_off && a.wts_off == b.wts_off && a.svgd_off == b.svgd_off;
-    for (int c = 0; c < kDpClasses; ++c) ok = ok && a.phi_off[c] == b.phi_off[c];
+    for (int c = 0; c < kPhi32Classes; ++c) ok = ok && a.phi_off[c] == b.phi_off[c];
     ok = ok && a.ctr16_off == b.ctr16_off && a.row16_off == b.row16_off && a.phi16_off[0] == b.phi16_off[0] &&
          a.phi16_off[1] == b.phi16_off[1];
     return ok;
@@ -528,7 +525,7 @@ int32_t stamp_svgd_bandwidth(stamp_ctx* ctx, int32_t N, int32_t d, const float* 
     const SvgdLayout L = svgd_workspace_layout(N, d);
     if (!workspace || ws_bytes < L.total)
         return fail(ctx, STAMP_ENOSPACE, "svgd workspace %zu < %zu bytes", ws_bytes, L.total);
-    hipError_t e = launch_median(N, d, theta, bandwidth, 1, workspace, L, h_out, (hipStream_t)stream);
+    hipError_t e = launch_svgd_bandwidth(N, d, theta, bandwidth, h_out, workspace, L, (hipStream_t)stream);
     return e == hipSuccess ? STAMP_OK : hip_fail(ctx, e, "svgd_bandwidth");
 }
 
@@ -727,7 +724,7 @@ static int32_t solve_impl(stamp_ctx* ctx, int32_t n_problems, const stamp_scene*
         if ((r = upload(P.dist_off, P.dist_work.data(), P.dist_work.size() * sizeof(int4))) != hipSuccess) return r;
         if ((r = upload(P.cand_off, P.cand_work.data(), P.cand_work.size() * sizeof(int4))) != hipSuccess) return r;
         if ((r = upload(P.red_off, P.red_work.data(), P.red_work.size() * sizeof(int4))) != hipSuccess) return r;
-        for (int c = 0; c < kDpClasses; ++c)
+        for (int c = 0; c < kPhi32Classes; ++c)
             if ((r = upload(P.phi_off[c], P.phi_work[c].data(), P.phi_work[c].size() * sizeof(int4))) != hipSuccess)
                 return r;
         if ((r = upload(P.ctr16_off, P.ctr_work.data(), P.ctr_work.size() * sizeof(int4))) != hipSuccess) return r;
@@ -748,7 +745,7 @@ static int32_t solve_impl(stamp_ctx* ctx, int32_t n_problems, const stamp_scene*
         B.med_classes = P.med_classes;
         B.cand_work = (const int4*)(ws + P.cand_off);
         B.n_cand = (int)P.cand_work.size();
-        for (int c = 0; c < kDpClasses; ++c) {
+        for (int c = 0; c < kPhi32Classes; ++c) {
             B.phi_work[c] = (const int4*)(ws + P.phi_off[c]);
             B.n_phi[c] = (int)P.phi_work[c].size();
         }
@@ -843,7 +840,7 @@ static int32_t solve_impl(stamp_ctx* ctx, int32_t n_problems, const stamp_scene*
     // side stream while the rollout produces the gradient; the direction stage
     // joins it.  exact = 0: the BF16 form's sampled median.
     auto bandwidth_stage = [&](hipStream_t s, int exact) -> hipError_t {
-        if (skern.empty()) return launch_median_batched(B, d_desc, theta, exact, d_svgd, s);
+        if (skern.empty()) return launch_svgd_bandwidth_batched(B, d_desc, theta, exact, d_svgd, s);
         for (int p = 0; p < n_problems; ++p) {
             const ProblemDesc& D = P.descs[p];
             hipError_t r = launch_struct_bandwidth(D.N, theta + D.theta_off, skern[p], d_svgd + D.svgd_off, D.sv, s);

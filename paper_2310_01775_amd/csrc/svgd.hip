@@ -6,16 +6,17 @@
 //   phi_i = (1/N) sum_j exp(-D_ij/h) [ g_j + (2/h)(theta_i - theta_j) ]
 //
 // The median (median.hip) is the exact order statistic of the FP32 distances,
-// found by an interval select seeded from a sample of pairs.
-//
-// The contraction recomputes D in (row block x column chunk) tiles with
-// theta_j and g_j staged through LDS, writes per-chunk partial sums, and a
-// second kernel sums the chunks in a fixed order.  Chunk boundaries depend on N
-// only, so the arithmetic is the same for every launch shape.
+// found by an interval select seeded from a sample of pairs.  The contraction
+// runs on the FP32 matrix cores (phi32.hip).  This file holds the workspace
+// layout, the step's launchers, the split-sum reduce that the structured
+// kernel's contraction shares, the importance weights of Eq. (4), the update
+// and small helpers.
 //
 // Each stage has a single-problem kernel and a batched kernel over a work list
 // of many problems; both call the same device body.
 #include <math.h>
+
+#include <algorithm>
 
 #include "common.h"
 #include "internal.h"
@@ -26,57 +27,6 @@ namespace {
 
 
 // ---- bodies -----------------------------------------------------------------
-
-// partial[split][l][i] = sum_{j in [j0, j1)} w_j K_ij (g_jl + (2/h)(theta_il - theta_jl))
-// for the rows i = row0 + threadIdx.x of this workgroup; w_j = wts[j], or 1
-// when wts is null (the importance weights of Eq. 4, scaled to mean 1).
-template <int DP>
-__device__ __forceinline__ void phi_partial_body(int N, int d, int row0, int j0, int j1, int split,
-                                                 const float* __restrict__ theta, const float* __restrict__ g,
-                                                 const float* __restrict__ wts, const SelState* __restrict__ sel,
-                                                 float* __restrict__ partial) {
-    constexpr int JT = 64;  // columns staged per round
-    __shared__ float tj[JT][DP];
-    __shared__ float gj[JT][DP];
-    __shared__ float wj[JT];
-    const int i = row0 + threadIdx.x;
-    const float inv_h = 1.0f / sel->h;
-    const float c2 = 2.0f * inv_h;
-    const int ii = min(i, N - 1);
-    float ti[DP], acc[DP];
-#pragma unroll
-    for (int l = 0; l < DP; ++l) {
-        ti[l] = l < d ? theta[(int64_t)l * N + ii] : 0.0f;
-        acc[l] = 0.0f;
-    }
-    for (int jb = j0; jb < j1; jb += JT) {
-        const int nj = min(JT, j1 - jb);
-        __syncthreads();
-        for (int e = threadIdx.x; e < JT * DP; e += blockDim.x) {  // consecutive threads, consecutive columns
-            const int jj = e % JT, l = e / JT;
-            const bool ok = jj < nj && l < d;
-            tj[jj][l] = ok ? theta[(int64_t)l * N + jb + jj] : 0.0f;
-            gj[jj][l] = ok ? g[(int64_t)l * N + jb + jj] : 0.0f;
-        }
-        for (int jj = threadIdx.x; jj < JT; jj += blockDim.x) wj[jj] = (wts && jj < nj) ? wts[jb + jj] : 1.0f;
-        __syncthreads();
-        for (int jj = 0; jj < nj; ++jj) {
-            float D = 0.0f;
-#pragma unroll
-            for (int l = 0; l < DP; ++l) {
-                const float df = ti[l] - tj[jj][l];
-                D = fmaf(df, df, D);
-            }
-            const float k = wts ? expf(-D * inv_h) * wj[jj] : expf(-D * inv_h);
-#pragma unroll
-            for (int l = 0; l < DP; ++l) acc[l] = fmaf(k, fmaf(c2, ti[l] - tj[jj][l], gj[jj][l]), acc[l]);
-        }
-    }
-    if (i < N) {
-        float* out = partial + (int64_t)split * d * N;
-        for (int l = 0; l < d; ++l) out[(int64_t)l * N + i] = acc[l];
-    }
-}
 
 // phi[e] = (sum over splits of partial[q][e], in split order) / N
 __device__ __forceinline__ void phi_reduce_elem(int64_t e, int64_t n, int N, int splits,
@@ -97,15 +47,6 @@ __device__ __forceinline__ void phi_reduce_elem(int64_t e, int64_t n, int N, int
 
 // ---- single-problem kernels ---------------------------------------------------
 
-template <int DP>
-__global__ __launch_bounds__(256) void k_phi_partial(int N, int d, int chunk, const float* __restrict__ theta,
-                                                     const float* __restrict__ g, const float* __restrict__ wts,
-                                                     const SelState* __restrict__ sel, float* __restrict__ partial) {
-    const int split = blockIdx.y;
-    const int j0 = split * chunk, j1 = min(j0 + chunk, N);
-    phi_partial_body<DP>(N, d, blockIdx.x * blockDim.x, j0, j1, split, theta, g, wts, sel, partial);
-}
-
 __global__ __launch_bounds__(256) void k_phi_reduce(int N, int d, int splits, const float* __restrict__ partial,
                                                     float* __restrict__ phi, uint32_t* status) {
     const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -113,31 +54,10 @@ __global__ __launch_bounds__(256) void k_phi_reduce(int N, int d, int splits, co
     if (e < n) phi_reduce_elem(e, n, N, splits, partial, phi, status);
 }
 
-__global__ void k_copy(const float* __restrict__ a, float* __restrict__ b, int64_t n) {
-    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (e < n) b[e] = a[e];
-}
-
 // ---- batched kernels ----------------------------------------------------------
 // Work-list entries are int4 (problem, a, b, c) with a stage-specific meaning.
 
 __device__ __forceinline__ char* svgd_base(const ProblemDesc& D, char* ws) { return ws + D.svgd_off; }
-
-// entry = (problem, row block, split, -)
-// wts: per-particle weights packed like the costs (problem p at cost_off), or null
-template <int DP>
-__global__ __launch_bounds__(256) void k_phi_partial_batched(const ProblemDesc* __restrict__ descs,
-                                                             const int4* __restrict__ work, const float* theta,
-                                                             const float* grad, const float* wts, char* ws) {
-    const int4 w = work[blockIdx.x];
-    const ProblemDesc& D = descs[w.x];
-    char* b = svgd_base(D, ws);
-    const int chunk = (D.N + D.sv.splits - 1) / D.sv.splits;
-    const int j0 = w.z * chunk, j1 = min(j0 + chunk, D.N);
-    phi_partial_body<DP>(D.N, D.d, w.y * (int)blockDim.x, j0, j1, w.z, theta + D.theta_off, grad + D.theta_off,
-                         wts ? wts + D.cost_off : nullptr, reinterpret_cast<const SelState*>(b + D.sv.sel_off),
-                         reinterpret_cast<float*>(b + D.sv.part_off));
-}
 
 // Importance weights of Eq. (4) for one problem (one workgroup of 256):
 // w_j proportional to exp(C_disc,j - C_rel,j), the relaxed over the discrete
@@ -191,23 +111,6 @@ __global__ __launch_bounds__(256) void k_dsvgd_weights_batched(const ProblemDesc
                                                                const float* c_rel, const float* c_disc, float* w) {
     const ProblemDesc& D = descs[blockIdx.x];
     dsvgd_weights_body(D.N, c_rel + D.cost_off, c_disc + D.cost_off, w + D.cost_off);
-}
-
-// entry = (problem, first element, end element, -) of the problem's d*N block
-__global__ __launch_bounds__(256) void k_phi_reduce_batched(const ProblemDesc* __restrict__ descs,
-                                                            const int4* __restrict__ work, const float* grad,
-                                                            float* phi, char* ws, uint32_t* status) {
-    const int4 w = work[blockIdx.x];
-    const ProblemDesc& D = descs[w.x];
-    const int64_t e = w.y + threadIdx.x;
-    if (e >= w.z) return;
-    if (D.N == 1) {  // phi = g
-        phi[D.theta_off + e] = grad[D.theta_off + e];
-        return;
-    }
-    const int64_t n = (int64_t)D.d * D.N;
-    phi_reduce_elem(e, n, D.N, D.sv.splits, reinterpret_cast<const float*>(svgd_base(D, ws) + D.sv.part_off),
-                    phi + D.theta_off, status);
 }
 
 __global__ __launch_bounds__(256) void k_update(int64_t n, float* __restrict__ theta, const float* __restrict__ phi,
@@ -264,23 +167,7 @@ __global__ void k_incr(int* p) { *p += 1; }
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-template <int DP>
-hipError_t launch_phi_partial(int N, int d, int chunk, int splits, int rows, const float* theta, const float* g,
-                              const float* wts, const SelState* sel, float* partial, hipStream_t st) {
-    dim3 grid((N + rows - 1) / rows, splits);
-    hipLaunchKernelGGL(k_phi_partial<DP>, grid, dim3(rows), 0, st, N, d, chunk, theta, g, wts, sel, partial);
-    return hipGetLastError();
-}
-
-template <int DP>
-void launch_phi_partial_batched(int n, int rows, const ProblemDesc* descs, const int4* work, const float* theta,
-                                const float* grad, const float* wts, char* ws, hipStream_t st) {
-    hipLaunchKernelGGL(k_phi_partial_batched<DP>, dim3(n), dim3(rows), 0, st, descs, work, theta, grad, wts, ws);
-}
-
 }  // namespace
-
-int svgd_dp_class(int d) { return d <= 8 ? 8 : d <= 16 ? 16 : d <= 24 ? 24 : d <= 32 ? 32 : d <= 48 ? 48 : 64; }
 
 SvgdLayout svgd_workspace_layout(int N, int d) {
     SvgdLayout L{};
@@ -307,7 +194,26 @@ SvgdLayout svgd_workspace_layout(int N, int d) {
     if (splits > 64) splits = 64;
     if (splits < 1) splits = 1;
     L.splits = splits;
-    L.part_floats = (size_t)splits * d * N;
+    // FP32 matrix-core form: rows padded to the 256-row block; column splits
+    // of a multiple of 16 columns: about 2048 (64-row wave x split) items, but
+    // at least 64 columns per split, so that small problems do not pay for many
+    // partial sums in the reduce
+    L.npad = (N + kRows16 - 1) / kRows16 * kRows16;
+    L.ks32 = phi32_ks(d);
+    L.ot32 = phi32_ot(d);
+    {
+        const int waves = L.npad / 64;
+        int s32 = (2048 + waves - 1) / waves;
+        if (s32 > L.npad / 64) s32 = L.npad / 64;
+        if (s32 < 1) s32 = 1;
+        const int chunk = ((L.npad + s32 - 1) / s32 + 15) / 16 * 16;
+        L.splits32 = (L.npad + chunk - 1) / chunk;
+        L.chunk32 = chunk;
+    }
+    // the partial sums of both contractions share one region: the FP32
+    // matrix-core form's [splits32][16 ot][npad] and the structured kernel's
+    // [splits][d][N]
+    L.part_floats = std::max((size_t)splits * d * N, (size_t)L.splits32 * 16 * L.ot32 * L.npad);
     size_t off = 0;
     L.cand_off = off;
     off = align256(off + (N >= 2 ? (size_t)L.cand_cap * 4 : 0));
@@ -319,8 +225,13 @@ SvgdLayout svgd_workspace_layout(int N, int d) {
     off = align256(off + sizeof(SelState));
     L.part_off = off;
     off = align256(off + L.part_floats * 4);
+    L.x32_off = off;
+    off = align256(off + (size_t)L.npad * 4 * L.ks32 * 4);
+    L.n32_off = off;
+    off = align256(off + (size_t)L.npad * 4);
+    L.v32_off = off;
+    off = align256(off + (size_t)L.npad * 16 * L.ot32 * 4);
     // BF16 matrix-core form
-    L.npad = (N + kRows16 - 1) / kRows16 * kRows16;
     L.kd = d <= 32 ? 32 : 64;
     L.vc = 2 * L.kd;
     {
@@ -356,63 +267,31 @@ SvgdLayout svgd_workspace_layout(int N, int d) {
 hipError_t launch_svgd(int N, int d, const float* theta, const float* grad_logp, float bandwidth, float* phi,
                        float* h_out, void* ws, const SvgdLayout& L, int phi_rows, uint32_t* status, hipStream_t st,
                        const float* wts) {
-    hipError_t e = launch_median(N, d, theta, bandwidth, 1, ws, L, h_out, st);
+    hipError_t e = launch_svgd_bandwidth(N, d, theta, bandwidth, h_out, ws, L, st);
     if (e != hipSuccess) return e;
     return launch_svgd_direction(N, d, theta, grad_logp, phi, ws, L, phi_rows, status, st, wts);
 }
 
-hipError_t launch_svgd_direction(int N, int d, const float* theta, const float* grad_logp, float* phi, void* ws,
-                                 const SvgdLayout& L, int phi_rows, uint32_t* status, hipStream_t st,
-                                 const float* wts) {
-    char* base = static_cast<char*>(ws);
-    SelState* sel = reinterpret_cast<SelState*>(base + L.sel_off);
-    hipError_t e;
-    if (N == 1) {  // phi = g
-        hipLaunchKernelGGL(k_copy, dim3((d + 255) / 256), dim3(256), 0, st, grad_logp, phi, (int64_t)d);
-        return hipGetLastError();
-    }
-    float* partial = reinterpret_cast<float*>(base + L.part_off);
-    const int chunk = (N + L.splits - 1) / L.splits;
-    const int rows = phi_rows > 0 ? phi_rows : 256;
-    switch (svgd_dp_class(d)) {
-        case 8: e = launch_phi_partial<8>(N, d, chunk, L.splits, rows, theta, grad_logp, wts, sel, partial, st); break;
-        case 16: e = launch_phi_partial<16>(N, d, chunk, L.splits, rows, theta, grad_logp, wts, sel, partial, st); break;
-        case 24: e = launch_phi_partial<24>(N, d, chunk, L.splits, rows, theta, grad_logp, wts, sel, partial, st); break;
-        case 32: e = launch_phi_partial<32>(N, d, chunk, L.splits, rows, theta, grad_logp, wts, sel, partial, st); break;
-        case 48: e = launch_phi_partial<48>(N, d, chunk, L.splits, rows, theta, grad_logp, wts, sel, partial, st); break;
-        default: e = launch_phi_partial<64>(N, d, chunk, L.splits, rows, theta, grad_logp, wts, sel, partial, st); break;
-    }
+hipError_t launch_svgd_bandwidth(int N, int d, const float* theta, float bandwidth, float* h_out, void* ws,
+                                 const SvgdLayout& L, hipStream_t st) {
+    hipError_t e = launch_median(N, d, theta, bandwidth, 1, ws, L, h_out, st);
     if (e != hipSuccess) return e;
-    const int64_t n = (int64_t)d * N;
-    hipLaunchKernelGGL(k_phi_reduce, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, N, d, L.splits, partial,
-                       phi, status);
-    return hipGetLastError();
+    return launch_operands32(N, d, theta, ws, L, st);
 }
 
 hipError_t launch_svgd_batched(const BatchPlan& P, const ProblemDesc* descs, const float* theta, const float* grad,
                                float* phi, char* ws, uint32_t* status, hipStream_t st, const float* wts) {
-    hipError_t e = launch_median_batched(P, descs, theta, 1, ws, st);
+    hipError_t e = launch_svgd_bandwidth_batched(P, descs, theta, 1, ws, st);
     if (e != hipSuccess) return e;
     return launch_svgd_direction_batched(P, descs, theta, grad, phi, ws, status, st, wts);
 }
 
-hipError_t launch_svgd_direction_batched(const BatchPlan& P, const ProblemDesc* descs, const float* theta,
-                                         const float* grad, float* phi, char* ws, uint32_t* status, hipStream_t st,
-                                         const float* wts) {
-    for (int c = 0; c < kDpClasses; ++c) {
-        if (!P.n_phi[c]) continue;
-        switch (kDpClass[c]) {
-            case 8: launch_phi_partial_batched<8>(P.n_phi[c], P.phi_rows, descs, P.phi_work[c], theta, grad, wts, ws, st); break;
-            case 16: launch_phi_partial_batched<16>(P.n_phi[c], P.phi_rows, descs, P.phi_work[c], theta, grad, wts, ws, st); break;
-            case 24: launch_phi_partial_batched<24>(P.n_phi[c], P.phi_rows, descs, P.phi_work[c], theta, grad, wts, ws, st); break;
-            case 32: launch_phi_partial_batched<32>(P.n_phi[c], P.phi_rows, descs, P.phi_work[c], theta, grad, wts, ws, st); break;
-            case 48: launch_phi_partial_batched<48>(P.n_phi[c], P.phi_rows, descs, P.phi_work[c], theta, grad, wts, ws, st); break;
-            default: launch_phi_partial_batched<64>(P.n_phi[c], P.phi_rows, descs, P.phi_work[c], theta, grad, wts, ws, st); break;
-        }
-    }
-    hipLaunchKernelGGL(k_phi_reduce_batched, dim3(P.n_red), dim3(256), 0, st, descs, P.red_work, grad, phi, ws,
-                       status);
-    return hipGetLastError();
+hipError_t launch_svgd_bandwidth_batched(const BatchPlan& P, const ProblemDesc* descs, const float* theta, int exact,
+                                         char* ws, hipStream_t st) {
+    hipError_t e = launch_median_batched(P, descs, theta, exact, ws, st);
+    if (e != hipSuccess) return e;
+    // the FP32 form's operands (the BF16 form, exact = 0, builds its own)
+    return exact ? launch_operands32_batched(P, descs, theta, ws, st) : hipSuccess;
 }
 
 hipError_t launch_phi_reduce(int N, int d, int splits, const float* partial, float* phi, uint32_t* status,
