@@ -200,8 +200,7 @@ def main():
         if evs:
             evs[2].record()
         main.wait_event(ev_join)
-        ctx.svgd_direction(theta, grad, sws, phi=phi)
-        ctx.adam_step(theta, phi, m, v, t, lr=lr)
+        ctx.svgd_update(theta, grad, sws, m, v, t, lr=lr)  # direction + Adam in one pass
         if evs:
             evs[3].record()
 

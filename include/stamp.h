@@ -210,6 +210,14 @@ int32_t stamp_svgd_bandwidth(stamp_ctx* ctx, int32_t N, int32_t d, const float* 
                              float* h_out, void* workspace, size_t ws_bytes, void* stream);
 int32_t stamp_svgd_direction(stamp_ctx* ctx, int32_t N, int32_t d, const float* theta, const float* grad_logp,
                              const float* weights, float* phi, void* workspace, size_t ws_bytes, void* stream);
+/* stamp_svgd_direction followed by stamp_adam_step in one pass: phi from the
+ * bandwidth the workspace holds, then the update of Algorithm 1 applied to
+ * theta in place (Adam at step t >= 1 with moments m, v, or theta += lr phi
+ * when use_adam = 0); phi [d][N] is also stored when not NULL.  Bit for bit
+ * the two calls' result.  Errors: those of both calls. */
+int32_t stamp_svgd_update(stamp_ctx* ctx, int32_t N, int32_t d, float* theta, const float* grad_logp,
+                          const float* weights, float* phi, float* m, float* v, int32_t t, float lr, float beta1,
+                          float beta2, float eps, int32_t use_adam, void* workspace, size_t ws_bytes, void* stream);
 
 /* The SVGD direction of stamp_svgd_step in reduced precision on the BF16
  * matrix cores, for iterations whose gradients are approximate anyway (the

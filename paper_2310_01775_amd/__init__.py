@@ -92,6 +92,8 @@ _sig = {
     "stamp_svgd_step_weighted": (_i32, [_vp, _i32, _i32, _vp, _vp, _vp, C.c_float, _vp, _vp, _vp, _sz, _vp]),
     "stamp_svgd_bandwidth": (_i32, [_vp, _i32, _i32, _vp, _f32, _vp, _vp, _sz, _vp]),
     "stamp_svgd_direction": (_i32, [_vp, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "stamp_svgd_update": (_i32, [_vp, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _f32, _f32, _f32, _f32, _i32,
+                                 _vp, _sz, _vp]),
     "stamp_svgd_step_structured": (_i32, [_vp, _i32, _i32, _vp, _vp, _vp, _P(StructKernel), _vp, _vp, _vp, _sz,
                                           _vp]),
     "stamp_plan_readout": (_i32, [_vp, _P(Scene), _P(CostW), _i32, _vp, _vp, _vp, _vp, _sz, _vp, _vp]),
@@ -348,6 +350,17 @@ class Context:
         self._check(_lib.stamp_svgd_direction(self._h, N, d, _ptr(theta), _ptr(grad_logp), _ptr(weights), _ptr(phi),
                                               _ptr(workspace), workspace.numel(), _stream(stream)))
         return phi
+
+    def svgd_update(self, theta, grad_logp, workspace, m, v, t: int, lr: float = 1e-3, beta1: float = 0.9,
+                    beta2: float = 0.999, eps: float = 1e-8, use_adam: bool = True, weights=None, phi=None,
+                    stream=None):
+        """stamp_svgd_update: direction from the workspace's bandwidth, then the update of theta in place."""
+        d, N = theta.shape
+        self._check(_lib.stamp_svgd_update(self._h, N, d, _ptr(theta), _ptr(grad_logp), _ptr(weights), _ptr(phi),
+                                           _ptr(m), _ptr(v), int(t), float(lr), float(beta1), float(beta2),
+                                           float(eps), int(bool(use_adam)), _ptr(workspace), workspace.numel(),
+                                           _stream(stream)))
+        return theta
 
     def svgd_step_structured(self, theta, grad_logp, kernel: StructKernel, weights=None, phi=None, h_out=None,
                              workspace=None, stream=None):

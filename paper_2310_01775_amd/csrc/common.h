@@ -174,6 +174,43 @@ struct BatchPlan {
     const int4* red_work;   int n_red;    // (p, first elem, end elem, -)
 };
 
+// The update of Algorithm 1 on one element: Adam minimising -phi with the
+// bias-correction denominators den = (1 - b1^t, 1 - b2^t), or theta += lr phi.
+struct UpdateArgs {
+    float* theta;
+    float* m;
+    float* v;
+    int t0;
+    const int* t_dev;  // non-null: step t = t0 + *t_dev + 1 (graph replay), else t = t0
+    float lr, b1, b2, eps;
+    int use_adam;
+};
+
+// den[0..1] for the workgroup, computed by thread 0 (call from every thread)
+__device__ __forceinline__ void update_denominators(const UpdateArgs& u, float* den) {
+    if (u.use_adam && threadIdx.x == 0) {
+        const int t = u.t_dev ? u.t0 + *u.t_dev + 1 : u.t0;
+        den[0] = 1.0f - powf(u.b1, (float)t);
+        den[1] = 1.0f - powf(u.b2, (float)t);
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ void update_elem(const UpdateArgs& u, const float* den, int64_t e, float f) {
+    if (!u.use_adam) {
+        u.theta[e] = u.theta[e] + u.lr * f;
+        return;
+    }
+    const float gr = -f;
+    const float mm = u.b1 * u.m[e] + (1.0f - u.b1) * gr;
+    const float vv = u.b2 * u.v[e] + (1.0f - u.b2) * gr * gr;
+    u.m[e] = mm;
+    u.v[e] = vv;
+    const float mhat = mm / den[0];
+    const float vhat = vv / den[1];
+    u.theta[e] = u.theta[e] - u.lr * mhat / (sqrtf(vhat) + u.eps);
+}
+
 // Phase k of a T-step, H-push rollout: steps [t_k, t_{k+1}), t_k = ceil(kT/H).
 __host__ __device__ inline int phase_start(int k, int T, int H) { return (k * T + H - 1) / H; }
 

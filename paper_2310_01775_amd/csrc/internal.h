@@ -47,12 +47,14 @@ hipError_t launch_operands32_batched(const BatchPlan& P, const ProblemDesc* desc
                                      hipStream_t st);
 // The step's second half: phi from the bandwidth and centre the workspace
 // holds (FP32 matrix cores, phi32.hip).
+// upd (nullable): apply the update of Algorithm 1 to theta in the same pass
+// (phi may then be null); theta is read for every element before its update.
 hipError_t launch_svgd_direction(int N, int d, const float* theta, const float* grad_logp, float* phi, void* ws,
                                  const SvgdLayout& L, int phi_rows, uint32_t* status, hipStream_t st,
-                                 const float* wts = nullptr);
+                                 const float* wts = nullptr, const UpdateArgs* upd = nullptr);
 hipError_t launch_svgd_direction_batched(const BatchPlan& P, const ProblemDesc* descs, const float* theta,
                                          const float* grad, float* phi, char* ws, uint32_t* status, hipStream_t st,
-                                         const float* wts = nullptr);
+                                         const float* wts = nullptr, const UpdateArgs* upd = nullptr);
 // The same step for every problem of a batch (work lists in P); wts packed
 // like the costs (problem p at its cost offset), or null.
 hipError_t launch_svgd_batched(const BatchPlan& P, const ProblemDesc* descs, const float* theta, const float* grad,

@@ -200,8 +200,11 @@ __device__ void phi32_body(int N, int d, int row0, int j0, int j1, int split, in
 
 // ---- phi from the split sums (fixed split order) ----------------------------------
 // the coordinate's row and the row-sum row of every split, 16 loads in flight
-__device__ void reduce32_elem(int N, int d, const SvgdLayout& L, int l, int i, const float* __restrict__ theta,
-                              float* __restrict__ phi, const View32& v, uint32_t* status) {
+// phi (stored when phi is not null) and, with upd, the update of Algorithm 1
+// on the same element (theta read for x before the update writes it)
+__device__ void reduce32_elem(int N, int d, const SvgdLayout& L, int l, int i, const float* theta, float* phi,
+                              const View32& v, uint32_t* status, const UpdateArgs* upd, const float* den,
+                              int64_t uoff) {
     const int64_t sstride = (int64_t)16 * L.ot32 * L.npad;
     const float* pa = v.part + (int64_t)l * L.npad + i;
     const float* p1 = v.part + (int64_t)d * L.npad + i;
@@ -222,8 +225,9 @@ __device__ void reduce32_elem(int N, int d, const SvgdLayout& L, int l, int i, c
     }
     const float x = theta[(int64_t)l * N + i] - v.ctr[l];
     const float r = fmaf(2.0f / v.sel->h * x, a1, a) / (float)N;
-    phi[(int64_t)l * N + i] = r;
+    if (phi) phi[(int64_t)l * N + i] = r;
     if (status && !isfinite(r)) atomicOr(status, STAMP_STATUS_NONFINITE_PHI);
+    if (upd) update_elem(*upd, den, uoff + (int64_t)l * N + i, r);
 }
 
 // ---- single-problem kernels -------------------------------------------------------
@@ -247,15 +251,21 @@ __global__ __launch_bounds__(256) void k_phi32(One32 a, const float* g, const fl
     phi32_body<KS, OT>(a.N, a.d, blockIdx.x * blockDim.x, j0, j1, split, a.L.npad, g, wts, view32(a.L, ws));
 }
 
+// upd.use_adam < 0: no update
 __global__ __launch_bounds__(256) void k_reduce32(One32 a, const float* theta, const float* g, float* phi, char* ws,
-                                                  uint32_t* status) {
+                                                  uint32_t* status, UpdateArgs upd) {
+    __shared__ float den[2];
+    const bool apply = upd.use_adam >= 0;
+    if (apply) update_denominators(upd, den);
     const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (e >= (int64_t)a.d * a.N) return;
     if (a.N == 1) {
-        phi[e] = g[e];
+        if (phi) phi[e] = g[e];
+        if (apply) update_elem(upd, den, e, g[e]);
         return;
     }
-    reduce32_elem(a.N, a.d, a.L, (int)(e / a.N), (int)(e % a.N), theta, phi, view32(a.L, ws), status);
+    reduce32_elem(a.N, a.d, a.L, (int)(e / a.N), (int)(e % a.N), theta, phi, view32(a.L, ws), status,
+                  apply ? &upd : nullptr, den, 0);
 }
 
 // ---- batched kernels (work-list entries as in svgd.hip) ------------------------------
@@ -292,20 +302,25 @@ __global__ __launch_bounds__(256) void k_phi32_batched(const ProblemDesc* __rest
 }
 
 // entry = (problem, first element, end element, -) of the problem's d*N block
+// phi may be null when the update is applied (upd.use_adam >= 0)
 __global__ __launch_bounds__(256) void k_reduce32_batched(const ProblemDesc* __restrict__ descs,
                                                           const int4* __restrict__ work, const float* theta,
                                                           const float* grad, float* phi, char* ws,
-                                                          uint32_t* status) {
+                                                          uint32_t* status, UpdateArgs upd) {
+    __shared__ float den[2];
+    const bool apply = upd.use_adam >= 0;
+    if (apply) update_denominators(upd, den);
     const int4 w = work[blockIdx.x];
     const ProblemDesc& D = descs[w.x];
     const int64_t e = w.y + threadIdx.x;
     if (e >= w.z) return;
     if (D.N == 1) {
-        phi[D.theta_off + e] = grad[D.theta_off + e];
+        if (phi) phi[D.theta_off + e] = grad[D.theta_off + e];
+        if (apply) update_elem(upd, den, D.theta_off + e, grad[D.theta_off + e]);
         return;
     }
-    reduce32_elem(D.N, D.d, D.sv, (int)(e / D.N), (int)(e % D.N), theta + D.theta_off, phi + D.theta_off,
-                  view32(D.sv, base32(D, ws)), status);
+    reduce32_elem(D.N, D.d, D.sv, (int)(e / D.N), (int)(e % D.N), theta + D.theta_off, phi ? phi + D.theta_off : nullptr,
+                  view32(D.sv, base32(D, ws)), status, apply ? &upd : nullptr, den, D.theta_off);
 }
 
 // (ks, ot) of each class, in the order of phi32_class
@@ -370,7 +385,7 @@ hipError_t launch_operands32_batched(const BatchPlan& P, const ProblemDesc* desc
 
 hipError_t launch_svgd_direction(int N, int d, const float* theta, const float* grad_logp, float* phi, void* ws,
                                  const SvgdLayout& L, int phi_rows, uint32_t* status, hipStream_t st,
-                                 const float* wts) {
+                                 const float* wts, const UpdateArgs* upd) {
     One32 a{N, d, L};
     char* b = static_cast<char*>(ws);
     if (N >= 2) {
@@ -379,22 +394,28 @@ hipError_t launch_svgd_direction(int N, int d, const float* theta, const float* 
         by_class(phi32_class(d), [&](auto c) { launch_class<decltype(c)::value>(grid, rows, st, a, grad_logp, wts, b); });
     }
     const int64_t n = (int64_t)d * N;
+    UpdateArgs u{};
+    u.use_adam = -1;
+    if (upd) u = *upd;
     hipLaunchKernelGGL(k_reduce32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a, theta, grad_logp, phi, b,
-                       status);
+                       status, u);
     return hipGetLastError();
 }
 
 hipError_t launch_svgd_direction_batched(const BatchPlan& P, const ProblemDesc* descs, const float* theta,
                                          const float* grad, float* phi, char* ws, uint32_t* status, hipStream_t st,
-                                         const float* wts) {
+                                         const float* wts, const UpdateArgs* upd) {
     for (int c = 0; c < kPhi32Classes; ++c)
         if (P.n_phi[c])
             by_class(c, [&](auto k) {
                 launch_class_batched<decltype(k)::value>(P.n_phi[c], P.phi_rows, st, descs, P.phi_work[c], grad, wts,
                                                          ws);
             });
+    UpdateArgs u{};
+    u.use_adam = -1;
+    if (upd) u = *upd;
     hipLaunchKernelGGL(k_reduce32_batched, dim3(P.n_red), dim3(256), 0, st, descs, P.red_work, theta, grad, phi, ws,
-                       status);
+                       status, u);
     return hipGetLastError();
 }
 

@@ -544,6 +544,27 @@ int32_t stamp_svgd_direction(stamp_ctx* ctx, int32_t N, int32_t d, const float* 
     return e == hipSuccess ? STAMP_OK : hip_fail(ctx, e, "svgd_direction");
 }
 
+int32_t stamp_svgd_update(stamp_ctx* ctx, int32_t N, int32_t d, float* theta, const float* grad_logp,
+                          const float* weights, float* phi, float* m, float* v, int32_t t, float lr, float beta1,
+                          float beta2, float eps, int32_t use_adam, void* workspace, size_t ws_bytes, void* stream) {
+    if (!ctx) return STAMP_EINVAL;
+    if (!theta || !grad_logp) return fail(ctx, STAMP_EINVAL, "null theta or grad_logp");
+    if (use_adam && (!m || !v)) return fail(ctx, STAMP_EINVAL, "Adam needs m and v");
+    if (N < 1 || d < 1) return fail(ctx, STAMP_EINVAL, "N=%d, d=%d must be >= 1", N, d);
+    if (d > kMaxSvgdDim || N > kMaxSvgdN)
+        return fail(ctx, STAMP_EUNSUPPORTED, "svgd step supports d <= %d, N <= %d", kMaxSvgdDim, kMaxSvgdN);
+    if (use_adam && t < 1) return fail(ctx, STAMP_EINVAL, "Adam step t=%d < 1", t);
+    if (!isfinite(lr) || (use_adam && !(beta1 >= 0 && beta1 < 1 && beta2 >= 0 && beta2 < 1 && eps >= 0)))
+        return fail(ctx, STAMP_EINVAL, "bad Adam hyper-parameters");
+    const SvgdLayout L = svgd_workspace_layout(N, d);
+    if (!workspace || ws_bytes < L.total)
+        return fail(ctx, STAMP_ENOSPACE, "svgd workspace %zu < %zu bytes", ws_bytes, L.total);
+    const UpdateArgs u{theta, m, v, t, nullptr, lr, beta1, beta2, eps, use_adam ? 1 : 0};
+    hipError_t e = launch_svgd_direction(N, d, theta, grad_logp, phi, workspace, L, 0, nullptr, (hipStream_t)stream,
+                                         weights, &u);
+    return e == hipSuccess ? STAMP_OK : hip_fail(ctx, e, "svgd_update");
+}
+
 int32_t stamp_svgd_step_weighted(stamp_ctx* ctx, int32_t N, int32_t d, const float* theta, const float* grad_logp,
                                  const float* weights, float bandwidth, float* phi, float* h_out, void* workspace,
                                  size_t ws_bytes, void* stream) {
@@ -856,6 +877,8 @@ static int32_t solve_impl(stamp_ctx* ctx, int32_t n_problems, const stamp_scene*
         return hipEventRecord(ctx->ev_join, ctx->side);
     };
     auto join = [&]() -> hipError_t { return hipStreamWaitEvent(st, ctx->ev_join, 0); };
+    const UpdateArgs upd{theta, adam_m, adam_v, cfg->t0, d_ctr, cfg->lr, cfg->beta1, cfg->beta2, cfg->adam_eps,
+                         cfg->use_adam};
     auto direction_stage = [&](const float* wts) -> hipError_t {
         if (skern.empty()) return launch_svgd_direction_batched(B, d_desc, theta, d_grad, d_phi, d_svgd, status, st, wts);
         for (int p = 0; p < n_problems; ++p) {
@@ -866,6 +889,16 @@ static int32_t solve_impl(stamp_ctx* ctx, int32_t n_problems, const stamp_scene*
             if (r != hipSuccess) return r;
         }
         return hipSuccess;
+    };
+    // the direction and the update in one pass (the FP32 form's reduce
+    // applies the update), or the direction then the update
+    auto direction_update_stage = [&](const float* wts) -> hipError_t {
+        if (skern.empty())
+            return launch_svgd_direction_batched(B, d_desc, theta, d_grad, nullptr, d_svgd, status, st, wts, &upd);
+        hipError_t r = direction_stage(wts);
+        if (r != hipSuccess) return r;
+        return launch_update(P.n_theta, theta, d_phi, adam_m, adam_v, cfg->t0, d_ctr, cfg->lr, cfg->beta1,
+                             cfg->beta2, cfg->adam_eps, cfg->use_adam, st);
     };
     auto iteration = [&]() -> hipError_t {
         hipError_t r;
@@ -890,10 +923,7 @@ static int32_t solve_impl(stamp_ctx* ctx, int32_t n_problems, const stamp_scene*
                 return r;
         }
         if ((r = join()) != hipSuccess) return r;
-        if ((r = direction_stage(cfg->dsvgd ? d_wts : nullptr)) != hipSuccess) return r;
-        if ((r = launch_update(P.n_theta, theta, d_phi, adam_m, adam_v, cfg->t0, d_ctr, cfg->lr, cfg->beta1,
-                               cfg->beta2, cfg->adam_eps, cfg->use_adam, st)) != hipSuccess)
-            return r;
+        if ((r = direction_update_stage(cfg->dsvgd ? d_wts : nullptr)) != hipSuccess) return r;
         return launch_incr(d_ctr, st);
     };
     // one SGD refinement iteration: the update takes phi = grad log rho
@@ -929,12 +959,16 @@ static int32_t solve_impl(stamp_ctx* ctx, int32_t n_problems, const stamp_scene*
         for (int p = 0; p < n_problems; ++p)
             if ((r = sur_infer(p, nullptr, d_grad, -1.0f)) != hipSuccess) return r;
         if ((r = join()) != hipSuccess) return r;
-        r = sur->phi_bf16 ? launch_svgd16_direction_batched(B, d_desc, theta, d_grad, d_phi, d_svgd, status, st)
-                          : direction_stage(nullptr);
-        if (r != hipSuccess) return r;
-        if ((r = launch_update(P.n_theta, theta, d_phi, adam_m, adam_v, cfg->t0, d_ctr, cfg->lr, cfg->beta1,
-                               cfg->beta2, cfg->adam_eps, cfg->use_adam, st)) != hipSuccess)
+        if (sur->phi_bf16) {
+            if ((r = launch_svgd16_direction_batched(B, d_desc, theta, d_grad, d_phi, d_svgd, status, st)) !=
+                hipSuccess)
+                return r;
+            if ((r = launch_update(P.n_theta, theta, d_phi, adam_m, adam_v, cfg->t0, d_ctr, cfg->lr, cfg->beta1,
+                                   cfg->beta2, cfg->adam_eps, cfg->use_adam, st)) != hipSuccess)
+                return r;
+        } else if ((r = direction_update_stage(nullptr)) != hipSuccess) {
             return r;
+        }
         return launch_incr(d_ctr, st);
     };
     char gkey[512];

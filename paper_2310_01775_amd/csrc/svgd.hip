@@ -113,33 +113,11 @@ __global__ __launch_bounds__(256) void k_dsvgd_weights_batched(const ProblemDesc
     dsvgd_weights_body(D.N, c_rel + D.cost_off, c_disc + D.cost_off, w + D.cost_off);
 }
 
-__global__ __launch_bounds__(256) void k_update(int64_t n, float* __restrict__ theta, const float* __restrict__ phi,
-                                                float* __restrict__ m, float* __restrict__ v, int t0,
-                                                const int* __restrict__ t_dev, float lr, float b1, float b2,
-                                                float eps, int use_adam) {
-    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (!use_adam) {
-        if (e < n) theta[e] = theta[e] + lr * phi[e];
-        return;
-    }
-    // bias-correction denominators, once per workgroup (the same expressions
-    // every thread would evaluate)
+__global__ __launch_bounds__(256) void k_update(int64_t n, const float* __restrict__ phi, UpdateArgs u) {
     __shared__ float den[2];
-    if (threadIdx.x == 0) {
-        const int t = t_dev ? t0 + *t_dev + 1 : t0;
-        den[0] = 1.0f - powf(b1, (float)t);
-        den[1] = 1.0f - powf(b2, (float)t);
-    }
-    __syncthreads();
-    if (e >= n) return;
-    const float gr = -phi[e];
-    const float mm = b1 * m[e] + (1.0f - b1) * gr;
-    const float vv = b2 * v[e] + (1.0f - b2) * gr * gr;
-    m[e] = mm;
-    v[e] = vv;
-    const float mhat = mm / den[0];
-    const float vhat = vv / den[1];
-    theta[e] = theta[e] - lr * mhat / (sqrtf(vhat) + eps);
+    update_denominators(u, den);
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e < n) update_elem(u, den, e, phi[e]);
 }
 
 __global__ void k_modes(int N, int H, const float* __restrict__ theta, int32_t* __restrict__ modes) {
@@ -315,8 +293,8 @@ hipError_t launch_dsvgd_weights_batched(int n_problems, const ProblemDesc* descs
 
 hipError_t launch_update(int64_t n, float* theta, const float* phi, float* m, float* v, int t0, const int* t_dev,
                          float lr, float b1, float b2, float eps, int use_adam, hipStream_t st) {
-    hipLaunchKernelGGL(k_update, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, theta, phi, m, v, t0,
-                       t_dev, lr, b1, b2, eps, use_adam);
+    const UpdateArgs u{theta, m, v, t0, t_dev, lr, b1, b2, eps, use_adam};
+    hipLaunchKernelGGL(k_update, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, phi, u);
     return hipGetLastError();
 }
 

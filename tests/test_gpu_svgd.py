@@ -170,3 +170,31 @@ def test_two_half_step_on_two_streams_equals_the_step(ctx, N, d):
         got = ctx.svgd_direction(th, g, ws)
     torch.cuda.synchronize()
     assert torch.equal(got, ref) and torch.equal(h1, h2)
+
+
+@pytest.mark.parametrize("N,d,use_adam,weighted", [(1, 6, True, False), (300, 18, True, False),
+                                                   (1000, 30, False, False), (777, 48, True, True)])
+def test_fused_direction_update_equals_direction_then_update(ctx, N, d, use_adam, weighted):
+    """stamp_svgd_update = stamp_svgd_direction + stamp_adam_step, bit for bit."""
+    import paper_2310_01775_amd as S
+    print("case", N, d, use_adam, weighted, flush=True)
+    rng = np.random.default_rng(N * 7 + d)
+    th = S.soa(W.f32(rng.standard_normal((N, d))))
+    g = S.soa(W.f32(rng.standard_normal((N, d)) * 3.0))
+    m0 = S.soa(W.f32(rng.standard_normal((N, d)) * 0.1))
+    v0 = S.soa(W.f32(rng.uniform(0.0, 0.2, (N, d))))
+    w = None
+    if weighted:
+        w = rng.uniform(0.0, 2.0, N)
+        w = torch.tensor(w * N / w.sum(), dtype=torch.float32, device="cuda")
+    ws = ctx.svgd_bandwidth(th)
+    a, ma, va = th.clone(), m0.clone(), v0.clone()
+    phi_a = ctx.svgd_direction(a, g, ws, weights=w)
+    ctx.adam_step(a, phi_a, ma, va, 7, lr=1e-2, use_adam=use_adam)
+    b, mb, vb = th.clone(), m0.clone(), v0.clone()
+    phi_b = torch.empty_like(th)
+    ctx.svgd_update(b, g, ws, mb, vb, 7, lr=1e-2, use_adam=use_adam, weights=w, phi=phi_b)
+    torch.cuda.synchronize()
+    assert torch.equal(phi_a, phi_b) and torch.equal(a, b)
+    if use_adam:
+        assert torch.equal(ma, mb) and torch.equal(va, vb)
