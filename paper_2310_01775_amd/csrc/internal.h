@@ -90,10 +90,17 @@ hipError_t launch_svgd16(int N, int d, const float* theta, const float* grad, fl
                          float* h_out, void* ws, const SvgdLayout& L, uint32_t* status, hipStream_t st);
 hipError_t launch_svgd16_batched(const BatchPlan& P, const ProblemDesc* descs, const float* theta, const float* grad,
                                  float* phi, char* ws, uint32_t* status, hipStream_t st);
-// its second half (after launch_median_batched with exact = 0)
+// its theta-only operands (particle mean, centred BF16 rows, norms, V's
+// [x~ | 1] columns), built with the sampled median, and its second half
+// (V's g columns, the contraction, the reduce; upd as for the FP32 form)
+hipError_t launch_operands16(int N, int d, const float* theta, void* ws, const SvgdLayout& L, hipStream_t st);
+hipError_t launch_operands16_batched(const BatchPlan& P, const ProblemDesc* descs, const float* theta, char* ws,
+                                     hipStream_t st);
+hipError_t launch_svgd16_direction(int N, int d, const float* grad, float* phi, void* ws, const SvgdLayout& L,
+                                   uint32_t* status, hipStream_t st, const UpdateArgs* upd = nullptr);
 hipError_t launch_svgd16_direction_batched(const BatchPlan& P, const ProblemDesc* descs, const float* theta,
                                            const float* grad, float* phi, char* ws, uint32_t* status,
-                                           hipStream_t st);
+                                           hipStream_t st, const UpdateArgs* upd = nullptr);
 
 // Adam (use_adam=1) or plain step, n elements.  t_dev: if non-null, the step
 // count is read as t0 + *t_dev + 1 on the device (graph replay); else t0 is t.

@@ -78,9 +78,11 @@ __device__ __forceinline__ int64_t vpos(int i, int c, int vc) {
     return ((int64_t)q * vc + c) * 32 + 8 * kq + s;
 }
 
-// ---- operands: x~ rows, their norms, V (one thread per padded row) -------------
-__device__ void pack16_row(int N, int d, int npad, int kd, int vc, int i, const float* __restrict__ theta,
-                           const float* __restrict__ g, const View16& w) {
+// ---- operands (one thread per padded row): the theta part -- x~ rows, their
+// norms, and V's columns [x~ | 1 | 0] -- depends on theta only and is built
+// with the median; the g columns of V come after the gradient
+__device__ void pack16_theta_row(int N, int d, int kd, int vc, int i, const float* __restrict__ theta,
+                                 const View16& w) {
     float nrm = 0.0f;
     for (int l = 0; l < kd; ++l) {
         float x = 0.0f;
@@ -89,13 +91,14 @@ __device__ void pack16_row(int N, int d, int npad, int kd, int vc, int i, const 
         const float xr = (float)xb;
         nrm = fmaf(xr, xr, nrm);
         w.xb[(int64_t)i * kd + l] = xb;
-        if (l < d) {
-            w.vt[vpos(i, d + l, vc)] = xb;
-            w.vt[vpos(i, l, vc)] = (__bf16)(i < N ? g[(int64_t)l * N + i] : 0.0f);
-        }
+        if (l < d) w.vt[vpos(i, d + l, vc)] = xb;
     }
     for (int c = 2 * d; c < vc; ++c) w.vt[vpos(i, c, vc)] = (__bf16)(c == 2 * d && i < N ? 1.0f : 0.0f);
     w.nrm[i] = nrm;
+}
+
+__device__ void pack16_g_row(int N, int d, int vc, int i, const float* __restrict__ g, const View16& w) {
+    for (int l = 0; l < d; ++l) w.vt[vpos(i, l, vc)] = (__bf16)(i < N ? g[(int64_t)l * N + i] : 0.0f);
 }
 
 // ---- contraction: partial sums of K [g | x~ | 1] over columns [j0, j1) --------
@@ -221,16 +224,20 @@ __device__ __forceinline__ float split_sum(const float* __restrict__ p, int64_t 
     return s;
 }
 
-__device__ void reduce16_elem(int N, int d, int npad, int kd, int vc, int splits, int l, int i, float* __restrict__ phi,
-                              const View16& w, uint32_t* status) {
+// phi (stored when phi is not null) and, with upd, the update of Algorithm 1
+// on element uoff + l N + i
+__device__ void reduce16_elem(int N, int d, int npad, int kd, int vc, int splits, int l, int i, float* phi,
+                              const View16& w, uint32_t* status, const UpdateArgs* upd, const float* den,
+                              int64_t uoff) {
     const int64_t sstride = (int64_t)vc * npad;
     const float sg = split_sum(w.p16 + (int64_t)l * npad + i, sstride, splits);
     const float sx = split_sum(w.p16 + (int64_t)(d + l) * npad + i, sstride, splits);
     const float s1 = split_sum(w.p16 + (int64_t)(2 * d) * npad + i, sstride, splits);
     const float xi = (float)w.xb[(int64_t)i * kd + l];
     const float r = (sg + (2.0f / w.sel->h) * (xi * s1 - sx)) / (float)N;
-    phi[(int64_t)l * N + i] = r;
+    if (phi) phi[(int64_t)l * N + i] = r;
     if (status && !isfinite(r)) atomicOr(status, STAMP_STATUS_NONFINITE_PHI);
+    if (upd) update_elem(*upd, den, uoff + (int64_t)l * N + i, r);
 }
 
 // ---- single-problem kernels -----------------------------------------------------
@@ -244,9 +251,12 @@ __global__ __launch_bounds__(256) void k_center(One16 a, const float* theta, cha
     center_body(a.N, blockIdx.x, theta, view16(a.L, ws).ctr);
 }
 
-__global__ __launch_bounds__(256) void k_pack16(One16 a, const float* theta, const float* g, char* ws) {
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    pack16_row(a.N, a.d, a.L.npad, a.L.kd, a.L.vc, i, theta, g, view16(a.L, ws));
+__global__ __launch_bounds__(256) void k_pack16_theta(One16 a, const float* theta, char* ws) {
+    pack16_theta_row(a.N, a.d, a.L.kd, a.L.vc, blockIdx.x * 256 + threadIdx.x, theta, view16(a.L, ws));
+}
+
+__global__ __launch_bounds__(256) void k_pack16_g(One16 a, const float* g, char* ws) {
+    pack16_g_row(a.N, a.d, a.L.vc, blockIdx.x * 256 + threadIdx.x, g, view16(a.L, ws));
 }
 
 template <int KD, int VC>
@@ -256,15 +266,22 @@ __global__ __launch_bounds__(256) void k_phi16(One16 a, char* ws) {
     phi16_body<KD, VC>(a.L.npad, blockIdx.x * kRows16, j0, j1, split, view16(a.L, ws));
 }
 
-__global__ __launch_bounds__(256) void k_reduce16(One16 a, const float* g, float* phi, char* ws, uint32_t* status) {
+// upd.use_adam < 0: no update
+__global__ __launch_bounds__(256) void k_reduce16(One16 a, const float* g, float* phi, char* ws, uint32_t* status,
+                                                  UpdateArgs upd) {
+    __shared__ float den[2];
+    const bool apply = upd.use_adam >= 0;
+    if (apply) update_denominators(upd, den);
     const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (e >= (int64_t)a.d * a.N) return;
     const int l = (int)(e / a.N), i = (int)(e % a.N);
     if (a.N == 1) {
-        phi[e] = g[e];
+        if (phi) phi[e] = g[e];
+        if (apply) update_elem(upd, den, e, g[e]);
         return;
     }
-    reduce16_elem(a.N, a.d, a.L.npad, a.L.kd, a.L.vc, a.L.splits16, l, i, phi, view16(a.L, ws), status);
+    reduce16_elem(a.N, a.d, a.L.npad, a.L.kd, a.L.vc, a.L.splits16, l, i, phi, view16(a.L, ws), status,
+                  apply ? &upd : nullptr, den, 0);
 }
 
 // ---- batched kernels (work-list entries as in svgd.hip) ---------------------------
@@ -279,14 +296,21 @@ __global__ __launch_bounds__(256) void k_center_batched(const ProblemDesc* __res
 }
 
 // entry = (problem, first row of a 256-row chunk, -, -)
-__global__ __launch_bounds__(256) void k_pack16_batched(const ProblemDesc* __restrict__ descs,
-                                                        const int4* __restrict__ work, const float* theta,
-                                                        const float* grad, char* ws) {
+__global__ __launch_bounds__(256) void k_pack16_theta_batched(const ProblemDesc* __restrict__ descs,
+                                                              const int4* __restrict__ work, const float* theta,
+                                                              char* ws) {
     const int4 e = work[blockIdx.x];
     const ProblemDesc& D = descs[e.x];
     if (D.N < 2) return;
-    pack16_row(D.N, D.d, D.sv.npad, D.sv.kd, D.sv.vc, e.y + threadIdx.x, theta + D.theta_off, grad + D.theta_off,
-               view16(D.sv, base_of(D, ws)));
+    pack16_theta_row(D.N, D.d, D.sv.kd, D.sv.vc, e.y + threadIdx.x, theta + D.theta_off, view16(D.sv, base_of(D, ws)));
+}
+
+__global__ __launch_bounds__(256) void k_pack16_g_batched(const ProblemDesc* __restrict__ descs,
+                                                          const int4* __restrict__ work, const float* grad, char* ws) {
+    const int4 e = work[blockIdx.x];
+    const ProblemDesc& D = descs[e.x];
+    if (D.N < 2) return;
+    pack16_g_row(D.N, D.d, D.sv.vc, e.y + threadIdx.x, grad + D.theta_off, view16(D.sv, base_of(D, ws)));
 }
 
 // entry = (problem, row block, split, -)
@@ -302,58 +326,93 @@ __global__ __launch_bounds__(256) void k_phi16_batched(const ProblemDesc* __rest
 // entry = (problem, first element, end element, -) of the problem's d*N block
 __global__ __launch_bounds__(256) void k_reduce16_batched(const ProblemDesc* __restrict__ descs,
                                                           const int4* __restrict__ work, const float* grad, float* phi,
-                                                          char* ws, uint32_t* status) {
+                                                          char* ws, uint32_t* status, UpdateArgs upd) {
+    __shared__ float den[2];
+    const bool apply = upd.use_adam >= 0;
+    if (apply) update_denominators(upd, den);
     const int4 w = work[blockIdx.x];
     const ProblemDesc& D = descs[w.x];
     const int64_t e = w.y + threadIdx.x;
     if (e >= w.z) return;
     if (D.N == 1) {
-        phi[D.theta_off + e] = grad[D.theta_off + e];
+        if (phi) phi[D.theta_off + e] = grad[D.theta_off + e];
+        if (apply) update_elem(upd, den, D.theta_off + e, grad[D.theta_off + e]);
         return;
     }
     reduce16_elem(D.N, D.d, D.sv.npad, D.sv.kd, D.sv.vc, D.sv.splits16, (int)(e / D.N), (int)(e % D.N),
-                  phi + D.theta_off, view16(D.sv, base_of(D, ws)), status);
+                  phi ? phi + D.theta_off : nullptr, view16(D.sv, base_of(D, ws)), status, apply ? &upd : nullptr,
+                  den, D.theta_off);
 }
 
 }  // namespace
 
-hipError_t launch_svgd16(int N, int d, const float* theta, const float* grad, float bandwidth, float* phi,
-                         float* h_out, void* ws, const SvgdLayout& L, uint32_t* status, hipStream_t st) {
-    One16 a{N, d, L, bandwidth > 0.0f ? bandwidth : 0.0f};
+hipError_t launch_operands16(int N, int d, const float* theta, void* ws, const SvgdLayout& L, hipStream_t st) {
+    if (N < 2) return hipSuccess;
+    One16 a{N, d, L, 0.0f};
     char* b = static_cast<char*>(ws);
-    hipError_t e = launch_median(N, d, theta, bandwidth, 0, ws, L, h_out, st);
-    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_center, dim3(d), dim3(256), 0, st, a, theta, b);
+    hipLaunchKernelGGL(k_pack16_theta, dim3(L.npad / 256), dim3(256), 0, st, a, theta, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_operands16_batched(const BatchPlan& P, const ProblemDesc* descs, const float* theta, char* ws,
+                                     hipStream_t st) {
+    if (P.n_ctr) hipLaunchKernelGGL(k_center_batched, dim3(P.n_ctr), dim3(256), 0, st, descs, P.ctr_work, theta, ws);
+    if (P.n_row16)
+        hipLaunchKernelGGL(k_pack16_theta_batched, dim3(P.n_row16), dim3(256), 0, st, descs, P.row16_work, theta, ws);
+    return hipGetLastError();
+}
+
+hipError_t launch_svgd16_direction(int N, int d, const float* grad, float* phi, void* ws, const SvgdLayout& L,
+                                   uint32_t* status, hipStream_t st, const UpdateArgs* upd) {
+    One16 a{N, d, L, 0.0f};
+    char* b = static_cast<char*>(ws);
     if (N >= 2) {
-        hipLaunchKernelGGL(k_center, dim3(d), dim3(256), 0, st, a, theta, b);
-        hipLaunchKernelGGL(k_pack16, dim3(L.npad / 256), dim3(256), 0, st, a, theta, grad, b);
+        hipLaunchKernelGGL(k_pack16_g, dim3(L.npad / 256), dim3(256), 0, st, a, grad, b);
         const dim3 grid(L.npad / kRows16, L.splits16);
         if (L.kd == 32) hipLaunchKernelGGL((k_phi16<32, 64>), grid, dim3(256), 0, st, a, b);
         else hipLaunchKernelGGL((k_phi16<64, 128>), grid, dim3(256), 0, st, a, b);
     }
+    UpdateArgs u{};
+    u.use_adam = -1;
+    if (upd) u = *upd;
     const int64_t n = (int64_t)d * N;
-    hipLaunchKernelGGL(k_reduce16, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a, grad, phi, b, status);
+    hipLaunchKernelGGL(k_reduce16, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a, grad, phi, b, status, u);
     return hipGetLastError();
+}
+
+hipError_t launch_svgd16(int N, int d, const float* theta, const float* grad, float bandwidth, float* phi,
+                         float* h_out, void* ws, const SvgdLayout& L, uint32_t* status, hipStream_t st) {
+    hipError_t e = launch_median(N, d, theta, bandwidth, 0, ws, L, h_out, st);
+    if (e != hipSuccess) return e;
+    if ((e = launch_operands16(N, d, theta, ws, L, st)) != hipSuccess) return e;
+    return launch_svgd16_direction(N, d, grad, phi, ws, L, status, st, nullptr);
 }
 
 hipError_t launch_svgd16_batched(const BatchPlan& P, const ProblemDesc* descs, const float* theta, const float* grad,
                                  float* phi, char* ws, uint32_t* status, hipStream_t st) {
     hipError_t e = launch_median_batched(P, descs, theta, 0, ws, st);
     if (e != hipSuccess) return e;
-    return launch_svgd16_direction_batched(P, descs, theta, grad, phi, ws, status, st);
+    if ((e = launch_operands16_batched(P, descs, theta, ws, st)) != hipSuccess) return e;
+    return launch_svgd16_direction_batched(P, descs, theta, grad, phi, ws, status, st, nullptr);
 }
 
 hipError_t launch_svgd16_direction_batched(const BatchPlan& P, const ProblemDesc* descs, const float* theta,
                                            const float* grad, float* phi, char* ws, uint32_t* status,
-                                           hipStream_t st) {
-    if (P.n_ctr) hipLaunchKernelGGL(k_center_batched, dim3(P.n_ctr), dim3(256), 0, st, descs, P.ctr_work, theta, ws);
+                                           hipStream_t st, const UpdateArgs* upd) {
+    (void)theta;
     if (P.n_row16)
-        hipLaunchKernelGGL(k_pack16_batched, dim3(P.n_row16), dim3(256), 0, st, descs, P.row16_work, theta, grad, ws);
+        hipLaunchKernelGGL(k_pack16_g_batched, dim3(P.n_row16), dim3(256), 0, st, descs, P.row16_work, grad, ws);
     if (P.n_phi16[0])
         hipLaunchKernelGGL((k_phi16_batched<32, 64>), dim3(P.n_phi16[0]), dim3(256), 0, st, descs, P.phi16_work[0], ws);
     if (P.n_phi16[1])
         hipLaunchKernelGGL((k_phi16_batched<64, 128>), dim3(P.n_phi16[1]), dim3(256), 0, st, descs, P.phi16_work[1],
                            ws);
-    hipLaunchKernelGGL(k_reduce16_batched, dim3(P.n_red), dim3(256), 0, st, descs, P.red_work, grad, phi, ws, status);
+    UpdateArgs u{};
+    u.use_adam = -1;
+    if (upd) u = *upd;
+    hipLaunchKernelGGL(k_reduce16_batched, dim3(P.n_red), dim3(256), 0, st, descs, P.red_work, grad, phi, ws, status,
+                       u);
     return hipGetLastError();
 }
 

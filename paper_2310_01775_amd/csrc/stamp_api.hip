@@ -960,11 +960,8 @@ static int32_t solve_impl(stamp_ctx* ctx, int32_t n_problems, const stamp_scene*
             if ((r = sur_infer(p, nullptr, d_grad, -1.0f)) != hipSuccess) return r;
         if ((r = join()) != hipSuccess) return r;
         if (sur->phi_bf16) {
-            if ((r = launch_svgd16_direction_batched(B, d_desc, theta, d_grad, d_phi, d_svgd, status, st)) !=
+            if ((r = launch_svgd16_direction_batched(B, d_desc, theta, d_grad, nullptr, d_svgd, status, st, &upd)) !=
                 hipSuccess)
-                return r;
-            if ((r = launch_update(P.n_theta, theta, d_phi, adam_m, adam_v, cfg->t0, d_ctr, cfg->lr, cfg->beta1,
-                                   cfg->beta2, cfg->adam_eps, cfg->use_adam, st)) != hipSuccess)
                 return r;
         } else if ((r = direction_update_stage(nullptr)) != hipSuccess) {
             return r;

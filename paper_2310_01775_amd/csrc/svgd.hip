@@ -268,8 +268,9 @@ hipError_t launch_svgd_bandwidth_batched(const BatchPlan& P, const ProblemDesc* 
                                          char* ws, hipStream_t st) {
     hipError_t e = launch_median_batched(P, descs, theta, exact, ws, st);
     if (e != hipSuccess) return e;
-    // the FP32 form's operands (the BF16 form, exact = 0, builds its own)
-    return exact ? launch_operands32_batched(P, descs, theta, ws, st) : hipSuccess;
+    // the theta-only operands of the FP32 form (exact median) or of the BF16
+    // form (sampled median)
+    return exact ? launch_operands32_batched(P, descs, theta, ws, st) : launch_operands16_batched(P, descs, theta, ws, st);
 }
 
 hipError_t launch_phi_reduce(int N, int d, int splits, const float* partial, float* phi, uint32_t* status,
