@@ -90,14 +90,15 @@ hipError_t launch_svgd16(int N, int d, const float* theta, const float* grad, fl
                          float* h_out, void* ws, const SvgdLayout& L, uint32_t* status, hipStream_t st);
 hipError_t launch_svgd16_batched(const BatchPlan& P, const ProblemDesc* descs, const float* theta, const float* grad,
                                  float* phi, char* ws, uint32_t* status, hipStream_t st);
-// its theta-only operands (particle mean, centred BF16 rows, norms, V's
-// [x~ | 1] columns), built with the sampled median, and its second half
-// (V's g columns, the contraction, the reduce; upd as for the FP32 form)
+// its theta-only operands (particle mean, centred BF16 rows, their norms),
+// built with the sampled median, and its second half (V, the contraction,
+// the reduce; upd as for the FP32 form)
 hipError_t launch_operands16(int N, int d, const float* theta, void* ws, const SvgdLayout& L, hipStream_t st);
 hipError_t launch_operands16_batched(const BatchPlan& P, const ProblemDesc* descs, const float* theta, char* ws,
                                      hipStream_t st);
-hipError_t launch_svgd16_direction(int N, int d, const float* grad, float* phi, void* ws, const SvgdLayout& L,
-                                   uint32_t* status, hipStream_t st, const UpdateArgs* upd = nullptr);
+hipError_t launch_svgd16_direction(int N, int d, const float* theta, const float* grad, float* phi, void* ws,
+                                   const SvgdLayout& L, uint32_t* status, hipStream_t st,
+                                   const UpdateArgs* upd = nullptr);
 hipError_t launch_svgd16_direction_batched(const BatchPlan& P, const ProblemDesc* descs, const float* theta,
                                            const float* grad, float* phi, char* ws, uint32_t* status,
                                            hipStream_t st, const UpdateArgs* upd = nullptr);

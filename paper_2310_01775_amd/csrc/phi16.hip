@@ -5,12 +5,13 @@
 //     squared distances of a fixed sample of kMedSample particle pairs (all
 //     N(N-1)/2 pairs when there are at most that many: then m2 is exact;
 //     median.hip, sampled mode);
-//   x~_i = bf16(theta_i - mean theta)   (centring shrinks the Gram cancellation)
+//   x_i = theta_i - mean theta, x~_i = bf16(x_i)   (centring shrinks the Gram cancellation)
 //   D_ij = |x~_i|^2 + |x~_j|^2 - 2 x~_i . x~_j   (Gram on MFMA, FP32 accumulate)
 //   K_ij = exp(-max(D_ij, 0) / h)
-//   [A_G | A_X | A_1]_i = sum_j bf16(K_ij) [g_j | x~_j | 1]   (MFMA, FP32 accumulate)
-//   phi_i = (A_G + (2/h)(x~_i A_1 - A_X)) / N
-// which is Eq. (1) with theta_i - theta_j = x~_i - x~_j.
+//   V_j = bf16[ g_j - (2/h) x_j | 1 | 0 ]
+//   A_i = sum_j bf16(K_ij) V_j                   (MFMA, FP32 accumulate)
+//   phi_i = (A_i[0..d) + (2/h) x_i A_i[d]) / N
+// which is Eq. (1) with theta_i - theta_j = x_i - x_j.
 //
 // Contraction tiling: a workgroup owns 256 rows (4 waves x 4 row tiles of 16)
 // and one column split; per 32 columns a wave issues, per row tile, two Gram
@@ -19,7 +20,8 @@
 // layout (lane holds columns j = 4(l/16)+t of row l%16) is exactly an A
 // operand whose k index is permuted; V is stored chunk by chunk in that same
 // permuted order, so no data moves between the two products and every lane
-// reads its 8 V values with one 16-byte load.
+// reads its 8 V values with one 16-byte load.  V has d + 1 columns rounded up
+// to the 16-column tile: 32 for d < 32, 64 for d < 64, 80 for d = 64.
 #include <math.h>
 
 #include "common.h"
@@ -78,11 +80,9 @@ __device__ __forceinline__ int64_t vpos(int i, int c, int vc) {
     return ((int64_t)q * vc + c) * 32 + 8 * kq + s;
 }
 
-// ---- operands (one thread per padded row): the theta part -- x~ rows, their
-// norms, and V's columns [x~ | 1 | 0] -- depends on theta only and is built
-// with the median; the g columns of V come after the gradient
-__device__ void pack16_theta_row(int N, int d, int kd, int vc, int i, const float* __restrict__ theta,
-                                 const View16& w) {
+// ---- operands (one thread per padded row): the x~ rows and their norms
+// depend on theta only and are built with the median; V needs g and h
+__device__ void pack16_theta_row(int N, int d, int kd, int i, const float* __restrict__ theta, const View16& w) {
     float nrm = 0.0f;
     for (int l = 0; l < kd; ++l) {
         float x = 0.0f;
@@ -91,17 +91,21 @@ __device__ void pack16_theta_row(int N, int d, int kd, int vc, int i, const floa
         const float xr = (float)xb;
         nrm = fmaf(xr, xr, nrm);
         w.xb[(int64_t)i * kd + l] = xb;
-        if (l < d) w.vt[vpos(i, d + l, vc)] = xb;
     }
-    for (int c = 2 * d; c < vc; ++c) w.vt[vpos(i, c, vc)] = (__bf16)(c == 2 * d && i < N ? 1.0f : 0.0f);
     w.nrm[i] = nrm;
 }
 
-__device__ void pack16_g_row(int N, int d, int vc, int i, const float* __restrict__ g, const View16& w) {
-    for (int l = 0; l < d; ++l) w.vt[vpos(i, l, vc)] = (__bf16)(i < N ? g[(int64_t)l * N + i] : 0.0f);
+__device__ void pack16_v_row(int N, int d, int vc, int i, const float* __restrict__ theta,
+                             const float* __restrict__ g, const View16& w) {
+    const float c2 = 2.0f / w.sel->h;
+    for (int c = 0; c < vc; ++c) {
+        float v = 0.0f;
+        if (i < N) v = c < d ? fmaf(-c2, theta[(int64_t)c * N + i] - w.ctr[c], g[(int64_t)c * N + i]) : (c == d ? 1.0f : 0.0f);
+        w.vt[vpos(i, c, vc)] = (__bf16)v;
+    }
 }
 
-// ---- contraction: partial sums of K [g | x~ | 1] over columns [j0, j1) --------
+// ---- contraction: partial sums of K V over columns [j0, j1) ----------------------
 // Operands of one 32-column chunk, as this lane holds them.
 template <int KS, int OT>
 struct Chunk16 {
@@ -210,8 +214,8 @@ __device__ void phi16_body(int npad, int row0, int j0, int j1, int split, const 
 }
 
 // ---- phi from the split sums (fixed split order) ---------------------------
-// One thread per element (l, i); rows l, d+l and 2d of every split are summed
-// with 16 loads in flight.
+// One thread per element (l, i); rows l and d of every split are summed with
+// 16 loads in flight.
 __device__ __forceinline__ float split_sum(const float* __restrict__ p, int64_t sstride, int splits) {
     float s = 0.0f;
     for (int q0 = 0; q0 < splits; q0 += 16) {
@@ -226,15 +230,14 @@ __device__ __forceinline__ float split_sum(const float* __restrict__ p, int64_t 
 
 // phi (stored when phi is not null) and, with upd, the update of Algorithm 1
 // on element uoff + l N + i
-__device__ void reduce16_elem(int N, int d, int npad, int kd, int vc, int splits, int l, int i, float* phi,
+__device__ void reduce16_elem(int N, int d, int npad, int vc, int splits, int l, int i, const float* theta, float* phi,
                               const View16& w, uint32_t* status, const UpdateArgs* upd, const float* den,
                               int64_t uoff) {
     const int64_t sstride = (int64_t)vc * npad;
-    const float sg = split_sum(w.p16 + (int64_t)l * npad + i, sstride, splits);
-    const float sx = split_sum(w.p16 + (int64_t)(d + l) * npad + i, sstride, splits);
-    const float s1 = split_sum(w.p16 + (int64_t)(2 * d) * npad + i, sstride, splits);
-    const float xi = (float)w.xb[(int64_t)i * kd + l];
-    const float r = (sg + (2.0f / w.sel->h) * (xi * s1 - sx)) / (float)N;
+    const float sv = split_sum(w.p16 + (int64_t)l * npad + i, sstride, splits);
+    const float s1 = split_sum(w.p16 + (int64_t)d * npad + i, sstride, splits);
+    const float x = theta[(int64_t)l * N + i] - w.ctr[l];
+    const float r = fmaf(2.0f / w.sel->h * x, s1, sv) / (float)N;
     if (phi) phi[(int64_t)l * N + i] = r;
     if (status && !isfinite(r)) atomicOr(status, STAMP_STATUS_NONFINITE_PHI);
     if (upd) update_elem(*upd, den, uoff + (int64_t)l * N + i, r);
@@ -252,11 +255,11 @@ __global__ __launch_bounds__(256) void k_center(One16 a, const float* theta, cha
 }
 
 __global__ __launch_bounds__(256) void k_pack16_theta(One16 a, const float* theta, char* ws) {
-    pack16_theta_row(a.N, a.d, a.L.kd, a.L.vc, blockIdx.x * 256 + threadIdx.x, theta, view16(a.L, ws));
+    pack16_theta_row(a.N, a.d, a.L.kd, blockIdx.x * 256 + threadIdx.x, theta, view16(a.L, ws));
 }
 
-__global__ __launch_bounds__(256) void k_pack16_g(One16 a, const float* g, char* ws) {
-    pack16_g_row(a.N, a.d, a.L.vc, blockIdx.x * 256 + threadIdx.x, g, view16(a.L, ws));
+__global__ __launch_bounds__(256) void k_pack16_v(One16 a, const float* theta, const float* g, char* ws) {
+    pack16_v_row(a.N, a.d, a.L.vc, blockIdx.x * 256 + threadIdx.x, theta, g, view16(a.L, ws));
 }
 
 template <int KD, int VC>
@@ -267,8 +270,8 @@ __global__ __launch_bounds__(256) void k_phi16(One16 a, char* ws) {
 }
 
 // upd.use_adam < 0: no update
-__global__ __launch_bounds__(256) void k_reduce16(One16 a, const float* g, float* phi, char* ws, uint32_t* status,
-                                                  UpdateArgs upd) {
+__global__ __launch_bounds__(256) void k_reduce16(One16 a, const float* theta, const float* g, float* phi, char* ws,
+                                                  uint32_t* status, UpdateArgs upd) {
     __shared__ float den[2];
     const bool apply = upd.use_adam >= 0;
     if (apply) update_denominators(upd, den);
@@ -280,7 +283,7 @@ __global__ __launch_bounds__(256) void k_reduce16(One16 a, const float* g, float
         if (apply) update_elem(upd, den, e, g[e]);
         return;
     }
-    reduce16_elem(a.N, a.d, a.L.npad, a.L.kd, a.L.vc, a.L.splits16, l, i, phi, view16(a.L, ws), status,
+    reduce16_elem(a.N, a.d, a.L.npad, a.L.vc, a.L.splits16, l, i, theta, phi, view16(a.L, ws), status,
                   apply ? &upd : nullptr, den, 0);
 }
 
@@ -302,15 +305,17 @@ __global__ __launch_bounds__(256) void k_pack16_theta_batched(const ProblemDesc*
     const int4 e = work[blockIdx.x];
     const ProblemDesc& D = descs[e.x];
     if (D.N < 2) return;
-    pack16_theta_row(D.N, D.d, D.sv.kd, D.sv.vc, e.y + threadIdx.x, theta + D.theta_off, view16(D.sv, base_of(D, ws)));
+    pack16_theta_row(D.N, D.d, D.sv.kd, e.y + threadIdx.x, theta + D.theta_off, view16(D.sv, base_of(D, ws)));
 }
 
-__global__ __launch_bounds__(256) void k_pack16_g_batched(const ProblemDesc* __restrict__ descs,
-                                                          const int4* __restrict__ work, const float* grad, char* ws) {
+__global__ __launch_bounds__(256) void k_pack16_v_batched(const ProblemDesc* __restrict__ descs,
+                                                          const int4* __restrict__ work, const float* theta,
+                                                          const float* grad, char* ws) {
     const int4 e = work[blockIdx.x];
     const ProblemDesc& D = descs[e.x];
     if (D.N < 2) return;
-    pack16_g_row(D.N, D.d, D.sv.vc, e.y + threadIdx.x, grad + D.theta_off, view16(D.sv, base_of(D, ws)));
+    pack16_v_row(D.N, D.d, D.sv.vc, e.y + threadIdx.x, theta + D.theta_off, grad + D.theta_off,
+                 view16(D.sv, base_of(D, ws)));
 }
 
 // entry = (problem, row block, split, -)
@@ -325,8 +330,9 @@ __global__ __launch_bounds__(256) void k_phi16_batched(const ProblemDesc* __rest
 
 // entry = (problem, first element, end element, -) of the problem's d*N block
 __global__ __launch_bounds__(256) void k_reduce16_batched(const ProblemDesc* __restrict__ descs,
-                                                          const int4* __restrict__ work, const float* grad, float* phi,
-                                                          char* ws, uint32_t* status, UpdateArgs upd) {
+                                                          const int4* __restrict__ work, const float* theta,
+                                                          const float* grad, float* phi, char* ws, uint32_t* status,
+                                                          UpdateArgs upd) {
     __shared__ float den[2];
     const bool apply = upd.use_adam >= 0;
     if (apply) update_denominators(upd, den);
@@ -339,7 +345,7 @@ __global__ __launch_bounds__(256) void k_reduce16_batched(const ProblemDesc* __r
         if (apply) update_elem(upd, den, D.theta_off + e, grad[D.theta_off + e]);
         return;
     }
-    reduce16_elem(D.N, D.d, D.sv.npad, D.sv.kd, D.sv.vc, D.sv.splits16, (int)(e / D.N), (int)(e % D.N),
+    reduce16_elem(D.N, D.d, D.sv.npad, D.sv.vc, D.sv.splits16, (int)(e / D.N), (int)(e % D.N), theta + D.theta_off,
                   phi ? phi + D.theta_off : nullptr, view16(D.sv, base_of(D, ws)), status, apply ? &upd : nullptr,
                   den, D.theta_off);
 }
@@ -363,21 +369,23 @@ hipError_t launch_operands16_batched(const BatchPlan& P, const ProblemDesc* desc
     return hipGetLastError();
 }
 
-hipError_t launch_svgd16_direction(int N, int d, const float* grad, float* phi, void* ws, const SvgdLayout& L,
-                                   uint32_t* status, hipStream_t st, const UpdateArgs* upd) {
+hipError_t launch_svgd16_direction(int N, int d, const float* theta, const float* grad, float* phi, void* ws,
+                                   const SvgdLayout& L, uint32_t* status, hipStream_t st, const UpdateArgs* upd) {
     One16 a{N, d, L, 0.0f};
     char* b = static_cast<char*>(ws);
     if (N >= 2) {
-        hipLaunchKernelGGL(k_pack16_g, dim3(L.npad / 256), dim3(256), 0, st, a, grad, b);
+        hipLaunchKernelGGL(k_pack16_v, dim3(L.npad / 256), dim3(256), 0, st, a, theta, grad, b);
         const dim3 grid(L.npad / kRows16, L.splits16);
-        if (L.kd == 32) hipLaunchKernelGGL((k_phi16<32, 64>), grid, dim3(256), 0, st, a, b);
-        else hipLaunchKernelGGL((k_phi16<64, 128>), grid, dim3(256), 0, st, a, b);
+        if (L.kd == 32) hipLaunchKernelGGL((k_phi16<32, 32>), grid, dim3(256), 0, st, a, b);
+        else if (L.vc == 64) hipLaunchKernelGGL((k_phi16<64, 64>), grid, dim3(256), 0, st, a, b);
+        else hipLaunchKernelGGL((k_phi16<64, 80>), grid, dim3(256), 0, st, a, b);
     }
     UpdateArgs u{};
     u.use_adam = -1;
     if (upd) u = *upd;
     const int64_t n = (int64_t)d * N;
-    hipLaunchKernelGGL(k_reduce16, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a, grad, phi, b, status, u);
+    hipLaunchKernelGGL(k_reduce16, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a, theta, grad, phi, b, status,
+                       u);
     return hipGetLastError();
 }
 
@@ -386,7 +394,7 @@ hipError_t launch_svgd16(int N, int d, const float* theta, const float* grad, fl
     hipError_t e = launch_median(N, d, theta, bandwidth, 0, ws, L, h_out, st);
     if (e != hipSuccess) return e;
     if ((e = launch_operands16(N, d, theta, ws, L, st)) != hipSuccess) return e;
-    return launch_svgd16_direction(N, d, grad, phi, ws, L, status, st, nullptr);
+    return launch_svgd16_direction(N, d, theta, grad, phi, ws, L, status, st, nullptr);
 }
 
 hipError_t launch_svgd16_batched(const BatchPlan& P, const ProblemDesc* descs, const float* theta, const float* grad,
@@ -400,19 +408,19 @@ hipError_t launch_svgd16_batched(const BatchPlan& P, const ProblemDesc* descs, c
 hipError_t launch_svgd16_direction_batched(const BatchPlan& P, const ProblemDesc* descs, const float* theta,
                                            const float* grad, float* phi, char* ws, uint32_t* status,
                                            hipStream_t st, const UpdateArgs* upd) {
-    (void)theta;
     if (P.n_row16)
-        hipLaunchKernelGGL(k_pack16_g_batched, dim3(P.n_row16), dim3(256), 0, st, descs, P.row16_work, grad, ws);
+        hipLaunchKernelGGL(k_pack16_v_batched, dim3(P.n_row16), dim3(256), 0, st, descs, P.row16_work, theta, grad, ws);
+    // a solve's problems have d = 6H <= 48: V takes the padded dimension's width
     if (P.n_phi16[0])
-        hipLaunchKernelGGL((k_phi16_batched<32, 64>), dim3(P.n_phi16[0]), dim3(256), 0, st, descs, P.phi16_work[0], ws);
+        hipLaunchKernelGGL((k_phi16_batched<32, 32>), dim3(P.n_phi16[0]), dim3(256), 0, st, descs, P.phi16_work[0], ws);
     if (P.n_phi16[1])
-        hipLaunchKernelGGL((k_phi16_batched<64, 128>), dim3(P.n_phi16[1]), dim3(256), 0, st, descs, P.phi16_work[1],
+        hipLaunchKernelGGL((k_phi16_batched<64, 64>), dim3(P.n_phi16[1]), dim3(256), 0, st, descs, P.phi16_work[1],
                            ws);
     UpdateArgs u{};
     u.use_adam = -1;
     if (upd) u = *upd;
-    hipLaunchKernelGGL(k_reduce16_batched, dim3(P.n_red), dim3(256), 0, st, descs, P.red_work, grad, phi, ws, status,
-                       u);
+    hipLaunchKernelGGL(k_reduce16_batched, dim3(P.n_red), dim3(256), 0, st, descs, P.red_work, theta, grad, phi, ws,
+                       status, u);
     return hipGetLastError();
 }
 

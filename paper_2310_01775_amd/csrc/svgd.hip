@@ -210,8 +210,8 @@ SvgdLayout svgd_workspace_layout(int N, int d) {
     L.v32_off = off;
     off = align256(off + (size_t)L.npad * 16 * L.ot32 * 4);
     // BF16 matrix-core form
-    L.kd = d <= 32 ? 32 : 64;
-    L.vc = 2 * L.kd;
+    L.kd = d < 32 ? 32 : 64;
+    L.vc = d < 32 ? 32 : d < 64 ? 64 : 80;  // V = [g - (2/h) x | 1 | 0]: d + 1 columns, padded
     {
         const int rowblocks = L.npad / kRows16;
         int s16 = (1024 + rowblocks - 1) / rowblocks;
