@@ -227,8 +227,9 @@ int32_t stamp_svgd_update(stamp_ctx* ctx, int32_t N, int32_t d, float* theta, co
  *   - the particles are centred on their mean and rounded to BF16; distances
  *     come from the Gram form |x~_i|^2 + |x~_j|^2 - 2 x~_i.x~_j (MFMA, FP32
  *     accumulation), clamped at 0;
- *   - K_ij is rounded to BF16 and K [g | x~ | 1] is accumulated on MFMA in FP32
- *     with g rounded to BF16.
+ *   - K_ij is rounded to BF16 and K V, V_j = [g_j - (2/h) x_j | 1] rounded to
+ *     BF16 (x_j the centred FP32 particle), is accumulated on MFMA in FP32;
+ *     phi_i = (K V)_i[0..d) + (2/h) x_i (K V)_i[d], over N.
  * Same arguments, layouts and workspace (stamp_svgd_workspace_bytes). */
 int32_t stamp_svgd_step_bf16(stamp_ctx* ctx, int32_t N, int32_t d, const float* theta,
                              const float* grad_logp, float bandwidth, float* phi, float* h_out,
