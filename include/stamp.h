@@ -189,7 +189,10 @@ int32_t stamp_rollout_adj(stamp_ctx* ctx, const stamp_scene* scene, const stamp_
  *   phi_i = (1/N) sum_j K_ij [ grad_logp_j + (2/h)(theta_i - theta_j) ].
  * bandwidth > 0 fixes h; otherwise h = max(m2 / ln N, 1e-12) with m2 the exact
  * lower median (the ceil(P/2)-th smallest) of the P = N(N-1)/2 squared distances
- * over i < j (median heuristic, Appendix D-B).  N = 1 gives phi = grad_logp.
+ * over i < j (median heuristic, Appendix D-B), as FP32 computes them: by direct
+ * differences when P <= 2^20, in the Gram form |x_i|^2 + |x_j|^2 - 2 x_i.x_j of
+ * the centred particles (matrix cores, clamped at 0) above.  The contraction
+ * takes distances in that Gram form throughout.  N = 1 gives phi = grad_logp.
  *   theta, grad_logp, phi: [d][N]; h_out: one device float (may be NULL).
  * Errors: STAMP_EINVAL for null pointers, N < 1, d < 1; STAMP_ENOSPACE. */
 int32_t stamp_svgd_step(stamp_ctx* ctx, int32_t N, int32_t d, const float* theta,

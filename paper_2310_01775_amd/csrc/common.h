@@ -154,11 +154,17 @@ __host__ __device__ inline int phi32_ot(int d) { return (d + 16) / 16; }
 // shape (padded dimension, rows) as a bit index 0..5.
 __host__ __device__ inline int med_dp(int d) { return d <= 16 ? 16 : d <= 32 ? 32 : 64; }
 __host__ __device__ inline int med_class(int dp, int rows) { return (dp == 16 ? 0 : dp == 32 ? 2 : 4) + (rows == 256); }
+// Work lists of the median's all-pairs items, one per item shape: 6 direct
+// shapes (med_class), then 16 Gram-form shapes (ks32, rows) of the problems
+// above 2^20 pairs.
+constexpr int kMedLists = 6 + 16;
+__host__ __device__ inline int med_gram_list(int ks32, int rows) { return 6 + 2 * (ks32 / 2 - 1) + (rows == 256); }
 
 struct BatchPlan {
     int n_problems;
-    const int4* dist_work;  int n_dist;   // (p, row block, column chunk, -) of the median passes
-    int med_classes;                      // bit med_class(dp, rows) set when a problem has that shape
+    const int4* dist_work;  int n_dist;   // (p, row block, column chunk, -) of the median passes,
+    int dist_start[kMedLists];            // sorted by item shape: list c = entries
+    int dist_n[kMedLists];                //   [dist_start[c], dist_start[c] + dist_n[c])
     const int4* cand_work;  int n_cand;   // (p, segment, part, -) of the median's candidate passes
     const int4* phi_work[kPhi32Classes];  // (p, 256-row block, split, -) per FP32 matrix-core class
     int n_phi[kPhi32Classes];

@@ -36,15 +36,19 @@ hipError_t launch_svgd(int N, int d, const float* theta, const float* grad_logp,
                        hipStream_t st, const float* wts = nullptr);
 // The step's first half, which depends on theta only (and may therefore run
 // concurrently with the rollout that produces grad_logp): the median into the
-// workspace's selection state, then the FP32 form's theta operands (particle
-// mean, centred rows, norms, X = -(2/h) x).
+// workspace's selection state and the FP32 form's theta operands (particle
+// mean, centred rows, norms -- which the median's Gram-form passes read --
+// then X = -(2/h) x).
 hipError_t launch_svgd_bandwidth(int N, int d, const float* theta, float bandwidth, float* h_out, void* ws,
                                  const SvgdLayout& L, hipStream_t st);
 hipError_t launch_svgd_bandwidth_batched(const BatchPlan& P, const ProblemDesc* descs, const float* theta, int exact,
                                          char* ws, hipStream_t st);
-hipError_t launch_operands32(int N, int d, const float* theta, void* ws, const SvgdLayout& L, hipStream_t st);
-hipError_t launch_operands32_batched(const BatchPlan& P, const ProblemDesc* descs, const float* theta, char* ws,
-                                     hipStream_t st);
+// part 0: particle mean, centred rows and norms (before the median); part 1:
+// X = -(2/h) x (after it)
+hipError_t launch_operands32(int N, int d, const float* theta, int part, void* ws, const SvgdLayout& L,
+                             hipStream_t st);
+hipError_t launch_operands32_batched(const BatchPlan& P, const ProblemDesc* descs, const float* theta, int part,
+                                     char* ws, hipStream_t st);
 // The step's second half: phi from the bandwidth and centre the workspace
 // holds (FP32 matrix cores, phi32.hip).
 // upd (nullable): apply the update of Algorithm 1 to theta in the same pass
@@ -80,8 +84,13 @@ hipError_t launch_dsvgd_weights_batched(int n_problems, const ProblemDesc* descs
 
 // Median-heuristic bandwidth into the problem's SelState (median.hip): exact = 1
 // the exact lower median of all pairs, 0 the lower median of a fixed sample.
+// gram = 1: problems above 2^20 pairs take, in their passes over every pair,
+// the Gram-form distances of the FP32 contraction's operands (which the
+// workspace must already hold for this theta: launch_operands32); smaller ones
+// keep direct differences.  The batched median always does so: its work lists
+// fix each problem's form (exact = 1 needs the operands of the large ones).
 hipError_t launch_median(int N, int d, const float* theta, float bandwidth, int exact, void* ws, const SvgdLayout& L,
-                         float* h_out, hipStream_t st);
+                         float* h_out, hipStream_t st, int gram = 0);
 hipError_t launch_median_batched(const BatchPlan& P, const ProblemDesc* descs, const float* theta, int exact,
                                  char* ws, hipStream_t st);
 

@@ -41,11 +41,14 @@
 
 namespace stamp {
 
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f4v;
+
 namespace {
 
 constexpr uint32_t kModeDone = 0, kModePass0 = 1, kModeCand = 2, kModeAll = 3;
 constexpr float kBracketSigmas = 6.0f;
 constexpr uint32_t kWaveBuf = 512;        // candidates a wave stages in LDS between flushes
+constexpr int kGramGroup = 1;             // column chunks of one Gram-form item
 constexpr uint32_t kSentinel = 0xffffffffu;  // above every candidate interval
 constexpr int kSelThreads = 1024;         // threads of the sample select
 
@@ -79,6 +82,8 @@ struct MedView {
     uint32_t* hist;
     uint32_t* cand;
     uint32_t* cnt;       // [rb * cc][2]: pairs under, over the bracket
+    const float* xr;     // Gram form: centred rows in MFMA operand order (4 ks floats each)
+    const float* nrm;    // and their squared norms (FP32 matrix-core operands)
 };
 
 __device__ __forceinline__ MedView med_view(int N, int d, float fixed_h, const SvgdLayout& L, char* b) {
@@ -95,6 +100,8 @@ __device__ __forceinline__ MedView med_view(int N, int d, float fixed_h, const S
     v.hist = reinterpret_cast<uint32_t*>(b + L.hist_off);
     v.cand = reinterpret_cast<uint32_t*>(b + L.cand_off);
     v.cnt = reinterpret_cast<uint32_t*>(b + L.cnt_off);
+    v.xr = reinterpret_cast<const float*>(b + L.x32_off);
+    v.nrm = reinterpret_cast<const float*>(b + L.n32_off);
     return v;
 }
 
@@ -525,6 +532,189 @@ __device__ void med_item(const MedView& v, const float* __restrict__ theta, int 
     }
 }
 
+// The same item with the distances in Gram form on the FP32 matrix cores:
+// D_ij = max(|x_i|^2 + |x_j|^2 - 2 x_i . x_j, 0) over the centred rows the
+// FP32 contraction uses (built before the median).  Each wave takes 64 rows
+// as four 16-row tiles; with 256-row items it takes every column of the item,
+// with 64-row items a 16-column quarter.  Per 16 columns and row tile, KS
+// MFMAs (16x16x4) give S[i][j] with lane l holding rows 4 (l / 16) + t of
+// column l % 16.  Every pass computes a pair's distance with the same
+// instructions, so the counts stay exact.
+template <int KS, int ROWS>
+__device__ void med_item_gram(const MedView& v, int rb, int cc) {
+    // an item spans kGramGroup column chunks: its counts go to the first
+    // chunk's slot and zeros to the others
+    const int cc1 = min(cc + kGramGroup, v.cc);
+    constexpr int NT = 256;
+    static_assert(ROWS == 64 || ROWS == 256, "item shape");
+    __shared__ uint32_t lh[kMedBins];
+    __shared__ uint32_t red[2][NT / 64];
+    constexpr uint32_t kBuf = 1024;  // a 16-column step yields at most 16 x 64 candidates per wave
+    __shared__ uint32_t wbuf[NT / 64][kBuf];
+    SelState* sel = v.sel;
+    const uint32_t mode = sel->mode;
+    if (mode != kModePass0 && mode != kModeAll) return;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int col = lane & 15, kq = lane >> 4;
+    const int N = v.N;
+    const int row0 = rb * ROWS, col0 = cc * kMedCols;
+    const bool pass0 = mode == kModePass0;
+    uint32_t* cnt = v.cnt + 2 * ((int64_t)rb * v.cc + cc);
+    if (pass0)
+        for (int e = 2 + tid; e < 2 * (cc1 - cc); e += NT) cnt[e] = 0;
+    if (cc1 * kMedCols <= row0 + 1) {  // no pair i < j in this item
+        if (pass0 && tid == 0) cnt[0] = cnt[1] = 0;
+        return;
+    }
+    const uint32_t lo = sel->lo, hi = sel->hi, s = sel->shift;
+    if (!pass0)
+        for (int b = tid; b < kMedBins; b += NT) lh[b] = 0;
+    __syncthreads();
+    const int wrow = ROWS == 256 ? row0 + 64 * wave : row0;
+    // 256-row items: every 16-column step for each wave; 64-row items: the
+    // waves take the steps in turn
+    const int cbeg = ROWS == 256 ? 0 : 16 * wave, cend = (cc1 - cc) * kMedCols, cstep = ROWS == 256 ? 16 : 64;
+    float xa[4][KS];
+    f4v ni[4];  // |x_i|^2 for i = wrow + 16 r + 4 kq + t
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const float* p = v.xr + (int64_t)(wrow + 16 * r + col) * (4 * KS) + kq * KS;
+#pragma unroll
+        for (int k = 0; k < KS; ++k) xa[r][k] = p[k];
+        ni[r] = *reinterpret_cast<const f4v*>(v.nrm + wrow + 16 * r + 4 * kq);
+    }
+    // one candidate segment per workgroup (hashed: in a work list only every
+    // kGramGroup-th entry runs, and a plain modulus would leave segments unused)
+    const int seg = (int)(mix32(blockIdx.y * gridDim.x + blockIdx.x) % kCandSegs);
+    const uint32_t seg_cap = v.cap / kCandSegs;
+    uint32_t* segbuf = v.cand + (size_t)seg * seg_cap;
+    uint32_t* wb = wbuf[wave];
+    uint32_t nwb = 0;
+    auto flush = [&]() {
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");  // the wave's LDS writes before its reads
+        uint32_t base = 0;
+        if (lane == 0) {
+            base = atomicAdd(&sel->seg[seg], nwb);
+            if ((uint64_t)base + nwb > seg_cap) atomicOr(&sel->overflow, 1u);
+        }
+        base = __shfl(base, 0);
+        for (uint32_t e = (uint32_t)lane; e < nwb; e += 64)
+            if (base + e < seg_cap) segbuf[base + e] = wb[e];
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");  // reads before the next writes
+        nwb = 0;
+    };
+    uint32_t nb = 0, na = 0;
+    // the first step with a pair j > i for some row of the wave; the next
+    // step's operands load while this one computes
+    int c0 = cbeg;
+    while (c0 < cend && col0 + c0 + 15 <= wrow) c0 += cstep;
+    float xb[KS], xn[KS];
+    float nj = 0.0f, nn = 0.0f;
+    auto load = [&](int c, float (&x)[KS], float& n) {
+        const float* p = v.xr + (int64_t)(col0 + c + col) * (4 * KS) + kq * KS;
+#pragma unroll
+        for (int k = 0; k < KS; ++k) x[k] = p[k];
+        n = v.nrm[col0 + c + col];
+    };
+    if (c0 < cend) load(c0, xb, nj);
+    for (int c = c0; c < cend; c += cstep) {
+        if (c + cstep < cend) load(c + cstep, xn, nn);
+        const int j = col0 + c + col;
+        // the lane's 16 distances of this step: counts, and the in-bracket
+        // ones marked for one wave-wide append
+        uint32_t bv[16], inm = 0;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            f4v S = f4v{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int k = 0; k < KS; ++k) S = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[r][k], xb[k], S, 0, 0, 0);
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int i = wrow + 16 * r + 4 * kq + t;
+                const float D = fmaxf(fmaf(-2.0f, S[t], ni[r][t] + nj), 0.0f);
+                const bool valid = i < N && j < N && j > i;
+                const uint32_t bits = __float_as_uint(D);
+                const bool below = valid && bits < lo;
+                const bool above = valid && bits > hi;
+                const bool inr = valid && !below && !above;
+                nb += below ? 1u : 0u;
+                na += above ? 1u : 0u;
+                bv[4 * r + t] = bits;
+                inm |= (inr ? 1u : 0u) << (4 * r + t);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < KS; ++k) xb[k] = xn[k];
+        nj = nn;
+        if (!pass0) {
+#pragma unroll
+            for (int e = 0; e < 16; ++e)
+                if ((inm >> e) & 1u) atomicAdd(&lh[(bv[e] - lo) >> s], 1u);
+            continue;
+        }
+        const uint32_t cnt_l = (uint32_t)__popc(inm);
+        uint32_t incl = cnt_l;  // inclusive prefix sum over the wave
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t y = __shfl_up(incl, off);
+            if (lane >= off) incl += y;
+        }
+        const uint32_t total = __shfl(incl, 63);
+        if (total) {
+            if (nwb + total > kBuf) flush();
+            uint32_t k = nwb + incl - cnt_l;
+#pragma unroll
+            for (int e = 0; e < 16; ++e)
+                if ((inm >> e) & 1u) wb[k++] = bv[e];
+            nwb += total;
+        }
+    }
+    if (!pass0) {
+        __syncthreads();
+        for (int b = tid; b < kMedBins; b += NT)
+            if (lh[b]) atomicAdd(&v.hist[b], lh[b]);
+        return;
+    }
+    // the workgroup's remaining candidates go out under one reservation (the
+    // segment counters are shared by every workgroup: one atomic each)
+    __shared__ uint32_t wn[NT / 64 + 1];
+    if (lane == 0) wn[wave] = nwb;
+    __syncthreads();
+    if (tid == 0) {
+        const uint32_t tot = wn[0] + wn[1] + wn[2] + wn[3];
+        uint32_t base = 0;
+        if (tot) {
+            base = atomicAdd(&sel->seg[seg], tot);
+            if ((uint64_t)base + tot > seg_cap) atomicOr(&sel->overflow, 1u);
+        }
+        wn[NT / 64] = base;
+    }
+    __syncthreads();
+    {
+        uint32_t off = wn[NT / 64];
+        for (int w = 0; w < wave; ++w) off += wn[w];
+        for (uint32_t e = (uint32_t)lane; e < nwb; e += 64)
+            if (off + e < seg_cap) segbuf[off + e] = wb[e];
+    }
+    for (int off = 32; off > 0; off >>= 1) {  // counts of the workgroup
+        nb += __shfl_xor(nb, off);
+        na += __shfl_xor(na, off);
+    }
+    if (lane == 0) {
+        red[0][wave] = nb;
+        red[1][wave] = na;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        uint32_t b = 0, a = 0;
+        for (int w = 0; w < NT / 64; ++w) {
+            b += red[0][w];
+            a += red[1][w];
+        }
+        cnt[0] = b;
+        cnt[1] = a;
+    }
+}
+
 // Candidate pass: histogram of the candidates in [lo, hi] (sentinels and
 // values outside are skipped); segment g, part `part` of kCandParts.
 __device__ void med_cand_body(const MedView& v, int g, int part) {
@@ -637,6 +827,12 @@ __device__ void med_select_body(const MedView& v, float* h_out) {
 // bracket width).  Else (rare) histogram passes run over every pair,
 // recomputed here.
 constexpr uint64_t kFinishPairs = 1ull << 20;
+
+// Problems above kFinishPairs pairs take the Gram-form distances in their
+// all-pairs passes (when the caller provides the operands); smaller ones keep
+// direct differences, in the single-problem and the batched paths alike, so
+// both reach the same bandwidth bit for bit.
+__host__ __device__ __forceinline__ bool med_gram(int N) { return pair_count(N) > kFinishPairs; }
 constexpr int kFinishThreads = 1024;
 constexpr int kFinishRegs = 40;         // candidate slots per thread held in registers
 constexpr int kSegThreads = kFinishThreads / kCandSegs;
@@ -748,6 +944,11 @@ __global__ __launch_bounds__(256) void k_med_items(OneMed a, const float* theta)
     med_item<DP, ROWS>(med_view(a.N, a.d, a.fixed_h, a.L, a.ws), theta, blockIdx.y, blockIdx.x);
 }
 
+template <int KS, int ROWS>
+__global__ __launch_bounds__(256) void k_med_items_gram(OneMed a) {
+    med_item_gram<KS, ROWS>(med_view(a.N, a.d, a.fixed_h, a.L, a.ws), blockIdx.y, blockIdx.x * kGramGroup);
+}
+
 __global__ __launch_bounds__(256) void k_med_cand(OneMed a) {
     med_cand_body(med_view(a.N, a.d, a.fixed_h, a.L, a.ws), blockIdx.x / kCandParts, blockIdx.x % kCandParts);
 }
@@ -779,16 +980,24 @@ __global__ __launch_bounds__(kSelThreads) void k_sample_select_batched(const Pro
     sample_select_body(med_of(descs[blockIdx.x], ws), exact, nullptr);
 }
 
-// entry = (problem, row block, column chunk, -); each class DP runs the items of
-// its problems and skips the others
+// entry = (problem, row block, column chunk, -) of this item shape's work list
 template <int DP, int ROWS>
 __global__ __launch_bounds__(256) void k_med_items_batched(const ProblemDesc* __restrict__ descs,
                                                             const int4* __restrict__ work, const float* theta,
                                                             char* ws) {
     const int4 w = work[blockIdx.x];
     const ProblemDesc& D = descs[w.x];
-    if (med_dp(D.d) != DP || D.sv.med_rows != ROWS) return;
     med_item<DP, ROWS>(med_of(D, ws), theta + D.theta_off, w.y, w.z);
+}
+
+template <int KS, int ROWS>
+__global__ __launch_bounds__(256) void k_med_items_gram_batched(const ProblemDesc* __restrict__ descs,
+                                                                 const int4* __restrict__ work, char* ws) {
+    const int4 w = work[blockIdx.x];
+    const ProblemDesc& D = descs[w.x];
+    // the entry that starts a group of kGramGroup column chunks runs them all
+    if (w.z % kGramGroup != 0) return;
+    med_item_gram<KS, ROWS>(med_of(D, ws), w.y, w.z);
 }
 
 // entry = (problem, segment, part, -)
@@ -816,42 +1025,87 @@ void launch_items(const OneMed& a, const float* theta, hipStream_t st) {
     else launch_items_rows<256>(a, theta, st);
 }
 
+template <int KS>
+void launch_items_gram_ks(const OneMed& a, hipStream_t st) {
+    const dim3 grid((a.L.med_cc + kGramGroup - 1) / kGramGroup, a.L.med_rb);
+    if (a.L.med_rows == 64) hipLaunchKernelGGL((k_med_items_gram<KS, 64>), grid, dim3(256), 0, st, a);
+    else hipLaunchKernelGGL((k_med_items_gram<KS, 256>), grid, dim3(256), 0, st, a);
+}
+
+void launch_items_gram(const OneMed& a, hipStream_t st) {
+    switch (a.L.ks32) {
+        case 2: launch_items_gram_ks<2>(a, st); break;
+        case 4: launch_items_gram_ks<4>(a, st); break;
+        case 6: launch_items_gram_ks<6>(a, st); break;
+        case 8: launch_items_gram_ks<8>(a, st); break;
+        case 10: launch_items_gram_ks<10>(a, st); break;
+        case 12: launch_items_gram_ks<12>(a, st); break;
+        case 14: launch_items_gram_ks<14>(a, st); break;
+        default: launch_items_gram_ks<16>(a, st); break;
+    }
+}
+
+// each item shape's work list, in its own launch
+template <int DP, int ROWS>
+void launch_direct_list(const BatchPlan& P, const ProblemDesc* descs, const float* theta, char* ws, hipStream_t st) {
+    const int c = med_class(DP, ROWS);
+    if (P.dist_n[c])
+        hipLaunchKernelGGL((k_med_items_batched<DP, ROWS>), dim3(P.dist_n[c]), dim3(256), 0, st, descs,
+                           P.dist_work + P.dist_start[c], theta, ws);
+}
+
+template <int KS>
+void launch_gram_lists(const BatchPlan& P, const ProblemDesc* descs, char* ws, hipStream_t st) {
+    const int c64 = med_gram_list(KS, 64), c256 = med_gram_list(KS, 256);
+    if (P.dist_n[c64])
+        hipLaunchKernelGGL((k_med_items_gram_batched<KS, 64>), dim3(P.dist_n[c64]), dim3(256), 0, st, descs,
+                           P.dist_work + P.dist_start[c64], ws);
+    if (P.dist_n[c256])
+        hipLaunchKernelGGL((k_med_items_gram_batched<KS, 256>), dim3(P.dist_n[c256]), dim3(256), 0, st, descs,
+                           P.dist_work + P.dist_start[c256], ws);
+}
+
 void launch_items_batched(const BatchPlan& P, const ProblemDesc* descs, const float* theta, char* ws,
                           hipStream_t st) {
     if (!P.n_dist) return;
-    const dim3 g(P.n_dist);
-    const int m = P.med_classes;  // launch only the classes the batch holds
-    if (m & (1 << med_class(16, 64)))
-        hipLaunchKernelGGL((k_med_items_batched<16, 64>), g, dim3(256), 0, st, descs, P.dist_work, theta, ws);
-    if (m & (1 << med_class(32, 64)))
-        hipLaunchKernelGGL((k_med_items_batched<32, 64>), g, dim3(256), 0, st, descs, P.dist_work, theta, ws);
-    if (m & (1 << med_class(64, 64)))
-        hipLaunchKernelGGL((k_med_items_batched<64, 64>), g, dim3(256), 0, st, descs, P.dist_work, theta, ws);
-    if (m & (1 << med_class(16, 256)))
-        hipLaunchKernelGGL((k_med_items_batched<16, 256>), g, dim3(256), 0, st, descs, P.dist_work, theta, ws);
-    if (m & (1 << med_class(32, 256)))
-        hipLaunchKernelGGL((k_med_items_batched<32, 256>), g, dim3(256), 0, st, descs, P.dist_work, theta, ws);
-    if (m & (1 << med_class(64, 256)))
-        hipLaunchKernelGGL((k_med_items_batched<64, 256>), g, dim3(256), 0, st, descs, P.dist_work, theta, ws);
+    launch_direct_list<16, 64>(P, descs, theta, ws, st);
+    launch_direct_list<32, 64>(P, descs, theta, ws, st);
+    launch_direct_list<64, 64>(P, descs, theta, ws, st);
+    launch_direct_list<16, 256>(P, descs, theta, ws, st);
+    launch_direct_list<32, 256>(P, descs, theta, ws, st);
+    launch_direct_list<64, 256>(P, descs, theta, ws, st);
+    launch_gram_lists<2>(P, descs, ws, st);
+    launch_gram_lists<4>(P, descs, ws, st);
+    launch_gram_lists<6>(P, descs, ws, st);
+    launch_gram_lists<8>(P, descs, ws, st);
+    launch_gram_lists<10>(P, descs, ws, st);
+    launch_gram_lists<12>(P, descs, ws, st);
+    launch_gram_lists<14>(P, descs, ws, st);
+    launch_gram_lists<16>(P, descs, ws, st);
 }
 
 }  // namespace
 
 hipError_t launch_median(int N, int d, const float* theta, float bandwidth, int exact, void* ws, const SvgdLayout& L,
-                         float* h_out, hipStream_t st) {
+                         float* h_out, hipStream_t st, int gram) {
     OneMed a{N, d, bandwidth > 0.0f ? bandwidth : 0.0f, L, static_cast<char*>(ws)};
     hipLaunchKernelGGL(k_med_dist, dim3(kMedSample / 256), dim3(256), 0, st, a, theta);
     hipLaunchKernelGGL(k_sample_select, dim3(1), dim3(kSelThreads), 0, st, a, exact, h_out);
     if (exact && N >= 2 && !(bandwidth > 0.0f) && pair_count(N) > (uint64_t)kMedSample) {
-        launch_items(a, theta, st);  // pass 0
-        if (pair_count(N) <= kFinishPairs) {  // small: one workgroup finishes
+        // pass 0; small problems keep direct differences, whose every-pair
+        // fallback lives in the finishing workgroup
+        const bool small = !med_gram(N);
+        if (gram && !small) launch_items_gram(a, st);
+        else launch_items(a, theta, st);
+        if (small) {  // one workgroup finishes
             hipLaunchKernelGGL(k_med_finish, dim3(1), dim3(kFinishThreads), 0, st, a, theta, h_out);
             return hipGetLastError();
         }
         hipLaunchKernelGGL(k_med_select, dim3(1), dim3(256), 0, st, a, h_out);
         for (int pass = 0; pass < 3; ++pass) {
             hipLaunchKernelGGL(k_med_cand, dim3(kCandSegs * kCandParts), dim3(256), 0, st, a);
-            launch_items(a, theta, st);
+            if (gram) launch_items_gram(a, st);
+            else launch_items(a, theta, st);
             hipLaunchKernelGGL(k_med_select, dim3(1), dim3(256), 0, st, a, h_out);
         }
     }
@@ -864,12 +1118,13 @@ hipError_t launch_median_batched(const BatchPlan& P, const ProblemDesc* descs, c
     hipLaunchKernelGGL(k_med_dist_batched, dim3(kMedSample / 256, np), dim3(256), 0, st, descs, theta, ws);
     hipLaunchKernelGGL(k_sample_select_batched, dim3(np), dim3(kSelThreads), 0, st, descs, ws, exact);
     if (exact && P.n_dist) {
-        launch_items_batched(P, descs, theta, ws, st);
+        auto items = [&]() { launch_items_batched(P, descs, theta, ws, st); };
+        items();
         hipLaunchKernelGGL(k_med_select_batched, dim3(np), dim3(256), 0, st, descs, ws);
         for (int pass = 0; pass < 3; ++pass) {
             if (P.n_cand)
                 hipLaunchKernelGGL(k_med_cand_batched, dim3(P.n_cand), dim3(256), 0, st, descs, P.cand_work, ws);
-            launch_items_batched(P, descs, theta, ws, st);
+            items();
             hipLaunchKernelGGL(k_med_select_batched, dim3(np), dim3(256), 0, st, descs, ws);
         }
     }

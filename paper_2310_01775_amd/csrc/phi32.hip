@@ -12,9 +12,10 @@
 // theta_i - theta_j = x_i - x_j.
 //
 // Stages: everything that depends on theta only runs with the median (the
-// bandwidth stage, which can overlap the rollout): the particle mean, then the
-// pack kernel (it needs h) writing the centred rows in the MFMA operand order,
-// their norms, and X = [-(2/h) x | 1 | 0] chunk-tiled.  The contraction adds g
+// bandwidth stage, which can overlap the rollout): the particle mean and the
+// centred rows in the MFMA operand order with their norms (the median's
+// all-pairs passes take their Gram-form distances from these), then after the
+// median X = [-(2/h) x | 1 | 0] chunk-tiled.  The contraction adds g
 // (read straight from its [d][N] layout) and the weights to X to form V; it (64, 128 or 256 rows per workgroup, 64 per wave as four 16-row
 // tiles, one column split) runs per 16 columns the Gram MFMAs of every row tile, turns
 // them into K in registers and feeds K as the A operand of the K.V MFMAs: the
@@ -71,29 +72,37 @@ __device__ void mean_body(int N, int l, const float* __restrict__ theta, float* 
 
 // ---- operands: 64 rows per 256 threads, lane group q = threadIdx.x / 64 takes
 // the coordinates l = 4 s + q (its MFMA lane group's values), so a thread's
-// stores of xr are contiguous and its loop is a quarter of the dimension
-__device__ void pack32_rows(int N, int d, int ks, int ot, int row0, const float* __restrict__ theta,
-                            const View32& v) {
+// stores of xr are contiguous and its loop is a quarter of the dimension.
+// The centred rows and their norms come first (the median's Gram form reads
+// them); X = [-(2/h) x | 1 | 0] needs h and comes after the median.
+__device__ void pack32_x_rows(int N, int d, int ks, int row0, const float* __restrict__ theta, const View32& v) {
     __shared__ float part[4][64];
     const int r = threadIdx.x & 63, q = threadIdx.x >> 6;
     const int i = row0 + r;
-    const float c2 = 2.0f / v.sel->h;
     const int kd = 4 * ks;
-    float* vt = v.vt + (int64_t)(i >> 4) * ot * 256 + (i & 15);
     float nrm = 0.0f;
     for (int s = 0; s < ks; ++s) {
         const int l = 4 * s + q;
         const float x = (i < N && l < d) ? theta[(int64_t)l * N + i] - v.ctr[l] : 0.0f;
         nrm = fmaf(x, x, nrm);
         v.xr[(int64_t)i * kd + q * ks + s] = x;
-        if (l < d) vt[(l >> 4) * 256 + (l & 15) * 16] = -c2 * x;
     }
-    for (int n = d + ((q - d) & 3); n < 16 * ot; n += 4)
-        vt[(n >> 4) * 256 + (n & 15) * 16] = (n == d && i < N) ? 1.0f : 0.0f;
     part[q][r] = nrm;
     __syncthreads();
     if (q == 0) v.nrm[i] = (part[0][r] + part[1][r]) + (part[2][r] + part[3][r]);
     __syncthreads();
+}
+
+__device__ void pack32_v_rows(int N, int d, int ot, int row0, const float* __restrict__ theta, const View32& v) {
+    const int r = threadIdx.x & 63, q = threadIdx.x >> 6;
+    const int i = row0 + r;
+    const float c2 = 2.0f / v.sel->h;
+    float* vt = v.vt + (int64_t)(i >> 4) * ot * 256 + (i & 15);
+    for (int n = q; n < 16 * ot; n += 4) {
+        float x = 0.0f;
+        if (i < N) x = n < d ? -c2 * (theta[(int64_t)n * N + i] - v.ctr[n]) : (n == d ? 1.0f : 0.0f);
+        vt[(n >> 4) * 256 + (n & 15) * 16] = x;
+    }
 }
 
 // ---- contraction: partial sums of K V over the columns [j0, j1) -------------------
@@ -240,8 +249,12 @@ __global__ __launch_bounds__(256) void k_mean(One32 a, const float* theta, char*
     mean_body(a.N, blockIdx.x, theta, reinterpret_cast<float*>(ws + a.L.ctr_off));
 }
 
-__global__ __launch_bounds__(256) void k_pack32(One32 a, const float* theta, char* ws) {
-    pack32_rows(a.N, a.d, a.L.ks32, a.L.ot32, blockIdx.x * 64, theta, view32(a.L, ws));
+__global__ __launch_bounds__(256) void k_pack32_x(One32 a, const float* theta, char* ws) {
+    pack32_x_rows(a.N, a.d, a.L.ks32, blockIdx.x * 64, theta, view32(a.L, ws));
+}
+
+__global__ __launch_bounds__(256) void k_pack32_v(One32 a, const float* theta, char* ws) {
+    pack32_v_rows(a.N, a.d, a.L.ot32, blockIdx.x * 64, theta, view32(a.L, ws));
 }
 
 template <int KS, int OT>
@@ -280,13 +293,22 @@ __global__ __launch_bounds__(256) void k_mean_batched(const ProblemDesc* __restr
 }
 
 // entry = (problem, first row of a 256-row chunk, -, -)
-__global__ __launch_bounds__(256) void k_pack32_batched(const ProblemDesc* __restrict__ descs,
-                                                        const int4* __restrict__ work, const float* theta, char* ws) {
+__global__ __launch_bounds__(256) void k_pack32_x_batched(const ProblemDesc* __restrict__ descs,
+                                                          const int4* __restrict__ work, const float* theta, char* ws) {
     const int4 e = work[blockIdx.x];
     const ProblemDesc& D = descs[e.x];
     if (D.N < 2) return;
     const View32 v = view32(D.sv, base32(D, ws));
-    for (int r0 = e.y; r0 < e.y + 256; r0 += 64) pack32_rows(D.N, D.d, D.sv.ks32, D.sv.ot32, r0, theta + D.theta_off, v);
+    for (int r0 = e.y; r0 < e.y + 256; r0 += 64) pack32_x_rows(D.N, D.d, D.sv.ks32, r0, theta + D.theta_off, v);
+}
+
+__global__ __launch_bounds__(256) void k_pack32_v_batched(const ProblemDesc* __restrict__ descs,
+                                                          const int4* __restrict__ work, const float* theta, char* ws) {
+    const int4 e = work[blockIdx.x];
+    const ProblemDesc& D = descs[e.x];
+    if (D.N < 2) return;
+    const View32 v = view32(D.sv, base32(D, ws));
+    for (int r0 = e.y; r0 < e.y + 256; r0 += 64) pack32_v_rows(D.N, D.d, D.sv.ot32, r0, theta + D.theta_off, v);
 }
 
 // entry = (problem, row block of blockDim.x rows, split, -)
@@ -366,20 +388,29 @@ int phi32_class(int d) {
     return -1;
 }
 
-hipError_t launch_operands32(int N, int d, const float* theta, void* ws, const SvgdLayout& L, hipStream_t st) {
+hipError_t launch_operands32(int N, int d, const float* theta, int part, void* ws, const SvgdLayout& L,
+                             hipStream_t st) {
     if (N < 2) return hipSuccess;
     One32 a{N, d, L};
     char* b = static_cast<char*>(ws);
-    hipLaunchKernelGGL(k_mean, dim3(d), dim3(256), 0, st, a, theta, b);
-    hipLaunchKernelGGL(k_pack32, dim3(L.npad / 64), dim3(256), 0, st, a, theta, b);
+    if (part == 0) {
+        hipLaunchKernelGGL(k_mean, dim3(d), dim3(256), 0, st, a, theta, b);
+        hipLaunchKernelGGL(k_pack32_x, dim3(L.npad / 64), dim3(256), 0, st, a, theta, b);
+    } else {
+        hipLaunchKernelGGL(k_pack32_v, dim3(L.npad / 64), dim3(256), 0, st, a, theta, b);
+    }
     return hipGetLastError();
 }
 
-hipError_t launch_operands32_batched(const BatchPlan& P, const ProblemDesc* descs, const float* theta, char* ws,
-                                     hipStream_t st) {
-    if (P.n_ctr) hipLaunchKernelGGL(k_mean_batched, dim3(P.n_ctr), dim3(256), 0, st, descs, P.ctr_work, theta, ws);
-    if (P.n_row16)
-        hipLaunchKernelGGL(k_pack32_batched, dim3(P.n_row16), dim3(256), 0, st, descs, P.row16_work, theta, ws);
+hipError_t launch_operands32_batched(const BatchPlan& P, const ProblemDesc* descs, const float* theta, int part,
+                                     char* ws, hipStream_t st) {
+    if (part == 0) {
+        if (P.n_ctr) hipLaunchKernelGGL(k_mean_batched, dim3(P.n_ctr), dim3(256), 0, st, descs, P.ctr_work, theta, ws);
+        if (P.n_row16)
+            hipLaunchKernelGGL(k_pack32_x_batched, dim3(P.n_row16), dim3(256), 0, st, descs, P.row16_work, theta, ws);
+    } else if (P.n_row16) {
+        hipLaunchKernelGGL(k_pack32_v_batched, dim3(P.n_row16), dim3(256), 0, st, descs, P.row16_work, theta, ws);
+    }
     return hipGetLastError();
 }
 

@@ -181,7 +181,7 @@ struct SolvePlan {
     std::vector<int4> phi_work[kPhi32Classes];
     std::vector<int4> ctr_work, row16_work, phi16_work[2];  // BF16 form
     int phi_rows = 256;
-    int med_classes = 0;  // item shapes among dist_work (bit med_class)
+    int dist_start[kMedLists] = {}, dist_n[kMedLists] = {};  // dist_work sorted by item shape
     size_t clk_off = 0, desc_off = 0, roll_off = 0, dist_off = 0, cand_off = 0, red_off = 0;
     size_t ctr16_off = 0, row16_off = 0, phi16_off[2] = {};
     size_t phi_off[kPhi32Classes] = {};
@@ -205,6 +205,7 @@ void build_plan(int n, const stamp_scene* scenes, const int32_t* N, int K, float
     size_t sv = 0;
     char buf[64];
     P.key.clear();
+    std::vector<int4> dist_lists[kMedLists];
     for (int p = 0; p < n; ++p) {
         ProblemDesc& D = P.descs[p];
         memset(&D, 0, sizeof D);
@@ -232,9 +233,11 @@ void build_plan(int n, const stamp_scene* scenes, const int32_t* N, int K, float
         // every (row block, column chunk) item (items without a pair i < j write
         // zero counts), and (segment, part) of the candidate passes
         if (D.N >= 2 && !(bandwidth > 0.0f) && (uint64_t)D.N * (uint64_t)(D.N - 1) / 2 > (uint64_t)kMedSample) {
+            // problems above 2^20 pairs take the Gram form (median.hip)
+            const bool gram = (uint64_t)D.N * (uint64_t)(D.N - 1) / 2 > (1ull << 20);
+            const int c = gram ? med_gram_list(D.sv.ks32, D.sv.med_rows) : med_class(med_dp(D.d), D.sv.med_rows);
             for (int rb = 0; rb < D.sv.med_rb; ++rb)
-                for (int cc = 0; cc < D.sv.med_cc; ++cc) P.dist_work.push_back(make_int4(p, rb, cc, 0));
-            P.med_classes |= 1 << med_class(med_dp(D.d), D.sv.med_rows);
+                for (int cc = 0; cc < D.sv.med_cc; ++cc) dist_lists[c].push_back(make_int4(p, rb, cc, 0));
             for (int g = 0; g < kCandSegs; ++g)
                 for (int q = 0; q < kCandParts; ++q) P.cand_work.push_back(make_int4(p, g, q, 0));
         }
@@ -256,6 +259,11 @@ void build_plan(int n, const stamp_scene* scenes, const int32_t* N, int K, float
             P.red_work.push_back(make_int4(p, (int)e, (int)std::min<int64_t>(e + kRedChunk, ne), 0));
     }
     P.n_theta = th;
+    for (int c = 0; c < kMedLists; ++c) {
+        P.dist_start[c] = (int)P.dist_work.size();
+        P.dist_n[c] = (int)dist_lists[c].size();
+        P.dist_work.insert(P.dist_work.end(), dist_lists[c].begin(), dist_lists[c].end());
+    }
     // The contraction lists get the room of their longest form (64-row
     // blocks), so that no region of the workspace moves when the row block
     // changes: pointers into it stay valid across every launch shape.
@@ -763,7 +771,10 @@ static int32_t solve_impl(stamp_ctx* ctx, int32_t n_problems, const stamp_scene*
         B.n_problems = n_problems;
         B.dist_work = (const int4*)(ws + P.dist_off);
         B.n_dist = (int)P.dist_work.size();
-        B.med_classes = P.med_classes;
+        for (int c = 0; c < kMedLists; ++c) {
+            B.dist_start[c] = P.dist_start[c];
+            B.dist_n[c] = P.dist_n[c];
+        }
         B.cand_work = (const int4*)(ws + P.cand_off);
         B.n_cand = (int)P.cand_work.size();
         for (int c = 0; c < kPhi32Classes; ++c) {

@@ -252,9 +252,10 @@ hipError_t launch_svgd(int N, int d, const float* theta, const float* grad_logp,
 
 hipError_t launch_svgd_bandwidth(int N, int d, const float* theta, float bandwidth, float* h_out, void* ws,
                                  const SvgdLayout& L, hipStream_t st) {
-    hipError_t e = launch_median(N, d, theta, bandwidth, 1, ws, L, h_out, st);
+    hipError_t e = launch_operands32(N, d, theta, 0, ws, L, st);
     if (e != hipSuccess) return e;
-    return launch_operands32(N, d, theta, ws, L, st);
+    if ((e = launch_median(N, d, theta, bandwidth, 1, ws, L, h_out, st, 1)) != hipSuccess) return e;
+    return launch_operands32(N, d, theta, 1, ws, L, st);
 }
 
 hipError_t launch_svgd_batched(const BatchPlan& P, const ProblemDesc* descs, const float* theta, const float* grad,
@@ -266,11 +267,12 @@ hipError_t launch_svgd_batched(const BatchPlan& P, const ProblemDesc* descs, con
 
 hipError_t launch_svgd_bandwidth_batched(const BatchPlan& P, const ProblemDesc* descs, const float* theta, int exact,
                                          char* ws, hipStream_t st) {
-    hipError_t e = launch_median_batched(P, descs, theta, exact, ws, st);
-    if (e != hipSuccess) return e;
-    // the theta-only operands of the FP32 form (exact median) or of the BF16
-    // form (sampled median)
-    return exact ? launch_operands32_batched(P, descs, theta, ws, st) : launch_operands16_batched(P, descs, theta, ws, st);
+    // the theta-only operands of the FP32 form (exact median, whose all-pairs
+    // passes read them) or of the BF16 form (sampled median)
+    hipError_t e;
+    if (exact && (e = launch_operands32_batched(P, descs, theta, 0, ws, st)) != hipSuccess) return e;
+    if ((e = launch_median_batched(P, descs, theta, exact, ws, st)) != hipSuccess) return e;
+    return exact ? launch_operands32_batched(P, descs, theta, 1, ws, st) : launch_operands16_batched(P, descs, theta, ws, st);
 }
 
 hipError_t launch_phi_reduce(int N, int d, int splits, const float* partial, float* phi, uint32_t* status,
