@@ -60,7 +60,9 @@ def test_batched_solve_equals_per_problem_iterations(ctx, autotune):
 
 
 def _check_batched_equals_loops(ctx, S):
-    sizes = [(64, 2, 1), (200, 5, 4), (1, 3, 2), (97, 3, 3), (130, 4, 2), (33, 2, 4)]
+    # 1600 particles: above 2^20 pairs, so its median's all-pairs passes take
+    # the Gram form in both paths
+    sizes = [(64, 2, 1), (200, 5, 4), (1, 3, 2), (97, 3, 3), (130, 4, 2), (33, 2, 4), (1600, 3, 1)]
     probs = _problems(sizes, 40, 0.005, 0)
     iters, lr = 6, 1e-3
     flat = _pack(S, probs)
