@@ -71,13 +71,16 @@ def test_median_of_many_pairs_is_exact(ctx, N, d):
     assert (D < lo).sum() < k <= (D <= hi).sum()
 
 
-def test_median_with_massive_ties_takes_the_all_pairs_passes(ctx):
+@pytest.mark.parametrize("N", [1000, 2000])
+def test_median_with_massive_ties_takes_the_all_pairs_passes(ctx, N):
     """Two clusters of identical particles: just under half the pairs are at
     distance 0 and the rest share one value, the median; the bracket then
-    holds more values than the candidate buffer and the select finishes with
-    passes over all pairs.  The result is that shared distance."""
+    holds more values than the candidate buffer (at 1000 particles) and the
+    select finishes with passes over all pairs.  The result is that shared
+    distance.  At 2000 particles (above 2^20 pairs) the passes take the
+    Gram form, whose identical operands give identical values too."""
     import paper_2310_01775_amd as S
-    N, d = 1000, 12
+    d = 12
     th = np.zeros((N, d))
     th[N // 2:] = W.f32(np.linspace(0.1, 1.2, d))
     h_out = torch.zeros(1, dtype=torch.float32, device="cuda")
