@@ -175,3 +175,34 @@ def test_structured_solve_matches_oracle(ctx):
     norm = np.linalg.norm(got - ref["theta"]) / np.linalg.norm(ref["theta"])
     print("structured solve state error: worst", err, "normwise", norm, flush=True)
     assert norm < 1e-4 and err < 1e-3
+
+
+def test_structured_dsvgd_solve_equals_the_per_call_loop(ctx):
+    """Importance weights (Eq. 4) with the structured kernel: the solve equals
+    rollout, discrete read-out, weights and the weighted structured step."""
+    import paper_2310_01775_amd as S
+    scene = W.make_scene(66, 0, 2, 3, 40, 0.005)
+    w = W.cost_weights(rot=0.5)
+    th = W.make_particles(66, 0, 70, 3)
+    sc, cw = S.make_scene(scene), S.make_cost(w)
+    N, H = th.shape[0], int(scene["H"])
+    flat = S.soa(th)
+    m, v = torch.zeros_like(flat), torch.zeros_like(flat)
+    st = ctx.status_word()
+    ctx.solve([sc], [cw], [N], S.make_cfg(3, lr=1e-3, dsvgd=True, kernel=S.struct_kernel(PUSH, 0)), flat, m, v,
+              status=st)
+    torch.cuda.synchronize()
+    assert int(st.item()) == 0
+    kp = S.struct_kernel(PUSH, H)
+    theta = S.soa(th)
+    mm, vv = torch.zeros_like(theta), torch.zeros_like(theta)
+    tape = torch.empty(ctx.tape_floats(sc, N, 0), dtype=torch.float32, device="cuda")
+    minus = torch.full((N,), -1.0, device="cuda")
+    for t in range(1, 4):
+        c_rel = ctx.rollout_fwd(sc, cw, theta, tape=tape)
+        gr = ctx.rollout_adj(sc, cw, theta, tape, cost_bar=minus)
+        _, c_disc = ctx.plan_readout(sc, cw, theta)
+        phi = ctx.svgd_step_structured(theta, gr, kp, weights=ctx.dsvgd_weights(c_rel, c_disc))
+        ctx.adam_step(theta, phi, mm, vv, t, lr=1e-3)
+    torch.cuda.synchronize()
+    assert torch.equal(flat, theta)
