@@ -246,12 +246,19 @@ __global__ __launch_bounds__(64 * kInfWaves) void k_mlp_infer(const float* __res
 #pragma unroll
     for (int rb = 0; rb < kInfRB; ++rb) stage_inputs(U + rb * 16 * kLdU, m, X, x_mode, M, n_in, d, enc, row0 + rb * 16);
     __syncthreads();
+    // Each column block's weight fragments are loaded two blocks ahead (a
+    // ring of three), so the L2 latency of a fragment overlaps the matrix
+    // products of the two blocks before it; the loops are unrolled so the
+    // ring slots are fixed registers.
     // layer 1
+    bf16x8 r1[3][kIn / 32];
+    load_frags<kIn / 32>(m.W1, kIn, 0, r1[0]);
+    load_frags<kIn / 32>(m.W1, kIn, 16, r1[1]);
+#pragma unroll
     for (int cb = 0; cb < kW / 16; ++cb) {
-        bf16x8 bv[kIn / 32];
-        load_frags<kIn / 32>(m.W1, kIn, cb * 16, bv);
+        if (cb + 2 < kW / 16) load_frags<kIn / 32>(m.W1, kIn, (cb + 2) * 16, r1[(cb + 2) % 3]);
         f4 acc[kInfRB] = {};
-        mma_blocks<kIn / 32>(U, kLdU, bv, acc);
+        mma_blocks<kIn / 32>(U, kLdU, r1[cb % 3], acc);
         const int c = cb * 16 + col;
         const float b1 = m.b1[c];
 #pragma unroll
@@ -261,11 +268,14 @@ __global__ __launch_bounds__(64 * kInfWaves) void k_mlp_infer(const float* __res
     __syncthreads();
     // layer 2, the output dot and delta2 = w3 gelu'(z2)
     float yp[kInfRB][4] = {};
+    bf16x8 r2[3][kW / 32];
+    load_frags<kW / 32>(m.W2, kW, 0, r2[0]);
+    load_frags<kW / 32>(m.W2, kW, 16, r2[1]);
+#pragma unroll
     for (int cb = 0; cb < kW / 16; ++cb) {
-        bf16x8 bv[kW / 32];
-        load_frags<kW / 32>(m.W2, kW, cb * 16, bv);
+        if (cb + 2 < kW / 16) load_frags<kW / 32>(m.W2, kW, (cb + 2) * 16, r2[(cb + 2) % 3]);
         f4 acc[kInfRB] = {};
-        mma_blocks<kW / 32>(Hb, kLdH, bv, acc);
+        mma_blocks<kW / 32>(Hb, kLdH, r2[cb % 3], acc);
         const int c = cb * 16 + col;
         const float b2 = m.b2[c], w3 = m.w3[c];
 #pragma unroll
@@ -284,13 +294,21 @@ __global__ __launch_bounds__(64 * kInfWaves) void k_mlp_infer(const float* __res
     __syncthreads();
     if (want_grad) {
         // delta1 = (delta2 W2) * gelu'(z1), z1 recomputed
+        bf16x8 rt[3][kW / 32], rw[3][kIn / 32];
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            load_frags<kW / 32>(m.W2T, kW, q * 16, rt[q]);
+            load_frags<kIn / 32>(m.W1, kIn, q * 16, rw[q]);
+        }
+#pragma unroll
         for (int kb = 0; kb < kW / 16; ++kb) {
-            bf16x8 bt2[kW / 32], bw1[kIn / 32];
-            load_frags<kW / 32>(m.W2T, kW, kb * 16, bt2);
-            load_frags<kIn / 32>(m.W1, kIn, kb * 16, bw1);
+            if (kb + 2 < kW / 16) {
+                load_frags<kW / 32>(m.W2T, kW, (kb + 2) * 16, rt[(kb + 2) % 3]);
+                load_frags<kIn / 32>(m.W1, kIn, (kb + 2) * 16, rw[(kb + 2) % 3]);
+            }
             f4 t[kInfRB] = {}, z1[kInfRB] = {};
-            mma_blocks<kW / 32>(Db, kLdH, bt2, t);
-            mma_blocks<kIn / 32>(U, kLdU, bw1, z1);
+            mma_blocks<kW / 32>(Db, kLdH, rt[kb % 3], t);
+            mma_blocks<kIn / 32>(U, kLdU, rw[kb % 3], z1);
             const int k = kb * 16 + col;
             const float b1 = m.b1[k];
 #pragma unroll
