@@ -180,6 +180,32 @@ struct BatchPlan {
     const int4* red_work;   int n_red;    // (p, first elem, end elem, -)
 };
 
+// Mean of coordinate l over N particles ([d][N] layout), one workgroup of
+// kMeanThreads: four independent partial sums per thread keep four loads in
+// flight; a fixed tree adds the threads' sums (same order on every launch).
+constexpr int kMeanThreads = 1024;
+__device__ __forceinline__ void particle_mean_body(int N, int l, const float* __restrict__ theta,
+                                                   float* __restrict__ ctr) {
+    __shared__ float red[kMeanThreads];
+    const float* t = theta + (int64_t)l * N;
+    float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, s3 = 0.0f;
+    int i = threadIdx.x;
+    for (; i + 3 * kMeanThreads < N; i += 4 * kMeanThreads) {
+        s0 += t[i];
+        s1 += t[i + kMeanThreads];
+        s2 += t[i + 2 * kMeanThreads];
+        s3 += t[i + 3 * kMeanThreads];
+    }
+    for (; i < N; i += kMeanThreads) s0 += t[i];
+    red[threadIdx.x] = (s0 + s1) + (s2 + s3);
+    __syncthreads();
+    for (int w = kMeanThreads / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) ctr[l] = red[0] / (float)N;
+}
+
 // The update of Algorithm 1 on one element: Adam minimising -phi with the
 // bias-correction denominators den = (1 - b1^t, 1 - b2^t), or theta += lr phi.
 struct UpdateArgs {

@@ -57,19 +57,6 @@ __device__ __forceinline__ View16 view16(const SvgdLayout& L, char* base) {
     return v;
 }
 
-// ---- particle mean of coordinate l (one workgroup of 256) --------------------
-__device__ void center_body(int N, int l, const float* __restrict__ theta, float* __restrict__ ctr) {
-    __shared__ float red[256];
-    float s = 0.0f;
-    for (int i = threadIdx.x; i < N; i += 256) s += theta[(int64_t)l * N + i];
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) ctr[l] = red[0] / (float)N;
-}
 
 // Position of particle i inside its 32-particle chunk of V: lane group kq of
 // the K.V MFMA holds k slots 8 kq .. 8 kq + 7 = particles 4 kq .. 4 kq + 3
@@ -250,8 +237,8 @@ struct One16 {
     float fixed_h;
 };
 
-__global__ __launch_bounds__(256) void k_center(One16 a, const float* theta, char* ws) {
-    center_body(a.N, blockIdx.x, theta, view16(a.L, ws).ctr);
+__global__ __launch_bounds__(kMeanThreads) void k_center(One16 a, const float* theta, char* ws) {
+    particle_mean_body(a.N, blockIdx.x, theta, view16(a.L, ws).ctr);
 }
 
 __global__ __launch_bounds__(256) void k_pack16_theta(One16 a, const float* theta, char* ws) {
@@ -291,11 +278,11 @@ __global__ __launch_bounds__(256) void k_reduce16(One16 a, const float* theta, c
 __device__ __forceinline__ char* base_of(const ProblemDesc& D, char* ws) { return ws + D.svgd_off; }
 
 // entry = (problem, coordinate, -, -)
-__global__ __launch_bounds__(256) void k_center_batched(const ProblemDesc* __restrict__ descs,
+__global__ __launch_bounds__(kMeanThreads) void k_center_batched(const ProblemDesc* __restrict__ descs,
                                                         const int4* __restrict__ work, const float* theta, char* ws) {
     const int4 e = work[blockIdx.x];
     const ProblemDesc& D = descs[e.x];
-    center_body(D.N, e.y, theta + D.theta_off, view16(D.sv, base_of(D, ws)).ctr);
+    particle_mean_body(D.N, e.y, theta + D.theta_off, view16(D.sv, base_of(D, ws)).ctr);
 }
 
 // entry = (problem, first row of a 256-row chunk, -, -)
@@ -356,14 +343,15 @@ hipError_t launch_operands16(int N, int d, const float* theta, void* ws, const S
     if (N < 2) return hipSuccess;
     One16 a{N, d, L, 0.0f};
     char* b = static_cast<char*>(ws);
-    hipLaunchKernelGGL(k_center, dim3(d), dim3(256), 0, st, a, theta, b);
+    hipLaunchKernelGGL(k_center, dim3(d), dim3(kMeanThreads), 0, st, a, theta, b);
     hipLaunchKernelGGL(k_pack16_theta, dim3(L.npad / 256), dim3(256), 0, st, a, theta, b);
     return hipGetLastError();
 }
 
 hipError_t launch_operands16_batched(const BatchPlan& P, const ProblemDesc* descs, const float* theta, char* ws,
                                      hipStream_t st) {
-    if (P.n_ctr) hipLaunchKernelGGL(k_center_batched, dim3(P.n_ctr), dim3(256), 0, st, descs, P.ctr_work, theta, ws);
+    if (P.n_ctr)
+        hipLaunchKernelGGL(k_center_batched, dim3(P.n_ctr), dim3(kMeanThreads), 0, st, descs, P.ctr_work, theta, ws);
     if (P.n_row16)
         hipLaunchKernelGGL(k_pack16_theta_batched, dim3(P.n_row16), dim3(256), 0, st, descs, P.row16_work, theta, ws);
     return hipGetLastError();

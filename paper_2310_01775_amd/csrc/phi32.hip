@@ -56,20 +56,6 @@ __device__ __forceinline__ View32 view32(const SvgdLayout& L, char* base) {
     return v;
 }
 
-// ---- particle mean of coordinate l (one workgroup of 256) ----------------------
-__device__ void mean_body(int N, int l, const float* __restrict__ theta, float* __restrict__ ctr) {
-    __shared__ float red[256];
-    float s = 0.0f;
-    for (int i = threadIdx.x; i < N; i += 256) s += theta[(int64_t)l * N + i];
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) ctr[l] = red[0] / (float)N;
-}
-
 // ---- operands: 64 rows per 256 threads, lane group q = threadIdx.x / 64 takes
 // the coordinates l = 4 s + q (its MFMA lane group's values), so a thread's
 // stores of xr are contiguous and its loop is a quarter of the dimension.
@@ -245,8 +231,8 @@ struct One32 {
     SvgdLayout L;
 };
 
-__global__ __launch_bounds__(256) void k_mean(One32 a, const float* theta, char* ws) {
-    mean_body(a.N, blockIdx.x, theta, reinterpret_cast<float*>(ws + a.L.ctr_off));
+__global__ __launch_bounds__(kMeanThreads) void k_mean(One32 a, const float* theta, char* ws) {
+    particle_mean_body(a.N, blockIdx.x, theta, reinterpret_cast<float*>(ws + a.L.ctr_off));
 }
 
 __global__ __launch_bounds__(256) void k_pack32_x(One32 a, const float* theta, char* ws) {
@@ -285,11 +271,11 @@ __global__ __launch_bounds__(256) void k_reduce32(One32 a, const float* theta, c
 __device__ __forceinline__ char* base32(const ProblemDesc& D, char* ws) { return ws + D.svgd_off; }
 
 // entry = (problem, coordinate, -, -)
-__global__ __launch_bounds__(256) void k_mean_batched(const ProblemDesc* __restrict__ descs,
+__global__ __launch_bounds__(kMeanThreads) void k_mean_batched(const ProblemDesc* __restrict__ descs,
                                                       const int4* __restrict__ work, const float* theta, char* ws) {
     const int4 e = work[blockIdx.x];
     const ProblemDesc& D = descs[e.x];
-    mean_body(D.N, e.y, theta + D.theta_off, reinterpret_cast<float*>(base32(D, ws) + D.sv.ctr_off));
+    particle_mean_body(D.N, e.y, theta + D.theta_off, reinterpret_cast<float*>(base32(D, ws) + D.sv.ctr_off));
 }
 
 // entry = (problem, first row of a 256-row chunk, -, -)
@@ -394,7 +380,7 @@ hipError_t launch_operands32(int N, int d, const float* theta, int part, void* w
     One32 a{N, d, L};
     char* b = static_cast<char*>(ws);
     if (part == 0) {
-        hipLaunchKernelGGL(k_mean, dim3(d), dim3(256), 0, st, a, theta, b);
+        hipLaunchKernelGGL(k_mean, dim3(d), dim3(kMeanThreads), 0, st, a, theta, b);
         hipLaunchKernelGGL(k_pack32_x, dim3(L.npad / 64), dim3(256), 0, st, a, theta, b);
     } else {
         hipLaunchKernelGGL(k_pack32_v, dim3(L.npad / 64), dim3(256), 0, st, a, theta, b);
@@ -405,7 +391,8 @@ hipError_t launch_operands32(int N, int d, const float* theta, int part, void* w
 hipError_t launch_operands32_batched(const BatchPlan& P, const ProblemDesc* descs, const float* theta, int part,
                                      char* ws, hipStream_t st) {
     if (part == 0) {
-        if (P.n_ctr) hipLaunchKernelGGL(k_mean_batched, dim3(P.n_ctr), dim3(256), 0, st, descs, P.ctr_work, theta, ws);
+        if (P.n_ctr)
+            hipLaunchKernelGGL(k_mean_batched, dim3(P.n_ctr), dim3(kMeanThreads), 0, st, descs, P.ctr_work, theta, ws);
         if (P.n_row16)
             hipLaunchKernelGGL(k_pack32_x_batched, dim3(P.n_row16), dim3(256), 0, st, descs, P.row16_work, theta, ws);
     } else if (P.n_row16) {
