@@ -266,6 +266,8 @@ __device__ __forceinline__ float hw_rsq(float x) { return __builtin_amdgcn_rsqf(
 __device__ __forceinline__ float hw_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ float hw_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
 __device__ __forceinline__ float hw_log2(float x) { return __builtin_amdgcn_logf(x); }
+// min(max(x, 0), 1): becomes the clamp bit of the instruction producing x
+__device__ __forceinline__ float unit_clamp(float x) { return __builtin_amdgcn_fmed3f(x, 0.0f, 1.0f); }
 
 // ---- smooth penalty ---------------------------------------------------------
 // sp(z) = log(1 + exp(beta z)) / beta = max(z,0) + log1p(exp(-beta|z|)) / beta.

@@ -8,6 +8,10 @@
 //   x_i = theta_i - mean theta, x~_i = bf16(x_i)   (centring shrinks the Gram cancellation)
 //   D_ij = |x~_i|^2 + |x~_j|^2 - 2 x~_i . x~_j   (Gram on MFMA, FP32 accumulate)
 //   K_ij = exp(-max(D_ij, 0) / h)
+// with log2 K_ij = m (x~_i . x~_j + e_j + e_i), m = 2 log2(e) / h and
+// e = -|x~|^2 / 2: e_j enters as the Gram MFMA's accumulator input and the
+// rest is one fused multiply-add; the exponential's clamp to [0, 1] is the
+// max(D, 0).
 //   V_j = bf16[ g_j - (2/h) x_j | 1 | 0 ]
 //   A_i = sum_j bf16(K_ij) V_j                   (MFMA, FP32 accumulate)
 //   phi_i = (A_i[0..d) + (2/h) x_i A_i[d]) / N
@@ -16,7 +20,8 @@
 // Contraction tiling: a workgroup owns 256 rows (4 waves x 4 row tiles of 16)
 // and one column split; per 32 columns a wave issues, per row tile, two Gram
 // MFMAs (16x16x32) giving S^T for 2 x 16 columns, turns them into K in
-// registers and feeds K as the A operand of the K.V MFMAs.  The S^T output
+// registers (one multiply-add, one exponential per element, one conversion
+// per pair) and feeds K as the A operand of the K.V MFMAs.  The S^T output
 // layout (lane holds columns j = 4(l/16)+t of row l%16) is exactly an A
 // operand whose k index is permuted; V is stored chunk by chunk in that same
 // permuted order, so no data moves between the two products and every lane
@@ -38,7 +43,7 @@ typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f4;
 struct View16 {  // one problem's BF16-form workspace
     float* smp;
     float* ctr;
-    float* nrm;
+    float* nrm;  // e_i = -|x~_i|^2 / 2
     __bf16* xb;
     __bf16* vt;  // V by 32-particle chunk: [npad / 32][vc][32], particles in MFMA k order
     float* p16;
@@ -57,38 +62,55 @@ __device__ __forceinline__ View16 view16(const SvgdLayout& L, char* base) {
     return v;
 }
 
+// Layout of V within a 32-particle chunk q: column c occupies the 32 values
+// at (q vc + c) 32; lane group kq of the K.V MFMA holds k slots 8 kq ..
+// 8 kq + 7, which are the chunk's particles 4 kq .. 4 kq + 3 and then
+// 16 + 4 kq .. 16 + 4 kq + 3.
 
-// Position of particle i inside its 32-particle chunk of V: lane group kq of
-// the K.V MFMA holds k slots 8 kq .. 8 kq + 7 = particles 4 kq .. 4 kq + 3
-// and 16 + 4 kq .. 16 + 4 kq + 3 of the chunk.
-__device__ __forceinline__ int64_t vpos(int i, int c, int vc) {
-    const int q = i >> 5, r = i & 31;
-    const int kq = (r & 15) >> 2, s = (r & 3) + (r >= 16 ? 4 : 0);
-    return ((int64_t)q * vc + c) * 32 + 8 * kq + s;
-}
-
-// ---- operands (one thread per padded row): the x~ rows and their norms
-// depend on theta only and are built with the median; V needs g and h
-__device__ void pack16_theta_row(int N, int d, int kd, int i, const float* __restrict__ theta, const View16& w) {
-    float nrm = 0.0f;
-    for (int l = 0; l < kd; ++l) {
-        float x = 0.0f;
-        if (i < N && l < d) x = theta[(int64_t)l * N + i] - w.ctr[l];
-        const __bf16 xb = (__bf16)x;
-        const float xr = (float)xb;
-        nrm = fmaf(xr, xr, nrm);
-        w.xb[(int64_t)i * kd + l] = xb;
+// ---- operands, a workgroup per 256 padded rows: the x~ rows and their norms
+// depend on theta only and are built with the median; V needs g and h.
+// x~: a thread per (row, group of 8 coordinates) makes one 16-byte store; the
+// groups of a row sit in adjacent lanes and add their norms by exchange.
+__device__ void pack16_theta_rows(int N, int d, int kd, int row0, const float* __restrict__ theta,
+                                  const View16& w) {
+    const int groups = kd >> 3;  // 4 or 8: every thread takes the same number of steps
+    for (int o = threadIdx.x; o < 256 * groups; o += 256) {
+        const int i = row0 + o / groups, l0 = 8 * (o & (groups - 1));
+        bf16x8 xb;
+        float nrm = 0.0f;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int l = l0 + k;
+            float x = 0.0f;
+            if (i < N && l < d) x = theta[(int64_t)l * N + i] - w.ctr[l];
+            xb[k] = (__bf16)x;
+            const float xr = (float)xb[k];
+            nrm = fmaf(xr, xr, nrm);
+        }
+        *reinterpret_cast<bf16x8*>(w.xb + (int64_t)i * kd + l0) = xb;
+        for (int m = 1; m < groups; m <<= 1) nrm += __shfl_xor(nrm, m);
+        if (l0 == 0) w.nrm[i] = -0.5f * nrm;
     }
-    w.nrm[i] = nrm;
 }
 
-__device__ void pack16_v_row(int N, int d, int vc, int i, const float* __restrict__ theta,
-                             const float* __restrict__ g, const View16& w) {
+// V: a thread per (32-particle chunk, column, lane group kq) makes one
+// 16-byte store, the 8 values that lane group of the K.V product reads.
+__device__ void pack16_v_rows(int N, int d, int vc, int row0, const float* __restrict__ theta,
+                              const float* __restrict__ g, const View16& w) {
     const float c2 = 2.0f / w.sel->h;
-    for (int c = 0; c < vc; ++c) {
-        float v = 0.0f;
-        if (i < N) v = c < d ? fmaf(-c2, theta[(int64_t)c * N + i] - w.ctr[c], g[(int64_t)c * N + i]) : (c == d ? 1.0f : 0.0f);
-        w.vt[vpos(i, c, vc)] = (__bf16)v;
+    const int per = 4 * vc;  // stores per chunk
+    for (int o = threadIdx.x; o < 8 * per; o += 256) {
+        const int q = (row0 >> 5) + o / per, c = (o >> 2) % vc, kq = o & 3;
+        const float ctr = c < d ? w.ctr[c] : 0.0f;
+        bf16x8 v;
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+            const int i = 32 * q + 4 * kq + (s & 3) + (s >= 4 ? 16 : 0);
+            float x = 0.0f;
+            if (i < N) x = c < d ? fmaf(-c2, theta[(int64_t)c * N + i] - ctr, g[(int64_t)c * N + i]) : (c == d ? 1.0f : 0.0f);
+            v[s] = (__bf16)x;
+        }
+        *reinterpret_cast<bf16x8*>(w.vt + ((int64_t)q * vc + c) * 32 + 8 * kq) = v;
     }
 }
 
@@ -97,7 +119,7 @@ __device__ void pack16_v_row(int N, int d, int vc, int i, const float* __restric
 template <int KS, int OT>
 struct Chunk16 {
     bf16x8 xj[2][KS];  // A of the Gram: rows j = jc + 16 sub + (l % 16)
-    f4 nj[2];          // |x~_j|^2 for j = jc + 16 sub + 4 (l / 16) + t
+    f4 nj[2];          // e_j for j = jc + 16 sub + 4 (l / 16) + t: the Gram accumulator's start
     bf16x8 vb[OT];     // B of K.V: V[j][16 o + l % 16], j in the permuted order
 };
 
@@ -122,25 +144,19 @@ __device__ __forceinline__ void load_chunk(Chunk16<KD / 32, VC / 16>& c, const V
 // row tile overlaps the MFMAs still in flight for the next ones.
 template <int KD, int VC>
 __device__ __forceinline__ void chunk16_compute(const Chunk16<KD / 32, VC / 16>& cur, const bf16x8 (&xi)[4][KD / 32],
-                                                const float (&ni)[4], float c, float m2c, f4 (&acc)[4][VC / 16]) {
+                                                const float (&ni)[4], float m, f4 (&acc)[4][VC / 16]) {
     constexpr int KS = KD / 32;
     constexpr int OT = VC / 16;
-    f4 s[4][2];
+    f4 s[4][2];  // x~_i . x~_j + e_j
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-        s[r][0] = f4{0.f, 0.f, 0.f, 0.f};
-        s[r][1] = f4{0.f, 0.f, 0.f, 0.f};
+        s[r][0] = cur.nj[0];
+        s[r][1] = cur.nj[1];
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) {
             s[r][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cur.xj[0][ks], xi[r][ks], s[r][0], 0, 0, 0);
             s[r][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cur.xj[1][ks], xi[r][ks], s[r][1], 0, 0, 0);
         }
-    }
-    float cn[8];
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-        cn[t] = c * cur.nj[0][t];
-        cn[4 + t] = c * cur.nj[1][t];
     }
     bf16x8 ka[4];
 #pragma unroll
@@ -148,8 +164,8 @@ __device__ __forceinline__ void chunk16_compute(const Chunk16<KD / 32, VC / 16>&
         float kv[8];
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
-            kv[t] = hw_exp2(fminf(fmaf(m2c, s[r][0][t], ni[r] + cn[t]), 0.0f));
-            kv[4 + t] = hw_exp2(fminf(fmaf(m2c, s[r][1][t], ni[r] + cn[4 + t]), 0.0f));
+            kv[t] = unit_clamp(hw_exp2(fmaf(m, s[r][0][t], ni[r])));
+            kv[4 + t] = unit_clamp(hw_exp2(fmaf(m, s[r][1][t], ni[r])));
         }
         ka[r] = bf16x8{(__bf16)kv[0], (__bf16)kv[1], (__bf16)kv[2], (__bf16)kv[3],
                        (__bf16)kv[4], (__bf16)kv[5], (__bf16)kv[6], (__bf16)kv[7]};
@@ -167,8 +183,7 @@ __device__ void phi16_body(int npad, int row0, int j0, int j1, int split, const 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int col = lane & 15, kq = lane >> 4;
     const int rbase = row0 + wave * 64;
-    const float c = -1.44269504088896341f / w.sel->h;  // -log2(e) / h
-    const float m2c = -2.0f * c;
+    const float m = 2.0f * 1.44269504088896341f / w.sel->h;  // 2 log2(e) / h
     bf16x8 xi[4][KS];
     float ni[4];
 #pragma unroll
@@ -176,7 +191,7 @@ __device__ void phi16_body(int npad, int row0, int j0, int j1, int split, const 
         const int i = rbase + 16 * r + col;
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) xi[r][ks] = *reinterpret_cast<const bf16x8*>(w.xb + (int64_t)i * KD + 32 * ks + 8 * kq);
-        ni[r] = c * w.nrm[i];
+        ni[r] = m * w.nrm[i];
     }
     f4 acc[4][OT];
 #pragma unroll
@@ -189,7 +204,7 @@ __device__ void phi16_body(int npad, int row0, int j0, int j1, int split, const 
     load_chunk<KD, VC>(cur, w, npad, j0, col, kq);
     for (int jc = j0; jc < j1; jc += 32) {
         if (jc + 32 < j1) load_chunk<KD, VC>(nxt, w, npad, jc + 32, col, kq);
-        chunk16_compute<KD, VC>(cur, xi, ni, c, m2c, acc);
+        chunk16_compute<KD, VC>(cur, xi, ni, m, acc);
         cur = nxt;
     }
     float* out = w.p16 + (int64_t)split * VC * npad;
@@ -242,11 +257,11 @@ __global__ __launch_bounds__(kMeanThreads) void k_center(One16 a, const float* t
 }
 
 __global__ __launch_bounds__(256) void k_pack16_theta(One16 a, const float* theta, char* ws) {
-    pack16_theta_row(a.N, a.d, a.L.kd, blockIdx.x * 256 + threadIdx.x, theta, view16(a.L, ws));
+    pack16_theta_rows(a.N, a.d, a.L.kd, blockIdx.x * 256, theta, view16(a.L, ws));
 }
 
 __global__ __launch_bounds__(256) void k_pack16_v(One16 a, const float* theta, const float* g, char* ws) {
-    pack16_v_row(a.N, a.d, a.L.vc, blockIdx.x * 256 + threadIdx.x, theta, g, view16(a.L, ws));
+    pack16_v_rows(a.N, a.d, a.L.vc, blockIdx.x * 256, theta, g, view16(a.L, ws));
 }
 
 template <int KD, int VC>
@@ -292,7 +307,7 @@ __global__ __launch_bounds__(256) void k_pack16_theta_batched(const ProblemDesc*
     const int4 e = work[blockIdx.x];
     const ProblemDesc& D = descs[e.x];
     if (D.N < 2) return;
-    pack16_theta_row(D.N, D.d, D.sv.kd, e.y + threadIdx.x, theta + D.theta_off, view16(D.sv, base_of(D, ws)));
+    pack16_theta_rows(D.N, D.d, D.sv.kd, e.y, theta + D.theta_off, view16(D.sv, base_of(D, ws)));
 }
 
 __global__ __launch_bounds__(256) void k_pack16_v_batched(const ProblemDesc* __restrict__ descs,
@@ -301,8 +316,7 @@ __global__ __launch_bounds__(256) void k_pack16_v_batched(const ProblemDesc* __r
     const int4 e = work[blockIdx.x];
     const ProblemDesc& D = descs[e.x];
     if (D.N < 2) return;
-    pack16_v_row(D.N, D.d, D.sv.vc, e.y + threadIdx.x, theta + D.theta_off, grad + D.theta_off,
-                 view16(D.sv, base_of(D, ws)));
+    pack16_v_rows(D.N, D.d, D.sv.vc, e.y, theta + D.theta_off, grad + D.theta_off, view16(D.sv, base_of(D, ws)));
 }
 
 // entry = (problem, row block, split, -)

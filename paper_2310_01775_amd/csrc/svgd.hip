@@ -213,8 +213,11 @@ SvgdLayout svgd_workspace_layout(int N, int d) {
     L.kd = d < 32 ? 32 : 64;
     L.vc = d < 32 ? 32 : d < 64 ? 64 : 80;  // V = [g - (2/h) x | 1 | 0]: d + 1 columns, padded
     {
+        // one full round of resident workgroups (3 per CU at 32 Gram
+        // columns, 2 at 64: register bound), not a round and a partial one
+        const int resident = (L.kd == 32 ? 3 : 2) * 256;
         const int rowblocks = L.npad / kRows16;
-        int s16 = (1024 + rowblocks - 1) / rowblocks;
+        int s16 = (resident + rowblocks / 2) / rowblocks;
         if (s16 > L.npad / 128) s16 = L.npad / 128;
         if (s16 > 32) s16 = 32;
         if (s16 < 1) s16 = 1;
