@@ -125,7 +125,8 @@ struct StructKernel {
 };
 
 constexpr int kMedSample = 8192;  // distances drawn for the sampled median
-constexpr int kRows16 = 256;      // rows per workgroup of the BF16 contraction
+constexpr int kRows16 = 256;      // row padding unit of both matrix-core forms
+constexpr int kTile16 = 64;       // rows per workgroup of the BF16 contraction
 
 // One problem of a batched solve, resident in device memory.
 struct ProblemDesc {
@@ -218,8 +219,10 @@ struct UpdateArgs {
     int use_adam;
 };
 
-// den[0..1] for the workgroup, computed by thread 0 (call from every thread)
-__device__ __forceinline__ void update_denominators(const UpdateArgs& u, float* den) {
+// The bias-correction denominators den[0..1] of the workgroup: thread 0
+// computes them into LDS.  Every thread calls this, after issuing its element
+// loads, so that the counter's load and the powers overlap those loads.
+__device__ __forceinline__ void block_denominators(const UpdateArgs& u, float* den) {
     if (u.use_adam && threadIdx.x == 0) {
         const int t = u.t_dev ? u.t0 + *u.t_dev + 1 : u.t0;
         den[0] = 1.0f - powf(u.b1, (float)t);
@@ -228,19 +231,51 @@ __device__ __forceinline__ void update_denominators(const UpdateArgs& u, float* 
     __syncthreads();
 }
 
-__device__ __forceinline__ void update_elem(const UpdateArgs& u, const float* den, int64_t e, float f) {
+// The update of element e from its loaded theta, m and v (the loads can be
+// issued with the kernel's other loads).
+struct UpdateIn {
+    float theta, m, v;
+};
+__device__ __forceinline__ UpdateIn update_load(const UpdateArgs& u, int64_t e) {
+    UpdateIn in{u.theta[e], 0.0f, 0.0f};
+    if (u.use_adam) {
+        in.m = u.m[e];
+        in.v = u.v[e];
+    }
+    return in;
+}
+__device__ __forceinline__ void update_apply(const UpdateArgs& u, const float* den, int64_t e, const UpdateIn& in,
+                                             float f) {
     if (!u.use_adam) {
-        u.theta[e] = u.theta[e] + u.lr * f;
+        u.theta[e] = in.theta + u.lr * f;
         return;
     }
     const float gr = -f;
-    const float mm = u.b1 * u.m[e] + (1.0f - u.b1) * gr;
-    const float vv = u.b2 * u.v[e] + (1.0f - u.b2) * gr * gr;
+    const float mm = u.b1 * in.m + (1.0f - u.b1) * gr;
+    const float vv = u.b2 * in.v + (1.0f - u.b2) * gr * gr;
     u.m[e] = mm;
     u.v[e] = vv;
     const float mhat = mm / den[0];
     const float vhat = vv / den[1];
-    u.theta[e] = u.theta[e] - u.lr * mhat / (sqrtf(vhat) + u.eps);
+    u.theta[e] = in.theta - u.lr * mhat / (sqrtf(vhat) + u.eps);
+}
+
+// One element's direction r and, for the update, its index and loaded operands.
+struct ElemOut {
+    bool ok;
+    float r;
+    int64_t ue;
+    UpdateIn in;
+};
+// a single particle: phi = g
+// (the update's arguments by reference with a flag: a pointer to a kernel
+// argument would place the argument in scratch memory)
+__device__ __forceinline__ ElemOut pass_elem(const float* g, float* phi, int64_t e, const UpdateArgs& upd,
+                                             bool apply) {
+    ElemOut o{true, g[e], e, {}};
+    if (phi) phi[e] = o.r;
+    if (apply) o.in = update_load(upd, e);
+    return o;
 }
 
 // Phase k of a T-step, H-push rollout: steps [t_k, t_{k+1}), t_k = ceil(kT/H).

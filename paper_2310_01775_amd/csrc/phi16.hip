@@ -17,8 +17,12 @@
 //   phi_i = (A_i[0..d) + (2/h) x_i A_i[d]) / N
 // which is Eq. (1) with theta_i - theta_j = x_i - x_j.
 //
-// Contraction tiling: a workgroup owns 256 rows (4 waves x 4 row tiles of 16)
-// and one column split; per 32 columns a wave issues, per row tile, two Gram
+// Contraction tiling: a workgroup owns 64 rows (4 row tiles of 16) and one
+// column split, whose columns its 4 waves take in consecutive quarters (each
+// wave holds all 64 rows' operands); the waves' sums for those rows are added
+// through LDS in wave order before the split's partial is stored, so the
+// partials, and the reduce that reads them, are a quarter of what a
+// workgroup of 4 x 64 rows would write.  Per 32 columns a wave issues, per row tile, two Gram
 // MFMAs (16x16x32) giving S^T for 2 x 16 columns, turns them into K in
 // registers (one multiply-add, one exponential per element, one conversion
 // per pair) and feeds K as the A operand of the K.V MFMAs.  The S^T output
@@ -67,14 +71,16 @@ __device__ __forceinline__ View16 view16(const SvgdLayout& L, char* base) {
 // 8 kq + 7, which are the chunk's particles 4 kq .. 4 kq + 3 and then
 // 16 + 4 kq .. 16 + 4 kq + 3.
 
-// ---- operands, a workgroup per 256 padded rows: the x~ rows and their norms
+// ---- operands, a workgroup per 64 padded rows (blockIdx.y picks them within
+// a 256-row chunk, so the grid fills more of the chip): the x~ rows and their norms
 // depend on theta only and are built with the median; V needs g and h.
 // x~: a thread per (row, group of 8 coordinates) makes one 16-byte store; the
 // groups of a row sit in adjacent lanes and add their norms by exchange.
 __device__ void pack16_theta_rows(int N, int d, int kd, int row0, const float* __restrict__ theta,
                                   const View16& w) {
     const int groups = kd >> 3;  // 4 or 8: every thread takes the same number of steps
-    for (int o = threadIdx.x; o < 256 * groups; o += 256) {
+    row0 += 64 * blockIdx.y;
+    for (int o = threadIdx.x; o < 64 * groups; o += 256) {
         const int i = row0 + o / groups, l0 = 8 * (o & (groups - 1));
         bf16x8 xb;
         float nrm = 0.0f;
@@ -99,7 +105,8 @@ __device__ void pack16_v_rows(int N, int d, int vc, int row0, const float* __res
                               const float* __restrict__ g, const View16& w) {
     const float c2 = 2.0f / w.sel->h;
     const int per = 4 * vc;  // stores per chunk
-    for (int o = threadIdx.x; o < 8 * per; o += 256) {
+    row0 += 64 * blockIdx.y;
+    for (int o = threadIdx.x; o < 2 * per; o += 256) {
         const int q = (row0 >> 5) + o / per, c = (o >> 2) % vc, kq = o & 3;
         const float ctr = c < d ? w.ctr[c] : 0.0f;
         bf16x8 v;
@@ -180,9 +187,15 @@ template <int KD, int VC>
 __device__ void phi16_body(int npad, int row0, int j0, int j1, int split, const View16& w) {
     constexpr int KS = KD / 32;   // Gram k-steps
     constexpr int OT = VC / 16;   // output column tiles
+    __shared__ f4 red[3][4 * OT][64];  // waves 1..3's sums, as their lanes hold them
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int col = lane & 15, kq = lane >> 4;
-    const int rbase = row0 + wave * 64;
+    const int rbase = row0;
+    {  // this wave's quarter of the split (a multiple of 32 columns)
+        const int q = (j1 - j0) >> 2;
+        j0 += wave * q;
+        j1 = j0 + q;
+    }
     const float m = 2.0f * 1.44269504088896341f / w.sel->h;  // 2 log2(e) / h
     bf16x8 xi[4][KS];
     float ni[4];
@@ -201,12 +214,26 @@ __device__ void phi16_body(int npad, int row0, int j0, int j1, int split, const 
 
     // the next chunk's operands load while this one computes
     Chunk16<KS, OT> cur, nxt;
-    load_chunk<KD, VC>(cur, w, npad, j0, col, kq);
+    if (j0 < j1) load_chunk<KD, VC>(cur, w, npad, j0, col, kq);
     for (int jc = j0; jc < j1; jc += 32) {
         if (jc + 32 < j1) load_chunk<KD, VC>(nxt, w, npad, jc + 32, col, kq);
         chunk16_compute<KD, VC>(cur, xi, ni, m, acc);
         cur = nxt;
     }
+    if (wave > 0) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int o = 0; o < OT; ++o) red[wave - 1][r * OT + o][lane] = acc[r][o];
+    }
+    __syncthreads();
+    if (wave > 0) return;
+#pragma unroll
+    for (int u = 0; u < 3; ++u)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int o = 0; o < OT; ++o) acc[r][o] += red[u][r * OT + o][lane];
     float* out = w.p16 + (int64_t)split * VC * npad;
 #pragma unroll
     for (int r = 0; r < 4; ++r)
@@ -216,33 +243,43 @@ __device__ void phi16_body(int npad, int row0, int j0, int j1, int split, const 
 }
 
 // ---- phi from the split sums (fixed split order) ---------------------------
-// One thread per element (l, i); rows l and d of every split are summed with
-// 16 loads in flight.
-__device__ __forceinline__ float split_sum(const float* __restrict__ p, int64_t sstride, int splits) {
-    float s = 0.0f;
-    for (int q0 = 0; q0 < splits; q0 += 16) {
-        float v[16];
+// One thread per element (l, i) adds rows l and d of every split in split
+// order, eight loads in flight (indices clamped, so no load is predicated).
+__device__ __forceinline__ void split_sums(const float* __restrict__ pl, const float* __restrict__ pd,
+                                           int64_t sstride, int splits, float& sl, float& sd) {
+    sl = 0.0f;
+    sd = 0.0f;
+    for (int q0 = 0; q0 < splits; q0 += 4) {
+        float a[4], b[4];
 #pragma unroll
-        for (int u = 0; u < 16; ++u) v[u] = q0 + u < splits ? p[(q0 + u) * sstride] : 0.0f;
+        for (int u = 0; u < 4; ++u) {
+            const int64_t k = min(q0 + u, splits - 1) * sstride;
+            a[u] = pl[k];
+            b[u] = pd[k];
+        }
 #pragma unroll
-        for (int u = 0; u < 16; ++u) s += v[u];
+        for (int u = 0; u < 4; ++u)
+            if (q0 + u < splits) {
+                sl += a[u];
+                sd += b[u];
+            }
     }
-    return s;
 }
 
-// phi (stored when phi is not null) and, with upd, the update of Algorithm 1
-// on element uoff + l N + i
-__device__ void reduce16_elem(int N, int d, int npad, int vc, int splits, int l, int i, const float* theta, float* phi,
-                              const View16& w, uint32_t* status, const UpdateArgs* upd, const float* den,
-                              int64_t uoff) {
-    const int64_t sstride = (int64_t)vc * npad;
-    const float sv = split_sum(w.p16 + (int64_t)l * npad + i, sstride, splits);
-    const float s1 = split_sum(w.p16 + (int64_t)d * npad + i, sstride, splits);
+// phi (stored when phi is not null) and, with upd, the operands of the
+// update of Algorithm 1 on element uoff + l N + i
+__device__ ElemOut reduce16_elem(int N, int d, int npad, int vc, int splits, int l, int i, const float* theta,
+                                 float* phi, const View16& w, uint32_t* status, const UpdateArgs& upd, bool apply,
+                                 int64_t uoff) {
+    ElemOut o{true, 0.0f, uoff + (int64_t)l * N + i, {}};
+    if (apply) o.in = update_load(upd, o.ue);  // issued with the sums' loads
+    float sv, s1;
+    split_sums(w.p16 + (int64_t)l * npad + i, w.p16 + (int64_t)d * npad + i, (int64_t)vc * npad, splits, sv, s1);
     const float x = theta[(int64_t)l * N + i] - w.ctr[l];
-    const float r = fmaf(2.0f / w.sel->h * x, s1, sv) / (float)N;
-    if (phi) phi[(int64_t)l * N + i] = r;
-    if (status && !isfinite(r)) atomicOr(status, STAMP_STATUS_NONFINITE_PHI);
-    if (upd) update_elem(*upd, den, uoff + (int64_t)l * N + i, r);
+    o.r = fmaf(2.0f / w.sel->h * x, s1, sv) / (float)N;
+    if (phi) phi[(int64_t)l * N + i] = o.r;
+    if (status && !isfinite(o.r)) atomicOr(status, STAMP_STATUS_NONFINITE_PHI);
+    return o;
 }
 
 // ---- single-problem kernels -----------------------------------------------------
@@ -268,7 +305,7 @@ template <int KD, int VC>
 __global__ __launch_bounds__(256) void k_phi16(One16 a, char* ws) {
     const int split = blockIdx.y;
     const int j0 = split * a.L.chunk16, j1 = min(j0 + a.L.chunk16, a.L.npad);
-    phi16_body<KD, VC>(a.L.npad, blockIdx.x * kRows16, j0, j1, split, view16(a.L, ws));
+    phi16_body<KD, VC>(a.L.npad, blockIdx.x * kTile16, j0, j1, split, view16(a.L, ws));
 }
 
 // upd.use_adam < 0: no update
@@ -276,17 +313,17 @@ __global__ __launch_bounds__(256) void k_reduce16(One16 a, const float* theta, c
                                                   uint32_t* status, UpdateArgs upd) {
     __shared__ float den[2];
     const bool apply = upd.use_adam >= 0;
-    if (apply) update_denominators(upd, den);
     const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (e >= (int64_t)a.d * a.N) return;
-    const int l = (int)(e / a.N), i = (int)(e % a.N);
-    if (a.N == 1) {
-        if (phi) phi[e] = g[e];
-        if (apply) update_elem(upd, den, e, g[e]);
-        return;
+    ElemOut o{};
+    if (e < (int64_t)a.d * a.N) {
+        if (a.N == 1) o = pass_elem(g, phi, e, upd, apply);
+        else o = reduce16_elem(a.N, a.d, a.L.npad, a.L.vc, a.L.splits16, (int)e / a.N, (int)e % a.N, theta, phi,
+                               view16(a.L, ws), status, upd, apply, 0);
     }
-    reduce16_elem(a.N, a.d, a.L.npad, a.L.vc, a.L.splits16, l, i, theta, phi, view16(a.L, ws), status,
-                  apply ? &upd : nullptr, den, 0);
+    if (apply) {
+        block_denominators(upd, den);
+        if (o.ok) update_apply(upd, den, o.ue, o.in, o.r);
+    }
 }
 
 // ---- batched kernels (work-list entries as in svgd.hip) ---------------------------
@@ -326,7 +363,7 @@ __global__ __launch_bounds__(256) void k_phi16_batched(const ProblemDesc* __rest
     const int4 e = work[blockIdx.x];
     const ProblemDesc& D = descs[e.x];
     const int j0 = e.z * D.sv.chunk16, j1 = min(j0 + D.sv.chunk16, D.sv.npad);
-    phi16_body<KD, VC>(D.sv.npad, e.y * kRows16, j0, j1, e.z, view16(D.sv, base_of(D, ws)));
+    phi16_body<KD, VC>(D.sv.npad, e.y * kTile16, j0, j1, e.z, view16(D.sv, base_of(D, ws)));
 }
 
 // entry = (problem, first element, end element, -) of the problem's d*N block
@@ -336,19 +373,20 @@ __global__ __launch_bounds__(256) void k_reduce16_batched(const ProblemDesc* __r
                                                           UpdateArgs upd) {
     __shared__ float den[2];
     const bool apply = upd.use_adam >= 0;
-    if (apply) update_denominators(upd, den);
     const int4 w = work[blockIdx.x];
     const ProblemDesc& D = descs[w.x];
     const int64_t e = w.y + threadIdx.x;
-    if (e >= w.z) return;
-    if (D.N == 1) {
-        if (phi) phi[D.theta_off + e] = grad[D.theta_off + e];
-        if (apply) update_elem(upd, den, D.theta_off + e, grad[D.theta_off + e]);
-        return;
+    ElemOut o{};
+    if (e < w.z) {
+        if (D.N == 1) o = pass_elem(grad, phi, D.theta_off + e, upd, apply);
+        else o = reduce16_elem(D.N, D.d, D.sv.npad, D.sv.vc, D.sv.splits16, (int)e / D.N, (int)e % D.N,
+                               theta + D.theta_off, phi ? phi + D.theta_off : nullptr, view16(D.sv, base_of(D, ws)),
+                               status, upd, apply, D.theta_off);
     }
-    reduce16_elem(D.N, D.d, D.sv.npad, D.sv.vc, D.sv.splits16, (int)(e / D.N), (int)(e % D.N), theta + D.theta_off,
-                  phi ? phi + D.theta_off : nullptr, view16(D.sv, base_of(D, ws)), status, apply ? &upd : nullptr,
-                  den, D.theta_off);
+    if (apply) {
+        block_denominators(upd, den);
+        if (o.ok) update_apply(upd, den, o.ue, o.in, o.r);
+    }
 }
 
 }  // namespace
@@ -358,7 +396,7 @@ hipError_t launch_operands16(int N, int d, const float* theta, void* ws, const S
     One16 a{N, d, L, 0.0f};
     char* b = static_cast<char*>(ws);
     hipLaunchKernelGGL(k_center, dim3(d), dim3(kMeanThreads), 0, st, a, theta, b);
-    hipLaunchKernelGGL(k_pack16_theta, dim3(L.npad / 256), dim3(256), 0, st, a, theta, b);
+    hipLaunchKernelGGL(k_pack16_theta, dim3(L.npad / 256, 4), dim3(256), 0, st, a, theta, b);
     return hipGetLastError();
 }
 
@@ -367,7 +405,8 @@ hipError_t launch_operands16_batched(const BatchPlan& P, const ProblemDesc* desc
     if (P.n_ctr)
         hipLaunchKernelGGL(k_center_batched, dim3(P.n_ctr), dim3(kMeanThreads), 0, st, descs, P.ctr_work, theta, ws);
     if (P.n_row16)
-        hipLaunchKernelGGL(k_pack16_theta_batched, dim3(P.n_row16), dim3(256), 0, st, descs, P.row16_work, theta, ws);
+        hipLaunchKernelGGL(k_pack16_theta_batched, dim3(P.n_row16, 4), dim3(256), 0, st, descs, P.row16_work, theta,
+                           ws);
     return hipGetLastError();
 }
 
@@ -376,8 +415,8 @@ hipError_t launch_svgd16_direction(int N, int d, const float* theta, const float
     One16 a{N, d, L, 0.0f};
     char* b = static_cast<char*>(ws);
     if (N >= 2) {
-        hipLaunchKernelGGL(k_pack16_v, dim3(L.npad / 256), dim3(256), 0, st, a, theta, grad, b);
-        const dim3 grid(L.npad / kRows16, L.splits16);
+        hipLaunchKernelGGL(k_pack16_v, dim3(L.npad / 256, 4), dim3(256), 0, st, a, theta, grad, b);
+        const dim3 grid(L.npad / kTile16, L.splits16);
         if (L.kd == 32) hipLaunchKernelGGL((k_phi16<32, 32>), grid, dim3(256), 0, st, a, b);
         else if (L.vc == 64) hipLaunchKernelGGL((k_phi16<64, 64>), grid, dim3(256), 0, st, a, b);
         else hipLaunchKernelGGL((k_phi16<64, 80>), grid, dim3(256), 0, st, a, b);
@@ -411,7 +450,8 @@ hipError_t launch_svgd16_direction_batched(const BatchPlan& P, const ProblemDesc
                                            const float* grad, float* phi, char* ws, uint32_t* status,
                                            hipStream_t st, const UpdateArgs* upd) {
     if (P.n_row16)
-        hipLaunchKernelGGL(k_pack16_v_batched, dim3(P.n_row16), dim3(256), 0, st, descs, P.row16_work, theta, grad, ws);
+        hipLaunchKernelGGL(k_pack16_v_batched, dim3(P.n_row16, 4), dim3(256), 0, st, descs, P.row16_work, theta, grad,
+                           ws);
     // a solve's problems have d = 6H <= 48: V takes the padded dimension's width
     if (P.n_phi16[0])
         hipLaunchKernelGGL((k_phi16_batched<32, 32>), dim3(P.n_phi16[0]), dim3(256), 0, st, descs, P.phi16_work[0], ws);

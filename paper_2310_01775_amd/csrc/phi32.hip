@@ -195,11 +195,14 @@ __device__ void phi32_body(int N, int d, int row0, int j0, int j1, int split, in
 
 // ---- phi from the split sums (fixed split order) ----------------------------------
 // the coordinate's row and the row-sum row of every split, 16 loads in flight
-// phi (stored when phi is not null) and, with upd, the update of Algorithm 1
-// on the same element (theta read for x before the update writes it)
-__device__ void reduce32_elem(int N, int d, const SvgdLayout& L, int l, int i, const float* theta, float* phi,
-                              const View32& v, uint32_t* status, const UpdateArgs* upd, const float* den,
-                              int64_t uoff) {
+// phi (stored when phi is not null) and, with upd, the operands of the
+// update of Algorithm 1 on the same element (theta read for x before the
+// update writes it)
+__device__ ElemOut reduce32_elem(int N, int d, const SvgdLayout& L, int l, int i, const float* theta, float* phi,
+                                 const View32& v, uint32_t* status, const UpdateArgs& upd, bool apply,
+                                 int64_t uoff) {
+    ElemOut o{true, 0.0f, uoff + (int64_t)l * N + i, {}};
+    if (apply) o.in = update_load(upd, o.ue);  // issued with the sums' loads
     const int64_t sstride = (int64_t)16 * L.ot32 * L.npad;
     const float* pa = v.part + (int64_t)l * L.npad + i;
     const float* p1 = v.part + (int64_t)d * L.npad + i;
@@ -207,22 +210,23 @@ __device__ void reduce32_elem(int N, int d, const SvgdLayout& L, int l, int i, c
     for (int q0 = 0; q0 < L.splits32; q0 += 8) {
         float u[8], u1[8];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const bool ok = q0 + k < L.splits32;
-            u[k] = ok ? pa[(q0 + k) * sstride] : 0.0f;
-            u1[k] = ok ? p1[(q0 + k) * sstride] : 0.0f;
+        for (int k = 0; k < 8; ++k) {  // indices clamped: no load is predicated
+            const int64_t o = min(q0 + k, L.splits32 - 1) * sstride;
+            u[k] = pa[o];
+            u1[k] = p1[o];
         }
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            a += u[k];
-            a1 += u1[k];
-        }
+        for (int k = 0; k < 8; ++k)
+            if (q0 + k < L.splits32) {
+                a += u[k];
+                a1 += u1[k];
+            }
     }
     const float x = theta[(int64_t)l * N + i] - v.ctr[l];
-    const float r = fmaf(2.0f / v.sel->h * x, a1, a) / (float)N;
-    if (phi) phi[(int64_t)l * N + i] = r;
-    if (status && !isfinite(r)) atomicOr(status, STAMP_STATUS_NONFINITE_PHI);
-    if (upd) update_elem(*upd, den, uoff + (int64_t)l * N + i, r);
+    o.r = fmaf(2.0f / v.sel->h * x, a1, a) / (float)N;
+    if (phi) phi[(int64_t)l * N + i] = o.r;
+    if (status && !isfinite(o.r)) atomicOr(status, STAMP_STATUS_NONFINITE_PHI);
+    return o;
 }
 
 // ---- single-problem kernels -------------------------------------------------------
@@ -255,16 +259,17 @@ __global__ __launch_bounds__(256) void k_reduce32(One32 a, const float* theta, c
                                                   uint32_t* status, UpdateArgs upd) {
     __shared__ float den[2];
     const bool apply = upd.use_adam >= 0;
-    if (apply) update_denominators(upd, den);
     const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (e >= (int64_t)a.d * a.N) return;
-    if (a.N == 1) {
-        if (phi) phi[e] = g[e];
-        if (apply) update_elem(upd, den, e, g[e]);
-        return;
+    ElemOut o{};
+    if (e < (int64_t)a.d * a.N) {
+        if (a.N == 1) o = pass_elem(g, phi, e, upd, apply);
+        else o = reduce32_elem(a.N, a.d, a.L, (int)e / a.N, (int)e % a.N, theta, phi, view32(a.L, ws), status,
+                               upd, apply, 0);
     }
-    reduce32_elem(a.N, a.d, a.L, (int)(e / a.N), (int)(e % a.N), theta, phi, view32(a.L, ws), status,
-                  apply ? &upd : nullptr, den, 0);
+    if (apply) {
+        block_denominators(upd, den);
+        if (o.ok) update_apply(upd, den, o.ue, o.in, o.r);
+    }
 }
 
 // ---- batched kernels (work-list entries as in svgd.hip) ------------------------------
@@ -317,18 +322,20 @@ __global__ __launch_bounds__(256) void k_reduce32_batched(const ProblemDesc* __r
                                                           uint32_t* status, UpdateArgs upd) {
     __shared__ float den[2];
     const bool apply = upd.use_adam >= 0;
-    if (apply) update_denominators(upd, den);
     const int4 w = work[blockIdx.x];
     const ProblemDesc& D = descs[w.x];
     const int64_t e = w.y + threadIdx.x;
-    if (e >= w.z) return;
-    if (D.N == 1) {
-        if (phi) phi[D.theta_off + e] = grad[D.theta_off + e];
-        if (apply) update_elem(upd, den, D.theta_off + e, grad[D.theta_off + e]);
-        return;
+    ElemOut o{};
+    if (e < w.z) {
+        if (D.N == 1) o = pass_elem(grad, phi, D.theta_off + e, upd, apply);
+        else o = reduce32_elem(D.N, D.d, D.sv, (int)e / D.N, (int)e % D.N, theta + D.theta_off,
+                               phi ? phi + D.theta_off : nullptr, view32(D.sv, base32(D, ws)), status,
+                               upd, apply, D.theta_off);
     }
-    reduce32_elem(D.N, D.d, D.sv, (int)(e / D.N), (int)(e % D.N), theta + D.theta_off, phi ? phi + D.theta_off : nullptr,
-                  view32(D.sv, base32(D, ws)), status, apply ? &upd : nullptr, den, D.theta_off);
+    if (apply) {
+        block_denominators(upd, den);
+        if (o.ok) update_apply(upd, den, o.ue, o.in, o.r);
+    }
 }
 
 // (ks, ot) of each class, in the order of phi32_class

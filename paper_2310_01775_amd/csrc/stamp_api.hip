@@ -252,7 +252,7 @@ void build_plan(int n, const stamp_scene* scenes, const int32_t* N, int K, float
         if (D.N >= 2) {
             for (int l = 0; l < D.d; ++l) P.ctr_work.push_back(make_int4(p, l, 0, 0));
             const int c16 = D.sv.kd == 32 ? 0 : 1;
-            for (int rb = 0; rb < D.sv.npad / kRows16; ++rb)
+            for (int rb = 0; rb < D.sv.npad / kTile16; ++rb)
                 for (int q = 0; q < D.sv.splits16; ++q) P.phi16_work[c16].push_back(make_int4(p, rb, q, 0));
         }
         const int64_t ne = (int64_t)D.d * D.N;

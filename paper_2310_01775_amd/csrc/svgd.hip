@@ -115,9 +115,11 @@ __global__ __launch_bounds__(256) void k_dsvgd_weights_batched(const ProblemDesc
 
 __global__ __launch_bounds__(256) void k_update(int64_t n, const float* __restrict__ phi, UpdateArgs u) {
     __shared__ float den[2];
-    update_denominators(u, den);
     const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (e < n) update_elem(u, den, e, phi[e]);
+    ElemOut o{};
+    if (e < n) o = pass_elem(phi, nullptr, e, u, true);
+    block_denominators(u, den);
+    if (o.ok) update_apply(u, den, o.ue, o.in, o.r);
 }
 
 __global__ void k_modes(int N, int H, const float* __restrict__ theta, int32_t* __restrict__ modes) {
@@ -214,14 +216,15 @@ SvgdLayout svgd_workspace_layout(int N, int d) {
     L.vc = d < 32 ? 32 : d < 64 ? 64 : 80;  // V = [g - (2/h) x | 1 | 0]: d + 1 columns, padded
     {
         // one full round of resident workgroups (3 per CU at 32 Gram
-        // columns, 2 at 64: register bound), not a round and a partial one
+        // columns, 2 at 64: register bound), not a round and a partial one;
+        // a split gives each of its workgroup's 4 waves at least 32 columns
         const int resident = (L.kd == 32 ? 3 : 2) * 256;
-        const int rowblocks = L.npad / kRows16;
+        const int rowblocks = L.npad / kTile16;
         int s16 = (resident + rowblocks / 2) / rowblocks;
         if (s16 > L.npad / 128) s16 = L.npad / 128;
         if (s16 > 32) s16 = 32;
         if (s16 < 1) s16 = 1;
-        const int chunk = ((L.npad + s16 - 1) / s16 + 31) / 32 * 32;
+        const int chunk = ((L.npad + s16 - 1) / s16 + 127) / 128 * 128;
         L.splits16 = (L.npad + chunk - 1) / chunk;
         L.chunk16 = chunk;
     }
