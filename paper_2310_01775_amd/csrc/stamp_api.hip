@@ -28,8 +28,7 @@ struct stamp_ctx {
     std::string err;
     hipStream_t stream = nullptr;  // library stream: solves are captured and replayed here
     hipStream_t side = nullptr;    // the bandwidth stage runs here, beside the rollout
-    hipStream_t side2 = nullptr;   // the BF16 form's theta operands, beside its sampled median
-    hipEvent_t ev_in = nullptr, ev_out = nullptr, ev_fork = nullptr, ev_join = nullptr, ev_join2 = nullptr;
+    hipEvent_t ev_in = nullptr, ev_out = nullptr, ev_fork = nullptr, ev_join = nullptr;
     std::map<std::string, StampTune> tune;  // autotune cache, keyed by batch signature
     int autotune = 1;
     StampTune pinned;                        // used when pinned.roll_block > 0
@@ -365,12 +364,10 @@ int32_t stamp_create(stamp_ctx** ctx, int32_t device) {
     // default-priority stream of our own: solves are captured into graphs here
     if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess ||
         hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
-        hipStreamCreateWithFlags(&c->side2, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&c->ev_join2, hipEventDisableTiming) != hipSuccess) {
+        hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
         delete c;
         return STAMP_EHIP;
     }
@@ -388,11 +385,8 @@ void stamp_destroy(stamp_ctx* ctx) {
     if (ctx->ev_out) (void)hipEventDestroy(ctx->ev_out);
     if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
     if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
-    if (ctx->ev_join2) (void)hipEventDestroy(ctx->ev_join2);
     if (ctx->side) (void)hipStreamSynchronize(ctx->side);
     if (ctx->side) (void)hipStreamDestroy(ctx->side);
-    if (ctx->side2) (void)hipStreamSynchronize(ctx->side2);
-    if (ctx->side2) (void)hipStreamDestroy(ctx->side2);
     if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
 }
@@ -886,36 +880,23 @@ static int32_t solve_impl(stamp_ctx* ctx, int32_t n_problems, const stamp_scene*
         }
         return hipSuccess;
     };
-    // The BF16 form's sampled median and its theta operands are independent:
-    // they take one side stream each (the FP32 form's operands feed its median,
-    // so they share one).
     // fork_at marks the point the bandwidth stage depends on; branch launches
-    // it (after the main stream's next work when that should lead the graph)
-    bool split_sides = false;
+    // it on the side stream (after the main stream's next work when that work
+    // should lead the graph).  One side stream only: every stream a process
+    // creates takes one of its few hardware queues, and two streams sharing a
+    // queue run one after the other.
     auto fork_at = [&]() -> hipError_t { return hipEventRecord(ctx->ev_fork, st); };
     auto branch = [&](int exact) -> hipError_t {
         hipError_t r;
-        split_sides = !exact && skern.empty();
         if ((r = hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0)) != hipSuccess) return r;
-        if (split_sides) {
-            if ((r = hipStreamWaitEvent(ctx->side2, ctx->ev_fork, 0)) != hipSuccess) return r;
-            if ((r = launch_median_batched(B, d_desc, theta, 0, d_svgd, ctx->side)) != hipSuccess) return r;
-            if ((r = launch_operands16_batched(B, d_desc, theta, d_svgd, ctx->side2)) != hipSuccess) return r;
-            if ((r = hipEventRecord(ctx->ev_join2, ctx->side2)) != hipSuccess) return r;
-        } else if ((r = bandwidth_stage(ctx->side, exact)) != hipSuccess) {
-            return r;
-        }
+        if ((r = bandwidth_stage(ctx->side, exact)) != hipSuccess) return r;
         return hipEventRecord(ctx->ev_join, ctx->side);
     };
     auto fork = [&](int exact) -> hipError_t {
         hipError_t r = fork_at();
         return r == hipSuccess ? branch(exact) : r;
     };
-    auto join = [&]() -> hipError_t {
-        hipError_t r = hipStreamWaitEvent(st, ctx->ev_join, 0);
-        if (r == hipSuccess && split_sides) r = hipStreamWaitEvent(st, ctx->ev_join2, 0);
-        return r;
-    };
+    auto join = [&]() -> hipError_t { return hipStreamWaitEvent(st, ctx->ev_join, 0); };
     const UpdateArgs upd{theta, adam_m, adam_v, cfg->t0, d_ctr, cfg->lr, cfg->beta1, cfg->beta2, cfg->adam_eps,
                          cfg->use_adam};
     auto direction_stage = [&](const float* wts) -> hipError_t {
