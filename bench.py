@@ -47,7 +47,7 @@ def rollout_bytes(N, d, B, T, H):
 
 
 KERNEL_SOURCES = ["paper_2310_01775_amd/csrc/rollout.hip", "paper_2310_01775_amd/csrc/common.h"]
-PROFILE = os.path.join(ROOT, "profiles", "rollout_cfg2_counters.md")
+PROFILE = os.path.join(ROOT, "profiles", "rollout_n1024_counters.md")
 
 
 def kernel_source_hash():

@@ -15,8 +15,10 @@ def pytest_configure(config):
 
 @pytest.fixture(scope="session", autouse=True)
 def _torch_threads():
+    # the oracle's problems are small: its many small tensor ops run fastest
+    # (and parallel test workers do not oversubscribe the cores) on one thread
     import torch
-    torch.set_num_threads(min(8, os.cpu_count() or 1))
+    torch.set_num_threads(1)
 
 
 @pytest.fixture(scope="session")
