@@ -33,15 +33,21 @@ struct stamp_ctx {
     int autotune = 1;
     StampTune pinned;                        // used when pinned.roll_block > 0
     int is_pinned = 0;
-    // the last instantiated iteration graph and the solve it belongs to
-    hipGraphExec_t graph = nullptr;
-    std::string graph_key;
-    // the same for the surrogate-phase iteration
-    hipGraphExec_t graph_sur = nullptr;
-    std::string graph_sur_key;
-    // the same for the SGD refinement iteration
-    hipGraphExec_t graph_sgd = nullptr;
-    std::string graph_sgd_key;
+    // The last instantiated graphs of each iteration kind (SVGD, surrogate
+    // phase, SGD refinement) and the solve they belong to: one iteration, and
+    // kGraphUnroll iterations in one graph (consecutive launches of a graph
+    // leave a gap of several microseconds on the queue; inside one graph the
+    // iterations follow each other directly).
+    struct IterGraphs {
+        hipGraphExec_t one = nullptr, many = nullptr;
+        std::string key_one, key_many;
+        void destroy() {
+            if (one) (void)hipGraphExecDestroy(one);
+            if (many) (void)hipGraphExecDestroy(many);
+            one = many = nullptr;
+        }
+    };
+    IterGraphs g_svgd, g_sur, g_sgd;
 };
 
 namespace stamp {
@@ -168,6 +174,7 @@ bool scene_ok(const stamp_scene* s) {
            s->M == kModes;
 }
 
+constexpr int kGraphUnroll = 4;  // iterations per unrolled graph
 constexpr int kMaxSvgdDim = 64;
 constexpr int kMaxSvgdN = 65536;
 
@@ -378,9 +385,9 @@ int32_t stamp_create(stamp_ctx** ctx, int32_t device) {
 void stamp_destroy(stamp_ctx* ctx) {
     if (!ctx) return;
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
-    if (ctx->graph) (void)hipGraphExecDestroy(ctx->graph);
-    if (ctx->graph_sur) (void)hipGraphExecDestroy(ctx->graph_sur);
-    if (ctx->graph_sgd) (void)hipGraphExecDestroy(ctx->graph_sgd);
+    ctx->g_svgd.destroy();
+    ctx->g_sur.destroy();
+    ctx->g_sgd.destroy();
     if (ctx->ev_in) (void)hipEventDestroy(ctx->ev_in);
     if (ctx->ev_out) (void)hipEventDestroy(ctx->ev_out);
     if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
@@ -1025,6 +1032,28 @@ static int32_t solve_impl(stamp_ctx* ctx, int32_t n_problems, const stamp_scene*
         have_key = key;
         return STAMP_OK;
     };
+    // `count` iterations of `body`: the unrolled graph as often as it fits,
+    // the one-iteration graph for the rest
+    auto run_iterations = [&](stamp_ctx::IterGraphs& G, const std::string& key, int count, auto&& body) -> int32_t {
+        if (count >= kGraphUnroll) {
+            int32_t r = ensure_graph(G.many, G.key_many, key + "|unrolled", [&]() -> hipError_t {
+                for (int u = 0; u < kGraphUnroll; ++u) {
+                    const hipError_t e2 = body();
+                    if (e2 != hipSuccess) return e2;
+                }
+                return hipSuccess;
+            });
+            if (r) return r;
+        }
+        if (count % kGraphUnroll) {
+            int32_t r = ensure_graph(G.one, G.key_one, key, body);
+            if (r) return r;
+        }
+        int it = 0;
+        for (; it + kGraphUnroll <= count; it += kGraphUnroll) STAMP_TRY(hipGraphLaunch(G.many, st), "graph launch");
+        for (; it < count; ++it) STAMP_TRY(hipGraphLaunch(G.one, st), "graph launch");
+        return STAMP_OK;
+    };
     STAMP_TRY(launch_fill_u32((uint32_t*)d_ctr, 0u, 1, st), "counter");
     if (solve_time_us)
         for (int p = 0; p < n_problems; ++p) STAMP_TRY(launch_clock(d_clk + 2 * p, st), "clock");
@@ -1042,14 +1071,13 @@ static int32_t solve_impl(stamp_ctx* ctx, int32_t n_problems, const stamp_scene*
             snprintf(skey, sizeof skey, "%.9g/%.9g/%.9g;", w[p].bound, w[p].o_max, w[p].d_max);
             sk += skey;
         }
-        int32_t r = ensure_graph(ctx->graph_sur, ctx->graph_sur_key, sk, sur_iteration);
-        if (r) return r;
         float* d_err = (float*)(ws + P.err_off);
         float* c_true = (float*)(ws + P.cost_off);
         std::vector<float> h_err(n_problems);
         while (run < s_iters) {
             const int chunk = sur->check_every > 0 ? std::min(sur->check_every, s_iters - run) : s_iters - run;
-            for (int it = 0; it < chunk; ++it) STAMP_TRY(hipGraphLaunch(ctx->graph_sur, st), "graph launch");
+            int32_t r = run_iterations(ctx->g_sur, sk, chunk, sur_iteration);
+            if (r) return r;
             run += chunk;
             STAMP_TRY(launch_rollout_fwd_batched(d_desc, d_roll, ntiles, tune.roll_block, rgrid, theta, c_true,
                                                  nullptr, status, st),
@@ -1075,14 +1103,12 @@ static int32_t solve_impl(stamp_ctx* ctx, int32_t n_problems, const stamp_scene*
         rep->log_err = last_err;
     }
     if (cfg->iters - run > 0) {
-        int32_t r = ensure_graph(ctx->graph, ctx->graph_key, full_key, iteration);
+        int32_t r = run_iterations(ctx->g_svgd, full_key, cfg->iters - run, iteration);
         if (r) return r;
-        for (int it = run; it < cfg->iters; ++it) STAMP_TRY(hipGraphLaunch(ctx->graph, st), "graph launch");
     }
     if (cfg->sgd_iters > 0) {  // refinement: the step counter runs on
-        int32_t r = ensure_graph(ctx->graph_sgd, ctx->graph_sgd_key, full_key, sgd_iteration);
+        int32_t r = run_iterations(ctx->g_sgd, full_key, cfg->sgd_iters, sgd_iteration);
         if (r) return r;
-        for (int it = 0; it < cfg->sgd_iters; ++it) STAMP_TRY(hipGraphLaunch(ctx->graph_sgd, st), "graph launch");
     }
     // final true cost and discrete plan of every particle
     STAMP_TRY(launch_rollout_fwd_batched(d_desc, d_roll, ntiles, tune.roll_block, rgrid, theta, cost_out, nullptr,
