@@ -106,12 +106,12 @@ __device__ __forceinline__ MedView med_view(int N, int d, float fixed_h, const S
 }
 
 // Sample slot t: pair t of the row-major enumeration of i < j when all pairs
-// fit (N <= 128), else a hashed pair i != j; +inf beyond the sample.
-__device__ float sample_dist(int N, int d, int t, const float* __restrict__ theta) {
+// fit (N <= 128), else a hashed pair i != j (oriented i < j, as in the
+// all-pairs passes); false beyond the sample.
+__device__ bool sample_pair(int N, int t, int& i, int& j) {
     const uint64_t P = pair_count(N);
     const bool all = P <= (uint64_t)kMedSample;
-    if (N < 2 || (all && (uint64_t)t >= P)) return __int_as_float(0x7f800000);
-    int i, j;
+    if (N < 2 || (all && (uint64_t)t >= P)) return false;
     if (all) {
         int r = t;
         i = 0;
@@ -124,34 +124,46 @@ __device__ float sample_dist(int N, int d, int t, const float* __restrict__ thet
         i = (int)(mix32(2u * (uint32_t)t + 1u) % (uint32_t)N);
         j = (int)(mix32((2u * (uint32_t)t + 2u) ^ 0x9e3779b9u) % (uint32_t)(N - 1));
         if (j >= i) ++j;
-        if (j < i) {  // orientation i < j, as in the all-pairs passes
+        if (j < i) {
             const int x = i;
             i = j;
             j = x;
         }
     }
-    const float* ti = theta + i;
-    const float* tj = theta + j;
+    return true;
+}
+
+// Slot t's squared distance (+inf beyond the sample), by the four lanes q of
+// a DPP quad: lane q adds coordinates q, q + 4, q + 8, ... in order (eight
+// gathers of each particle in flight, indices clamped so no load is
+// predicated) and the quad adds its four sums as (s0 + s1) + (s2 + s3).  The
+// random gathers are what a sample slot costs; four lanes per slot put four
+// times the waves on them.  Every lane of the quad must call this.
+__device__ float sample_dist4(int N, int d, int t, int q, const float* __restrict__ theta) {
+    int i = 0, j = 0;
+    const bool ok = sample_pair(N, t, i, j);
     float acc = 0.0f;
-    int l = 0;
-    for (; l + 8 <= d; l += 8) {  // 16 loads in flight
-        float a[8], b[8];
+    if (ok) {
+        const float* ti = theta + i;
+        const float* tj = theta + j;
+        for (int l0 = 0; l0 < d; l0 += 32) {
+            float a[8], b[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            a[u] = ti[(int64_t)(l + u) * N];
-            b[u] = tj[(int64_t)(l + u) * N];
-        }
+            for (int u = 0; u < 8; ++u) {
+                const int64_t o = (int64_t)min(l0 + q + 4 * u, d - 1) * N;
+                a[u] = ti[o];
+                b[u] = tj[o];
+            }
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const float df = a[u] - b[u];
-            acc = fmaf(df, df, acc);
+            for (int u = 0; u < 8; ++u)
+                if (l0 + q + 4 * u < d) {
+                    const float df = a[u] - b[u];
+                    acc = fmaf(df, df, acc);
+                }
         }
     }
-    for (; l < d; ++l) {
-        const float df = ti[(int64_t)l * N] - tj[(int64_t)l * N];
-        acc = fmaf(df, df, acc);
-    }
-    return acc;
+    const float s = quad_sum(acc);
+    return ok ? s : __int_as_float(0x7f800000);
 }
 
 __device__ __forceinline__ void set_bandwidth(SelState* sel, int N, uint32_t m2_bits, float* h_out) {
@@ -388,8 +400,7 @@ __device__ void sample_select_body(const MedView& v, int exact, float* h_out) {
 // 256 threads: ROWS rows and 256 / ROWS column groups (a 64-row item gives each
 // wave a quarter of the columns, so small problems still fill the chip).  A
 // thread measures four columns at a time (four independent FMA chains, 16-byte
-// LDS broadcasts); each distance is summed over the coordinates in order, as
-// in the sample.
+// LDS broadcasts); each distance is summed over the coordinates in order.
 template <int DP, int ROWS>
 __device__ void med_item(const MedView& v, const float* __restrict__ theta, int rb, int cc) {
     constexpr int NT = 256;
@@ -929,10 +940,12 @@ struct OneMed {
     char* ws;
 };
 
+// four lanes per sample slot
 __global__ __launch_bounds__(256) void k_med_dist(OneMed a, const float* theta) {
     if (a.N < 2 || a.fixed_h > 0.0f) return;
-    const int t = blockIdx.x * 256 + threadIdx.x;
-    med_view(a.N, a.d, a.fixed_h, a.L, a.ws).smp[t] = sample_dist(a.N, a.d, t, theta);
+    const int t = blockIdx.x * 64 + (threadIdx.x >> 2), q = threadIdx.x & 3;
+    const float v = sample_dist4(a.N, a.d, t, q, theta);
+    if (q == 0) med_view(a.N, a.d, a.fixed_h, a.L, a.ws).smp[t] = v;
 }
 
 __global__ __launch_bounds__(kSelThreads) void k_sample_select(OneMed a, int exact, float* h_out) {
@@ -966,13 +979,14 @@ __device__ __forceinline__ MedView med_of(const ProblemDesc& D, char* ws) {
     return med_view(D.N, D.d, D.fixed_h, D.sv, ws + D.svgd_off);
 }
 
-// grid (kMedSample / 256, problems)
+// grid (kMedSample / 64, problems): four lanes per sample slot
 __global__ __launch_bounds__(256) void k_med_dist_batched(const ProblemDesc* __restrict__ descs, const float* theta,
                                                           char* ws) {
     const ProblemDesc& D = descs[blockIdx.y];
     if (D.N < 2 || D.fixed_h > 0.0f) return;
-    const int t = blockIdx.x * 256 + threadIdx.x;
-    med_of(D, ws).smp[t] = sample_dist(D.N, D.d, t, theta + D.theta_off);
+    const int t = blockIdx.x * 64 + (threadIdx.x >> 2), q = threadIdx.x & 3;
+    const float v = sample_dist4(D.N, D.d, t, q, theta + D.theta_off);
+    if (q == 0) med_of(D, ws).smp[t] = v;
 }
 
 __global__ __launch_bounds__(kSelThreads) void k_sample_select_batched(const ProblemDesc* __restrict__ descs, char* ws,
@@ -1089,7 +1103,7 @@ void launch_items_batched(const BatchPlan& P, const ProblemDesc* descs, const fl
 hipError_t launch_median(int N, int d, const float* theta, float bandwidth, int exact, void* ws, const SvgdLayout& L,
                          float* h_out, hipStream_t st, int gram) {
     OneMed a{N, d, bandwidth > 0.0f ? bandwidth : 0.0f, L, static_cast<char*>(ws)};
-    hipLaunchKernelGGL(k_med_dist, dim3(kMedSample / 256), dim3(256), 0, st, a, theta);
+    hipLaunchKernelGGL(k_med_dist, dim3(kMedSample / 64), dim3(256), 0, st, a, theta);
     hipLaunchKernelGGL(k_sample_select, dim3(1), dim3(kSelThreads), 0, st, a, exact, h_out);
     if (exact && N >= 2 && !(bandwidth > 0.0f) && pair_count(N) > (uint64_t)kMedSample) {
         // pass 0; small problems keep direct differences, whose every-pair
@@ -1115,7 +1129,7 @@ hipError_t launch_median(int N, int d, const float* theta, float bandwidth, int 
 hipError_t launch_median_batched(const BatchPlan& P, const ProblemDesc* descs, const float* theta, int exact,
                                  char* ws, hipStream_t st) {
     const int np = P.n_problems;
-    hipLaunchKernelGGL(k_med_dist_batched, dim3(kMedSample / 256, np), dim3(256), 0, st, descs, theta, ws);
+    hipLaunchKernelGGL(k_med_dist_batched, dim3(kMedSample / 64, np), dim3(256), 0, st, descs, theta, ws);
     hipLaunchKernelGGL(k_sample_select_batched, dim3(np), dim3(kSelThreads), 0, st, descs, ws, exact);
     if (exact && P.n_dist) {
         auto items = [&]() { launch_items_batched(P, descs, theta, ws, st); };
