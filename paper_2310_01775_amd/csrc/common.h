@@ -185,8 +185,10 @@ struct BatchPlan {
 // kMeanThreads: four independent partial sums per thread keep four loads in
 // flight; a fixed tree adds the threads' sums (same order on every launch).
 constexpr int kMeanThreads = 1024;
+template <int NT = kMeanThreads>
 __device__ __forceinline__ void particle_mean_body(int N, int l, const float* __restrict__ theta,
                                                    float* __restrict__ ctr) {
+    constexpr int kMeanThreads = NT;
     __shared__ float red[kMeanThreads];
     const float* t = theta + (int64_t)l * N;
     float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, s3 = 0.0f;

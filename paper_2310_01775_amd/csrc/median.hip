@@ -36,6 +36,7 @@
 // Sampled path: the bandwidth from the sample's own lower median.
 #include <math.h>
 
+#include "bf16_operands.h"
 #include "common.h"
 #include "internal.h"
 
@@ -994,6 +995,47 @@ __global__ __launch_bounds__(kSelThreads) void k_sample_select_batched(const Pro
     sample_select_body(med_of(descs[blockIdx.x], ws), exact, nullptr);
 }
 
+// The BF16 form's bandwidth stage in two launches.  First: blocks below
+// nd = (kMedSample / 64) x problems gather the sample distances (four lanes a
+// slot), the rest take one entry (problem, coordinate) of the centre list
+// each.  Second: blocks below the problem count select the sample median,
+// the rest build the centred BF16 rows of one entry (problem, 256-row chunk)
+// of the row list, a quarter per 256 threads.
+__global__ __launch_bounds__(256) void k_bw16_gather_batched(const ProblemDesc* __restrict__ descs,
+                                                             const int4* __restrict__ ctr_work, int nd,
+                                                             const float* theta, char* ws) {
+    constexpr int per = kMedSample / 64;
+    if ((int)blockIdx.x < nd) {
+        const ProblemDesc& D = descs[blockIdx.x / per];
+        if (D.N < 2 || D.fixed_h > 0.0f) return;
+        const int t = (blockIdx.x % per) * 64 + (threadIdx.x >> 2), q = threadIdx.x & 3;
+        const float v = sample_dist4(D.N, D.d, t, q, theta + D.theta_off);
+        if (q == 0) med_of(D, ws).smp[t] = v;
+        return;
+    }
+    const int4 e = ctr_work[blockIdx.x - nd];
+    const ProblemDesc& D = descs[e.x];
+    particle_mean_body<kCentreThreads>(D.N, e.y, theta + D.theta_off,
+                                       reinterpret_cast<float*>(ws + D.svgd_off + D.sv.ctr_off));
+}
+
+__global__ __launch_bounds__(kSelThreads) void k_bw16_select_batched(const ProblemDesc* __restrict__ descs,
+                                                                     const int4* __restrict__ row_work, int np,
+                                                                     const float* theta, char* ws) {
+    if ((int)blockIdx.x < np) {
+        sample_select_body(med_of(descs[blockIdx.x], ws), 0, nullptr);
+        return;
+    }
+    static_assert(kSelThreads == 1024, "four 256-thread quarters per row chunk");
+    const int4 e = row_work[blockIdx.x - np];
+    const ProblemDesc& D = descs[e.x];
+    if (D.N < 2) return;
+    char* b = ws + D.svgd_off;
+    pack16_theta_rows(D.N, D.d, D.sv.kd, e.y + 64 * (threadIdx.x >> 8), threadIdx.x & 255, theta + D.theta_off,
+                      reinterpret_cast<const float*>(b + D.sv.ctr_off), reinterpret_cast<__bf16*>(b + D.sv.xb_off),
+                      reinterpret_cast<float*>(b + D.sv.nrm_off));
+}
+
 // entry = (problem, row block, column chunk, -) of this item shape's work list
 template <int DP, int ROWS>
 __global__ __launch_bounds__(256) void k_med_items_batched(const ProblemDesc* __restrict__ descs,
@@ -1123,6 +1165,15 @@ hipError_t launch_median(int N, int d, const float* theta, float bandwidth, int 
             hipLaunchKernelGGL(k_med_select, dim3(1), dim3(256), 0, st, a, h_out);
         }
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_bandwidth16_batched(const BatchPlan& P, const ProblemDesc* descs, const float* theta, char* ws,
+                                      hipStream_t st) {
+    const int np = P.n_problems, nd = (kMedSample / 64) * np;
+    hipLaunchKernelGGL(k_bw16_gather_batched, dim3(nd + P.n_ctr), dim3(256), 0, st, descs, P.ctr_work, nd, theta, ws);
+    hipLaunchKernelGGL(k_bw16_select_batched, dim3(np + P.n_row16), dim3(kSelThreads), 0, st, descs, P.row16_work, np,
+                       theta, ws);
     return hipGetLastError();
 }
 

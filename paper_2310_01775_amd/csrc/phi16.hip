@@ -33,6 +33,7 @@
 // to the 16-column tile: 32 for d < 32, 64 for d < 64, 80 for d = 64.
 #include <math.h>
 
+#include "bf16_operands.h"
 #include "common.h"
 #include "internal.h"
 
@@ -71,34 +72,10 @@ __device__ __forceinline__ View16 view16(const SvgdLayout& L, char* base) {
 // 8 kq + 7, which are the chunk's particles 4 kq .. 4 kq + 3 and then
 // 16 + 4 kq .. 16 + 4 kq + 3.
 
-// ---- operands, a workgroup per 64 padded rows (blockIdx.y picks them within
-// a 256-row chunk, so the grid fills more of the chip): the x~ rows and their norms
-// depend on theta only and are built with the median; V needs g and h.
-// x~: a thread per (row, group of 8 coordinates) makes one 16-byte store; the
-// groups of a row sit in adjacent lanes and add their norms by exchange.
-__device__ void pack16_theta_rows(int N, int d, int kd, int row0, const float* __restrict__ theta,
-                                  const View16& w) {
-    const int groups = kd >> 3;  // 4 or 8: every thread takes the same number of steps
-    row0 += 64 * blockIdx.y;
-    for (int o = threadIdx.x; o < 64 * groups; o += 256) {
-        const int i = row0 + o / groups, l0 = 8 * (o & (groups - 1));
-        bf16x8 xb;
-        float nrm = 0.0f;
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const int l = l0 + k;
-            float x = 0.0f;
-            if (i < N && l < d) x = theta[(int64_t)l * N + i] - w.ctr[l];
-            xb[k] = (__bf16)x;
-            const float xr = (float)xb[k];
-            nrm = fmaf(xr, xr, nrm);
-        }
-        *reinterpret_cast<bf16x8*>(w.xb + (int64_t)i * kd + l0) = xb;
-        for (int m = 1; m < groups; m <<= 1) nrm += __shfl_xor(nrm, m);
-        if (l0 == 0) w.nrm[i] = -0.5f * nrm;
-    }
-}
-
+// ---- operands: the x~ rows and their norms depend on theta only and are
+// built with the median (bf16_operands.h); V needs g and h.  A workgroup
+// takes 64 padded rows (blockIdx.y picks them within a 256-row chunk, so the
+// grid fills more of the chip).
 // V: a thread per (32-particle chunk, column, lane group kq) makes one
 // 16-byte store, the 8 values that lane group of the K.V product reads.
 __device__ void pack16_v_rows(int N, int d, int vc, int row0, const float* __restrict__ theta,
@@ -289,12 +266,13 @@ struct One16 {
     float fixed_h;
 };
 
-__global__ __launch_bounds__(kMeanThreads) void k_center(One16 a, const float* theta, char* ws) {
-    particle_mean_body(a.N, blockIdx.x, theta, view16(a.L, ws).ctr);
+__global__ __launch_bounds__(kCentreThreads) void k_center(One16 a, const float* theta, char* ws) {
+    particle_mean_body<kCentreThreads>(a.N, blockIdx.x, theta, view16(a.L, ws).ctr);
 }
 
 __global__ __launch_bounds__(256) void k_pack16_theta(One16 a, const float* theta, char* ws) {
-    pack16_theta_rows(a.N, a.d, a.L.kd, blockIdx.x * 256, theta, view16(a.L, ws));
+    const View16 w = view16(a.L, ws);
+    pack16_theta_rows(a.N, a.d, a.L.kd, blockIdx.x * 256 + 64 * blockIdx.y, threadIdx.x, theta, w.ctr, w.xb, w.nrm);
 }
 
 __global__ __launch_bounds__(256) void k_pack16_v(One16 a, const float* theta, const float* g, char* ws) {
@@ -329,23 +307,8 @@ __global__ __launch_bounds__(256) void k_reduce16(One16 a, const float* theta, c
 // ---- batched kernels (work-list entries as in svgd.hip) ---------------------------
 __device__ __forceinline__ char* base_of(const ProblemDesc& D, char* ws) { return ws + D.svgd_off; }
 
-// entry = (problem, coordinate, -, -)
-__global__ __launch_bounds__(kMeanThreads) void k_center_batched(const ProblemDesc* __restrict__ descs,
-                                                        const int4* __restrict__ work, const float* theta, char* ws) {
-    const int4 e = work[blockIdx.x];
-    const ProblemDesc& D = descs[e.x];
-    particle_mean_body(D.N, e.y, theta + D.theta_off, view16(D.sv, base_of(D, ws)).ctr);
-}
-
-// entry = (problem, first row of a 256-row chunk, -, -)
-__global__ __launch_bounds__(256) void k_pack16_theta_batched(const ProblemDesc* __restrict__ descs,
-                                                              const int4* __restrict__ work, const float* theta,
-                                                              char* ws) {
-    const int4 e = work[blockIdx.x];
-    const ProblemDesc& D = descs[e.x];
-    if (D.N < 2) return;
-    pack16_theta_rows(D.N, D.d, D.sv.kd, e.y, theta + D.theta_off, view16(D.sv, base_of(D, ws)));
-}
+// (the batched theta operands are built by the fused bandwidth-stage kernels
+// of median.hip, with the sampled median)
 
 __global__ __launch_bounds__(256) void k_pack16_v_batched(const ProblemDesc* __restrict__ descs,
                                                           const int4* __restrict__ work, const float* theta,
@@ -395,18 +358,8 @@ hipError_t launch_operands16(int N, int d, const float* theta, void* ws, const S
     if (N < 2) return hipSuccess;
     One16 a{N, d, L, 0.0f};
     char* b = static_cast<char*>(ws);
-    hipLaunchKernelGGL(k_center, dim3(d), dim3(kMeanThreads), 0, st, a, theta, b);
+    hipLaunchKernelGGL(k_center, dim3(d), dim3(kCentreThreads), 0, st, a, theta, b);
     hipLaunchKernelGGL(k_pack16_theta, dim3(L.npad / 256, 4), dim3(256), 0, st, a, theta, b);
-    return hipGetLastError();
-}
-
-hipError_t launch_operands16_batched(const BatchPlan& P, const ProblemDesc* descs, const float* theta, char* ws,
-                                     hipStream_t st) {
-    if (P.n_ctr)
-        hipLaunchKernelGGL(k_center_batched, dim3(P.n_ctr), dim3(kMeanThreads), 0, st, descs, P.ctr_work, theta, ws);
-    if (P.n_row16)
-        hipLaunchKernelGGL(k_pack16_theta_batched, dim3(P.n_row16, 4), dim3(256), 0, st, descs, P.row16_work, theta,
-                           ws);
     return hipGetLastError();
 }
 
@@ -440,9 +393,8 @@ hipError_t launch_svgd16(int N, int d, const float* theta, const float* grad, fl
 
 hipError_t launch_svgd16_batched(const BatchPlan& P, const ProblemDesc* descs, const float* theta, const float* grad,
                                  float* phi, char* ws, uint32_t* status, hipStream_t st) {
-    hipError_t e = launch_median_batched(P, descs, theta, 0, ws, st);
+    hipError_t e = launch_bandwidth16_batched(P, descs, theta, ws, st);
     if (e != hipSuccess) return e;
-    if ((e = launch_operands16_batched(P, descs, theta, ws, st)) != hipSuccess) return e;
     return launch_svgd16_direction_batched(P, descs, theta, grad, phi, ws, status, st, nullptr);
 }
 

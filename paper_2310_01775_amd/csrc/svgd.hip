@@ -275,10 +275,11 @@ hipError_t launch_svgd_bandwidth_batched(const BatchPlan& P, const ProblemDesc* 
                                          char* ws, hipStream_t st) {
     // the theta-only operands of the FP32 form (exact median, whose all-pairs
     // passes read them) or of the BF16 form (sampled median)
+    if (!exact) return launch_bandwidth16_batched(P, descs, theta, ws, st);
     hipError_t e;
-    if (exact && (e = launch_operands32_batched(P, descs, theta, 0, ws, st)) != hipSuccess) return e;
-    if ((e = launch_median_batched(P, descs, theta, exact, ws, st)) != hipSuccess) return e;
-    return exact ? launch_operands32_batched(P, descs, theta, 1, ws, st) : launch_operands16_batched(P, descs, theta, ws, st);
+    if ((e = launch_operands32_batched(P, descs, theta, 0, ws, st)) != hipSuccess) return e;
+    if ((e = launch_median_batched(P, descs, theta, 1, ws, st)) != hipSuccess) return e;
+    return launch_operands32_batched(P, descs, theta, 1, ws, st);
 }
 
 hipError_t launch_phi_reduce(int N, int d, int splits, const float* partial, float* phi, uint32_t* status,
