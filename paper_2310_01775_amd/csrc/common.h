@@ -219,6 +219,7 @@ struct UpdateArgs {
     const int* t_dev;  // non-null: step t = t0 + *t_dev + 1 (graph replay), else t = t0
     float lr, b1, b2, eps;
     int use_adam;
+    int t_pre;         // 1: this iteration's first kernel already advanced *t_dev, so t = t0 + *t_dev
 };
 
 // The bias-correction denominators den[0..1] of the workgroup: thread 0
@@ -226,7 +227,7 @@ struct UpdateArgs {
 // loads, so that the counter's load and the powers overlap those loads.
 __device__ __forceinline__ void block_denominators(const UpdateArgs& u, float* den) {
     if (u.use_adam && threadIdx.x == 0) {
-        const int t = u.t_dev ? u.t0 + *u.t_dev + 1 : u.t0;
+        const int t = u.t_dev ? u.t0 + *u.t_dev + (u.t_pre ? 0 : 1) : u.t0;
         den[0] = 1.0f - powf(u.b1, (float)t);
         den[1] = 1.0f - powf(u.b2, (float)t);
     }

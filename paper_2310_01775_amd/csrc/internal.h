@@ -104,9 +104,10 @@ hipError_t launch_svgd16_batched(const BatchPlan& P, const ProblemDesc* descs, c
 // the reduce; upd as for the FP32 form)
 hipError_t launch_operands16(int N, int d, const float* theta, void* ws, const SvgdLayout& L, hipStream_t st);
 // the sampled median and those operands for a batch, in two fused launches
-// (sample distances with the centres, then the sample select with the rows)
+// (sample distances with the centres, then the sample select with the rows);
+// a non-null step counter is advanced by one on the way
 hipError_t launch_bandwidth16_batched(const BatchPlan& P, const ProblemDesc* descs, const float* theta, char* ws,
-                                      hipStream_t st);
+                                      hipStream_t st, int* step = nullptr);
 hipError_t launch_svgd16_direction(int N, int d, const float* theta, const float* grad, float* phi, void* ws,
                                    const SvgdLayout& L, uint32_t* status, hipStream_t st,
                                    const UpdateArgs* upd = nullptr);

@@ -1000,11 +1000,14 @@ __global__ __launch_bounds__(kSelThreads) void k_sample_select_batched(const Pro
 // slot), the rest take one entry (problem, coordinate) of the centre list
 // each.  Second: blocks below the problem count select the sample median,
 // the rest build the centred BF16 rows of one entry (problem, 256-row chunk)
-// of the row list, a quarter per 256 threads.
+// of the row list, a quarter per 256 threads.  A non-null step counter is
+// advanced once by the first launch (a solve's iteration counter, read by
+// the update at the iteration's end).
 __global__ __launch_bounds__(256) void k_bw16_gather_batched(const ProblemDesc* __restrict__ descs,
                                                              const int4* __restrict__ ctr_work, int nd,
-                                                             const float* theta, char* ws) {
+                                                             const float* theta, char* ws, int* step) {
     constexpr int per = kMedSample / 64;
+    if (step && blockIdx.x == 0 && threadIdx.x == 0) *step += 1;
     if ((int)blockIdx.x < nd) {
         const ProblemDesc& D = descs[blockIdx.x / per];
         if (D.N < 2 || D.fixed_h > 0.0f) return;
@@ -1169,9 +1172,10 @@ hipError_t launch_median(int N, int d, const float* theta, float bandwidth, int 
 }
 
 hipError_t launch_bandwidth16_batched(const BatchPlan& P, const ProblemDesc* descs, const float* theta, char* ws,
-                                      hipStream_t st) {
+                                      hipStream_t st, int* step) {
     const int np = P.n_problems, nd = (kMedSample / 64) * np;
-    hipLaunchKernelGGL(k_bw16_gather_batched, dim3(nd + P.n_ctr), dim3(256), 0, st, descs, P.ctr_work, nd, theta, ws);
+    hipLaunchKernelGGL(k_bw16_gather_batched, dim3(nd + P.n_ctr), dim3(256), 0, st, descs, P.ctr_work, nd, theta, ws,
+                       step);
     hipLaunchKernelGGL(k_bw16_select_batched, dim3(np + P.n_row16), dim3(kSelThreads), 0, st, descs, P.row16_work, np,
                        theta, ws);
     return hipGetLastError();

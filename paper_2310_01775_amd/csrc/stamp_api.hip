@@ -983,12 +983,16 @@ static int32_t solve_impl(stamp_ctx* ctx, int32_t n_problems, const stamp_scene*
     auto sur_iteration = [&]() -> hipError_t {
         hipError_t r;
         if (sur->phi_bf16) {
-            // The sampled median and the BF16 operands take ~25 us when they
+            // The sampled median and the BF16 operands take ~15 us when they
             // have the chip to themselves, but beside the network's inference
             // their single-workgroup select waits for its workgroups to drain,
             // and the fork and join cost ~10 us each: they run first, on the
-            // same stream.
-            if ((r = bandwidth_stage(st, 0)) != hipSuccess) return r;
+            // same stream (and advance the step counter on the way).
+            if (skern.empty()) {
+                if ((r = launch_bandwidth16_batched(B, d_desc, theta, d_svgd, st, d_ctr)) != hipSuccess) return r;
+            } else if ((r = bandwidth_stage(st, 0)) != hipSuccess) {
+                return r;
+            }
             for (int p = 0; p < n_problems; ++p)
                 if ((r = sur_infer(p, nullptr, d_grad, -1.0f)) != hipSuccess) return r;
         } else {
@@ -998,6 +1002,11 @@ static int32_t solve_impl(stamp_ctx* ctx, int32_t n_problems, const stamp_scene*
                 if ((r = sur_infer(p, nullptr, d_grad, -1.0f)) != hipSuccess) return r;
             if ((r = branch(1)) != hipSuccess) return r;
             if ((r = join()) != hipSuccess) return r;
+        }
+        if (sur->phi_bf16 && skern.empty()) {  // the counter was advanced at the start
+            UpdateArgs u = upd;
+            u.t_pre = 1;
+            return launch_svgd16_direction_batched(B, d_desc, theta, d_grad, nullptr, d_svgd, status, st, &u);
         }
         if (sur->phi_bf16) {
             if ((r = launch_svgd16_direction_batched(B, d_desc, theta, d_grad, nullptr, d_svgd, status, st, &upd)) !=
