@@ -242,6 +242,16 @@ __global__ __launch_bounds__(64 * kInfWaves) void k_mlp_infer(const float* __res
     __bf16* Db = sD[wave];
     const MlpPtrs m = mlp_ptrs(P, Wb);
     const bool want_grad = grad_out != nullptr;
+    // Biases, output weights and input scales in LDS: global loads complete
+    // in order, so a global load of one of them inside a loop would make
+    // the wave wait for the weight fragments prefetched before it.
+    __shared__ float sB1[kW], sB2[kW], sW3[kW], sIs[kIn];
+    for (int c = threadIdx.x; c < kW; c += 64 * kInfWaves) {
+        sB1[c] = m.b1[c];
+        sB2[c] = m.b2[c];
+        sW3[c] = m.w3[c];
+    }
+    for (int f = threadIdx.x; f < kIn; f += 64 * kInfWaves) sIs[f] = m.isig[f];
 
 #pragma unroll
     for (int rb = 0; rb < kInfRB; ++rb) stage_inputs(U + rb * 16 * kLdU, m, X, x_mode, M, n_in, d, enc, row0 + rb * 16);
@@ -260,7 +270,7 @@ __global__ __launch_bounds__(64 * kInfWaves) void k_mlp_infer(const float* __res
         f4 acc[kInfRB] = {};
         mma_blocks<kIn / 32>(U, kLdU, r1[cb % 3], acc);
         const int c = cb * 16 + col;
-        const float b1 = m.b1[c];
+        const float b1 = sB1[c];
 #pragma unroll
         for (int rb = 0; rb < kInfRB; ++rb)
             for (int j = 0; j < 4; ++j) Hb[(rb * 16 + 4 * kq + j) * kLdH + c] = (__bf16)gelu(acc[rb][j] + b1);
@@ -277,7 +287,7 @@ __global__ __launch_bounds__(64 * kInfWaves) void k_mlp_infer(const float* __res
         f4 acc[kInfRB] = {};
         mma_blocks<kW / 32>(Hb, kLdH, r2[cb % 3], acc);
         const int c = cb * 16 + col;
-        const float b2 = m.b2[c], w3 = m.w3[c];
+        const float b2 = sB2[c], w3 = sW3[c];
 #pragma unroll
         for (int rb = 0; rb < kInfRB; ++rb)
             for (int j = 0; j < 4; ++j) {
@@ -310,7 +320,7 @@ __global__ __launch_bounds__(64 * kInfWaves) void k_mlp_infer(const float* __res
             mma_blocks<kW / 32>(Db, kLdH, rt[kb % 3], t);
             mma_blocks<kIn / 32>(U, kLdU, rw[kb % 3], z1);
             const int k = kb * 16 + col;
-            const float b1 = m.b1[k];
+            const float b1 = sB1[k];
 #pragma unroll
             for (int rb = 0; rb < kInfRB; ++rb)
                 for (int j = 0; j < 4; ++j)
@@ -319,27 +329,43 @@ __global__ __launch_bounds__(64 * kInfWaves) void k_mlp_infer(const float* __res
     }
     __syncthreads();
     if (want_grad) {
-        // dy/dx = delta1 W1, then the chain through the standardisation
-        for (int fb = 0; fb < kIn / 16; ++fb) {
+        // dy/dx = delta1 W1, then the chain through the standardisation (only
+        // the first d inputs are asked for).  Global memory operations complete
+        // in order, so every load of a block (the next block's fragments, the
+        // raw inputs of the bound term) is issued before the block's stores.
+        bf16x8 bv[kW / 32], bn[kW / 32];
+        load_frags<kW / 32>(m.W1T, kW, 0, bv);
+        for (int fb = 0; fb * 16 < d && fb < kIn / 16; ++fb) {
             const int f = fb * 16 + col;
-            if (fb * 16 >= d) break;  // only the first d inputs are asked for
-            bf16x8 bv[kW / 32];
-            load_frags<kW / 32>(m.W1T, kW, fb * 16, bv);
+            const bool more = (fb + 1) * 16 < d && fb + 1 < kIn / 16;
+            if (more) load_frags<kW / 32>(m.W1T, kW, (fb + 1) * 16, bn);
+            float xr[kInfRB][4] = {};
+            if (bt.H && f < d) {
+#pragma unroll
+                for (int rb = 0; rb < kInfRB; ++rb)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        xr[rb][j] = x_raw(X, x_mode, M, n_in, min(row0 + rb * 16 + 4 * kq + j, M - 1), f);
+            }
             f4 g[kInfRB] = {};
             mma_blocks<kW / 32>(Hb, kLdH, bv, g);
             if (f < d) {
-                const float is = m.isig[f];
+                const float is = sIs[f];
 #pragma unroll
                 for (int rb = 0; rb < kInfRB; ++rb)
+#pragma unroll
                     for (int j = 0; j < 4; ++j) {
                         const int i = row0 + rb * 16 + 4 * kq + j;
                         if (i < M) {
                             float gi = expf(y[rb][j]) * g[rb][j] * is;
-                            if (bt.H) gi += bound_grad(bt, f, x_raw(X, x_mode, M, n_in, i, f));
+                            if (bt.H) gi += bound_grad(bt, f, xr[rb][j]);
                             grad_out[(int64_t)f * M + i] = grad_scale * gi;
                         }
                     }
             }
+            if (more)
+#pragma unroll
+                for (int k = 0; k < kW / 32; ++k) bv[k] = bn[k];
         }
     }
     if (col == 0) {
