@@ -136,14 +136,25 @@ __device__ __forceinline__ void stage_inputs(__bf16* U, const MlpPtrs& m, const 
     const int l = threadIdx.x & 63;
     const int r = l & 15;
     const int i = row0 + r;
-    const int64_t src = (src_row && i < M) ? src_row[r] : i;
-    for (int f = l >> 4; f < kIn; f += 4) {
-        float x = 0.0f;
-        if (i < M && f < n_in) {
-            if (x_mode == 0) x = X[src * n_in + f];
-            else x = f < d ? X[(int64_t)f * M + i] : enc[f - d];
-        }
-        const float u = f < n_in ? (x - m.mu[f]) * m.isig[f] : 0.0f;
+    const int ic = min(i, M - 1);
+    const int64_t src = (src_row && i < M) ? src_row[r] : ic;
+    // every load is issued before the first use (addresses clamped into
+    // range, out-of-range values replaced afterwards): global loads complete
+    // in order, so a load-use chain per feature would wait once per feature
+    float xv[kIn / 4], mu[kIn / 4], is[kIn / 4];
+#pragma unroll
+    for (int q = 0; q < kIn / 4; ++q) {
+        const int f = (l >> 4) + 4 * q, fc = min(f, n_in - 1);
+        const float* p = x_mode == 0 ? X + src * n_in + fc : (fc < d ? X + (int64_t)fc * M + ic : enc + (fc - d));
+        xv[q] = *p;
+        mu[q] = m.mu[fc];
+        is[q] = m.isig[fc];
+    }
+#pragma unroll
+    for (int q = 0; q < kIn / 4; ++q) {
+        const int f = (l >> 4) + 4 * q;
+        const float x = (i < M && f < n_in) ? xv[q] : 0.0f;
+        const float u = f < n_in ? (x - mu[q]) * is[q] : 0.0f;
         U[r * kLdU + f] = (__bf16)u;
     }
 }
