@@ -621,18 +621,21 @@ __device__ __forceinline__ void rollout_adj_lane(const SimConst& c, int N, const
         prof.reset(invL);
         if (g.ckpt == 0) {
             // reverse sweep over the full tape; the states of the next two
-            // (earlier) steps are in flight while a step is reversed
+            // (earlier) steps are in flight while a step is reversed.  The
+            // loads are unconditional (indices clamped at entry 0, whose
+            // extra copies go unused): with a load on some paths only, the
+            // compiler waits for every load in flight at the loop head.
             const float* base = tape + (int64_t)tk * stride;  // step j's entry: base + j stride
             int j = tk1 - tk - 1;
             Blk XA, XB;
             load_blk_at(XA, base + (int64_t)j * stride, loff);
-            if (j >= 1) load_blk_at(XB, base + (int64_t)(j - 1) * stride, loff);
+            load_blk_at(XB, base + (int64_t)max(j - 1, 0) * stride, loff);
             for (; j >= 1; j -= 2) {
                 Blk X = XA;
-                if (j >= 2) load_blk_at(XA, base + (int64_t)(j - 2) * stride, loff);
+                load_blk_at(XA, base + (int64_t)max(j - 2, 0) * stride, loff);
                 step_reverse<B>(c, k, b, X, L, p, prof.at(j), P0xb, P0yb, Vxb, Vyb);
                 X = XB;
-                if (j >= 3) load_blk_at(XB, base + (int64_t)(j - 3) * stride, loff);
+                load_blk_at(XB, base + (int64_t)max(j - 3, 0) * stride, loff);
                 step_reverse<B>(c, k, b, X, L, p, prof.at(j - 1), P0xb, P0yb, Vxb, Vyb);
             }
             if (j == 0) step_reverse<B>(c, k, b, XA, L, p, prof.at(0), P0xb, P0yb, Vxb, Vyb);
