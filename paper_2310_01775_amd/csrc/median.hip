@@ -4,12 +4,14 @@
 //
 // Exact path (interval select).  Non-negative floats order like their bit
 // patterns, so the median is the rank-k bit pattern, k = ceil(P/2).
-//   1. A fixed sample of kMedSample pairs is measured (the same arithmetic as
-//      every later pass, so its values are population values) and its order
-//      statistics at ranks S(1/2 -+ 3/sqrt S) give a bracket [lo, hi] that
-//      holds rank k unless the sample is off by six standard deviations.
-//      When all pairs fit in the sample, it is the population and its median
-//      is final.  The sample sits in LDS for the select.
+//   1. A fixed sample of kMedSample pairs is measured (the same squared
+//      distances, summed in a fixed order of their own, so within rounding of
+//      the passes' values) and its order statistics at ranks
+//      S(1/2 -+ 3/sqrt S) give a bracket [lo, hi] that holds rank k unless the
+//      sample is off by six standard deviations (a rank outside it sends the
+//      passes back over every pair, step 3).  When all pairs fit in the
+//      sample, it is the population and its median is final.  The sample sits
+//      in LDS for the select.
 //   2. Pass 0 over every pair counts the pairs below lo and above hi and
 //      copies the in-bracket bit patterns into a candidate buffer.
 //   3. Each later pass histograms the current interval [lo, hi] into 2048
