@@ -99,7 +99,7 @@ def _t(v, n):
     return torch.full((n,), float(v), dtype=DT)
 
 
-def rollout(scene: dict, w: dict, theta: torch.Tensor, vel0=None, record=False):
+def rollout(scene: dict, w: dict, theta: torch.Tensor, vel0=None, record=False, detach_phases=False):
     """Roll every particle forward and evaluate its cost.
 
     Each push phase k runs once per side s from the same start state S_k
@@ -113,6 +113,12 @@ def rollout(scene: dict, w: dict, theta: torch.Tensor, vel0=None, record=False):
       ends    [H][6B][N][4]  sub-rollout states after the last step of a phase,
       blended [H+1][6B][N]   the mixed phase-start states S_0..S_H,
     as detached numpy arrays (state order per block: x, y, phi, vx, vy, omega).
+
+    detach_phases: each phase starts from a detached copy of S_k, so gradients
+    stop at phase boundaries (the per-phase split of the appendix on exploding
+    gradients); the result then also holds Pend, the block-0 (x, y) of every
+    phase's end state S_{k+1} before detaching (k = 0..H-1), through which
+    phase k's own gradient flows.  ``cost`` keeps its value either way.
     """
     N = theta.shape[0]
     H, B, T = int(scene["H"]), int(scene["B"]), int(scene["T"])
@@ -151,8 +157,11 @@ def rollout(scene: dict, w: dict, theta: torch.Tensor, vel0=None, record=False):
     nx, ny = NORMALS[:, 0], NORMALS[:, 1]
     tx, ty = TANGENTS[:, 0], TANGENTS[:, 1]
     P = []
+    Pend = []
     for k in range(H):
         tk, tk1 = phase_bounds(k, T, H)
+        if detach_phases:
+            S = [[c.detach() for c in blk] for blk in S]
         if record:
             for b in range(B):
                 for c in range(6):
@@ -225,6 +234,7 @@ def rollout(scene: dict, w: dict, theta: torch.Tensor, vel0=None, record=False):
             snap_sides(ends[k], X)
         # mixture of the side outcomes, weighted by the relaxed action z~_k
         S = [[(zt * X[b][c]).sum(dim=1) for c in range(6)] for b in range(B)]
+        Pend.append((S[0][0], S[0][1]))
     if record:
         for b in range(B):
             for c in range(6):
@@ -232,7 +242,7 @@ def rollout(scene: dict, w: dict, theta: torch.Tensor, vel0=None, record=False):
     P.append((S[0][0], S[0][1]))
 
     cost = total_cost(scene, w, theta, P, S[0][2])
-    out = dict(cost=cost, P=P, phiT=S[0][2])
+    out = dict(cost=cost, P=P, phiT=S[0][2], Pend=Pend)
     if record:
         out.update(tape=tape, ends=ends, blended=blended)
     return out
@@ -272,6 +282,74 @@ def bound_term(theta, w, H):
         L_bound = (L_bound + _relu(torch.abs(o) - float(w["o_max"])) ** 2
                    + _relu(-Dk) ** 2 + _relu(Dk - float(w["d_max"])) ** 2)
     return L_bound
+
+
+def bound_term_push(theta, w, k):
+    """Push k's share of L_bound: relu(|o_k|-o_max)^2 + relu(-D_k)^2 + relu(D_k-D_max)^2."""
+    o, Dk = theta[:, 6 * k + 4], theta[:, 6 * k + 5]
+    return (_relu(torch.abs(o) - float(w["o_max"])) ** 2 + _relu(-Dk) ** 2
+            + _relu(Dk - float(w["d_max"])) ** 2)
+
+
+def phase_costs(scene, w, theta, frozen=None):
+    """Per-phase costs C_0..C_{H-1} whose sum is the cost C -- the split the
+    appendix on exploding gradients proposes for costs that are sums of
+    per-action terms, so that each action's parameters follow their own term
+    and no gradient crosses a phase boundary.
+
+    Terms go to the phase whose end state they read: push k's bound term to
+    phase k; L_traj's term j (MH(P_{j-1},P_j) + MH(P_j,P_H) - MH(P_{j-1},P_H),
+    j = 1..H) to phase j-1, whose end is P_j; L_target and L_rot, which read
+    the final state, to the last phase.  Inside C_k every position another
+    phase produces -- its start P_k and, for k < H-1, the final P_H -- is a
+    constant, and the rollout restarts each phase from a detached state, so
+    dC_k/dtheta reaches theta_k only, through phase k's own trajectory.
+
+    frozen: optional (starts, final) from a previous call's ``frozen`` to hold
+    in place of this theta's own (the constants of a finite-difference check).
+    Returns dict(costs: list of H tensors [N], cost [N] (the rollout's C),
+    frozen: ([(x, y)] * H starts, (x, y) final) as numpy)."""
+    H = int(scene["H"])
+    out = rollout(scene, w, theta, detach_phases=True)
+    Pend, P = out["Pend"], out["P"]
+    if frozen is None:
+        starts = [(x.detach(), y.detach()) for x, y in P[:H]]
+        final = (Pend[H - 1][0].detach(), Pend[H - 1][1].detach())
+    else:
+        starts = [(torch.as_tensor(x), torch.as_tensor(y)) for x, y in frozen[0]]
+        final = tuple(torch.as_tensor(v) for v in frozen[1])
+    ea2 = float(w["traj_eps"]) ** 2
+
+    def mh(p, q):
+        return torch.sqrt((p[0] - q[0]) ** 2 + ea2) + torch.sqrt((p[1] - q[1]) ** 2 + ea2)
+
+    gx, gy, gphi = (float(v) for v in scene["goal"])
+    tol = float(scene["goal_tol"])
+    costs = []
+    for k in range(H):
+        end = Pend[k]
+        c = float(w["bound"]) * bound_term_push(theta, w, k)
+        if k < H - 1:
+            c = c + float(w["traj"]) * (mh(starts[k], end) + mh(end, final) - mh(starts[k], final))
+        else:
+            c = c + float(w["traj"]) * (mh(starts[k], end) + mh(end, end) - mh(starts[k], end))
+            c = c + float(w["target"]) * (_relu(torch.abs(end[0] - gx) - tol) ** 2
+                                          + _relu(torch.abs(end[1] - gy) - tol) ** 2)
+            c = c + float(w["rot"]) * (1.0 - torch.cos(out["phiT"] - gphi))
+        costs.append(c)
+    frz = ([(x.numpy(), y.numpy()) for x, y in starts], (final[0].numpy(), final[1].numpy()))
+    return dict(costs=costs, cost=out["cost"].detach(), frozen=frz)
+
+
+def per_phase_cost_and_grad(scene, w, theta, cost_bar=None):
+    """(C [N], cost_bar * sum_k dC_k/dtheta [N][d]): the gradient of the
+    per-phase split (``phase_costs``), block k of which is dC_k/dtheta_k."""
+    th = torch.as_tensor(np.asarray(theta, dtype=np.float64)).clone().requires_grad_(True)
+    r = phase_costs(scene, w, th)
+    c = torch.stack(r["costs"]).sum(dim=0)
+    cb = torch.ones_like(c) if cost_bar is None else torch.as_tensor(np.asarray(cost_bar, dtype=np.float64))
+    (g,) = torch.autograd.grad(c, th, grad_outputs=cb)
+    return c.detach().numpy(), g.numpy()
 
 
 def cost_np(scene, w, theta, **kw):

@@ -72,6 +72,46 @@ def svgd_phi(theta: np.ndarray, g: np.ndarray, h: float, w: np.ndarray | None = 
     return (drive + repulse) / N
 
 
+def svgd_phi_rows(theta: np.ndarray, g: np.ndarray, h: float, rows, w: np.ndarray | None = None,
+                  chunk: int = 32) -> np.ndarray:
+    """phi_i of Eq. (1) for the particles i in ``rows`` only: the same sum as
+    ``svgd_phi`` written per row (direct differences to every particle j),
+    so large particle sets need no N x N matrix.  Returns [len(rows)][d]."""
+    theta = np.asarray(theta, dtype=np.float64)
+    g = np.asarray(g, dtype=np.float64)
+    rows = np.asarray(rows, dtype=np.int64)
+    N = theta.shape[0]
+    wj = np.ones(N) if w is None else np.asarray(w, dtype=np.float64)
+    out = np.empty((rows.size, theta.shape[1]))
+    for s in range(0, rows.size, chunk):
+        r = rows[s:s + chunk]
+        diff = theta[r][:, None, :] - theta[None, :, :]          # theta_i - theta_j
+        k = np.exp(-np.einsum("rjl,rjl->rj", diff, diff) / h) * wj[None, :]
+        out[s:s + chunk] = (k @ g + (2.0 / h) * np.einsum("rj,rjl->rl", k, diff)) / N
+    return out
+
+
+def median_sqdist_blocked(theta: np.ndarray, block: int = 16) -> float:
+    """The same lower median as ``median_sqdist``, with the pair distances
+    (direct differences) of a block of rows i against the columns j > i
+    formed one block at a time: P values held, no N x N x d array."""
+    theta = np.asarray(theta, dtype=np.float64)
+    N = theta.shape[0]
+    if N < 2:
+        raise ValueError("median needs N >= 2")
+    parts = []
+    for s in range(0, N - 1, block):
+        e = min(s + block, N - 1)
+        diff = theta[s:e][:, None, :] - theta[None, s + 1:, :]      # rows s..e-1, columns s+1..N-1
+        D = np.einsum("rjl,rjl->rj", diff, diff)
+        i = np.arange(s, e)[:, None]
+        j = np.arange(s + 1, N)[None, :]
+        parts.append(D[j > i])
+    D = np.concatenate(parts)
+    k = (D.size + 1) // 2
+    return float(np.partition(D, k - 1)[k - 1])
+
+
 def dsvgd_weights(c_relaxed: np.ndarray, c_discrete: np.ndarray) -> np.ndarray:
     """Importance weights of Eq. (4): the relaxed plan's likelihood over the
     discrete plan's, exp(-C_rel) / exp(-C_disc), scaled to mean 1.  A

@@ -125,3 +125,43 @@ def test_solve_runs_and_reduces_cost():
     out = svgd.solve(scene, w, th, iters=30, lr=1e-2, history=True)
     assert out["hist"][-1]["mean_cost"] < 0.7 * out["hist"][0]["mean_cost"]
     assert out["modes"].shape == (32, 2)
+
+
+def _double_loop_phi(th, g, h, w=None):
+    """Eq. (1) written as a plain double loop (the weights of Eq. (4) scale term j)."""
+    N, d = th.shape
+    w = np.ones(N) if w is None else w
+    want = np.zeros((N, d))
+    for i in range(N):
+        for j in range(N):
+            k = w[j] * math.exp(-sum((th[i, l] - th[j, l]) ** 2 for l in range(d)) / h)
+            for l in range(d):
+                want[i, l] += g[j, l] * k + (2.0 / h) * (th[i, l] - th[j, l]) * k
+    return want / N
+
+
+@pytest.mark.parametrize("weighted", [False, True])
+def test_row_sampled_phi_matches_double_loop_and_full_phi(weighted):
+    rng = np.random.default_rng(11)
+    N, d = 9, 4
+    th = rng.standard_normal((N, d))
+    g = rng.standard_normal((N, d)) * 3
+    w = rng.uniform(0.2, 2.0, N) if weighted else None
+    h = 1.3
+    rows = np.array([7, 0, 4, 4])
+    want = _double_loop_phi(th, g, h, w)[rows]
+    got = svgd.svgd_phi_rows(th, g, h, rows, w=w, chunk=3)
+    assert np.allclose(got, want, rtol=1e-13, atol=1e-14)
+    big = rng.standard_normal((300, 30))
+    gb = rng.standard_normal((300, 30))
+    hb = svgd.bandwidth(big)
+    r = rng.choice(300, 40, replace=False)
+    assert np.allclose(svgd.svgd_phi_rows(big, gb, hb, r), svgd.svgd_phi(big, gb, hb)[r], rtol=1e-12, atol=1e-13)
+
+
+@pytest.mark.parametrize("N", [2, 5, 12])
+def test_blocked_median_matches_brute_force(N):
+    th = np.random.default_rng(100 + N).standard_normal((N, 3))
+    assert svgd.median_sqdist_blocked(th, block=4) == pytest.approx(brute_lower_median(th.tolist()), rel=1e-14)
+    big = np.random.default_rng(N).standard_normal((257, 6))
+    assert svgd.median_sqdist_blocked(big, block=16) == svgd.median_sqdist(big)
