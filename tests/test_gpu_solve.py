@@ -1,10 +1,18 @@
 """GPU solve (Algorithm 1, SVGD phase) against the FP64 oracle.
 
-Parity bar on particle states after 100 iterations at the default lr 1e-3 (the
-regime in which the FP64 oracle is itself well-conditioned; see the
-conditioning test): relative error <= 1e-4 normwise and, per coordinate l
-(scaled by max_i |theta_ref[i, l]|), for 99.9% of coordinates; <= 1e-3 for the
-single worst coordinate."""
+Parity bar on the particle states after 100 iterations at the default lr 1e-3
+(the regime in which the FP64 oracle is itself well-conditioned; see the
+conditioning test), each coordinate's error scaled by its largest magnitude
+over the particle set.  The bar comes from the FP32 floor measured on this very
+metric by tests/golden/fp32_floor.py: twelve FP32 evaluations of the oracle's
+own arithmetic that differ only in rounding (IEEE float32; Gram-form distances;
+one-ulp moves of the initial particles, of every gradient, of every
+transcendental result, and all together) land at
+  normwise 2.6e-7 .. 4.2e-7,  99.9th percentile 5.1e-6 .. 1.06e-5,
+  worst coordinate 3.2e-5 .. 3.2e-4 (always particle 23 or 131: a sensitive
+  contact state that amplifies any rounding difference),
+so an FP32 result is held to normwise < 2e-6, 99.9th percentile < 2e-5 and
+worst coordinate < 5e-4 (about 5x, 2x and 1.6x the largest of the twelve)."""
 import os
 
 import numpy as np
@@ -74,10 +82,8 @@ def test_cfg2_solve_matches_stored_oracle(ctx, name):
     got, cost, modes = _gpu_solve(ctx, scene, w, th, int(gold["iters"]), float(gold["lr"]))
     st = _err_stats(got, gold["theta"])
     print(name, "state error", st, flush=True)
-    # 1e-4 relative on the particle states, normwise and for 99.9% of the
-    # coordinates; the few most sensitive particles amplify FP32 rounding
-    # further, so the single worst coordinate is held to 1e-3
-    assert st["norm"] < 1e-4 and st["p999"] < 1e-4 and st["max"] < 1e-3
+    # the FP32-floor bar of the module docstring
+    assert st["norm"] < 2e-6 and st["p999"] < 2e-5 and st["max"] < 5e-4
     agree = (modes == gold["modes"]).mean()
     print("mode agreement", agree, flush=True)
     assert agree == 1.0
