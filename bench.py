@@ -1,15 +1,21 @@
 """Benchmark of the STAMP SVGD hot path on one MI355X.
 
-One step = one SVGD iteration of Algorithm 1 over the whole particle set:
-rollout forward (full tape) -> rollout adjoint (grad log rho) -> median
-bandwidth -> SVGD direction (Eq. 1) -> Adam update, all in the library's HIP
-kernels.  Workload: N=1024 particles, 3 blocks, 3 pushes (d=18), T=200 steps
-of dt=0.005, seeded synthetic scene and particles.
+Default line -- the metric's own workload: SVGD particle-iterations/s of the
+learned-surrogate form against the plain method at equal final cost, on the
+N = 16384, B = 3, H = 5 (d = 30), T = 200 scene.  One step is one complete
+300-iteration solve (Algorithm 1's SVGD phase with Adam) in the surrogate form:
+the network's gradient drives iterations 0..239 (BF16 direction), the simulator
+(rollout forward + adjoint, exact median, FP32 direction) iterations 240..299,
+all in the library's HIP kernels, graph-replayed by stamp_solve_surrogate.
+The plain method (300 simulator iterations) is timed the same way beside it.
 
-Metric: particle-iterations/s = N * steps / wall seconds of the timed region
-(inputs resident in HBM, synchronised on both sides).  The dominant kernel's
-duration comes from HIP events recorded on the stream it is launched on.
-cpu_baseline times the FP64 oracle on a bounded sample of the same workload.
+value = N * 300 * steps / wall seconds of the timed surrogate-form solves
+(inputs resident in HBM, synchronised on both sides).  The network is trained
+by the library's own kernels first; that time is reported apart.  The
+dominant kernel's duration comes from HIP events on the stream it is launched
+on, around per-call launches of the same kernel at the same shape.
+cpu_baseline times the FP64 oracle on bounded samples of each stage and
+extrapolates to one solve.  --workload selects the other measurements.
 """
 import argparse
 import json
@@ -23,31 +29,40 @@ sys.path.insert(0, ROOT)
 
 METRIC = "SVGD particle-iters/s incl. sim fwd+adjoint; surrogate vs plain at equal cost"
 UNIT = "particle-iters/s"
-FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X published FP32 vector peak
 HBM_PEAK_GBS = 8000.0
-
-
-def rollout_flops_per_lane_step(B, adjoint=False):
-    """Algorithmic FP32 operations of one sub-rollout step (one lane), counted
-    from the forward step (friction 16/block, contact 26/pair, pusher 52,
-    integrator 15/block, time scaling 8) and its reverse (which also recomputes
-    the forward intermediates it needs)."""
-    pairs = B * (B - 1) // 2
-    if not adjoint:
-        return 16 * B + 26 * pairs + 52 + 15 * B + 8
-    return 12 * B + 36 * B + 54 * pairs + 119 + 8
+MFMA_FP32_PEAK_TFLOPS = 157.3     # MI355X published dense FP32 matrix peak
+MFMA_BF16_PEAK_TFLOPS = 2500.0    # MI355X published dense BF16 matrix peak
 
 
 def rollout_bytes(N, d, B, T, H):
-    """Algorithmic HBM bytes of one forward (or adjoint) launch with the full
-    tape: theta (4d per particle), the tape of (T+H) states of 6B floats for
-    each of the 4 side lanes, and the per-particle output (cost, or 4d grad)."""
+    """Algorithmic HBM bytes of one forward and one adjoint launch with the
+    full tape.  Per particle: theta (4d), the tape -- the pre-step state of
+    every step (T) plus the H phase-end states, 6 floats per block, for each of
+    the 4 side sub-rollouts the phase mixture runs -- written by the forward
+    and read once by the adjoint, and the output (cost 4 B; grad 4d)."""
     tape = (T + H) * 6 * B * 4 * 4
-    return N * (4 * d + tape), N * (4 * d + tape + 4 * d)
+    return N * (4 * d + tape + 4), N * (4 * d + tape + 4 * d)
+
+
+def rollout_bytes_single_trajectory(N, d, B, T):
+    """The same count for one trajectory per particle (24 B (T+1) per block):
+    the tape a rollout without the phase mixture would keep."""
+    return N * (4 * d + 24 * B * (T + 1) + 4 * d)
+
+
+def phi_flops(N, d):
+    """Algorithmic flops of the SVGD contraction: the Gram distances (2d per
+    pair) and K.[g - (2/h)x | 1] (2(d+1) per pair) over all N^2 pairs."""
+    return N * N * (2 * d + 2 * (d + 1))
+
+
+def mlp_flops(M, n_in, width=256):
+    """Forward + input gradient of the 3-layer surrogate network per launch."""
+    return M * 2 * 2 * (n_in * width + width * width + width)
 
 
 KERNEL_SOURCES = ["paper_2310_01775_amd/csrc/rollout.hip", "paper_2310_01775_amd/csrc/common.h"]
-PROFILE = os.path.join(ROOT, "profiles", "rollout_n1024_counters.md")
+PROFILE = os.path.join(ROOT, "profiles", "rollout_adj_n16384_counters.md")
 
 
 def kernel_source_hash():
@@ -75,18 +90,112 @@ def measured_traffic(kernel):
     return float(v) if v else None
 
 
-def cpu_baseline(seconds_target=15.0):
-    """Time the FP64 oracle (as it stands) on a bounded sample of the same
-    workload: full N=1024 scene, a few iterations of rollout+autodiff gradient,
-    median bandwidth, phi and Adam."""
+def _host_cpu():
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    return model, avail
+
+
+def _oracle_stage_times(net_params, enc, scene, w, th, iters, s_iters):
+    """Seconds per particle / row / call of each stage of the FP64 oracle on
+    bounded samples of the N = 16384 workload, and the solve time they
+    extrapolate to (s_iters surrogate iterations + the rest plain)."""
+    import numpy as np
+
+    from oracle import mlp, sim, svgd
+
+    N, d = th.shape
+    rng = np.random.default_rng(0)
+    t = {}
+    ns = 1024
+    x = th[rng.choice(N, ns, replace=False)]
+    t0 = time.perf_counter()
+    sim.cost_and_grad(scene, w, x)
+    t["sim_per_particle"] = (time.perf_counter() - t0) / ns
+    nm = N
+    t0 = time.perf_counter()
+    mlp.surrogate_cost_and_grad(net_params, th[:nm], enc, w)
+    t["mlp_per_particle"] = (time.perf_counter() - t0) / nm
+    g = rng.standard_normal(th.shape) * 20.0
+    nr = 2048
+    t0 = time.perf_counter()
+    svgd.svgd_phi_rows(th, g, 1.0, np.arange(nr))
+    t["phi_per_row"] = (time.perf_counter() - t0) / nr
+    nmed = 8192
+    t0 = time.perf_counter()
+    svgd.median_sqdist_blocked(th[:nmed])
+    t["median_per_pair"] = (time.perf_counter() - t0) / (nmed * (nmed - 1) / 2)
+    m = np.zeros_like(th)
+    t0 = time.perf_counter()
+    svgd.adam_step(th, g, m, m, 1, 1e-3)
+    t["adam_per_call"] = time.perf_counter() - t0
+    shared = N * t["phi_per_row"] + N * (N - 1) / 2 * t["median_per_pair"] + t["adam_per_call"]
+    it_plain = N * t["sim_per_particle"] + shared
+    it_sur = N * t["mlp_per_particle"] + shared
+    t["solve_s"] = s_iters * it_sur + (iters - s_iters) * it_plain
+    t["plain_solve_s"] = iters * it_plain
+    return t
+
+
+def cpu_baseline_surrogate(net_params, enc, scene, w, th, iters, s_iters):
+    """The FP64 oracle as it stands, timed on bounded samples of every stage of
+    the surrogate-form solve and extrapolated per iteration to N = 16384: the
+    rollout + autodiff gradient on 1024 particles, the network's cost + input
+    gradient on all N, the SVGD direction on 2048 rows against all N, the exact
+    median on the pairs of 8192 particles (scaled by the pair count), Adam on
+    all of theta; once on every host core and once on one."""
+    import torch
+    from threadpoolctl import threadpool_limits
+
+    from oracle import mlp, sim
+
+    model, avail = _host_cpu()
+    torch.set_num_threads(avail)
+    sim.cost_and_grad(scene, w, th[:2])  # first-use costs of torch and numpy stay out of the timing
+    mlp.surrogate_cost_and_grad(net_params, th[:16], enc, w)
+    t0 = time.perf_counter()
+    allc = _oracle_stage_times(net_params, enc, scene, w, th, iters, s_iters)
+    wall_all = time.perf_counter() - t0
+    with threadpool_limits(1):
+        torch.set_num_threads(1)
+        t0 = time.perf_counter()
+        one = _oracle_stage_times(net_params, enc, scene, w, th, iters, s_iters)
+        wall_one = time.perf_counter() - t0
+    torch.set_num_threads(avail)
+    N = th.shape[0]
+    return {"value": N * iters / allc["solve_s"], "unit": UNIT, "cores": avail, "kind": "oracle",
+            "extrapolated": True, "value_1core": N * iters / one["solve_s"],
+            "plain_value": N * iters / allc["plain_solve_s"], "cpu_model": model,
+            "stage_seconds": {k: v for k, v in allc.items() if not k.endswith("solve_s")},
+            "sample": f"FP64 oracle stages on bounded samples of the N={N}, B=3, H=5, T=200 workload "
+                      f"(rollout+autodiff on 1024 particles, network on all, phi on 2048 rows x N, exact median "
+                      f"over the pairs of 8192 particles, Adam on all), extrapolated to a {iters}-iteration "
+                      f"surrogate-form solve ({s_iters} network iterations); {wall_all:.1f} s on {avail} cores, "
+                      f"{wall_one:.1f} s on 1 core"}
+
+
+def cpu_baseline_plain(seconds_target=15.0):
+    """The FP64 oracle (as it stands) on a bounded sample of the N = 1024,
+    B = 3, H = 3 workload: whole SVGD iterations of rollout + autodiff
+    gradient, median bandwidth, phi and Adam."""
     import numpy as np
     import torch
 
     import workloads as W
     from oracle import sim, svgd
 
-    threads = os.cpu_count() or 1
-    torch.set_num_threads(threads)
+    _, avail = _host_cpu()
+    torch.set_num_threads(avail)
     scene, w, th = W.config_problem(2)
     N = th.shape[0]
     m = np.zeros_like(th)
@@ -110,18 +219,19 @@ def cpu_baseline(seconds_target=15.0):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=5,
+                    help="timed steps: 300-iteration solves (default workload) or iterations (plain)")
+    ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--workload", default="plain", choices=["plain", "batched", "long", "surrogate", "refine",
-                                                              "structured"],
-                    help="plain: the metric's workload; batched: 64 uneven problems in one graph-replayed "
-                         "solve; long: checkpointed differentiation (report only); surrogate: the learned "
-                         "surrogate form against the plain method at N=16384 (report only); refine: SVGD "
-                         "alone against SVGD followed by SGD refinement, with the plan read-out (report only); "
-                         "structured: the structured pusher kernel against the RBF kernel (step time, and "
-                         "solutions per plan after a solve; report only)")
+    ap.add_argument("--workload", default="surrogate",
+                    choices=["surrogate", "plain", "batched", "long", "refine", "structured", "surrogate-report"],
+                    help="surrogate (default): the metric's workload, the surrogate form against the plain "
+                         "method at N=16384; plain: per-call SVGD iterations at N=1024, B=3, H=3; batched: 64 "
+                         "uneven problems in one graph-replayed solve; long: checkpointed and per-phase "
+                         "differentiation at T=1000; refine: SVGD alone against SVGD followed by SGD refinement, "
+                         "with the plan read-out; structured: the structured pusher kernel against the RBF "
+                         "kernel; surrogate-report: the network's accuracy and both direction forms")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -140,29 +250,213 @@ def main():
               "(the particle set would shard by particle with one all-gather of "
               "[theta | grad] per iteration; see DESIGN.md)", file=sys.stderr)
         sys.exit(2)
+    fn = {"surrogate": bench_headline, "plain": bench_plain_line, "batched": bench_batched, "long": bench_long,
+          "refine": bench_refine, "structured": bench_structured, "surrogate-report": bench_surrogate}
+    return fn[args.workload](args)
 
+
+def _time_launches(fn, reps=10, warm=2):
+    """Mean ms of fn() over reps launches, each bracketed by HIP events on the
+    current stream (the stream the library launches on)."""
+    import numpy as np
+    import torch
+    for _ in range(warm):
+        fn()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for a, b in evs:
+        a.record()
+        fn()
+        b.record()
+    torch.cuda.synchronize()
+    return float(np.mean([a.elapsed_time(b) for a, b in evs]))
+
+
+def bench_headline(args):
+    """The metric's workload: the surrogate form against the plain method at
+    N = 16384, B = 3, H = 5, T = 200, 300 Adam SVGD iterations each; one
+    step = one surrogate-form solve."""
     import numpy as np
     import torch
 
     import paper_2310_01775_amd as S
     import workloads as W
+    from paper_2310_01775_amd import surrogate as SG
 
-    if args.workload == "batched":
-        return bench_batched(args)
-    if args.workload == "long":
-        return bench_long(args)
-    if args.workload == "surrogate":
-        return bench_surrogate(args)
-    if args.workload == "refine":
-        return bench_refine(args)
-    if args.workload == "structured":
-        return bench_structured(args)
+    torch.cuda.set_device(0)
+    ctx = S.Context(0)
+    R = dict(W.SURROGATE_RECIPE)
+    H = 5
+    n_in = 6 * H + W.SCENE_ENC
+    cw = S.make_cost(W.cost_weights())
+    scenes = W.surrogate_dataset_scenes(max(R["random_scenes"], R["rounds"] * R["round_scenes"]))
+    structs = [S.make_scene(sc) for sc in scenes]
+    encs = [torch.as_tensor(W.scene_encoding(sc), dtype=torch.float32, device="cuda") for sc in scenes]
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(R["seed"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    net, ds, log, _ = SG.train_recipe(ctx, R, lambda p: (structs[p], cw, encs[p]),
+                                      lambda p, n: S.soa(W.surrogate_training_plans(p, n, H)),
+                                      lambda p, n: S.soa(W.make_particles(5, 1000 + p, n, H)),
+                                      W.mlp_init(n_in, seed=R["seed"]), n_in, gen)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+
+    scene, w, th0 = W.config_problem(5)
+    N, d = th0.shape
+    B, T = scene["B"], scene["T"]
+    sc = S.make_scene(scene)
+    enc = torch.as_tensor(W.scene_encoding(scene), dtype=torch.float32, device="cuda")
+    iters, s_iters = W.CONFIGS[5].iters, int(round(W.CONFIGS[5].extra["surrogate_frac"] * W.CONFIGS[5].iters))
+    lr = W.DEFAULT_ADAM["lr"]
+    cfg = S.make_cfg(iters, lr=lr)
+    work = ctx._bytes(ctx.solve_workspace_bytes([sc], [N], cfg))
+    status = ctx.status_word()
+    theta0 = S.soa(th0)
+
+    def plain_solve():
+        th = theta0.clone()
+        m, v = torch.zeros_like(th), torch.zeros_like(th)
+        c = ctx.solve([sc], [cw], [N], cfg, th, m, v, workspace=work, status=status)
+        return c, None
+
+    def surrogate_solve():
+        th = theta0.clone()
+        m, v = torch.zeros_like(th), torch.zeros_like(th)
+        return ctx.solve_surrogate([sc], [cw], [N], cfg, s_iters, net.params, net.wbf16, n_in, enc, th, m, v,
+                                   check_every=80, phi_bf16=True, workspace=work, status=status)
+
+    def timed(fn, warm, steps):
+        for _ in range(max(warm, 1)):  # the first solve tunes and captures
+            fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            out = fn()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t, out
+
+    wall_p, (cost_p, _) = timed(plain_solve, args.warmup, args.steps)
+    wall_s, (cost_s, rep) = timed(surrogate_solve, args.warmup, args.steps)
+    assert int(status.item()) == 0, "non-finite values during the benchmark"
+
+    def stats(c):
+        c = c.double()
+        return {"mean": float(c.mean()), "median": float(c.median()), "p10": float(c.quantile(0.1))}
+
+    value = N * iters * args.steps / wall_s
+    plain_value = N * iters * args.steps / wall_p
+    cs, cp = stats(cost_s), stats(cost_p)
+
+    # per-call launches of each stage's kernel at this shape, timed with HIP
+    # events on the stream they run on; the solve's single-problem rollout
+    # is the same kernel (k_rollout_fwd<3>, k_rollout_adj<3>)
+    tape = torch.empty(ctx.tape_floats(sc, N, 0), dtype=torch.float32, device="cuda")
+    cost = torch.empty(N, dtype=torch.float32, device="cuda")
+    grad = torch.empty_like(theta0)
+    minus = torch.full((N,), -1.0, device="cuda")
+    sws = ctx._bytes(ctx.svgd_workspace_bytes(N, d))
+    th = theta0.clone()
+    ctx.rollout_fwd(sc, cw, th, tape=tape, cost=cost)
+    ctx.rollout_adj(sc, cw, th, tape, cost_bar=minus, grad=grad)
+    ms = {
+        "rollout_fwd": _time_launches(lambda: ctx.rollout_fwd(sc, cw, th, tape=tape, cost=cost)),
+        "rollout_adj": _time_launches(lambda: ctx.rollout_adj(sc, cw, th, tape, cost_bar=minus, grad=grad)),
+        "bandwidth_fp32_exact": _time_launches(lambda: ctx.svgd_bandwidth(th, 0.0, workspace=sws)),
+    }
+    ctx.svgd_bandwidth(th, 0.0, workspace=sws)
+    phi = torch.empty_like(th)
+    ms["direction_fp32"] = _time_launches(lambda: ctx.svgd_direction(th, grad, sws, phi=phi))
+    ms["mlp_infer"] = _time_launches(lambda: ctx.mlp_forward(net.params, net.wbf16, th, n_in, d, x_layout=1,
+                                                             enc=enc, want_y=False, grad=grad, grad_scale=-1.0,
+                                                             w=cw))
+    ms["step_bf16"] = _time_launches(lambda: ctx.svgd_step_bf16(th, grad, phi=phi, workspace=sws))
+    # launches per surrogate-form solve: simulator iterations, network
+    # iterations, simulator checks every 80 network iterations, final cost
+    n_sim, n_net, n_chk = iters - s_iters, s_iters, s_iters // 80
+    share = {"rollout_adj": n_sim * ms["rollout_adj"], "rollout_fwd": (n_sim + n_chk + 1) * ms["rollout_fwd"],
+             "direction_fp32": n_sim * ms["direction_fp32"], "mlp_infer": (n_net + n_chk) * ms["mlp_infer"],
+             "step_bf16": n_net * ms["step_bf16"]}
+    dom = max(share, key=share.get)
+    by_f, by_a = rollout_bytes(N, d, B, T, H)
+    if dom in ("rollout_adj", "rollout_fwd"):
+        byts = by_a if dom == "rollout_adj" else by_f
+        achieved = byts / (ms[dom] * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom),
+                "kernel": "k_%s<%d>" % (dom, B), "kernel_ms": ms[dom], "bytes_per_launch": byts}
+        if dom == "rollout_adj":
+            one = rollout_bytes_single_trajectory(N, d, B, T)
+            roof["frac_single_trajectory_bytes"] = one / (ms[dom] * 1e-3) / 1e9 / HBM_PEAK_GBS
+    elif dom == "mlp_infer":
+        fl = mlp_flops(N, n_in)
+        achieved = fl / (ms[dom] * 1e-3) / 1e12
+        roof = {"bound": "mfma", "achieved": achieved, "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / MFMA_BF16_PEAK_TFLOPS, "traffic": None, "kernel": "k_mlp_infer",
+                "kernel_ms": ms[dom]}
+    else:
+        fl = phi_flops(N, d)
+        peak = MFMA_FP32_PEAK_TFLOPS if dom == "direction_fp32" else MFMA_BF16_PEAK_TFLOPS
+        achieved = fl / (ms[dom] * 1e-3) / 1e12
+        roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+                "traffic": None, "kernel": dom, "kernel_ms": ms[dom]}
+
+    out = {
+        "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": wall_s * 1e3 / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "bf16+f32", "data": "synthetic",
+        "config": {"workload": f"surrogate form vs plain STAMP SVGD: N={N} particles, B={B} blocks, H={H} pushes "
+                               f"(d={d}), T={T} steps of dt={scene['dt']:.3f}, {iters} Adam SVGD iterations per "
+                               f"solve (one step = one solve); surrogate form: the network's gradient (BF16 "
+                               f"matrix cores) and the BF16 direction for iterations 0..{s_iters - 1}, the "
+                               f"simulator (full-tape adjoint, exact median, FP32 direction) after",
+                   "N": N, "d": d, "B": B, "H": H, "T": T, "iters": iters, "surrogate_iters": s_iters},
+        "plain": {"value": plain_value, "ms_per_solve": wall_p * 1e3 / args.steps, "final_true_cost": cp},
+        "surrogate": {"final_true_cost": cs, "surrogate_iters_run": rep.iters_run, "fell_back": rep.fell_back,
+                      "handoff_log_error": rep.log_err},
+        "speedup_vs_plain": value / plain_value,
+        "equal_cost": {"surrogate_mean_le_plain_mean": cs["mean"] <= cp["mean"],
+                       "surrogate_median_le_plain_median": cs["median"] <= cp["median"]},
+        "training": {"rows": ds.n, "seconds": train_s, "steps": log.steps},
+        "roofline": roof,
+        "kernels_ms": ms,
+        "kernel_ms_per_solve": share,
+    }
+    out["secondary"] = {"plain_n1024": bench_plain(argparse.Namespace(steps=100, warmup=5), ctx)}
+    if not args.no_cpu_baseline:
+        from paper_2310_01775_amd import unpack_mlp
+        params = unpack_mlp(net.params.cpu().numpy(), n_in)
+        out["cpu_baseline"] = cpu_baseline_surrogate(params, W.scene_encoding(scene), scene, W.cost_weights(),
+                                                     th0, iters, s_iters)
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+def bench_plain_line(args):
+    """The per-call plain workload alone (N = 1024, B = 3, H = 3), as its own
+    JSON line with the FP64 oracle beside it."""
+    import paper_2310_01775_amd as S
+    ctx = S.Context(0)
+    out = bench_plain(args, ctx)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_plain(args.cpu_seconds)
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+def bench_plain(args, ctx):
+    """Per-call SVGD iterations on the N = 1024, B = 3, H = 3 (d = 18), T = 200
+    scene: bandwidth stage on a side stream beside rollout forward + adjoint,
+    then direction + Adam in one pass; returns its measurements."""
+    import numpy as np
+    import torch
+
+    import paper_2310_01775_amd as S
+    import workloads as W
     dev = torch.device("cuda", 0)
-    torch.cuda.set_device(dev)
-    cfg = W.CONFIGS[2]
     scene, w, th = W.config_problem(2)
     N, d, B, T, H = th.shape[0], th.shape[1], scene["B"], scene["T"], scene["H"]
-    ctx = S.Context(0)
     sc, cw = S.make_scene(scene), S.make_cost(w)
     theta = S.soa(th)
     m = torch.zeros_like(theta)
@@ -170,7 +464,6 @@ def main():
     tape = torch.empty(ctx.tape_floats(sc, N, 0), dtype=torch.float32, device=dev)
     cost = torch.empty(N, dtype=torch.float32, device=dev)
     grad = torch.empty_like(theta)
-    phi = torch.empty_like(theta)
     minus_one = torch.full((N,), -1.0, dtype=torch.float32, device=dev)
     sws = torch.empty(ctx.svgd_workspace_bytes(N, d), dtype=torch.uint8, device=dev)
     status = ctx.status_word()
@@ -214,39 +507,18 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     assert int(status.item()) == 0, "non-finite values during the benchmark"
-
     fwd_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in events]))
     adj_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in events]))
-    svgd_ms = float(np.mean([e[2].elapsed_time(e[3]) for e in events]))
-    bw_ms = float(np.mean([e[4].elapsed_time(e[5]) for e in events]))
-    value = N * args.steps / wall
-    fl_f = rollout_flops_per_lane_step(B) * 4 * N * T
-    fl_a = rollout_flops_per_lane_step(B, True) * 4 * N * T
     by_f, by_a = rollout_bytes(N, d, B, T, H)
-    dom = "rollout_adj" if adj_ms >= fwd_ms else "rollout_fwd"
-    dom_ms = max(adj_ms, fwd_ms)
-    dom_fl = fl_a if dom == "rollout_adj" else fl_f
-    achieved = dom_fl / (dom_ms * 1e-3) / 1e12
-    out = {
-        "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": wall * 1e3 / args.steps, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": f"plain STAMP SVGD, FP32: N={N} particles, B={B} blocks, H={H} pushes "
-                               f"(d={d}), T={T} steps of dt={scene['dt']:.3f}, full-tape adjoint, "
-                               f"exact median bandwidth (on a side stream beside the rollout), Adam",
-                   "N": N, "d": d, "B": B, "H": H, "T": T, "tape": "full"},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / FP32_VECTOR_PEAK_TFLOPS,
-                     "traffic": measured_traffic(dom),
-                     "kernel": dom, "kernel_ms": dom_ms,
-                     "hbm_GBps": (by_a if dom == "rollout_adj" else by_f) / (dom_ms * 1e-3) / 1e9},
-        "kernels_ms": {"rollout_fwd": fwd_ms, "rollout_adj": adj_ms, "direction+update": svgd_ms,
-                       "bandwidth_beside_rollout": bw_ms},
-    }
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
-    ctx.close()
-    print(json.dumps(out), flush=True)
+    return {"metric": METRIC, "value": N * args.steps / wall, "unit": UNIT, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": wall * 1e3 / args.steps,
+            "config": {"workload": f"plain STAMP SVGD per call, FP32: N={N}, B={B}, H={H} (d={d}), T={T}, "
+                                   f"full-tape adjoint, exact median beside the rollout, Adam",
+                       "N": N, "d": d, "B": B, "H": H, "T": T},
+            "kernels_ms": {"rollout_fwd": fwd_ms, "rollout_adj": adj_ms,
+                           "direction+update": float(np.mean([e[2].elapsed_time(e[3]) for e in events])),
+                           "bandwidth_beside_rollout": float(np.mean([e[4].elapsed_time(e[5]) for e in events]))},
+            "rollout_adj_GBps": by_a / (adj_ms * 1e-3) / 1e9}
 
 
 def bench_batched(args):
@@ -322,6 +594,25 @@ def bench_long(args):
         b.record()
         torch.cuda.synchronize()
         out[f"K{K}"] = {"fwd_bwd_ms": a.elapsed_time(b) / args.steps, "kept_bytes": tape_bytes(sc, N, K)}
+    # the per-phase split of the cost: gradient size per push, full adjoint
+    # against the split's (median over the particles of each push's gradient
+    # norm), and the time of the split's adjoint
+    theta = S.soa(th)
+    tape = torch.empty(ctx.tape_floats(sc, N, 0), dtype=torch.float32, device="cuda")
+    ctx.rollout_fwd(sc, cw, theta, tape=tape)
+    norms = {}
+    for name, pp in (("full", False), ("per_phase", True)):
+        g = ctx.rollout_adj(sc, cw, theta, tape, per_phase=pp)
+        gg = g.double().view(int(scene["H"]), 6, N).norm(dim=1)
+        norms[name] = [float(x) for x in gg.median(dim=1).values]
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(args.steps):
+        ctx.rollout_adj(sc, cw, theta, tape, per_phase=True)
+    b.record()
+    torch.cuda.synchronize()
+    out["grad_norm_median_per_push"] = norms
+    out["per_phase_adj_ms"] = a.elapsed_time(b) / args.steps
     print(json.dumps(out), flush=True)
     ctx.close()
 

@@ -115,7 +115,8 @@ typedef struct stamp_solver_cfg {
     int32_t dsvgd;     /* 1: weight the SVGD sum by the importance weights of Eq. (4)
                           (stamp_dsvgd_weights of the relaxed and the discrete plan's cost,
                           one extra rollout per particle and iteration); 0: w_j = 1 */
-    int32_t reserved;  /* 0 */
+    int32_t per_phase; /* 1: every simulator iteration takes the gradient of the per-phase split
+                          of the cost (stamp_rollout_adj_phases); 0: the gradient of C */
     const struct stamp_struct_kernel* kernel; /* NULL: the RBF kernel on theta; else the
                           structured kernel (push layout; K is taken from each scene's H,
                           the field itself is ignored) in every SVGD iteration */
@@ -167,23 +168,45 @@ size_t stamp_solve_workspace_bytes(int32_t n_problems, const stamp_scene* scenes
  * each push phase runs once per side from the shared phase-start state and the
  * next phase starts from the softmax(a_k)-weighted mixture of the outcomes.
  *   theta [d][N] in; cost [N] out (C of Appendix E-B);
- *   tape  [stamp_tape_floats] out, or NULL when no adjoint follows.
+ *   tape  out, or NULL when no adjoint follows; tape_floats is its length in
+ *         floats (ignored when tape is NULL) and must be at least
+ *         stamp_tape_floats(scene, N, ckpt_every).
  * Errors: STAMP_EINVAL for null ctx/scene/w/theta/cost, N < 1, H not in 1..8,
- * M != 4, B not in 1..4, T < H, dt <= 0, ckpt_every < 0. */
+ * M != 4, B not in 1..4, T < H, dt <= 0, ckpt_every < 0; STAMP_ENOSPACE when
+ * tape_floats is too small (nothing is enqueued). */
 int32_t stamp_rollout_fwd(stamp_ctx* ctx, const stamp_scene* scene, const stamp_cost_w* w,
-                          int32_t N, const float* theta, float* cost, float* tape,
+                          int32_t N, const float* theta, float* cost, float* tape, size_t tape_floats,
                           int32_t ckpt_every, uint32_t* status, void* stream);
 
 /* Reverse sweep of the rollout (back-propagation through the trajectory,
  * Sec. III-B): grad[l*N+i] = cost_bar[i] * dC_i/dtheta_{l,i}.
- *   tape from stamp_rollout_fwd with the same theta and ckpt_every;
+ *   tape from stamp_rollout_fwd with the same theta and ckpt_every, of
+ *         tape_floats floats (>= stamp_tape_floats(scene, N, ckpt_every));
  *   cost_bar [N] or NULL (= all ones); pass cost_bar = -1 to get grad log rho.
  *   workspace >= stamp_adj_workspace_bytes (may be NULL when that is 0).
- * Errors as stamp_rollout_fwd; STAMP_ENOSPACE if ws_bytes is too small. */
+ * Errors as stamp_rollout_fwd (tape may not be NULL here); STAMP_ENOSPACE if
+ * tape_floats or ws_bytes is too small. */
 int32_t stamp_rollout_adj(stamp_ctx* ctx, const stamp_scene* scene, const stamp_cost_w* w,
-                          int32_t N, const float* theta, const float* tape, int32_t ckpt_every,
-                          const float* cost_bar, float* grad, void* workspace, size_t ws_bytes,
-                          uint32_t* status, void* stream);
+                          int32_t N, const float* theta, const float* tape, size_t tape_floats,
+                          int32_t ckpt_every, const float* cost_bar, float* grad, void* workspace,
+                          size_t ws_bytes, uint32_t* status, void* stream);
+
+/* The adjoint of the per-phase split of the cost (appendix "Exploding Gradient
+ * Issues": a cost that is a sum of per-action terms C = sum_k C_k lets each
+ * action be optimised against its own term, so no gradient has to cross the
+ * whole horizon).  The pushing cost splits by the phase whose end state a term
+ * reads: push k's bound term to phase k; L_traj's term j = MH(P_{j-1}, P_j) +
+ * MH(P_j, P_H) - MH(P_{j-1}, P_H) to phase j-1 (whose end is P_j); L_target and
+ * L_rot to the last phase.  Inside C_k the positions other phases produce (its
+ * start P_k and, for k < H-1, the final P_H) are constants and the rollout's
+ * adjoint stops at the phase start, so
+ *   grad[l*N+i] = cost_bar[i] * dC_{k(l),i}/dtheta_{l,i},   k(l) = l / 6.
+ * The costs still sum to C (the value stamp_rollout_fwd returns).  Arguments,
+ * layouts and errors as stamp_rollout_adj; one push (H = 1) gives its result. */
+int32_t stamp_rollout_adj_phases(stamp_ctx* ctx, const stamp_scene* scene, const stamp_cost_w* w,
+                                 int32_t N, const float* theta, const float* tape, size_t tape_floats,
+                                 int32_t ckpt_every, const float* cost_bar, float* grad, void* workspace,
+                                 size_t ws_bytes, uint32_t* status, void* stream);
 
 /* SVGD direction of Eq. (1) with the RBF kernel K_ij = exp(-|theta_i-theta_j|^2/h):
  *   phi_i = (1/N) sum_j K_ij [ grad_logp_j + (2/h)(theta_i - theta_j) ].

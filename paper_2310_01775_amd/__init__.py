@@ -62,7 +62,7 @@ class SolverCfg(C.Structure):
     _fields_ = [("iters", C.c_int32), ("t0", C.c_int32), ("lr", C.c_float), ("beta1", C.c_float),
                 ("beta2", C.c_float), ("adam_eps", C.c_float), ("use_adam", C.c_int32),
                 ("bandwidth", C.c_float), ("ckpt_every", C.c_int32), ("sgd_iters", C.c_int32),
-                ("dsvgd", C.c_int32), ("reserved", C.c_int32), ("kernel", C.POINTER(StructKernel))]
+                ("dsvgd", C.c_int32), ("per_phase", C.c_int32), ("kernel", C.POINTER(StructKernel))]
 
 
 class Surrogate(C.Structure):
@@ -99,9 +99,11 @@ _sig = {
     "stamp_plan_readout": (_i32, [_vp, _P(Scene), _P(CostW), _i32, _vp, _vp, _vp, _vp, _sz, _vp, _vp]),
     "stamp_svgd_workspace_bytes": (_sz, [_i32, _i32]),
     "stamp_solve_workspace_bytes": (_sz, [_i32, _P(Scene), _P(_i32), _P(SolverCfg)]),
-    "stamp_rollout_fwd": (_i32, [_vp, _P(Scene), _P(CostW), _i32, _vp, _vp, _vp, _i32, _vp, _vp]),
-    "stamp_rollout_adj": (_i32, [_vp, _P(Scene), _P(CostW), _i32, _vp, _vp, _i32, _vp, _vp, _vp, _sz,
+    "stamp_rollout_fwd": (_i32, [_vp, _P(Scene), _P(CostW), _i32, _vp, _vp, _vp, _sz, _i32, _vp, _vp]),
+    "stamp_rollout_adj": (_i32, [_vp, _P(Scene), _P(CostW), _i32, _vp, _vp, _sz, _i32, _vp, _vp, _vp, _sz,
                                  _vp, _vp]),
+    "stamp_rollout_adj_phases": (_i32, [_vp, _P(Scene), _P(CostW), _i32, _vp, _vp, _sz, _i32, _vp, _vp, _vp,
+                                        _sz, _vp, _vp]),
     "stamp_svgd_step": (_i32, [_vp, _i32, _i32, _vp, _vp, _f32, _vp, _vp, _vp, _sz, _vp]),
     "stamp_svgd_step_bf16": (_i32, [_vp, _i32, _i32, _vp, _vp, _f32, _vp, _vp, _vp, _sz, _vp]),
     "stamp_adam_step": (_i32, [_vp, _i64, _vp, _vp, _vp, _vp, _i32, _f32, _f32, _f32, _f32, _i32, _vp]),
@@ -163,10 +165,11 @@ def make_cost(w: dict) -> CostW:
 
 
 def make_cfg(iters, t0=0, lr=1e-3, beta1=0.9, beta2=0.999, adam_eps=1e-8, use_adam=True,
-             bandwidth=0.0, ckpt_every=0, sgd_iters=0, dsvgd=False, kernel=None) -> SolverCfg:
-    """stamp_solver_cfg; kernel: a StructKernel (push layout) or None for the RBF kernel on theta."""
+             bandwidth=0.0, ckpt_every=0, sgd_iters=0, dsvgd=False, kernel=None, per_phase=False) -> SolverCfg:
+    """stamp_solver_cfg; kernel: a StructKernel (push layout) or None for the RBF kernel on theta;
+    per_phase: the simulator iterations take the gradient of the per-phase split of the cost."""
     cfg = SolverCfg(int(iters), int(t0), lr, beta1, beta2, adam_eps, int(bool(use_adam)), bandwidth,
-                    int(ckpt_every), int(sgd_iters), int(bool(dsvgd)), 0)
+                    int(ckpt_every), int(sgd_iters), int(bool(dsvgd)), int(bool(per_phase)))
     if kernel is not None:
         cfg.kernel = C.pointer(kernel)
         cfg._kernel_ref = kernel  # keeps the pointed-to struct alive with the cfg
@@ -296,13 +299,38 @@ class Context:
         return torch.zeros(1, dtype=torch.int32, device=self.device)
 
     # -- hot path -------------------------------------------------------------
+    @staticmethod
+    def _particles(scene: Scene, theta: torch.Tensor) -> int:
+        """Checks theta is float32 [6H][N] for this scene; returns N."""
+        if theta.dtype != torch.float32 or theta.dim() != 2 or theta.shape[0] != 6 * int(scene.H):
+            raise ValueError("theta must be float32 [6H][N] = [%d][N], got %s %s"
+                             % (6 * int(scene.H), theta.dtype, tuple(theta.shape)))
+        return int(theta.shape[1])
+
+    @staticmethod
+    def _vec(t, n: int, what: str):
+        """Checks an optional float32 device array holds n floats."""
+        if t is not None and (t.dtype != torch.float32 or t.numel() != n):
+            raise ValueError("%s must be %d float32, got %s with %d elements" % (what, n, t.dtype, t.numel()))
+
+    def _tape(self, scene: Scene, N: int, ckpt_every: int, tape):
+        if tape is None:
+            return 0
+        need = self.tape_floats(scene, N, ckpt_every)
+        if tape.dtype != torch.float32 or tape.numel() < need:
+            raise ValueError("tape must hold >= %d float32 for ckpt_every=%d, got %s with %d elements"
+                             % (need, ckpt_every, tape.dtype, tape.numel()))
+        return tape.numel()
+
     def rollout_fwd(self, scene: Scene, w: CostW, theta: torch.Tensor, tape=None, ckpt_every: int = 0,
                     status=None, stream=None, cost=None):
-        N = theta.shape[1]
+        N = self._particles(scene, theta)
         if cost is None:
             cost = torch.empty(N, dtype=torch.float32, device=self.device)
+        self._vec(cost, N, "cost")
+        n_tape = self._tape(scene, N, ckpt_every, tape)
         self._check(_lib.stamp_rollout_fwd(self._h, C.byref(scene), C.byref(w), N, _ptr(theta), _ptr(cost),
-                                           _ptr(tape), ckpt_every, _ptr(status), _stream(stream)))
+                                           _ptr(tape), n_tape, ckpt_every, _ptr(status), _stream(stream)))
         return cost
 
     def dsvgd_weights(self, cost_relaxed, cost_discrete, weights=None, stream=None):
@@ -397,17 +425,25 @@ class Context:
         return modes, cost
 
     def rollout_adj(self, scene: Scene, w: CostW, theta: torch.Tensor, tape: torch.Tensor,
-                    ckpt_every: int = 0, cost_bar=None, grad=None, workspace=None, status=None, stream=None):
-        N = theta.shape[1]
+                    ckpt_every: int = 0, cost_bar=None, grad=None, workspace=None, status=None, stream=None,
+                    per_phase: bool = False):
+        """stamp_rollout_adj (cost_bar * dC/dtheta), or with per_phase
+        stamp_rollout_adj_phases (the gradient of the per-phase split)."""
+        N = self._particles(scene, theta)
         if grad is None:
             grad = torch.empty_like(theta)
+        self._vec(grad, theta.numel(), "grad")
+        self._vec(cost_bar, N, "cost_bar")
+        if tape is None:
+            raise ValueError("the adjoint needs the forward's tape")
+        n_tape = self._tape(scene, N, ckpt_every, tape)
         need = self.adj_workspace_bytes(scene, N, ckpt_every)
         if workspace is None and need:
             workspace = self._bytes(need)
         ws_bytes = workspace.numel() if workspace is not None else 0
-        self._check(_lib.stamp_rollout_adj(self._h, C.byref(scene), C.byref(w), N, _ptr(theta), _ptr(tape),
-                                           ckpt_every, _ptr(cost_bar), _ptr(grad), _ptr(workspace), ws_bytes,
-                                           _ptr(status), _stream(stream)))
+        fn = _lib.stamp_rollout_adj_phases if per_phase else _lib.stamp_rollout_adj
+        self._check(fn(self._h, C.byref(scene), C.byref(w), N, _ptr(theta), _ptr(tape), n_tape, ckpt_every,
+                       _ptr(cost_bar), _ptr(grad), _ptr(workspace), ws_bytes, _ptr(status), _stream(stream)))
         return grad
 
     def svgd_step(self, theta: torch.Tensor, grad_logp: torch.Tensor, bandwidth: float = 0.0, phi=None,

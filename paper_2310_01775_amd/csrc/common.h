@@ -1,10 +1,14 @@
 // Shared device-side definitions of the STAMP hot path (gfx950).
 //
-// Lane mapping of the rollout kernels: lane 4*i + s runs particle i's
-// sub-rollout of push side s (North, East, South, West = 0..3).  The four
-// lanes of a particle are one DPP quad, so the phase mixture
-// S_{k+1} = sum_s softmax(a_k)_s X_s and every per-particle reduction of the
-// adjoint are two quad_perm DPP moves, no LDS and no barrier.
+// Lane mapping of the rollout kernels: one lane per (particle i, push side s,
+// block b), lane = 4 SL i + SL s + b, where SL = 1, 2 or 4 block slots (B
+// rounded up; slots b >= B are idle copies of block 0) hold the blocks of the
+// sub-rollout of side s (North, East, South, West = 0..3).  The blocks of a
+// sub-rollout exchange positions (and, in the reverse sweep, force adjoints)
+// by quad_perm DPP moves within their quad; the four sides of a particle meet
+// only at phase boundaries, where the phase mixture
+// S_{k+1} = sum_s softmax(a_k)_s X_s and the adjoint's per-particle sums are
+// cross-lane DPP adds over the particle's 4 SL lanes (no LDS, no barrier).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -42,6 +46,10 @@ struct SimConst {
     // cost (Appendix E-B)
     float goal[3], tol;
     float wt, wr, wtr, wb, omax, dmax, ea2;
+    // 1: the adjoint returns the gradient of the per-phase split of the cost
+    // (each push's parameters follow their own phase's term; no adjoint crosses
+    // a phase boundary); 0: the gradient of C
+    int per_phase;
 };
 
 // Layout of the rollout tape (floats), lane-contiguous so that each lane moves

@@ -571,14 +571,28 @@ __device__ __forceinline__ void rollout_adj_lane(const SimConst& c, int N, const
     }
     const float phTb = cb * c.wr * sinf(phT - c.goal[2]);
     const float wtr = cb * c.wtr;
-    for (int kk = 1; kk <= H; ++kk) {
-        float u, dd;
-        u = Px[kk - 1] - Px[kk];  dd = wtr * u / smooth_abs(u, c.ea2);  Pxb[kk - 1] += dd; Pxb[kk] -= dd;
-        u = Py[kk - 1] - Py[kk];  dd = wtr * u / smooth_abs(u, c.ea2);  Pyb[kk - 1] += dd; Pyb[kk] -= dd;
-        u = Px[kk] - Px[H];       dd = wtr * u / smooth_abs(u, c.ea2);  Pxb[kk] += dd;     Pxb[H] -= dd;
-        u = Py[kk] - Py[H];       dd = wtr * u / smooth_abs(u, c.ea2);  Pyb[kk] += dd;     Pyb[H] -= dd;
-        u = Px[kk - 1] - Px[H];   dd = wtr * u / smooth_abs(u, c.ea2);  Pxb[kk - 1] -= dd; Pxb[H] += dd;
-        u = Py[kk - 1] - Py[H];   dd = wtr * u / smooth_abs(u, c.ea2);  Pyb[kk - 1] -= dd; Pyb[H] += dd;
+    if (!c.per_phase) {
+        for (int kk = 1; kk <= H; ++kk) {
+            float u, dd;
+            u = Px[kk - 1] - Px[kk];  dd = wtr * u / smooth_abs(u, c.ea2);  Pxb[kk - 1] += dd; Pxb[kk] -= dd;
+            u = Py[kk - 1] - Py[kk];  dd = wtr * u / smooth_abs(u, c.ea2);  Pyb[kk - 1] += dd; Pyb[kk] -= dd;
+            u = Px[kk] - Px[H];       dd = wtr * u / smooth_abs(u, c.ea2);  Pxb[kk] += dd;     Pxb[H] -= dd;
+            u = Py[kk] - Py[H];       dd = wtr * u / smooth_abs(u, c.ea2);  Pyb[kk] += dd;     Pyb[H] -= dd;
+            u = Px[kk - 1] - Px[H];   dd = wtr * u / smooth_abs(u, c.ea2);  Pxb[kk - 1] -= dd; Pxb[H] += dd;
+            u = Py[kk - 1] - Py[H];   dd = wtr * u / smooth_abs(u, c.ea2);  Pyb[kk - 1] -= dd; Pyb[H] += dd;
+        }
+    } else {
+        // Per-phase split: term kk of L_traj is phase kk-1's and reaches only
+        // that phase's end P_kk (its start P_{kk-1} and the final P_H are other
+        // phases' constants); the last term, MH(P_H, P_H) = 2 eps_a, has no
+        // gradient.  The target and rotation terms stay on the last phase.
+        for (int kk = 1; kk < H; ++kk) {
+            float u, dd;
+            u = Px[kk - 1] - Px[kk];  dd = wtr * u / smooth_abs(u, c.ea2);  Pxb[kk] -= dd;
+            u = Py[kk - 1] - Py[kk];  dd = wtr * u / smooth_abs(u, c.ea2);  Pyb[kk] -= dd;
+            u = Px[kk] - Px[H];       dd = wtr * u / smooth_abs(u, c.ea2);  Pxb[kk] += dd;
+            u = Py[kk] - Py[H];       dd = wtr * u / smooth_abs(u, c.ea2);  Pyb[kk] += dd;
+        }
     }
 
     // adjoint of S_H (block 0 carries the cost's terms)
@@ -675,10 +689,20 @@ __device__ __forceinline__ void rollout_adj_lane(const SimConst& c, int N, const
         Ls.om = side_sum<SL>(L.om);
         const float Axs = side_sum<SL>(P0xb), Ays = side_sum<SL>(P0yb), Aphs = side_sum<SL>(Aphb);
         const float obs = side_sum<SL>(ob), Dbs = side_sum<SL>(Db);
+        if (c.per_phase) {
+            // S_k is the previous phase's output: its adjoint stops here, and
+            // the previous phase starts from its own term's seed on P_k
+            Ls.x = Ls.y = Ls.ph = Ls.vx = Ls.vy = Ls.om = 0.0f;
+        }
         if (b == 0) {
-            Ls.x += Axs + Pxb[kk];
-            Ls.y += Ays + Pyb[kk];
-            Ls.ph += Aphs;
+            if (c.per_phase) {
+                Ls.x = Pxb[kk];
+                Ls.y = Pyb[kk];
+            } else {
+                Ls.x += Axs + Pxb[kk];
+                Ls.y += Ays + Pyb[kk];
+                Ls.ph += Aphs;
+            }
             // bound loss on o_k, D_k
             const float wb2 = 2.0f * cb * c.wb;
             const float obt = obs + wb2 * relu(fabsf(o) - c.omax) * copysignf(1.0f, o);
@@ -734,12 +758,14 @@ __device__ __forceinline__ void adj_tile(const ProblemDesc& D, int i0, int l, co
                         grad + D.theta_off, seg + D.seg_off, status, lane);
 }
 
-__global__ __launch_bounds__(256) void k_rollout_fwd_batched(const ProblemDesc* __restrict__ descs,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_rollout_fwd_batched(const ProblemDesc* __restrict__ descs,
                                                              const int2* __restrict__ tiles, int ntiles,
                                                              const float* __restrict__ theta, float* __restrict__ cost,
                                                              float* __restrict__ tape, uint32_t* status) {
     const int waves = blockDim.x >> 6;
-    const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
+    // the wave index is uniform across the wave: readfirstlane lets the tile,
+    // its problem descriptor and the scene constants live in scalar registers
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), l = threadIdx.x & 63;
     for (int t = blockIdx.x * waves + wave; t < ntiles; t += gridDim.x * waves) {
         const int2 tl = tiles[t];
         const ProblemDesc& D = descs[tl.x];
@@ -752,14 +778,16 @@ __global__ __launch_bounds__(256) void k_rollout_fwd_batched(const ProblemDesc* 
     }
 }
 
-__global__ __launch_bounds__(256) void k_rollout_adj_batched(const ProblemDesc* __restrict__ descs,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_rollout_adj_batched(const ProblemDesc* __restrict__ descs,
                                                              const int2* __restrict__ tiles, int ntiles,
                                                              const float* __restrict__ theta,
                                                              const float* __restrict__ tape, float cb_scalar,
                                                              float* __restrict__ grad, float* __restrict__ seg,
                                                              uint32_t* status) {
     const int waves = blockDim.x >> 6;
-    const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
+    // the wave index is uniform across the wave: readfirstlane lets the tile,
+    // its problem descriptor and the scene constants live in scalar registers
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), l = threadIdx.x & 63;
     for (int t = blockIdx.x * waves + wave; t < ntiles; t += gridDim.x * waves) {
         const int2 tl = tiles[t];
         const ProblemDesc& D = descs[tl.x];

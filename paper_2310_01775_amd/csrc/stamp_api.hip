@@ -446,8 +446,8 @@ size_t stamp_solve_workspace_bytes(int32_t n_problems, const stamp_scene* scenes
 }
 
 int32_t stamp_rollout_fwd(stamp_ctx* ctx, const stamp_scene* scene, const stamp_cost_w* w, int32_t N,
-                          const float* theta, float* cost, float* tape, int32_t ckpt_every, uint32_t* status,
-                          void* stream) {
+                          const float* theta, float* cost, float* tape, size_t tape_len, int32_t ckpt_every,
+                          uint32_t* status, void* stream) {
     if (!ctx) return STAMP_EINVAL;
     if (!theta || !cost) return fail(ctx, STAMP_EINVAL, "null theta or cost");
     if (N < 1) return fail(ctx, STAMP_EINVAL, "N=%d < 1", N);
@@ -455,6 +455,8 @@ int32_t stamp_rollout_fwd(stamp_ctx* ctx, const stamp_scene* scene, const stamp_
     SimConst c;
     int r = derive(ctx, scene, w, &c);
     if (r) return r;
+    if (tape && tape_len < tape_floats(scene, N, ckpt_every))
+        return fail(ctx, STAMP_ENOSPACE, "tape %zu < %zu floats", tape_len, tape_floats(scene, N, ckpt_every));
     const TapeGeom g = tape_geom(scene, N, ckpt_every);
     hipError_t e = launch_rollout_fwd(c, N, theta, cost, tape, g, status, (hipStream_t)stream);
     return e == hipSuccess ? STAMP_OK : hip_fail(ctx, e, "rollout_fwd");
@@ -493,9 +495,10 @@ int32_t stamp_plan_readout(stamp_ctx* ctx, const stamp_scene* scene, const stamp
     return e == hipSuccess ? STAMP_OK : hip_fail(ctx, e, "plan_readout");
 }
 
-int32_t stamp_rollout_adj(stamp_ctx* ctx, const stamp_scene* scene, const stamp_cost_w* w, int32_t N,
-                          const float* theta, const float* tape, int32_t ckpt_every, const float* cost_bar,
-                          float* grad, void* workspace, size_t ws_bytes, uint32_t* status, void* stream) {
+static int32_t rollout_adj_impl(stamp_ctx* ctx, const stamp_scene* scene, const stamp_cost_w* w, int32_t N,
+                                const float* theta, const float* tape, size_t tape_len, int32_t ckpt_every,
+                                const float* cost_bar, float* grad, void* workspace, size_t ws_bytes,
+                                uint32_t* status, void* stream, int per_phase) {
     if (!ctx) return STAMP_EINVAL;
     if (!theta || !tape || !grad) return fail(ctx, STAMP_EINVAL, "null theta, tape or grad");
     if (N < 1) return fail(ctx, STAMP_EINVAL, "N=%d < 1", N);
@@ -503,13 +506,32 @@ int32_t stamp_rollout_adj(stamp_ctx* ctx, const stamp_scene* scene, const stamp_
     SimConst c;
     int r = derive(ctx, scene, w, &c);
     if (r) return r;
+    if (tape_len < tape_floats(scene, N, ckpt_every))
+        return fail(ctx, STAMP_ENOSPACE, "tape %zu < %zu floats", tape_len, tape_floats(scene, N, ckpt_every));
     const size_t need = adj_ws_bytes(scene, N, ckpt_every);
     if (need && (!workspace || ws_bytes < need))
         return fail(ctx, STAMP_ENOSPACE, "adjoint workspace %zu < %zu bytes", ws_bytes, need);
     const TapeGeom g = tape_geom(scene, N, ckpt_every);
+    c.per_phase = per_phase;
     hipError_t e = launch_rollout_adj(c, N, theta, tape, g, cost_bar, 1.0f, grad, (float*)workspace, status,
                                       (hipStream_t)stream);
     return e == hipSuccess ? STAMP_OK : hip_fail(ctx, e, "rollout_adj");
+}
+
+int32_t stamp_rollout_adj(stamp_ctx* ctx, const stamp_scene* scene, const stamp_cost_w* w, int32_t N,
+                          const float* theta, const float* tape, size_t tape_len, int32_t ckpt_every,
+                          const float* cost_bar, float* grad, void* workspace, size_t ws_bytes, uint32_t* status,
+                          void* stream) {
+    return rollout_adj_impl(ctx, scene, w, N, theta, tape, tape_len, ckpt_every, cost_bar, grad, workspace,
+                            ws_bytes, status, stream, 0);
+}
+
+int32_t stamp_rollout_adj_phases(stamp_ctx* ctx, const stamp_scene* scene, const stamp_cost_w* w, int32_t N,
+                                 const float* theta, const float* tape, size_t tape_len, int32_t ckpt_every,
+                                 const float* cost_bar, float* grad, void* workspace, size_t ws_bytes,
+                                 uint32_t* status, void* stream) {
+    return rollout_adj_impl(ctx, scene, w, N, theta, tape, tape_len, ckpt_every, cost_bar, grad, workspace,
+                            ws_bytes, status, stream, 1);
 }
 
 int32_t stamp_svgd_step(stamp_ctx* ctx, int32_t N, int32_t d, const float* theta, const float* grad_logp,
@@ -678,7 +700,7 @@ static int32_t solve_impl(stamp_ctx* ctx, int32_t n_problems, const stamp_scene*
         cfg->dsvgd > 1)
         return fail(ctx, STAMP_EINVAL, "bad solver cfg");
     if (cfg->dsvgd && sur) return fail(ctx, STAMP_EINVAL, "importance weights apply to the simulator iterations only");
-    if (cfg->reserved != 0) return fail(ctx, STAMP_EINVAL, "cfg->reserved must be 0");
+    if (cfg->per_phase < 0 || cfg->per_phase > 1) return fail(ctx, STAMP_EINVAL, "cfg->per_phase must be 0 or 1");
     // structured kernel: the push layout with K = each problem's H
     std::vector<StructKernel> skern;
     if (cfg->kernel) {
@@ -702,6 +724,7 @@ static int32_t solve_impl(stamp_ctx* ctx, int32_t n_problems, const stamp_scene*
     for (int p = 0; p < n_problems; ++p) {
         int r = derive(ctx, &scenes[p], &w[p], &consts[p]);
         if (r) return r;
+        consts[p].per_phase = cfg->per_phase;
         if (N[p] < 1) return fail(ctx, STAMP_EINVAL, "problem %d: N=%d < 1", p, N[p]);
         if (6 * scenes[p].H > kMaxSvgdDim || N[p] > kMaxSvgdN)
             return fail(ctx, STAMP_EUNSUPPORTED, "problem %d too large for the svgd step", p);
@@ -827,6 +850,7 @@ static int32_t solve_impl(stamp_ctx* ctx, int32_t n_problems, const stamp_scene*
             StampTune cand;
             const int persist = ctx->num_cus * 4;
             for (int block : {64, 128, 256}) {
+                if (n_problems == 1) break;  // a single problem takes the per-call rollout kernels
                 for (int grid : {0, persist}) {
                     cand.roll_block = block;
                     cand.roll_grid = grid;
@@ -867,6 +891,28 @@ static int32_t solve_impl(stamp_ctx* ctx, int32_t n_problems, const stamp_scene*
     }
     const BatchPlan B = batch_plan();
     const int rgrid = roll_grid(tune);
+    // Rollouts of the batch.  A single problem takes the per-call kernels,
+    // compiled for its block count (fewer registers than the batched kernel,
+    // which holds every block count's body: at 16 384 particles of 3 blocks the
+    // adjoint fits four waves per SIMD instead of three).
+    const bool single = n_problems == 1;
+    auto roll_fwd = [&](const float* th, float* cost, float* tape, uint32_t* stat) -> hipError_t {
+        if (single) {
+            const ProblemDesc& D = P.descs[0];
+            return launch_rollout_fwd(D.c, D.N, th + D.theta_off, cost + D.cost_off, tape ? tape + D.tape_off : nullptr,
+                                      D.g, stat, st);
+        }
+        return launch_rollout_fwd_batched(d_desc, d_roll, ntiles, tune.roll_block, rgrid, th, cost, tape, stat, st);
+    };
+    auto roll_adj = [&](uint32_t* stat) -> hipError_t {
+        if (single) {
+            const ProblemDesc& D = P.descs[0];
+            return launch_rollout_adj(D.c, D.N, theta + D.theta_off, d_tape + D.tape_off, D.g, nullptr, -1.0f,
+                                      d_grad + D.theta_off, d_seg + D.seg_off, stat, st);
+        }
+        return launch_rollout_adj_batched(d_desc, d_roll, ntiles, tune.roll_block, rgrid, theta, d_tape, -1.0f,
+                                          d_grad, d_seg, stat, st);
+    };
 
     // one SVGD iteration over every problem, captured once and replayed; with
     // importance weights (Eq. 4) each particle's discrete plan is rolled out
@@ -930,21 +976,15 @@ static int32_t solve_impl(stamp_ctx* ctx, int32_t n_problems, const stamp_scene*
     auto iteration = [&]() -> hipError_t {
         hipError_t r;
         if ((r = fork(1)) != hipSuccess) return r;
-        if ((r = launch_rollout_fwd_batched(d_desc, d_roll, ntiles, tune.roll_block, rgrid, theta,
-                                            (float*)(ws + P.cost_off), d_tape, status, st)) != hipSuccess)
-            return r;
-        if ((r = launch_rollout_adj_batched(d_desc, d_roll, ntiles, tune.roll_block, rgrid, theta, d_tape, -1.0f,
-                                            d_grad, d_seg, status, st)) != hipSuccess)
-            return r;
+        if ((r = roll_fwd(theta, (float*)(ws + P.cost_off), d_tape, status)) != hipSuccess) return r;
+        if ((r = roll_adj(status)) != hipSuccess) return r;
         if (cfg->dsvgd) {
             for (int p = 0; p < n_problems; ++p) {
                 const ProblemDesc& D = P.descs[p];
                 if ((r = launch_onehot(D.N, scenes[p].H, theta + D.theta_off, d_phi + D.theta_off, st)) != hipSuccess)
                     return r;
             }
-            if ((r = launch_rollout_fwd_batched(d_desc, d_roll, ntiles, tune.roll_block, rgrid, d_phi, d_cdisc,
-                                                nullptr, status, st)) != hipSuccess)
-                return r;
+            if ((r = roll_fwd(d_phi, d_cdisc, nullptr, status)) != hipSuccess) return r;
             if ((r = launch_dsvgd_weights_batched(n_problems, d_desc, (const float*)(ws + P.cost_off), d_cdisc,
                                                   d_wts, st)) != hipSuccess)
                 return r;
@@ -956,12 +996,8 @@ static int32_t solve_impl(stamp_ctx* ctx, int32_t n_problems, const stamp_scene*
     // one SGD refinement iteration: the update takes phi = grad log rho
     auto sgd_iteration = [&]() -> hipError_t {
         hipError_t r;
-        if ((r = launch_rollout_fwd_batched(d_desc, d_roll, ntiles, tune.roll_block, rgrid, theta,
-                                            (float*)(ws + P.cost_off), d_tape, status, st)) != hipSuccess)
-            return r;
-        if ((r = launch_rollout_adj_batched(d_desc, d_roll, ntiles, tune.roll_block, rgrid, theta, d_tape, -1.0f,
-                                            d_grad, d_seg, status, st)) != hipSuccess)
-            return r;
+        if ((r = roll_fwd(theta, (float*)(ws + P.cost_off), d_tape, status)) != hipSuccess) return r;
+        if ((r = roll_adj(status)) != hipSuccess) return r;
         if ((r = launch_update(P.n_theta, theta, d_grad, adam_m, adam_v, cfg->t0, d_ctr, cfg->lr, cfg->beta1,
                                cfg->beta2, cfg->adam_eps, cfg->use_adam, st)) != hipSuccess)
             return r;
@@ -1099,9 +1135,7 @@ static int32_t solve_impl(stamp_ctx* ctx, int32_t n_problems, const stamp_scene*
             int32_t r = run_iterations(ctx->g_sur, sk, chunk, sur_iteration);
             if (r) return r;
             run += chunk;
-            STAMP_TRY(launch_rollout_fwd_batched(d_desc, d_roll, ntiles, tune.roll_block, rgrid, theta, c_true,
-                                                 nullptr, status, st),
-                      "check rollout");
+            STAMP_TRY(roll_fwd(theta, c_true, nullptr, status), "check rollout");
             for (int p = 0; p < n_problems; ++p) STAMP_TRY(sur_infer(p, d_phi, nullptr, 1.0f), "check network");
             STAMP_TRY(launch_log_err(d_desc, n_problems, c_true, d_phi, d_err, st), "check error");
             STAMP_TRY(hipMemcpyAsync(h_err.data(), d_err, n_problems * sizeof(float), hipMemcpyDeviceToHost, st),
@@ -1131,9 +1165,7 @@ static int32_t solve_impl(stamp_ctx* ctx, int32_t n_problems, const stamp_scene*
         if (r) return r;
     }
     // final true cost and discrete plan of every particle
-    STAMP_TRY(launch_rollout_fwd_batched(d_desc, d_roll, ntiles, tune.roll_block, rgrid, theta, cost_out, nullptr,
-                                         status, st),
-              "final rollout");
+    STAMP_TRY(roll_fwd(theta, cost_out, nullptr, status), "final rollout");
     if (modes_out) {
         int64_t m_off = 0;
         for (int p = 0; p < n_problems; ++p) {

@@ -90,7 +90,8 @@ def test_sizing_rejects_bad_arguments():
 def test_null_context_is_rejected():
     import paper_2310_01775_amd as S
     lib = S._lib
-    assert lib.stamp_rollout_fwd(None, None, None, 1, None, None, None, 0, None, None) == S.EINVAL
+    assert lib.stamp_rollout_fwd(None, None, None, 1, None, None, None, 0, 0, None, None) == S.EINVAL
+    assert lib.stamp_rollout_adj(None, None, None, 1, None, None, 0, 0, None, None, None, 0, None, None) == S.EINVAL
     assert lib.stamp_svgd_step(None, 1, 1, None, None, 0.0, None, None, None, 0, None) == S.EINVAL
     assert lib.stamp_create(None, 0) == S.EINVAL
 

@@ -3,7 +3,9 @@
 FP32 tolerance: each step's force evaluation rounds at ~6e-8 relative and the
 trajectory carries the error forward through T steps; the measured relative
 error of the cost stays well under the 1e-4 that the FP32 paths are held to.
-Gradients are compared relative to each particle's largest gradient entry."""
+Gradients are compared relative to each particle's largest gradient entry
+(bar 2e-4; measured <= 3.0e-5: FP32 rounding of the stiff contact derivatives
+carried back through the trajectory)."""
 import numpy as np
 import pytest
 import torch
@@ -78,7 +80,7 @@ def test_adjoint_matches_oracle_gradient(ctx, label, builder, N):
     scale = np.abs(ref).max(axis=1, keepdims=True) + 1e-6
     err = (np.abs(g - ref) / scale).max()
     print("max grad err / particle scale", err, flush=True)
-    assert err < 1e-3
+    assert err < 2e-4  # measured <= 3.0e-5 over these scenes
 
 
 @pytest.mark.parametrize("K", [1, 7, 32])
@@ -134,7 +136,7 @@ def test_argument_errors(ctx):
     bad = S.make_scene(scene)
     bad.H = 9
     with pytest.raises(S.StampError) as e:
-        ctx.rollout_fwd(bad, cw, theta)
+        ctx.rollout_fwd(bad, cw, torch.zeros(54, 4, device="cuda"))
     assert e.value.code == S.EINVAL and "H=9" in str(e.value)
     bad = S.make_scene(scene)
     bad.dt = 0.0
@@ -146,3 +148,41 @@ def test_argument_errors(ctx):
     with pytest.raises(S.StampError) as e:
         ctx.rollout_adj(sc, cw, theta, tape, ckpt_every=8, workspace=small)
     assert e.value.code == S.ENOSPACE
+
+
+def test_tape_length_and_particle_shape_are_checked(ctx):
+    """The binding rejects a theta of the wrong dtype or dimension and a tape
+    shorter than stamp_tape_floats for the tape mode in use; the C ABI itself
+    returns STAMP_ENOSPACE for a short tape before enqueuing anything."""
+    import ctypes as C
+    import paper_2310_01775_amd as S
+    scene = W.make_scene(2, 0, 2, 3, 60, 0.005)
+    sc, cw = S.make_scene(scene), S.make_cost(W.cost_weights())
+    th = W.make_particles(2, 0, 8, 3)
+    theta = S.soa(th)
+    with pytest.raises(ValueError):
+        ctx.rollout_fwd(sc, cw, theta.double())
+    with pytest.raises(ValueError):
+        ctx.rollout_fwd(sc, cw, theta[:12].contiguous())
+    full = ctx.tape_floats(sc, 8, 0)
+    ck = ctx.tape_floats(sc, 8, 4)
+    assert ck < full
+    short = torch.empty(ck, dtype=torch.float32, device="cuda")
+    with pytest.raises(ValueError):
+        ctx.rollout_fwd(sc, cw, theta, tape=short, ckpt_every=0)  # sized for checkpoints, used as full
+    cost = torch.empty(8, dtype=torch.float32, device="cuda")
+    rc = S._lib.stamp_rollout_fwd(ctx._h, C.byref(sc), C.byref(cw), 8, C.c_void_p(theta.data_ptr()),
+                                  C.c_void_p(cost.data_ptr()), C.c_void_p(short.data_ptr()), ck, 0, None,
+                                  S._stream())
+    assert rc == S.ENOSPACE
+    grad = torch.empty_like(theta)
+    rc = S._lib.stamp_rollout_adj(ctx._h, C.byref(sc), C.byref(cw), 8, C.c_void_p(theta.data_ptr()),
+                                  C.c_void_p(short.data_ptr()), ck, 0, None, C.c_void_p(grad.data_ptr()), None, 0,
+                                  None, S._stream())
+    assert rc == S.ENOSPACE
+    ctx.rollout_fwd(sc, cw, theta, tape=short, ckpt_every=4)  # the right mode is accepted
+    with pytest.raises(ValueError):
+        ctx.rollout_adj(sc, cw, theta, short, ckpt_every=4, cost_bar=torch.ones(7, device="cuda"))
+    g = ctx.rollout_adj(sc, cw, theta, short, ckpt_every=4)
+    torch.cuda.synchronize()
+    assert torch.isfinite(g).all()

@@ -201,3 +201,69 @@ def test_fused_direction_update_equals_direction_then_update(ctx, N, d, use_adam
     assert torch.equal(phi_a, phi_b) and torch.equal(a, b)
     if use_adam:
         assert torch.equal(ma, mb) and torch.equal(va, vb)
+
+
+# --------------------------------------------------------------------------
+# Full size of the surrogate workload: N = 16384 particles of d = 30 (5 pushes).
+# The contraction runs its 2048-column splits and the median its Gram-form
+# passes here; the oracle computes phi on 512 sampled rows (svgd_phi_rows,
+# pinned against the full svgd_phi) and the exact median over all 134 M pairs.
+FULL_N, FULL_D, FULL_ROWS = 16384, 30, 512
+
+
+def _full_case():
+    """The surrogate workload's initial particles (cfg5 scene sampler) and a
+    gradient of the rollout's magnitude, FP32-rounded."""
+    _, _, th = W.config_problem(5)
+    assert th.shape == (FULL_N, FULL_D)
+    rng = np.random.default_rng(16384)
+    g = W.f32(rng.standard_normal(th.shape) * 20.0)
+    rows = np.sort(rng.choice(FULL_N, FULL_ROWS, replace=False))
+    rows[0], rows[-1] = 0, FULL_N - 1  # first and last row of the split grid
+    return th, g, rows
+
+
+def test_full_size_median_is_the_exact_order_statistic(ctx):
+    import paper_2310_01775_amd as S
+    th, g, _ = _full_case()
+    print("case N=16384 d=30 exact median", flush=True)
+    h_out = torch.zeros(1, dtype=torch.float32, device="cuda")
+    ctx.svgd_step(S.soa(th), S.soa(g), 0.0, h_out=h_out)
+    torch.cuda.synchronize()
+    m2 = float(h_out.item()) * math.log(FULL_N)
+    ref = svgd.median_sqdist_blocked(th)
+    print("median gpu/oracle", m2 / ref, flush=True)
+    assert abs(m2 - ref) <= 3e-6 * ref
+
+
+def test_full_size_fp32_phi_matches_oracle_on_sampled_rows(ctx):
+    import paper_2310_01775_amd as S
+    th, g, rows = _full_case()
+    print("case N=16384 d=30 FP32 phi, 512 rows", flush=True)
+    h_out = torch.zeros(1, dtype=torch.float32, device="cuda")
+    phi = ctx.svgd_step(S.soa(th), S.soa(g), 0.0, h_out=h_out)
+    torch.cuda.synchronize()
+    h = float(h_out.item())  # the exact median is checked by the test above
+    got = S.aos(phi)[rows]
+    ref = svgd.svgd_phi_rows(th, g, h, rows)
+    scale = np.abs(ref).max(axis=0, keepdims=True) + 1e-9
+    err = (np.abs(got - ref) / scale).max()
+    print("phi err (coordinate-scaled)", err, flush=True)
+    assert err < 2e-5
+    assert np.isfinite(S.aos(phi)).all()
+
+
+def test_full_size_bf16_phi_matches_oracle_at_its_bandwidth(ctx):
+    import paper_2310_01775_amd as S
+    th, g, rows = _full_case()
+    print("case N=16384 d=30 BF16 phi, 512 rows", flush=True)
+    h_out = torch.zeros(1, dtype=torch.float32, device="cuda")
+    phi = ctx.svgd_step_bf16(S.soa(th), S.soa(g), 0.0, h_out=h_out)
+    torch.cuda.synchronize()
+    h = float(h_out.item())
+    got = S.aos(phi)[rows]
+    ref = svgd.svgd_phi_rows(th, g, h, rows)
+    err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    print("bf16 normwise error", err, flush=True)
+    assert err < 2e-2  # the BF16 bar (8-bit significands, FP32 accumulation)
+    assert np.isfinite(S.aos(phi)).all()
