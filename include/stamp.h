@@ -62,6 +62,9 @@ extern "C" {
 #define STAMP_MLP_BF16_WEIGHTS 163840 /* bf16 elements of the working copies */
 #define STAMP_SCENE_ENC 24           /* floats of the scene encoding */
 
+/* scratch bytes each GPU holds for stamp_svgd_step_noalloc */
+#define STAMP_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+
 /* bits of the device status word */
 #define STAMP_STATUS_NONFINITE_COST 1u
 #define STAMP_STATUS_NONFINITE_GRAD 2u
@@ -221,6 +224,23 @@ int32_t stamp_rollout_adj_phases(stamp_ctx* ctx, const stamp_scene* scene, const
 int32_t stamp_svgd_step(stamp_ctx* ctx, int32_t N, int32_t d, const float* theta,
                         const float* grad_logp, float bandwidth, float* phi, float* h_out,
                         void* workspace, size_t ws_bytes, void* stream);
+
+/* stamp_svgd_step without a workspace argument, for callers that cannot
+ * allocate: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  The step's scratch (median select state and candidates,
+ * operand tiles, partial sums) lives in a device array of
+ * STAMP_NOALLOC_SCRATCH_BYTES (64 MiB) that each GPU the library runs on holds
+ * from the library's load until the process ends; the call allocates nothing.
+ * Results equal stamp_svgd_step's for the same arguments bit for bit (the
+ * same kernels).  The array is shared by every call on a GPU and keeps the last
+ * call's contents (nothing in it needs to start at zero): calls that overlap
+ * on one GPU -- from two streams or two contexts -- race and give undefined
+ * results; serialise them.
+ * Errors as stamp_svgd_step; STAMP_ENOSPACE when stamp_svgd_workspace_bytes(N, d)
+ * exceeds the array (it fits N <= 4096 particles at d <= 36, e.g. 4096 x 30). */
+int32_t stamp_svgd_step_noalloc(stamp_ctx* ctx, int32_t N, int32_t d, const float* theta,
+                                const float* grad_logp, float bandwidth, float* phi, float* h_out,
+                                void* stream);
 
 /* stamp_svgd_step in two halves, for callers that overlap the bandwidth with
  * the rollout (it depends on theta only):

@@ -106,6 +106,7 @@ _sig = {
                                         _sz, _vp, _vp]),
     "stamp_svgd_step": (_i32, [_vp, _i32, _i32, _vp, _vp, _f32, _vp, _vp, _vp, _sz, _vp]),
     "stamp_svgd_step_bf16": (_i32, [_vp, _i32, _i32, _vp, _vp, _f32, _vp, _vp, _vp, _sz, _vp]),
+    "stamp_svgd_step_noalloc": (_i32, [_vp, _i32, _i32, _vp, _vp, _f32, _vp, _vp, _vp]),
     "stamp_adam_step": (_i32, [_vp, _i64, _vp, _vp, _vp, _vp, _i32, _f32, _f32, _f32, _f32, _i32, _vp]),
     "stamp_solve": (_i32, [_vp, _i32, _P(Scene), _P(CostW), _P(_i32), _P(SolverCfg), _vp, _vp, _vp, _vp,
                            _vp, _vp, _vp, _sz, _vp, _vp]),
@@ -456,6 +457,20 @@ class Context:
         self._check(_lib.stamp_svgd_step(self._h, N, d, _ptr(theta), _ptr(grad_logp), float(bandwidth),
                                          _ptr(phi), _ptr(h_out), _ptr(workspace), workspace.numel(),
                                          _stream(stream)))
+        return phi
+
+    def svgd_step_noalloc(self, theta: torch.Tensor, grad_logp: torch.Tensor, bandwidth: float = 0.0, phi=None,
+                          h_out=None, stream=None):
+        """stamp_svgd_step_noalloc: the step without a workspace (the library's
+        per-device scratch array; calls on one GPU must not overlap)."""
+        d, N = theta.shape
+        for t in (theta, grad_logp):
+            if t.dtype != torch.float32 or t.shape != (d, N):
+                raise ValueError("theta and grad_logp must be float32 [d][N]")
+        if phi is None:
+            phi = torch.empty_like(theta)
+        self._check(_lib.stamp_svgd_step_noalloc(self._h, N, d, _ptr(theta), _ptr(grad_logp), float(bandwidth),
+                                                 _ptr(phi), _ptr(h_out), _stream(stream)))
         return phi
 
     def svgd_step_bf16(self, theta: torch.Tensor, grad_logp: torch.Tensor, bandwidth: float = 0.0, phi=None,

@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -48,7 +49,36 @@ struct stamp_ctx {
         }
     };
     IterGraphs g_svgd, g_sur, g_sgd;
+    void* scratch = nullptr;  // this device's copy of the no-alloc scratch array (device address)
 };
+
+// Scratch memory of stamp_svgd_step_noalloc: a file-scope device array that
+// each GPU holds from the library's load until the process ends.  Host code
+// never uses the array's name (a host-side stand-in, not a device address):
+// stamp_create looks up each device's address with hipGetSymbolAddress, with
+// that device current, and every launch takes that pointer.
+static __device__ __align__(256) unsigned char scratch[STAMP_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_addr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device `device` (looked up once).
+hipError_t scratch_address(int device, void** out) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    if (!g_scratch_addr[device]) {
+        void* p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_addr[device] = p;
+    }
+    *out = g_scratch_addr[device];
+    return hipSuccess;
+}
+}  // namespace
 
 namespace stamp {
 namespace {
@@ -374,8 +404,9 @@ int32_t stamp_create(stamp_ctx** ctx, int32_t device) {
         hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
-        delete c;
+        hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess ||
+        scratch_address(device, &c->scratch) != hipSuccess) {
+        stamp_destroy(c);
         return STAMP_EHIP;
     }
     *ctx = c;
@@ -549,6 +580,25 @@ int32_t stamp_svgd_step(stamp_ctx* ctx, int32_t N, int32_t d, const float* theta
     hipError_t e = launch_svgd(N, d, theta, grad_logp, bandwidth, phi, h_out, workspace, L, 0, nullptr,
                                (hipStream_t)stream);
     return e == hipSuccess ? STAMP_OK : hip_fail(ctx, e, "svgd_step");
+}
+
+int32_t stamp_svgd_step_noalloc(stamp_ctx* ctx, int32_t N, int32_t d, const float* theta, const float* grad_logp,
+                                float bandwidth, float* phi, float* h_out, void* stream) {
+    if (!ctx) return STAMP_EINVAL;
+    if (!theta || !grad_logp || !phi) return fail(ctx, STAMP_EINVAL, "null theta, grad_logp or phi");
+    if (N < 1 || d < 1) return fail(ctx, STAMP_EINVAL, "N=%d, d=%d must be >= 1", N, d);
+    if (d > kMaxSvgdDim || N > kMaxSvgdN)
+        return fail(ctx, STAMP_EUNSUPPORTED, "svgd step supports d <= %d, N <= %d", kMaxSvgdDim, kMaxSvgdN);
+    if (!isfinite(bandwidth)) return fail(ctx, STAMP_EINVAL, "non-finite bandwidth");
+    const SvgdLayout L = svgd_workspace_layout(N, d);
+    if (L.total > (size_t)STAMP_NOALLOC_SCRATCH_BYTES)
+        return fail(ctx, STAMP_ENOSPACE, "N=%d, d=%d needs %zu bytes of scratch; the no-alloc step holds %zu "
+                                         "(use stamp_svgd_step with a workspace)",
+                    N, d, L.total, (size_t)STAMP_NOALLOC_SCRATCH_BYTES);
+    if (!ctx->scratch) return fail(ctx, STAMP_EHIP, "no scratch address on device %d", ctx->device);
+    hipError_t e = launch_svgd(N, d, theta, grad_logp, bandwidth, phi, h_out, ctx->scratch, L, 0, nullptr,
+                               (hipStream_t)stream);
+    return e == hipSuccess ? STAMP_OK : hip_fail(ctx, e, "svgd_step_noalloc");
 }
 
 int32_t stamp_svgd_bandwidth(stamp_ctx* ctx, int32_t N, int32_t d, const float* theta, float bandwidth, float* h_out,
