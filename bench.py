@@ -225,13 +225,15 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--workload", default="surrogate",
-                    choices=["surrogate", "plain", "batched", "long", "refine", "structured", "surrogate-report"],
+                    choices=["surrogate", "plain", "batched", "long", "refine", "structured", "surrogate-report",
+                             "kernels"],
                     help="surrogate (default): the metric's workload, the surrogate form against the plain "
                          "method at N=16384; plain: per-call SVGD iterations at N=1024, B=3, H=3; batched: 64 "
                          "uneven problems in one graph-replayed solve; long: checkpointed and per-phase "
                          "differentiation at T=1000; refine: SVGD alone against SVGD followed by SGD refinement, "
                          "with the plan read-out; structured: the structured pusher kernel against the RBF "
-                         "kernel; surrogate-report: the network's accuracy and both direction forms")
+                         "kernel; surrogate-report: the network's accuracy and both direction forms; kernels: "
+                         "the default line's stage timings alone (for kernel traces and counters)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -251,7 +253,8 @@ def main():
               "[theta | grad] per iteration; see DESIGN.md)", file=sys.stderr)
         sys.exit(2)
     fn = {"surrogate": bench_headline, "plain": bench_plain_line, "batched": bench_batched, "long": bench_long,
-          "refine": bench_refine, "structured": bench_structured, "surrogate-report": bench_surrogate}
+          "refine": bench_refine, "structured": bench_structured, "surrogate-report": bench_surrogate,
+          "kernels": bench_kernels}
     return fn[args.workload](args)
 
 
@@ -270,6 +273,60 @@ def _time_launches(fn, reps=10, warm=2):
         b.record()
     torch.cuda.synchronize()
     return float(np.mean([a.elapsed_time(b) for a, b in evs]))
+
+
+def stage_timings(ctx, sc, cw, theta0, params, wbf16, n_in, enc):
+    """Per-call launches of each stage of the surrogate-form solve at its
+    shape, timed with HIP events on the stream they run on (ms, mean of 10):
+    the rollout forward and adjoint (the single-problem solve runs these very
+    kernels), the exact FP32 bandwidth stage, the FP32 direction stage (V
+    packing, the matrix-core contraction k_phi32, the reduce), the network's
+    cost and input gradient, and the BF16 step."""
+    import torch
+    d, N = theta0.shape
+    tape = torch.empty(ctx.tape_floats(sc, N, 0), dtype=torch.float32, device="cuda")
+    cost = torch.empty(N, dtype=torch.float32, device="cuda")
+    grad = torch.empty_like(theta0)
+    minus = torch.full((N,), -1.0, device="cuda")
+    sws = ctx._bytes(ctx.svgd_workspace_bytes(N, d))
+    th = theta0.clone()
+    ctx.rollout_fwd(sc, cw, th, tape=tape, cost=cost)
+    ctx.rollout_adj(sc, cw, th, tape, cost_bar=minus, grad=grad)
+    ms = {
+        "rollout_fwd": _time_launches(lambda: ctx.rollout_fwd(sc, cw, th, tape=tape, cost=cost)),
+        "rollout_adj": _time_launches(lambda: ctx.rollout_adj(sc, cw, th, tape, cost_bar=minus, grad=grad)),
+        "bandwidth_fp32_exact": _time_launches(lambda: ctx.svgd_bandwidth(th, 0.0, workspace=sws)),
+    }
+    ctx.svgd_bandwidth(th, 0.0, workspace=sws)
+    phi = torch.empty_like(th)
+    ms["direction_fp32"] = _time_launches(lambda: ctx.svgd_direction(th, grad, sws, phi=phi))
+    ms["mlp_infer"] = _time_launches(lambda: ctx.mlp_forward(params, wbf16, th, n_in, d, x_layout=1, enc=enc,
+                                                             want_y=False, grad=grad, grad_scale=-1.0, w=cw))
+    ms["step_bf16"] = _time_launches(lambda: ctx.svgd_step_bf16(th, grad, phi=phi, workspace=sws))
+    return ms
+
+
+def bench_kernels(args):
+    """The stage timings of the default line alone (no training: the network
+    takes its seeded initial weights, which time the same), so that a kernel
+    trace of this command holds exactly the launches the line's roofline
+    reads."""
+    import torch
+
+    import paper_2310_01775_amd as S
+    import workloads as W
+    torch.cuda.set_device(0)
+    ctx = S.Context(0)
+    scene, w, th0 = W.config_problem(5)
+    H = int(scene["H"])
+    n_in = 6 * H + W.SCENE_ENC
+    params = torch.as_tensor(S.pack_mlp(W.mlp_init(n_in, seed=0)), device="cuda")
+    wbf16 = ctx.mlp_weights()
+    ctx.mlp_prepare(params, wbf16)
+    enc = torch.as_tensor(W.scene_encoding(scene), dtype=torch.float32, device="cuda")
+    ms = stage_timings(ctx, S.make_scene(scene), S.make_cost(w), S.soa(th0), params, wbf16, n_in, enc)
+    ctx.close()
+    print(json.dumps({"workload": "stage timings at N=16384, B=3, H=5 (d=30), T=200", "kernels_ms": ms}), flush=True)
 
 
 def bench_headline(args):
@@ -349,29 +406,7 @@ def bench_headline(args):
     plain_value = N * iters * args.steps / wall_p
     cs, cp = stats(cost_s), stats(cost_p)
 
-    # per-call launches of each stage's kernel at this shape, timed with HIP
-    # events on the stream they run on; the solve's single-problem rollout
-    # is the same kernel (k_rollout_fwd<3>, k_rollout_adj<3>)
-    tape = torch.empty(ctx.tape_floats(sc, N, 0), dtype=torch.float32, device="cuda")
-    cost = torch.empty(N, dtype=torch.float32, device="cuda")
-    grad = torch.empty_like(theta0)
-    minus = torch.full((N,), -1.0, device="cuda")
-    sws = ctx._bytes(ctx.svgd_workspace_bytes(N, d))
-    th = theta0.clone()
-    ctx.rollout_fwd(sc, cw, th, tape=tape, cost=cost)
-    ctx.rollout_adj(sc, cw, th, tape, cost_bar=minus, grad=grad)
-    ms = {
-        "rollout_fwd": _time_launches(lambda: ctx.rollout_fwd(sc, cw, th, tape=tape, cost=cost)),
-        "rollout_adj": _time_launches(lambda: ctx.rollout_adj(sc, cw, th, tape, cost_bar=minus, grad=grad)),
-        "bandwidth_fp32_exact": _time_launches(lambda: ctx.svgd_bandwidth(th, 0.0, workspace=sws)),
-    }
-    ctx.svgd_bandwidth(th, 0.0, workspace=sws)
-    phi = torch.empty_like(th)
-    ms["direction_fp32"] = _time_launches(lambda: ctx.svgd_direction(th, grad, sws, phi=phi))
-    ms["mlp_infer"] = _time_launches(lambda: ctx.mlp_forward(net.params, net.wbf16, th, n_in, d, x_layout=1,
-                                                             enc=enc, want_y=False, grad=grad, grad_scale=-1.0,
-                                                             w=cw))
-    ms["step_bf16"] = _time_launches(lambda: ctx.svgd_step_bf16(th, grad, phi=phi, workspace=sws))
+    ms = stage_timings(ctx, sc, cw, theta0, net.params, net.wbf16, n_in, enc)
     # launches per surrogate-form solve: simulator iterations, network
     # iterations, simulator checks every 80 network iterations, final cost
     n_sim, n_net, n_chk = iters - s_iters, s_iters, s_iters // 80

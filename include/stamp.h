@@ -151,6 +151,21 @@ int32_t stamp_set_launch_shape(stamp_ctx* ctx, int32_t roll_block, int32_t roll_
 
 /* ---- sizing (host only, no GPU work) ------------------------------------- */
 
+/* Rollout lane layout (results are the same bit for bit; only speed differs):
+ * STAMP_LAYOUT_BLOCKS gives each block of a (particle, side) sub-rollout its
+ * own lane (more waves: faster while the rollout is latency-bound on a small
+ * particle set), STAMP_LAYOUT_PACKED one lane per sub-rollout holding all its
+ * blocks (about half the instructions per particle), for the forward and the
+ * adjoint alike.  STAMP_LAYOUT_AUTO (default): the forward keeps one lane per
+ * block (its tape stores coalesce better), the adjoint takes the packed
+ * layout once the block-per-lane form would need 2^17 lanes (two waves per
+ * SIMD), e.g. from 8192 particles of 3 or 4 blocks.  Applies to every rollout
+ * of the context's later calls.  STAMP_EINVAL for another value. */
+#define STAMP_LAYOUT_AUTO 0
+#define STAMP_LAYOUT_BLOCKS 1
+#define STAMP_LAYOUT_PACKED 2
+int32_t stamp_set_rollout_layout(stamp_ctx* ctx, int32_t layout);
+
 /* Floats of the rollout tape for N particles.  ckpt_every = 0 keeps the full
  * trajectory; K > 0 keeps a checkpoint every K steps inside each push phase.
  * Layout: [n_entries][4N][6B] then the phase-end block [H][4N][6B]: lane

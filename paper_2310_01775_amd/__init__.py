@@ -24,6 +24,7 @@ if not os.path.exists(LIB_PATH):
 _lib = C.CDLL(LIB_PATH)
 
 OK, EINVAL, ENOSPACE, EHIP, EUNSUPPORTED = 0, -1, -2, -3, -4
+LAYOUT_AUTO, LAYOUT_BLOCKS, LAYOUT_PACKED = 0, 1, 2
 STATUS_NONFINITE_COST, STATUS_NONFINITE_GRAD, STATUS_NONFINITE_PHI, STATUS_BAD_INDEX = 1, 2, 4, 8
 MAX_BLOCKS, MAX_PUSHES, MODES = 4, 8, 4
 
@@ -85,6 +86,7 @@ _sig = {
     "stamp_version": (C.c_char_p, []),
     "stamp_set_autotune": (_i32, [_vp, _i32]),
     "stamp_set_launch_shape": (_i32, [_vp, _i32, _i32, _i32]),
+    "stamp_set_rollout_layout": (_i32, [_vp, _i32]),
     "stamp_tape_floats": (_sz, [_P(Scene), _i32, _i32]),
     "stamp_adj_workspace_bytes": (_sz, [_P(Scene), _i32, _i32]),
     "stamp_readout_workspace_bytes": (_sz, [_P(Scene), _i32]),
@@ -266,6 +268,10 @@ class Context:
 
     def set_autotune(self, enable: bool):
         self._check(_lib.stamp_set_autotune(self._h, int(bool(enable))))
+
+    def set_rollout_layout(self, layout: int):
+        """stamp_set_rollout_layout: LAYOUT_AUTO, LAYOUT_BLOCKS or LAYOUT_PACKED."""
+        self._check(_lib.stamp_set_rollout_layout(self._h, int(layout)))
 
     def set_launch_shape(self, roll_block=0, roll_grid=0, phi_rows=0):
         self._check(_lib.stamp_set_launch_shape(self._h, int(roll_block), int(roll_grid), int(phi_rows)))

@@ -9,20 +9,22 @@
 
 namespace stamp {
 
+// packed: one lane per (particle, side) holding all B blocks, instead of one
+// lane per block (same results bit for bit, same tape layout).
 hipError_t launch_rollout_fwd(const SimConst& c, int N, const float* theta, float* cost, float* tape,
-                              const TapeGeom& g, uint32_t* status, hipStream_t st);
+                              const TapeGeom& g, uint32_t* status, hipStream_t st, bool packed);
 hipError_t launch_rollout_adj(const SimConst& c, int N, const float* theta, const float* tape,
                               const TapeGeom& g, const float* cost_bar, float cb_scalar, float* grad,
-                              float* seg, uint32_t* status, hipStream_t st);
+                              float* seg, uint32_t* status, hipStream_t st, bool packed);
 
 // Particles per 64-lane rollout tile of a problem with B blocks.
-int rollout_tile_particles(int B);
+int rollout_tile_particles(int B, bool packed);
 hipError_t launch_rollout_fwd_batched(const ProblemDesc* descs, const int2* tiles, int ntiles, int block,
                                       int grid, const float* theta, float* cost, float* tape, uint32_t* status,
-                                      hipStream_t st);
+                                      hipStream_t st, bool packed);
 hipError_t launch_rollout_adj_batched(const ProblemDesc* descs, const int2* tiles, int ntiles, int block,
                                       int grid, const float* theta, const float* tape, float cb_scalar,
-                                      float* grad, float* seg, uint32_t* status, hipStream_t st);
+                                      float* grad, float* seg, uint32_t* status, hipStream_t st, bool packed);
 
 // SVGD step of one problem.  h: when bandwidth > 0 it is used as is; otherwise
 // the median heuristic runs and writes h into the workspace (and h_out if

@@ -719,6 +719,494 @@ __device__ __forceinline__ void rollout_adj_lane(const SimConst& c, int N, const
 }
 
 // ---------------------------------------------------------------------------
+// Packed lanes: one lane per (particle i, side s) sub-rollout, holding all B
+// blocks (lane = 4i + s).  A step then costs B frictions, B(B-1)/2 pair terms
+// (each once) and one pusher per lane, with no cross-lane moves, instead of
+// 4 SL lanes per particle that repeat every pair term twice and the pusher on
+// every block slot (at B = 3 one slot in four idles).  It rounds exactly as
+// the block-per-lane form: each block's forces add in the same order
+// (friction, partners by increasing index, pusher), the higher block of a
+// pair takes the lower block's term with Delta negated (negation is exact),
+// and the sides and blocks meet in the same sums.  Same tape layout.
+
+// One semi-implicit Euler step of all B blocks of a sub-rollout.
+template <int B>
+__device__ __forceinline__ void step_forward_packed(const SimConst& c, Blk (&X)[B], const Push& p, float sig) {
+    float Fx[B], Fy[B], Tq[B];
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+        const float inv = hw_rsq(fmaf(X[b].vx, X[b].vx, fmaf(X[b].vy, X[b].vy, c.ev2[b])));
+        const float kf = c.cf[b] * inv;
+        Fx[b] = -kf * X[b].vx;
+        Fy[b] = -kf * X[b].vy;
+        const float invw = hw_rsq(fmaf(X[b].om, X[b].om, c.ew2[b]));
+        Tq[b] = -(c.cr[b] * invw) * X[b].om;
+    }
+    // pair terms, once per pair b < q: Delta = x_b - x_q, force fr Delta on b
+    float pdx[B][B], pdy[B][B], pfr[B][B];
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+#pragma unroll
+        for (int q = b + 1; q < B; ++q) {
+            const float dx = X[b].x - X[q].x, dy = X[b].y - X[q].y;
+            const float d2 = fmaf(dx, dx, fmaf(dy, dy, c.er2));
+            const float rinv = hw_rsq(d2);
+            const float pen = fmaf(-d2, rinv, c.hsum[b][q]);
+            pdx[b][q] = dx;
+            pdy[b][q] = dy;
+            pfr[b][q] = c.kb * softplus(pen, c.beta_log2e, c.ln2_over_beta) * rinv;
+        }
+    }
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+#pragma unroll
+        for (int q = 0; q < B; ++q) {
+            if (q == b) continue;
+            const float fr = q > b ? pfr[b][q] : pfr[q][b];
+            const float dx = q > b ? pdx[b][q] : -pdx[q][b];
+            const float dy = q > b ? pdy[b][q] : -pdy[q][b];
+            Fx[b] = fmaf(fr, dx, Fx[b]);
+            Fy[b] = fmaf(fr, dy, Fy[b]);
+        }
+    }
+    // the virtual pusher of this side, on block 0: contact normal e = R(phi0) n
+    {
+        const float relx = fmaf(sig, p.Vx, p.P0x) - X[0].x;
+        const float rely = fmaf(sig, p.Vy, p.P0y) - X[0].y;
+        float s0, c0;
+        sincos_rd(X[0].ph, s0, c0);
+        const float ex = fmaf(c0, p.nx, -(s0 * p.ny)), ey = fmaf(s0, p.nx, c0 * p.ny);
+        const float pen = c.h0 - fmaf(ex, relx, ey * rely);
+        const float f = c.kp * softplus(pen, c.beta_log2e, c.ln2_over_beta);
+        Fx[0] = fmaf(-f, ex, Fx[0]);
+        Fy[0] = fmaf(-f, ey, Fy[0]);
+        Tq[0] = fmaf(-f, fmaf(relx, ey, -(rely * ex)), Tq[0]);
+    }
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+        X[b].vx = fmaf(c.dtm[b], Fx[b], X[b].vx);
+        X[b].vy = fmaf(c.dtm[b], Fy[b], X[b].vy);
+        X[b].om = fmaf(c.dtI[b], Tq[b], X[b].om);
+        X[b].x = fmaf(c.dt, X[b].vx, X[b].x);
+        X[b].y = fmaf(c.dt, X[b].vy, X[b].y);
+        X[b].ph = fmaf(c.dt, X[b].om, X[b].ph);
+    }
+}
+
+// Reverse of step_forward_packed at pre-step states X; L: post-step adjoints
+// on entry, pre-step adjoints on exit; pusher adjoints accumulate as in
+// step_reverse (block 0).
+template <int B>
+__device__ __forceinline__ void step_reverse_packed(const SimConst& c, const Blk (&X)[B], Blk (&L)[B], const Push& p,
+                                                    float sig, float& P0xb, float& P0yb, float& Vxb, float& Vyb) {
+    float Fxb[B], Fyb[B], Tqb[B];
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+        L[b].vx = fmaf(c.dt, L[b].x, L[b].vx);
+        L[b].vy = fmaf(c.dt, L[b].y, L[b].vy);
+        L[b].om = fmaf(c.dt, L[b].ph, L[b].om);
+        Fxb[b] = c.dtm[b] * L[b].vx;
+        Fyb[b] = c.dtm[b] * L[b].vy;
+        Tqb[b] = c.dtI[b] * L[b].om;
+    }
+    // pusher (block 0)
+    {
+        const float relx = fmaf(sig, p.Vx, p.P0x) - X[0].x;
+        const float rely = fmaf(sig, p.Vy, p.P0y) - X[0].y;
+        float s0, c0;
+        sincos_rd(X[0].ph, s0, c0);
+        const float ex = fmaf(c0, p.nx, -(s0 * p.ny)), ey = fmaf(s0, p.nx, c0 * p.ny);
+        const float cross = fmaf(relx, ey, -(rely * ex));
+        const float pen = c.h0 - fmaf(ex, relx, ey * rely);
+        const float u = softplus_u(pen, c.beta_log2e);
+        const float f = c.kp * fmaf(hw_log2(1.0f + u), c.ln2_over_beta, fmaxf(pen, 0.0f));
+        const float rr = hw_rcp(1.0f + u);
+        const float spg = pen >= 0.0f ? rr : u * rr;
+        const float fb = -fmaf(cross, Tqb[0], fmaf(ex, Fxb[0], ey * Fyb[0]));
+        const float crossb = -f * Tqb[0];
+        const float penb = fb * c.kp * spg;
+        const float exb = fmaf(-f, Fxb[0], -fmaf(crossb, rely, penb * relx));
+        const float eyb = fmaf(-f, Fyb[0], fmaf(crossb, relx, -(penb * rely)));
+        const float relxb = fmaf(crossb, ey, -(penb * ex));
+        const float relyb = -fmaf(crossb, ex, penb * ey);
+        const float c0b = fmaf(exb, p.nx, eyb * p.ny);
+        const float s0b = fmaf(eyb, p.nx, -(exb * p.ny));
+        L[0].ph += fmaf(c0, s0b, -(s0 * c0b));
+        L[0].x -= relxb;
+        L[0].y -= relyb;
+        P0xb += relxb;
+        P0yb += relyb;
+        Vxb = fmaf(sig, relxb, Vxb);
+        Vyb = fmaf(sig, relyb, Vyb);
+    }
+    // block-block contacts, once per pair b < q; each block adds its partners
+    // in increasing order
+    float pdx[B][B], pdy[B][B], pfr[B][B], pk2[B][B], pgx[B][B], pgy[B][B];
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+#pragma unroll
+        for (int q = b + 1; q < B; ++q) {
+            const float dx = X[b].x - X[q].x, dy = X[b].y - X[q].y;
+            const float d2 = fmaf(dx, dx, fmaf(dy, dy, c.er2));
+            const float rinv = hw_rsq(d2);
+            const float pen = fmaf(-d2, rinv, c.hsum[b][q]);
+            const float u = softplus_u(pen, c.beta_log2e);
+            const float fr = c.kb * fmaf(hw_log2(1.0f + u), c.ln2_over_beta, fmaxf(pen, 0.0f)) * rinv;
+            const float rr = hw_rcp(1.0f + u);
+            const float fp = c.kb * (pen >= 0.0f ? rr : u * rr);
+            const float gx = Fxb[b] - Fxb[q], gy = Fyb[b] - Fyb[q];
+            const float gu = fmaf(gx, dx, gy * dy) * rinv;
+            pdx[b][q] = dx;
+            pdy[b][q] = dy;
+            pfr[b][q] = fr;
+            pk2[b][q] = (fr + fp) * gu * rinv;
+            pgx[b][q] = gx;
+            pgy[b][q] = gy;
+        }
+    }
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+#pragma unroll
+        for (int q = 0; q < B; ++q) {
+            if (q == b) continue;
+            const int lo = q > b ? b : q, hi = q > b ? q : b;
+            const float sg = q > b ? 1.0f : -1.0f;  // the higher block sees Delta and g negated
+            const float fr = pfr[lo][hi], k2 = pk2[lo][hi];
+            const float dx = sg * pdx[lo][hi], dy = sg * pdy[lo][hi];
+            const float gx = sg * pgx[lo][hi], gy = sg * pgy[lo][hi];
+            L[b].x += fmaf(fr, gx, -(k2 * dx));
+            L[b].y += fmaf(fr, gy, -(k2 * dy));
+        }
+    }
+    // friction
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+        const float inv = hw_rsq(fmaf(X[b].vx, X[b].vx, fmaf(X[b].vy, X[b].vy, c.ev2[b])));
+        const float kf = c.cf[b] * inv;
+        const float kd = kf * inv * inv * fmaf(Fxb[b], X[b].vx, Fyb[b] * X[b].vy);
+        L[b].vx = fmaf(kd, X[b].vx, fmaf(-kf, Fxb[b], L[b].vx));
+        L[b].vy = fmaf(kd, X[b].vy, fmaf(-kf, Fyb[b], L[b].vy));
+        const float invw = hw_rsq(fmaf(X[b].om, X[b].om, c.ew2[b]));
+        L[b].om = fmaf(-(c.crw2[b] * (invw * invw * invw)), Tqb[b], L[b].om);
+    }
+}
+
+template <int B>
+__device__ __forceinline__ void load_blks(Blk (&X)[B], const float* __restrict__ entry, uint32_t off) {
+#pragma unroll
+    for (int b = 0; b < B; ++b) load_blk_at(X[b], entry, off + 6 * b);
+}
+
+template <int B>
+__device__ __forceinline__ void store_blks(const Blk (&X)[B], float* __restrict__ entry, uint32_t off) {
+#pragma unroll
+    for (int b = 0; b < B; ++b) store_blk_at(X[b], entry, off + 6 * b);
+}
+
+// Sum over the block slots in the block-per-lane form's order: (v0+v1)+(v2+v3),
+// an absent fourth slot adding zero.
+template <int B>
+__device__ __forceinline__ float blocks_sum(const float (&v)[B]) {
+    if constexpr (B == 1) return v[0];
+    else if constexpr (B == 2) return v[0] + v[1];
+    else if constexpr (B == 3) return (v[0] + v[1]) + (v[2] + 0.0f);
+    else return (v[0] + v[1]) + (v[2] + v[3]);
+}
+
+// Forward rollout of one packed lane (particle i, side s); as rollout_fwd_lane.
+template <int B>
+__device__ __forceinline__ void rollout_fwd_packed(const SimConst& c, int N, const float* __restrict__ theta,
+                                                   float* __restrict__ cost, float* __restrict__ tape,
+                                                   const TapeGeom& g, uint32_t* status, int64_t lane) {
+    const int64_t iw = lane / 4;
+    const bool live = iw < N;
+    const int i = live ? (int)iw : N - 1;
+    const int s = (int)(lane % 4);
+    const uint32_t off = (uint32_t)(((int64_t)4 * i + s) * B * 6);
+    const int64_t stride = 6 * B * g.lanes;
+    const int H = c.H, T = c.T;
+    Blk S[B];
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+        S[b].x = c.pose0[b][0];
+        S[b].y = c.pose0[b][1];
+        S[b].ph = c.pose0[b][2];
+        S[b].vx = S[b].vy = S[b].om = 0.0f;
+    }
+    float Px[kMaxPushes + 1], Py[kMaxPushes + 1];
+    float Lbound = 0.0f;
+    Push p;
+    side_frame(s, p);
+    int64_t entry = 0;
+    for (int kk = 0; kk < H; ++kk) {
+        const int tk = phase_start(kk, T, H), tk1 = phase_start(kk + 1, T, H);
+        const float invL = 1.0f / (float)(tk1 - tk);
+        Px[kk] = S[0].x;
+        Py[kk] = S[0].y;
+        const float z = side_weight(theta, N, i, kk, s);
+        const float o = theta[(int64_t)(6 * kk + 4) * N + i];
+        const float D = theta[(int64_t)(6 * kk + 5) * N + i];
+        Anchor an;
+        phase_push(c, S[0].x, S[0].y, S[0].ph, o, D, p, an);
+        Lbound += relu(fabsf(o) - c.omax) * relu(fabsf(o) - c.omax) + relu(-D) * relu(-D) +
+                  relu(D - c.dmax) * relu(D - c.dmax);
+        Blk X[B];
+#pragma unroll
+        for (int b = 0; b < B; ++b) X[b] = S[b];
+        Profile prof;
+        prof.reset(invL);
+        const int nst = tk1 - tk;
+        if (tape && g.ckpt == 0) {
+            float* e = tape + (int64_t)tk * stride;
+            for (int j = 0; j < nst; ++j, e += stride) {
+                if (live) store_blks<B>(X, e, off);
+                step_forward_packed<B>(c, X, p, prof.at(j));
+            }
+        } else {
+            int until = 0;
+            for (int j = 0; j < nst; ++j) {
+                if (tape && until == 0) {
+                    if (live) store_blks<B>(X, tape + entry * stride, off);
+                    ++entry;
+                    until = g.ckpt;
+                }
+                --until;
+                step_forward_packed<B>(c, X, p, prof.at(j));
+            }
+        }
+        if (tape && live) store_blks<B>(X, tape + g.ends_off + (int64_t)kk * stride, off);
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            S[b].x = side_sum<1>(z * X[b].x);
+            S[b].y = side_sum<1>(z * X[b].y);
+            S[b].ph = side_sum<1>(z * X[b].ph);
+            S[b].vx = side_sum<1>(z * X[b].vx);
+            S[b].vy = side_sum<1>(z * X[b].vy);
+            S[b].om = side_sum<1>(z * X[b].om);
+        }
+    }
+    Px[H] = S[0].x;
+    Py[H] = S[0].y;
+    if (s != 0 || !live) return;
+    const float dxg = fabsf(Px[H] - c.goal[0]) - c.tol, dyg = fabsf(Py[H] - c.goal[1]) - c.tol;
+    const float Ltarget = relu(dxg) * relu(dxg) + relu(dyg) * relu(dyg);
+    const float Lrot = 1.0f - cosf(S[0].ph - c.goal[2]);
+    float Ltraj = 0.0f;
+    for (int kk = 1; kk <= H; ++kk) {
+        Ltraj += smooth_abs(Px[kk - 1] - Px[kk], c.ea2) + smooth_abs(Py[kk - 1] - Py[kk], c.ea2);
+        Ltraj += smooth_abs(Px[kk] - Px[H], c.ea2) + smooth_abs(Py[kk] - Py[H], c.ea2);
+        Ltraj -= smooth_abs(Px[kk - 1] - Px[H], c.ea2) + smooth_abs(Py[kk - 1] - Py[H], c.ea2);
+    }
+    const float C = c.wt * Ltarget + c.wr * Lrot + c.wtr * Ltraj + c.wb * Lbound;
+    cost[i] = C;
+    if (status && !isfinite(C)) atomicOr(status, STAMP_STATUS_NONFINITE_COST);
+}
+
+// Reverse sweep of one packed lane; as rollout_adj_lane.
+template <int B>
+__device__ __forceinline__ void rollout_adj_packed(const SimConst& c, int N, const float* __restrict__ theta,
+                                                   const float* __restrict__ tape, const TapeGeom& g,
+                                                   const float* __restrict__ cost_bar, float cb_scalar,
+                                                   float* __restrict__ grad, float* __restrict__ seg,
+                                                   uint32_t* status, int64_t lane) {
+    const int64_t iw = lane / 4;
+    const bool live = iw < N;
+    const int i = live ? (int)iw : N - 1;
+    const int s = (int)(lane % 4);
+    const int64_t slot0 = ((int64_t)4 * i + s) * B;
+    const uint32_t off = (uint32_t)(slot0 * 6);
+    const int H = c.H, T = c.T;
+    const int64_t stride = 6 * B * g.lanes;
+
+    int ent[kMaxPushes];
+    {
+        int e = 0;
+        for (int kk = 0; kk < H; ++kk) {
+            const int tk = phase_start(kk, T, H), tk1 = phase_start(kk + 1, T, H);
+            ent[kk] = (g.ckpt == 0) ? tk : e;
+            if (g.ckpt) e += (tk1 - tk + g.ckpt - 1) / g.ckpt;
+        }
+    }
+    float Px[kMaxPushes + 1], Py[kMaxPushes + 1];
+    for (int kk = 0; kk < H; ++kk) {
+        Px[kk] = tape[ent[kk] * stride + slot0 * 6 + 0];
+        Py[kk] = tape[ent[kk] * stride + slot0 * 6 + 1];
+    }
+    float phT;
+    {
+        const float z = side_weight(theta, N, i, H - 1, s);
+        const float* e = tape + g.ends_off + (int64_t)(H - 1) * stride + slot0 * 6;
+        Px[H] = side_sum<1>(z * e[0]);
+        Py[H] = side_sum<1>(z * e[1]);
+        phT = side_sum<1>(z * e[2]);
+    }
+    const float cb = cost_bar ? cost_bar[i] : cb_scalar;
+    float Pxb[kMaxPushes + 1], Pyb[kMaxPushes + 1];
+    for (int kk = 0; kk <= H; ++kk) Pxb[kk] = Pyb[kk] = 0.0f;
+    {
+        const float ux = Px[H] - c.goal[0], uy = Py[H] - c.goal[1];
+        Pxb[H] += cb * c.wt * 2.0f * relu(fabsf(ux) - c.tol) * copysignf(1.0f, ux);
+        Pyb[H] += cb * c.wt * 2.0f * relu(fabsf(uy) - c.tol) * copysignf(1.0f, uy);
+    }
+    const float phTb = cb * c.wr * sinf(phT - c.goal[2]);
+    const float wtr = cb * c.wtr;
+    if (!c.per_phase) {
+        for (int kk = 1; kk <= H; ++kk) {
+            float u, dd;
+            u = Px[kk - 1] - Px[kk];  dd = wtr * u / smooth_abs(u, c.ea2);  Pxb[kk - 1] += dd; Pxb[kk] -= dd;
+            u = Py[kk - 1] - Py[kk];  dd = wtr * u / smooth_abs(u, c.ea2);  Pyb[kk - 1] += dd; Pyb[kk] -= dd;
+            u = Px[kk] - Px[H];       dd = wtr * u / smooth_abs(u, c.ea2);  Pxb[kk] += dd;     Pxb[H] -= dd;
+            u = Py[kk] - Py[H];       dd = wtr * u / smooth_abs(u, c.ea2);  Pyb[kk] += dd;     Pyb[H] -= dd;
+            u = Px[kk - 1] - Px[H];   dd = wtr * u / smooth_abs(u, c.ea2);  Pxb[kk - 1] -= dd; Pxb[H] += dd;
+            u = Py[kk - 1] - Py[H];   dd = wtr * u / smooth_abs(u, c.ea2);  Pyb[kk - 1] -= dd; Pyb[H] += dd;
+        }
+    } else {
+        for (int kk = 1; kk < H; ++kk) {
+            float u, dd;
+            u = Px[kk - 1] - Px[kk];  dd = wtr * u / smooth_abs(u, c.ea2);  Pxb[kk] -= dd;
+            u = Py[kk - 1] - Py[kk];  dd = wtr * u / smooth_abs(u, c.ea2);  Pyb[kk] -= dd;
+            u = Px[kk] - Px[H];       dd = wtr * u / smooth_abs(u, c.ea2);  Pxb[kk] += dd;
+            u = Py[kk] - Py[H];       dd = wtr * u / smooth_abs(u, c.ea2);  Pyb[kk] += dd;
+        }
+    }
+    Blk Ls[B];
+#pragma unroll
+    for (int b = 0; b < B; ++b) Ls[b].x = Ls[b].y = Ls[b].ph = Ls[b].vx = Ls[b].vy = Ls[b].om = 0.0f;
+    Ls[0].x = Pxb[H];
+    Ls[0].y = Pyb[H];
+    Ls[0].ph = phTb;
+
+    Push p;
+    side_frame(s, p);
+    bool bad = false;
+    for (int kk = H - 1; kk >= 0; --kk) {
+        const int tk = phase_start(kk, T, H), tk1 = phase_start(kk + 1, T, H);
+        const float invL = 1.0f / (float)(tk1 - tk);
+        const float z = side_weight(theta, N, i, kk, s);
+        const float o = theta[(int64_t)(6 * kk + 4) * N + i];
+        const float D = theta[(int64_t)(6 * kk + 5) * N + i];
+        Blk Xe[B], L[B];
+        load_blks<B>(Xe, tape + g.ends_off + (int64_t)kk * stride, off);
+        float zpb[B];
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            zpb[b] = Ls[b].x * Xe[b].x + Ls[b].y * Xe[b].y + Ls[b].ph * Xe[b].ph + Ls[b].vx * Xe[b].vx +
+                     Ls[b].vy * Xe[b].vy + Ls[b].om * Xe[b].om;
+            L[b].x = z * Ls[b].x;
+            L[b].y = z * Ls[b].y;
+            L[b].ph = z * Ls[b].ph;
+            L[b].vx = z * Ls[b].vx;
+            L[b].vy = z * Ls[b].vy;
+            L[b].om = z * Ls[b].om;
+        }
+        const float zb = blocks_sum<B>(zpb);
+        const float ab = z * (zb - side_sum<1>(z * zb));  // softmax VJP
+        Blk A;
+        load_blk_at(A, tape + ent[kk] * stride, off);  // block 0's pose: the anchor
+        Anchor an;
+        phase_push(c, A.x, A.y, A.ph, o, D, p, an);
+        float P0xb = 0.0f, P0yb = 0.0f, Vxb = 0.0f, Vyb = 0.0f;
+        Profile prof;
+        prof.reset(invL);
+        if (g.ckpt == 0) {
+            const float* base = tape + (int64_t)tk * stride;
+            int j = tk1 - tk - 1;
+            Blk XA[B], XB[B];
+            load_blks<B>(XA, base + (int64_t)j * stride, off);
+            load_blks<B>(XB, base + (int64_t)max(j - 1, 0) * stride, off);
+            for (; j >= 1; j -= 2) {
+                Blk X[B];
+#pragma unroll
+                for (int b = 0; b < B; ++b) X[b] = XA[b];
+                load_blks<B>(XA, base + (int64_t)max(j - 2, 0) * stride, off);
+                step_reverse_packed<B>(c, X, L, p, prof.at(j), P0xb, P0yb, Vxb, Vyb);
+#pragma unroll
+                for (int b = 0; b < B; ++b) X[b] = XB[b];
+                load_blks<B>(XB, base + (int64_t)max(j - 3, 0) * stride, off);
+                step_reverse_packed<B>(c, X, L, p, prof.at(j - 1), P0xb, P0yb, Vxb, Vyb);
+            }
+            if (j == 0) step_reverse_packed<B>(c, XA, L, p, prof.at(0), P0xb, P0yb, Vxb, Vyb);
+        } else {
+            const int nseg = (tk1 - tk + g.ckpt - 1) / g.ckpt;
+            for (int q = nseg - 1; q >= 0; --q) {
+                const int js = q * g.ckpt;
+                const int je = min(js + g.ckpt, tk1 - tk);
+                Blk X[B];
+                load_blks<B>(X, tape + (int64_t)(ent[kk] + q) * stride, off);
+                for (int j = js; j < je; ++j) {
+                    if (live) store_blks<B>(X, seg + (int64_t)(j - js) * stride, off);
+                    step_forward_packed<B>(c, X, p, prof.at(j));
+                }
+                for (int j = je - 1; j >= js; --j) {
+                    if (live) load_blks<B>(X, seg + (int64_t)(j - js) * stride, off);
+                    step_reverse_packed<B>(c, X, L, p, prof.at(j), P0xb, P0yb, Vxb, Vyb);
+                }
+            }
+        }
+        const float eAx = fmaf(an.cA, p.nx, -(an.sA * p.ny)), eAy = fmaf(an.sA, p.nx, an.cA * p.ny);
+        const float Db = -fmaf(Vxb, eAx, Vyb * eAy);
+        const float eAxb = -D * Vxb, eAyb = -D * Vyb;
+        const float cAb = fmaf(eAxb, p.nx, eAyb * p.ny) + fmaf(P0xb, an.q0x, P0yb * an.q0y);
+        const float sAb = fmaf(eAyb, p.nx, -(eAxb * p.ny)) + fmaf(P0yb, an.q0x, -(P0xb * an.q0y));
+        const float q0xb = fmaf(an.cA, P0xb, an.sA * P0yb), q0yb = fmaf(an.cA, P0yb, -(an.sA * P0xb));
+        const float ob = fmaf(q0xb, p.tx, q0yb * p.ty);
+        const float Aphb = fmaf(an.cA, sAb, -(an.sA * cAb));
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            Ls[b].x = side_sum<1>(L[b].x);
+            Ls[b].y = side_sum<1>(L[b].y);
+            Ls[b].ph = side_sum<1>(L[b].ph);
+            Ls[b].vx = side_sum<1>(L[b].vx);
+            Ls[b].vy = side_sum<1>(L[b].vy);
+            Ls[b].om = side_sum<1>(L[b].om);
+        }
+        const float Axs = side_sum<1>(P0xb), Ays = side_sum<1>(P0yb), Aphs = side_sum<1>(Aphb);
+        const float obs = side_sum<1>(ob), Dbs = side_sum<1>(Db);
+        if (c.per_phase) {
+#pragma unroll
+            for (int b = 0; b < B; ++b) Ls[b].x = Ls[b].y = Ls[b].ph = Ls[b].vx = Ls[b].vy = Ls[b].om = 0.0f;
+            Ls[0].x = Pxb[kk];
+            Ls[0].y = Pyb[kk];
+        } else {
+            Ls[0].x += Axs + Pxb[kk];
+            Ls[0].y += Ays + Pyb[kk];
+            Ls[0].ph += Aphs;
+        }
+        const float wb2 = 2.0f * cb * c.wb;
+        const float obt = obs + wb2 * relu(fabsf(o) - c.omax) * copysignf(1.0f, o);
+        const float Dbt = Dbs + wb2 * (relu(D - c.dmax) - relu(-D));
+        if (live) {
+            grad[(int64_t)(6 * kk + s) * N + i] = ab;
+            if (s == 0) grad[(int64_t)(6 * kk + 4) * N + i] = obt;
+            if (s == 1) grad[(int64_t)(6 * kk + 5) * N + i] = Dbt;
+            bad = bad || !isfinite(ab) || !isfinite(obt) || !isfinite(Dbt);
+        }
+    }
+    if (status && bad) atomicOr(status, STAMP_STATUS_NONFINITE_GRAD);
+}
+
+template <int B>
+__global__ __launch_bounds__(kRolloutBlock) void k_rollout_fwd_packed(SimConst c, int N,
+                                                                      const float* __restrict__ theta,
+                                                                      float* __restrict__ cost,
+                                                                      float* __restrict__ tape, TapeGeom g,
+                                                                      uint32_t* status) {
+    const int64_t lane = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    rollout_fwd_packed<B>(c, N, theta, cost, tape, g, status, lane);
+}
+
+template <int B>
+__global__ __launch_bounds__(kRolloutBlock) void k_rollout_adj_packed(SimConst c, int N,
+                                                                      const float* __restrict__ theta,
+                                                                      const float* __restrict__ tape, TapeGeom g,
+                                                                      const float* __restrict__ cost_bar,
+                                                                      float cb_scalar, float* __restrict__ grad,
+                                                                      float* __restrict__ seg, uint32_t* status) {
+    const int64_t lane = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    rollout_adj_packed<B>(c, N, theta, tape, g, cost_bar, cb_scalar, grad, seg, status, lane);
+}
+
+// ---------------------------------------------------------------------------
 template <int B>
 __global__ __launch_bounds__(kRolloutBlock) void k_rollout_fwd(SimConst c, int N, const float* __restrict__ theta,
                                                                float* __restrict__ cost, float* __restrict__ tape,
@@ -742,23 +1230,32 @@ __global__ __launch_bounds__(kRolloutBlock) void k_rollout_adj(SimConst c, int N
 // (problem p, first particle i0) and covers 64 lanes: 64 / (4 SL) particles
 // (rollout_tile_particles); each wave takes tiles in a grid-stride loop.  The
 // block count B of the problem selects the compiled body at run time.
-template <int B>
+template <int B, bool PK>
 __device__ __forceinline__ void fwd_tile(const ProblemDesc& D, int i0, int l, const float* theta, float* cost,
                                          float* tape, uint32_t* status) {
-    const int64_t lane = (int64_t)Slots<B>::LANES * i0 + l;
-    rollout_fwd_lane<B>(D.c, D.N, theta + D.theta_off, cost + D.cost_off, tape ? tape + D.tape_off : nullptr, D.g,
-                        status, lane);
+    const int64_t lane = (int64_t)(PK ? 4 : Slots<B>::LANES) * i0 + l;
+    if constexpr (PK)
+        rollout_fwd_packed<B>(D.c, D.N, theta + D.theta_off, cost + D.cost_off, tape ? tape + D.tape_off : nullptr,
+                              D.g, status, lane);
+    else
+        rollout_fwd_lane<B>(D.c, D.N, theta + D.theta_off, cost + D.cost_off, tape ? tape + D.tape_off : nullptr,
+                            D.g, status, lane);
 }
 
-template <int B>
+template <int B, bool PK>
 __device__ __forceinline__ void adj_tile(const ProblemDesc& D, int i0, int l, const float* theta, const float* tape,
                                          float cb_scalar, float* grad, float* seg, uint32_t* status) {
-    const int64_t lane = (int64_t)Slots<B>::LANES * i0 + l;
-    rollout_adj_lane<B>(D.c, D.N, theta + D.theta_off, tape + D.tape_off, D.g, nullptr, cb_scalar,
-                        grad + D.theta_off, seg + D.seg_off, status, lane);
+    const int64_t lane = (int64_t)(PK ? 4 : Slots<B>::LANES) * i0 + l;
+    if constexpr (PK)
+        rollout_adj_packed<B>(D.c, D.N, theta + D.theta_off, tape + D.tape_off, D.g, nullptr, cb_scalar,
+                              grad + D.theta_off, seg + D.seg_off, status, lane);
+    else
+        rollout_adj_lane<B>(D.c, D.N, theta + D.theta_off, tape + D.tape_off, D.g, nullptr, cb_scalar,
+                            grad + D.theta_off, seg + D.seg_off, status, lane);
 }
 
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_rollout_fwd_batched(const ProblemDesc* __restrict__ descs,
+template <bool PK>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PK ? 2 : 4))) void k_rollout_fwd_batched(const ProblemDesc* __restrict__ descs,
                                                              const int2* __restrict__ tiles, int ntiles,
                                                              const float* __restrict__ theta, float* __restrict__ cost,
                                                              float* __restrict__ tape, uint32_t* status) {
@@ -770,15 +1267,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
         const int2 tl = tiles[t];
         const ProblemDesc& D = descs[tl.x];
         switch (D.c.B) {
-            case 1: fwd_tile<1>(D, tl.y, l, theta, cost, tape, status); break;
-            case 2: fwd_tile<2>(D, tl.y, l, theta, cost, tape, status); break;
-            case 3: fwd_tile<3>(D, tl.y, l, theta, cost, tape, status); break;
-            default: fwd_tile<4>(D, tl.y, l, theta, cost, tape, status); break;
+            case 1: fwd_tile<1, PK>(D, tl.y, l, theta, cost, tape, status); break;
+            case 2: fwd_tile<2, PK>(D, tl.y, l, theta, cost, tape, status); break;
+            case 3: fwd_tile<3, PK>(D, tl.y, l, theta, cost, tape, status); break;
+            default: fwd_tile<4, PK>(D, tl.y, l, theta, cost, tape, status); break;
         }
     }
 }
 
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_rollout_adj_batched(const ProblemDesc* __restrict__ descs,
+template <bool PK>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PK ? 2 : 4))) void k_rollout_adj_batched(const ProblemDesc* __restrict__ descs,
                                                              const int2* __restrict__ tiles, int ntiles,
                                                              const float* __restrict__ theta,
                                                              const float* __restrict__ tape, float cb_scalar,
@@ -792,73 +1290,92 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
         const int2 tl = tiles[t];
         const ProblemDesc& D = descs[tl.x];
         switch (D.c.B) {
-            case 1: adj_tile<1>(D, tl.y, l, theta, tape, cb_scalar, grad, seg, status); break;
-            case 2: adj_tile<2>(D, tl.y, l, theta, tape, cb_scalar, grad, seg, status); break;
-            case 3: adj_tile<3>(D, tl.y, l, theta, tape, cb_scalar, grad, seg, status); break;
-            default: adj_tile<4>(D, tl.y, l, theta, tape, cb_scalar, grad, seg, status); break;
+            case 1: adj_tile<1, PK>(D, tl.y, l, theta, tape, cb_scalar, grad, seg, status); break;
+            case 2: adj_tile<2, PK>(D, tl.y, l, theta, tape, cb_scalar, grad, seg, status); break;
+            case 3: adj_tile<3, PK>(D, tl.y, l, theta, tape, cb_scalar, grad, seg, status); break;
+            default: adj_tile<4, PK>(D, tl.y, l, theta, tape, cb_scalar, grad, seg, status); break;
         }
     }
 }
 
-int rollout_tile_particles(int B) { return 64 / (4 * (B == 1 ? 1 : (B == 2 ? 2 : 4))); }
+int rollout_tile_particles(int B, bool packed) { return packed ? 16 : 64 / (4 * (B == 1 ? 1 : (B == 2 ? 2 : 4))); }
 
 hipError_t launch_rollout_fwd_batched(const ProblemDesc* descs, const int2* tiles, int ntiles, int block,
                                       int grid, const float* theta, float* cost, float* tape, uint32_t* status,
-                                      hipStream_t st) {
-    hipLaunchKernelGGL(k_rollout_fwd_batched, dim3(grid), dim3(block), 0, st, descs, tiles, ntiles, theta, cost,
-                       tape, status);
+                                      hipStream_t st, bool packed) {
+    if (packed)
+        hipLaunchKernelGGL(k_rollout_fwd_batched<true>, dim3(grid), dim3(block), 0, st, descs, tiles, ntiles, theta,
+                           cost, tape, status);
+    else
+        hipLaunchKernelGGL(k_rollout_fwd_batched<false>, dim3(grid), dim3(block), 0, st, descs, tiles, ntiles, theta,
+                           cost, tape, status);
     return hipGetLastError();
 }
 
 hipError_t launch_rollout_adj_batched(const ProblemDesc* descs, const int2* tiles, int ntiles, int block,
                                       int grid, const float* theta, const float* tape, float cb_scalar,
-                                      float* grad, float* seg, uint32_t* status, hipStream_t st) {
-    hipLaunchKernelGGL(k_rollout_adj_batched, dim3(grid), dim3(block), 0, st, descs, tiles, ntiles, theta, tape,
-                       cb_scalar, grad, seg, status);
+                                      float* grad, float* seg, uint32_t* status, hipStream_t st, bool packed) {
+    if (packed)
+        hipLaunchKernelGGL(k_rollout_adj_batched<true>, dim3(grid), dim3(block), 0, st, descs, tiles, ntiles, theta,
+                           tape, cb_scalar, grad, seg, status);
+    else
+        hipLaunchKernelGGL(k_rollout_adj_batched<false>, dim3(grid), dim3(block), 0, st, descs, tiles, ntiles, theta,
+                           tape, cb_scalar, grad, seg, status);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
 template <int B>
 static hipError_t launch_fwd_b(const SimConst& c, int N, const float* theta, float* cost, float* tape,
-                               const TapeGeom& g, uint32_t* status, hipStream_t st) {
-    const int64_t lanes = (int64_t)Slots<B>::LANES * N;
+                               const TapeGeom& g, uint32_t* status, hipStream_t st, bool packed) {
+    // one block: both layouts are the same lanes; the block-per-lane kernel runs it
+    const bool pk = packed && B > 1;
+    const int64_t lanes = (int64_t)(pk ? 4 : Slots<B>::LANES) * N;
     const unsigned grid = (unsigned)((lanes + kRolloutBlock - 1) / kRolloutBlock);
-    hipLaunchKernelGGL(k_rollout_fwd<B>, dim3(grid), dim3(kRolloutBlock), 0, st, c, N, theta, cost, tape, g,
-                       status);
+    if (pk)
+        hipLaunchKernelGGL(k_rollout_fwd_packed<B>, dim3(grid), dim3(kRolloutBlock), 0, st, c, N, theta, cost, tape,
+                           g, status);
+    else
+        hipLaunchKernelGGL(k_rollout_fwd<B>, dim3(grid), dim3(kRolloutBlock), 0, st, c, N, theta, cost, tape, g,
+                           status);
     return hipGetLastError();
 }
 
 template <int B>
 static hipError_t launch_adj_b(const SimConst& c, int N, const float* theta, const float* tape,
                                const TapeGeom& g, const float* cost_bar, float cb_scalar, float* grad,
-                               float* seg, uint32_t* status, hipStream_t st) {
-    const int64_t lanes = (int64_t)Slots<B>::LANES * N;
+                               float* seg, uint32_t* status, hipStream_t st, bool packed) {
+    const bool pk = packed && B > 1;
+    const int64_t lanes = (int64_t)(pk ? 4 : Slots<B>::LANES) * N;
     const unsigned grid = (unsigned)((lanes + kRolloutBlock - 1) / kRolloutBlock);
-    hipLaunchKernelGGL(k_rollout_adj<B>, dim3(grid), dim3(kRolloutBlock), 0, st, c, N, theta, tape, g, cost_bar,
-                       cb_scalar, grad, seg, status);
+    if (pk)
+        hipLaunchKernelGGL(k_rollout_adj_packed<B>, dim3(grid), dim3(kRolloutBlock), 0, st, c, N, theta, tape, g,
+                           cost_bar, cb_scalar, grad, seg, status);
+    else
+        hipLaunchKernelGGL(k_rollout_adj<B>, dim3(grid), dim3(kRolloutBlock), 0, st, c, N, theta, tape, g, cost_bar,
+                           cb_scalar, grad, seg, status);
     return hipGetLastError();
 }
 
 hipError_t launch_rollout_fwd(const SimConst& c, int N, const float* theta, float* cost, float* tape,
-                              const TapeGeom& g, uint32_t* status, hipStream_t st) {
+                              const TapeGeom& g, uint32_t* status, hipStream_t st, bool packed) {
     switch (c.B) {
-        case 1: return launch_fwd_b<1>(c, N, theta, cost, tape, g, status, st);
-        case 2: return launch_fwd_b<2>(c, N, theta, cost, tape, g, status, st);
-        case 3: return launch_fwd_b<3>(c, N, theta, cost, tape, g, status, st);
-        case 4: return launch_fwd_b<4>(c, N, theta, cost, tape, g, status, st);
+        case 1: return launch_fwd_b<1>(c, N, theta, cost, tape, g, status, st, packed);
+        case 2: return launch_fwd_b<2>(c, N, theta, cost, tape, g, status, st, packed);
+        case 3: return launch_fwd_b<3>(c, N, theta, cost, tape, g, status, st, packed);
+        case 4: return launch_fwd_b<4>(c, N, theta, cost, tape, g, status, st, packed);
     }
     return hipErrorInvalidValue;
 }
 
 hipError_t launch_rollout_adj(const SimConst& c, int N, const float* theta, const float* tape,
                               const TapeGeom& g, const float* cost_bar, float cb_scalar, float* grad,
-                              float* seg, uint32_t* status, hipStream_t st) {
+                              float* seg, uint32_t* status, hipStream_t st, bool packed) {
     switch (c.B) {
-        case 1: return launch_adj_b<1>(c, N, theta, tape, g, cost_bar, cb_scalar, grad, seg, status, st);
-        case 2: return launch_adj_b<2>(c, N, theta, tape, g, cost_bar, cb_scalar, grad, seg, status, st);
-        case 3: return launch_adj_b<3>(c, N, theta, tape, g, cost_bar, cb_scalar, grad, seg, status, st);
-        case 4: return launch_adj_b<4>(c, N, theta, tape, g, cost_bar, cb_scalar, grad, seg, status, st);
+        case 1: return launch_adj_b<1>(c, N, theta, tape, g, cost_bar, cb_scalar, grad, seg, status, st, packed);
+        case 2: return launch_adj_b<2>(c, N, theta, tape, g, cost_bar, cb_scalar, grad, seg, status, st, packed);
+        case 3: return launch_adj_b<3>(c, N, theta, tape, g, cost_bar, cb_scalar, grad, seg, status, st, packed);
+        case 4: return launch_adj_b<4>(c, N, theta, tape, g, cost_bar, cb_scalar, grad, seg, status, st, packed);
     }
     return hipErrorInvalidValue;
 }

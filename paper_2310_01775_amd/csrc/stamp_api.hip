@@ -32,6 +32,7 @@ struct stamp_ctx {
     hipEvent_t ev_in = nullptr, ev_out = nullptr, ev_fork = nullptr, ev_join = nullptr;
     std::map<std::string, StampTune> tune;  // autotune cache, keyed by batch signature
     int autotune = 1;
+    int rollout_layout = STAMP_LAYOUT_AUTO;  // block per lane, or all blocks of a sub-rollout per lane
     StampTune pinned;                        // used when pinned.roll_block > 0
     int is_pinned = 0;
     // The last instantiated graphs of each iteration kind (SVGD, surrogate
@@ -204,6 +205,24 @@ bool scene_ok(const stamp_scene* s) {
            s->M == kModes;
 }
 
+// Lanes of the block-per-lane rollout layout (4 sides x SL block slots per particle).
+int64_t block_lanes(int N, int B) { return (int64_t)4 * (B == 1 ? 1 : (B == 2 ? 2 : 4)) * N; }
+
+// Automatic layout.  The block-per-lane form keeps more waves in flight,
+// which pays while a rollout is latency-bound (few waves per SIMD).  Once its
+// lanes fill the chip (kPackedAutoLanes) the packed adjoint, with a single
+// lane per sub-rollout, issues about half the instructions per particle and
+// wins (N = 16384, B = 3: 178 vs 343 us); the packed forward does not (397 vs
+// 244 us: each lane's tape stores span 6B floats, so a wave's store touches
+// B times the cache lines), so the forward keeps one lane per block.  The
+// tape layout is the same, and so are the results, bit for bit.
+constexpr int64_t kPackedAutoLanes = (int64_t)2 * 64 * 1024;
+bool packed_for(const stamp_ctx* ctx, int64_t lanes, bool adjoint) {
+    if (ctx->rollout_layout == STAMP_LAYOUT_BLOCKS) return false;
+    if (ctx->rollout_layout == STAMP_LAYOUT_PACKED) return true;
+    return adjoint && lanes >= kPackedAutoLanes;
+}
+
 constexpr int kGraphUnroll = 4;  // iterations per unrolled graph
 constexpr int kMaxSvgdDim = 64;
 constexpr int kMaxSvgdN = 65536;
@@ -213,13 +232,13 @@ constexpr int kMaxSvgdN = 65536;
 //   tapes | segment buffers | grad | phi | cost scratch | per-problem SVGD regions
 struct SolvePlan {
     std::vector<stamp::ProblemDesc> descs;
-    std::vector<int2> roll_tiles;
+    std::vector<int2> roll_tiles, adj_tiles;  // forward and adjoint rollout tiles (their layouts may differ)
     std::vector<int4> dist_work, cand_work, red_work;
     std::vector<int4> phi_work[kPhi32Classes];
     std::vector<int4> ctr_work, row16_work, phi16_work[2];  // BF16 form
     int phi_rows = 256;
     int dist_start[kMedLists] = {}, dist_n[kMedLists] = {};  // dist_work sorted by item shape
-    size_t clk_off = 0, desc_off = 0, roll_off = 0, dist_off = 0, cand_off = 0, red_off = 0;
+    size_t clk_off = 0, desc_off = 0, roll_off = 0, adj_tiles_off = 0, dist_off = 0, cand_off = 0, red_off = 0;
     size_t ctr16_off = 0, row16_off = 0, phi16_off[2] = {};
     size_t phi_off[kPhi32Classes] = {};
     size_t ctr_off = 0, err_off = 0, tape_off = 0, seg_off = 0, grad_off = 0, phi_vec_off = 0, cost_off = 0,
@@ -234,7 +253,8 @@ constexpr int kRedChunk = 256;    // elements per workgroup of the phi reduction
 // Lay out the workspace and build the work lists.  phi_rows fixes the row
 // blocks of the contraction work list.
 void build_plan(int n, const stamp_scene* scenes, const int32_t* N, int K, float bandwidth, int phi_rows,
-                const std::vector<stamp::SimConst>* consts, SolvePlan& P) {
+                const std::vector<stamp::SimConst>* consts, SolvePlan& P, bool packed_fwd = false,
+                bool packed_adj = false) {
     P = SolvePlan{};  // rebuilt from scratch: appending twice would repeat work items
     P.phi_rows = phi_rows;
     P.descs.resize(n);
@@ -265,7 +285,10 @@ void build_plan(int n, const stamp_scene* scenes, const int32_t* N, int K, float
         sv += align256(D.sv.total);
         snprintf(buf, sizeof buf, "%d/%d/%d/%d;", N[p], s->H, s->B, s->T);
         P.key += buf;
-        for (int i0 = 0; i0 < D.N; i0 += rollout_tile_particles(s->B)) P.roll_tiles.push_back(make_int2(p, i0));
+        for (int i0 = 0; i0 < D.N; i0 += rollout_tile_particles(s->B, packed_fwd))
+            P.roll_tiles.push_back(make_int2(p, i0));
+        for (int i0 = 0; i0 < D.N; i0 += rollout_tile_particles(s->B, packed_adj))
+            P.adj_tiles.push_back(make_int2(p, i0));
         // median passes over all pairs, for problems whose pairs exceed the sample:
         // every (row block, column chunk) item (items without a pair i < j write
         // zero counts), and (segment, part) of the candidate passes
@@ -319,6 +342,7 @@ void build_plan(int n, const stamp_scene* scenes, const int32_t* N, int K, float
     P.clk_off = take((size_t)n * 2 * sizeof(uint64_t));
     P.desc_off = take(P.descs.size() * sizeof(ProblemDesc));
     P.roll_off = take(P.roll_tiles.size() * sizeof(int2));
+    P.adj_tiles_off = take(P.adj_tiles.size() * sizeof(int2));
     P.dist_off = take(P.dist_work.size() * sizeof(int4));
     P.cand_off = take(P.cand_work.size() * sizeof(int4));
     P.red_off = take(P.red_work.size() * sizeof(int4));
@@ -349,6 +373,7 @@ size_t plan_bytes(int n, const stamp_scene* scenes, const int32_t* N, int K, flo
 // True when two plans place every workspace region at the same offset.
 bool same_layout(const SolvePlan& a, const SolvePlan& b) {
     bool ok = a.total == b.total && a.clk_off == b.clk_off && a.desc_off == b.desc_off && a.roll_off == b.roll_off &&
+              a.adj_tiles_off == b.adj_tiles_off &&
               a.dist_off == b.dist_off && a.cand_off == b.cand_off && a.red_off == b.red_off &&
               a.ctr_off == b.ctr_off && a.err_off == b.err_off && a.tape_off == b.tape_off && a.seg_off == b.seg_off &&
               a.grad_off == b.grad_off && a.phi_vec_off == b.phi_vec_off && a.cost_off == b.cost_off &&
@@ -435,6 +460,14 @@ int32_t stamp_set_autotune(stamp_ctx* ctx, int32_t enable) {
     return STAMP_OK;
 }
 
+int32_t stamp_set_rollout_layout(stamp_ctx* ctx, int32_t layout) {
+    if (!ctx) return STAMP_EINVAL;
+    if (layout != STAMP_LAYOUT_AUTO && layout != STAMP_LAYOUT_BLOCKS && layout != STAMP_LAYOUT_PACKED)
+        return fail(ctx, STAMP_EINVAL, "layout %d is not STAMP_LAYOUT_AUTO, _BLOCKS or _PACKED", layout);
+    ctx->rollout_layout = layout;
+    return STAMP_OK;
+}
+
 int32_t stamp_set_launch_shape(stamp_ctx* ctx, int32_t roll_block, int32_t roll_grid, int32_t phi_rows) {
     if (!ctx) return STAMP_EINVAL;
     if (roll_block == 0 && roll_grid == 0 && phi_rows == 0) {
@@ -489,7 +522,8 @@ int32_t stamp_rollout_fwd(stamp_ctx* ctx, const stamp_scene* scene, const stamp_
     if (tape && tape_len < tape_floats(scene, N, ckpt_every))
         return fail(ctx, STAMP_ENOSPACE, "tape %zu < %zu floats", tape_len, tape_floats(scene, N, ckpt_every));
     const TapeGeom g = tape_geom(scene, N, ckpt_every);
-    hipError_t e = launch_rollout_fwd(c, N, theta, cost, tape, g, status, (hipStream_t)stream);
+    hipError_t e = launch_rollout_fwd(c, N, theta, cost, tape, g, status, (hipStream_t)stream,
+                                      packed_for(ctx, block_lanes(N, c.B), false));
     return e == hipSuccess ? STAMP_OK : hip_fail(ctx, e, "rollout_fwd");
 }
 
@@ -522,7 +556,9 @@ int32_t stamp_plan_readout(stamp_ctx* ctx, const stamp_scene* scene, const stamp
     float* plan = (float*)workspace;
     hipError_t e = launch_modes(N, scene->H, theta, modes, st);
     if (e == hipSuccess) e = launch_onehot(N, scene->H, theta, plan, st);
-    if (e == hipSuccess) e = launch_rollout_fwd(c, N, plan, cost, nullptr, tape_geom(scene, N, 0), status, st);
+    if (e == hipSuccess)
+        e = launch_rollout_fwd(c, N, plan, cost, nullptr, tape_geom(scene, N, 0), status, st,
+                               packed_for(ctx, block_lanes(N, c.B), false));
     return e == hipSuccess ? STAMP_OK : hip_fail(ctx, e, "plan_readout");
 }
 
@@ -545,7 +581,7 @@ static int32_t rollout_adj_impl(stamp_ctx* ctx, const stamp_scene* scene, const 
     const TapeGeom g = tape_geom(scene, N, ckpt_every);
     c.per_phase = per_phase;
     hipError_t e = launch_rollout_adj(c, N, theta, tape, g, cost_bar, 1.0f, grad, (float*)workspace, status,
-                                      (hipStream_t)stream);
+                                      (hipStream_t)stream, packed_for(ctx, block_lanes(N, c.B), true));
     return e == hipSuccess ? STAMP_OK : hip_fail(ctx, e, "rollout_adj");
 }
 
@@ -795,13 +831,17 @@ static int32_t solve_impl(stamp_ctx* ctx, int32_t n_problems, const stamp_scene*
     STAMP_TRY(hipStreamWaitEvent(st, ctx->ev_in, 0), "stream wait");
 
     // launch shapes: tuned once per batch signature
+    // rollout layout of the whole batch, by its block-per-lane lane count
+    int64_t all_lanes = 0;
+    for (int p = 0; p < n_problems; ++p) all_lanes += block_lanes(N[p], scenes[p].B);
+    const bool packed = packed_for(ctx, all_lanes, false), packed_adj = packed_for(ctx, all_lanes, true);
     SolvePlan P;
-    build_plan(n_problems, scenes, N, K, cfg->bandwidth, 256, &consts, P);
+    build_plan(n_problems, scenes, N, K, cfg->bandwidth, 256, &consts, P, packed, packed_adj);
     // Every rebuild below (another row block) must keep the regions where the
     // pointers derived next point: the layout reserves the longest lists.
     const SolvePlan layout0 = P;
     auto rebuild = [&](int rows) -> bool {
-        build_plan(n_problems, scenes, N, K, cfg->bandwidth, rows, &consts, P);
+        build_plan(n_problems, scenes, N, K, cfg->bandwidth, rows, &consts, P, packed, packed_adj);
         return same_layout(P, layout0);
     };
     const std::string tkey = P.key + "K" + std::to_string(K) + (cfg->bandwidth > 0 ? "fixed" : "median");
@@ -816,6 +856,7 @@ static int32_t solve_impl(stamp_ctx* ctx, int32_t n_problems, const stamp_scene*
     char* ws = (char*)workspace;
     ProblemDesc* d_desc = (ProblemDesc*)(ws + P.desc_off);
     int2* d_roll = (int2*)(ws + P.roll_off);
+    int2* d_adj_tiles = (int2*)(ws + P.adj_tiles_off);
     int* d_ctr = (int*)(ws + P.ctr_off);
     uint64_t* d_clk = (uint64_t*)(ws + P.clk_off);
     float* d_tape = (float*)(ws + P.tape_off);
@@ -830,6 +871,8 @@ static int32_t solve_impl(stamp_ctx* ctx, int32_t n_problems, const stamp_scene*
         hipError_t r;
         if ((r = upload(P.desc_off, P.descs.data(), P.descs.size() * sizeof(ProblemDesc))) != hipSuccess) return r;
         if ((r = upload(P.roll_off, P.roll_tiles.data(), P.roll_tiles.size() * sizeof(int2))) != hipSuccess) return r;
+        if ((r = upload(P.adj_tiles_off, P.adj_tiles.data(), P.adj_tiles.size() * sizeof(int2))) != hipSuccess)
+            return r;
         if ((r = upload(P.dist_off, P.dist_work.data(), P.dist_work.size() * sizeof(int4))) != hipSuccess) return r;
         if ((r = upload(P.cand_off, P.cand_work.data(), P.cand_work.size() * sizeof(int4))) != hipSuccess) return r;
         if ((r = upload(P.red_off, P.red_work.data(), P.red_work.size() * sizeof(int4))) != hipSuccess) return r;
@@ -845,7 +888,7 @@ static int32_t solve_impl(stamp_ctx* ctx, int32_t n_problems, const stamp_scene*
         return hipStreamSynchronize(st);  // host lists may go out of scope after this
     };
     STAMP_TRY(upload_lists(), "upload work lists");
-    const int ntiles = (int)P.roll_tiles.size();
+    const int ntiles = (int)P.roll_tiles.size(), nadj = (int)P.adj_tiles.size();
     auto batch_plan = [&]() {
         BatchPlan B{};
         B.n_problems = n_problems;
@@ -874,9 +917,9 @@ static int32_t solve_impl(stamp_ctx* ctx, int32_t n_problems, const stamp_scene*
         }
         return B;
     };
-    auto roll_grid = [&](const StampTune& t) {
+    auto roll_grid = [&](const StampTune& t, int tiles) {
         const int waves = t.roll_block / 64;
-        const int full = (ntiles + waves - 1) / waves;
+        const int full = (tiles + waves - 1) / waves;
         return t.roll_grid > 0 ? std::min(t.roll_grid, full) : full;
     };
 
@@ -905,10 +948,10 @@ static int32_t solve_impl(stamp_ctx* ctx, int32_t n_problems, const stamp_scene*
                     cand.roll_block = block;
                     cand.roll_grid = grid;
                     const float ms = timed([&] {
-                        (void)launch_rollout_fwd_batched(d_desc, d_roll, ntiles, block, roll_grid(cand), theta,
-                                                         d_phi, d_tape, nullptr, st);
-                        (void)launch_rollout_adj_batched(d_desc, d_roll, ntiles, block, roll_grid(cand), theta, d_tape,
-                                                   -1.0f, d_grad, d_seg, nullptr, st);
+                        (void)launch_rollout_fwd_batched(d_desc, d_roll, ntiles, block, roll_grid(cand, ntiles), theta,
+                                                         d_phi, d_tape, nullptr, st, packed);
+                        (void)launch_rollout_adj_batched(d_desc, d_adj_tiles, nadj, block, roll_grid(cand, nadj), theta,
+                                                         d_tape, -1.0f, d_grad, d_seg, nullptr, st, packed_adj);
                     });
                     if (ms < best) {
                         best = ms;
@@ -940,7 +983,7 @@ static int32_t solve_impl(stamp_ctx* ctx, int32_t n_problems, const stamp_scene*
         ctx->tune[tkey] = tune;
     }
     const BatchPlan B = batch_plan();
-    const int rgrid = roll_grid(tune);
+    const int rgrid = roll_grid(tune, ntiles);
     // Rollouts of the batch.  A single problem takes the per-call kernels,
     // compiled for its block count (fewer registers than the batched kernel,
     // which holds every block count's body: at 16 384 particles of 3 blocks the
@@ -950,18 +993,19 @@ static int32_t solve_impl(stamp_ctx* ctx, int32_t n_problems, const stamp_scene*
         if (single) {
             const ProblemDesc& D = P.descs[0];
             return launch_rollout_fwd(D.c, D.N, th + D.theta_off, cost + D.cost_off, tape ? tape + D.tape_off : nullptr,
-                                      D.g, stat, st);
+                                      D.g, stat, st, packed);
         }
-        return launch_rollout_fwd_batched(d_desc, d_roll, ntiles, tune.roll_block, rgrid, th, cost, tape, stat, st);
+        return launch_rollout_fwd_batched(d_desc, d_roll, ntiles, tune.roll_block, rgrid, th, cost, tape, stat, st,
+                                          packed);
     };
     auto roll_adj = [&](uint32_t* stat) -> hipError_t {
         if (single) {
             const ProblemDesc& D = P.descs[0];
             return launch_rollout_adj(D.c, D.N, theta + D.theta_off, d_tape + D.tape_off, D.g, nullptr, -1.0f,
-                                      d_grad + D.theta_off, d_seg + D.seg_off, stat, st);
+                                      d_grad + D.theta_off, d_seg + D.seg_off, stat, st, packed_adj);
         }
-        return launch_rollout_adj_batched(d_desc, d_roll, ntiles, tune.roll_block, rgrid, theta, d_tape, -1.0f,
-                                          d_grad, d_seg, stat, st);
+        return launch_rollout_adj_batched(d_desc, d_adj_tiles, nadj, tune.roll_block, roll_grid(tune, nadj), theta,
+                                          d_tape, -1.0f, d_grad, d_seg, stat, st, packed_adj);
     };
 
     // one SVGD iteration over every problem, captured once and replayed; with
@@ -1303,7 +1347,8 @@ int32_t stamp_mlp_label(stamp_ctx* ctx, const stamp_scene* scene, const stamp_co
     if (n_in < d || n_in > kMlpIn) return fail(ctx, STAMP_EINVAL, "n_in=%d not in [d=%d, %d]", n_in, d, kMlpIn);
     if (n_in > d && !enc) return fail(ctx, STAMP_EINVAL, "null scene encoding");
     const TapeGeom g = tape_geom(scene, N, 0);
-    hipError_t e = launch_rollout_fwd(c, N, theta, cost, nullptr, g, status, (hipStream_t)stream);
+    hipError_t e = launch_rollout_fwd(c, N, theta, cost, nullptr, g, status, (hipStream_t)stream,
+                                      packed_for(ctx, block_lanes(N, c.B), false));
     if (e == hipSuccess) e = launch_mlp_pack_rows(theta, N, d, enc, n_in, x, (hipStream_t)stream);
     return e == hipSuccess ? STAMP_OK : hip_fail(ctx, e, "mlp_label");
 }

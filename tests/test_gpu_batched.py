@@ -179,3 +179,32 @@ def test_first_autotuned_solve_of_a_large_batch_is_exact():
         finally:
             c.close()
     assert torch.equal(results[0], results[1])
+
+
+def test_full_batch_sampled_against_oracle(ctx):
+    """The 64-problem batch itself (N ~ U{64..2048}, H ~ U{2..5}, B ~ U{1..4},
+    T = 200), 10 graph-replayed iterations, autotuned; four of its problems
+    (one of each block count) checked against the oracle's solve of that
+    problem alone (problems in a batch do not interact)."""
+    import paper_2310_01775_amd as S
+    probs = W.batched_problems(4)
+    assert len(probs) == 64
+    iters, lr = 10, 1e-3
+    flat = _pack(S, probs)
+    m, v = torch.zeros_like(flat), torch.zeros_like(flat)
+    Ns = [th.shape[0] for _, _, th in probs]
+    st = ctx.status_word()
+    ctx.solve([S.make_scene(s) for s, _, _ in probs], [S.make_cost(w) for _, w, _ in probs], Ns,
+              S.make_cfg(iters, lr=lr), flat, m, v, status=st)
+    torch.cuda.synchronize()
+    assert int(st.item()) == 0
+    got = _unpack(S, flat, probs)
+    for k in (22, 60, 34, 10):  # B = 2, 1, 4, 3; N = 94, 160, 168, 317
+        scene, w, th = probs[k]
+        print("problem", k, "N", th.shape[0], "B", scene["B"], "H", scene["H"], flush=True)
+        ref = svgd.solve(scene, w, th, iters, lr=lr)["theta"]
+        g = S.aos(got[k])
+        norm = np.linalg.norm(g - ref) / np.linalg.norm(ref)
+        worst = (np.abs(g - ref) / np.abs(ref).max(axis=0, keepdims=True)).max()
+        print("problem", k, "normwise", norm, "worst coordinate", worst, flush=True)
+        assert norm < 2e-6 and worst < 1e-4
