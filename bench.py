@@ -61,15 +61,18 @@ def mlp_flops(M, n_in, width=256):
     return M * 2 * 2 * (n_in * width + width * width + width)
 
 
-KERNEL_SOURCES = ["paper_2310_01775_amd/csrc/rollout.hip", "paper_2310_01775_amd/csrc/common.h"]
-PROFILE = os.path.join(ROOT, "profiles", "rollout_adj_n16384_counters.md")
+PROFILE = os.path.join(ROOT, "profiles", "stages_n16384_counters.md")
 
 
 def kernel_source_hash():
+    """SHA-256 (first 16 hex digits) of every kernel source, *.hip then *.h in
+    name order: the counters in PROFILE hold only while it matches."""
+    import glob
     import hashlib
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
-        h.update(open(os.path.join(ROOT, f), "rb").read())
+    csrc = os.path.join(ROOT, "paper_2310_01775_amd", "csrc")
+    for f in sorted(glob.glob(os.path.join(csrc, "*.hip"))) + sorted(glob.glob(os.path.join(csrc, "*.h"))):
+        h.update(open(f, "rb").read())
     return h.hexdigest()[:16]
 
 
@@ -117,7 +120,7 @@ def _oracle_stage_times(net_params, enc, scene, w, th, iters, s_iters):
     N, d = th.shape
     rng = np.random.default_rng(0)
     t = {}
-    ns = 1024
+    ns = 4096
     x = th[rng.choice(N, ns, replace=False)]
     t0 = time.perf_counter()
     sim.cost_and_grad(scene, w, x)
@@ -127,11 +130,11 @@ def _oracle_stage_times(net_params, enc, scene, w, th, iters, s_iters):
     mlp.surrogate_cost_and_grad(net_params, th[:nm], enc, w)
     t["mlp_per_particle"] = (time.perf_counter() - t0) / nm
     g = rng.standard_normal(th.shape) * 20.0
-    nr = 2048
+    nr = 8192
     t0 = time.perf_counter()
     svgd.svgd_phi_rows(th, g, 1.0, np.arange(nr))
     t["phi_per_row"] = (time.perf_counter() - t0) / nr
-    nmed = 8192
+    nmed = N
     t0 = time.perf_counter()
     svgd.median_sqdist_blocked(th[:nmed])
     t["median_per_pair"] = (time.perf_counter() - t0) / (nmed * (nmed - 1) / 2)
@@ -150,10 +153,9 @@ def _oracle_stage_times(net_params, enc, scene, w, th, iters, s_iters):
 def cpu_baseline_surrogate(net_params, enc, scene, w, th, iters, s_iters):
     """The FP64 oracle as it stands, timed on bounded samples of every stage of
     the surrogate-form solve and extrapolated per iteration to N = 16384: the
-    rollout + autodiff gradient on 1024 particles, the network's cost + input
-    gradient on all N, the SVGD direction on 2048 rows against all N, the exact
-    median on the pairs of 8192 particles (scaled by the pair count), Adam on
-    all of theta; once on every host core and once on one."""
+    rollout + autodiff gradient on 4096 particles, the network's cost + input
+    gradient on all N, the SVGD direction on 8192 rows against all N, the exact
+    median over all pairs, Adam on all of theta; once on every host core and once on one."""
     import torch
     from threadpoolctl import threadpool_limits
 
@@ -178,8 +180,8 @@ def cpu_baseline_surrogate(net_params, enc, scene, w, th, iters, s_iters):
             "plain_value": N * iters / allc["plain_solve_s"], "cpu_model": model,
             "stage_seconds": {k: v for k, v in allc.items() if not k.endswith("solve_s")},
             "sample": f"FP64 oracle stages on bounded samples of the N={N}, B=3, H=5, T=200 workload "
-                      f"(rollout+autodiff on 1024 particles, network on all, phi on 2048 rows x N, exact median "
-                      f"over the pairs of 8192 particles, Adam on all), extrapolated to a {iters}-iteration "
+                      f"(rollout+autodiff on 4096 particles, network on all, phi on 8192 rows x N, exact median "
+                      f"over all pairs, Adam on all), extrapolated to a {iters}-iteration "
                       f"surrogate-form solve ({s_iters} network iterations); {wall_all:.1f} s on {avail} cores, "
                       f"{wall_one:.1f} s on 1 core"}
 
@@ -435,7 +437,9 @@ def bench_headline(args):
         peak = MFMA_FP32_PEAK_TFLOPS if dom == "direction_fp32" else MFMA_BF16_PEAK_TFLOPS
         achieved = fl / (ms[dom] * 1e-3) / 1e12
         roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-                "traffic": None, "kernel": dom, "kernel_ms": ms[dom]}
+                "traffic": measured_traffic(dom), "kernel_ms": ms[dom], "flops_per_launch": fl,
+                "kernel": ("k_phi32<8,2> (FP32 matrix cores; the stage also holds k_pack32_v and k_reduce32)"
+                           if dom == "direction_fp32" else dom)}
 
     out = {
         "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": args.steps,

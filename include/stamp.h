@@ -156,10 +156,9 @@ int32_t stamp_set_launch_shape(stamp_ctx* ctx, int32_t roll_block, int32_t roll_
  * own lane (more waves: faster while the rollout is latency-bound on a small
  * particle set), STAMP_LAYOUT_PACKED one lane per sub-rollout holding all its
  * blocks (about half the instructions per particle), for the forward and the
- * adjoint alike.  STAMP_LAYOUT_AUTO (default): the forward keeps one lane per
- * block (its tape stores coalesce better), the adjoint takes the packed
- * layout once the block-per-lane form would need 2^17 lanes (two waves per
- * SIMD), e.g. from 8192 particles of 3 or 4 blocks.  Applies to every rollout
+ * adjoint alike.  STAMP_LAYOUT_AUTO (default): packed once the block-per-lane
+ * form would need 2^17 lanes (two waves per SIMD), e.g. from 8192 particles of
+ * 3 or 4 blocks, or a whole batch of that many lanes.  Applies to every rollout
  * of the context's later calls.  STAMP_EINVAL for another value. */
 #define STAMP_LAYOUT_AUTO 0
 #define STAMP_LAYOUT_BLOCKS 1

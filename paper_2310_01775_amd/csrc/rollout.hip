@@ -913,8 +913,30 @@ __device__ __forceinline__ float blocks_sum(const float (&v)[B]) {
     else return (v[0] + v[1]) + (v[2] + v[3]);
 }
 
-// Forward rollout of one packed lane (particle i, side s); as rollout_fwd_lane.
+// Orders a wave's LDS writes before its later LDS reads by other lanes of the
+// same wave (and those reads before later writes): LDS instructions of one
+// wave execute in issue order; the fences keep the compiler from moving them
+// and wait for the writes.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <int B>
+__device__ __forceinline__ void stage_blks(const Blk (&X)[B], float* stage, int lw) {
+    float2* q = reinterpret_cast<float2*>(stage + lw * 6 * B);
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+        q[3 * b + 0] = make_float2(X[b].x, X[b].y);
+        q[3 * b + 1] = make_float2(X[b].ph, X[b].vx);
+        q[3 * b + 2] = make_float2(X[b].vy, X[b].om);
+    }
+}
+
+// Forward rollout of one packed lane (particle i, side s); as rollout_fwd_lane.
+// WAVES: waves per workgroup (each stages its tape stores in its own LDS region).
+template <int B, int WAVES>
 __device__ __forceinline__ void rollout_fwd_packed(const SimConst& c, int N, const float* __restrict__ theta,
                                                    float* __restrict__ cost, float* __restrict__ tape,
                                                    const TapeGeom& g, uint32_t* status, int64_t lane) {
@@ -925,6 +947,15 @@ __device__ __forceinline__ void rollout_fwd_packed(const SimConst& c, int N, con
     const uint32_t off = (uint32_t)(((int64_t)4 * i + s) * B * 6);
     const int64_t stride = 6 * B * g.lanes;
     const int H = c.H, T = c.T;
+    // the wave's span of a tape entry: its live lanes' 6B floats each, from
+    // the first lane's slot on (a multiple of 4 floats: lanes come in
+    // particles of 4)
+    __shared__ __align__(16) float stage_all[WAVES][64 * 6 * B];  // one region per wave of a workgroup
+    float* stage = stage_all[WAVES == 1 ? 0 : (threadIdx.x >> 6) % WAVES];
+    const int lw = (int)(lane & 63);
+    const int64_t lane0 = lane - lw;
+    const int64_t wave_off = lane0 * 6 * B;
+    const int span4 = (int)(min((int64_t)64, (int64_t)4 * N - lane0) * 6 * B / 4);
     Blk S[B];
 #pragma unroll
     for (int b = 0; b < B; ++b) {
@@ -957,9 +988,17 @@ __device__ __forceinline__ void rollout_fwd_packed(const SimConst& c, int N, con
         prof.reset(invL);
         const int nst = tk1 - tk;
         if (tape && g.ckpt == 0) {
-            float* e = tape + (int64_t)tk * stride;
+            // Each step's states go through LDS so that the wave writes its
+            // contiguous span of the entry with 16-byte stores of consecutive
+            // lanes (a lane's own 6B floats would make every store
+            // instruction touch B times the cache lines).
+            float* e = tape + (int64_t)tk * stride + wave_off;
             for (int j = 0; j < nst; ++j, e += stride) {
-                if (live) store_blks<B>(X, e, off);
+                stage_blks<B>(X, stage, lw);
+                wave_lds_sync();
+                for (int k = lw; k < span4; k += 64)
+                    *reinterpret_cast<float4*>(e + 4 * k) = *reinterpret_cast<const float4*>(stage + 4 * k);
+                wave_lds_sync();
                 step_forward_packed<B>(c, X, p, prof.at(j));
             }
         } else {
@@ -1192,7 +1231,7 @@ __global__ __launch_bounds__(kRolloutBlock) void k_rollout_fwd_packed(SimConst c
                                                                       float* __restrict__ tape, TapeGeom g,
                                                                       uint32_t* status) {
     const int64_t lane = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    rollout_fwd_packed<B>(c, N, theta, cost, tape, g, status, lane);
+    rollout_fwd_packed<B, 1>(c, N, theta, cost, tape, g, status, lane);
 }
 
 template <int B>
@@ -1235,7 +1274,7 @@ __device__ __forceinline__ void fwd_tile(const ProblemDesc& D, int i0, int l, co
                                          float* tape, uint32_t* status) {
     const int64_t lane = (int64_t)(PK ? 4 : Slots<B>::LANES) * i0 + l;
     if constexpr (PK)
-        rollout_fwd_packed<B>(D.c, D.N, theta + D.theta_off, cost + D.cost_off, tape ? tape + D.tape_off : nullptr,
+        rollout_fwd_packed<B, 4>(D.c, D.N, theta + D.theta_off, cost + D.cost_off, tape ? tape + D.tape_off : nullptr,
                               D.g, status, lane);
     else
         rollout_fwd_lane<B>(D.c, D.N, theta + D.theta_off, cost + D.cost_off, tape ? tape + D.tape_off : nullptr,

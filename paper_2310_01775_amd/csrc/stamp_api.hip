@@ -209,18 +209,20 @@ bool scene_ok(const stamp_scene* s) {
 int64_t block_lanes(int N, int B) { return (int64_t)4 * (B == 1 ? 1 : (B == 2 ? 2 : 4)) * N; }
 
 // Automatic layout.  The block-per-lane form keeps more waves in flight,
-// which pays while a rollout is latency-bound (few waves per SIMD).  Once its
-// lanes fill the chip (kPackedAutoLanes) the packed adjoint, with a single
-// lane per sub-rollout, issues about half the instructions per particle and
-// wins (N = 16384, B = 3: 178 vs 343 us); the packed forward does not (397 vs
-// 244 us: each lane's tape stores span 6B floats, so a wave's store touches
-// B times the cache lines), so the forward keeps one lane per block.  The
-// tape layout is the same, and so are the results, bit for bit.
+// which pays while a rollout is latency-bound (few waves per SIMD: at N = 1024
+// or 4096 particles of 3 blocks it is 1.3-1.6x faster).  Once its lanes fill
+// the chip (kPackedAutoLanes), one lane per sub-rollout issues about half the
+// instructions per particle and wins: N = 16384, B = 3, forward 177 vs 236 us,
+// adjoint 178 vs 336 us; the 64-problem batch 1.88 vs 2.12 ms per iteration.
+// The tape layout is the same, and so are the results, bit for bit.  (The
+// forward and the adjoint take the rule separately, so either may be chosen
+// on its own.)
 constexpr int64_t kPackedAutoLanes = (int64_t)2 * 64 * 1024;
 bool packed_for(const stamp_ctx* ctx, int64_t lanes, bool adjoint) {
+    (void)adjoint;
     if (ctx->rollout_layout == STAMP_LAYOUT_BLOCKS) return false;
     if (ctx->rollout_layout == STAMP_LAYOUT_PACKED) return true;
-    return adjoint && lanes >= kPackedAutoLanes;
+    return lanes >= kPackedAutoLanes;
 }
 
 constexpr int kGraphUnroll = 4;  // iterations per unrolled graph
