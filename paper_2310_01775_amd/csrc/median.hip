@@ -38,6 +38,8 @@
 // Sampled path: the bandwidth from the sample's own lower median.
 #include <math.h>
 
+#include <type_traits>
+
 #include "bf16_operands.h"
 #include "common.h"
 #include "internal.h"
@@ -51,7 +53,7 @@ namespace {
 constexpr uint32_t kModeDone = 0, kModePass0 = 1, kModeCand = 2, kModeAll = 3;
 constexpr float kBracketSigmas = 6.0f;
 constexpr uint32_t kWaveBuf = 512;        // candidates a wave stages in LDS between flushes
-constexpr int kGramGroup = 1;             // column chunks of one Gram-form item
+constexpr int kGramGroup = 2;             // column chunks of one Gram-form item
 constexpr uint32_t kSentinel = 0xffffffffu;  // above every candidate interval
 constexpr int kSelThreads = 1024;         // threads of the sample select
 
@@ -561,14 +563,17 @@ __device__ void med_item_gram(const MedView& v, int rb, int cc) {
     const int cc1 = min(cc + kGramGroup, v.cc);
     constexpr int NT = 256;
     static_assert(ROWS == 64 || ROWS == 256, "item shape");
-    __shared__ uint32_t lh[kMedBins];
+    // pass 0 stages candidates per wave, the histogram passes count into lh:
+    // one LDS region serves both
+    constexpr uint32_t kBuf = 2048;  // flushed when a step (at most 16 x 64 values) might not fit
+    static_assert(kMedBins <= (NT / 64) * kBuf, "histogram inside the staging region");
+    __shared__ uint32_t lds_region[(NT / 64) * kBuf];
+    uint32_t* const lh = lds_region;
     __shared__ uint32_t red[2][NT / 64];
-    constexpr uint32_t kBuf = 1024;  // a 16-column step yields at most 16 x 64 candidates per wave
-    __shared__ uint32_t wbuf[NT / 64][kBuf];
     SelState* sel = v.sel;
     const uint32_t mode = sel->mode;
     if (mode != kModePass0 && mode != kModeAll) return;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int col = lane & 15, kq = lane >> 4;
     const int N = v.N;
     const int row0 = rb * ROWS, col0 = cc * kMedCols;
@@ -602,9 +607,9 @@ __device__ void med_item_gram(const MedView& v, int rb, int cc) {
     const int seg = (int)(mix32(blockIdx.y * gridDim.x + blockIdx.x) % kCandSegs);
     const uint32_t seg_cap = v.cap / kCandSegs;
     uint32_t* segbuf = v.cand + (size_t)seg * seg_cap;
-    uint32_t* wb = wbuf[wave];
+    uint32_t* wb = lds_region + wave * kBuf;
     uint32_t nwb = 0;
-    auto flush = [&]() {
+    auto flush = [&]() __attribute__((always_inline)) {
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");  // the wave's LDS writes before its reads
         uint32_t base = 0;
         if (lane == 0) {
@@ -617,71 +622,83 @@ __device__ void med_item_gram(const MedView& v, int rb, int cc) {
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");  // reads before the next writes
         nwb = 0;
     };
-    uint32_t nb = 0, na = 0;
+    // wave-uniform counts of the wave's valid pairs, of those below lo and of
+    // those inside [lo, hi] (a pair is inside iff bits - lo <= hi - lo,
+    // unsigned); the pairs above hi are the rest
+    uint32_t nvalid = 0, nb = 0, nin = 0;
+    const uint32_t wlo = hi - lo;
     // the first step with a pair j > i for some row of the wave; the next
     // step's operands load while this one computes
     int c0 = cbeg;
     while (c0 < cend && col0 + c0 + 15 <= wrow) c0 += cstep;
     float xb[KS], xn[KS];
     float nj = 0.0f, nn = 0.0f;
-    auto load = [&](int c, float (&x)[KS], float& n) {
+    auto load = [&](int c, float (&x)[KS], float& n) __attribute__((always_inline)) {
         const float* p = v.xr + (int64_t)(col0 + c + col) * (4 * KS) + kq * KS;
 #pragma unroll
         for (int k = 0; k < KS; ++k) x[k] = p[k];
         n = v.nrm[col0 + c + col];
     };
-    if (c0 < cend) load(c0, xb, nj);
-    for (int c = c0; c < cend; c += cstep) {
-        if (c + cstep < cend) load(c + cstep, xn, nn);
-        const int j = col0 + c + col;
-        // the lane's 16 distances of this step: counts, and the in-bracket
-        // ones marked for one wave-wide append
-        uint32_t bv[16], inm = 0;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            f4v S = f4v{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-            for (int k = 0; k < KS; ++k) S = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[r][k], xb[k], S, 0, 0, 0);
-#pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const int i = wrow + 16 * r + 4 * kq + t;
-                const float D = fmaxf(fmaf(-2.0f, S[t], ni[r][t] + nj), 0.0f);
-                const bool valid = i < N && j < N && j > i;
-                const uint32_t bits = __float_as_uint(D);
-                const bool below = valid && bits < lo;
-                const bool above = valid && bits > hi;
-                const bool inr = valid && !below && !above;
-                nb += below ? 1u : 0u;
-                na += above ? 1u : 0u;
-                bv[4 * r + t] = bits;
-                inm |= (inr ? 1u : 0u) << (4 * r + t);
+    // one distance of the step: counted, and appended (pass 0) or
+    // histogrammed when inside the bracket; ALL: every pair of the step is
+    // valid (no row or column checks)
+    auto classify = [&](auto all_tag, auto p0_tag, uint32_t x, bool valid) __attribute__((always_inline)) {
+        constexpr bool ALL = decltype(all_tag)::value, P0 = decltype(p0_tag)::value;
+        const bool in = (ALL || valid) && x - lo <= wlo;
+        if (P0) {
+            nb += (uint32_t)__popcll(__ballot((ALL || valid) && x < lo));
+            if (!ALL) nvalid += (uint32_t)__popcll(__ballot(valid));
+        }
+        const uint64_t m = __ballot(in);
+        if (m) {
+            if (P0) {
+                const uint32_t nm = (uint32_t)__popcll(m);
+                nin += nm;
+                const uint32_t pos =
+                    nwb + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                if (in) wb[pos] = x;
+                nwb = __builtin_amdgcn_readfirstlane(nwb + nm);  // uniform: keep it scalar
+            } else if (in) {
+                atomicAdd(&lh[(x - lo) >> s], 1u);
             }
         }
+    };
+    auto sweep = [&](auto p0_tag) __attribute__((always_inline)) {
+        constexpr bool P0 = decltype(p0_tag)::value;
+        if (c0 < cend) load(c0, xb, nj);
+        for (int c = c0; c < cend; c += cstep) {
+            if (c + cstep < cend) load(c + cstep, xn, nn);
+            const int jb = col0 + c, j = jb + col;
+            // a step appends at most 16 x 64 values
+            if (P0 && nwb + 1024 > kBuf) flush();
+            uint32_t bv[16];
 #pragma unroll
-        for (int k = 0; k < KS; ++k) xb[k] = xn[k];
-        nj = nn;
-        if (!pass0) {
+            for (int r = 0; r < 4; ++r) {
+                f4v S = f4v{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-            for (int e = 0; e < 16; ++e)
-                if ((inm >> e) & 1u) atomicAdd(&lh[(bv[e] - lo) >> s], 1u);
-            continue;
-        }
-        const uint32_t cnt_l = (uint32_t)__popc(inm);
-        uint32_t incl = cnt_l;  // inclusive prefix sum over the wave
-        for (int off = 1; off < 64; off <<= 1) {
-            const uint32_t y = __shfl_up(incl, off);
-            if (lane >= off) incl += y;
-        }
-        const uint32_t total = __shfl(incl, 63);
-        if (total) {
-            if (nwb + total > kBuf) flush();
-            uint32_t k = nwb + incl - cnt_l;
+                for (int k = 0; k < KS; ++k) S = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[r][k], xb[k], S, 0, 0, 0);
 #pragma unroll
-            for (int e = 0; e < 16; ++e)
-                if ((inm >> e) & 1u) wb[k++] = bv[e];
-            nwb += total;
+                for (int t = 0; t < 4; ++t)
+                    bv[4 * r + t] = __float_as_uint(fmaxf(fmaf(-2.0f, S[t], ni[r][t] + nj), 0.0f));
+            }
+#pragma unroll
+            for (int k = 0; k < KS; ++k) xb[k] = xn[k];
+            nj = nn;
+            if (jb > wrow + 63 && jb + 16 <= N) {  // wave-uniform
+#pragma unroll
+                for (int e = 0; e < 16; ++e) classify(std::true_type{}, p0_tag, bv[e], true);
+                nvalid += 1024;
+            } else {
+#pragma unroll
+                for (int e = 0; e < 16; ++e) {
+                    const int i = wrow + 16 * (e >> 2) + 4 * kq + (e & 3);
+                    classify(std::false_type{}, p0_tag, bv[e], i < N && j < N && j > i);
+                }
+            }
         }
-    }
+    };
+    if (pass0) sweep(std::true_type{});
+    else sweep(std::false_type{});
     if (!pass0) {
         __syncthreads();
         for (int b = tid; b < kMedBins; b += NT)
@@ -709,13 +726,9 @@ __device__ void med_item_gram(const MedView& v, int rb, int cc) {
         for (uint32_t e = (uint32_t)lane; e < nwb; e += 64)
             if (off + e < seg_cap) segbuf[off + e] = wb[e];
     }
-    for (int off = 32; off > 0; off >>= 1) {  // counts of the workgroup
-        nb += __shfl_xor(nb, off);
-        na += __shfl_xor(na, off);
-    }
-    if (lane == 0) {
+    if (lane == 0) {  // counts of the workgroup
         red[0][wave] = nb;
-        red[1][wave] = na;
+        red[1][wave] = nvalid - nb - nin;
     }
     __syncthreads();
     if (tid == 0) {

@@ -11,11 +11,11 @@
 // so every B operand is one contiguous 16-byte load.  Layer 3 (one output)
 // and the GELUs are FP32 VALU work.
 //
-// Inference (k_mlp_infer): a workgroup takes 64 samples, each wave 16 rows;
-// the wave keeps its 16 x 256 pre-activations of layer 2 in registers, and
-// runs forward, the output dot, and the input gradient
+// Inference (k_mlp_infer): a workgroup of four waves takes 64 samples and the
+// waves split the neurons of every layer; it runs forward, the output dot, and
+// the input gradient
 //   dy/dx = ((w3 * gelu'(z2)) W2 * gelu'(z1)) W1 * inv_sigma
-// with z1 recomputed by MFMA instead of stored.
+// with gelu'(z1) kept in registers from the forward.
 // Training (k_mlp_train_fb, k_mlp_wgrad, k_mlp_adam): the same forward with
 // the loss gradient, activations written feature-major for the weight
 // gradients dW = delta^T act (MFMA with the samples as K), per-tile bias
@@ -203,197 +203,240 @@ __device__ __forceinline__ float bound_grad(const BoundTerm& bt, int f, float x)
 // for f < d (structure of arrays, the SVGD gradient layout; grad_out holds
 // exactly d rows of M, in either input layout).
 //
-// A wave takes kInfRB blocks of 16 samples: each weight fragment it loads (16
-// output columns x 256 inputs, eight 16-byte loads in flight) feeds kInfRB
-// matrix products, and delta2 = w3 gelu'(z2) goes to LDS as layer 2 runs.
-constexpr int kInfRB = 2;     // 16-sample blocks per wave
-constexpr int kInfWaves = 1;  // waves per workgroup
-constexpr int kInfRows = 16 * kInfRB * kInfWaves;
+// A workgroup of NW waves takes 16 SB samples; the waves split the 256
+// neurons of each layer (TN = 16 / NW tiles of 16 each), so every weight
+// fragment is read once per workgroup and all four SIMDs of a CU work.  The
+// products are taken transposed, Z^T = W U^T: the weights are the A operand
+// (rows of W, one 16-byte load a lane), the activations the B operand (rows
+// of the sample-major LDS buffers), and a lane receives four consecutive
+// neurons of one sample, which it writes to LDS as one 8-byte store.  The
+// biases start the accumulators.  gelu'(z1) stays in registers from the
+// forward for the input gradient (same layout as the backward product).
+template <int NW>
+struct InferShape {
+    static constexpr int TN = 16 / NW;  // 16-neuron tiles per wave
+};
 
-// acc[rb] += A_rb (16 rows x 32 KS, LDS) * B for KS k-steps, B fragments given.
-template <int KS>
-__device__ __forceinline__ void mma_blocks(const __bf16* A, int lda, const bf16x8 (&bv)[KS], f4 (&acc)[kInfRB]) {
+// Fragment of A = rows n0..n0+15 of a row-major bf16 matrix with ld columns,
+// k-step kk (32 columns).
+__device__ __forceinline__ bf16x8 a_frag(const __bf16* __restrict__ W, int ld, int n0, int kk) {
     const int l = threadIdx.x & 63;
-    const int r = l & 15, kq = l >> 4;
-#pragma unroll
-    for (int rb = 0; rb < kInfRB; ++rb) {
-        const __bf16* a = A + (rb * 16 + r) * lda + 8 * kq;
-#pragma unroll
-        for (int k = 0; k < KS; ++k)
-            acc[rb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(*reinterpret_cast<const bf16x8*>(a + 32 * k), bv[k],
-                                                              acc[rb], 0, 0, 0);
-    }
+    return *reinterpret_cast<const bf16x8*>(W + (int64_t)(n0 + (l & 15)) * ld + 32 * kk + 8 * (l >> 4));
+}
+// Fragment of B = activations of samples s0..s0+15 (sample-major LDS, row stride ld), k-step kk.
+__device__ __forceinline__ bf16x8 b_frag(const __bf16* S, int ld, int s0, int kk) {
+    const int l = threadIdx.x & 63;
+    return *reinterpret_cast<const bf16x8*>(S + (s0 + (l & 15)) * ld + 32 * kk + 8 * (l >> 4));
+}
+// Four bf16 values as one 8-byte LDS store.
+__device__ __forceinline__ void store4(__bf16* p, float a, float b, float c, float d) {
+    typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
+    bf16x4 v = {(__bf16)a, (__bf16)b, (__bf16)c, (__bf16)d};
+    *reinterpret_cast<bf16x4*>(p) = v;
 }
 
-// The KS k-step B fragments of output columns n0..n0+15 of Bt [n][ldb].
-template <int KS>
-__device__ __forceinline__ void load_frags(const __bf16* __restrict__ Bt, int ldb, int n0, bf16x8 (&bv)[KS]) {
-    const int l = threadIdx.x & 63;
-    const __bf16* b = Bt + (int64_t)(n0 + (l & 15)) * ldb + 8 * (l >> 4);
-#pragma unroll
-    for (int k = 0; k < KS; ++k) bv[k] = *reinterpret_cast<const bf16x8*>(b + 32 * k);
-}
-
-__global__ __launch_bounds__(64 * kInfWaves) void k_mlp_infer(const float* __restrict__ P,
-                                                                const __bf16* __restrict__ Wb,
-                                                                const float* __restrict__ X, int x_mode, int M,
-                                                                int n_in, int d, const float* __restrict__ enc,
-                                                                BoundTerm bt, float* __restrict__ y_out,
-                                                                float* __restrict__ cost_out,
-                                                                float* __restrict__ grad_out, float grad_scale) {
-    constexpr int R = 16 * kInfRB;  // samples per wave
-    __shared__ __bf16 sU[kInfWaves][R * kLdU];
-    __shared__ __bf16 sH[kInfWaves][R * kLdH];
-    __shared__ __bf16 sD[kInfWaves][R * kLdH];
-    const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
-    const int kq = l >> 4, col = l & 15;
-    const int row0 = blockIdx.x * kInfRows + wave * R;
-    __bf16* U = sU[wave];
-    __bf16* Hb = sH[wave];
-    __bf16* Db = sD[wave];
+template <int NW, int SB>
+__global__ __launch_bounds__(64 * NW) void k_mlp_infer(const float* __restrict__ P, const __bf16* __restrict__ Wb,
+                                                       const float* __restrict__ X, int x_mode, int M, int n_in, int d,
+                                                       const float* __restrict__ enc, BoundTerm bt,
+                                                       float* __restrict__ y_out, float* __restrict__ cost_out,
+                                                       float* __restrict__ grad_out, float grad_scale) {
+    constexpr int TN = InferShape<NW>::TN;
+    constexpr int S = 16 * SB;  // samples per workgroup
+    constexpr int K1 = kIn / 32, K2 = kW / 32;
+    __shared__ __align__(16) __bf16 sU[S * kLdU];
+    __shared__ __align__(16) __bf16 sH[S * kLdH];  // h1, then delta1
+    __shared__ __align__(16) __bf16 sD[S * kLdH];  // delta2
+    __shared__ __align__(16) float sB1[kW], sB2[kW], sW3[kW], sIs[kIn];
+    __shared__ float sYp[NW][S];
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int l = threadIdx.x & 63, col = l & 15, kq = l >> 4;
+    const int row0 = blockIdx.x * S;
+    const int n0 = wave * 16 * TN;  // the wave's first neuron
     const MlpPtrs m = mlp_ptrs(P, Wb);
     const bool want_grad = grad_out != nullptr;
-    // Biases, output weights and input scales in LDS: global loads complete
-    // in order, so a global load of one of them inside a loop would make
-    // the wave wait for the weight fragments prefetched before it.
-    __shared__ float sB1[kW], sB2[kW], sW3[kW], sIs[kIn];
-    for (int c = threadIdx.x; c < kW; c += 64 * kInfWaves) {
+
+    // this wave's weight fragments of both forward layers, in flight while
+    // the inputs are staged (loads complete in order: layer 1's first)
+    bf16x8 a1[TN][K1], a2[TN][K2];
+#pragma unroll
+    for (int a = 0; a < TN; ++a)
+#pragma unroll
+        for (int k = 0; k < K1; ++k) a1[a][k] = a_frag(m.W1, kIn, n0 + 16 * a, k);
+#pragma unroll
+    for (int a = 0; a < TN; ++a)
+#pragma unroll
+        for (int k = 0; k < K2; ++k) a2[a][k] = a_frag(m.W2, kW, n0 + 16 * a, k);
+    for (int c = threadIdx.x; c < kW; c += 64 * NW) {
         sB1[c] = m.b1[c];
         sB2[c] = m.b2[c];
         sW3[c] = m.w3[c];
     }
-    for (int f = threadIdx.x; f < kIn; f += 64 * kInfWaves) sIs[f] = m.isig[f];
+    for (int f = threadIdx.x; f < kIn; f += 64 * NW) sIs[f] = m.isig[f];
+    for (int b = wave; b < SB; b += NW) stage_inputs(sU + b * 16 * kLdU, m, X, x_mode, M, n_in, d, enc, row0 + 16 * b);
+    __syncthreads();
 
+    // layer 1: z1^T = W1 u^T + b1; h1 to LDS, gelu'(z1) kept
+    float gp1[TN][SB][4];
+    {
+        f4 acc[TN][SB];
 #pragma unroll
-    for (int rb = 0; rb < kInfRB; ++rb) stage_inputs(U + rb * 16 * kLdU, m, X, x_mode, M, n_in, d, enc, row0 + rb * 16);
-    __syncthreads();
-    // Each column block's weight fragments are loaded two blocks ahead (a
-    // ring of three), so the L2 latency of a fragment overlaps the matrix
-    // products of the two blocks before it; the loops are unrolled so the
-    // ring slots are fixed registers.
-    // layer 1
-    bf16x8 r1[3][kIn / 32];
-    load_frags<kIn / 32>(m.W1, kIn, 0, r1[0]);
-    load_frags<kIn / 32>(m.W1, kIn, 16, r1[1]);
+        for (int a = 0; a < TN; ++a) {
+            const f4 bias = *reinterpret_cast<const f4*>(sB1 + n0 + 16 * a + 4 * kq);
 #pragma unroll
-    for (int cb = 0; cb < kW / 16; ++cb) {
-        if (cb + 2 < kW / 16) load_frags<kIn / 32>(m.W1, kIn, (cb + 2) * 16, r1[(cb + 2) % 3]);
-        f4 acc[kInfRB] = {};
-        mma_blocks<kIn / 32>(U, kLdU, r1[cb % 3], acc);
-        const int c = cb * 16 + col;
-        const float b1 = sB1[c];
+            for (int b = 0; b < SB; ++b) acc[a][b] = bias;
+        }
 #pragma unroll
-        for (int rb = 0; rb < kInfRB; ++rb)
-            for (int j = 0; j < 4; ++j) Hb[(rb * 16 + 4 * kq + j) * kLdH + c] = (__bf16)gelu(acc[rb][j] + b1);
+        for (int k = 0; k < K1; ++k) {
+            bf16x8 bu[SB];
+#pragma unroll
+            for (int b = 0; b < SB; ++b) bu[b] = b_frag(sU, kLdU, 16 * b, k);
+#pragma unroll
+            for (int a = 0; a < TN; ++a)
+#pragma unroll
+                for (int b = 0; b < SB; ++b)
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1[a][k], bu[b], acc[a][b], 0, 0, 0);
+        }
+#pragma unroll
+        for (int a = 0; a < TN; ++a)
+#pragma unroll
+            for (int b = 0; b < SB; ++b) {
+                float h[4];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) gelu_pair(acc[a][b][t], h[t], gp1[a][b][t]);
+                store4(sH + (16 * b + col) * kLdH + n0 + 16 * a + 4 * kq, h[0], h[1], h[2], h[3]);
+            }
     }
     __syncthreads();
+
     // layer 2, the output dot and delta2 = w3 gelu'(z2)
-    float yp[kInfRB][4] = {};
-    bf16x8 r2[3][kW / 32];
-    load_frags<kW / 32>(m.W2, kW, 0, r2[0]);
-    load_frags<kW / 32>(m.W2, kW, 16, r2[1]);
+    {
+        f4 acc[TN][SB];
 #pragma unroll
-    for (int cb = 0; cb < kW / 16; ++cb) {
-        if (cb + 2 < kW / 16) load_frags<kW / 32>(m.W2, kW, (cb + 2) * 16, r2[(cb + 2) % 3]);
-        f4 acc[kInfRB] = {};
-        mma_blocks<kW / 32>(Hb, kLdH, r2[cb % 3], acc);
-        const int c = cb * 16 + col;
-        const float b2 = sB2[c], w3 = sW3[c];
+        for (int a = 0; a < TN; ++a) {
+            const f4 bias = *reinterpret_cast<const f4*>(sB2 + n0 + 16 * a + 4 * kq);
 #pragma unroll
-        for (int rb = 0; rb < kInfRB; ++rb)
-            for (int j = 0; j < 4; ++j) {
-                float g, gp;
-                gelu_pair(acc[rb][j] + b2, g, gp);
-                yp[rb][j] = fmaf(w3, g, yp[rb][j]);
-                if (want_grad) Db[(rb * 16 + 4 * kq + j) * kLdH + c] = (__bf16)(w3 * gp);
-            }
-    }
-    float y[kInfRB][4];
-#pragma unroll
-    for (int rb = 0; rb < kInfRB; ++rb)
-        for (int j = 0; j < 4; ++j) y[rb][j] = sum16(yp[rb][j]) + m.b3;
-    __syncthreads();
-    if (want_grad) {
-        // delta1 = (delta2 W2) * gelu'(z1), z1 recomputed
-        bf16x8 rt[3][kW / 32], rw[3][kIn / 32];
-#pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            load_frags<kW / 32>(m.W2T, kW, q * 16, rt[q]);
-            load_frags<kIn / 32>(m.W1, kIn, q * 16, rw[q]);
+            for (int b = 0; b < SB; ++b) acc[a][b] = bias;
         }
 #pragma unroll
-        for (int kb = 0; kb < kW / 16; ++kb) {
-            if (kb + 2 < kW / 16) {
-                load_frags<kW / 32>(m.W2T, kW, (kb + 2) * 16, rt[(kb + 2) % 3]);
-                load_frags<kIn / 32>(m.W1, kIn, (kb + 2) * 16, rw[(kb + 2) % 3]);
-            }
-            f4 t[kInfRB] = {}, z1[kInfRB] = {};
-            mma_blocks<kW / 32>(Db, kLdH, rt[kb % 3], t);
-            mma_blocks<kIn / 32>(U, kLdU, rw[kb % 3], z1);
-            const int k = kb * 16 + col;
-            const float b1 = sB1[k];
+        for (int k = 0; k < K2; ++k) {
+            bf16x8 bh[SB];
 #pragma unroll
-            for (int rb = 0; rb < kInfRB; ++rb)
-                for (int j = 0; j < 4; ++j)
-                    Hb[(rb * 16 + 4 * kq + j) * kLdH + k] = (__bf16)(t[rb][j] * gelu_grad(z1[rb][j] + b1));
+            for (int b = 0; b < SB; ++b) bh[b] = b_frag(sH, kLdH, 16 * b, k);
+#pragma unroll
+            for (int a = 0; a < TN; ++a)
+#pragma unroll
+                for (int b = 0; b < SB; ++b)
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2[a][k], bh[b], acc[a][b], 0, 0, 0);
+        }
+        // the backward's weight fragments (W2^T rows of the same neurons) load
+        // while the activations are evaluated
+        if (want_grad) {
+#pragma unroll
+            for (int a = 0; a < TN; ++a)
+#pragma unroll
+                for (int k = 0; k < K2; ++k) a2[a][k] = a_frag(m.W2T, kW, n0 + 16 * a, k);
+        }
+        float yp[SB];
+#pragma unroll
+        for (int b = 0; b < SB; ++b) yp[b] = 0.0f;
+#pragma unroll
+        for (int a = 0; a < TN; ++a) {
+            const f4 w3 = *reinterpret_cast<const f4*>(sW3 + n0 + 16 * a + 4 * kq);
+#pragma unroll
+            for (int b = 0; b < SB; ++b) {
+                float dl[4];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    float g, gp;
+                    gelu_pair(acc[a][b][t], g, gp);
+                    yp[b] = fmaf(w3[t], g, yp[b]);
+                    dl[t] = w3[t] * gp;
+                }
+                if (want_grad) store4(sD + (16 * b + col) * kLdH + n0 + 16 * a + 4 * kq, dl[0], dl[1], dl[2], dl[3]);
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < SB; ++b) {
+            const float v = sum_groups(yp[b]);
+            if (kq == 0) sYp[wave][16 * b + col] = v;
         }
     }
     __syncthreads();
+
     if (want_grad) {
-        // dy/dx = delta1 W1, then the chain through the standardisation (only
-        // the first d inputs are asked for).  Global memory operations complete
-        // in order, so every load of a block (the next block's fragments, the
-        // raw inputs of the bound term) is issued before the block's stores.
-        bf16x8 bv[kW / 32], bn[kW / 32];
-        load_frags<kW / 32>(m.W1T, kW, 0, bv);
-        for (int fb = 0; fb * 16 < d && fb < kIn / 16; ++fb) {
-            const int f = fb * 16 + col;
-            const bool more = (fb + 1) * 16 < d && fb + 1 < kIn / 16;
-            if (more) load_frags<kW / 32>(m.W1T, kW, (fb + 1) * 16, bn);
-            float xr[kInfRB][4] = {};
-            if (bt.H && f < d) {
+        // delta1^T = (W2^T delta2^T) * gelu'(z1), to LDS over h1 (every wave is
+        // past layer 2)
+        f4 acc[TN][SB];
 #pragma unroll
-                for (int rb = 0; rb < kInfRB; ++rb)
+        for (int a = 0; a < TN; ++a)
 #pragma unroll
-                    for (int j = 0; j < 4; ++j)
-                        xr[rb][j] = x_raw(X, x_mode, M, n_in, min(row0 + rb * 16 + 4 * kq + j, M - 1), f);
-            }
-            f4 g[kInfRB] = {};
-            mma_blocks<kW / 32>(Hb, kLdH, bv, g);
-            if (f < d) {
-                const float is = sIs[f];
+            for (int b = 0; b < SB; ++b) acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-                for (int rb = 0; rb < kInfRB; ++rb)
+        for (int k = 0; k < K2; ++k) {
+            bf16x8 bd[SB];
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) {
-                        const int i = row0 + rb * 16 + 4 * kq + j;
-                        if (i < M) {
-                            float gi = expf(y[rb][j]) * g[rb][j] * is;
-                            if (bt.H) gi += bound_grad(bt, f, xr[rb][j]);
-                            grad_out[(int64_t)f * M + i] = grad_scale * gi;
-                        }
+            for (int b = 0; b < SB; ++b) bd[b] = b_frag(sD, kLdH, 16 * b, k);
+#pragma unroll
+            for (int a = 0; a < TN; ++a)
+#pragma unroll
+                for (int b = 0; b < SB; ++b)
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2[a][k], bd[b], acc[a][b], 0, 0, 0);
+        }
+#pragma unroll
+        for (int a = 0; a < TN; ++a)
+#pragma unroll
+            for (int b = 0; b < SB; ++b)
+                store4(sH + (16 * b + col) * kLdH + n0 + 16 * a + 4 * kq, acc[a][b][0] * gp1[a][b][0],
+                       acc[a][b][1] * gp1[a][b][1], acc[a][b][2] * gp1[a][b][2], acc[a][b][3] * gp1[a][b][3]);
+        __syncthreads();
+        // dy/dx^T = W1^T delta1^T on (16-input tile, sample block) items taken
+        // by the waves in turn, then the chain through the standardisation
+        // (only the first d inputs are asked for)
+        const int ft = min((d + 15) / 16, kIn / 16);
+        for (int it = wave; it < ft * SB; it += NW) {
+            const int f0 = 16 * (it / SB), b = it % SB;
+            const int s = 16 * b + col, i = row0 + s;
+            bf16x8 aw[K2];
+#pragma unroll
+            for (int k = 0; k < K2; ++k) aw[k] = a_frag(m.W1T, kW, f0, k);
+            float xr[4] = {0.f, 0.f, 0.f, 0.f};
+            if (bt.H && i < M)
+#pragma unroll
+                for (int t = 0; t < 4; ++t) xr[t] = x_raw(X, x_mode, M, n_in, i, min(f0 + 4 * kq + t, d - 1));
+            float y = m.b3;
+            for (int w = 0; w < NW; ++w) y += sYp[w][s];
+            const float ey = expf(y);
+            f4 g = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int k = 0; k < K2; ++k) g = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aw[k], b_frag(sH, kLdH, 16 * b, k), g, 0, 0, 0);
+            if (i < M) {
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const int f = f0 + 4 * kq + t;
+                    if (f < d) {
+                        float gi = ey * g[t] * sIs[f];
+                        if (bt.H) gi += bound_grad(bt, f, xr[t]);
+                        grad_out[(int64_t)f * M + i] = grad_scale * gi;
                     }
-            }
-            if (more)
-#pragma unroll
-                for (int k = 0; k < kW / 32; ++k) bv[k] = bn[k];
-        }
-    }
-    if (col == 0) {
-#pragma unroll
-        for (int rb = 0; rb < kInfRB; ++rb)
-            for (int j = 0; j < 4; ++j) {
-                const int i = row0 + rb * 16 + 4 * kq + j;
-                if (i < M) {
-                    if (y_out) y_out[i] = y[rb][j];
-                    if (cost_out)
-                        cost_out[i] = expm1f(y[rb][j]) + (bt.H ? bound_cost(bt, X, x_mode, M, n_in, i) : 0.0f);
                 }
             }
+        }
+    }
+    for (int s = threadIdx.x; s < S; s += 64 * NW) {
+        const int i = row0 + s;
+        if (i < M) {
+            float y = m.b3;
+            for (int w = 0; w < NW; ++w) y += sYp[w][s];
+            if (y_out) y_out[i] = y;
+            if (cost_out) cost_out[i] = expm1f(y) + (bt.H ? bound_cost(bt, X, x_mode, M, n_in, i) : 0.0f);
+        }
     }
 }
+constexpr int kInfWaves = 8;    // waves per workgroup
+constexpr int kInfBlocks = 4;   // 16-sample blocks per workgroup
+constexpr int kInfRows = 16 * kInfBlocks;
 
-// ---------------------------------------------------------------------------
 // Training forward + backward of a minibatch (M a multiple of 64, inputs AoS):
 // sample i is dataset row src = idx ? idx[i] : i of X [n_rows][n_in], its
 // target log(1 + cost[src]).  An index outside [0, n_rows) reads row 0 and
@@ -690,7 +733,8 @@ hipError_t launch_mlp_infer(const float* P, const __bf16* Wb, const float* X, in
                             const float* enc, int bound_H, float wb, float omax, float dmax, float* y_out,
                             float* cost_out, float* grad_out, float grad_scale, hipStream_t st) {
     const BoundTerm bt{bound_H, wb, omax, dmax};
-    hipLaunchKernelGGL(k_mlp_infer, dim3((M + kInfRows - 1) / kInfRows), dim3(64 * kInfWaves), 0, st, P, Wb, X,
+    hipLaunchKernelGGL((k_mlp_infer<kInfWaves, kInfBlocks>), dim3((M + kInfRows - 1) / kInfRows), dim3(64 * kInfWaves), 0,
+                       st, P, Wb, X,
                        x_mode, M, n_in, d, enc, bt, y_out, cost_out, grad_out, grad_scale);
     return hipGetLastError();
 }

@@ -94,33 +94,52 @@ __device__ void pack32_v_rows(int N, int d, int ot, int row0, const float* __res
 // ---- contraction: partial sums of K V over the columns [j0, j1) -------------------
 // V[j][n] = w_j (X[j][n] + g[n][j]) for the lane's j = jc + 4 kq + t and
 // n = 16 o + col: X from its tile, g from [d][N] (one 16-byte load when the
-// four columns are in range and aligned), w_j = 1 without weights
+// four columns are in range and aligned), w_j = 1 without weights.  The
+// loads are issued by fetch_v and combined by finish_v, so a step's operands
+// can be fetched a step ahead without waiting for them at once.
 template <int OT>
-__device__ __forceinline__ void load_v(int jc, int col, int kq, int N, int d, bool g4, const float* __restrict__ g,
-                                       const float* __restrict__ wts, const View32& v, f4 (&vv)[OT]) {
+struct VRaw {
+    f4 x[OT], g[OT], w;
+};
+
+template <int OT>
+__device__ __forceinline__ void fetch_v(int jc, int col, int kq, int N, int d, bool g4, const float* __restrict__ g,
+                                        const float* __restrict__ wts, const View32& v, VRaw<OT>& R) {
     const int j = jc + 4 * kq;
     const float* vp = v.vt + (int64_t)(jc >> 4) * OT * 256 + col * 16 + kq * 4;
     const bool full = g4 && j + 4 <= N;
 #pragma unroll
     for (int o = 0; o < OT; ++o) {
-        f4 x = *reinterpret_cast<const f4*>(vp + o * 256);
-        const int n = 16 * o + col;
-        const int nc = min(n, d - 1);
-        const float* gp = g + (int64_t)nc * N;
-        f4 gv;
+        R.x[o] = *reinterpret_cast<const f4*>(vp + o * 256);
+        const float* gp = g + (int64_t)min(16 * o + col, d - 1) * N;
         if (full) {
-            gv = *reinterpret_cast<const f4*>(gp + j);
+            R.g[o] = *reinterpret_cast<const f4*>(gp + j);
         } else {
 #pragma unroll
-            for (int t = 0; t < 4; ++t) gv[t] = gp[min(j + t, N - 1)] * (j + t < N ? 1.0f : 0.0f);
+            for (int t = 0; t < 4; ++t) R.g[o][t] = gp[min(j + t, N - 1)];
         }
-        if (n >= d) gv = f4{0.f, 0.f, 0.f, 0.f};
-        vv[o] = x + gv;
+    }
+    if (wts)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) R.w[t] = wts[min(j + t, N - 1)];
+}
+
+template <int OT>
+__device__ __forceinline__ void finish_v(int jc, int col, int kq, int N, int d, const float* __restrict__ wts,
+                                         const VRaw<OT>& R, f4 (&vv)[OT]) {
+    const int j = jc + 4 * kq;
+#pragma unroll
+    for (int o = 0; o < OT; ++o) {
+        f4 gv = R.g[o];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) gv[t] *= j + t < N ? 1.0f : 0.0f;
+        if (16 * o + col >= d) gv = f4{0.f, 0.f, 0.f, 0.f};
+        vv[o] = R.x[o] + gv;
     }
     if (wts) {
         f4 w;
 #pragma unroll
-        for (int t = 0; t < 4; ++t) w[t] = j + t < N ? wts[j + t] : 0.0f;
+        for (int t = 0; t < 4; ++t) w[t] = j + t < N ? R.w[t] : 0.0f;
 #pragma unroll
         for (int o = 0; o < OT; ++o) vv[o] *= w;
     }
@@ -149,19 +168,28 @@ __device__ void phi32_body(int N, int d, int row0, int j0, int j1, int split, in
     for (int r = 0; r < 4; ++r)
 #pragma unroll
         for (int o = 0; o < OT; ++o) acc[r][o] = f4{0.f, 0.f, 0.f, 0.f};
-    // the next 16 columns' operands load while these compute
+    // the next 16 columns' operands load while these compute; V is combined
+    // from its loads only after the step, so the loads stay in flight
     float xj[KS], xn[KS];
-    f4 nj, nn, vb[OT], vn[OT];
-    auto load = [&](int jc, float (&x)[KS], f4& n, f4 (&vv)[OT]) {
+    f4 nj, nn, vb[OT];
+    VRaw<OT> rn;
+    auto load_x = [&](int jc, float (&x)[KS], f4& n) {
         const float* p = v.xr + (int64_t)(jc + col) * (4 * KS) + kq * KS;
 #pragma unroll
         for (int s = 0; s < KS; ++s) x[s] = p[s];
         n = *reinterpret_cast<const f4*>(v.nrm + jc + 4 * kq);
-        load_v<OT>(jc, col, kq, N, d, g4, g, wts, v, vv);
     };
-    if (j0 < j1) load(j0, xj, nj, vb);
+    if (j0 < j1) {
+        load_x(j0, xj, nj);
+        fetch_v<OT>(j0, col, kq, N, d, g4, g, wts, v, rn);
+        finish_v<OT>(j0, col, kq, N, d, wts, rn, vb);
+    }
     for (int jc = j0; jc < j1; jc += 16) {
-        if (jc + 16 < j1) load(jc + 16, xn, nn, vn);
+        const bool more = jc + 16 < j1;
+        if (more) {
+            load_x(jc + 16, xn, nn);
+            fetch_v<OT>(jc + 16, col, kq, N, d, g4, g, wts, v, rn);
+        }
         float cn[4];
 #pragma unroll
         for (int t = 0; t < 4; ++t) cn[t] = c * nj[t];
@@ -179,11 +207,12 @@ __device__ void phi32_body(int N, int d, int row0, int j0, int j1, int split, in
                 for (int o = 0; o < OT; ++o)
                     acc[r][o] = __builtin_amdgcn_mfma_f32_16x16x4f32(kv[t], vb[o][t], acc[r][o], 0, 0, 0);
         }
+        if (more) {
 #pragma unroll
-        for (int s = 0; s < KS; ++s) xj[s] = xn[s];
-        nj = nn;
-#pragma unroll
-        for (int o = 0; o < OT; ++o) vb[o] = vn[o];
+            for (int s = 0; s < KS; ++s) xj[s] = xn[s];
+            nj = nn;
+            finish_v<OT>(jc + 16, col, kq, N, d, wts, rn, vb);
+        }
     }
     float* out = v.part + (int64_t)split * (16 * OT) * npad;
 #pragma unroll
@@ -248,7 +277,7 @@ __global__ __launch_bounds__(256) void k_pack32_v(One32 a, const float* theta, c
 }
 
 template <int KS, int OT>
-__global__ __launch_bounds__(256) void k_phi32(One32 a, const float* g, const float* wts, char* ws) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_phi32(One32 a, const float* g, const float* wts, char* ws) {
     const int split = blockIdx.y;
     const int j0 = split * a.L.chunk32, j1 = min(j0 + a.L.chunk32, a.L.npad);
     phi32_body<KS, OT>(a.N, a.d, blockIdx.x * blockDim.x, j0, j1, split, a.L.npad, g, wts, view32(a.L, ws));
@@ -304,7 +333,7 @@ __global__ __launch_bounds__(256) void k_pack32_v_batched(const ProblemDesc* __r
 
 // entry = (problem, row block of blockDim.x rows, split, -)
 template <int KS, int OT>
-__global__ __launch_bounds__(256) void k_phi32_batched(const ProblemDesc* __restrict__ descs,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_phi32_batched(const ProblemDesc* __restrict__ descs,
                                                        const int4* __restrict__ work, const float* grad,
                                                        const float* wts, char* ws) {
     const int4 e = work[blockIdx.x];
