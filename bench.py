@@ -562,7 +562,10 @@ def bench_plain(args, ctx):
 
 def bench_batched(args):
     """64 seeded problems, N ~ U{64..2048}, H ~ U{2..5}, B ~ U{1..4}, T=200,
-    one stamp_solve call (batched stages, graph replay, autotuned shapes)."""
+    one stamp_solve call (batched stages, graph replay, autotuned shapes):
+    once as one lockstep batch, and once class-scheduled (cfg.classes: the
+    problems in cost classes, cheapest first, each class a batch of its own),
+    where a problem's solve time is its class's end."""
     import numpy as np
     import torch
 
@@ -576,32 +579,41 @@ def bench_batched(args):
     Ns = [th.shape[0] for _, _, th in probs]
     flat = torch.cat([S.soa(th).reshape(-1) for _, _, th in probs]).contiguous()
     lr = W.DEFAULT_ADAM["lr"]
-    work = torch.empty(ctx.solve_workspace_bytes(scenes, Ns, S.make_cfg(args.steps, lr=lr)), dtype=torch.uint8,
-                       device="cuda")
-    times = torch.zeros(len(probs), device="cuda")
-    status = ctx.status_word()
-
-    def run(iters, theta):
-        m, v = torch.zeros_like(theta), torch.zeros_like(theta)
-        return ctx.solve(scenes, ws_, Ns, S.make_cfg(iters, lr=lr), theta, m, v, solve_time_us=times,
-                         workspace=work, status=status)
-
-    warm = flat.clone()
-    run(max(args.warmup, 1), warm)  # autotune + graph instantiation
-    torch.cuda.synchronize()
-    theta = flat.clone()
-    t0 = time.perf_counter()
-    run(args.steps, theta)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    assert int(status.item()) == 0
-    tus = times.cpu().numpy()
     total = sum(Ns)
-    print(json.dumps({"workload": "batched: 64 problems N~U{64..2048} H~U{2..5} B~U{1..4} T=200",
-                      "particles": total, "iters": args.steps, "wall_s": wall,
-                      "particle_iters_per_s": total * args.steps / wall,
-                      "solve_time_us_p50": float(np.percentile(tus, 50)),
-                      "solve_time_us_p99": float(np.percentile(tus, 99))}), flush=True)
+    out = {"workload": "batched: 64 problems N~U{64..2048} H~U{2..5} B~U{1..4} T=200", "particles": total,
+           "iters": args.steps}
+    results = {}
+    for name, classes in (("lockstep", 0), ("classes2", 2), ("classes4", 4), ("classes8", 8)):
+        cfg = lambda iters: S.make_cfg(iters, lr=lr, classes=classes)
+        work = torch.empty(ctx.solve_workspace_bytes(scenes, Ns, cfg(args.steps)), dtype=torch.uint8,
+                           device="cuda")
+        times = torch.zeros(len(probs), device="cuda")
+        status = ctx.status_word()
+
+        def run(iters, theta):
+            m, v = torch.zeros_like(theta), torch.zeros_like(theta)
+            return ctx.solve(scenes, ws_, Ns, cfg(iters), theta, m, v, solve_time_us=times, workspace=work,
+                             status=status)
+
+        warm = flat.clone()
+        run(max(args.warmup, 1), warm)  # autotune + graph instantiation
+        torch.cuda.synchronize()
+        theta = flat.clone()
+        t0 = time.perf_counter()
+        cost = run(args.steps, theta)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        assert int(status.item()) == 0
+        tus = times.cpu().numpy()
+        results[name] = (theta, cost)
+        out[name] = {"wall_s": wall, "particle_iters_per_s": total * args.steps / wall,
+                     "solve_time_us_p50": float(np.percentile(tus, 50)),
+                     "solve_time_us_p99": float(np.percentile(tus, 99)),
+                     "solve_time_us_mean": float(tus.mean())}
+        del work
+    out["classes_equal_lockstep"] = all(torch.equal(results["lockstep"][0], r[0]) and
+                                        torch.equal(results["lockstep"][1], r[1]) for r in results.values())
+    print(json.dumps(out), flush=True)
     ctx.close()
 
 

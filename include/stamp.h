@@ -120,6 +120,12 @@ typedef struct stamp_solver_cfg {
                           one extra rollout per particle and iteration); 0: w_j = 1 */
     int32_t per_phase; /* 1: every simulator iteration takes the gradient of the per-phase split
                           of the cost (stamp_rollout_adj_phases); 0: the gradient of C */
+    int32_t classes;   /* stamp_solve over several problems: 0 or 1, one batch in which the
+                          problems advance in lockstep; C > 1, the problems are ordered by
+                          their predicted cost per iteration and solved in min(C, n_problems)
+                          classes of consecutive cost, cheapest class first, each class one
+                          batch of its own (same results, bit for bit), so that a cheap
+                          problem is done when its class is */
     const struct stamp_struct_kernel* kernel; /* NULL: the RBF kernel on theta; else the
                           structured kernel (push layout; K is taken from each scene's H,
                           the field itself is ignored) in every SVGD iteration */
@@ -365,8 +371,13 @@ int32_t stamp_adam_step(stamp_ctx* ctx, int64_t n, float* theta, const float* ph
  *   theta, adam_m, adam_v: sum_p 6*H_p*N_p floats, problem p's block [d_p][N_p];
  *   cost_out: sum_p N_p (final true cost); modes_out: sum_p H_p*N_p int32,
  *   problem p's block [H_p][N_p] = argmax side per push (Gamma, Eq. 5), or NULL;
- *   solve_time_us: n_problems floats (device time from the solve's first to its
- *   last kernel; the problems advance in lockstep, so the values coincide) or NULL.
+ *   solve_time_us: n_problems floats or NULL: device time from the solve's first
+ *   kernel to the last kernel of the problem's own batch (cfg->classes <= 1: the
+ *   problems advance in lockstep and the values coincide; cfg->classes > 1: the
+ *   end of the problem's class).
+ * cfg->classes > 1: the workspace holds each class's packed inputs and outputs
+ * beside the largest class's batch (stamp_solve_workspace_bytes with the same
+ * cfg); the classes run one after another on the context's stream.
  * adam_m/adam_v may be NULL only when use_adam = 0; m and v are not cleared.
  * Every stage of an iteration is one kernel over all problems (work lists of
  * (problem, tile)); the iteration is captured once into a HIP graph on the

@@ -63,7 +63,8 @@ class SolverCfg(C.Structure):
     _fields_ = [("iters", C.c_int32), ("t0", C.c_int32), ("lr", C.c_float), ("beta1", C.c_float),
                 ("beta2", C.c_float), ("adam_eps", C.c_float), ("use_adam", C.c_int32),
                 ("bandwidth", C.c_float), ("ckpt_every", C.c_int32), ("sgd_iters", C.c_int32),
-                ("dsvgd", C.c_int32), ("per_phase", C.c_int32), ("kernel", C.POINTER(StructKernel))]
+                ("dsvgd", C.c_int32), ("per_phase", C.c_int32), ("classes", C.c_int32),
+                ("kernel", C.POINTER(StructKernel))]
 
 
 class Surrogate(C.Structure):
@@ -168,11 +169,13 @@ def make_cost(w: dict) -> CostW:
 
 
 def make_cfg(iters, t0=0, lr=1e-3, beta1=0.9, beta2=0.999, adam_eps=1e-8, use_adam=True,
-             bandwidth=0.0, ckpt_every=0, sgd_iters=0, dsvgd=False, kernel=None, per_phase=False) -> SolverCfg:
+             bandwidth=0.0, ckpt_every=0, sgd_iters=0, dsvgd=False, kernel=None, per_phase=False,
+             classes=0) -> SolverCfg:
     """stamp_solver_cfg; kernel: a StructKernel (push layout) or None for the RBF kernel on theta;
-    per_phase: the simulator iterations take the gradient of the per-phase split of the cost."""
+    per_phase: the simulator iterations take the gradient of the per-phase split of the cost;
+    classes > 1: the problems of a solve run in that many cost classes, cheapest first."""
     cfg = SolverCfg(int(iters), int(t0), lr, beta1, beta2, adam_eps, int(bool(use_adam)), bandwidth,
-                    int(ckpt_every), int(sgd_iters), int(bool(dsvgd)), int(bool(per_phase)))
+                    int(ckpt_every), int(sgd_iters), int(bool(dsvgd)), int(bool(per_phase)), int(classes))
     if kernel is not None:
         cfg.kernel = C.pointer(kernel)
         cfg._kernel_ref = kernel  # keeps the pointed-to struct alive with the cfg

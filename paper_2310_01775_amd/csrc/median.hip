@@ -777,11 +777,25 @@ __device__ void med_select_body(const MedView& v, float* h_out) {
     const uint32_t lo = sel->lo, hi = sel->hi, s = sel->shift;
     const uint32_t r = sel->rank;
     if (mode == kModePass0) {
+        // sum the items' counts in a fixed order, sixteen 8-byte loads in
+        // flight per thread (this step waits on memory, often beside a
+        // bandwidth-bound rollout)
         const int items = v.rb * v.cc;
-        for (int k = 0; k < 2; ++k) {  // sum the items' counts in a fixed order
-            uint32_t c = 0;
-            for (int e = tid; e < items; e += 256) c += v.cnt[2 * e + k];
-            psum[tid] = c;
+        const uint2* cnt2 = reinterpret_cast<const uint2*>(v.cnt);
+        uint32_t cb = 0, ca = 0;
+        for (int e = tid; e < items; e += 256 * 16) {
+            uint2 q[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) q[u] = cnt2[min(e + 256 * u, items - 1)];
+#pragma unroll
+            for (int u = 0; u < 16; ++u)
+                if (e + 256 * u < items) {
+                    cb += q[u].x;
+                    ca += q[u].y;
+                }
+        }
+        for (int k = 0; k < 2; ++k) {
+            psum[tid] = k == 0 ? cb : ca;
             __syncthreads();
             for (int w = 128; w > 0; w >>= 1) {
                 if (tid < w) psum[tid] += psum[tid + w];

@@ -312,23 +312,22 @@ __global__ __launch_bounds__(kMeanThreads) void k_mean_batched(const ProblemDesc
     particle_mean_body(D.N, e.y, theta + D.theta_off, reinterpret_cast<float*>(base32(D, ws) + D.sv.ctr_off));
 }
 
-// entry = (problem, first row of a 256-row chunk, -, -)
+// entry = (problem, first row of a 256-row chunk, -, -); four workgroups per
+// entry, 64 rows each
 __global__ __launch_bounds__(256) void k_pack32_x_batched(const ProblemDesc* __restrict__ descs,
                                                           const int4* __restrict__ work, const float* theta, char* ws) {
-    const int4 e = work[blockIdx.x];
+    const int4 e = work[blockIdx.x >> 2];
     const ProblemDesc& D = descs[e.x];
     if (D.N < 2) return;
-    const View32 v = view32(D.sv, base32(D, ws));
-    for (int r0 = e.y; r0 < e.y + 256; r0 += 64) pack32_x_rows(D.N, D.d, D.sv.ks32, r0, theta + D.theta_off, v);
+    pack32_x_rows(D.N, D.d, D.sv.ks32, e.y + 64 * (blockIdx.x & 3), theta + D.theta_off, view32(D.sv, base32(D, ws)));
 }
 
 __global__ __launch_bounds__(256) void k_pack32_v_batched(const ProblemDesc* __restrict__ descs,
                                                           const int4* __restrict__ work, const float* theta, char* ws) {
-    const int4 e = work[blockIdx.x];
+    const int4 e = work[blockIdx.x >> 2];
     const ProblemDesc& D = descs[e.x];
     if (D.N < 2) return;
-    const View32 v = view32(D.sv, base32(D, ws));
-    for (int r0 = e.y; r0 < e.y + 256; r0 += 64) pack32_v_rows(D.N, D.d, D.sv.ot32, r0, theta + D.theta_off, v);
+    pack32_v_rows(D.N, D.d, D.sv.ot32, e.y + 64 * (blockIdx.x & 3), theta + D.theta_off, view32(D.sv, base32(D, ws)));
 }
 
 // entry = (problem, row block of blockDim.x rows, split, -)
@@ -430,9 +429,10 @@ hipError_t launch_operands32_batched(const BatchPlan& P, const ProblemDesc* desc
         if (P.n_ctr)
             hipLaunchKernelGGL(k_mean_batched, dim3(P.n_ctr), dim3(kMeanThreads), 0, st, descs, P.ctr_work, theta, ws);
         if (P.n_row16)
-            hipLaunchKernelGGL(k_pack32_x_batched, dim3(P.n_row16), dim3(256), 0, st, descs, P.row16_work, theta, ws);
+            hipLaunchKernelGGL(k_pack32_x_batched, dim3(4 * P.n_row16), dim3(256), 0, st, descs, P.row16_work, theta,
+                               ws);
     } else if (P.n_row16) {
-        hipLaunchKernelGGL(k_pack32_v_batched, dim3(P.n_row16), dim3(256), 0, st, descs, P.row16_work, theta, ws);
+        hipLaunchKernelGGL(k_pack32_v_batched, dim3(4 * P.n_row16), dim3(256), 0, st, descs, P.row16_work, theta, ws);
     }
     return hipGetLastError();
 }

@@ -35,11 +35,12 @@ struct stamp_ctx {
     int rollout_layout = STAMP_LAYOUT_AUTO;  // block per lane, or all blocks of a sub-rollout per lane
     StampTune pinned;                        // used when pinned.roll_block > 0
     int is_pinned = 0;
-    // The last instantiated graphs of each iteration kind (SVGD, surrogate
-    // phase, SGD refinement) and the solve they belong to: one iteration, and
-    // kGraphUnroll iterations in one graph (consecutive launches of a graph
-    // leave a gap of several microseconds on the queue; inside one graph the
-    // iterations follow each other directly).
+    // Instantiated graphs of an iteration kind (SVGD, surrogate phase, SGD
+    // refinement) for one solve: one iteration, and kGraphUnroll iterations in
+    // one graph (consecutive launches of a graph leave a gap of several
+    // microseconds on the queue; inside one graph the iterations follow each
+    // other directly).  Kept per kind and batch, so that the classes of a
+    // class-scheduled solve each keep theirs.
     struct IterGraphs {
         hipGraphExec_t one = nullptr, many = nullptr;
         std::string key_one, key_many;
@@ -49,7 +50,22 @@ struct stamp_ctx {
             one = many = nullptr;
         }
     };
-    IterGraphs g_svgd, g_sur, g_sgd;
+    std::map<std::string, IterGraphs> graphs;
+    static constexpr size_t kMaxGraphSlots = 48;
+    // the slot of `kind` for the batch `key`; the cache is emptied (after the
+    // library stream has drained) when it would outgrow kMaxGraphSlots
+    IterGraphs& graph_slot(const std::string& kind, const std::string& key) {
+        const std::string k = kind + "#" + key;
+        auto it = graphs.find(k);
+        if (it != graphs.end()) return it->second;
+        if (graphs.size() >= kMaxGraphSlots) destroy_graphs();
+        return graphs[k];
+    }
+    void destroy_graphs() {
+        if (stream) (void)hipStreamSynchronize(stream);
+        for (auto& g : graphs) g.second.destroy();
+        graphs.clear();
+    }
     void* scratch = nullptr;  // this device's copy of the no-alloc scratch array (device address)
 };
 
@@ -372,6 +388,98 @@ size_t plan_bytes(int n, const stamp_scene* scenes, const int32_t* N, int K, flo
     return P.total;
 }
 
+// ---- class-scheduled solve --------------------------------------------------
+// With cfg->classes = C > 1 the problems are ordered by a prediction of their
+// device time per iteration and cut into min(C, n) classes of consecutive
+// cost and about equal predicted work, each solved as a batch of its own, the
+// cheapest first, so a cheap problem is done when its class is instead of
+// when the most expensive one is.  The prediction adds the rollout's block steps (4 sides x B blocks x
+// (T + H) steps per particle) and the pairwise stages' pairs scaled by the
+// dimension; at N = 16384, B = 3, d = 30 one block step costs about 9.4 ps
+// and one ordered pair about 2.4 ps, hence the weight 0.26 of a pair at d = 30.
+struct ClassPlan {
+    std::vector<int> order;                       // problems by predicted cost, ascending
+    std::vector<int> first;                       // class c: order[first[c] .. first[c + 1])
+    std::vector<int64_t> th_off, co_off, mo_off;  // each problem's place in the packed arrays
+    size_t clk_off = 0, th_off_s = 0, m_off_s = 0, v_off_s = 0, cost_off_s = 0, modes_off_s = 0, plan_off = 0;
+    size_t plan_bytes = 0, total = 0;
+};
+
+bool class_plan(int n, const stamp_scene* scenes, const int32_t* N, const stamp_solver_cfg* cfg, ClassPlan& L) {
+    const int C = std::min(cfg->classes, n);
+    std::vector<double> cost(n);
+    L.th_off.assign(n, 0);
+    L.co_off.assign(n, 0);
+    L.mo_off.assign(n, 0);
+    int64_t th = 0, co = 0, mo = 0;
+    for (int p = 0; p < n; ++p) {
+        const stamp_scene& sc = scenes[p];
+        const double d = 6.0 * sc.H, np = N[p];
+        cost[p] = 4.0 * sc.B * (double)(sc.T + sc.H) * np + 0.26 * (d / 30.0) * np * np;
+        L.th_off[p] = th;
+        L.co_off[p] = co;
+        L.mo_off[p] = mo;
+        th += (int64_t)6 * sc.H * N[p];
+        co += N[p];
+        mo += (int64_t)sc.H * N[p];
+    }
+    L.order.resize(n);
+    for (int p = 0; p < n; ++p) L.order[p] = p;
+    std::stable_sort(L.order.begin(), L.order.end(), [&](int a, int b) { return cost[a] < cost[b]; });
+    // classes of equal predicted work: class c ends at the first problem whose
+    // running sum reaches (c + 1) / C of the total, and holds at least one
+    // problem (a class of many cheap problems costs one iteration's launch
+    // latency per iteration, as a class of one does)
+    double total = 0.0;
+    for (int p = 0; p < n; ++p) total += cost[p];
+    L.first.assign(1, 0);
+    double run = 0.0;
+    for (int q = 0; q < n; ++q) {
+        run += cost[L.order[q]];
+        const int c = (int)L.first.size() - 1;  // the open class
+        const int left = n - (q + 1);             // problems after this one
+        const int need = C - (c + 1);             // classes still to open after this one
+        if ((run >= total * (c + 1) / C && left >= need && need > 0) || left == need) L.first.push_back(q + 1);
+        if ((int)L.first.size() == C + 1) break;
+    }
+    while ((int)L.first.size() < C + 1) L.first.push_back(n);
+    int64_t fmax = 0, nmax = 0, hmax = 0;
+    for (int c = 0; c < C; ++c) {
+        int64_t f = 0, k = 0, h = 0;
+        std::vector<stamp_scene> sc;
+        std::vector<int32_t> nn;
+        for (int q = L.first[c]; q < L.first[c + 1]; ++q) {
+            const int p = L.order[q];
+            f += (int64_t)6 * scenes[p].H * N[p];
+            k += N[p];
+            h += (int64_t)scenes[p].H * N[p];
+            sc.push_back(scenes[p]);
+            nn.push_back(N[p]);
+        }
+        fmax = std::max(fmax, f);
+        nmax = std::max(nmax, k);
+        hmax = std::max(hmax, h);
+        const size_t b = plan_bytes((int)sc.size(), sc.data(), nn.data(), cfg->ckpt_every, cfg->bandwidth);
+        if (!b) return false;
+        L.plan_bytes = std::max(L.plan_bytes, b);
+    }
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = (off + bytes + 255) & ~size_t(255);
+        return o;
+    };
+    L.clk_off = take((size_t)2 * n * sizeof(uint64_t));
+    L.th_off_s = take((size_t)fmax * 4);
+    L.m_off_s = take((size_t)fmax * 4);
+    L.v_off_s = take((size_t)fmax * 4);
+    L.cost_off_s = take((size_t)nmax * 4);
+    L.modes_off_s = take((size_t)hmax * 4);
+    L.plan_off = take(L.plan_bytes);
+    L.total = off;
+    return true;
+}
+
 // True when two plans place every workspace region at the same offset.
 bool same_layout(const SolvePlan& a, const SolvePlan& b) {
     bool ok = a.total == b.total && a.clk_off == b.clk_off && a.desc_off == b.desc_off && a.roll_off == b.roll_off &&
@@ -443,9 +551,7 @@ int32_t stamp_create(stamp_ctx** ctx, int32_t device) {
 void stamp_destroy(stamp_ctx* ctx) {
     if (!ctx) return;
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
-    ctx->g_svgd.destroy();
-    ctx->g_sur.destroy();
-    ctx->g_sgd.destroy();
+    ctx->destroy_graphs();
     if (ctx->ev_in) (void)hipEventDestroy(ctx->ev_in);
     if (ctx->ev_out) (void)hipEventDestroy(ctx->ev_out);
     if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
@@ -508,6 +614,10 @@ size_t stamp_solve_workspace_bytes(int32_t n_problems, const stamp_scene* scenes
     if (n_problems < 1 || !scenes || !N || !cfg || cfg->ckpt_every < 0) return 0;
     for (int p = 0; p < n_problems; ++p)
         if (!scene_ok(&scenes[p]) || N[p] < 1 || N[p] > kMaxSvgdN) return 0;
+    if (cfg->classes > 1 && n_problems > 1) {
+        ClassPlan L;
+        return class_plan(n_problems, scenes, N, cfg, L) ? L.total : 0;
+    }
     return plan_bytes(n_problems, scenes, N, cfg->ckpt_every, cfg->bandwidth);
 }
 
@@ -1154,6 +1264,14 @@ static int32_t solve_impl(stamp_ctx* ctx, int32_t n_problems, const stamp_scene*
              (void*)adam_m, (void*)adam_v, (void*)status, cfg->t0, cfg->use_adam, cfg->lr, cfg->beta1, cfg->beta2,
              cfg->adam_eps, tune.roll_block, rgrid, tune.phi_rows, cfg->dsvgd);
     std::string full_key = tkey + gkey;
+    {  // every problem's constants (scene, cost weights, split): the single-problem
+       // rollout launches take them by value, so the captured graph holds them
+        uint64_t hsh = 1469598103934665603ull;  // FNV-1a over the bytes
+        const unsigned char* b = reinterpret_cast<const unsigned char*>(consts.data());
+        for (size_t i = 0; i < consts.size() * sizeof(SimConst); ++i) hsh = (hsh ^ b[i]) * 1099511628211ull;
+        snprintf(gkey, sizeof gkey, "c%016llx|", (unsigned long long)hsh);
+        full_key += gkey;
+    }
     if (cfg->kernel) {  // the kernel's parameters are arguments of the captured launches
         const stamp_struct_kernel& k = *cfg->kernel;
         snprintf(gkey, sizeof gkey, "struct|%.9g|%.9g|%.9g|%.9g|%.9g|%.9g|", k.alpha_g, k.alpha_z, k.alpha_p, k.h_g,
@@ -1228,7 +1346,7 @@ static int32_t solve_impl(stamp_ctx* ctx, int32_t n_problems, const stamp_scene*
         std::vector<float> h_err(n_problems);
         while (run < s_iters) {
             const int chunk = sur->check_every > 0 ? std::min(sur->check_every, s_iters - run) : s_iters - run;
-            int32_t r = run_iterations(ctx->g_sur, sk, chunk, sur_iteration);
+            int32_t r = run_iterations(ctx->graph_slot("sur", sk), sk, chunk, sur_iteration);
             if (r) return r;
             run += chunk;
             STAMP_TRY(roll_fwd(theta, c_true, nullptr, status), "check rollout");
@@ -1253,11 +1371,11 @@ static int32_t solve_impl(stamp_ctx* ctx, int32_t n_problems, const stamp_scene*
         rep->log_err = last_err;
     }
     if (cfg->iters - run > 0) {
-        int32_t r = run_iterations(ctx->g_svgd, full_key, cfg->iters - run, iteration);
+        int32_t r = run_iterations(ctx->graph_slot("svgd", full_key), full_key, cfg->iters - run, iteration);
         if (r) return r;
     }
     if (cfg->sgd_iters > 0) {  // refinement: the step counter runs on
-        int32_t r = run_iterations(ctx->g_sgd, full_key, cfg->sgd_iters, sgd_iteration);
+        int32_t r = run_iterations(ctx->graph_slot("sgd", full_key), full_key, cfg->sgd_iters, sgd_iteration);
         if (r) return r;
     }
     // final true cost and discrete plan of every particle
@@ -1282,12 +1400,95 @@ static int32_t solve_impl(stamp_ctx* ctx, int32_t n_problems, const stamp_scene*
     return STAMP_OK;
 }
 
+static int32_t solve_classes(stamp_ctx* ctx, int32_t n, const stamp_scene* scenes, const stamp_cost_w* w,
+                             const int32_t* N, const stamp_solver_cfg* cfg, float* theta, float* adam_m,
+                             float* adam_v, float* cost_out, int32_t* modes_out, float* solve_time_us,
+                             void* workspace, size_t ws_bytes, uint32_t* status, void* stream) {
+    if (!scenes || !w || !N) return fail(ctx, STAMP_EINVAL, "null problem arrays");
+    if (!theta || !cost_out) return fail(ctx, STAMP_EINVAL, "null theta or cost_out");
+    for (int p = 0; p < n; ++p)
+        if (!scene_ok(&scenes[p]) || N[p] < 1 || N[p] > kMaxSvgdN)
+            return fail(ctx, STAMP_EINVAL, "problem %d: bad scene or N=%d", p, N[p]);
+    ClassPlan L;
+    if (!class_plan(n, scenes, N, cfg, L)) return fail(ctx, STAMP_EINVAL, "bad solver cfg");
+    if (!workspace || ws_bytes < L.total)
+        return fail(ctx, STAMP_ENOSPACE, "class-scheduled solve workspace %zu < %zu", ws_bytes, L.total);
+    hipStream_t caller = (hipStream_t)stream;
+    char* ws = (char*)workspace;
+    uint64_t* d_clk = (uint64_t*)(ws + L.clk_off);
+    float* s_th = (float*)(ws + L.th_off_s);
+    float* s_m = (float*)(ws + L.m_off_s);
+    float* s_v = (float*)(ws + L.v_off_s);
+    float* s_cost = (float*)(ws + L.cost_off_s);
+    int32_t* s_modes = (int32_t*)(ws + L.modes_off_s);
+    stamp_solver_cfg one = *cfg;
+    one.classes = 0;
+    hipError_t e;
+#define STAMP_TRY(x, what)                                          \
+    do {                                                            \
+        if ((e = (x)) != hipSuccess) return hip_fail(ctx, e, what); \
+    } while (0)
+    // a problem's [off, off + count) elements between the packed array and the class's
+    auto move = [&](void* dst, const void* src, size_t bytes) -> hipError_t {
+        return bytes ? hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, caller) : hipSuccess;
+    };
+    if (solve_time_us)
+        for (int p = 0; p < n; ++p) STAMP_TRY(launch_clock(d_clk + 2 * p, caller), "clock");
+    for (size_t c = 0; c + 1 < L.first.size(); ++c) {
+        std::vector<stamp_scene> sc;
+        std::vector<stamp_cost_w> wc;
+        std::vector<int32_t> nc;
+        int64_t f = 0, k = 0, h = 0;
+        for (int q = L.first[c]; q < L.first[c + 1]; ++q) {  // the class's inputs, packed in its order
+            const int p = L.order[q];
+            sc.push_back(scenes[p]);
+            wc.push_back(w[p]);
+            nc.push_back(N[p]);
+            const size_t fb = (size_t)6 * scenes[p].H * N[p] * 4;
+            STAMP_TRY(move(s_th + f, theta + L.th_off[p], fb), "pack theta");
+            if (adam_m) STAMP_TRY(move(s_m + f, adam_m + L.th_off[p], fb), "pack m");
+            if (adam_v) STAMP_TRY(move(s_v + f, adam_v + L.th_off[p], fb), "pack v");
+            f += (int64_t)6 * scenes[p].H * N[p];
+        }
+        const int32_t r = solve_impl(ctx, (int32_t)sc.size(), sc.data(), wc.data(), nc.data(), &one, nullptr, s_th,
+                                     adam_m ? s_m : nullptr, adam_v ? s_v : nullptr, s_cost,
+                                     modes_out ? s_modes : nullptr, nullptr, nullptr, ws + L.plan_off, L.plan_bytes,
+                                     status, stream);
+        if (r) return r;
+        f = 0;
+        for (int q = L.first[c]; q < L.first[c + 1]; ++q) {  // and back to their places
+            const int p = L.order[q];
+            const size_t fb = (size_t)6 * scenes[p].H * N[p] * 4;
+            STAMP_TRY(move(theta + L.th_off[p], s_th + f, fb), "unpack theta");
+            if (adam_m) STAMP_TRY(move(adam_m + L.th_off[p], s_m + f, fb), "unpack m");
+            if (adam_v) STAMP_TRY(move(adam_v + L.th_off[p], s_v + f, fb), "unpack v");
+            STAMP_TRY(move(cost_out + L.co_off[p], s_cost + k, (size_t)N[p] * 4), "unpack cost");
+            if (modes_out)
+                STAMP_TRY(move(modes_out + L.mo_off[p], s_modes + h, (size_t)scenes[p].H * N[p] * 4), "unpack modes");
+            if (solve_time_us) STAMP_TRY(launch_clock(d_clk + 2 * p + 1, caller), "clock");
+            f += (int64_t)6 * scenes[p].H * N[p];
+            k += N[p];
+            h += (int64_t)scenes[p].H * N[p];
+        }
+    }
+    if (solve_time_us)
+        STAMP_TRY(launch_clock_to_us(d_clk, n, 1000.0f / (float)ctx->clock_khz, solve_time_us, caller), "clock");
+#undef STAMP_TRY
+    return STAMP_OK;
+}
+
 extern "C" {
 
 int32_t stamp_solve(stamp_ctx* ctx, int32_t n_problems, const stamp_scene* scenes, const stamp_cost_w* w,
                     const int32_t* N, const stamp_solver_cfg* cfg, float* theta, float* adam_m, float* adam_v,
                     float* cost_out, int32_t* modes_out, float* solve_time_us, void* workspace, size_t ws_bytes,
                     uint32_t* status, void* stream) {
+    if (!ctx) return STAMP_EINVAL;
+    if (!cfg) return fail(ctx, STAMP_EINVAL, "null cfg");
+    if (cfg->classes < 0) return fail(ctx, STAMP_EINVAL, "cfg->classes=%d < 0", cfg->classes);
+    if (cfg->classes > 1 && n_problems > 1)
+        return solve_classes(ctx, n_problems, scenes, w, N, cfg, theta, adam_m, adam_v, cost_out, modes_out,
+                             solve_time_us, workspace, ws_bytes, status, stream);
     return solve_impl(ctx, n_problems, scenes, w, N, cfg, nullptr, theta, adam_m, adam_v, cost_out, modes_out,
                       solve_time_us, nullptr, workspace, ws_bytes, status, stream);
 }
@@ -1299,6 +1500,7 @@ int32_t stamp_solve_surrogate(stamp_ctx* ctx, int32_t n_problems, const stamp_sc
                               void* stream) {
     if (!ctx) return STAMP_EINVAL;
     if (!sur || !cfg || !scenes || n_problems < 1) return fail(ctx, STAMP_EINVAL, "null surrogate, cfg or scenes");
+    if (cfg->classes > 1) return fail(ctx, STAMP_EINVAL, "class scheduling applies to stamp_solve");
     if (sur->iters < 0 || sur->iters > cfg->iters)
         return fail(ctx, STAMP_EINVAL, "surrogate iters=%d not in [0, iters=%d]", sur->iters, cfg->iters);
     if (sur->n_in < 1 || sur->n_in > kMlpIn) return fail(ctx, STAMP_EINVAL, "n_in=%d not in [1,%d]", sur->n_in, kMlpIn);

@@ -208,3 +208,114 @@ def test_full_batch_sampled_against_oracle(ctx):
         worst = (np.abs(g - ref) / np.abs(ref).max(axis=0, keepdims=True)).max()
         print("problem", k, "normwise", norm, "worst coordinate", worst, flush=True)
         assert norm < 2e-6 and worst < 1e-4
+
+
+def _solve_batch(ctx, S, probs, sizes, cfg):
+    flat = _pack(S, probs)
+    m, v = torch.zeros_like(flat), torch.zeros_like(flat)
+    Ns = [th.shape[0] for _, _, th in probs]
+    times = torch.zeros(len(probs), device="cuda")
+    modes = torch.empty(sum(N * s[1] for N, s in zip(Ns, sizes)), dtype=torch.int32, device="cuda")
+    st = ctx.status_word()
+    cost = ctx.solve([S.make_scene(s) for s, _, _ in probs], [S.make_cost(w) for _, w, _ in probs], Ns, cfg,
+                     flat, m, v, modes_out=modes, solve_time_us=times, status=st)
+    torch.cuda.synchronize()
+    assert int(st.item()) == 0
+    return flat, m, v, cost, modes, times.cpu().numpy()
+
+
+def _classes(sizes, T, C):
+    """The class of each problem under the library's rule: problems by predicted
+    cost per iteration (4 B (T + H) N + 0.26 (d / 30) N^2), cut where the
+    running sum reaches c / C of the total, one problem per class at least."""
+    cost = [4.0 * B * (T + H) * N + 0.26 * (H / 5.0) * N * N for N, H, B in sizes]
+    n = len(sizes)
+    order = sorted(range(n), key=lambda p: (cost[p], p))
+    C = min(C, n)
+    total, run, first = sum(cost), 0.0, [0]
+    for q in range(n):
+        run += cost[order[q]]
+        c, left = len(first) - 1, n - (q + 1)
+        need = C - (c + 1)
+        if (run >= total * (c + 1) / C and left >= need and need > 0) or left == need:
+            first.append(q + 1)
+        if len(first) == C + 1:
+            break
+    first += [n] * (C + 1 - len(first))
+    cls = np.empty(n, dtype=int)
+    for c in range(C):
+        cls[order[first[c]:first[c + 1]]] = c
+    return cls
+
+
+@pytest.mark.parametrize("classes", [2, 3, 7, 50])
+def test_class_schedule_equals_the_lockstep_batch(ctx, classes):
+    """cfg.classes > 1: the problems run in cost classes, cheapest first, each
+    class a batch of its own.  Every output equals the one-batch solve bit for
+    bit (the batched kernels reproduce each problem's own iteration), and a
+    problem's time is its class's end: never before a cheaper class's."""
+    import paper_2310_01775_amd as S
+    sizes = [(64, 2, 1), (200, 5, 4), (1, 3, 2), (97, 3, 3), (130, 4, 2), (33, 2, 4), (1600, 3, 1)]
+    probs = _problems(sizes, 40, 0.005, 0)
+    print("classes", classes, flush=True)
+    a = _solve_batch(ctx, S, probs, sizes, S.make_cfg(6, lr=1e-3))
+    b = _solve_batch(ctx, S, probs, sizes, S.make_cfg(6, lr=1e-3, classes=classes))
+    for x, y in zip(a[:5], b[:5]):
+        assert torch.equal(x, y)
+    t = b[5]
+    print("lockstep us", a[5], "classes us", t, flush=True)
+    assert (t > 0).all()
+    cls = _classes(sizes, 40, classes)
+    for p in range(len(sizes)):
+        for q in range(len(sizes)):
+            if cls[p] < cls[q]:
+                assert t[p] <= t[q], (p, q)
+            if cls[p] == cls[q]:
+                assert abs(t[p] - t[q]) < 0.05 * t[q] + 50.0, (p, q)
+
+
+def test_class_schedule_workspace_and_errors(ctx):
+    import paper_2310_01775_amd as S
+    sizes = [(64, 2, 1), (200, 5, 4), (97, 3, 3)]
+    probs = _problems(sizes, 40, 0.005, 3)
+    scenes = [S.make_scene(s) for s, _, _ in probs]
+    ws_ = [S.make_cost(w) for _, w, _ in probs]
+    Ns = [th.shape[0] for _, _, th in probs]
+    cfg = S.make_cfg(2, classes=3)
+    need = ctx.solve_workspace_bytes(scenes, Ns, cfg)
+    assert need > 0
+    flat = _pack(S, probs)
+    m, v = torch.zeros_like(flat), torch.zeros_like(flat)
+    small = torch.empty(need - 1, dtype=torch.uint8, device="cuda")
+    with pytest.raises(S.StampError, match="workspace"):
+        ctx.solve(scenes, ws_, Ns, cfg, flat, m, v, workspace=small)
+    with pytest.raises(S.StampError, match="classes"):
+        ctx.solve(scenes, ws_, Ns, S.make_cfg(2, classes=-1), flat, m, v)
+
+
+def test_single_problem_graph_follows_the_cost_weights(ctx):
+    """A single-problem solve captures its rollout launches with the problem's
+    constants (scene, cost weights) as arguments: a second solve on the same
+    buffers with other weights must not replay the first one's graph."""
+    import paper_2310_01775_amd as S
+    (scene, w, th), = _problems([(300, 3, 2)], 40, 0.005, 4)
+    w2 = dict(w)
+    w2["target"] = 3.0 * w["target"]
+    sc = S.make_scene(scene)
+    N = th.shape[0]
+    cfg = S.make_cfg(4, lr=1e-3)
+    work = torch.empty(ctx.solve_workspace_bytes([sc], [N], cfg), dtype=torch.uint8, device="cuda")
+    theta = S.soa(th)
+    m, v = torch.zeros_like(theta), torch.zeros_like(theta)
+    out = []
+    for ww in (w, w2):
+        theta.copy_(S.soa(th))
+        m.zero_()
+        v.zero_()
+        cost = ctx.solve([sc], [S.make_cost(ww)], [N], cfg, theta, m, v, workspace=work)
+        torch.cuda.synchronize()
+        out.append((theta.clone(), cost.clone()))
+    ref_theta, ref_cost = _per_problem_loop(ctx, S, scene, w2, th, 4, 1e-3)
+    torch.cuda.synchronize()
+    assert torch.equal(out[1][0], ref_theta) and torch.equal(out[1][1], ref_cost)
+    assert not torch.equal(out[0][1], out[1][1])
