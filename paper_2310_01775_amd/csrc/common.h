@@ -175,6 +175,9 @@ struct BatchPlan {
     int dist_start[kMedLists];            // sorted by item shape: list c = entries
     int dist_n[kMedLists];                //   [dist_start[c], dist_start[c] + dist_n[c])
     const int4* cand_work;  int n_cand;   // (p, segment, part, -) of the median's candidate passes
+                                          //   (problems above 2^20 pairs)
+    const int4* fin_work;   int n_fin;    // (p, -, -, -): problems of 2^20 pairs at most, whose select
+                                          //   ends in one workgroup after pass 0
     const int4* phi_work[kPhi32Classes];  // (p, 256-row block, split, -) per FP32 matrix-core class
     int n_phi[kPhi32Classes];
     // BF16 matrix-core form: (problem, coordinate), (problem, 256-row chunk),

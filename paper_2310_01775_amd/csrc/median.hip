@@ -1099,6 +1099,15 @@ __global__ __launch_bounds__(256) void k_med_select_batched(const ProblemDesc* _
     med_select_body(med_of(descs[blockIdx.x], ws), nullptr);
 }
 
+// entry = (problem, -, -, -) of a problem of 2^20 pairs at most: the select
+// ends in one workgroup after pass 0, as in the single-problem path
+__global__ __launch_bounds__(kFinishThreads) void k_med_finish_batched(const ProblemDesc* __restrict__ descs,
+                                                                       const int4* __restrict__ work,
+                                                                       const float* theta, char* ws) {
+    const ProblemDesc& D = descs[work[blockIdx.x].x];
+    med_finish_body(med_of(D, ws), theta + D.theta_off, nullptr);
+}
+
 template <int ROWS>
 void launch_items_rows(const OneMed& a, const float* theta, hipStream_t st) {
     const dim3 grid(a.L.med_cc, a.L.med_rb);
@@ -1218,12 +1227,19 @@ hipError_t launch_median_batched(const BatchPlan& P, const ProblemDesc* descs, c
     if (exact && P.n_dist) {
         auto items = [&]() { launch_items_batched(P, descs, theta, ws, st); };
         items();
-        hipLaunchKernelGGL(k_med_select_batched, dim3(np), dim3(256), 0, st, descs, ws);
-        for (int pass = 0; pass < 3; ++pass) {
-            if (P.n_cand)
-                hipLaunchKernelGGL(k_med_cand_batched, dim3(P.n_cand), dim3(256), 0, st, descs, P.cand_work, ws);
-            items();
+        // problems of 2^20 pairs at most end in one workgroup each; the larger
+        // ones take the select and the candidate passes (which skip the
+        // problems already done)
+        if (P.n_fin)
+            hipLaunchKernelGGL(k_med_finish_batched, dim3(P.n_fin), dim3(kFinishThreads), 0, st, descs, P.fin_work,
+                               theta, ws);
+        if (P.n_cand) {
             hipLaunchKernelGGL(k_med_select_batched, dim3(np), dim3(256), 0, st, descs, ws);
+            for (int pass = 0; pass < 3; ++pass) {
+                hipLaunchKernelGGL(k_med_cand_batched, dim3(P.n_cand), dim3(256), 0, st, descs, P.cand_work, ws);
+                items();
+                hipLaunchKernelGGL(k_med_select_batched, dim3(np), dim3(256), 0, st, descs, ws);
+            }
         }
     }
     return hipGetLastError();

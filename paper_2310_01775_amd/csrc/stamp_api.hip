@@ -251,12 +251,13 @@ constexpr int kMaxSvgdN = 65536;
 struct SolvePlan {
     std::vector<stamp::ProblemDesc> descs;
     std::vector<int2> roll_tiles, adj_tiles;  // forward and adjoint rollout tiles (their layouts may differ)
-    std::vector<int4> dist_work, cand_work, red_work;
+    std::vector<int4> dist_work, cand_work, fin_work, red_work;
     std::vector<int4> phi_work[kPhi32Classes];
     std::vector<int4> ctr_work, row16_work, phi16_work[2];  // BF16 form
     int phi_rows = 256;
     int dist_start[kMedLists] = {}, dist_n[kMedLists] = {};  // dist_work sorted by item shape
-    size_t clk_off = 0, desc_off = 0, roll_off = 0, adj_tiles_off = 0, dist_off = 0, cand_off = 0, red_off = 0;
+    size_t clk_off = 0, desc_off = 0, roll_off = 0, adj_tiles_off = 0, dist_off = 0, cand_off = 0, fin_off = 0,
+           red_off = 0;
     size_t ctr16_off = 0, row16_off = 0, phi16_off[2] = {};
     size_t phi_off[kPhi32Classes] = {};
     size_t ctr_off = 0, err_off = 0, tape_off = 0, seg_off = 0, grad_off = 0, phi_vec_off = 0, cost_off = 0,
@@ -316,8 +317,12 @@ void build_plan(int n, const stamp_scene* scenes, const int32_t* N, int K, float
             const int c = gram ? med_gram_list(D.sv.ks32, D.sv.med_rows) : med_class(med_dp(D.d), D.sv.med_rows);
             for (int rb = 0; rb < D.sv.med_rb; ++rb)
                 for (int cc = 0; cc < D.sv.med_cc; ++cc) dist_lists[c].push_back(make_int4(p, rb, cc, 0));
-            for (int g = 0; g < kCandSegs; ++g)
-                for (int q = 0; q < kCandParts; ++q) P.cand_work.push_back(make_int4(p, g, q, 0));
+            if (gram) {
+                for (int g = 0; g < kCandSegs; ++g)
+                    for (int q = 0; q < kCandParts; ++q) P.cand_work.push_back(make_int4(p, g, q, 0));
+            } else {
+                P.fin_work.push_back(make_int4(p, 0, 0, 0));
+            }
         }
         if (D.N >= 2) {
             const int c = phi32_class(D.d);
@@ -363,6 +368,7 @@ void build_plan(int n, const stamp_scene* scenes, const int32_t* N, int K, float
     P.adj_tiles_off = take(P.adj_tiles.size() * sizeof(int2));
     P.dist_off = take(P.dist_work.size() * sizeof(int4));
     P.cand_off = take(P.cand_work.size() * sizeof(int4));
+    P.fin_off = take(P.fin_work.size() * sizeof(int4));
     P.red_off = take(P.red_work.size() * sizeof(int4));
     for (int c = 0; c < kPhi32Classes; ++c) P.phi_off[c] = take(phi_cap[c] * sizeof(int4));
     P.ctr16_off = take(P.ctr_work.size() * sizeof(int4));
@@ -484,7 +490,8 @@ bool class_plan(int n, const stamp_scene* scenes, const int32_t* N, const stamp_
 bool same_layout(const SolvePlan& a, const SolvePlan& b) {
     bool ok = a.total == b.total && a.clk_off == b.clk_off && a.desc_off == b.desc_off && a.roll_off == b.roll_off &&
               a.adj_tiles_off == b.adj_tiles_off &&
-              a.dist_off == b.dist_off && a.cand_off == b.cand_off && a.red_off == b.red_off &&
+              a.dist_off == b.dist_off && a.cand_off == b.cand_off && a.fin_off == b.fin_off &&
+              a.red_off == b.red_off &&
               a.ctr_off == b.ctr_off && a.err_off == b.err_off && a.tape_off == b.tape_off && a.seg_off == b.seg_off &&
               a.grad_off == b.grad_off && a.phi_vec_off == b.phi_vec_off && a.cost_off == b.cost_off &&
               a.cdisc_off == b.cdisc_off && a.wts_off == b.wts_off && a.svgd_off == b.svgd_off;
@@ -987,6 +994,7 @@ static int32_t solve_impl(stamp_ctx* ctx, int32_t n_problems, const stamp_scene*
             return r;
         if ((r = upload(P.dist_off, P.dist_work.data(), P.dist_work.size() * sizeof(int4))) != hipSuccess) return r;
         if ((r = upload(P.cand_off, P.cand_work.data(), P.cand_work.size() * sizeof(int4))) != hipSuccess) return r;
+        if ((r = upload(P.fin_off, P.fin_work.data(), P.fin_work.size() * sizeof(int4))) != hipSuccess) return r;
         if ((r = upload(P.red_off, P.red_work.data(), P.red_work.size() * sizeof(int4))) != hipSuccess) return r;
         for (int c = 0; c < kPhi32Classes; ++c)
             if ((r = upload(P.phi_off[c], P.phi_work[c].data(), P.phi_work[c].size() * sizeof(int4))) != hipSuccess)
@@ -1011,6 +1019,8 @@ static int32_t solve_impl(stamp_ctx* ctx, int32_t n_problems, const stamp_scene*
             B.dist_n[c] = P.dist_n[c];
         }
         B.cand_work = (const int4*)(ws + P.cand_off);
+        B.fin_work = (const int4*)(ws + P.fin_off);
+        B.n_fin = (int)P.fin_work.size();
         B.n_cand = (int)P.cand_work.size();
         for (int c = 0; c < kPhi32Classes; ++c) {
             B.phi_work[c] = (const int4*)(ws + P.phi_off[c]);
