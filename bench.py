@@ -66,13 +66,19 @@ PROFILE = os.path.join(ROOT, "profiles", "stages_n16384_counters.md")
 
 def kernel_source_hash():
     """SHA-256 (first 16 hex digits) of every kernel source, *.hip then *.h in
-    name order: the counters in PROFILE hold only while it matches."""
+    name order, with comments and blank lines left out (they change no
+    kernel): the counters in PROFILE hold only while it matches."""
     import glob
     import hashlib
+    import re
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2310_01775_amd", "csrc")
     for f in sorted(glob.glob(os.path.join(csrc, "*.hip"))) + sorted(glob.glob(os.path.join(csrc, "*.h"))):
-        h.update(open(f, "rb").read())
+        text = re.sub(r"/\*.*?\*/", "", open(f).read(), flags=re.S)
+        for line in text.splitlines():
+            code = line.split("//", 1)[0].rstrip()
+            if code:
+                h.update(code.encode() + b"\n")
     return h.hexdigest()[:16]
 
 
@@ -305,6 +311,13 @@ def stage_timings(ctx, sc, cw, theta0, params, wbf16, n_in, enc):
     ms["mlp_infer"] = _time_launches(lambda: ctx.mlp_forward(params, wbf16, th, n_in, d, x_layout=1, enc=enc,
                                                              want_y=False, grad=grad, grad_scale=-1.0, w=cw))
     ms["step_bf16"] = _time_launches(lambda: ctx.svgd_step_bf16(th, grad, phi=phi, workspace=sws))
+    # the BF16 step at a given bandwidth skips the sampled median: its operands,
+    # the matrix-core contraction k_phi16 and the reduce
+    h = torch.zeros(1, dtype=torch.float32, device="cuda")
+    ctx.svgd_step_bf16(th, grad, phi=phi, h_out=h, workspace=sws)
+    torch.cuda.synchronize()
+    hb = float(h.item())
+    ms["direction_bf16"] = _time_launches(lambda: ctx.svgd_step_bf16(th, grad, bandwidth=hb, phi=phi, workspace=sws))
     return ms
 
 
@@ -414,7 +427,8 @@ def bench_headline(args):
     n_sim, n_net, n_chk = iters - s_iters, s_iters, s_iters // 80
     share = {"rollout_adj": n_sim * ms["rollout_adj"], "rollout_fwd": (n_sim + n_chk + 1) * ms["rollout_fwd"],
              "direction_fp32": n_sim * ms["direction_fp32"], "mlp_infer": (n_net + n_chk) * ms["mlp_infer"],
-             "step_bf16": n_net * ms["step_bf16"]}
+             "direction_bf16": n_net * ms["direction_bf16"],
+             "bandwidth_bf16": n_net * max(ms["step_bf16"] - ms["direction_bf16"], 0.0)}
     dom = max(share, key=share.get)
     by_f, by_a = rollout_bytes(N, d, B, T, H)
     if dom in ("rollout_adj", "rollout_fwd"):
@@ -430,16 +444,17 @@ def bench_headline(args):
         fl = mlp_flops(N, n_in)
         achieved = fl / (ms[dom] * 1e-3) / 1e12
         roof = {"bound": "mfma", "achieved": achieved, "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / MFMA_BF16_PEAK_TFLOPS, "traffic": None, "kernel": "k_mlp_infer",
+                "frac": achieved / MFMA_BF16_PEAK_TFLOPS, "traffic": measured_traffic("mlp_infer"), "kernel": "k_mlp_infer",
                 "kernel_ms": ms[dom]}
-    else:
+    else:  # a direction stage (the BF16 bandwidth stage, several small kernels, never leads)
         fl = phi_flops(N, d)
         peak = MFMA_FP32_PEAK_TFLOPS if dom == "direction_fp32" else MFMA_BF16_PEAK_TFLOPS
         achieved = fl / (ms[dom] * 1e-3) / 1e12
         roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
                 "traffic": measured_traffic(dom), "kernel_ms": ms[dom], "flops_per_launch": fl,
                 "kernel": ("k_phi32<8,2> (FP32 matrix cores; the stage also holds k_pack32_v and k_reduce32)"
-                           if dom == "direction_fp32" else dom)}
+                           if dom == "direction_fp32" else
+                           "k_phi16<32,32> (BF16 matrix cores; the stage also holds k_pack16_v and k_reduce16)")}
 
     out = {
         "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": args.steps,

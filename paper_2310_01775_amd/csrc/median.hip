@@ -301,7 +301,7 @@ __device__ uint32_t wg_select_array(const uint32_t* __restrict__ a, uint32_t n, 
     return lo;
 }
 
-// The sample's order statistics (one workgroup of 256, exact selects over
+// The sample's order statistics (one workgroup of kSelThreads = 1024, exact selects over
 // the 8192 sample values; +inf padding ranks last).  exact = 0: the sample
 // median is the result; exact = 1: the bracket of the full select (or the
 // result, when the sample holds every pair).

@@ -11,7 +11,7 @@
 // so every B operand is one contiguous 16-byte load.  Layer 3 (one output)
 // and the GELUs are FP32 VALU work.
 //
-// Inference (k_mlp_infer): a workgroup of four waves takes 64 samples and the
+// Inference (k_mlp_infer): a workgroup of eight waves takes 64 samples and the
 // waves split the neurons of every layer; it runs forward, the output dot, and
 // the input gradient
 //   dy/dx = ((w3 * gelu'(z2)) W2 * gelu'(z1)) W1 * inv_sigma
