@@ -489,6 +489,21 @@ int32_t stamp_mlp_train_step(stamp_ctx* ctx, int32_t M, int32_t n_in, const floa
                              float* adam_v, int32_t t, float lr, float beta1, float beta2, float eps, float* loss,
                              uint32_t* status, void* workspace, size_t ws_bytes, void* stream);
 
+/* n_steps consecutive Adam steps of stamp_mlp_train_step in one call, the
+ * kernels launched back to back by the library: step s (0-based) is Adam step
+ * t0 + s + 1 on the minibatch rows idx[s * M .. s * M + M) (idx: n_steps * M
+ * device int32, not NULL) with learning rate lr[s] (lr: n_steps host floats);
+ * loss (n_steps device floats, may be NULL) receives each step's loss before
+ * its update.  The result equals n_steps calls of stamp_mlp_train_step bit for
+ * bit.  Same workspace (stamp_mlp_train_workspace_bytes(M)).
+ * Errors: those of stamp_mlp_train_step; STAMP_EINVAL for n_steps < 1, a null
+ * idx or lr, t0 < 0 or a non-finite lr[s]. */
+int32_t stamp_mlp_train_steps(stamp_ctx* ctx, int32_t n_steps, int32_t M, int32_t n_in, const float* x,
+                              const float* cost, const int32_t* idx, int32_t n_rows, float* params, void* wbf16,
+                              float* adam_m, float* adam_v, int32_t t0, const float* lr, float beta1, float beta2,
+                              float eps, float* loss, uint32_t* status, void* workspace, size_t ws_bytes,
+                              void* stream);
+
 /* Surrogate phase of stamp_solve_surrogate. */
 typedef struct stamp_surrogate {
     int32_t iters;        /* leading iterations that take the network's gradient (0..cfg->iters) */

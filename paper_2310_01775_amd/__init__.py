@@ -121,6 +121,8 @@ _sig = {
     "stamp_mlp_train_workspace_bytes": (_sz, [_i32]),
     "stamp_mlp_train_step": (_i32, [_vp, _i32, _i32, _vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp, _i32, _f32, _f32,
                                     _f32, _f32, _vp, _vp, _vp, _sz, _vp]),
+    "stamp_mlp_train_steps": (_i32, [_vp, _i32, _i32, _i32, _vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp, _i32,
+                                     _P(_f32), _f32, _f32, _f32, _vp, _vp, _vp, _sz, _vp]),
     "stamp_solve_surrogate": (_i32, [_vp, _i32, _P(Scene), _P(CostW), _P(_i32), _P(SolverCfg), _P(Surrogate), _vp,
                                      _vp, _vp, _vp, _vp, _vp, _P(SurrogateReport), _vp, _sz, _vp, _vp]),
 }
@@ -612,6 +614,30 @@ class Context:
                                               _ptr(wbf16), _ptr(adam_m), _ptr(adam_v), int(t), lr, beta1, beta2, eps,
                                               _ptr(loss), _ptr(status), _ptr(workspace), workspace.numel(),
                                               _stream(stream)))
+
+    def mlp_train_steps(self, params, wbf16, adam_m, adam_v, x, cost, t0, idx, lr, beta1=0.9, beta2=0.999,
+                        eps=1e-8, loss=None, status=None, workspace=None, stream=None):
+        """len(lr) consecutive Adam steps t0+1.. in one call: step s on the rows
+        idx[s] (int32 [n_steps][M]) with learning rate lr[s]; loss (float32
+        [n_steps], optional) receives each step's loss before its update."""
+        self._mlp_buffers(params, wbf16, adam_m, adam_v)
+        n_rows, n_in = x.shape
+        if tuple(cost.shape) != (n_rows,):
+            raise ValueError("cost must be [n_rows]")
+        if idx.dtype != torch.int32 or idx.dim() != 2 or not idx.is_contiguous():
+            raise ValueError("idx must be a contiguous int32 [n_steps][M] tensor")
+        n_steps, M = idx.shape
+        if len(lr) != n_steps:
+            raise ValueError("one learning rate per step")
+        if loss is not None and (loss.dtype != torch.float32 or loss.numel() < n_steps):
+            raise ValueError("loss must hold n_steps float32")
+        if workspace is None:
+            workspace = self._bytes(self.mlp_train_workspace_bytes(M))
+        lrs = (C.c_float * n_steps)(*[float(v) for v in lr])
+        self._check(_lib.stamp_mlp_train_steps(self._h, n_steps, M, n_in, _ptr(x), _ptr(cost), _ptr(idx), n_rows,
+                                               _ptr(params), _ptr(wbf16), _ptr(adam_m), _ptr(adam_v), int(t0), lrs,
+                                               beta1, beta2, eps, _ptr(loss), _ptr(status), _ptr(workspace),
+                                               workspace.numel(), _stream(stream)))
 
     def solve_surrogate(self, scenes, ws_, Ns, cfg: SolverCfg, sur_iters: int, params, wbf16, n_in: int, enc,
                         theta, adam_m=None, adam_v=None, check_every: int = 0, max_log_err: float = 0.0,

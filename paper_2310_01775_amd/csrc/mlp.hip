@@ -566,40 +566,87 @@ __global__ __launch_bounds__(256) void k_mlp_train_fb(const float* __restrict__ 
     }
 }
 
-// out[c][k] (row stride ldo) = sum_s AT[c][s] BT[k][s], one wave per 16 x 16
-// block; K = M samples (multiple of 32).
-__global__ __launch_bounds__(64) void k_mlp_wgrad(const __bf16* __restrict__ AT, const __bf16* __restrict__ BT, int M,
-                                                  int ncol, float* __restrict__ out) {
-    const int nb = ncol / 16;
-    const int cb = blockIdx.x / nb, kb = blockIdx.x % nb;
-    const int l = threadIdx.x;
+// Weight-gradient partials of a minibatch split in `splits` sample ranges:
+// part[q][c][k] = sum over the samples s of range q of AT[c][s] BT[k][s]
+// (AT [nc][M], BT [nk][M], BF16 feature-major; nc, nk multiples of 64).  A
+// workgroup of four waves takes a 64 x 64 output tile of one range, each wave
+// a 32 x 32 quarter as 2 x 2 MFMA tiles; Adam adds the ranges in order.
+__global__ __launch_bounds__(256) void k_mlp_wgrad(const __bf16* __restrict__ AT, const __bf16* __restrict__ BT,
+                                                   int M, int nc, int nk, int per, float* __restrict__ part) {
+    const int tk = nk / 64;
+    const int c0 = (int)(blockIdx.x / tk) * 64, k0 = (int)(blockIdx.x % tk) * 64;
+    const int q = blockIdx.y;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), l = threadIdx.x & 63;
     const int r = l & 15, kq = l >> 4;
-    const __bf16* a = AT + (int64_t)(cb * 16 + r) * M + 8 * kq;
-    const __bf16* b = BT + (int64_t)(kb * 16 + r) * M + 8 * kq;
-    f4 acc = {0.f, 0.f, 0.f, 0.f};
-    for (int s0 = 0; s0 < M; s0 += 32) {
-        const bf16x8 av = *reinterpret_cast<const bf16x8*>(a + s0);
-        const bf16x8 bv = *reinterpret_cast<const bf16x8*>(b + s0);
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc, 0, 0, 0);
+    const int cw = c0 + 32 * (wave >> 1), kw = k0 + 32 * (wave & 1);
+    const int s0 = q * per;
+    const __bf16* a0 = AT + (int64_t)(cw + r) * M + 8 * kq;
+    const __bf16* b0 = BT + (int64_t)(kw + r) * M + 8 * kq;
+    f4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int s = s0; s < s0 + per; s += 32) {
+        bf16x8 av[2], bv[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) av[i] = *reinterpret_cast<const bf16x8*>(a0 + (int64_t)16 * i * M + s);
+#pragma unroll
+        for (int j = 0; j < 2; ++j) bv[j] = *reinterpret_cast<const bf16x8*>(b0 + (int64_t)16 * j * M + s);
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[i], bv[j], acc[i][j], 0, 0, 0);
     }
-    for (int j = 0; j < 4; ++j) out[(int64_t)(cb * 16 + 4 * kq + j) * ncol + kb * 16 + r] = acc[j];
+    float* out = part + (int64_t)q * nc * nk;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) out[(int64_t)(cw + 16 * i + 4 * kq + t) * nk + kw + 16 * j + r] = acc[i][j][t];
 }
 
-// Adam on the trained tensors (FP32 master weights), gradients from the
-// weight-gradient buffers and the per-tile partial sums (summed in tile order).
+// Sample ranges of the weight gradients: the largest power of two up to 32
+// whose ranges are whole 32-sample MFMA steps.
+__host__ __device__ __forceinline__ int wgrad_splits(int M) {
+    int q = 32;
+    while (q > 1 && M % (32 * q)) q >>= 1;
+    return q;
+}
+
+// Adam on the trained tensors (FP32 master weights): the weight gradients add
+// their sample ranges in range order, the bias and output-weight gradients
+// the training workgroups' partial sums in workgroup order (eight loads in
+// flight).  Element 0 (mu, not trained) writes the loss instead when asked.
 __global__ __launch_bounds__(256) void k_mlp_adam(float* __restrict__ P, float* __restrict__ mom,
                                                   float* __restrict__ vel, const float* __restrict__ dW1,
-                                                  const float* __restrict__ dW2, const float* __restrict__ part,
-                                                  int tiles, int n_in, int t, float lr, float b1, float b2,
-                                                  float eps) {
+                                                  const float* __restrict__ dW2, int splits,
+                                                  const float* __restrict__ part, int tiles, int n_in, int t,
+                                                  float lr, float b1, float b2, float eps, float* loss) {
     const int e = blockIdx.x * 256 + threadIdx.x;
     if (e >= kMlpParams) return;
+    // the range sum (stride bytes between ranges) or the workgroup sum
+    auto sum = [&](const float* base, int64_t stride, int n) {
+        float g = 0.0f;
+        for (int q0 = 0; q0 < n; q0 += 8) {
+            float u[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) u[k] = base[(int64_t)min(q0 + k, n - 1) * stride];
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                if (q0 + k < n) g += u[k];
+        }
+        return g;
+    };
+    if (e == 0 && loss) *loss = sum(part + 769, kMlpPartStride, tiles);
     float g;
     if (e >= kMlpOffW1 && e < kMlpOffB1) {
         const int k = (e - kMlpOffW1) / kIn, f = (e - kMlpOffW1) % kIn;
-        g = f < n_in ? dW1[k * kIn + f] : 0.0f;
+        g = f < n_in ? sum(dW1 + k * kIn + f, (int64_t)kW * kIn, splits) : 0.0f;
     } else if (e >= kMlpOffW2 && e < kMlpOffB2) {
-        g = dW2[e - kMlpOffW2];
+        g = sum(dW2 + (e - kMlpOffW2), (int64_t)kW * kW, splits);
     } else {
         int idx;
         if (e >= kMlpOffB1 && e < kMlpOffW2) idx = e - kMlpOffB1;              // sum delta1
@@ -607,8 +654,7 @@ __global__ __launch_bounds__(256) void k_mlp_adam(float* __restrict__ P, float* 
         else if (e >= kMlpOffW3 && e < kMlpOffB3) idx = 512 + (e - kMlpOffW3);  // sum delta3 h2
         else if (e == kMlpOffB3) idx = 768;                                     // sum delta3
         else return;  // mu, inv_sigma and padding are not trained
-        g = 0.0f;
-        for (int q = 0; q < tiles; ++q) g += part[(int64_t)q * kMlpPartStride + idx];
+        g = sum(part + idx, kMlpPartStride, tiles);
     }
     const float mm = b1 * mom[e] + (1.0f - b1) * g;
     const float vv = b2 * vel[e] + (1.0f - b2) * g * g;
@@ -716,11 +762,6 @@ __global__ __launch_bounds__(256) void k_log_err(const ProblemDesc* __restrict__
     if (threadIdx.x == 0) out[p] = red[0] / (float)N;
 }
 
-__global__ void k_mlp_loss(const float* __restrict__ part, int tiles, float* loss) {
-    float s = 0.0f;
-    for (int q = 0; q < tiles; ++q) s += part[(int64_t)q * kMlpPartStride + 769];
-    *loss = s;
-}
 
 }  // namespace
 
@@ -771,8 +812,8 @@ MlpTrainLayout mlp_train_layout(int M) {
     L.h1t = take(act * kW);
     L.d2t = take(act * kW);
     L.d1t = take(act * kW);
-    L.dw1 = take((size_t)kW * kIn * 4);
-    L.dw2 = take((size_t)kW * kW * 4);
+    L.dw1 = take((size_t)wgrad_splits(M) * kW * kIn * 4);
+    L.dw2 = take((size_t)wgrad_splits(M) * kW * kW * 4);
     L.part = take((size_t)(M / kRows) * kMlpPartStride * 4);
     L.total = off;
     return L;
@@ -790,13 +831,15 @@ hipError_t launch_mlp_train_step(float* P, __bf16* Wb, float* mom, float* vel, i
     float* dW2 = reinterpret_cast<float*>(ws + L.dw2);
     float* part = reinterpret_cast<float*>(ws + L.part);
     const int tiles = M / kRows;
+    const int splits = wgrad_splits(M), per = M / splits;
     hipLaunchKernelGGL(k_mlp_train_fb, dim3(tiles), dim3(256), 0, st, P, Wb, X, cost, idx, n_rows, M, n_in, status,
                        UT, H1T, D2T, D1T, part);
-    hipLaunchKernelGGL(k_mlp_wgrad, dim3((kW / 16) * (kW / 16)), dim3(64), 0, st, D2T, H1T, M, kW, dW2);
-    hipLaunchKernelGGL(k_mlp_wgrad, dim3((kW / 16) * (kIn / 16)), dim3(64), 0, st, D1T, UT, M, kIn, dW1);
-    if (loss_out) hipLaunchKernelGGL(k_mlp_loss, dim3(1), dim3(1), 0, st, part, tiles, loss_out);
-    hipLaunchKernelGGL(k_mlp_adam, dim3((kMlpParams + 255) / 256), dim3(256), 0, st, P, mom, vel, dW1, dW2, part,
-                       tiles, n_in, t, lr, b1, b2, eps);
+    hipLaunchKernelGGL(k_mlp_wgrad, dim3((kW / 64) * (kW / 64), splits), dim3(256), 0, st, D2T, H1T, M, kW, kW, per,
+                       dW2);
+    hipLaunchKernelGGL(k_mlp_wgrad, dim3((kW / 64) * (kIn / 64), splits), dim3(256), 0, st, D1T, UT, M, kW, kIn, per,
+                       dW1);
+    hipLaunchKernelGGL(k_mlp_adam, dim3((kMlpParams + 255) / 256), dim3(256), 0, st, P, mom, vel, dW1, dW2, splits,
+                       part, tiles, n_in, t, lr, b1, b2, eps, loss_out);
     hipLaunchKernelGGL(k_mlp_prepare, dim3((kW * kW + 255) / 256), dim3(256), 0, st, P, Wb);
     return hipGetLastError();
 }

@@ -1614,4 +1614,28 @@ int32_t stamp_mlp_train_step(stamp_ctx* ctx, int32_t M, int32_t n_in, const floa
     return e == hipSuccess ? STAMP_OK : hip_fail(ctx, e, "mlp_train_step");
 }
 
+int32_t stamp_mlp_train_steps(stamp_ctx* ctx, int32_t n_steps, int32_t M, int32_t n_in, const float* x,
+                              const float* cost, const int32_t* idx, int32_t n_rows, float* params, void* wbf16,
+                              float* adam_m, float* adam_v, int32_t t0, const float* lr, float beta1, float beta2,
+                              float eps, float* loss, uint32_t* status, void* workspace, size_t ws_bytes,
+                              void* stream) {
+    if (!ctx) return STAMP_EINVAL;
+    if (n_steps < 1 || !idx || !lr || t0 < 0) return fail(ctx, STAMP_EINVAL, "n_steps < 1, null idx or lr, or t0 < 0");
+    for (int s = 0; s < n_steps; ++s)
+        if (!isfinite(lr[s])) return fail(ctx, STAMP_EINVAL, "lr[%d] is not finite", s);
+    // the checks of one step cover every step
+    const int32_t r = stamp_mlp_train_step(ctx, M, n_in, x, cost, idx, n_rows, params, wbf16, adam_m, adam_v, t0 + 1,
+                                           lr[0], beta1, beta2, eps, loss, status, workspace, ws_bytes, stream);
+    if (r) return r;
+    const MlpTrainLayout L = mlp_train_layout(M);
+    for (int s = 1; s < n_steps; ++s) {
+        const hipError_t e = launch_mlp_train_step(params, (__bf16*)wbf16, adam_m, adam_v, t0 + s + 1, lr[s], beta1,
+                                                   beta2, eps, x, cost, idx + (int64_t)s * M, n_rows, M, n_in,
+                                                   loss ? loss + s : nullptr, status, (char*)workspace, L,
+                                                   (hipStream_t)stream);
+        if (e != hipSuccess) return hip_fail(ctx, e, "mlp_train_steps");
+    }
+    return STAMP_OK;
+}
+
 }  // extern "C"

@@ -74,18 +74,24 @@ def fit(ctx: Context, net: Network, ds: Dataset, steps: int, gen: torch.Generato
     log = log or TrainLog()
     m = torch.zeros_like(net.params)
     v = torch.zeros_like(net.params)
-    loss = torch.zeros(1, dtype=torch.float32, device=ctx.device)
     status = ctx.status_word()
     ws = ctx._bytes(ctx.mlp_train_workspace_bytes(batch))
     X, C = ds.x[:ds.n], ds.c[:ds.n]
-    for t in range(1, steps + 1):
-        idx = torch.randint(0, ds.n, (batch,), generator=gen, device=ctx.device, dtype=torch.int32)
-        lr_t = lr_min + (lr - lr_min) * 0.5 * (1.0 + math.cos(math.pi * (t - 1) / steps))
-        want = log_every and (t == 1 or t % log_every == 0 or t == steps)
-        ctx.mlp_train_step(net.params, net.wbf16, m, v, X, C, t, idx=idx, lr=lr_t, loss=loss if want else None,
-                           status=status, workspace=ws)
-        if want:
-            log.losses.append((log.steps + t, float(loss.item())))
+    # steps go to the library in chunks (one call launches a chunk's kernels
+    # back to back); every step's loss is kept, the logged ones read per chunk
+    chunk = 256
+    losses = torch.zeros(chunk, dtype=torch.float32, device=ctx.device)
+    for c0 in range(1, steps + 1, chunk):
+        n = min(chunk, steps + 1 - c0)
+        idx = torch.randint(0, ds.n, (n, batch), generator=gen, device=ctx.device, dtype=torch.int32)
+        lrs = [lr_min + (lr - lr_min) * 0.5 * (1.0 + math.cos(math.pi * (t - 1) / steps)) for t in range(c0, c0 + n)]
+        ctx.mlp_train_steps(net.params, net.wbf16, m, v, X, C, c0 - 1, idx, lrs, loss=losses, status=status,
+                            workspace=ws)
+        logged = [t for t in range(c0, c0 + n) if log_every and (t == 1 or t % log_every == 0 or t == steps)]
+        if logged:
+            host = losses[:n].cpu()
+            for t in logged:
+                log.losses.append((log.steps + t, float(host[t - c0])))
     log.steps += steps
     if int(status.item()) != 0:
         raise RuntimeError("training reported status %#x" % int(status.item()))

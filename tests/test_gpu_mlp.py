@@ -195,6 +195,42 @@ def test_training_fits_and_oracle_agrees(ctx):
     assert abs(L_gpu - L_ref) < 0.1 * L_ref + 1e-4
 
 
+def test_train_steps_equal_single_steps(ctx):
+    """stamp_mlp_train_steps launches the steps of stamp_mlp_train_step back to
+    back: parameters, moments, BF16 copies and every step's loss are the same
+    bits as those of the single-step calls."""
+    import paper_2310_01775_amd as S
+    n_rows, M, steps = 3000, 1024, 5
+    x, _ = _inputs(n_rows)
+    p = _params(4, x=x)
+    rng = np.random.default_rng(11)
+    X = _dev(x)
+    Cst = _dev(W.f32(np.expm1(rng.normal(1.0, 1.0, n_rows))))
+    idx = torch.as_tensor(rng.integers(0, n_rows, (steps, M)), dtype=torch.int32, device="cuda").contiguous()
+    lrs = [1e-3 * (0.9 ** s) for s in range(steps)]
+    out = []
+    for multi in (False, True):
+        P = _dev(S.pack_mlp(p))
+        Wb = ctx.mlp_weights()
+        ctx.mlp_prepare(P, Wb)
+        m = torch.zeros(S.MLP_PARAMS, device="cuda")
+        v = torch.zeros(S.MLP_PARAMS, device="cuda")
+        loss = torch.zeros(steps, device="cuda")
+        st = ctx.status_word()
+        if multi:
+            ctx.mlp_train_steps(P, Wb, m, v, X, Cst, 2, idx, lrs, loss=loss, status=st)
+        else:
+            for s in range(steps):
+                ctx.mlp_train_step(P, Wb, m, v, X, Cst, 3 + s, idx=idx[s].contiguous(), lr=lrs[s], loss=loss[s:s + 1],
+                                   status=st)
+        torch.cuda.synchronize()
+        assert int(st.item()) == 0
+        out.append((P, Wb.view(torch.int16), m, v, loss))
+    for a, b in zip(*out):
+        assert torch.equal(a, b)
+    assert bool((out[1][4] > 0).all())
+
+
 def test_argument_errors(ctx):
     import paper_2310_01775_amd as S
     P = torch.zeros(S.MLP_PARAMS, device="cuda")
