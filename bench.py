@@ -610,8 +610,10 @@ def bench_batched(args):
             return ctx.solve(scenes, ws_, Ns, cfg(iters), theta, m, v, solve_time_us=times, workspace=work,
                              status=status)
 
-        warm = flat.clone()
-        run(max(args.warmup, 1), warm)  # autotune + graph instantiation
+        # warm-up: the same solve, so that the autotuning and the capture of
+        # every graph the timed call replays happen before it
+        for _ in range(max(args.warmup, 1)):
+            run(args.steps, flat.clone())
         torch.cuda.synchronize()
         theta = flat.clone()
         t0 = time.perf_counter()

@@ -123,9 +123,10 @@ typedef struct stamp_solver_cfg {
     int32_t classes;   /* stamp_solve over several problems: 0 or 1, one batch in which the
                           problems advance in lockstep; C > 1, the problems are ordered by
                           their predicted cost per iteration and solved in min(C, n_problems)
-                          classes of consecutive cost, cheapest class first, each class one
-                          batch of its own (same results, bit for bit), so that a cheap
-                          problem is done when its class is */
+                          classes of consecutive cost and about equal predicted work,
+                          cheapest class first, each class one batch of its own (same
+                          results, bit for bit), so that a cheap problem is done when its
+                          class is */
     const struct stamp_struct_kernel* kernel; /* NULL: the RBF kernel on theta; else the
                           structured kernel (push layout; K is taken from each scene's H,
                           the field itself is ignored) in every SVGD iteration */

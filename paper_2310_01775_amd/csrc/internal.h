@@ -39,20 +39,18 @@ hipError_t launch_svgd(int N, int d, const float* theta, const float* grad_logp,
 // The step's first half, which depends on theta only (and may therefore run
 // concurrently with the rollout that produces grad_logp): the median into the
 // workspace's selection state and the FP32 form's theta operands (particle
-// mean, centred rows, norms -- which the median's Gram-form passes read --
-// then X = -(2/h) x).
+// mean, centred rows, norms -- which the median's Gram-form passes read).
 hipError_t launch_svgd_bandwidth(int N, int d, const float* theta, float bandwidth, float* h_out, void* ws,
                                  const SvgdLayout& L, hipStream_t st);
 hipError_t launch_svgd_bandwidth_batched(const BatchPlan& P, const ProblemDesc* descs, const float* theta, int exact,
                                          char* ws, hipStream_t st);
-// part 0: particle mean, centred rows and norms (before the median); part 1:
-// X = -(2/h) x (after it)
-hipError_t launch_operands32(int N, int d, const float* theta, int part, void* ws, const SvgdLayout& L,
-                             hipStream_t st);
-hipError_t launch_operands32_batched(const BatchPlan& P, const ProblemDesc* descs, const float* theta, int part,
-                                     char* ws, hipStream_t st);
-// The step's second half: phi from the bandwidth and centre the workspace
-// holds (FP32 matrix cores, phi32.hip).
+// particle mean, centred rows and norms (before the median)
+hipError_t launch_operands32(int N, int d, const float* theta, void* ws, const SvgdLayout& L, hipStream_t st);
+hipError_t launch_operands32_batched(const BatchPlan& P, const ProblemDesc* descs, const float* theta, char* ws,
+                                     hipStream_t st);
+// The step's second half: V = w [g - (2/h) x | 1] packed from theta, the
+// gradient and the weights, then phi from the bandwidth, centre and rows the
+// workspace holds (FP32 matrix cores, phi32.hip).
 // upd (nullable): apply the update of Algorithm 1 to theta in the same pass
 // (phi may then be null); theta is read for every element before its update.
 hipError_t launch_svgd_direction(int N, int d, const float* theta, const float* grad_logp, float* phi, void* ws,

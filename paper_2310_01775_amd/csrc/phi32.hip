@@ -9,15 +9,20 @@
 //   phi_i = ( A_i[0..d) + (2/h) x_i A_i[d] ) / N
 //
 // which is (1/N) sum_j w_j K_ij [g_j + (2/h)(theta_i - theta_j)] with
-// theta_i - theta_j = x_i - x_j.
+// theta_i - theta_j = x_i - x_j.  With c = -log2(e) / h, log2 K_ij =
+// -2c (x_i . x_j + e_j) + c |x_i|^2 for e_j = -|x_j|^2 / 2: e_j enters as the
+// Gram MFMA's accumulator input, the rest is one fused multiply-add, and the
+// exponential's clamp to [0, 1] is the max(D, 0) (one multiply-add and one
+// exponential per pair: the VALU work shares the issue port with the MFMAs).
 //
 // Stages: everything that depends on theta only runs with the median (the
 // bandwidth stage, which can overlap the rollout): the particle mean and the
 // centred rows in the MFMA operand order with their norms (the median's
-// all-pairs passes take their Gram-form distances from these), then after the
-// median X = [-(2/h) x | 1 | 0] chunk-tiled.  The contraction adds g
-// (read straight from its [d][N] layout) and the weights to X to form V; it (64, 128 or 256 rows per workgroup, 64 per wave as four 16-row
-// tiles, one column split) runs per 16 columns the Gram MFMAs of every row tile, turns
+// all-pairs passes take their Gram-form distances from these).  The direction
+// stage packs V = w [g - (2/h) x | 1 | 0] chunk-tiled from theta, g and the
+// weights, so the contraction's loop only loads it; the contraction (64, 128
+// or 256 rows per workgroup, 64 per wave as four 16-row tiles, one column
+// split) runs per 16 columns the Gram MFMAs of every row tile, turns
 // them into K in registers and feeds K as the A operand of the K.V MFMAs: the
 // Gram output (lane holds columns j = 4(l/16)+t of row l%16) is an A operand
 // whose k index runs over (l/16, t), and V is stored in that order, so each
@@ -79,81 +84,42 @@ __device__ void pack32_x_rows(int N, int d, int ks, int row0, const float* __res
     __syncthreads();
 }
 
-__device__ void pack32_v_rows(int N, int d, int ot, int row0, const float* __restrict__ theta, const View32& v) {
+// V[i][n] = w_i (g[n][i] - (2/h) x_i[n]) for n < d, w_i for n = d, 0 past it
+// and for the padding rows i >= N (w_i = 1 without weights)
+__device__ void pack32_v_rows(int N, int d, int ot, int row0, const float* __restrict__ theta,
+                              const float* __restrict__ g, const float* __restrict__ wts, const View32& v) {
     const int r = threadIdx.x & 63, q = threadIdx.x >> 6;
     const int i = row0 + r;
     const float c2 = 2.0f / v.sel->h;
+    const float w = (i < N && wts) ? wts[i] : 1.0f;
     float* vt = v.vt + (int64_t)(i >> 4) * ot * 256 + (i & 15);
     for (int n = q; n < 16 * ot; n += 4) {
         float x = 0.0f;
-        if (i < N) x = n < d ? -c2 * (theta[(int64_t)n * N + i] - v.ctr[n]) : (n == d ? 1.0f : 0.0f);
+        if (i < N) {
+            if (n < d) x = -c2 * (theta[(int64_t)n * N + i] - v.ctr[n]) + g[(int64_t)n * N + i];
+            else x = n == d ? 1.0f : 0.0f;
+            if (wts) x *= w;
+        }
         vt[(n >> 4) * 256 + (n & 15) * 16] = x;
     }
 }
 
 // ---- contraction: partial sums of K V over the columns [j0, j1) -------------------
-// V[j][n] = w_j (X[j][n] + g[n][j]) for the lane's j = jc + 4 kq + t and
-// n = 16 o + col: X from its tile, g from [d][N] (one 16-byte load when the
-// four columns are in range and aligned), w_j = 1 without weights.  The
-// loads are issued by fetch_v and combined by finish_v, so a step's operands
-// can be fetched a step ahead without waiting for them at once.
+// V[j][n] for the lane's j = jc + 4 kq + t and n = 16 o + col, one 16-byte
+// load per output tile (the tile stores the lane's four j together).
 template <int OT>
-struct VRaw {
-    f4 x[OT], g[OT], w;
-};
-
-template <int OT>
-__device__ __forceinline__ void fetch_v(int jc, int col, int kq, int N, int d, bool g4, const float* __restrict__ g,
-                                        const float* __restrict__ wts, const View32& v, VRaw<OT>& R) {
-    const int j = jc + 4 * kq;
+__device__ __forceinline__ void load_v(int jc, int col, int kq, const View32& v, f4 (&vv)[OT]) {
     const float* vp = v.vt + (int64_t)(jc >> 4) * OT * 256 + col * 16 + kq * 4;
-    const bool full = g4 && j + 4 <= N;
 #pragma unroll
-    for (int o = 0; o < OT; ++o) {
-        R.x[o] = *reinterpret_cast<const f4*>(vp + o * 256);
-        const float* gp = g + (int64_t)min(16 * o + col, d - 1) * N;
-        if (full) {
-            R.g[o] = *reinterpret_cast<const f4*>(gp + j);
-        } else {
-#pragma unroll
-            for (int t = 0; t < 4; ++t) R.g[o][t] = gp[min(j + t, N - 1)];
-        }
-    }
-    if (wts)
-#pragma unroll
-        for (int t = 0; t < 4; ++t) R.w[t] = wts[min(j + t, N - 1)];
-}
-
-template <int OT>
-__device__ __forceinline__ void finish_v(int jc, int col, int kq, int N, int d, const float* __restrict__ wts,
-                                         const VRaw<OT>& R, f4 (&vv)[OT]) {
-    const int j = jc + 4 * kq;
-#pragma unroll
-    for (int o = 0; o < OT; ++o) {
-        f4 gv = R.g[o];
-#pragma unroll
-        for (int t = 0; t < 4; ++t) gv[t] *= j + t < N ? 1.0f : 0.0f;
-        if (16 * o + col >= d) gv = f4{0.f, 0.f, 0.f, 0.f};
-        vv[o] = R.x[o] + gv;
-    }
-    if (wts) {
-        f4 w;
-#pragma unroll
-        for (int t = 0; t < 4; ++t) w[t] = j + t < N ? R.w[t] : 0.0f;
-#pragma unroll
-        for (int o = 0; o < OT; ++o) vv[o] *= w;
-    }
+    for (int o = 0; o < OT; ++o) vv[o] = *reinterpret_cast<const f4*>(vp + o * 256);
 }
 
 template <int KS, int OT>
-__device__ void phi32_body(int N, int d, int row0, int j0, int j1, int split, int npad, const float* __restrict__ g,
-                           const float* __restrict__ wts, const View32& v) {
+__device__ void phi32_body(int row0, int j0, int j1, int split, int npad, const View32& v) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int col = lane & 15, kq = lane >> 4;
     const int rbase = row0 + wave * 64;
     const float c = -1.44269504088896341f / v.sel->h;  // K = 2^(c D)
-    // 16-byte loads of g need every row start aligned
-    const bool g4 = (N & 3) == 0 && (reinterpret_cast<uintptr_t>(g) & 15) == 0;
     const float m2c = -2.0f * c;
     float xi[4][KS], ni[4];
 #pragma unroll
@@ -168,11 +134,9 @@ __device__ void phi32_body(int N, int d, int row0, int j0, int j1, int split, in
     for (int r = 0; r < 4; ++r)
 #pragma unroll
         for (int o = 0; o < OT; ++o) acc[r][o] = f4{0.f, 0.f, 0.f, 0.f};
-    // the next 16 columns' operands load while these compute; V is combined
-    // from its loads only after the step, so the loads stay in flight
+    // the next 16 columns' operands load while these compute
     float xj[KS], xn[KS];
-    f4 nj, nn, vb[OT];
-    VRaw<OT> rn;
+    f4 nj, nn, vb[OT], vn[OT];
     auto load_x = [&](int jc, float (&x)[KS], f4& n) {
         const float* p = v.xr + (int64_t)(jc + col) * (4 * KS) + kq * KS;
 #pragma unroll
@@ -181,26 +145,23 @@ __device__ void phi32_body(int N, int d, int row0, int j0, int j1, int split, in
     };
     if (j0 < j1) {
         load_x(j0, xj, nj);
-        fetch_v<OT>(j0, col, kq, N, d, g4, g, wts, v, rn);
-        finish_v<OT>(j0, col, kq, N, d, wts, rn, vb);
+        load_v<OT>(j0, col, kq, v, vb);
     }
     for (int jc = j0; jc < j1; jc += 16) {
         const bool more = jc + 16 < j1;
         if (more) {
             load_x(jc + 16, xn, nn);
-            fetch_v<OT>(jc + 16, col, kq, N, d, g4, g, wts, v, rn);
+            load_v<OT>(jc + 16, col, kq, v, vn);
         }
-        float cn[4];
-#pragma unroll
-        for (int t = 0; t < 4; ++t) cn[t] = c * nj[t];
+        const f4 ej = nj * -0.5f;  // e_j of the lane's four columns
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            f4 s = f4{0.f, 0.f, 0.f, 0.f};
+            f4 s = ej;  // x_i . x_j + e_j
 #pragma unroll
             for (int k = 0; k < KS; ++k) s = __builtin_amdgcn_mfma_f32_16x16x4f32(xj[k], xi[r][k], s, 0, 0, 0);
             float kv[4];
 #pragma unroll
-            for (int t = 0; t < 4; ++t) kv[t] = hw_exp2(fminf(fmaf(m2c, s[t], ni[r] + cn[t]), 0.0f));
+            for (int t = 0; t < 4; ++t) kv[t] = unit_clamp(hw_exp2(fmaf(m2c, s[t], ni[r])));
 #pragma unroll
             for (int t = 0; t < 4; ++t)
 #pragma unroll
@@ -211,7 +172,8 @@ __device__ void phi32_body(int N, int d, int row0, int j0, int j1, int split, in
 #pragma unroll
             for (int s = 0; s < KS; ++s) xj[s] = xn[s];
             nj = nn;
-            finish_v<OT>(jc + 16, col, kq, N, d, wts, rn, vb);
+#pragma unroll
+            for (int o = 0; o < OT; ++o) vb[o] = vn[o];
         }
     }
     float* out = v.part + (int64_t)split * (16 * OT) * npad;
@@ -272,15 +234,16 @@ __global__ __launch_bounds__(256) void k_pack32_x(One32 a, const float* theta, c
     pack32_x_rows(a.N, a.d, a.L.ks32, blockIdx.x * 64, theta, view32(a.L, ws));
 }
 
-__global__ __launch_bounds__(256) void k_pack32_v(One32 a, const float* theta, char* ws) {
-    pack32_v_rows(a.N, a.d, a.L.ot32, blockIdx.x * 64, theta, view32(a.L, ws));
+__global__ __launch_bounds__(256) void k_pack32_v(One32 a, const float* theta, const float* g, const float* wts,
+                                                  char* ws) {
+    pack32_v_rows(a.N, a.d, a.L.ot32, blockIdx.x * 64, theta, g, wts, view32(a.L, ws));
 }
 
 template <int KS, int OT>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_phi32(One32 a, const float* g, const float* wts, char* ws) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_phi32(One32 a, char* ws) {
     const int split = blockIdx.y;
     const int j0 = split * a.L.chunk32, j1 = min(j0 + a.L.chunk32, a.L.npad);
-    phi32_body<KS, OT>(a.N, a.d, blockIdx.x * blockDim.x, j0, j1, split, a.L.npad, g, wts, view32(a.L, ws));
+    phi32_body<KS, OT>(blockIdx.x * blockDim.x, j0, j1, split, a.L.npad, view32(a.L, ws));
 }
 
 // upd.use_adam < 0: no update
@@ -323,23 +286,23 @@ __global__ __launch_bounds__(256) void k_pack32_x_batched(const ProblemDesc* __r
 }
 
 __global__ __launch_bounds__(256) void k_pack32_v_batched(const ProblemDesc* __restrict__ descs,
-                                                          const int4* __restrict__ work, const float* theta, char* ws) {
+                                                          const int4* __restrict__ work, const float* theta,
+                                                          const float* grad, const float* wts, char* ws) {
     const int4 e = work[blockIdx.x >> 2];
     const ProblemDesc& D = descs[e.x];
     if (D.N < 2) return;
-    pack32_v_rows(D.N, D.d, D.sv.ot32, e.y + 64 * (blockIdx.x & 3), theta + D.theta_off, view32(D.sv, base32(D, ws)));
+    pack32_v_rows(D.N, D.d, D.sv.ot32, e.y + 64 * (blockIdx.x & 3), theta + D.theta_off, grad + D.theta_off,
+                  wts ? wts + D.cost_off : nullptr, view32(D.sv, base32(D, ws)));
 }
 
 // entry = (problem, row block of blockDim.x rows, split, -)
 template <int KS, int OT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_phi32_batched(const ProblemDesc* __restrict__ descs,
-                                                       const int4* __restrict__ work, const float* grad,
-                                                       const float* wts, char* ws) {
+                                                       const int4* __restrict__ work, char* ws) {
     const int4 e = work[blockIdx.x];
     const ProblemDesc& D = descs[e.x];
     const int j0 = e.z * D.sv.chunk32, j1 = min(j0 + D.sv.chunk32, D.sv.npad);
-    phi32_body<KS, OT>(D.N, D.d, e.y * (int)blockDim.x, j0, j1, e.z, D.sv.npad, grad + D.theta_off,
-                       wts ? wts + D.cost_off : nullptr, view32(D.sv, base32(D, ws)));
+    phi32_body<KS, OT>(e.y * (int)blockDim.x, j0, j1, e.z, D.sv.npad, view32(D.sv, base32(D, ws)));
 }
 
 // entry = (problem, first element, end element, -) of the problem's d*N block
@@ -371,15 +334,13 @@ constexpr int kCls[kPhi32Classes][2] = {{2, 1},  {4, 1},  {4, 2},  {6, 2},  {8, 
                                         {10, 3}, {12, 3}, {12, 4}, {14, 4}, {16, 4}, {16, 5}};
 
 template <int C>
-void launch_class(dim3 grid, int rows, hipStream_t st, const One32& a, const float* g, const float* wts, char* ws) {
-    hipLaunchKernelGGL((k_phi32<kCls[C][0], kCls[C][1]>), grid, dim3(rows), 0, st, a, g, wts, ws);
+void launch_class(dim3 grid, int rows, hipStream_t st, const One32& a, char* ws) {
+    hipLaunchKernelGGL((k_phi32<kCls[C][0], kCls[C][1]>), grid, dim3(rows), 0, st, a, ws);
 }
 
 template <int C>
-void launch_class_batched(int n, int rows, hipStream_t st, const ProblemDesc* descs, const int4* work,
-                          const float* grad, const float* wts, char* ws) {
-    hipLaunchKernelGGL((k_phi32_batched<kCls[C][0], kCls[C][1]>), dim3(n), dim3(rows), 0, st, descs, work, grad, wts,
-                       ws);
+void launch_class_batched(int n, int rows, hipStream_t st, const ProblemDesc* descs, const int4* work, char* ws) {
+    hipLaunchKernelGGL((k_phi32_batched<kCls[C][0], kCls[C][1]>), dim3(n), dim3(rows), 0, st, descs, work, ws);
 }
 
 template <typename F>
@@ -409,31 +370,21 @@ int phi32_class(int d) {
     return -1;
 }
 
-hipError_t launch_operands32(int N, int d, const float* theta, int part, void* ws, const SvgdLayout& L,
-                             hipStream_t st) {
+hipError_t launch_operands32(int N, int d, const float* theta, void* ws, const SvgdLayout& L, hipStream_t st) {
     if (N < 2) return hipSuccess;
     One32 a{N, d, L};
     char* b = static_cast<char*>(ws);
-    if (part == 0) {
-        hipLaunchKernelGGL(k_mean, dim3(d), dim3(kMeanThreads), 0, st, a, theta, b);
-        hipLaunchKernelGGL(k_pack32_x, dim3(L.npad / 64), dim3(256), 0, st, a, theta, b);
-    } else {
-        hipLaunchKernelGGL(k_pack32_v, dim3(L.npad / 64), dim3(256), 0, st, a, theta, b);
-    }
+    hipLaunchKernelGGL(k_mean, dim3(d), dim3(kMeanThreads), 0, st, a, theta, b);
+    hipLaunchKernelGGL(k_pack32_x, dim3(L.npad / 64), dim3(256), 0, st, a, theta, b);
     return hipGetLastError();
 }
 
-hipError_t launch_operands32_batched(const BatchPlan& P, const ProblemDesc* descs, const float* theta, int part,
-                                     char* ws, hipStream_t st) {
-    if (part == 0) {
-        if (P.n_ctr)
-            hipLaunchKernelGGL(k_mean_batched, dim3(P.n_ctr), dim3(kMeanThreads), 0, st, descs, P.ctr_work, theta, ws);
-        if (P.n_row16)
-            hipLaunchKernelGGL(k_pack32_x_batched, dim3(4 * P.n_row16), dim3(256), 0, st, descs, P.row16_work, theta,
-                               ws);
-    } else if (P.n_row16) {
-        hipLaunchKernelGGL(k_pack32_v_batched, dim3(4 * P.n_row16), dim3(256), 0, st, descs, P.row16_work, theta, ws);
-    }
+hipError_t launch_operands32_batched(const BatchPlan& P, const ProblemDesc* descs, const float* theta, char* ws,
+                                     hipStream_t st) {
+    if (P.n_ctr)
+        hipLaunchKernelGGL(k_mean_batched, dim3(P.n_ctr), dim3(kMeanThreads), 0, st, descs, P.ctr_work, theta, ws);
+    if (P.n_row16)
+        hipLaunchKernelGGL(k_pack32_x_batched, dim3(4 * P.n_row16), dim3(256), 0, st, descs, P.row16_work, theta, ws);
     return hipGetLastError();
 }
 
@@ -443,9 +394,10 @@ hipError_t launch_svgd_direction(int N, int d, const float* theta, const float* 
     One32 a{N, d, L};
     char* b = static_cast<char*>(ws);
     if (N >= 2) {
+        hipLaunchKernelGGL(k_pack32_v, dim3(L.npad / 64), dim3(256), 0, st, a, theta, grad_logp, wts, b);
         const int rows = phi_rows > 0 ? phi_rows : 256;
         const dim3 grid(L.npad / rows, L.splits32);
-        by_class(phi32_class(d), [&](auto c) { launch_class<decltype(c)::value>(grid, rows, st, a, grad_logp, wts, b); });
+        by_class(phi32_class(d), [&](auto c) { launch_class<decltype(c)::value>(grid, rows, st, a, b); });
     }
     const int64_t n = (int64_t)d * N;
     UpdateArgs u{};
@@ -459,11 +411,13 @@ hipError_t launch_svgd_direction(int N, int d, const float* theta, const float* 
 hipError_t launch_svgd_direction_batched(const BatchPlan& P, const ProblemDesc* descs, const float* theta,
                                          const float* grad, float* phi, char* ws, uint32_t* status, hipStream_t st,
                                          const float* wts, const UpdateArgs* upd) {
+    if (P.n_row16)
+        hipLaunchKernelGGL(k_pack32_v_batched, dim3(4 * P.n_row16), dim3(256), 0, st, descs, P.row16_work, theta, grad,
+                           wts, ws);
     for (int c = 0; c < kPhi32Classes; ++c)
         if (P.n_phi[c])
             by_class(c, [&](auto k) {
-                launch_class_batched<decltype(k)::value>(P.n_phi[c], P.phi_rows, st, descs, P.phi_work[c], grad, wts,
-                                                         ws);
+                launch_class_batched<decltype(k)::value>(P.n_phi[c], P.phi_rows, st, descs, P.phi_work[c], ws);
             });
     UpdateArgs u{};
     u.use_adam = -1;

@@ -258,10 +258,9 @@ hipError_t launch_svgd(int N, int d, const float* theta, const float* grad_logp,
 
 hipError_t launch_svgd_bandwidth(int N, int d, const float* theta, float bandwidth, float* h_out, void* ws,
                                  const SvgdLayout& L, hipStream_t st) {
-    hipError_t e = launch_operands32(N, d, theta, 0, ws, L, st);
+    hipError_t e = launch_operands32(N, d, theta, ws, L, st);
     if (e != hipSuccess) return e;
-    if ((e = launch_median(N, d, theta, bandwidth, 1, ws, L, h_out, st, 1)) != hipSuccess) return e;
-    return launch_operands32(N, d, theta, 1, ws, L, st);
+    return launch_median(N, d, theta, bandwidth, 1, ws, L, h_out, st, 1);
 }
 
 hipError_t launch_svgd_batched(const BatchPlan& P, const ProblemDesc* descs, const float* theta, const float* grad,
@@ -277,9 +276,8 @@ hipError_t launch_svgd_bandwidth_batched(const BatchPlan& P, const ProblemDesc* 
     // passes read them) or of the BF16 form (sampled median)
     if (!exact) return launch_bandwidth16_batched(P, descs, theta, ws, st);
     hipError_t e;
-    if ((e = launch_operands32_batched(P, descs, theta, 0, ws, st)) != hipSuccess) return e;
-    if ((e = launch_median_batched(P, descs, theta, 1, ws, st)) != hipSuccess) return e;
-    return launch_operands32_batched(P, descs, theta, 1, ws, st);
+    if ((e = launch_operands32_batched(P, descs, theta, ws, st)) != hipSuccess) return e;
+    return launch_median_batched(P, descs, theta, 1, ws, st);
 }
 
 hipError_t launch_phi_reduce(int N, int d, int splits, const float* partial, float* phi, uint32_t* status,
