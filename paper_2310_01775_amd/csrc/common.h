@@ -107,12 +107,13 @@ struct SvgdLayout {
     size_t x32_off;                 // npad x 4 ks32 floats: centred rows in MFMA operand order
     size_t n32_off;                 // npad floats: their squared norms
     size_t v32_off;                 // npad x 16 ot32 floats: V = w [g - (2/h) x | 1 | 0], tiled
-    int kd, vc;                     // padded dimension (32 or 64) and V columns (2 kd)
+    int kd, vc;                     // Gram width (d + 2 rounded up to 32) and V columns (d + 1 rounded up)
     int splits16, chunk16;          // column splits of its contraction and their width
     size_t smp_off;                 // kMedSample floats: the sampled distances
     size_t ctr_off;                 // 64 floats: particle mean
-    size_t nrm_off;                 // npad floats: |x~_i|^2
-    size_t xb_off;                  // npad x kd bf16: centred particles, row-major
+    size_t nrm_off;                 // npad floats: e_i = -|x^_i|^2 / 2
+    size_t xb_off;                  // npad x kd bf16: scaled centred rows [x^ | e hi | e lo | 0], the Gram's row operand
+    size_t xc_off;                  // npad x kd bf16: the same rows as [x^ | 1 | 1 | 0], its column operand
     size_t vt_off;                  // vc x npad bf16: V = [g | x~ | 1 | 0], chunked
     size_t p16_off;                 // splits16 x vc x npad floats: partial sums
     // structured kernel: per-particle features (at most 2d rows of N floats)

@@ -1027,9 +1027,8 @@ __global__ __launch_bounds__(kSelThreads) void k_sample_select_batched(const Pro
 // The BF16 form's bandwidth stage in two launches.  First: blocks below
 // nd = (kMedSample / 64) x problems gather the sample distances (four lanes a
 // slot), the rest take one entry (problem, coordinate) of the centre list
-// each.  Second: blocks below the problem count select the sample median,
-// the rest build the centred BF16 rows of one entry (problem, 256-row chunk)
-// of the row list, a quarter per 256 threads.  A non-null step counter is
+// each.  Second: one workgroup per problem selects the sample median (the
+// scaled rows, which need it, are packed with V).  A non-null step counter is
 // advanced once by the first launch (a solve's iteration counter, read by
 // the update at the iteration's end).
 __global__ __launch_bounds__(256) void k_bw16_gather_batched(const ProblemDesc* __restrict__ descs,
@@ -1049,23 +1048,6 @@ __global__ __launch_bounds__(256) void k_bw16_gather_batched(const ProblemDesc* 
     const ProblemDesc& D = descs[e.x];
     particle_mean_body<kCentreThreads>(D.N, e.y, theta + D.theta_off,
                                        reinterpret_cast<float*>(ws + D.svgd_off + D.sv.ctr_off));
-}
-
-__global__ __launch_bounds__(kSelThreads) void k_bw16_select_batched(const ProblemDesc* __restrict__ descs,
-                                                                     const int4* __restrict__ row_work, int np,
-                                                                     const float* theta, char* ws) {
-    if ((int)blockIdx.x < np) {
-        sample_select_body(med_of(descs[blockIdx.x], ws), 0, nullptr);
-        return;
-    }
-    static_assert(kSelThreads == 1024, "four 256-thread quarters per row chunk");
-    const int4 e = row_work[blockIdx.x - np];
-    const ProblemDesc& D = descs[e.x];
-    if (D.N < 2) return;
-    char* b = ws + D.svgd_off;
-    pack16_theta_rows(D.N, D.d, D.sv.kd, e.y + 64 * (threadIdx.x >> 8), threadIdx.x & 255, theta + D.theta_off,
-                      reinterpret_cast<const float*>(b + D.sv.ctr_off), reinterpret_cast<__bf16*>(b + D.sv.xb_off),
-                      reinterpret_cast<float*>(b + D.sv.nrm_off));
 }
 
 // entry = (problem, row block, column chunk, -) of this item shape's work list
@@ -1214,8 +1196,7 @@ hipError_t launch_bandwidth16_batched(const BatchPlan& P, const ProblemDesc* des
     const int np = P.n_problems, nd = (kMedSample / 64) * np;
     hipLaunchKernelGGL(k_bw16_gather_batched, dim3(nd + P.n_ctr), dim3(256), 0, st, descs, P.ctr_work, nd, theta, ws,
                        step);
-    hipLaunchKernelGGL(k_bw16_select_batched, dim3(np + P.n_row16), dim3(kSelThreads), 0, st, descs, P.row16_work, np,
-                       theta, ws);
+    hipLaunchKernelGGL(k_sample_select_batched, dim3(np), dim3(kSelThreads), 0, st, descs, ws, 0);
     return hipGetLastError();
 }
 

@@ -5,13 +5,14 @@
 //     squared distances of a fixed sample of kMedSample particle pairs (all
 //     N(N-1)/2 pairs when there are at most that many: then m2 is exact;
 //     median.hip, sampled mode);
-//   x_i = theta_i - mean theta, x~_i = bf16(x_i)   (centring shrinks the Gram cancellation)
-//   D_ij = |x~_i|^2 + |x~_j|^2 - 2 x~_i . x~_j   (Gram on MFMA, FP32 accumulate)
-//   K_ij = exp(-max(D_ij, 0) / h)
-// with log2 K_ij = m (x~_i . x~_j + e_j + e_i), m = 2 log2(e) / h and
-// e = -|x~|^2 / 2: e_j enters as the Gram MFMA's accumulator input and the
-// rest is one fused multiply-add; the exponential's clamp to [0, 1] is the
-// max(D, 0).
+//   x_i = theta_i - mean theta, x^_i = bf16(sqrt(m) x_i), m = 2 log2(e) / h
+//     (centring shrinks the Gram cancellation)
+//   K_ij = exp(-max(D_ij, 0) / h) with D_ij = |x_i - x_j|^2, so
+//   log2 K_ij = x^_i . x^_j + e_i + e_j, e = -|x^|^2 / 2   (Gram on MFMA, FP32 accumulate)
+// e_i rides in two more Gram columns of the row operand (a BF16 hi/lo pair
+// against ones in the column operand) and e_j is the Gram accumulator's
+// starting value (bf16_operands.h), so the Gram MFMA gives log2 K itself: one
+// exponential per element, whose clamp to [0, 1] is the max(D, 0).
 //   V_j = bf16[ g_j - (2/h) x_j | 1 | 0 ]
 //   A_i = sum_j bf16(K_ij) V_j                   (MFMA, FP32 accumulate)
 //   phi_i = (A_i[0..d) + (2/h) x_i A_i[d]) / N
@@ -48,8 +49,9 @@ typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f4;
 struct View16 {  // one problem's BF16-form workspace
     float* smp;
     float* ctr;
-    float* nrm;  // e_i = -|x~_i|^2 / 2
-    __bf16* xb;
+    float* nrm;  // e_i = -|x^_i|^2 / 2
+    __bf16* xb;  // the Gram's row operand [x^ | e hi | e lo | 0]
+    __bf16* xc;  // its column operand [x^ | 1 | 1 | 0]
     __bf16* vt;  // V by 32-particle chunk: [npad / 32][vc][32], particles in MFMA k order
     float* p16;
     SelState* sel;
@@ -61,6 +63,7 @@ __device__ __forceinline__ View16 view16(const SvgdLayout& L, char* base) {
     v.ctr = reinterpret_cast<float*>(base + L.ctr_off);
     v.nrm = reinterpret_cast<float*>(base + L.nrm_off);
     v.xb = reinterpret_cast<__bf16*>(base + L.xb_off);
+    v.xc = reinterpret_cast<__bf16*>(base + L.xc_off);
     v.vt = reinterpret_cast<__bf16*>(base + L.vt_off);
     v.p16 = reinterpret_cast<float*>(base + L.p16_off);
     v.sel = reinterpret_cast<SelState*>(base + L.sel_off);
@@ -72,17 +75,19 @@ __device__ __forceinline__ View16 view16(const SvgdLayout& L, char* base) {
 // 8 kq + 7, which are the chunk's particles 4 kq .. 4 kq + 3 and then
 // 16 + 4 kq .. 16 + 4 kq + 3.
 
-// ---- operands: the x~ rows and their norms depend on theta only and are
-// built with the median (bf16_operands.h); V needs g and h.  A workgroup
+// ---- operands: the scaled rows x^ and e need h, V needs g and h; both are
+// packed after the bandwidth (bf16_operands.h for the rows).  A workgroup
 // takes 64 padded rows (blockIdx.y picks them within a 256-row chunk, so the
 // grid fills more of the chip).
 // V: a thread per (32-particle chunk, column, lane group kq) makes one
 // 16-byte store, the 8 values that lane group of the K.V product reads.
-__device__ void pack16_v_rows(int N, int d, int vc, int row0, const float* __restrict__ theta,
+__device__ void pack16_v_rows(int N, int d, int kd, int vc, int row0, const float* __restrict__ theta,
                               const float* __restrict__ g, const View16& w) {
     const float c2 = 2.0f / w.sel->h;
     const int per = 4 * vc;  // stores per chunk
     row0 += 64 * blockIdx.y;
+    pack16_theta_rows(N, d, kd, row0, threadIdx.x, theta, w.ctr, sqrtf(2.0f * 1.44269504088896341f / w.sel->h),
+                      w.xb, w.xc, w.nrm);
     for (int o = threadIdx.x; o < 2 * per; o += 256) {
         const int q = (row0 >> 5) + o / per, c = (o >> 2) % vc, kq = o & 3;
         const float ctr = c < d ? w.ctr[c] : 0.0f;
@@ -102,7 +107,7 @@ __device__ void pack16_v_rows(int N, int d, int vc, int row0, const float* __res
 // Operands of one 32-column chunk, as this lane holds them.
 template <int KS, int OT>
 struct Chunk16 {
-    bf16x8 xj[2][KS];  // A of the Gram: rows j = jc + 16 sub + (l % 16)
+    bf16x8 xj[2][KS];  // A of the Gram (column operand): rows j = jc + 16 sub + (l % 16)
     f4 nj[2];          // e_j for j = jc + 16 sub + 4 (l / 16) + t: the Gram accumulator's start
     bf16x8 vb[OT];     // B of K.V: V[j][16 o + l % 16], j in the permuted order
 };
@@ -115,7 +120,7 @@ __device__ __forceinline__ void load_chunk(Chunk16<KD / 32, VC / 16>& c, const V
         const int j = jc + 16 * sub + col;
 #pragma unroll
         for (int ks = 0; ks < KD / 32; ++ks)
-            c.xj[sub][ks] = *reinterpret_cast<const bf16x8*>(w.xb + (int64_t)j * KD + 32 * ks + 8 * kq);
+            c.xj[sub][ks] = *reinterpret_cast<const bf16x8*>(w.xc + (int64_t)j * KD + 32 * ks + 8 * kq);
         c.nj[sub] = *reinterpret_cast<const f4*>(w.nrm + jc + 16 * sub + 4 * kq);
     }
     const __bf16* vch = w.vt + ((int64_t)(jc >> 5) * VC + col) * 32 + 8 * kq;
@@ -128,10 +133,10 @@ __device__ __forceinline__ void load_chunk(Chunk16<KD / 32, VC / 16>& c, const V
 // row tile overlaps the MFMAs still in flight for the next ones.
 template <int KD, int VC>
 __device__ __forceinline__ void chunk16_compute(const Chunk16<KD / 32, VC / 16>& cur, const bf16x8 (&xi)[4][KD / 32],
-                                                const float (&ni)[4], float m, f4 (&acc)[4][VC / 16]) {
+                                                f4 (&acc)[4][VC / 16]) {
     constexpr int KS = KD / 32;
     constexpr int OT = VC / 16;
-    f4 s[4][2];  // x~_i . x~_j + e_j
+    f4 s[4][2];  // log2 K: x^_i . x^_j + e_i + e_j
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         s[r][0] = cur.nj[0];
@@ -148,8 +153,8 @@ __device__ __forceinline__ void chunk16_compute(const Chunk16<KD / 32, VC / 16>&
         float kv[8];
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
-            kv[t] = unit_clamp(hw_exp2(fmaf(m, s[r][0][t], ni[r])));
-            kv[4 + t] = unit_clamp(hw_exp2(fmaf(m, s[r][1][t], ni[r])));
+            kv[t] = unit_clamp(hw_exp2(s[r][0][t]));
+            kv[4 + t] = unit_clamp(hw_exp2(s[r][1][t]));
         }
         ka[r] = bf16x8{(__bf16)kv[0], (__bf16)kv[1], (__bf16)kv[2], (__bf16)kv[3],
                        (__bf16)kv[4], (__bf16)kv[5], (__bf16)kv[6], (__bf16)kv[7]};
@@ -173,15 +178,12 @@ __device__ void phi16_body(int npad, int row0, int j0, int j1, int split, const 
         j0 += wave * q;
         j1 = j0 + q;
     }
-    const float m = 2.0f * 1.44269504088896341f / w.sel->h;  // 2 log2(e) / h
-    bf16x8 xi[4][KS];
-    float ni[4];
+    bf16x8 xi[4][KS];  // B of the Gram (row operand)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int i = rbase + 16 * r + col;
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) xi[r][ks] = *reinterpret_cast<const bf16x8*>(w.xb + (int64_t)i * KD + 32 * ks + 8 * kq);
-        ni[r] = m * w.nrm[i];
     }
     f4 acc[4][OT];
 #pragma unroll
@@ -189,13 +191,26 @@ __device__ void phi16_body(int npad, int row0, int j0, int j1, int split, const 
 #pragma unroll
         for (int o = 0; o < OT; ++o) acc[r][o] = f4{0.f, 0.f, 0.f, 0.f};
 
-    // the next chunk's operands load while this one computes
-    Chunk16<KS, OT> cur, nxt;
-    if (j0 < j1) load_chunk<KD, VC>(cur, w, npad, j0, col, kq);
-    for (int jc = j0; jc < j1; jc += 32) {
-        if (jc + 32 < j1) load_chunk<KD, VC>(nxt, w, npad, jc + 32, col, kq);
-        chunk16_compute<KD, VC>(cur, xi, ni, m, acc);
-        cur = nxt;
+    // the next chunk's operands load while this one computes: at kd = 32 two
+    // buffers in turn, so no operand is copied between them; the wider Grams
+    // copy the next chunk into the current one instead (two live buffers in
+    // the unrolled loop would take them past 256 registers, one wave per SIMD)
+    Chunk16<KS, OT> c0, c1;
+    if (j0 < j1) load_chunk<KD, VC>(c0, w, npad, j0, col, kq);
+    if constexpr (KD == 32) {
+        for (int jc = j0; jc < j1; jc += 64) {
+            if (jc + 32 < j1) load_chunk<KD, VC>(c1, w, npad, jc + 32, col, kq);
+            chunk16_compute<KD, VC>(c0, xi, acc);
+            if (jc + 32 >= j1) break;
+            if (jc + 64 < j1) load_chunk<KD, VC>(c0, w, npad, jc + 64, col, kq);
+            chunk16_compute<KD, VC>(c1, xi, acc);
+        }
+    } else {
+        for (int jc = j0; jc < j1; jc += 32) {
+            if (jc + 32 < j1) load_chunk<KD, VC>(c1, w, npad, jc + 32, col, kq);
+            chunk16_compute<KD, VC>(c0, xi, acc);
+            c0 = c1;
+        }
     }
     if (wave > 0) {
 #pragma unroll
@@ -270,13 +285,8 @@ __global__ __launch_bounds__(kCentreThreads) void k_center(One16 a, const float*
     particle_mean_body<kCentreThreads>(a.N, blockIdx.x, theta, view16(a.L, ws).ctr);
 }
 
-__global__ __launch_bounds__(256) void k_pack16_theta(One16 a, const float* theta, char* ws) {
-    const View16 w = view16(a.L, ws);
-    pack16_theta_rows(a.N, a.d, a.L.kd, blockIdx.x * 256 + 64 * blockIdx.y, threadIdx.x, theta, w.ctr, w.xb, w.nrm);
-}
-
 __global__ __launch_bounds__(256) void k_pack16_v(One16 a, const float* theta, const float* g, char* ws) {
-    pack16_v_rows(a.N, a.d, a.L.vc, blockIdx.x * 256, theta, g, view16(a.L, ws));
+    pack16_v_rows(a.N, a.d, a.L.kd, a.L.vc, blockIdx.x * 256, theta, g, view16(a.L, ws));
 }
 
 template <int KD, int VC>
@@ -307,16 +317,14 @@ __global__ __launch_bounds__(256) void k_reduce16(One16 a, const float* theta, c
 // ---- batched kernels (work-list entries as in svgd.hip) ---------------------------
 __device__ __forceinline__ char* base_of(const ProblemDesc& D, char* ws) { return ws + D.svgd_off; }
 
-// (the batched theta operands are built by the fused bandwidth-stage kernels
-// of median.hip, with the sampled median)
-
 __global__ __launch_bounds__(256) void k_pack16_v_batched(const ProblemDesc* __restrict__ descs,
                                                           const int4* __restrict__ work, const float* theta,
                                                           const float* grad, char* ws) {
     const int4 e = work[blockIdx.x];
     const ProblemDesc& D = descs[e.x];
     if (D.N < 2) return;
-    pack16_v_rows(D.N, D.d, D.sv.vc, e.y, theta + D.theta_off, grad + D.theta_off, view16(D.sv, base_of(D, ws)));
+    pack16_v_rows(D.N, D.d, D.sv.kd, D.sv.vc, e.y, theta + D.theta_off, grad + D.theta_off,
+                  view16(D.sv, base_of(D, ws)));
 }
 
 // entry = (problem, row block, split, -)
@@ -359,7 +367,6 @@ hipError_t launch_operands16(int N, int d, const float* theta, void* ws, const S
     One16 a{N, d, L, 0.0f};
     char* b = static_cast<char*>(ws);
     hipLaunchKernelGGL(k_center, dim3(d), dim3(kCentreThreads), 0, st, a, theta, b);
-    hipLaunchKernelGGL(k_pack16_theta, dim3(L.npad / 256, 4), dim3(256), 0, st, a, theta, b);
     return hipGetLastError();
 }
 
@@ -371,8 +378,8 @@ hipError_t launch_svgd16_direction(int N, int d, const float* theta, const float
         hipLaunchKernelGGL(k_pack16_v, dim3(L.npad / 256, 4), dim3(256), 0, st, a, theta, grad, b);
         const dim3 grid(L.npad / kTile16, L.splits16);
         if (L.kd == 32) hipLaunchKernelGGL((k_phi16<32, 32>), grid, dim3(256), 0, st, a, b);
-        else if (L.vc == 64) hipLaunchKernelGGL((k_phi16<64, 64>), grid, dim3(256), 0, st, a, b);
-        else hipLaunchKernelGGL((k_phi16<64, 80>), grid, dim3(256), 0, st, a, b);
+        else if (L.kd == 64) hipLaunchKernelGGL((k_phi16<64, 64>), grid, dim3(256), 0, st, a, b);
+        else hipLaunchKernelGGL((k_phi16<96, 80>), grid, dim3(256), 0, st, a, b);
     }
     UpdateArgs u{};
     u.use_adam = -1;

@@ -333,6 +333,7 @@ void build_plan(int n, const stamp_scene* scenes, const int32_t* N, int K, float
         for (int r0 = 0; r0 < D.N; r0 += kRows16) P.row16_work.push_back(make_int4(p, r0, 0, 0));
         if (D.N >= 2) {
             for (int l = 0; l < D.d; ++l) P.ctr_work.push_back(make_int4(p, l, 0, 0));
+            static_assert(6 * kMaxPushes <= 62, "a solve's problems take the 32- or 64-wide BF16 Gram");
             const int c16 = D.sv.kd == 32 ? 0 : 1;
             for (int rb = 0; rb < D.sv.npad / kTile16; ++rb)
                 for (int q = 0; q < D.sv.splits16; ++q) P.phi16_work[c16].push_back(make_int4(p, rb, q, 0));

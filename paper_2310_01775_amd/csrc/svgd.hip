@@ -212,13 +212,13 @@ SvgdLayout svgd_workspace_layout(int N, int d) {
     L.v32_off = off;
     off = align256(off + (size_t)L.npad * 16 * L.ot32 * 4);
     // BF16 matrix-core form
-    L.kd = d < 32 ? 32 : 64;
-    L.vc = d < 32 ? 32 : d < 64 ? 64 : 80;  // V = [g - (2/h) x | 1 | 0]: d + 1 columns, padded
+    L.kd = d <= 30 ? 32 : d <= 62 ? 64 : 96;  // the rows and two more Gram columns for e_i
+    L.vc = d <= 30 ? 32 : d <= 62 ? 64 : 80;  // V = [g - (2/h) x | 1 | 0]: d + 1 columns, padded
     {
         // one full round of resident workgroups (3 per CU at 32 Gram
-        // columns, 2 at 64: register bound), not a round and a partial one;
+        // columns, 2 at 64, 1 at 96: register bound), not a round and a partial one;
         // a split gives each of its workgroup's 4 waves at least 32 columns
-        const int resident = (L.kd == 32 ? 3 : 2) * 256;
+        const int resident = (L.kd == 32 ? 3 : L.kd == 64 ? 2 : 1) * 256;
         const int rowblocks = L.npad / kTile16;
         int s16 = (resident + rowblocks / 2) / rowblocks;
         if (s16 > L.npad / 128) s16 = L.npad / 128;
@@ -235,6 +235,8 @@ SvgdLayout svgd_workspace_layout(int N, int d) {
     L.nrm_off = off;
     off = align256(off + (size_t)L.npad * 4);
     L.xb_off = off;
+    off = align256(off + (size_t)L.npad * L.kd * 2);
+    L.xc_off = off;
     off = align256(off + (size_t)L.npad * L.kd * 2);
     L.vt_off = off;
     off = align256(off + (size_t)L.vc * L.npad * 2);

@@ -55,7 +55,8 @@ def test_sampled_median_is_close(ctx, N, d):
 
 
 @pytest.mark.parametrize("N,d,bw", [(1, 6, 0.0), (2, 6, 0.0), (37, 12, 0.0), (300, 18, 0.0), (513, 30, 0.0),
-                                    (1024, 30, 2.0), (700, 36, 0.0), (2100, 48, 0.0)])
+                                    (1024, 30, 2.0), (100, 31, 0.0), (700, 36, 0.0), (2100, 48, 0.0),
+                                    (300, 63, 0.0), (257, 64, 0.0)])
 def test_direction_matches_oracle_at_the_same_bandwidth(ctx, N, d, bw):
     import paper_2310_01775_amd as S
     print("case", N, d, bw, flush=True)
