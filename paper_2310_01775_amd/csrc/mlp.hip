@@ -365,6 +365,19 @@ __global__ __launch_bounds__(64 * NW) void k_mlp_infer(const float* __restrict__
     __syncthreads();
 
     if (want_grad) {
+        // the input gradient's first item of this wave (items go to the waves
+        // in turn): its W1^T fragments and raw inputs load during the backward
+        const int ft = min((d + 15) / 16, kIn / 16);
+        bf16x8 aw0[K2];
+        float xr0[4] = {0.f, 0.f, 0.f, 0.f};
+        if (wave < ft * SB) {
+            const int f0 = 16 * (wave / SB), i = row0 + 16 * (wave % SB) + col;
+#pragma unroll
+            for (int k = 0; k < K2; ++k) aw0[k] = a_frag(m.W1T, kW, f0, k);
+            if (bt.H && i < M)
+#pragma unroll
+                for (int t = 0; t < 4; ++t) xr0[t] = x_raw(X, x_mode, M, n_in, i, min(f0 + 4 * kq + t, d - 1));
+        }
         // delta1^T = (W2^T delta2^T) * gelu'(z1), to LDS over h1 (every wave is
         // past layer 2)
         f4 acc[TN][SB];
@@ -393,17 +406,23 @@ __global__ __launch_bounds__(64 * NW) void k_mlp_infer(const float* __restrict__
         // dy/dx^T = W1^T delta1^T on (16-input tile, sample block) items taken
         // by the waves in turn, then the chain through the standardisation
         // (only the first d inputs are asked for)
-        const int ft = min((d + 15) / 16, kIn / 16);
         for (int it = wave; it < ft * SB; it += NW) {
             const int f0 = 16 * (it / SB), b = it % SB;
             const int s = 16 * b + col, i = row0 + s;
             bf16x8 aw[K2];
-#pragma unroll
-            for (int k = 0; k < K2; ++k) aw[k] = a_frag(m.W1T, kW, f0, k);
             float xr[4] = {0.f, 0.f, 0.f, 0.f};
-            if (bt.H && i < M)
+            if (it == wave) {
 #pragma unroll
-                for (int t = 0; t < 4; ++t) xr[t] = x_raw(X, x_mode, M, n_in, i, min(f0 + 4 * kq + t, d - 1));
+                for (int k = 0; k < K2; ++k) aw[k] = aw0[k];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) xr[t] = xr0[t];
+            } else {
+#pragma unroll
+                for (int k = 0; k < K2; ++k) aw[k] = a_frag(m.W1T, kW, f0, k);
+                if (bt.H && i < M)
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) xr[t] = x_raw(X, x_mode, M, n_in, i, min(f0 + 4 * kq + t, d - 1));
+            }
             float y = m.b3;
             for (int w = 0; w < NW; ++w) y += sYp[w][s];
             const float ey = expf(y);
