@@ -18,41 +18,60 @@ namespace stamp {
 // Threads of the BF16 form's centre (one workgroup per coordinate).
 constexpr int kCentreThreads = 256;
 
-// Rows row0 .. row0 + 63 of the padded set: thread tid < 64 packs row
-// row0 + tid (the other threads return).  Padding rows (i >= N) hold x^ = 0
-// and e = 0, so every kernel value with them stays finite (and their V rows
-// are zero).  kd >= d + 2.
+// Rows row0 .. row0 + 63 of the padded set, by the 256 threads of a
+// workgroup (tid; every thread must call it, it holds a barrier): a thread per
+// (group of 8 coordinates, row), rows fastest so the loads of a coordinate
+// are contiguous; the groups' partial norms meet in LDS and every row adds
+// its own in group order.  Padding rows (i >= N) hold x^ = 0 and e = 0, so
+// every kernel value with them stays finite (and their V rows are zero).
+// kd >= d + 2, kd <= 96.
 __device__ __forceinline__ void pack16_theta_rows(int N, int d, int kd, int row0, int tid,
                                                   const float* __restrict__ theta, const float* __restrict__ ctr,
                                                   float scale, __bf16* __restrict__ xr, __bf16* __restrict__ xc,
                                                   float* __restrict__ nrm) {
     typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8_t;
-    if (tid >= 64) return;
-    const int i = row0 + tid;
-    auto coord = [&](int l) -> __bf16 {
-        return (__bf16)((i < N && l < d) ? scale * (theta[(int64_t)l * N + i] - ctr[l]) : 0.0f);
-    };
-    float n = 0.0f;
-    for (int l = 0; l < d; ++l) {
-        const float x = (float)coord(l);
-        n = fmaf(x, x, n);
-    }
-    const float e = -0.5f * n;
-    const __bf16 hi = (__bf16)e, lo = (__bf16)(e - (float)hi);
-    const __bf16 one = (__bf16)1.0f;
-    for (int l0 = 0; l0 < kd; l0 += 8) {
-        bf16x8_t a, c;
+    constexpr int kSteps = 3;  // 64 rows x 12 groups at kd = 96, over 256 threads
+    __shared__ float part[12][64];
+    const int groups = kd >> 3;
+    bf16x8_t x8[kSteps];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const int l = l0 + k;
-            const __bf16 x = coord(l);
-            a[k] = l == d ? hi : l == d + 1 ? lo : x;
-            c[k] = (l == d || l == d + 1) ? one : x;
+    for (int k = 0; k < kSteps; ++k) {
+        const int o = tid + 256 * k, r = o & 63, g = o >> 6, i = row0 + r;
+        if (g < groups) {
+            float n = 0.0f;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int l = 8 * g + u;
+                x8[k][u] = (__bf16)((i < N && l < d) ? scale * (theta[(int64_t)l * N + i] - ctr[l]) : 0.0f);
+                const float x = (float)x8[k][u];
+                n = fmaf(x, x, n);
+            }
+            part[g][r] = n;
         }
-        *reinterpret_cast<bf16x8_t*>(xr + (int64_t)i * kd + l0) = a;
-        *reinterpret_cast<bf16x8_t*>(xc + (int64_t)i * kd + l0) = c;
     }
-    nrm[i] = e;
+    __syncthreads();
+    const __bf16 one = (__bf16)1.0f;
+#pragma unroll
+    for (int k = 0; k < kSteps; ++k) {
+        const int o = tid + 256 * k, r = o & 63, g = o >> 6, i = row0 + r;
+        if (g < groups) {
+            float n = 0.0f;
+            for (int q = 0; q < groups; ++q) n += part[q][r];
+            const float e = -0.5f * n;
+            const __bf16 hi = (__bf16)e, lo = (__bf16)(e - (float)hi);
+            bf16x8_t a = x8[k], c = x8[k];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int l = 8 * g + u;
+                if (l == d) a[u] = hi;
+                if (l == d + 1) a[u] = lo;
+                if (l == d || l == d + 1) c[u] = one;
+            }
+            *reinterpret_cast<bf16x8_t*>(xr + (int64_t)i * kd + 8 * g) = a;
+            *reinterpret_cast<bf16x8_t*>(xc + (int64_t)i * kd + 8 * g) = c;
+            if (g == 0) nrm[i] = e;
+        }
+    }
 }
 
 }  // namespace stamp
