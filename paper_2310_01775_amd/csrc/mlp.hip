@@ -130,33 +130,52 @@ __device__ __forceinline__ MlpPtrs mlp_ptrs(const float* P, const __bf16* Wb) {
 // Stage this wave's 16 standardised input rows into U (bf16).  Input sample i:
 // x_mode 0: X[src * n_in + f] with src = idx ? idx[i] : i (d unused);
 // x_mode 1: f < d from X[f * M + i] (structure of arrays), f >= d from enc[f - d].
-__device__ __forceinline__ void stage_inputs(__bf16* U, const MlpPtrs& m, const float* __restrict__ X, int x_mode,
-                                             int M, int n_in, int d, const float* __restrict__ enc, int row0,
-                                             const int* __restrict__ src_row = nullptr) {
+// One lane's share of a 16-sample block's standardised inputs, loaded but not
+// yet stored (lane l takes features l / 16 + 4 q of sample l % 16).
+struct StageVals {
+    float xv[kIn / 4], mu[kIn / 4], is[kIn / 4];
+};
+
+__device__ __forceinline__ void stage_load(StageVals& v, const MlpPtrs& m, const float* __restrict__ X, int x_mode,
+                                           int M, int n_in, int d, const float* __restrict__ enc, int row0,
+                                           const int* __restrict__ src_row = nullptr) {
     const int l = threadIdx.x & 63;
     const int r = l & 15;
     const int i = row0 + r;
     const int ic = min(i, M - 1);
     const int64_t src = (src_row && i < M) ? src_row[r] : ic;
     // every load is issued before the first use (addresses clamped into
-    // range, out-of-range values replaced afterwards): global loads complete
+    // range, out-of-range values replaced when stored): global loads complete
     // in order, so a load-use chain per feature would wait once per feature
-    float xv[kIn / 4], mu[kIn / 4], is[kIn / 4];
 #pragma unroll
     for (int q = 0; q < kIn / 4; ++q) {
         const int f = (l >> 4) + 4 * q, fc = min(f, n_in - 1);
         const float* p = x_mode == 0 ? X + src * n_in + fc : (fc < d ? X + (int64_t)fc * M + ic : enc + (fc - d));
-        xv[q] = *p;
-        mu[q] = m.mu[fc];
-        is[q] = m.isig[fc];
+        v.xv[q] = *p;
+        v.mu[q] = m.mu[fc];
+        v.is[q] = m.isig[fc];
     }
+}
+
+__device__ __forceinline__ void stage_store(__bf16* U, const StageVals& v, int M, int n_in, int row0) {
+    const int l = threadIdx.x & 63;
+    const int r = l & 15;
+    const int i = row0 + r;
 #pragma unroll
     for (int q = 0; q < kIn / 4; ++q) {
         const int f = (l >> 4) + 4 * q;
-        const float x = (i < M && f < n_in) ? xv[q] : 0.0f;
-        const float u = f < n_in ? (x - mu[q]) * is[q] : 0.0f;
+        const float x = (i < M && f < n_in) ? v.xv[q] : 0.0f;
+        const float u = f < n_in ? (x - v.mu[q]) * v.is[q] : 0.0f;
         U[r * kLdU + f] = (__bf16)u;
     }
+}
+
+__device__ __forceinline__ void stage_inputs(__bf16* U, const MlpPtrs& m, const float* __restrict__ X, int x_mode,
+                                             int M, int n_in, int d, const float* __restrict__ enc, int row0,
+                                             const int* __restrict__ src_row = nullptr) {
+    StageVals v;
+    stage_load(v, m, X, x_mode, M, n_in, d, enc, row0, src_row);
+    stage_store(U, v, M, n_in, row0);
 }
 
 // Exact bound term of the plan cost, added to the network's prediction of
@@ -256,8 +275,20 @@ __global__ __launch_bounds__(64 * NW) void k_mlp_infer(const float* __restrict__
     const MlpPtrs m = mlp_ptrs(P, Wb);
     const bool want_grad = grad_out != nullptr;
 
-    // this wave's weight fragments of both forward layers, in flight while
-    // the inputs are staged (loads complete in order: layer 1's first)
+    // Loads complete in order, so what the first barrier waits for is issued
+    // first: the inputs (a 16-sample block per wave, NW >= SB) and the
+    // constants; then this wave's weight fragments of both forward layers
+    // (layer 1's first), which stay in flight through the barrier.
+    static_assert(NW >= SB && 64 * NW >= kW, "one input block and one constant per thread at most");
+    StageVals sv;
+    if (wave < SB) stage_load(sv, m, X, x_mode, M, n_in, d, enc, row0 + 16 * wave);
+    float cb1 = 0.f, cb2 = 0.f, cw3 = 0.f, cis = 0.f;
+    if (threadIdx.x < kW) {
+        cb1 = m.b1[threadIdx.x];
+        cb2 = m.b2[threadIdx.x];
+        cw3 = m.w3[threadIdx.x];
+    }
+    if (threadIdx.x < kIn) cis = m.isig[threadIdx.x];
     bf16x8 a1[TN][K1], a2[TN][K2];
 #pragma unroll
     for (int a = 0; a < TN; ++a)
@@ -267,13 +298,13 @@ __global__ __launch_bounds__(64 * NW) void k_mlp_infer(const float* __restrict__
     for (int a = 0; a < TN; ++a)
 #pragma unroll
         for (int k = 0; k < K2; ++k) a2[a][k] = a_frag(m.W2, kW, n0 + 16 * a, k);
-    for (int c = threadIdx.x; c < kW; c += 64 * NW) {
-        sB1[c] = m.b1[c];
-        sB2[c] = m.b2[c];
-        sW3[c] = m.w3[c];
+    if (wave < SB) stage_store(sU + wave * 16 * kLdU, sv, M, n_in, row0 + 16 * wave);
+    if (threadIdx.x < kW) {
+        sB1[threadIdx.x] = cb1;
+        sB2[threadIdx.x] = cb2;
+        sW3[threadIdx.x] = cw3;
     }
-    for (int f = threadIdx.x; f < kIn; f += 64 * NW) sIs[f] = m.isig[f];
-    for (int b = wave; b < SB; b += NW) stage_inputs(sU + b * 16 * kLdU, m, X, x_mode, M, n_in, d, enc, row0 + 16 * b);
+    if (threadIdx.x < kIn) sIs[threadIdx.x] = cis;
     __syncthreads();
 
     // layer 1: z1^T = W1 u^T + b1; h1 to LDS, gelu'(z1) kept
