@@ -42,12 +42,14 @@ hipError_t launch_svgd(int N, int d, const float* theta, const float* grad_logp,
 // mean, centred rows, norms -- which the median's Gram-form passes read).
 hipError_t launch_svgd_bandwidth(int N, int d, const float* theta, float bandwidth, float* h_out, void* ws,
                                  const SvgdLayout& L, hipStream_t st);
+// step (nullable): advanced once by the stage's first launch (only when
+// P.n_ctr > 0: some problem has N >= 2)
 hipError_t launch_svgd_bandwidth_batched(const BatchPlan& P, const ProblemDesc* descs, const float* theta, int exact,
-                                         char* ws, hipStream_t st);
+                                         char* ws, hipStream_t st, int* step = nullptr);
 // particle mean, centred rows and norms (before the median)
 hipError_t launch_operands32(int N, int d, const float* theta, void* ws, const SvgdLayout& L, hipStream_t st);
 hipError_t launch_operands32_batched(const BatchPlan& P, const ProblemDesc* descs, const float* theta, char* ws,
-                                     hipStream_t st);
+                                     hipStream_t st, int* step = nullptr);
 // The step's second half: V = w [g - (2/h) x | 1] packed from theta, the
 // gradient and the weights, then phi from the bandwidth, centre and rows the
 // workspace holds (FP32 matrix cores, phi32.hip).

@@ -268,8 +268,12 @@ __global__ __launch_bounds__(256) void k_reduce32(One32 a, const float* theta, c
 __device__ __forceinline__ char* base32(const ProblemDesc& D, char* ws) { return ws + D.svgd_off; }
 
 // entry = (problem, coordinate, -, -)
+// a non-null step counter is advanced once (a solve's iteration counter, read
+// by the update at the iteration's end)
 __global__ __launch_bounds__(kMeanThreads) void k_mean_batched(const ProblemDesc* __restrict__ descs,
-                                                      const int4* __restrict__ work, const float* theta, char* ws) {
+                                                      const int4* __restrict__ work, const float* theta, char* ws,
+                                                      int* step) {
+    if (step && blockIdx.x == 0 && threadIdx.x == 0) *step += 1;
     const int4 e = work[blockIdx.x];
     const ProblemDesc& D = descs[e.x];
     particle_mean_body(D.N, e.y, theta + D.theta_off, reinterpret_cast<float*>(base32(D, ws) + D.sv.ctr_off));
@@ -380,9 +384,10 @@ hipError_t launch_operands32(int N, int d, const float* theta, void* ws, const S
 }
 
 hipError_t launch_operands32_batched(const BatchPlan& P, const ProblemDesc* descs, const float* theta, char* ws,
-                                     hipStream_t st) {
+                                     hipStream_t st, int* step) {
     if (P.n_ctr)
-        hipLaunchKernelGGL(k_mean_batched, dim3(P.n_ctr), dim3(kMeanThreads), 0, st, descs, P.ctr_work, theta, ws);
+        hipLaunchKernelGGL(k_mean_batched, dim3(P.n_ctr), dim3(kMeanThreads), 0, st, descs, P.ctr_work, theta, ws,
+                           step);
     if (P.n_row16)
         hipLaunchKernelGGL(k_pack32_x_batched, dim3(4 * P.n_row16), dim3(256), 0, st, descs, P.row16_work, theta, ws);
     return hipGetLastError();

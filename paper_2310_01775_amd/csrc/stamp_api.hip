@@ -1141,8 +1141,8 @@ static int32_t solve_impl(stamp_ctx* ctx, int32_t n_problems, const stamp_scene*
     // structured kernel's features) depends on theta only, so it runs on the
     // side stream while the rollout produces the gradient; the direction stage
     // joins it.  exact = 0: the BF16 form's sampled median.
-    auto bandwidth_stage = [&](hipStream_t s, int exact) -> hipError_t {
-        if (skern.empty()) return launch_svgd_bandwidth_batched(B, d_desc, theta, exact, d_svgd, s);
+    auto bandwidth_stage = [&](hipStream_t s, int exact, int* step = nullptr) -> hipError_t {
+        if (skern.empty()) return launch_svgd_bandwidth_batched(B, d_desc, theta, exact, d_svgd, s, step);
         for (int p = 0; p < n_problems; ++p) {
             const ProblemDesc& D = P.descs[p];
             hipError_t r = launch_struct_bandwidth(D.N, theta + D.theta_off, skern[p], d_svgd + D.svgd_off, D.sv, s);
@@ -1156,15 +1156,15 @@ static int32_t solve_impl(stamp_ctx* ctx, int32_t n_problems, const stamp_scene*
     // creates takes one of its few hardware queues, and two streams sharing a
     // queue run one after the other.
     auto fork_at = [&]() -> hipError_t { return hipEventRecord(ctx->ev_fork, st); };
-    auto branch = [&](int exact) -> hipError_t {
+    auto branch = [&](int exact, int* step = nullptr) -> hipError_t {
         hipError_t r;
         if ((r = hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0)) != hipSuccess) return r;
-        if ((r = bandwidth_stage(ctx->side, exact)) != hipSuccess) return r;
+        if ((r = bandwidth_stage(ctx->side, exact, step)) != hipSuccess) return r;
         return hipEventRecord(ctx->ev_join, ctx->side);
     };
-    auto fork = [&](int exact) -> hipError_t {
+    auto fork = [&](int exact, int* step = nullptr) -> hipError_t {
         hipError_t r = fork_at();
-        return r == hipSuccess ? branch(exact) : r;
+        return r == hipSuccess ? branch(exact, step) : r;
     };
     auto join = [&]() -> hipError_t { return hipStreamWaitEvent(st, ctx->ev_join, 0); };
     const UpdateArgs upd{theta, adam_m, adam_v, cfg->t0, d_ctr, cfg->lr, cfg->beta1, cfg->beta2, cfg->adam_eps,
@@ -1182,17 +1182,24 @@ static int32_t solve_impl(stamp_ctx* ctx, int32_t n_problems, const stamp_scene*
     };
     // the direction and the update in one pass (the FP32 form's reduce
     // applies the update), or the direction then the update
-    auto direction_update_stage = [&](const float* wts) -> hipError_t {
+    auto direction_update_stage = [&](const float* wts, const UpdateArgs& u) -> hipError_t {
         if (skern.empty())
-            return launch_svgd_direction_batched(B, d_desc, theta, d_grad, nullptr, d_svgd, status, st, wts, &upd);
+            return launch_svgd_direction_batched(B, d_desc, theta, d_grad, nullptr, d_svgd, status, st, wts, &u);
         hipError_t r = direction_stage(wts);
         if (r != hipSuccess) return r;
         return launch_update(P.n_theta, theta, d_phi, adam_m, adam_v, cfg->t0, d_ctr, cfg->lr, cfg->beta1,
                              cfg->beta2, cfg->adam_eps, cfg->use_adam, st);
     };
+    // the bandwidth stage's first launch advances the step counter when it
+    // has one (the particle mean of some problem with N >= 2): the update
+    // then reads the counter already advanced, and no counter kernel ends the
+    // iteration
+    const bool ctr_in_mean = skern.empty() && B.n_ctr > 0;
+    UpdateArgs upd_pre = upd;
+    upd_pre.t_pre = 1;
     auto iteration = [&]() -> hipError_t {
         hipError_t r;
-        if ((r = fork(1)) != hipSuccess) return r;
+        if ((r = fork(1, ctr_in_mean ? d_ctr : nullptr)) != hipSuccess) return r;
         if ((r = roll_fwd(theta, (float*)(ws + P.cost_off), d_tape, status)) != hipSuccess) return r;
         if ((r = roll_adj(status)) != hipSuccess) return r;
         if (cfg->dsvgd) {
@@ -1207,7 +1214,8 @@ static int32_t solve_impl(stamp_ctx* ctx, int32_t n_problems, const stamp_scene*
                 return r;
         }
         if ((r = join()) != hipSuccess) return r;
-        if ((r = direction_update_stage(cfg->dsvgd ? d_wts : nullptr)) != hipSuccess) return r;
+        if (ctr_in_mean) return direction_update_stage(cfg->dsvgd ? d_wts : nullptr, upd_pre);
+        if ((r = direction_update_stage(cfg->dsvgd ? d_wts : nullptr, upd)) != hipSuccess) return r;
         return launch_incr(d_ctr, st);
     };
     // one SGD refinement iteration: the update takes phi = grad log rho
@@ -1265,7 +1273,7 @@ static int32_t solve_impl(stamp_ctx* ctx, int32_t n_problems, const stamp_scene*
             if ((r = launch_svgd16_direction_batched(B, d_desc, theta, d_grad, nullptr, d_svgd, status, st, &upd)) !=
                 hipSuccess)
                 return r;
-        } else if ((r = direction_update_stage(nullptr)) != hipSuccess) {
+        } else if ((r = direction_update_stage(nullptr, upd)) != hipSuccess) {
             return r;
         }
         return launch_incr(d_ctr, st);

@@ -273,12 +273,12 @@ hipError_t launch_svgd_batched(const BatchPlan& P, const ProblemDesc* descs, con
 }
 
 hipError_t launch_svgd_bandwidth_batched(const BatchPlan& P, const ProblemDesc* descs, const float* theta, int exact,
-                                         char* ws, hipStream_t st) {
+                                         char* ws, hipStream_t st, int* step) {
     // the theta-only operands of the FP32 form (exact median, whose all-pairs
     // passes read them) or of the BF16 form (sampled median)
-    if (!exact) return launch_bandwidth16_batched(P, descs, theta, ws, st);
+    if (!exact) return launch_bandwidth16_batched(P, descs, theta, ws, st, step);
     hipError_t e;
-    if ((e = launch_operands32_batched(P, descs, theta, ws, st)) != hipSuccess) return e;
+    if ((e = launch_operands32_batched(P, descs, theta, ws, st, step)) != hipSuccess) return e;
     return launch_median_batched(P, descs, theta, 1, ws, st);
 }
 
