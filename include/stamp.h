@@ -291,9 +291,10 @@ int32_t stamp_svgd_update(stamp_ctx* ctx, int32_t N, int32_t d, float* theta, co
  * surrogate phase).  Differences from stamp_svgd_step:
  *   - the median heuristic uses a fixed sample of 8192 particle pairs (all
  *     pairs when N(N-1)/2 <= 8192, then it is exact), distances in FP32;
- *   - the particles are centred on their mean and rounded to BF16; distances
- *     come from the Gram form |x~_i|^2 + |x~_j|^2 - 2 x~_i.x~_j (MFMA, FP32
- *     accumulation), clamped at 0;
+ *   - the particles are centred on their mean, scaled by sqrt(2 log2(e) / h)
+ *     and rounded to BF16 (x^); log2 K_ij comes from the Gram form
+ *     x^_i.x^_j - |x^_i|^2/2 - |x^_j|^2/2 (MFMA, FP32 accumulation), so the
+ *     distance is clamped at 0 by clamping K_ij to [0, 1];
  *   - K_ij is rounded to BF16 and K V, V_j = [g_j - (2/h) x_j | 1] rounded to
  *     BF16 (x_j the centred FP32 particle), is accumulated on MFMA in FP32;
  *     phi_i = (K V)_i[0..d) + (2/h) x_i (K V)_i[d], over N.

@@ -114,7 +114,7 @@ struct SvgdLayout {
     size_t nrm_off;                 // npad floats: e_i = -|x^_i|^2 / 2
     size_t xb_off;                  // npad x kd bf16: scaled centred rows [x^ | e hi | e lo | 0], the Gram's row operand
     size_t xc_off;                  // npad x kd bf16: the same rows as [x^ | 1 | 1 | 0], its column operand
-    size_t vt_off;                  // vc x npad bf16: V = [g | x~ | 1 | 0], chunked
+    size_t vt_off;                  // vc x npad bf16: V = [g - (2/h) x | 1 | 0], chunked
     size_t p16_off;                 // splits16 x vc x npad floats: partial sums
     // structured kernel: per-particle features (at most 2d rows of N floats)
     // and the selection state of its second median

@@ -101,13 +101,13 @@ hipError_t launch_svgd16(int N, int d, const float* theta, const float* grad, fl
                          float* h_out, void* ws, const SvgdLayout& L, uint32_t* status, hipStream_t st);
 hipError_t launch_svgd16_batched(const BatchPlan& P, const ProblemDesc* descs, const float* theta, const float* grad,
                                  float* phi, char* ws, uint32_t* status, hipStream_t st);
-// its theta-only operands (particle mean, centred BF16 rows, their norms),
-// built with the sampled median, and its second half (V, the contraction,
-// the reduce; upd as for the FP32 form)
+// its theta-only operand (the particle mean), built with the sampled median,
+// and its second half (the scaled BF16 rows and V, which need h, the
+// contraction, the reduce; upd as for the FP32 form)
 hipError_t launch_operands16(int N, int d, const float* theta, void* ws, const SvgdLayout& L, hipStream_t st);
-// the sampled median and those operands for a batch, in two fused launches
-// (sample distances with the centres, then the sample select with the rows);
-// a non-null step counter is advanced by one on the way
+// the sampled median and the centres for a batch, in two launches (sample
+// distances with the centres, then the sample select); a non-null step
+// counter is advanced by one on the way
 hipError_t launch_bandwidth16_batched(const BatchPlan& P, const ProblemDesc* descs, const float* theta, char* ws,
                                       hipStream_t st, int* step = nullptr);
 hipError_t launch_svgd16_direction(int N, int d, const float* theta, const float* grad, float* phi, void* ws,
