@@ -78,11 +78,13 @@ def test_direction_matches_oracle_at_the_same_bandwidth(ctx, N, d, bw):
     assert np.isfinite(got).all()
 
 
-def test_surrogate_solve_with_the_bf16_direction_equals_its_loop(ctx):
+@pytest.mark.parametrize("sizes,dmax", [([(300, 3, 2), (64, 5, 1)], 30),   # Gram width 32
+                                        ([(200, 6, 2), (70, 6, 1)], 36)])  # Gram width 64
+def test_surrogate_solve_with_the_bf16_direction_equals_its_loop(ctx, sizes, dmax):
     import paper_2310_01775_amd as S
     from tests.test_gpu_surrogate import _batch, _enc, _network, _dev
-    probs = _batch(S, [(300, 3, 2), (64, 5, 1)], 4)
-    n_in = 30 + W.SCENE_ENC
+    probs = _batch(S, sizes, 4)
+    n_in = dmax + W.SCENE_ENC
     P, Wb = _network(ctx, S, n_in, 8)
     flat = torch.cat([S.soa(th).reshape(-1) for _, _, th, _ in probs]).contiguous()
     enc = _dev(np.concatenate([_enc(e, n_in, 6 * s["H"]) for s, _, _, e in probs]))
