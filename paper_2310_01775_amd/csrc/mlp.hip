@@ -68,19 +68,26 @@ __device__ __forceinline__ float gelu_grad(float z) {
     return gp;
 }
 
-// acc += A (16 rows x K, LDS, row stride lda) * B where B[k][n] = Bt[n][k]
-// (global, rows of ldb bf16); the 16 B columns start at Bt row n0.
-__device__ __forceinline__ f4 mma_rows(const __bf16* A, int lda, const __bf16* __restrict__ Bt, int ldb, int n0,
-                                       int K, f4 acc) {
+
+// For acc += A B with A 16 rows x K (LDS, row stride lda) and B[k][n] =
+// Bt[n][k] (global, rows of ldb bf16): the B fragments of the 16 columns that
+// start at Bt row n0, every k-step of K, loaded ahead of their products.
+template <int K>
+__device__ __forceinline__ void load_wfrag(bf16x8 (&w)[K / 32], const __bf16* __restrict__ Bt, int ldb, int n0) {
     const int l = threadIdx.x & 63;
-    const int r = l & 15, kq = l >> 4;
-    const __bf16* a = A + r * lda + 8 * kq;
-    const __bf16* b = Bt + (int64_t)(n0 + r) * ldb + 8 * kq;
-    for (int k0 = 0; k0 < K; k0 += 32) {
-        const bf16x8 av = *reinterpret_cast<const bf16x8*>(a + k0);
-        const bf16x8 bv = *reinterpret_cast<const bf16x8*>(b + k0);
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc, 0, 0, 0);
-    }
+    const __bf16* b = Bt + (int64_t)(n0 + (l & 15)) * ldb + 8 * (l >> 4);
+#pragma unroll
+    for (int k = 0; k < K / 32; ++k) w[k] = *reinterpret_cast<const bf16x8*>(b + 32 * k);
+}
+
+// The product itself, k-steps in order, from the fragments in registers.
+template <int K>
+__device__ __forceinline__ f4 mma_rows_w(const __bf16* A, int lda, const bf16x8 (&w)[K / 32], f4 acc) {
+    const int l = threadIdx.x & 63;
+    const __bf16* a = A + (l & 15) * lda + 8 * (l >> 4);
+#pragma unroll
+    for (int k = 0; k < K / 32; ++k)
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(*reinterpret_cast<const bf16x8*>(a + 32 * k), w[k], acc, 0, 0, 0);
     return acc;
 }
 
@@ -528,29 +535,57 @@ __global__ __launch_bounds__(256) void k_mlp_train_fb(const float* __restrict__ 
     __syncthreads();
     // U^T for dW1
     for (int f = kq; f < kIn; f += 4) UT[(int64_t)f * M + row0 + col] = U[col * kLdU + f];
-    for (int cb = 0; cb < kW / 16; ++cb) {
-        f4 acc = {0.f, 0.f, 0.f, 0.f};
-        acc = mma_rows(U, kLdU, m.W1, kIn, cb * 16, kIn, acc);
-        const int c = cb * 16 + col;
-        for (int j = 0; j < 4; ++j) {
-            const __bf16 h = (__bf16)gelu(acc[j] + m.b1[c]);
-            Hb[(4 * kq + j) * kLdH + c] = h;
-            H1T[(int64_t)c * M + row0 + 4 * kq + j] = h;
+    // every column block's weight fragments and constants load while the
+    // previous block computes (a load-use chain per block would wait once per
+    // block); the products keep their order
+    {
+        bf16x8 w0[kIn / 32], w1[kIn / 32];
+        float bb0 = m.b1[col], bb1 = 0.0f;
+        load_wfrag<kIn>(w0, m.W1, kIn, 0);
+#pragma unroll
+        for (int cb = 0; cb < kW / 16; ++cb) {
+            if (cb + 1 < kW / 16) {
+                load_wfrag<kIn>(w1, m.W1, kIn, (cb + 1) * 16);
+                bb1 = m.b1[(cb + 1) * 16 + col];
+            }
+            const f4 acc = mma_rows_w<kIn>(U, kLdU, w0, f4{0.f, 0.f, 0.f, 0.f});
+            const int c = cb * 16 + col;
+            for (int j = 0; j < 4; ++j) {
+                const __bf16 h = (__bf16)gelu(acc[j] + bb0);
+                Hb[(4 * kq + j) * kLdH + c] = h;
+                H1T[(int64_t)c * M + row0 + 4 * kq + j] = h;
+            }
+#pragma unroll
+            for (int k = 0; k < kIn / 32; ++k) w0[k] = w1[k];
+            bb0 = bb1;
         }
     }
     __syncthreads();
     f4 z2[kW / 16];
+    float w3v[kW / 16];  // w3 of the lane's column in every block, for delta2
     float yp[4] = {0.f, 0.f, 0.f, 0.f};
+    {
+        bf16x8 v0[kW / 32], v1[kW / 32];
+        float b20 = m.b2[col], b21 = 0.0f;
+        w3v[0] = m.w3[col];
+        load_wfrag<kW>(v0, m.W2, kW, 0);
 #pragma unroll
-    for (int cb = 0; cb < kW / 16; ++cb) {
-        f4 acc = {0.f, 0.f, 0.f, 0.f};
-        acc = mma_rows(Hb, kLdH, m.W2, kW, cb * 16, kW, acc);
-        const int c = cb * 16 + col;
-        for (int j = 0; j < 4; ++j) {
-            acc[j] += m.b2[c];
-            yp[j] += m.w3[c] * gelu(acc[j]);
+        for (int cb = 0; cb < kW / 16; ++cb) {
+            if (cb + 1 < kW / 16) {
+                load_wfrag<kW>(v1, m.W2, kW, (cb + 1) * 16);
+                b21 = m.b2[(cb + 1) * 16 + col];
+                w3v[cb + 1] = m.w3[(cb + 1) * 16 + col];
+            }
+            f4 acc = mma_rows_w<kW>(Hb, kLdH, v0, f4{0.f, 0.f, 0.f, 0.f});
+            for (int j = 0; j < 4; ++j) {
+                acc[j] += b20;
+                yp[j] += w3v[cb] * gelu(acc[j]);
+            }
+            z2[cb] = acc;
+#pragma unroll
+            for (int k = 0; k < kW / 32; ++k) v0[k] = v1[k];
+            b20 = b21;
         }
-        z2[cb] = acc;
     }
     // delta3 = dL/dy = 2 (y - t) / M
     float d3[4];
@@ -567,7 +602,7 @@ __global__ __launch_bounds__(256) void k_mlp_train_fb(const float* __restrict__ 
         const int c = cb * 16 + col;
         float s2 = 0.0f, s3 = 0.0f;
         for (int j = 0; j < 4; ++j) {
-            const float dz = d3[j] * m.w3[c] * gelu_grad(z2[cb][j]);
+            const float dz = d3[j] * w3v[cb] * gelu_grad(z2[cb][j]);
             const __bf16 db = (__bf16)dz;
             Db[(4 * kq + j) * kLdH + c] = db;
             D2T[(int64_t)c * M + row0 + 4 * kq + j] = db;
@@ -591,21 +626,36 @@ __global__ __launch_bounds__(256) void k_mlp_train_fb(const float* __restrict__ 
         }
     }
     __syncthreads();
-    // delta1 = (delta2 W2) gelu'(z1)
-    for (int kb = 0; kb < kW / 16; ++kb) {
-        f4 t = {0.f, 0.f, 0.f, 0.f};
-        t = mma_rows(Db, kLdH, m.W2T, kW, kb * 16, kW, t);
-        f4 z1 = {0.f, 0.f, 0.f, 0.f};
-        z1 = mma_rows(U, kLdU, m.W1, kIn, kb * 16, kIn, z1);
-        const int k = kb * 16 + col;
-        float s1 = 0.0f;
-        for (int j = 0; j < 4; ++j) {
-            const float dz = t[j] * gelu_grad(z1[j] + m.b1[k]);
-            D1T[(int64_t)k * M + row0 + 4 * kq + j] = (__bf16)dz;
-            s1 += dz;
+    // delta1 = (delta2 W2) gelu'(z1), the next block's fragments in flight
+    {
+        bf16x8 t0[kW / 32], t1[kW / 32], u0[kIn / 32], u1[kIn / 32];
+        float bb0 = m.b1[col], bb1 = 0.0f;
+        load_wfrag<kW>(t0, m.W2T, kW, 0);
+        load_wfrag<kIn>(u0, m.W1, kIn, 0);
+#pragma unroll
+        for (int kb = 0; kb < kW / 16; ++kb) {
+            if (kb + 1 < kW / 16) {
+                load_wfrag<kW>(t1, m.W2T, kW, (kb + 1) * 16);
+                load_wfrag<kIn>(u1, m.W1, kIn, (kb + 1) * 16);
+                bb1 = m.b1[(kb + 1) * 16 + col];
+            }
+            const f4 t = mma_rows_w<kW>(Db, kLdH, t0, f4{0.f, 0.f, 0.f, 0.f});
+            const f4 z1 = mma_rows_w<kIn>(U, kLdU, u0, f4{0.f, 0.f, 0.f, 0.f});
+            const int k = kb * 16 + col;
+            float s1 = 0.0f;
+            for (int j = 0; j < 4; ++j) {
+                const float dz = t[j] * gelu_grad(z1[j] + bb0);
+                D1T[(int64_t)k * M + row0 + 4 * kq + j] = (__bf16)dz;
+                s1 += dz;
+            }
+            s1 = sum_groups(s1);
+            if (kq == 0) red[k] = s1;
+#pragma unroll
+            for (int q = 0; q < kW / 32; ++q) t0[q] = t1[q];
+#pragma unroll
+            for (int q = 0; q < kIn / 32; ++q) u0[q] = u1[q];
+            bb0 = bb1;
         }
-        s1 = sum_groups(s1);
-        if (kq == 0) red[k] = s1;
     }
     __syncthreads();
     // per-tile partial sums: the four waves in a fixed order
