@@ -35,7 +35,7 @@ typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f4;
 
 constexpr int kIn = kMlpIn;    // padded input width
 constexpr int kW = kMlpWidth;  // hidden width
-constexpr int kRows = 64;      // samples per workgroup
+constexpr int kTrainRows = 16;  // samples per training workgroup (one partial-sum tile)
 constexpr int kLdU = kIn + 8;  // LDS row strides (bf16), padded against bank conflicts
 constexpr int kLdH = kW + 8;
 
@@ -498,6 +498,10 @@ constexpr int kInfRows = 16 * kInfBlocks;
 // sample i is dataset row src = idx ? idx[i] : i of X [n_rows][n_in], its
 // target log(1 + cost[src]).  An index outside [0, n_rows) reads row 0 and
 // sets STAMP_STATUS_BAD_INDEX.
+// A workgroup of four waves takes kTrainRows = 16 samples and each wave 64 of
+// every layer's 256 neurons (four 16-neuron blocks), the activations passing
+// between the waves through LDS; every block's weight fragments load while
+// the previous block computes.
 // Writes feature-major BF16 activations for the weight gradients and per-tile
 // partial sums: part[tile][0..255] = sum delta1, [256..511] = sum delta2,
 // [512..767] = sum delta3 * h2, [768] = sum delta3, [769] = sum (y - t)^2 / M.
@@ -507,163 +511,162 @@ __global__ __launch_bounds__(256) void k_mlp_train_fb(const float* __restrict__ 
                                                       uint32_t* __restrict__ status, __bf16* __restrict__ UT,
                                                       __bf16* __restrict__ H1T, __bf16* __restrict__ D2T,
                                                       __bf16* __restrict__ D1T, float* __restrict__ part) {
-    __shared__ __bf16 sU[4][16 * kLdU];
-    __shared__ __bf16 sH[4][16 * kLdH];
-    __shared__ __bf16 sD[4][16 * kLdH];
-    __shared__ float sRed[4][kMlpPartStride];
-    __shared__ int sSrc[4][16];
-    const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
+    static_assert(kTrainRows == 16, "one 16-row block per workgroup");
+    constexpr int NB = kW / 16 / 4;  // 16-neuron blocks per wave
+    __shared__ __bf16 sU[16 * kLdU];
+    __shared__ __bf16 sH[16 * kLdH];
+    __shared__ __bf16 sD[16 * kLdH];
+    __shared__ float sRed[kMlpPartStride];
+    __shared__ float sY[4][16];
+    __shared__ int sSrc[16];
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), l = threadIdx.x & 63;
     const int kq = l >> 4, col = l & 15;
-    const int row0 = blockIdx.x * kRows + wave * 16;
-    __bf16* U = sU[wave];
-    __bf16* Hb = sH[wave];
-    __bf16* Db = sD[wave];
-    float* red = sRed[wave];
+    const int row0 = blockIdx.x * kTrainRows;
+    const int nb0 = wave * NB;  // the wave's first neuron block
     const MlpPtrs m = mlp_ptrs(P, Wb);
     const float inv_m = 1.0f / (float)M;
 
-    if (l < 16) {
-        int src = idx ? idx[row0 + l] : row0 + l;
+    if (threadIdx.x < 16) {
+        int src = idx ? idx[row0 + threadIdx.x] : row0 + threadIdx.x;
         if (src < 0 || src >= n_rows) {
             if (status) atomicOr(status, (uint32_t)STAMP_STATUS_BAD_INDEX);
             src = 0;
         }
-        sSrc[wave][l] = src;
+        sSrc[threadIdx.x] = src;
     }
     __syncthreads();
-    stage_inputs(U, m, X, 0, M, n_in, 0, nullptr, row0, sSrc[wave]);
+    if (wave == 0) stage_inputs(sU, m, X, 0, M, n_in, 0, nullptr, row0, sSrc);
     __syncthreads();
     // U^T for dW1
-    for (int f = kq; f < kIn; f += 4) UT[(int64_t)f * M + row0 + col] = U[col * kLdU + f];
-    // every column block's weight fragments and constants load while the
-    // previous block computes (a load-use chain per block would wait once per
-    // block); the products keep their order
+    for (int e = threadIdx.x; e < kIn * 16; e += 256) {
+        const int f = e >> 4, r = e & 15;
+        UT[(int64_t)f * M + row0 + r] = sU[r * kLdU + f];
+    }
+    // layer 1 on the wave's neurons: z1 kept for delta1, h1 to LDS
+    f4 z1[NB];
+    float b1v[NB];
     {
         bf16x8 w0[kIn / 32], w1[kIn / 32];
-        float bb0 = m.b1[col], bb1 = 0.0f;
-        load_wfrag<kIn>(w0, m.W1, kIn, 0);
+        b1v[0] = m.b1[nb0 * 16 + col];
+        load_wfrag<kIn>(w0, m.W1, kIn, nb0 * 16);
 #pragma unroll
-        for (int cb = 0; cb < kW / 16; ++cb) {
-            if (cb + 1 < kW / 16) {
+        for (int a = 0; a < NB; ++a) {
+            const int cb = nb0 + a;
+            if (a + 1 < NB) {
                 load_wfrag<kIn>(w1, m.W1, kIn, (cb + 1) * 16);
-                bb1 = m.b1[(cb + 1) * 16 + col];
+                b1v[a + 1] = m.b1[(cb + 1) * 16 + col];
             }
-            const f4 acc = mma_rows_w<kIn>(U, kLdU, w0, f4{0.f, 0.f, 0.f, 0.f});
+            z1[a] = mma_rows_w<kIn>(sU, kLdU, w0, f4{0.f, 0.f, 0.f, 0.f});
             const int c = cb * 16 + col;
             for (int j = 0; j < 4; ++j) {
-                const __bf16 h = (__bf16)gelu(acc[j] + bb0);
-                Hb[(4 * kq + j) * kLdH + c] = h;
+                const __bf16 h = (__bf16)gelu(z1[a][j] + b1v[a]);
+                sH[(4 * kq + j) * kLdH + c] = h;
                 H1T[(int64_t)c * M + row0 + 4 * kq + j] = h;
             }
 #pragma unroll
             for (int k = 0; k < kIn / 32; ++k) w0[k] = w1[k];
-            bb0 = bb1;
         }
     }
     __syncthreads();
-    f4 z2[kW / 16];
-    float w3v[kW / 16];  // w3 of the lane's column in every block, for delta2
+    // layer 2 on the wave's neurons and their part of y
+    f4 z2[NB];
+    float w3v[NB];
     float yp[4] = {0.f, 0.f, 0.f, 0.f};
     {
         bf16x8 v0[kW / 32], v1[kW / 32];
-        float b20 = m.b2[col], b21 = 0.0f;
-        w3v[0] = m.w3[col];
-        load_wfrag<kW>(v0, m.W2, kW, 0);
+        float b20 = m.b2[nb0 * 16 + col], b21 = 0.0f;
+        w3v[0] = m.w3[nb0 * 16 + col];
+        load_wfrag<kW>(v0, m.W2, kW, nb0 * 16);
 #pragma unroll
-        for (int cb = 0; cb < kW / 16; ++cb) {
-            if (cb + 1 < kW / 16) {
+        for (int a = 0; a < NB; ++a) {
+            const int cb = nb0 + a;
+            if (a + 1 < NB) {
                 load_wfrag<kW>(v1, m.W2, kW, (cb + 1) * 16);
                 b21 = m.b2[(cb + 1) * 16 + col];
-                w3v[cb + 1] = m.w3[(cb + 1) * 16 + col];
+                w3v[a + 1] = m.w3[(cb + 1) * 16 + col];
             }
-            f4 acc = mma_rows_w<kW>(Hb, kLdH, v0, f4{0.f, 0.f, 0.f, 0.f});
+            f4 acc = mma_rows_w<kW>(sH, kLdH, v0, f4{0.f, 0.f, 0.f, 0.f});
             for (int j = 0; j < 4; ++j) {
                 acc[j] += b20;
-                yp[j] += w3v[cb] * gelu(acc[j]);
+                yp[j] += w3v[a] * gelu(acc[j]);
             }
-            z2[cb] = acc;
+            z2[a] = acc;
 #pragma unroll
             for (int k = 0; k < kW / 32; ++k) v0[k] = v1[k];
             b20 = b21;
         }
     }
-    // delta3 = dL/dy = 2 (y - t) / M
+    for (int j = 0; j < 4; ++j) {
+        const float v = sum16(yp[j]);
+        if (col == 0) sY[wave][4 * kq + j] = v;
+    }
+    __syncthreads();
+    // delta3 = dL/dy = 2 (y - t) / M, y from the waves' parts in wave order
     float d3[4];
     float lsum = 0.0f;
     for (int j = 0; j < 4; ++j) {
-        const float y = sum16(yp[j]) + m.b3;
-        const float e = y - log1pf(cost[sSrc[wave][4 * kq + j]]);
+        const int r = 4 * kq + j;
+        const float y = (((sY[0][r] + sY[1][r]) + sY[2][r]) + sY[3][r]) + m.b3;
+        const float e = y - log1pf(cost[sSrc[r]]);
         d3[j] = 2.0f * e * inv_m;
         lsum += e * e * inv_m;
     }
-    // delta2 = delta3 w3 gelu'(z2); partial sums of delta2 and delta3 h2
+    // delta2 = delta3 w3 gelu'(z2) on the wave's neurons; partial sums of
+    // delta2 and delta3 h2
 #pragma unroll
-    for (int cb = 0; cb < kW / 16; ++cb) {
-        const int c = cb * 16 + col;
+    for (int a = 0; a < NB; ++a) {
+        const int c = (nb0 + a) * 16 + col;
         float s2 = 0.0f, s3 = 0.0f;
         for (int j = 0; j < 4; ++j) {
-            const float dz = d3[j] * w3v[cb] * gelu_grad(z2[cb][j]);
+            const float dz = d3[j] * w3v[a] * gelu_grad(z2[a][j]);
             const __bf16 db = (__bf16)dz;
-            Db[(4 * kq + j) * kLdH + c] = db;
+            sD[(4 * kq + j) * kLdH + c] = db;
             D2T[(int64_t)c * M + row0 + 4 * kq + j] = db;
             s2 += dz;
-            s3 += d3[j] * gelu(z2[cb][j]);
+            s3 += d3[j] * gelu(z2[a][j]);
         }
         s2 = sum_groups(s2);
         s3 = sum_groups(s3);
         if (kq == 0) {
-            red[256 + c] = s2;
-            red[512 + c] = s3;
+            sRed[256 + c] = s2;
+            sRed[512 + c] = s3;
         }
     }
-    {
+    if (wave == 0) {
         float s = d3[0] + d3[1] + d3[2] + d3[3];
         s = sum_groups(s);
-        float ls = sum_groups(lsum);
+        const float ls = sum_groups(lsum);
         if (l == 0) {
-            red[768] = s;
-            red[769] = ls;
+            sRed[768] = s;
+            sRed[769] = ls;
         }
     }
     __syncthreads();
-    // delta1 = (delta2 W2) gelu'(z1), the next block's fragments in flight
+    // delta1 = (delta2 W2) gelu'(z1) on the wave's neurons
     {
-        bf16x8 t0[kW / 32], t1[kW / 32], u0[kIn / 32], u1[kIn / 32];
-        float bb0 = m.b1[col], bb1 = 0.0f;
-        load_wfrag<kW>(t0, m.W2T, kW, 0);
-        load_wfrag<kIn>(u0, m.W1, kIn, 0);
+        bf16x8 t0[kW / 32], t1[kW / 32];
+        load_wfrag<kW>(t0, m.W2T, kW, nb0 * 16);
 #pragma unroll
-        for (int kb = 0; kb < kW / 16; ++kb) {
-            if (kb + 1 < kW / 16) {
-                load_wfrag<kW>(t1, m.W2T, kW, (kb + 1) * 16);
-                load_wfrag<kIn>(u1, m.W1, kIn, (kb + 1) * 16);
-                bb1 = m.b1[(kb + 1) * 16 + col];
-            }
-            const f4 t = mma_rows_w<kW>(Db, kLdH, t0, f4{0.f, 0.f, 0.f, 0.f});
-            const f4 z1 = mma_rows_w<kIn>(U, kLdU, u0, f4{0.f, 0.f, 0.f, 0.f});
+        for (int a = 0; a < NB; ++a) {
+            const int kb = nb0 + a;
+            if (a + 1 < NB) load_wfrag<kW>(t1, m.W2T, kW, (kb + 1) * 16);
+            const f4 t = mma_rows_w<kW>(sD, kLdH, t0, f4{0.f, 0.f, 0.f, 0.f});
             const int k = kb * 16 + col;
             float s1 = 0.0f;
             for (int j = 0; j < 4; ++j) {
-                const float dz = t[j] * gelu_grad(z1[j] + bb0);
+                const float dz = t[j] * gelu_grad(z1[a][j] + b1v[a]);
                 D1T[(int64_t)k * M + row0 + 4 * kq + j] = (__bf16)dz;
                 s1 += dz;
             }
             s1 = sum_groups(s1);
-            if (kq == 0) red[k] = s1;
+            if (kq == 0) sRed[k] = s1;
 #pragma unroll
             for (int q = 0; q < kW / 32; ++q) t0[q] = t1[q];
-#pragma unroll
-            for (int q = 0; q < kIn / 32; ++q) u0[q] = u1[q];
-            bb0 = bb1;
         }
     }
     __syncthreads();
-    // per-tile partial sums: the four waves in a fixed order
-    for (int e = threadIdx.x; e < kMlpPartStride; e += 256) {
-        float s = 0.0f;
-        if (e < 770) s = ((sRed[0][e] + sRed[1][e]) + sRed[2][e]) + sRed[3][e];
-        part[(int64_t)blockIdx.x * kMlpPartStride + e] = s;
-    }
+    for (int e = threadIdx.x; e < kMlpPartStride; e += 256)
+        part[(int64_t)blockIdx.x * kMlpPartStride + e] = e < 770 ? sRed[e] : 0.0f;
 }
 
 // Weight-gradient partials of a minibatch split in `splits` sample ranges:
@@ -718,7 +721,7 @@ __host__ __device__ __forceinline__ int wgrad_splits(int M) {
 
 // Adam on the trained tensors (FP32 master weights): the weight gradients add
 // their sample ranges in range order, the bias and output-weight gradients
-// the training workgroups' partial sums in workgroup order (eight loads in
+// the training workgroups' partial sums in workgroup order (32 loads in
 // flight).  Element 0 (mu, not trained) writes the loss instead when asked.
 __global__ __launch_bounds__(256) void k_mlp_adam(float* __restrict__ P, float* __restrict__ mom,
                                                   float* __restrict__ vel, const float* __restrict__ dW1,
@@ -729,13 +732,14 @@ __global__ __launch_bounds__(256) void k_mlp_adam(float* __restrict__ P, float* 
     if (e >= kMlpParams) return;
     // the range sum (stride bytes between ranges) or the workgroup sum
     auto sum = [&](const float* base, int64_t stride, int n) {
+        constexpr int F = 32;  // loads in flight (the 16-row tiles of a large batch are many)
         float g = 0.0f;
-        for (int q0 = 0; q0 < n; q0 += 8) {
-            float u[8];
+        for (int q0 = 0; q0 < n; q0 += F) {
+            float u[F];
 #pragma unroll
-            for (int k = 0; k < 8; ++k) u[k] = base[(int64_t)min(q0 + k, n - 1) * stride];
+            for (int k = 0; k < F; ++k) u[k] = base[(int64_t)min(q0 + k, n - 1) * stride];
 #pragma unroll
-            for (int k = 0; k < 8; ++k)
+            for (int k = 0; k < F; ++k)
                 if (q0 + k < n) g += u[k];
         }
         return g;
@@ -914,7 +918,7 @@ MlpTrainLayout mlp_train_layout(int M) {
     L.d1t = take(act * kW);
     L.dw1 = take((size_t)wgrad_splits(M) * kW * kIn * 4);
     L.dw2 = take((size_t)wgrad_splits(M) * kW * kW * 4);
-    L.part = take((size_t)(M / kRows) * kMlpPartStride * 4);
+    L.part = take((size_t)(M / kTrainRows) * kMlpPartStride * 4);
     L.total = off;
     return L;
 }
@@ -930,7 +934,7 @@ hipError_t launch_mlp_train_step(float* P, __bf16* Wb, float* mom, float* vel, i
     float* dW1 = reinterpret_cast<float*>(ws + L.dw1);
     float* dW2 = reinterpret_cast<float*>(ws + L.dw2);
     float* part = reinterpret_cast<float*>(ws + L.part);
-    const int tiles = M / kRows;
+    const int tiles = M / kTrainRows;
     const int splits = wgrad_splits(M), per = M / splits;
     hipLaunchKernelGGL(k_mlp_train_fb, dim3(tiles), dim3(256), 0, st, P, Wb, X, cost, idx, n_rows, M, n_in, status,
                        UT, H1T, D2T, D1T, part);
