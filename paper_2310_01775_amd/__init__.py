@@ -200,6 +200,11 @@ def _ptr(t):
         return None
     if not t.is_cuda or not t.is_contiguous():
         raise ValueError("device tensors must be contiguous CUDA/HIP tensors")
+    # every array of the C ABI holds 4-byte (float32, int32) or narrower
+    # elements: a float64 array (say one made from numpy without a dtype) would
+    # be read as garbage
+    if t.element_size() > 4:
+        raise ValueError("the C ABI takes float32/int32 (or narrower) arrays, got %s" % t.dtype)
     return C.c_void_p(t.data_ptr())
 
 
@@ -657,7 +662,7 @@ class Context:
         if need_enc and (enc is None or enc.numel() < need_enc):
             raise ValueError("enc needs %d floats" % need_enc)
         sur = Surrogate(int(sur_iters), int(n_in), int(check_every), float(max_log_err), int(bool(phi_bf16)), 0,
-                        params.data_ptr(), wbf16.data_ptr(), enc.data_ptr() if enc is not None else None)
+                        _ptr(params), _ptr(wbf16), _ptr(enc))
         rep = SurrogateReport()
         self._check(_lib.stamp_solve_surrogate(self._h, n, arr, warr, ns, C.byref(cfg), C.byref(sur), _ptr(theta),
                                                _ptr(adam_m), _ptr(adam_v), _ptr(cost_out), _ptr(modes_out),

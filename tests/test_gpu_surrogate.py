@@ -302,3 +302,19 @@ def test_trained_network_gains_over_the_method_without_it(ctx):
     # equal cost, in the plain method's mean final true cost and in the median
     assert med["surrogate240+60"] < med["plain300"]
     assert mean["surrogate240+60"] < mean["plain300"]
+
+
+def test_binding_rejects_64_bit_arrays(ctx):
+    """A float64 array (numpy's default) handed to the C ABI, which takes
+    float32, is refused by the binding instead of being read as garbage."""
+    import paper_2310_01775_amd as S
+    probs = _batch(S, [(40, 3, 2)], 1)
+    n_in = 18 + W.SCENE_ENC
+    P, Wb = _network(ctx, S, n_in, 4)
+    scene, w, th, e = probs[0]
+    theta = S.soa(th)
+    m, v = torch.zeros_like(theta), torch.zeros_like(theta)
+    enc64 = torch.as_tensor(_enc(e, n_in, 18), dtype=torch.float64, device="cuda")
+    with pytest.raises(ValueError, match="float32"):
+        ctx.solve_surrogate([S.make_scene(scene)], [S.make_cost(w)], [th.shape[0]], S.make_cfg(2, lr=1e-3), 2, P, Wb,
+                            n_in, enc64, theta, m, v)
