@@ -101,12 +101,16 @@ struct SvgdLayout {
     int tiles;                      // 64-row tiles
     // BF16 matrix-core form (sampled median, centred Gram distances)
     int npad;                       // N rounded up to the 256-row block
-    // FP32 matrix-core form of the contraction (phi32.hip)
+    // FP32 direction (phi32.hip): on the FP32 matrix cores, or for d <= 31 in
+    // split form (every operand as three BF16 parts on the BF16 matrix cores)
     int ks32, ot32;                 // Gram k-steps (4 coordinates each), 16-column tiles of V
-    int splits32, chunk32;          // column splits and their width (a multiple of 16)
+    int split3;                     // 1: the split form runs the contraction
+    int splits32, chunk32;          // column splits and their width (a multiple of 16; of 128 in split form)
     size_t x32_off;                 // npad x 4 ks32 floats: centred rows in MFMA operand order
     size_t n32_off;                 // npad floats: their squared norms
     size_t v32_off;                 // npad x 16 ot32 floats: V = w [g - (2/h) x | 1 | 0], tiled
+    size_t xs3_off;                 // split form: npad x 3 x 32 bf16, the centred rows' three parts
+    size_t vs3_off;                 // split form: 3 x npad x 16 ot32 bf16, V's three parts, chunked
     int kd, vc;                     // Gram width (d + 2 rounded up to 32) and V columns (d + 1 rounded up)
     int splits16, chunk16;          // column splits of its contraction and their width
     size_t smp_off;                 // kMedSample floats: the sampled distances
@@ -152,10 +156,12 @@ struct ProblemDesc {
     int64_t svgd_off;   // bytes into the SVGD region
 };
 
-// Classes of the padded particle dimension of the contraction kernel.
-// Shape classes of the FP32 matrix-core contraction: Gram k-steps (an even
-// count of 4-coordinate steps) and 16-column tiles of V = [.. d .. | 1].
-constexpr int kPhi32Classes = 12;
+// Shape classes of the FP32 direction's contraction: the split form for
+// d <= 31 (classes 0 and 1: one or two 16-column tiles of V = [.. d .. | 1]),
+// then the FP32 matrix-core form by Gram k-steps (an even count of
+// 4-coordinate steps) and 16-column tiles of V.
+constexpr int kPhi32Classes = 9;
+constexpr int kPhi3MaxD = 31;  // the split form's Gram is 32 coordinates wide, V 32 columns
 __host__ __device__ inline int phi32_ks(int d) { return 2 * ((d + 7) / 8); }
 __host__ __device__ inline int phi32_ot(int d) { return (d + 16) / 16; }
 
@@ -179,7 +185,7 @@ struct BatchPlan {
                                           //   (problems above 2^20 pairs)
     const int4* fin_work;   int n_fin;    // (p, -, -, -): problems of 2^20 pairs at most, whose select
                                           //   ends in one workgroup after pass 0
-    const int4* phi_work[kPhi32Classes];  // (p, 256-row block, split, -) per FP32 matrix-core class
+    const int4* phi_work[kPhi32Classes];  // (p, row block, split, -) per contraction class
     int n_phi[kPhi32Classes];
     // BF16 matrix-core form: (problem, coordinate), (problem, 256-row chunk),
     // and (problem, row block, split) per padded dimension 32 / 64

@@ -30,7 +30,8 @@ hipError_t launch_rollout_adj_batched(const ProblemDesc* descs, const int2* tile
 // the median heuristic runs and writes h into the workspace (and h_out if
 // non-null).  phi_rows: rows per contraction workgroup (0 = 256).
 SvgdLayout svgd_workspace_layout(int N, int d);
-// class index (0 .. kPhi32Classes-1) of the FP32 matrix-core contraction for dimension d
+// class index (0 .. kPhi32Classes-1) of the FP32 direction's contraction for dimension d
+// (0, 1: the split form for d <= kPhi3MaxD; then the FP32 matrix-core form)
 int phi32_class(int d);
 // wts: null, or per-particle importance weights (mean 1) of Eq. (4).
 hipError_t launch_svgd(int N, int d, const float* theta, const float* grad_logp, float bandwidth, float* phi,

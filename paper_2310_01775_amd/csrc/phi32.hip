@@ -28,6 +28,23 @@
 // whose k index runs over (l/16, t), and V is stored in that order, so each
 // lane reads its four V values of an output tile with one 16-byte load.  The
 // reduce sums the splits in a fixed order.  Splits depend on N only.
+//
+// Split form (d <= 31).  The FP32 matrix cores do a sixteenth of the BF16
+// ones' work per cycle, so the same contraction runs there with every FP32
+// operand v written as three BF16 parts, hi = bf16(v), mid = bf16(v - hi),
+// lo = bf16(v - hi - mid) (both differences exact in FP32, and
+// hi + mid + lo = v within 2^-25 |v|).  A product a b is then the sum of the
+// six part products whose order is at least 2^-16 of it (hh, hm, mh, hl, lh,
+// mm; the three dropped ones are below 2^-24), each exact in the FP32
+// accumulator: the Gram x_i . x_j takes six BF16 MFMAs over 32 coordinates,
+// K V six over 32 particles, where the FP32 form takes eight 4-wide ones and
+// eight.  e_j still enters as the Gram accumulator's start and K is the same
+// multiply-add and clamped exponential of the FP32 Gram value, so the
+// result is the FP32 form's within its own rounding.  Tiling as in the BF16
+// direction (phi16.hip): a workgroup of 4 waves owns 64 rows and one column
+// split, the waves take its quarters and add their sums through LDS; the
+// Gram's output layout is the K.V product's A operand, V is stored in that
+// permuted order.  The reduce is the FP32 form's.
 #include <math.h>
 
 #include <type_traits>
@@ -40,6 +57,7 @@ namespace stamp {
 namespace {
 
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f4;
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 
 struct View32 {  // one problem's FP32 matrix-core workspace
     const float* ctr;
@@ -47,6 +65,8 @@ struct View32 {  // one problem's FP32 matrix-core workspace
     float* nrm;  // [npad]: |x_i|^2
     float* vt;   // [npad / 16][ot][16 columns n][16 rows j]: X[j][16 o + n] at 16 n + j of tile (j/16, o)
     float* part; // [splits32][16 ot][npad]
+    __bf16* xs3; // split form: [npad][3][32], row i's part p at (3 i + p) 32
+    __bf16* vs3; // split form: part p of V at p npad 16 ot, as [npad / 32][16 ot][32] in MFMA k order
     const SelState* sel;
 };
 
@@ -57,8 +77,21 @@ __device__ __forceinline__ View32 view32(const SvgdLayout& L, char* base) {
     v.nrm = reinterpret_cast<float*>(base + L.n32_off);
     v.vt = reinterpret_cast<float*>(base + L.v32_off);
     v.part = reinterpret_cast<float*>(base + L.part_off);
+    v.xs3 = reinterpret_cast<__bf16*>(base + L.xs3_off);
+    v.vs3 = reinterpret_cast<__bf16*>(base + L.vs3_off);
     v.sel = reinterpret_cast<const SelState*>(base + L.sel_off);
     return v;
+}
+
+// v = hi + mid + lo into slot u of three part vectors (BF16 parts; the two
+// differences are exact in FP32)
+__device__ __forceinline__ void split3(float v, bf16x8& hi, bf16x8& mid, bf16x8& lo, int u) {
+    const __bf16 h = (__bf16)v;
+    const float r = v - (float)h;
+    const __bf16 m = (__bf16)r;
+    hi[u] = h;
+    mid[u] = m;
+    lo[u] = (__bf16)(r - (float)m);
 }
 
 // ---- operands: 64 rows per 256 threads, lane group q = threadIdx.x / 64 takes
@@ -101,6 +134,53 @@ __device__ void pack32_v_rows(int N, int d, int ot, int row0, const float* __res
             if (wts) x *= w;
         }
         vt[(n >> 4) * 256 + (n & 15) * 16] = x;
+    }
+}
+
+// Split form, 64 rows per 256 threads: the centred rows' parts (thread
+// (r, q) the coordinates 8 q .. 8 q + 7 of row r, as the MFMA lane group q
+// reads them) and V's parts, V[i][n] as in pack32_v_rows, in the order the
+// K.V product reads them: within a 32-particle chunk, column n holds 32
+// values whose slot 8 q + u is particle 4 q + (u & 3) (+ 16 for u >= 4), one
+// 16-byte store per (chunk, column, q) and part.
+__device__ void pack3_rows(int N, int d, int ot, int npad, int row0, const float* __restrict__ theta,
+                           const float* __restrict__ g, const float* __restrict__ wts, const View32& v) {
+    const int vc = 16 * ot;
+    {
+        const int r = threadIdx.x & 63, q = threadIdx.x >> 6;
+        const int i = row0 + r;
+        bf16x8 p0, p1, p2;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int l = 8 * q + u;
+            const float x = (i < N && l < d) ? theta[(int64_t)l * N + i] - v.ctr[l] : 0.0f;
+            split3(x, p0, p1, p2, u);
+        }
+        __bf16* o = v.xs3 + (int64_t)i * 96 + 8 * q;
+        *reinterpret_cast<bf16x8*>(o) = p0;
+        *reinterpret_cast<bf16x8*>(o + 32) = p1;
+        *reinterpret_cast<bf16x8*>(o + 64) = p2;
+    }
+    const float c2 = 2.0f / v.sel->h;
+    const int64_t plane = (int64_t)npad * vc;
+    for (int o = threadIdx.x; o < 8 * vc; o += 256) {  // 2 chunks x vc columns x 4 lane groups
+        const int qc = (row0 >> 5) + o / (4 * vc), n = (o >> 2) % vc, q = o & 3;
+        bf16x8 p0, p1, p2;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int i = 32 * qc + 4 * q + (u & 3) + (u >= 4 ? 16 : 0);
+            float x = 0.0f;
+            if (i < N) {
+                if (n < d) x = -c2 * (theta[(int64_t)n * N + i] - v.ctr[n]) + g[(int64_t)n * N + i];
+                else x = n == d ? 1.0f : 0.0f;
+                if (wts) x *= wts[i];
+            }
+            split3(x, p0, p1, p2, u);
+        }
+        __bf16* dst = v.vs3 + ((int64_t)qc * vc + n) * 32 + 8 * q;
+        *reinterpret_cast<bf16x8*>(dst) = p0;
+        *reinterpret_cast<bf16x8*>(dst + plane) = p1;
+        *reinterpret_cast<bf16x8*>(dst + 2 * plane) = p2;
     }
 }
 
@@ -184,6 +264,139 @@ __device__ void phi32_body(int row0, int j0, int j1, int split, int npad, const 
             *reinterpret_cast<f4*>(out + (int64_t)(16 * o + col) * npad + rbase + 16 * r + 4 * kq) = acc[r][o];
 }
 
+// ---- split form: partial sums of K V over the columns [j0, j1) ---------------------
+// Operands of one 32-column chunk as this lane holds them.
+template <int OT>
+struct Chunk3 {
+    bf16x8 xj[3][2];  // A of the Gram, part p: row j = jc + 16 sub + l % 16
+    f4 nj[2];         // |x_j|^2 for j = jc + 16 sub + 4 (l / 16) + t
+    bf16x8 vb[3][OT]; // B of K.V, part p: V[j][16 o + l % 16], j in the permuted order
+};
+
+template <int OT>
+__device__ __forceinline__ void load_x3(Chunk3<OT>& c, const View32& v, int jc, int col, int kq) {
+#pragma unroll
+    for (int sub = 0; sub < 2; ++sub) {
+        const __bf16* x = v.xs3 + (int64_t)(jc + 16 * sub + col) * 96 + 8 * kq;
+#pragma unroll
+        for (int p = 0; p < 3; ++p) c.xj[p][sub] = *reinterpret_cast<const bf16x8*>(x + 32 * p);
+        c.nj[sub] = *reinterpret_cast<const f4*>(v.nrm + jc + 16 * sub + 4 * kq);
+    }
+}
+
+template <int OT>
+__device__ __forceinline__ void load_v3(Chunk3<OT>& c, const View32& v, int npad, int jc, int col, int kq) {
+    const int64_t plane = (int64_t)npad * 16 * OT;
+    const __bf16* vch = v.vs3 + ((int64_t)(jc >> 5) * 16 * OT + col) * 32 + 8 * kq;
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+#pragma unroll
+        for (int o = 0; o < OT; ++o) c.vb[p][o] = *reinterpret_cast<const bf16x8*>(vch + p * plane + 16 * o * 32);
+}
+
+// The six part products of a x b (parts 0 = hi, 1 = mid, 2 = lo) whose
+// order is at least 2^-16 of it, smallest first.
+__device__ constexpr int kPairs3[6][2] = {{1, 1}, {2, 0}, {0, 2}, {1, 0}, {0, 1}, {0, 0}};
+
+// One 32-column chunk for the wave's 4 row tiles: the Gram MFMAs (accumulator
+// starting at e_j = -|x_j|^2 / 2), then per row tile K = 2^(c D) split in
+// three (VALU) and the K.V MFMAs.  One operand buffer: the next chunk's Gram
+// operands load as soon as this chunk's Gram has read them (they arrive
+// during its K.V work), its V as soon as the K.V products have read V
+// (arriving during the next Gram).
+template <int OT>
+__device__ __forceinline__ void chunk3_step(Chunk3<OT>& cur, const bf16x8 (&xi)[3][4], const float (&ni)[4], float m2c,
+                                            f4 (&acc)[4][OT], const View32& v, int npad, int jn, bool more, int col,
+                                            int kq) {
+    f4 s[4][2];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int sub = 0; sub < 2; ++sub) {
+            s[r][sub] = cur.nj[sub] * -0.5f;
+#pragma unroll
+            for (int e = 0; e < 6; ++e)
+                s[r][sub] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cur.xj[kPairs3[e][0]][sub], xi[kPairs3[e][1]][r],
+                                                                    s[r][sub], 0, 0, 0);
+        }
+    if (more) load_x3<OT>(cur, v, jn, col, kq);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        bf16x8 ka[3];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            const float k = unit_clamp(hw_exp2(fmaf(m2c, s[r][t >> 2][t & 3], ni[r])));
+            split3(k, ka[0], ka[1], ka[2], t);
+        }
+#pragma unroll
+        for (int e = 0; e < 6; ++e)
+#pragma unroll
+            for (int o = 0; o < OT; ++o)
+                acc[r][o] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ka[kPairs3[e][0]], cur.vb[kPairs3[e][1]][o],
+                                                                    acc[r][o], 0, 0, 0);
+    }
+    if (more) load_v3<OT>(cur, v, npad, jn, col, kq);
+}
+
+// 64 rows from row0, columns [j0, j1) (a multiple of 128: the 4 waves take
+// consecutive quarters); the waves' sums are added in wave order through LDS
+// and stored as the split's partial, laid out as the FP32 form's.
+template <int OT>
+__device__ void phi3_body(int npad, int row0, int j0, int j1, int split, const View32& v) {
+    __shared__ f4 red[3][4 * OT][64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int col = lane & 15, kq = lane >> 4;
+    {
+        const int q = (j1 - j0) >> 2;
+        j0 += wave * q;
+        j1 = j0 + q;
+    }
+    const float c = -1.44269504088896341f / v.sel->h;  // K = 2^(c D)
+    const float m2c = -2.0f * c;
+    bf16x8 xi[3][4];  // B of the Gram, part p, row tile r
+    float ni[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int i = row0 + 16 * r + col;
+        const __bf16* x = v.xs3 + (int64_t)i * 96 + 8 * kq;
+#pragma unroll
+        for (int p = 0; p < 3; ++p) xi[p][r] = *reinterpret_cast<const bf16x8*>(x + 32 * p);
+        ni[r] = c * v.nrm[i];
+    }
+    f4 acc[4][OT];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int o = 0; o < OT; ++o) acc[r][o] = f4{0.f, 0.f, 0.f, 0.f};
+    Chunk3<OT> cur;
+    if (j0 < j1) {
+        load_x3<OT>(cur, v, j0, col, kq);
+        load_v3<OT>(cur, v, npad, j0, col, kq);
+    }
+    for (int jc = j0; jc < j1; jc += 32)
+        chunk3_step<OT>(cur, xi, ni, m2c, acc, v, npad, jc + 32, jc + 32 < j1, col, kq);
+    if (wave > 0) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int o = 0; o < OT; ++o) red[wave - 1][r * OT + o][lane] = acc[r][o];
+    }
+    __syncthreads();
+    if (wave > 0) return;
+#pragma unroll
+    for (int u = 0; u < 3; ++u)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int o = 0; o < OT; ++o) acc[r][o] += red[u][r * OT + o][lane];
+    float* out = v.part + (int64_t)split * (16 * OT) * npad;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int o = 0; o < OT; ++o)
+            *reinterpret_cast<f4*>(out + (int64_t)(16 * o + col) * npad + row0 + 16 * r + 4 * kq) = acc[r][o];
+}
+
 // ---- phi from the split sums (fixed split order) ----------------------------------
 // the coordinate's row and the row-sum row of every split, 16 loads in flight
 // phi (stored when phi is not null) and, with upd, the operands of the
@@ -236,7 +449,8 @@ __global__ __launch_bounds__(256) void k_pack32_x(One32 a, const float* theta, c
 
 __global__ __launch_bounds__(256) void k_pack32_v(One32 a, const float* theta, const float* g, const float* wts,
                                                   char* ws) {
-    pack32_v_rows(a.N, a.d, a.L.ot32, blockIdx.x * 64, theta, g, wts, view32(a.L, ws));
+    if (a.L.split3) pack3_rows(a.N, a.d, a.L.ot32, a.L.npad, blockIdx.x * 64, theta, g, wts, view32(a.L, ws));
+    else pack32_v_rows(a.N, a.d, a.L.ot32, blockIdx.x * 64, theta, g, wts, view32(a.L, ws));
 }
 
 template <int KS, int OT>
@@ -244,6 +458,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     const int split = blockIdx.y;
     const int j0 = split * a.L.chunk32, j1 = min(j0 + a.L.chunk32, a.L.npad);
     phi32_body<KS, OT>(blockIdx.x * blockDim.x, j0, j1, split, a.L.npad, view32(a.L, ws));
+}
+
+// split form: 64 rows per workgroup of 256
+template <int OT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_phi3(One32 a, char* ws) {
+    const int split = blockIdx.y;
+    const int j0 = split * a.L.chunk32, j1 = min(j0 + a.L.chunk32, a.L.npad);
+    phi3_body<OT>(a.L.npad, blockIdx.x * 64, j0, j1, split, view32(a.L, ws));
 }
 
 // upd.use_adam < 0: no update
@@ -295,8 +517,12 @@ __global__ __launch_bounds__(256) void k_pack32_v_batched(const ProblemDesc* __r
     const int4 e = work[blockIdx.x >> 2];
     const ProblemDesc& D = descs[e.x];
     if (D.N < 2) return;
-    pack32_v_rows(D.N, D.d, D.sv.ot32, e.y + 64 * (blockIdx.x & 3), theta + D.theta_off, grad + D.theta_off,
-                  wts ? wts + D.cost_off : nullptr, view32(D.sv, base32(D, ws)));
+    if (D.sv.split3)
+        pack3_rows(D.N, D.d, D.sv.ot32, D.sv.npad, e.y + 64 * (blockIdx.x & 3), theta + D.theta_off,
+                   grad + D.theta_off, wts ? wts + D.cost_off : nullptr, view32(D.sv, base32(D, ws)));
+    else
+        pack32_v_rows(D.N, D.d, D.sv.ot32, e.y + 64 * (blockIdx.x & 3), theta + D.theta_off, grad + D.theta_off,
+                      wts ? wts + D.cost_off : nullptr, view32(D.sv, base32(D, ws)));
 }
 
 // entry = (problem, row block of blockDim.x rows, split, -)
@@ -307,6 +533,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     const ProblemDesc& D = descs[e.x];
     const int j0 = e.z * D.sv.chunk32, j1 = min(j0 + D.sv.chunk32, D.sv.npad);
     phi32_body<KS, OT>(e.y * (int)blockDim.x, j0, j1, e.z, D.sv.npad, view32(D.sv, base32(D, ws)));
+}
+
+// split form: entry = (problem, 64-row block, split, -)
+template <int OT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_phi3_batched(const ProblemDesc* __restrict__ descs,
+                                                      const int4* __restrict__ work, char* ws) {
+    const int4 e = work[blockIdx.x];
+    const ProblemDesc& D = descs[e.x];
+    const int j0 = e.z * D.sv.chunk32, j1 = min(j0 + D.sv.chunk32, D.sv.npad);
+    phi3_body<OT>(D.sv.npad, e.y * 64, j0, j1, e.z, view32(D.sv, base32(D, ws)));
 }
 
 // entry = (problem, first element, end element, -) of the problem's d*N block
@@ -333,18 +569,26 @@ __global__ __launch_bounds__(256) void k_reduce32_batched(const ProblemDesc* __r
     }
 }
 
-// (ks, ot) of each class, in the order of phi32_class
-constexpr int kCls[kPhi32Classes][2] = {{2, 1},  {4, 1},  {4, 2},  {6, 2},  {8, 2},  {8, 3},
-                                        {10, 3}, {12, 3}, {12, 4}, {14, 4}, {16, 4}, {16, 5}};
+// (ks, ot) of each class, in the order of phi32_class; classes 0 and 1 are
+// the split form (one or two 16-column tiles of V), the rest the FP32
+// matrix-core form
+constexpr int kCls[kPhi32Classes][2] = {{8, 1}, {8, 2}, {8, 3}, {10, 3}, {12, 3},
+                                        {12, 4}, {14, 4}, {16, 4}, {16, 5}};
 
 template <int C>
 void launch_class(dim3 grid, int rows, hipStream_t st, const One32& a, char* ws) {
-    hipLaunchKernelGGL((k_phi32<kCls[C][0], kCls[C][1]>), grid, dim3(rows), 0, st, a, ws);
+    if constexpr (C < 2)
+        hipLaunchKernelGGL((k_phi3<kCls[C][1]>), grid, dim3(256), 0, st, a, ws);
+    else
+        hipLaunchKernelGGL((k_phi32<kCls[C][0], kCls[C][1]>), grid, dim3(rows), 0, st, a, ws);
 }
 
 template <int C>
 void launch_class_batched(int n, int rows, hipStream_t st, const ProblemDesc* descs, const int4* work, char* ws) {
-    hipLaunchKernelGGL((k_phi32_batched<kCls[C][0], kCls[C][1]>), dim3(n), dim3(rows), 0, st, descs, work, ws);
+    if constexpr (C < 2)
+        hipLaunchKernelGGL((k_phi3_batched<kCls[C][1]>), dim3(n), dim3(256), 0, st, descs, work, ws);
+    else
+        hipLaunchKernelGGL((k_phi32_batched<kCls[C][0], kCls[C][1]>), dim3(n), dim3(rows), 0, st, descs, work, ws);
 }
 
 template <typename F>
@@ -358,18 +602,16 @@ void by_class(int c, F&& f) {
         case 5: f(std::integral_constant<int, 5>()); break;
         case 6: f(std::integral_constant<int, 6>()); break;
         case 7: f(std::integral_constant<int, 7>()); break;
-        case 8: f(std::integral_constant<int, 8>()); break;
-        case 9: f(std::integral_constant<int, 9>()); break;
-        case 10: f(std::integral_constant<int, 10>()); break;
-        default: f(std::integral_constant<int, 11>()); break;
+        default: f(std::integral_constant<int, 8>()); break;
     }
 }
 
 }  // namespace
 
 int phi32_class(int d) {
+    if (d <= kPhi3MaxD) return phi32_ot(d) - 1;
     const int ks = phi32_ks(d), ot = phi32_ot(d);
-    for (int c = 0; c < kPhi32Classes; ++c)
+    for (int c = 2; c < kPhi32Classes; ++c)
         if (kCls[c][0] == ks && kCls[c][1] == ot) return c;
     return -1;
 }
@@ -400,7 +642,8 @@ hipError_t launch_svgd_direction(int N, int d, const float* theta, const float* 
     char* b = static_cast<char*>(ws);
     if (N >= 2) {
         hipLaunchKernelGGL(k_pack32_v, dim3(L.npad / 64), dim3(256), 0, st, a, theta, grad_logp, wts, b);
-        const int rows = phi_rows > 0 ? phi_rows : 256;
+        // the split form takes 64 rows per workgroup whatever the row block
+        const int rows = L.split3 ? 64 : phi_rows > 0 ? phi_rows : 256;
         const dim3 grid(L.npad / rows, L.splits32);
         by_class(phi32_class(d), [&](auto c) { launch_class<decltype(c)::value>(grid, rows, st, a, b); });
     }

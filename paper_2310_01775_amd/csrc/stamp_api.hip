@@ -326,7 +326,8 @@ void build_plan(int n, const stamp_scene* scenes, const int32_t* N, int K, float
         }
         if (D.N >= 2) {
             const int c = phi32_class(D.d);
-            for (int rb = 0; rb * phi_rows < D.sv.npad; ++rb)
+            const int rows = D.sv.split3 ? 64 : phi_rows;  // the split form's workgroups take 64 rows
+            for (int rb = 0; rb * rows < D.sv.npad; ++rb)
                 for (int q = 0; q < D.sv.splits32; ++q) P.phi_work[c].push_back(make_int4(p, rb, q, 0));
         }
         // BF16 form: its lists do not depend on the row block of the FP32 form

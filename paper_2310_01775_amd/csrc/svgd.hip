@@ -181,7 +181,20 @@ SvgdLayout svgd_workspace_layout(int N, int d) {
     L.npad = (N + kRows16 - 1) / kRows16 * kRows16;
     L.ks32 = phi32_ks(d);
     L.ot32 = phi32_ot(d);
-    {
+    L.split3 = d <= kPhi3MaxD ? 1 : 0;
+    if (L.split3) {
+        // split form: 64-row workgroups whose 4 waves take quarters of a
+        // split (so a split is a multiple of 128 columns); about one full
+        // round of resident workgroups (2 per CU: register bound)
+        const int rowblocks = L.npad / 64;
+        int s3 = (512 + rowblocks / 2) / rowblocks;
+        if (s3 > L.npad / 128) s3 = L.npad / 128;
+        if (s3 > 32) s3 = 32;
+        if (s3 < 1) s3 = 1;
+        const int chunk = ((L.npad + s3 - 1) / s3 + 127) / 128 * 128;
+        L.splits32 = (L.npad + chunk - 1) / chunk;
+        L.chunk32 = chunk;
+    } else {
         const int waves = L.npad / 64;
         int s32 = (2048 + waves - 1) / waves;
         if (s32 > L.npad / 64) s32 = L.npad / 64;
@@ -210,7 +223,11 @@ SvgdLayout svgd_workspace_layout(int N, int d) {
     L.n32_off = off;
     off = align256(off + (size_t)L.npad * 4);
     L.v32_off = off;
-    off = align256(off + (size_t)L.npad * 16 * L.ot32 * 4);
+    off = align256(off + (L.split3 ? 0 : (size_t)L.npad * 16 * L.ot32 * 4));
+    L.xs3_off = off;
+    off = align256(off + (L.split3 ? (size_t)L.npad * 3 * 32 * 2 : 0));
+    L.vs3_off = off;
+    off = align256(off + (L.split3 ? (size_t)3 * L.npad * 16 * L.ot32 * 2 : 0));
     // BF16 matrix-core form
     L.kd = d <= 30 ? 32 : d <= 62 ? 64 : 96;  // the rows and two more Gram columns for e_i
     L.vc = d <= 30 ? 32 : d <= 62 ? 64 : 80;  // V = [g - (2/h) x | 1 | 0]: d + 1 columns, padded

@@ -95,7 +95,8 @@ def test_median_with_massive_ties_takes_the_all_pairs_passes(ctx, N):
 
 
 @pytest.mark.parametrize("N,d,bw", [(1, 6, 0.0), (2, 6, 0.0), (37, 12, 0.0), (65, 18, 2.5), (300, 18, 0.0),
-                                    (1024, 18, 0.0), (513, 30, 0.0), (200, 48, 0.0)])
+                                    (1024, 18, 0.0), (513, 30, 0.0), (300, 31, 0.0), (300, 32, 0.0),
+                                    (200, 48, 0.0)])
 def test_phi_matches_oracle(ctx, N, d, bw):
     import paper_2310_01775_amd as S
     print("case", N, d, bw, flush=True)
