@@ -172,9 +172,12 @@ __host__ __device__ inline int med_dp(int d) { return d <= 16 ? 16 : d <= 32 ? 3
 __host__ __device__ inline int med_class(int dp, int rows) { return (dp == 16 ? 0 : dp == 32 ? 2 : 4) + (rows == 256); }
 // Work lists of the median's all-pairs items, one per item shape: 6 direct
 // shapes (med_class), then 16 Gram-form shapes (ks32, rows) of the problems
-// above 2^20 pairs.
-constexpr int kMedLists = 6 + 16;
-__host__ __device__ inline int med_gram_list(int ks32, int rows) { return 6 + 2 * (ks32 / 2 - 1) + (rows == 256); }
+// above 2^20 pairs, then 2 of the split-form Gram (ks32 = 0: d <= 31, the
+// rows as three BF16 parts).
+constexpr int kMedLists = 6 + 16 + 2;
+__host__ __device__ inline int med_gram_list(int ks32, int rows) {
+    return (ks32 == 0 ? 22 : 6 + 2 * (ks32 / 2 - 1)) + (rows == 256);
+}
 
 struct BatchPlan {
     int n_problems;

@@ -47,6 +47,7 @@
 namespace stamp {
 
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f4v;
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8v;
 
 namespace {
 
@@ -89,6 +90,7 @@ struct MedView {
     uint32_t* cnt;       // [rb * cc][2]: pairs under, over the bracket
     const float* xr;     // Gram form: centred rows in MFMA operand order (4 ks floats each)
     const float* nrm;    // and their squared norms (FP32 matrix-core operands)
+    const __bf16* xs3;   // split form (d <= 31): the same rows as three BF16 parts, [npad][3][32]
 };
 
 __device__ __forceinline__ MedView med_view(int N, int d, float fixed_h, const SvgdLayout& L, char* b) {
@@ -107,6 +109,7 @@ __device__ __forceinline__ MedView med_view(int N, int d, float fixed_h, const S
     v.cnt = reinterpret_cast<uint32_t*>(b + L.cnt_off);
     v.xr = reinterpret_cast<const float*>(b + L.x32_off);
     v.nrm = reinterpret_cast<const float*>(b + L.n32_off);
+    v.xs3 = reinterpret_cast<const __bf16*>(b + L.xs3_off);
     return v;
 }
 
@@ -554,8 +557,14 @@ __device__ void med_item(const MedView& v, const float* __restrict__ theta, int 
 // as four 16-row tiles; with 256-row items it takes every column of the item,
 // with 64-row items a 16-column quarter.  Per 16 columns and row tile, KS
 // MFMAs (16x16x4) give S[i][j] with lane l holding rows 4 (l / 16) + t of
-// column l % 16.  Every pass computes a pair's distance with the same
-// instructions, so the counts stay exact.
+// column l % 16.  KS = 0 is the split form (d <= 31): the rows as three
+// BF16 parts and x_i . x_j as the six part products of order >= 2^-16 on the
+// BF16 matrix cores (16x16x32, the same output layout), FP32-accurate as the
+// FP32 direction's split form.  Every pass computes a pair's distance with
+// the same instructions, so the counts stay exact.
+// The split form's part products (row part, column part), smallest first.
+__device__ constexpr int kGramPairs3[6][2] = {{1, 1}, {2, 0}, {0, 2}, {1, 0}, {0, 1}, {0, 0}};
+
 template <int KS, int ROWS>
 __device__ void med_item_gram(const MedView& v, int rb, int cc) {
     // an item spans kGramGroup column chunks: its counts go to the first
@@ -593,13 +602,23 @@ __device__ void med_item_gram(const MedView& v, int rb, int cc) {
     // 256-row items: every 16-column step for each wave; 64-row items: the
     // waves take the steps in turn
     const int cbeg = ROWS == 256 ? 0 : 16 * wave, cend = (cc1 - cc) * kMedCols, cstep = ROWS == 256 ? 16 : 64;
-    float xa[4][KS];
+    constexpr bool SPLIT = KS == 0;
+    constexpr int KA = SPLIT ? 1 : KS;   // FP32 operand steps
+    constexpr int NP = SPLIT ? 3 : 1;    // split-form parts
+    float xa[4][KA];
+    bf16x8v xa3[NP][4];
     f4v ni[4];  // |x_i|^2 for i = wrow + 16 r + 4 kq + t
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-        const float* p = v.xr + (int64_t)(wrow + 16 * r + col) * (4 * KS) + kq * KS;
+        if constexpr (SPLIT) {
+            const __bf16* p = v.xs3 + (int64_t)(wrow + 16 * r + col) * 96 + 8 * kq;
 #pragma unroll
-        for (int k = 0; k < KS; ++k) xa[r][k] = p[k];
+            for (int q = 0; q < NP; ++q) xa3[q][r] = *reinterpret_cast<const bf16x8v*>(p + 32 * q);
+        } else {
+            const float* p = v.xr + (int64_t)(wrow + 16 * r + col) * (4 * KS) + kq * KS;
+#pragma unroll
+            for (int k = 0; k < KS; ++k) xa[r][k] = p[k];
+        }
         ni[r] = *reinterpret_cast<const f4v*>(v.nrm + wrow + 16 * r + 4 * kq);
     }
     // one candidate segment per workgroup (hashed: in a work list only every
@@ -631,12 +650,19 @@ __device__ void med_item_gram(const MedView& v, int rb, int cc) {
     // step's operands load while this one computes
     int c0 = cbeg;
     while (c0 < cend && col0 + c0 + 15 <= wrow) c0 += cstep;
-    float xb[KS], xn[KS];
+    float xb[KA], xn[KA];
+    bf16x8v xb3[NP], xn3[NP];
     float nj = 0.0f, nn = 0.0f;
-    auto load = [&](int c, float (&x)[KS], float& n) __attribute__((always_inline)) {
-        const float* p = v.xr + (int64_t)(col0 + c + col) * (4 * KS) + kq * KS;
+    auto load = [&](int c, float (&x)[KA], bf16x8v (&x3)[NP], float& n) __attribute__((always_inline)) {
+        if constexpr (SPLIT) {
+            const __bf16* p = v.xs3 + (int64_t)(col0 + c + col) * 96 + 8 * kq;
 #pragma unroll
-        for (int k = 0; k < KS; ++k) x[k] = p[k];
+            for (int q = 0; q < NP; ++q) x3[q] = *reinterpret_cast<const bf16x8v*>(p + 32 * q);
+        } else {
+            const float* p = v.xr + (int64_t)(col0 + c + col) * (4 * KS) + kq * KS;
+#pragma unroll
+            for (int k = 0; k < KS; ++k) x[k] = p[k];
+        }
         n = v.nrm[col0 + c + col];
     };
     // one distance of the step: counted, and appended (pass 0) or
@@ -665,9 +691,9 @@ __device__ void med_item_gram(const MedView& v, int rb, int cc) {
     };
     auto sweep = [&](auto p0_tag) __attribute__((always_inline)) {
         constexpr bool P0 = decltype(p0_tag)::value;
-        if (c0 < cend) load(c0, xb, nj);
+        if (c0 < cend) load(c0, xb, xb3, nj);
         for (int c = c0; c < cend; c += cstep) {
-            if (c + cstep < cend) load(c + cstep, xn, nn);
+            if (c + cstep < cend) load(c + cstep, xn, xn3, nn);
             const int jb = col0 + c, j = jb + col;
             // a step appends at most 16 x 64 values
             if (P0 && nwb + 1024 > kBuf) flush();
@@ -675,14 +701,26 @@ __device__ void med_item_gram(const MedView& v, int rb, int cc) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 f4v S = f4v{0.f, 0.f, 0.f, 0.f};
+                if constexpr (SPLIT) {
 #pragma unroll
-                for (int k = 0; k < KS; ++k) S = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[r][k], xb[k], S, 0, 0, 0);
+                    for (int e = 0; e < 6; ++e)
+                        S = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa3[kGramPairs3[e][0]][r], xb3[kGramPairs3[e][1]],
+                                                                    S, 0, 0, 0);
+                } else {
+#pragma unroll
+                    for (int k = 0; k < KS; ++k) S = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[r][k], xb[k], S, 0, 0, 0);
+                }
 #pragma unroll
                 for (int t = 0; t < 4; ++t)
                     bv[4 * r + t] = __float_as_uint(fmaxf(fmaf(-2.0f, S[t], ni[r][t] + nj), 0.0f));
             }
+            if constexpr (SPLIT) {
 #pragma unroll
-            for (int k = 0; k < KS; ++k) xb[k] = xn[k];
+                for (int q = 0; q < NP; ++q) xb3[q] = xn3[q];
+            } else {
+#pragma unroll
+                for (int k = 0; k < KS; ++k) xb[k] = xn[k];
+            }
             nj = nn;
             if (jb > wrow + 63 && jb + 16 <= N) {  // wave-uniform
 #pragma unroll
@@ -1112,6 +1150,10 @@ void launch_items_gram_ks(const OneMed& a, hipStream_t st) {
 }
 
 void launch_items_gram(const OneMed& a, hipStream_t st) {
+    if (a.L.split3) {
+        launch_items_gram_ks<0>(a, st);
+        return;
+    }
     switch (a.L.ks32) {
         case 2: launch_items_gram_ks<2>(a, st); break;
         case 4: launch_items_gram_ks<4>(a, st); break;
@@ -1153,6 +1195,7 @@ void launch_items_batched(const BatchPlan& P, const ProblemDesc* descs, const fl
     launch_direct_list<16, 256>(P, descs, theta, ws, st);
     launch_direct_list<32, 256>(P, descs, theta, ws, st);
     launch_direct_list<64, 256>(P, descs, theta, ws, st);
+    launch_gram_lists<0>(P, descs, ws, st);
     launch_gram_lists<2>(P, descs, ws, st);
     launch_gram_lists<4>(P, descs, ws, st);
     launch_gram_lists<6>(P, descs, ws, st);

@@ -44,7 +44,9 @@
 // direction (phi16.hip): a workgroup of 4 waves owns 64 rows and one column
 // split, the waves take its quarters and add their sums through LDS; the
 // Gram's output layout is the K.V product's A operand, V is stored in that
-// permuted order.  The reduce is the FP32 form's.
+// permuted order.  The rows' parts are packed in the bandwidth stage (the
+// median's Gram form reads them too), V's after the gradient.  The reduce is
+// the FP32 form's.
 #include <math.h>
 
 #include <type_traits>
@@ -83,15 +85,32 @@ __device__ __forceinline__ View32 view32(const SvgdLayout& L, char* base) {
     return v;
 }
 
-// v = hi + mid + lo into slot u of three part vectors (BF16 parts; the two
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f2v __attribute__((ext_vector_type(2)));
+typedef uint32_t u4v __attribute__((ext_vector_type(4)));
+
+// Two values as packed BF16 pairs (element 0 in the low half): one
+// conversion, and the pair's values back in FP32 by shift and mask.
+__device__ __forceinline__ uint32_t bf16_pair(float a, float b) {
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(f2v{a, b}, bf16x2));
+}
+__device__ __forceinline__ float pair_lo(uint32_t p) { return __uint_as_float(p << 16); }
+__device__ __forceinline__ float pair_hi(uint32_t p) { return __uint_as_float(p & 0xffff0000u); }
+
+// v[u] = hi[u] + mid[u] + lo[u] for eight values (BF16 parts; the two
 // differences are exact in FP32)
-__device__ __forceinline__ void split3(float v, bf16x8& hi, bf16x8& mid, bf16x8& lo, int u) {
-    const __bf16 h = (__bf16)v;
-    const float r = v - (float)h;
-    const __bf16 m = (__bf16)r;
-    hi[u] = h;
-    mid[u] = m;
-    lo[u] = (__bf16)(r - (float)m);
+__device__ __forceinline__ void split3(const float (&v)[8], bf16x8& hi, bf16x8& mid, bf16x8& lo) {
+    u4v h, m, l;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        h[q] = bf16_pair(v[2 * q], v[2 * q + 1]);
+        const float ra = v[2 * q] - pair_lo(h[q]), rb = v[2 * q + 1] - pair_hi(h[q]);
+        m[q] = bf16_pair(ra, rb);
+        l[q] = bf16_pair(ra - pair_lo(m[q]), rb - pair_hi(m[q]));
+    }
+    hi = __builtin_bit_cast(bf16x8, h);
+    mid = __builtin_bit_cast(bf16x8, m);
+    lo = __builtin_bit_cast(bf16x8, l);
 }
 
 // ---- operands: 64 rows per 256 threads, lane group q = threadIdx.x / 64 takes
@@ -99,7 +118,11 @@ __device__ __forceinline__ void split3(float v, bf16x8& hi, bf16x8& mid, bf16x8&
 // stores of xr are contiguous and its loop is a quarter of the dimension.
 // The centred rows and their norms come first (the median's Gram form reads
 // them); X = [-(2/h) x | 1 | 0] needs h and comes after the median.
-__device__ void pack32_x_rows(int N, int d, int ks, int row0, const float* __restrict__ theta, const View32& v) {
+// In split form the rows are also written as three BF16 parts (thread (r, q)
+// the coordinates 8 q .. 8 q + 7 of row r, as the MFMA lane group q reads
+// them), which the median's Gram form and the contraction both read.
+__device__ void pack32_x_rows(int N, int d, int ks, int row0, const float* __restrict__ theta, const View32& v,
+                              bool parts) {
     __shared__ float part[4][64];
     const int r = threadIdx.x & 63, q = threadIdx.x >> 6;
     const int i = row0 + r;
@@ -115,6 +138,20 @@ __device__ void pack32_x_rows(int N, int d, int ks, int row0, const float* __res
     __syncthreads();
     if (q == 0) v.nrm[i] = (part[0][r] + part[1][r]) + (part[2][r] + part[3][r]);
     __syncthreads();
+    if (parts) {
+        float x[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int l = 8 * q + u;
+            x[u] = (i < N && l < d) ? theta[(int64_t)l * N + i] - v.ctr[l] : 0.0f;
+        }
+        bf16x8 p0, p1, p2;
+        split3(x, p0, p1, p2);
+        __bf16* o = v.xs3 + (int64_t)i * 96 + 8 * q;
+        *reinterpret_cast<bf16x8*>(o) = p0;
+        *reinterpret_cast<bf16x8*>(o + 32) = p1;
+        *reinterpret_cast<bf16x8*>(o + 64) = p2;
+    }
 }
 
 // V[i][n] = w_i (g[n][i] - (2/h) x_i[n]) for n < d, w_i for n = d, 0 past it
@@ -137,46 +174,31 @@ __device__ void pack32_v_rows(int N, int d, int ot, int row0, const float* __res
     }
 }
 
-// Split form, 64 rows per 256 threads: the centred rows' parts (thread
-// (r, q) the coordinates 8 q .. 8 q + 7 of row r, as the MFMA lane group q
-// reads them) and V's parts, V[i][n] as in pack32_v_rows, in the order the
-// K.V product reads them: within a 32-particle chunk, column n holds 32
-// values whose slot 8 q + u is particle 4 q + (u & 3) (+ 16 for u >= 4), one
-// 16-byte store per (chunk, column, q) and part.
+// Split form, 64 rows per 256 threads: V's parts (the rows' parts come with
+// the bandwidth stage), V[i][n] as in pack32_v_rows, in the order the K.V
+// product reads them: within a 32-particle chunk, column n holds 32 values
+// whose slot 8 q + u is particle 4 q + (u & 3) (+ 16 for u >= 4), one 16-byte
+// store per (chunk, column, q) and part.
 __device__ void pack3_rows(int N, int d, int ot, int npad, int row0, const float* __restrict__ theta,
                            const float* __restrict__ g, const float* __restrict__ wts, const View32& v) {
     const int vc = 16 * ot;
-    {
-        const int r = threadIdx.x & 63, q = threadIdx.x >> 6;
-        const int i = row0 + r;
-        bf16x8 p0, p1, p2;
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int l = 8 * q + u;
-            const float x = (i < N && l < d) ? theta[(int64_t)l * N + i] - v.ctr[l] : 0.0f;
-            split3(x, p0, p1, p2, u);
-        }
-        __bf16* o = v.xs3 + (int64_t)i * 96 + 8 * q;
-        *reinterpret_cast<bf16x8*>(o) = p0;
-        *reinterpret_cast<bf16x8*>(o + 32) = p1;
-        *reinterpret_cast<bf16x8*>(o + 64) = p2;
-    }
     const float c2 = 2.0f / v.sel->h;
     const int64_t plane = (int64_t)npad * vc;
     for (int o = threadIdx.x; o < 8 * vc; o += 256) {  // 2 chunks x vc columns x 4 lane groups
         const int qc = (row0 >> 5) + o / (4 * vc), n = (o >> 2) % vc, q = o & 3;
-        bf16x8 p0, p1, p2;
+        float x[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
             const int i = 32 * qc + 4 * q + (u & 3) + (u >= 4 ? 16 : 0);
-            float x = 0.0f;
+            x[u] = 0.0f;
             if (i < N) {
-                if (n < d) x = -c2 * (theta[(int64_t)n * N + i] - v.ctr[n]) + g[(int64_t)n * N + i];
-                else x = n == d ? 1.0f : 0.0f;
-                if (wts) x *= wts[i];
+                if (n < d) x[u] = -c2 * (theta[(int64_t)n * N + i] - v.ctr[n]) + g[(int64_t)n * N + i];
+                else x[u] = n == d ? 1.0f : 0.0f;
+                if (wts) x[u] *= wts[i];
             }
-            split3(x, p0, p1, p2, u);
         }
+        bf16x8 p0, p1, p2;
+        split3(x, p0, p1, p2);
         __bf16* dst = v.vs3 + ((int64_t)qc * vc + n) * 32 + 8 * q;
         *reinterpret_cast<bf16x8*>(dst) = p0;
         *reinterpret_cast<bf16x8*>(dst + plane) = p1;
@@ -322,12 +344,11 @@ __device__ __forceinline__ void chunk3_step(Chunk3<OT>& cur, const bf16x8 (&xi)[
     if (more) load_x3<OT>(cur, v, jn, col, kq);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-        bf16x8 ka[3];
+        float k[8];
 #pragma unroll
-        for (int t = 0; t < 8; ++t) {
-            const float k = unit_clamp(hw_exp2(fmaf(m2c, s[r][t >> 2][t & 3], ni[r])));
-            split3(k, ka[0], ka[1], ka[2], t);
-        }
+        for (int t = 0; t < 8; ++t) k[t] = unit_clamp(hw_exp2(fmaf(m2c, s[r][t >> 2][t & 3], ni[r])));
+        bf16x8 ka[3];
+        split3(k, ka[0], ka[1], ka[2]);
 #pragma unroll
         for (int e = 0; e < 6; ++e)
 #pragma unroll
@@ -444,7 +465,7 @@ __global__ __launch_bounds__(kMeanThreads) void k_mean(One32 a, const float* the
 }
 
 __global__ __launch_bounds__(256) void k_pack32_x(One32 a, const float* theta, char* ws) {
-    pack32_x_rows(a.N, a.d, a.L.ks32, blockIdx.x * 64, theta, view32(a.L, ws));
+    pack32_x_rows(a.N, a.d, a.L.ks32, blockIdx.x * 64, theta, view32(a.L, ws), a.L.split3);
 }
 
 __global__ __launch_bounds__(256) void k_pack32_v(One32 a, const float* theta, const float* g, const float* wts,
@@ -508,7 +529,8 @@ __global__ __launch_bounds__(256) void k_pack32_x_batched(const ProblemDesc* __r
     const int4 e = work[blockIdx.x >> 2];
     const ProblemDesc& D = descs[e.x];
     if (D.N < 2) return;
-    pack32_x_rows(D.N, D.d, D.sv.ks32, e.y + 64 * (blockIdx.x & 3), theta + D.theta_off, view32(D.sv, base32(D, ws)));
+    pack32_x_rows(D.N, D.d, D.sv.ks32, e.y + 64 * (blockIdx.x & 3), theta + D.theta_off, view32(D.sv, base32(D, ws)),
+                  D.sv.split3);
 }
 
 __global__ __launch_bounds__(256) void k_pack32_v_batched(const ProblemDesc* __restrict__ descs,

@@ -314,7 +314,8 @@ void build_plan(int n, const stamp_scene* scenes, const int32_t* N, int K, float
         if (D.N >= 2 && !(bandwidth > 0.0f) && (uint64_t)D.N * (uint64_t)(D.N - 1) / 2 > (uint64_t)kMedSample) {
             // problems above 2^20 pairs take the Gram form (median.hip)
             const bool gram = (uint64_t)D.N * (uint64_t)(D.N - 1) / 2 > (1ull << 20);
-            const int c = gram ? med_gram_list(D.sv.ks32, D.sv.med_rows) : med_class(med_dp(D.d), D.sv.med_rows);
+            const int c = gram ? med_gram_list(D.sv.split3 ? 0 : D.sv.ks32, D.sv.med_rows)
+                               : med_class(med_dp(D.d), D.sv.med_rows);
             for (int rb = 0; rb < D.sv.med_rb; ++rb)
                 for (int cc = 0; cc < D.sv.med_cc; ++cc) dist_lists[c].push_back(make_int4(p, rb, cc, 0));
             if (gram) {
