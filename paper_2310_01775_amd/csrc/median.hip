@@ -575,8 +575,11 @@ __device__ void med_item_gram(const MedView& v, int rb, int cc) {
     // pass 0 stages candidates per wave, the histogram passes count into lh:
     // one LDS region serves both
     constexpr uint32_t kBuf = 2048;  // flushed when a step (at most 16 x 64 values) might not fit
-    static_assert(kMedBins <= (NT / 64) * kBuf, "histogram inside the staging region");
-    __shared__ uint32_t lds_region[(NT / 64) * kBuf];
+    // a wave's staging is kBuf words and 64 more, one per lane, that take the
+    // stores of the values outside the bracket (the unconditional store)
+    constexpr uint32_t kWave = kBuf + 64;
+    static_assert(kMedBins <= (NT / 64) * kWave, "histogram inside the staging region");
+    __shared__ uint32_t lds_region[(NT / 64) * kWave];
     uint32_t* const lh = lds_region;
     __shared__ uint32_t red[2][NT / 64];
     SelState* sel = v.sel;
@@ -626,7 +629,7 @@ __device__ void med_item_gram(const MedView& v, int rb, int cc) {
     const int seg = (int)(mix32(blockIdx.y * gridDim.x + blockIdx.x) % kCandSegs);
     const uint32_t seg_cap = v.cap / kCandSegs;
     uint32_t* segbuf = v.cand + (size_t)seg * seg_cap;
-    uint32_t* wb = lds_region + wave * kBuf;
+    uint32_t* wb = lds_region + wave * kWave;
     uint32_t nwb = 0;
     auto flush = [&]() __attribute__((always_inline)) {
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");  // the wave's LDS writes before its reads
@@ -645,6 +648,7 @@ __device__ void med_item_gram(const MedView& v, int rb, int cc) {
     // those inside [lo, hi] (a pair is inside iff bits - lo <= hi - lo,
     // unsigned); the pairs above hi are the rest
     uint32_t nvalid = 0, nb = 0, nin = 0;
+    uint32_t nbl = 0;  // this lane's pairs below lo on the steps without checks (added to nb at the end)
     const uint32_t wlo = hi - lo;
     // the first step with a pair j > i for some row of the wave; the next
     // step's operands load while this one computes
@@ -670,6 +674,21 @@ __device__ void med_item_gram(const MedView& v, int rb, int cc) {
     // valid (no row or column checks)
     auto classify = [&](auto all_tag, auto p0_tag, uint32_t x, bool valid) __attribute__((always_inline)) {
         constexpr bool ALL = decltype(all_tag)::value, P0 = decltype(p0_tag)::value;
+        if constexpr (ALL && P0) {
+            // the common step, without branches: the lane counts its pairs
+            // below lo, and every lane stores, an in-bracket value at its
+            // compacted place, any other value at the lane's own spare word
+            nbl += x < lo ? 1u : 0u;
+            const bool inb = x - lo <= wlo;
+            const uint64_t mb = __ballot(inb);
+            const uint32_t nm = (uint32_t)__popcll(mb);
+            const uint32_t pos =
+                nwb + __builtin_amdgcn_mbcnt_hi((uint32_t)(mb >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mb, 0u));
+            wb[inb ? pos : kBuf + (uint32_t)lane] = x;
+            nin += nm;
+            nwb = __builtin_amdgcn_readfirstlane(nwb + nm);
+            return;
+        }
         const bool in = (ALL || valid) && x - lo <= wlo;
         if (P0) {
             nb += (uint32_t)__popcll(__ballot((ALL || valid) && x < lo));
@@ -735,8 +754,14 @@ __device__ void med_item_gram(const MedView& v, int rb, int cc) {
             }
         }
     };
-    if (pass0) sweep(std::true_type{});
-    else sweep(std::false_type{});
+    if (pass0) {
+        sweep(std::true_type{});
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) nbl += __shfl_xor(nbl, o);
+        nb += __builtin_amdgcn_readfirstlane(nbl);
+    } else {
+        sweep(std::false_type{});
+    }
     if (!pass0) {
         __syncthreads();
         for (int b = tid; b < kMedBins; b += NT)
