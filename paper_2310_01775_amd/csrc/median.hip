@@ -560,7 +560,8 @@ __device__ void med_item(const MedView& v, const float* __restrict__ theta, int 
 // column l % 16.  KS = 0 is the split form (d <= 31): the rows as three
 // BF16 parts and x_i . x_j as the six part products of order >= 2^-16 on the
 // BF16 matrix cores (16x16x32, the same output layout), FP32-accurate as the
-// FP32 direction's split form.  Every pass computes a pair's distance with
+// FP32 direction's split form (its rows' slot 31, which holds -|x|^2 / 2's
+// parts for the contraction, is zeroed in the row operand).  Every pass computes a pair's distance with
 // the same instructions, so the counts stay exact.
 // The split form's part products (row part, column part), smallest first.
 __device__ constexpr int kGramPairs3[6][2] = {{1, 1}, {2, 0}, {0, 2}, {1, 0}, {0, 1}, {0, 0}};
@@ -616,7 +617,10 @@ __device__ void med_item_gram(const MedView& v, int rb, int cc) {
         if constexpr (SPLIT) {
             const __bf16* p = v.xs3 + (int64_t)(wrow + 16 * r + col) * 96 + 8 * kq;
 #pragma unroll
-            for (int q = 0; q < NP; ++q) xa3[q][r] = *reinterpret_cast<const bf16x8v*>(p + 32 * q);
+            for (int q = 0; q < NP; ++q) {
+                xa3[q][r] = *reinterpret_cast<const bf16x8v*>(p + 32 * q);
+                if (kq == 3) xa3[q][r][7] = (__bf16)0.0f;  // slot 31 holds e_i's part for the contraction
+            }
         } else {
             const float* p = v.xr + (int64_t)(wrow + 16 * r + col) * (4 * KS) + kq * KS;
 #pragma unroll

@@ -120,7 +120,10 @@ __device__ __forceinline__ void split3(const float (&v)[8], bf16x8& hi, bf16x8& 
 // them); X = [-(2/h) x | 1 | 0] needs h and comes after the median.
 // In split form the rows are also written as three BF16 parts (thread (r, q)
 // the coordinates 8 q .. 8 q + 7 of row r, as the MFMA lane group q reads
-// them), which the median's Gram form and the contraction both read.
+// them), which the median's Gram form and the contraction both read.  The
+// spare slot 31 (d <= 31) holds e_i = -|x_i|^2 / 2's parts: as a column
+// operand against (1, 0, 0) in the row operand's slot, the contraction's Gram
+// adds e_j itself; the median's row operand zeroes the slot.
 __device__ void pack32_x_rows(int N, int d, int ks, int row0, const float* __restrict__ theta, const View32& v,
                               bool parts) {
     __shared__ float part[4][64];
@@ -145,6 +148,7 @@ __device__ void pack32_x_rows(int N, int d, int ks, int row0, const float* __res
             const int l = 8 * q + u;
             x[u] = (i < N && l < d) ? theta[(int64_t)l * N + i] - v.ctr[l] : 0.0f;
         }
+        if (q == 3) x[7] = -0.5f * ((part[0][r] + part[1][r]) + (part[2][r] + part[3][r]));
         bf16x8 p0, p1, p2;
         split3(x, p0, p1, p2);
         __bf16* o = v.xs3 + (int64_t)i * 96 + 8 * q;
@@ -290,8 +294,7 @@ __device__ void phi32_body(int row0, int j0, int j1, int split, int npad, const 
 // Operands of one 32-column chunk as this lane holds them.
 template <int OT>
 struct Chunk3 {
-    bf16x8 xj[3][2];  // A of the Gram, part p: row j = jc + 16 sub + l % 16
-    f4 nj[2];         // |x_j|^2 for j = jc + 16 sub + 4 (l / 16) + t
+    bf16x8 xj[3][2];  // A of the Gram, part p: row j = jc + 16 sub + l % 16 (e_j's part in slot 31)
     bf16x8 vb[3][OT]; // B of K.V, part p: V[j][16 o + l % 16], j in the permuted order
 };
 
@@ -302,7 +305,6 @@ __device__ __forceinline__ void load_x3(Chunk3<OT>& c, const View32& v, int jc, 
         const __bf16* x = v.xs3 + (int64_t)(jc + 16 * sub + col) * 96 + 8 * kq;
 #pragma unroll
         for (int p = 0; p < 3; ++p) c.xj[p][sub] = *reinterpret_cast<const bf16x8*>(x + 32 * p);
-        c.nj[sub] = *reinterpret_cast<const f4*>(v.nrm + jc + 16 * sub + 4 * kq);
     }
 }
 
@@ -320,8 +322,8 @@ __device__ __forceinline__ void load_v3(Chunk3<OT>& c, const View32& v, int npad
 // order is at least 2^-16 of it, smallest first.
 __device__ constexpr int kPairs3[6][2] = {{1, 1}, {2, 0}, {0, 2}, {1, 0}, {0, 1}, {0, 0}};
 
-// One 32-column chunk for the wave's 4 row tiles: the Gram MFMAs (accumulator
-// starting at e_j = -|x_j|^2 / 2), then per row tile K = 2^(c D) split in
+// One 32-column chunk for the wave's 4 row tiles: the Gram MFMAs (x_i . x_j,
+// and e_j = -|x_j|^2 / 2 from slot 31), then per row tile K = 2^(c D) split in
 // three (VALU) and the K.V MFMAs.  One operand buffer: the next chunk's Gram
 // operands load as soon as this chunk's Gram has read them (they arrive
 // during its K.V work), its V as soon as the K.V products have read V
@@ -335,7 +337,7 @@ __device__ __forceinline__ void chunk3_step(Chunk3<OT>& cur, const bf16x8 (&xi)[
     for (int r = 0; r < 4; ++r)
 #pragma unroll
         for (int sub = 0; sub < 2; ++sub) {
-            s[r][sub] = cur.nj[sub] * -0.5f;
+            s[r][sub] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int e = 0; e < 6; ++e)
                 s[r][sub] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(cur.xj[kPairs3[e][0]][sub], xi[kPairs3[e][1]][r],
@@ -374,7 +376,7 @@ __device__ void phi3_body(int npad, int row0, int j0, int j1, int split, const V
     }
     const float c = -1.44269504088896341f / v.sel->h;  // K = 2^(c D)
     const float m2c = -2.0f * c;
-    bf16x8 xi[3][4];  // B of the Gram, part p, row tile r
+    bf16x8 xi[3][4];  // B of the Gram, part p, row tile r; slot 31 = (1, 0, 0) picks e_j
     float ni[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -382,6 +384,11 @@ __device__ void phi3_body(int npad, int row0, int j0, int j1, int split, const V
         const __bf16* x = v.xs3 + (int64_t)i * 96 + 8 * kq;
 #pragma unroll
         for (int p = 0; p < 3; ++p) xi[p][r] = *reinterpret_cast<const bf16x8*>(x + 32 * p);
+        if (kq == 3) {
+            xi[0][r][7] = (__bf16)1.0f;
+            xi[1][r][7] = (__bf16)0.0f;
+            xi[2][r][7] = (__bf16)0.0f;
+        }
         ni[r] = c * v.nrm[i];
     }
     f4 acc[4][OT];
