@@ -61,8 +61,11 @@ def test_batched_solve_equals_per_problem_iterations(ctx, autotune):
 
 def _check_batched_equals_loops(ctx, S):
     # 1600 particles: above 2^20 pairs, so its median's all-pairs passes take
-    # the Gram form in both paths
-    sizes = [(64, 2, 1), (200, 5, 4), (1, 3, 2), (97, 3, 3), (130, 4, 2), (33, 2, 4), (1600, 3, 1)]
+    # the Gram form in both paths (split form at d = 18); H = 6 and 8 (d = 36,
+    # 48) take the FP32 matrix-core contraction, and 1500 particles at d = 48
+    # its Gram-form median
+    sizes = [(64, 2, 1), (200, 5, 4), (1, 3, 2), (97, 3, 3), (130, 4, 2), (33, 2, 4), (1600, 3, 1), (150, 6, 2),
+             (1500, 8, 1)]
     probs = _problems(sizes, 40, 0.005, 0)
     iters, lr = 6, 1e-3
     flat = _pack(S, probs)
@@ -90,7 +93,11 @@ def _check_batched_equals_loops(ctx, S):
 
 def test_batched_solve_matches_oracle(ctx):
     import paper_2310_01775_amd as S
-    sizes = [(24, 2, 2), (40, 3, 1), (17, 4, 3)]
+    # d = 12, 18, 24 (split form), 36 (FP32 matrix-core form).  Every problem
+    # is well conditioned: the oracle's own solve moves by at most 3e-5
+    # normwise when theta is perturbed by 2^-24 (at H = 6 the (20, 6, 2) draw
+    # moves by 3e-4, so FP32 rounding alone puts it above the bar)
+    sizes = [(24, 2, 2), (40, 3, 1), (17, 4, 3), (16, 6, 2)]
     probs = _problems(sizes, 60, 0.005, 1)
     iters, lr = 20, 1e-3
     flat = _pack(S, probs)
