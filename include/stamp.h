@@ -239,7 +239,11 @@ int32_t stamp_rollout_adj_phases(stamp_ctx* ctx, const stamp_scene* scene, const
  * over i < j (median heuristic, Appendix D-B), as FP32 computes them: by direct
  * differences when P <= 2^20, in the Gram form |x_i|^2 + |x_j|^2 - 2 x_i.x_j of
  * the centred particles (matrix cores, clamped at 0) above.  The contraction
- * takes distances in that Gram form throughout.  N = 1 gives phi = grad_logp.
+ * takes distances in that Gram form throughout.  For d <= 31 both Gram forms
+ * and the contraction run on the BF16 matrix cores with every FP32 operand as
+ * three BF16 parts (six part products per FP32 product, FP32 accumulation):
+ * results of FP32 accuracy, not bit-equal to an FP32 matrix product.
+ * N = 1 gives phi = grad_logp.
  *   theta, grad_logp, phi: [d][N]; h_out: one device float (may be NULL).
  * Errors: STAMP_EINVAL for null pointers, N < 1, d < 1; STAMP_ENOSPACE. */
 int32_t stamp_svgd_step(stamp_ctx* ctx, int32_t N, int32_t d, const float* theta,
