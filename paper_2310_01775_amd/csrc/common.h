@@ -109,7 +109,7 @@ struct SvgdLayout {
     size_t x32_off;                 // npad x 4 ks32 floats: centred rows in MFMA operand order
     size_t n32_off;                 // npad floats: their squared norms
     size_t v32_off;                 // npad x 16 ot32 floats: V = w [g - (2/h) x | 1 | 0], tiled
-    size_t xs3_off;                 // split form: npad x 3 x 32 bf16, the centred rows' three parts
+    size_t xs3_off;                 // split form: npad x 3 x 32 bf16, the centred rows' three parts (slot 31: -|x|^2/2)
     size_t vs3_off;                 // split form: 3 x npad x 16 ot32 bf16, V's three parts, chunked
     int kd, vc;                     // Gram width (d + 2 rounded up to 32) and V columns (d + 1 rounded up)
     int splits16, chunk16;          // column splits of its contraction and their width

@@ -38,9 +38,10 @@
 // mm; the three dropped ones are below 2^-24), each exact in the FP32
 // accumulator: the Gram x_i . x_j takes six BF16 MFMAs over 32 coordinates,
 // K V six over 32 particles, where the FP32 form takes eight 4-wide ones and
-// eight.  e_j still enters as the Gram accumulator's start and K is the same
-// multiply-add and clamped exponential of the FP32 Gram value, so the
-// result is the FP32 form's within its own rounding.  Tiling as in the BF16
+// eight.  e_j enters through the Gram's spare slot 31 (d <= 31): its three
+// parts in the column operand against (1, 0, 0) in the row operand's slot.
+// K is the same multiply-add and clamped exponential of the Gram value, so
+// the result is the FP32 form's within its own rounding.  Tiling as in the BF16
 // direction (phi16.hip): a workgroup of 4 waves owns 64 rows and one column
 // split, the waves take its quarters and add their sums through LDS; the
 // Gram's output layout is the K.V product's A operand, V is stored in that
@@ -67,7 +68,7 @@ struct View32 {  // one problem's FP32 matrix-core workspace
     float* nrm;  // [npad]: |x_i|^2
     float* vt;   // [npad / 16][ot][16 columns n][16 rows j]: X[j][16 o + n] at 16 n + j of tile (j/16, o)
     float* part; // [splits32][16 ot][npad]
-    __bf16* xs3; // split form: [npad][3][32], row i's part p at (3 i + p) 32
+    __bf16* xs3; // split form: [npad][3][32], row i's part p at (3 i + p) 32 (slot 31: -|x_i|^2 / 2's part)
     __bf16* vs3; // split form: part p of V at p npad 16 ot, as [npad / 32][16 ot][32] in MFMA k order
     const SelState* sel;
 };
