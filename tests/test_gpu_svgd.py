@@ -118,6 +118,29 @@ def test_phi_matches_oracle(ctx, N, d, bw):
         assert np.array_equal(got, g)
 
 
+@pytest.mark.parametrize("N,d,lo,hi", [(300, 24, 1e-3, 1e2), (257, 31, 1e-2, 1e3)])
+def test_phi_matches_oracle_with_mixed_coordinate_scales(ctx, N, d, lo, hi):
+    """Coordinates of very different scales side by side (the split form
+    carries each FP32 operand as three BF16 parts, whose exponent range is
+    FP32's): phi still within 2e-5 of each coordinate's scale."""
+    import paper_2310_01775_amd as S
+    print("case", N, d, lo, hi, flush=True)
+    rng = np.random.default_rng(N * 3 + d)
+    scales = np.where(np.arange(d) % 2 == 0, lo, hi)
+    th = (rng.standard_normal((N, d)) * scales).astype(np.float32).astype(np.float64)
+    g = (rng.standard_normal((N, d)) * 50 / scales).astype(np.float32).astype(np.float64)
+    h_out = torch.zeros(1, dtype=torch.float32, device="cuda")
+    phi = ctx.svgd_step(S.soa(th), S.soa(g), 0.0, h_out=h_out)
+    torch.cuda.synchronize()
+    h = svgd.bandwidth(th, 0.0)
+    ref = svgd.svgd_phi(th, g, h)
+    got = S.aos(phi)
+    scale = np.abs(ref).max(axis=0, keepdims=True) + 1e-30
+    err = (np.abs(got - ref) / scale).max()
+    print("phi err", err, flush=True)
+    assert err < 2e-5
+
+
 def test_adam_and_plain_step_match_oracle(ctx):
     import paper_2310_01775_amd as S
     rng = np.random.default_rng(9)
