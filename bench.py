@@ -436,39 +436,46 @@ def bench_headline(args):
              "direction_fp32": n_sim * ms["direction_fp32"], "mlp_infer": (n_net + n_chk) * ms["mlp_infer"],
              "direction_bf16": n_net * ms["direction_bf16"],
              "bandwidth_bf16": n_net * max(ms["step_bf16"] - ms["direction_bf16"], 0.0)}
+    def roof_for(dom):
+        """The roofline object of one stage (its dominant kernel at this shape)."""
+        by_f, by_a = rollout_bytes(N, d, B, T, H)
+        if dom in ("rollout_adj", "rollout_fwd"):
+            byts = by_a if dom == "rollout_adj" else by_f
+            achieved = byts / (ms[dom] * 1e-3) / 1e9
+            roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom),
+                    "kernel": "k_%s_packed<%d>" % (dom, B), "kernel_ms": ms[dom], "bytes_per_launch": byts}
+            if dom == "rollout_adj":
+                one = rollout_bytes_single_trajectory(N, d, B, T)
+                roof["frac_single_trajectory_bytes"] = one / (ms[dom] * 1e-3) / 1e9 / HBM_PEAK_GBS
+        elif dom == "mlp_infer":
+            fl = mlp_flops(N, n_in)
+            achieved = fl / (ms[dom] * 1e-3) / 1e12
+            roof = {"bound": "mfma", "achieved": achieved, "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": achieved / MFMA_BF16_PEAK_TFLOPS, "traffic": measured_traffic("mlp_infer"), "kernel": "k_mlp_infer",
+                    "kernel_ms": ms[dom]}
+        else:  # a direction stage (the BF16 bandwidth stage, several small kernels, never leads)
+            # both directions run on the BF16 matrix cores at d = 30: the FP32 one
+            # in split form (three BF16 parts per operand), so its algorithmic
+            # flops are priced against the BF16 peak too
+            fl = phi_flops(N, d)
+            achieved = fl / (ms[dom] * 1e-3) / 1e12
+            roof = {"bound": "mfma", "achieved": achieved, "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": achieved / MFMA_BF16_PEAK_TFLOPS, "traffic": measured_traffic(dom), "kernel_ms": ms[dom],
+                    "flops_per_launch": fl,
+                    "kernel": ("k_phi3<2> (FP32 direction in split form on the BF16 matrix cores; the stage also holds "
+                               "k_pack32_v and k_reduce32)" if dom == "direction_fp32" else
+                               "k_phi16<32,32> (BF16 matrix cores; the stage also holds k_pack16_v and k_reduce16)")}
+            if dom == "direction_fp32":
+                ex = split3_mfma_flops(N)
+                roof["executed_mfma_tflops"] = ex / (ms[dom] * 1e-3) / 1e12
+                roof["executed_mfma_frac"] = roof["executed_mfma_tflops"] / MFMA_BF16_PEAK_TFLOPS
+        return roof
+
     dom = max(share, key=share.get)
-    by_f, by_a = rollout_bytes(N, d, B, T, H)
-    if dom in ("rollout_adj", "rollout_fwd"):
-        byts = by_a if dom == "rollout_adj" else by_f
-        achieved = byts / (ms[dom] * 1e-3) / 1e9
-        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom),
-                "kernel": "k_%s<%d>" % (dom, B), "kernel_ms": ms[dom], "bytes_per_launch": byts}
-        if dom == "rollout_adj":
-            one = rollout_bytes_single_trajectory(N, d, B, T)
-            roof["frac_single_trajectory_bytes"] = one / (ms[dom] * 1e-3) / 1e9 / HBM_PEAK_GBS
-    elif dom == "mlp_infer":
-        fl = mlp_flops(N, n_in)
-        achieved = fl / (ms[dom] * 1e-3) / 1e12
-        roof = {"bound": "mfma", "achieved": achieved, "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / MFMA_BF16_PEAK_TFLOPS, "traffic": measured_traffic("mlp_infer"), "kernel": "k_mlp_infer",
-                "kernel_ms": ms[dom]}
-    else:  # a direction stage (the BF16 bandwidth stage, several small kernels, never leads)
-        # both directions run on the BF16 matrix cores at d = 30: the FP32 one
-        # in split form (three BF16 parts per operand), so its algorithmic
-        # flops are priced against the BF16 peak too
-        fl = phi_flops(N, d)
-        achieved = fl / (ms[dom] * 1e-3) / 1e12
-        roof = {"bound": "mfma", "achieved": achieved, "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / MFMA_BF16_PEAK_TFLOPS, "traffic": measured_traffic(dom), "kernel_ms": ms[dom],
-                "flops_per_launch": fl,
-                "kernel": ("k_phi3<2> (FP32 direction in split form on the BF16 matrix cores; the stage also holds "
-                           "k_pack32_v and k_reduce32)" if dom == "direction_fp32" else
-                           "k_phi16<32,32> (BF16 matrix cores; the stage also holds k_pack16_v and k_reduce16)")}
-        if dom == "direction_fp32":
-            ex = split3_mfma_flops(N)
-            roof["executed_mfma_tflops"] = ex / (ms[dom] * 1e-3) / 1e12
-            roof["executed_mfma_frac"] = roof["executed_mfma_tflops"] / MFMA_BF16_PEAK_TFLOPS
+    roof = roof_for(dom)
+    # every stage's own roofline beside it (the BF16 bandwidth stage is a few small kernels: none)
+    stage_roofs = {k: roof_for(k) for k in share if k != "bandwidth_bf16"}
 
     out = {
         "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": args.steps,
@@ -488,6 +495,7 @@ def bench_headline(args):
                        "surrogate_median_le_plain_median": cs["median"] <= cp["median"]},
         "training": {"rows": ds.n, "seconds": train_s, "steps": log.steps},
         "roofline": roof,
+        "stage_rooflines": stage_roofs,
         "kernels_ms": ms,
         "kernel_ms_per_solve": share,
     }
