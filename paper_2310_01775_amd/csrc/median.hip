@@ -1240,7 +1240,10 @@ void launch_items_batched(const BatchPlan& P, const ProblemDesc* descs, const fl
 hipError_t launch_median(int N, int d, const float* theta, float bandwidth, int exact, void* ws, const SvgdLayout& L,
                          float* h_out, hipStream_t st, int gram) {
     OneMed a{N, d, bandwidth > 0.0f ? bandwidth : 0.0f, L, static_cast<char*>(ws)};
-    hipLaunchKernelGGL(k_med_dist, dim3(kMedSample / 64), dim3(256), 0, st, a, theta);
+    // the sample distances only when a median is wanted: with a given
+    // bandwidth (or one particle) the select just records h
+    if (N >= 2 && !(bandwidth > 0.0f))
+        hipLaunchKernelGGL(k_med_dist, dim3(kMedSample / 64), dim3(256), 0, st, a, theta);
     hipLaunchKernelGGL(k_sample_select, dim3(1), dim3(kSelThreads), 0, st, a, exact, h_out);
     if (exact && N >= 2 && !(bandwidth > 0.0f) && pair_count(N) > (uint64_t)kMedSample) {
         // pass 0; small problems keep direct differences, whose every-pair
