@@ -33,9 +33,10 @@
 // ones' work per cycle, so the same contraction runs there with every FP32
 // operand v written as three BF16 parts, hi = bf16(v), mid = bf16(v - hi),
 // lo = bf16(v - hi - mid) (both differences exact in FP32, and
-// hi + mid + lo = v within 2^-25 |v|).  A product a b is then the sum of the
-// six part products whose order is at least 2^-16 of it (hh, hm, mh, hl, lh,
-// mm; the three dropped ones are below 2^-24), each exact in the FP32
+// hi + mid + lo = v exactly for normal v: 24 significant bits, 8 per part).
+// A product a b is then the sum of the six part products whose order is at
+// least 2^-16 of it (hh, hm, mh, hl, lh, mm; the three dropped ones are
+// below 2^-24, the only error besides the sums), each exact in the FP32
 // accumulator: the Gram x_i . x_j takes six BF16 MFMAs over 32 coordinates,
 // K V six over 32 particles, where the FP32 form takes eight 4-wide ones and
 // eight.  e_j enters through the Gram's spare slot 31 (d <= 31): its three
