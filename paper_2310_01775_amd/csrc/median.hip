@@ -7,9 +7,11 @@
 //   1. A fixed sample of kMedSample pairs is measured (the same squared
 //      distances, summed in a fixed order of their own, so within rounding of
 //      the passes' values) and its order statistics at ranks
-//      S(1/2 -+ 3/sqrt S) give a bracket [lo, hi] that holds rank k unless the
-//      sample is off by six standard deviations (a rank outside it sends the
-//      passes back over every pair, step 3).  When all pairs fit in the
+//      S(1/2 -+ 2/sqrt S) give a bracket [lo, hi] that holds rank k unless the
+//      sample is off by four standard deviations (about once in 16 000
+//      selects; a rank outside it sends the passes back over every pair, step
+//      3, so the result stays exact).  A wider bracket makes every pass 0
+//      stage and every candidate pass read more candidates.  When all pairs fit in the
 //      sample, it is the population and its median is final.  The sample sits
 //      in LDS for the select.
 //   2. Pass 0 over every pair counts the pairs below lo and above hi and
@@ -52,7 +54,7 @@ typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8v;
 namespace {
 
 constexpr uint32_t kModeDone = 0, kModePass0 = 1, kModeCand = 2, kModeAll = 3;
-constexpr float kBracketSigmas = 6.0f;
+constexpr float kBracketSigmas = 4.0f;
 constexpr uint32_t kWaveBuf = 512;        // candidates a wave stages in LDS between flushes
 constexpr int kGramGroup = 2;             // column chunks of one Gram-form item
 constexpr uint32_t kSentinel = 0xffffffffu;  // above every candidate interval
@@ -332,7 +334,7 @@ __device__ void sample_select_body(const MedView& v, int exact, float* h_out) {
     const uint32_t S = all ? (uint32_t)P : (uint32_t)kMedSample;
     uint32_t rank[3];
     rank[1] = (S + 1) / 2;
-    const float half = kBracketSigmas * 0.5f / sqrtf((float)S);  // six sigmas of the sample median's rank
+    const float half = kBracketSigmas * 0.5f / sqrtf((float)S);  // four sigmas of the sample median's rank
     rank[0] = (uint32_t)fmaxf(1.0f, floorf((float)S * (0.5f - half)));
     rank[2] = (uint32_t)fminf((float)S, ceilf((float)S * (0.5f + half)));
     uint32_t mn = 0xffffffffu, mx = 0u;  // range of the sample's (non-NaN) values
